@@ -1,0 +1,6 @@
+"""FP64 CPU oracle of the MEG7 scheme (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It shares no code with the HIP path.
+"""
+from .oracle import *  # noqa: F401,F403

@@ -1,0 +1,767 @@
+/*
+ * meg7_oracle.c -- plain, slow, FP64 CPU oracle for the MEG7 scheme of
+ * Chamarthi, "Efficient high-order Gradient-based Reconstruction for
+ * compressible flows" (arXiv 2305.00762).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py may load this library.  It shares no code,
+ * header, table or helper with the HIP path in paper_2305_00762_amd/csrc/.
+ *
+ * Every step follows the paper in its own order and notation:
+ *   Sec. 1      eq. (CNS-base), the flux vectors, eq. (eqn:pressure),
+ *               eq. (eqn:visc)                         -> physics
+ *   Sec. 1      eqs. (eqn-differencing_residual), (deriv), (eqn:Riemann)
+ *                                                      -> residual
+ *   Sec. 2.1    eqs. (eqn:visc-interface), (eqn:alphad), (sixth-ordergrad)
+ *                                                      -> viscous flux
+ *   Sec. 2.2    eqs. (eqn:six), (eqn:grb)              -> GRB states
+ *   Sec. 2.3    eqs. (eqn:hocus/mp5Condition), (eqn:alpha),
+ *               (eqn:mp-procedure)                     -> MP limiter (MEG7)
+ *   Sec. 2.4    hybrid F_L / F_R, eqs. (flux-full), (flux-right),
+ *               the detector and eq. (buffer)          -> hybrid flux
+ *   Sec. 2.5    eq. (rk) and the CFL time step          -> time integration
+ *
+ * Readings taken where the paper is silent or garbled (all listed in
+ * the design doc):
+ *   R-T    T := gamma p / rho, so that q = -mu/(Pr(gamma-1)) dT/dx matches
+ *          kappa = Cp mu / Pr (Cp cancels).
+ *   R-DET  psi = (2ab + eps) / (a^2 + b^2 + eps): the printed psi omits the
+ *          eps that eq. (buffer) defines; with it the free stream (a=b=0)
+ *          is defined and a=0, b=xi gives psi = 0.9 psi_c exactly.  One
+ *          detector per direction, on density; psi == psi_c gives sigma=1.
+ *   R-MP   The MP limiter and the characteristic projection act only on
+ *          interfaces the detector flags (sigma = 0); sigma = 1 interfaces
+ *          use the unlimited GRB states (mp_mode 0).  mp_mode 1 applies the
+ *          MP test to the states of every interface.
+ *   R-CHAR Characteristic variables: left/right eigenvectors of the
+ *          primitive-variable Jacobian at the arithmetic-mean density and
+ *          pressure of the two cells beside the interface.
+ *   R-HLLC HLLC of Toro with Einfeldt (Roe-average) wave-speed bounds,
+ *          evaluated in the wave-sum form of eq. (eqn:Riemann); with
+ *          F_L = F(Q_L), F_R = F(Q_R) it is the textbook HLLC flux.
+ *   R-VISC 2D viscous interface flux: normal derivatives alpha-damped,
+ *          tangential derivatives and interface velocities as two-cell
+ *          means; mu constant.
+ *   R-BC   Ghost cells (6 layers): periodic wrap or zeroth-order copy
+ *          (transmissive).
+ *   R-MPG  In eq. (eqn:mp-procedure) the hat on Phi_{j-1} and the mixed
+ *          i/j subscripts are typesetting slips: plain Phi_{j-1}, index j.
+ *          The MP xi (=7) and the detector xi (=1e-3) are different
+ *          constants.  The right state is the mirror image of the left.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (no FMA
+ * contraction anywhere, so the detector is evaluated with one rounding per
+ * operation in the order written).
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NG 6 /* ghost layers: the shock branch reaches Phi_{j-5..j+6} */
+
+enum { ORC_BC_PERIODIC = 0, ORC_BC_TRANSMISSIVE = 1 };
+
+typedef struct {
+    int nx, ny;
+    double x0, x1, y0, y1;
+    int bc_x, bc_y;
+    double gamma, mu, Pr;
+    int mp_mode;   /* 0: MP only where sigma=0 (R-MP); 1: MP test everywhere */
+    int force_sigma; /* -1: detector decides; 0 or 1: force sigma (tests)    */
+} orc_cfg;
+
+/* ---------------------------------------------------------------------- */
+/* Constants of the paper.                                                 */
+/* ---------------------------------------------------------------------- */
+static const double ALPHA_V = 4.0;      /* eq. (eqn:alphad): alpha_v = 4            */
+static const double XI_MP = 7.0;        /* eq. (eqn:alpha): xi = 7                  */
+static const double MP_TOL = 1e-40;     /* eq. (eqn:hocus/mp5Condition)             */
+static const double PSI_C = 0.5;        /* eq. (buffer)                             */
+static const double XI_DET = 1e-3;      /* eq. (buffer)                             */
+
+double orc_detector_eps(void)
+{
+    /* eq. (buffer): eps = 0.9 psi_c / (1 - 0.9 psi_c) * xi^2 */
+    return (0.9 * PSI_C) / (1.0 - 0.9 * PSI_C) * (XI_DET * XI_DET);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Coefficient tables exactly as printed (integer numerators over a        */
+/* common denominator).  Exported so tests can check them against the      */
+/* paper's derivation from (alpha, beta).                                  */
+/* ---------------------------------------------------------------------- */
+/* eq. (eqn:six): Phi'_j = [45(P_{j+1}-P_{j-1}) - 9(P_{j+2}-P_{j-2}) + (P_{j+3}-P_{j-3})]/60 */
+static const int GRAD6[7] = {-1, 9, -45, 0, 45, -9, 1}; /* offsets -3..3, /60 */
+static const int GRAD6_DEN = 60;
+/* eq. (eqn:grb), left state at j+1/2: values at offsets -2..2, gradients at -1..1, /840 */
+static const int GRB_L_VAL[5] = {3, 178, 478, 178, 3};
+static const int GRB_L_GRD[3] = {60, 420, -60};
+/* eq. (eqn:grb), right state at j+1/2: values at offsets -1..3, gradients at 0..2, /840 */
+static const int GRB_R_VAL[5] = {3, 178, 478, 178, 3};
+static const int GRB_R_GRD[3] = {60, -420, -60};
+static const int GRB_DEN = 840;
+/* eq. (flux-full): F(f_L) on offsets -4..4, /840 */
+static const int FLUX_L[9] = {-1, 2, 22, -146, 568, 484, -104, 16, -1};
+/* eq. (flux-right): F(f_R) on offsets -3..5, /840 */
+static const int FLUX_R[9] = {-1, 16, -104, 484, 568, -146, 22, 2, -1};
+static const int FLUX_DEN = 840;
+/* eq. (eqn:grb-sec): Delta x^2 Phi_xx = (60 P'_{j-1} - 60 P'_{j+1} - 362 P_j
+ * + 178 (P_{j-1}+P_{j+1}) + 3 (P_{j-2}+P_{j+2}))/70 -- exported for tests only. */
+static const int SEC_VAL[5] = {3, 178, -362, 178, 3};
+static const int SEC_GRD[3] = {60, 0, -60};
+static const int SEC_DEN = 70;
+
+/* which: 0 grad6, 1 grb_L values, 2 grb_L grads, 3 grb_R values, 4 grb_R grads,
+ *        5 flux_L, 6 flux_R, 7 second-derivative values, 8 second-derivative grads.
+ * Writes the numerators into num[], returns the count; *den gets the denominator. */
+int orc_table(int which, int *num, int *den)
+{
+    const int *t; int n, d;
+    switch (which) {
+    case 0: t = GRAD6; n = 7; d = GRAD6_DEN; break;
+    case 1: t = GRB_L_VAL; n = 5; d = GRB_DEN; break;
+    case 2: t = GRB_L_GRD; n = 3; d = GRB_DEN; break;
+    case 3: t = GRB_R_VAL; n = 5; d = GRB_DEN; break;
+    case 4: t = GRB_R_GRD; n = 3; d = GRB_DEN; break;
+    case 5: t = FLUX_L; n = 9; d = FLUX_DEN; break;
+    case 6: t = FLUX_R; n = 9; d = FLUX_DEN; break;
+    case 7: t = SEC_VAL; n = 5; d = SEC_DEN; break;
+    case 8: t = SEC_GRD; n = 3; d = SEC_DEN; break;
+    default: return -1;
+    }
+    for (int k = 0; k < n; ++k) num[k] = t[k];
+    *den = d;
+    return n;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Small building blocks, each an equation of the paper.                   */
+/* ---------------------------------------------------------------------- */
+
+/* eq. (eqn:six) / (sixth-ordergrad): Phi' = Delta x * dPhi/dx at the centre
+ * of p[0..6] (offsets -3..3). */
+double orc_grad6(const double *p)
+{
+    return (45.0 * (p[4] - p[2]) - 9.0 * (p[5] - p[1]) + (p[6] - p[0])) / 60.0;
+}
+
+/* The detector of Sec. 2.4 (eq. detector, reading R-DET) at cell j from
+ * rho_{j-2..j+2}; evaluated with one rounding per operation in this order. */
+double orc_psi(double rm2, double rm1, double r0, double rp1, double rp2)
+{
+    const double eps = orc_detector_eps();
+    double a = fabs(r0 - rm1) + fabs((r0 - 2.0 * rm1) + rm2);
+    double b = fabs(r0 - rp1) + fabs((r0 - 2.0 * rp1) + rp2);
+    double num = (2.0 * a) * b + eps;
+    double den = (a * a + b * b) + eps;
+    return num / den;
+}
+
+/* eq. (eqn:grb): left state at j+1/2 from p[-2..2] (p points at j) and
+ * gradients g[-1..1] (Phi' = Delta x dPhi/dx, g points at j). */
+static double grb_left(const double *p, const double *g)
+{
+    return (420.0 * g[0] + 60.0 * g[-1] - 60.0 * g[1] + 478.0 * p[0] + 178.0 * p[-1]
+            + 3.0 * p[-2] + 178.0 * p[1] + 3.0 * p[2]) / 840.0;
+}
+
+/* eq. (eqn:grb): right state at j+1/2 from p[-1..3] and g[0..2] (pointers at j). */
+static double grb_right(const double *p, const double *g)
+{
+    return (60.0 * g[0] - 420.0 * g[1] - 60.0 * g[2] + 178.0 * p[0] + 3.0 * p[-1]
+            + 478.0 * p[1] + 178.0 * p[2] + 3.0 * p[3]) / 840.0;
+}
+
+/* eq. (flux-full): F(f_L) at j+1/2 from f[-4..4] (pointer at j). */
+static double flux_left(const double *f)
+{
+    return (568.0 * f[0] - 146.0 * f[-1] + 22.0 * f[-2] + 2.0 * f[-3] - f[-4]
+            + 484.0 * f[1] - 104.0 * f[2] + 16.0 * f[3] - f[4]) / 840.0;
+}
+
+/* eq. (flux-right): F(f_R) at j+1/2 from f[-3..5] (pointer at j). */
+static double flux_right(const double *f)
+{
+    return (-f[5] + 2.0 * f[4] + 22.0 * f[3] - 146.0 * f[2] + 568.0 * f[1]
+            + 484.0 * f[0] - 104.0 * f[-1] + 16.0 * f[-2] - f[-3]) / 840.0;
+}
+
+/* Exported stencil applications for the polynomial / symbol tests. */
+void orc_apply_interface(const double *v10, const double *g6, double out[4])
+{
+    /* v10: values at offsets -4..5, g6: gradients at offsets -2..3 (interface
+     * j+1/2, j at index 4 of v10 and index 2 of g6).
+     * out = {GRB left, GRB right, F(f_L), F(f_R)} */
+    out[0] = grb_left(v10 + 4, g6 + 2);
+    out[1] = grb_right(v10 + 4, g6 + 2);
+    out[2] = flux_left(v10 + 4);
+    out[3] = flux_right(v10 + 4);
+}
+
+static double minmod(double a, double b)
+{
+    /* eq. (eqn:alpha): minmod(a,b) = (sign(a)+sign(b))/2 * min(|a|,|b|) */
+    double sa = (a > 0.0) - (a < 0.0);
+    double sb = (b > 0.0) - (b < 0.0);
+    return 0.5 * (sa + sb) * fmin(fabs(a), fabs(b));
+}
+
+static double min3(double a, double b, double c) { return fmin(a, fmin(b, c)); }
+static double max3(double a, double b, double c) { return fmax(a, fmax(b, c)); }
+
+/* MP curvature of eq. (eqn:mp-procedure):
+ * d_j = 2(P_{j+1} - 2P_j + P_{j-1}) - 0.5 (P'_{j+1} - P'_{j-1}) */
+static double mp_curv(const double *p, const double *g)
+{
+    return 2.0 * (p[1] - 2.0 * p[0] + p[-1]) - 0.5 * (g[1] - g[-1]);
+}
+
+/* Sec. 2.3: MEG7 left value at j+1/2 for one scalar component.
+ * p, g point at cell j; p[-2..3], g[-2..3] are read. */
+double orc_meg7_left(const double *p, const double *g, int *limited)
+{
+    double phi = grb_left(p, g);
+    double phi_mp = p[0] + minmod(p[1] - p[0], XI_MP * (p[0] - p[-1]));
+    if ((phi - p[0]) * (phi - phi_mp) <= MP_TOL) {
+        if (limited) *limited = 0;
+        return phi;
+    }
+    double dm1 = mp_curv(p - 1, g - 1);
+    double d0 = mp_curv(p, g);
+    double dp1 = mp_curv(p + 1, g + 1);
+    double md = 0.5 * (p[0] + p[1]) - 0.5 * minmod(d0, dp1);
+    double ul = p[0] + XI_MP * (p[0] - p[-1]);
+    double lc = 0.5 * (3.0 * p[0] - p[-1]) + (4.0 / 3.0) * minmod(d0, dm1);
+    double pmin = fmax(min3(p[0], p[1], md), min3(p[0], ul, lc));
+    double pmax = fmin(max3(p[0], p[1], md), max3(p[0], ul, lc));
+    if (limited) *limited = 1;
+    return phi + minmod(pmin - phi, pmax - phi);
+}
+
+/* Mirror image of orc_meg7_left: right value at j+1/2 (p, g point at j). */
+double orc_meg7_right(const double *p, const double *g, int *limited)
+{
+    double phi = grb_right(p, g);
+    double phi_mp = p[1] + minmod(p[0] - p[1], XI_MP * (p[1] - p[2]));
+    if ((phi - p[1]) * (phi - phi_mp) <= MP_TOL) {
+        if (limited) *limited = 0;
+        return phi;
+    }
+    double d0 = mp_curv(p, g);
+    double dp1 = mp_curv(p + 1, g + 1);
+    double dp2 = mp_curv(p + 2, g + 2);
+    double md = 0.5 * (p[1] + p[0]) - 0.5 * minmod(dp1, d0);
+    double ul = p[1] + XI_MP * (p[1] - p[2]);
+    double lc = 0.5 * (3.0 * p[1] - p[2]) + (4.0 / 3.0) * minmod(dp1, dp2);
+    double pmin = fmax(min3(p[1], p[0], md), min3(p[1], ul, lc));
+    double pmax = fmin(max3(p[1], p[0], md), max3(p[1], ul, lc));
+    if (limited) *limited = 1;
+    return phi + minmod(pmin - phi, pmax - phi);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Physics in a frame rotated to the interface normal: W = (rho, un, ut, p),
+ * Q = (rho, rho un, rho ut, E).                                           */
+/* ---------------------------------------------------------------------- */
+
+/* eq. (eqn:pressure) inverted: conservative from primitive. */
+static void prim_to_cons(const double W[4], double gamma, double Q[4])
+{
+    Q[0] = W[0];
+    Q[1] = W[0] * W[1];
+    Q[2] = W[0] * W[2];
+    Q[3] = W[3] / (gamma - 1.0) + 0.5 * W[0] * (W[1] * W[1] + W[2] * W[2]);
+}
+
+/* The convective flux vector of Sec. 1 along the normal. */
+static void conv_flux(const double W[4], double gamma, double F[4])
+{
+    double Q[4];
+    prim_to_cons(W, gamma, Q);
+    F[0] = W[0] * W[1];
+    F[1] = W[0] * W[1] * W[1] + W[3];
+    F[2] = W[0] * W[1] * W[2];
+    F[3] = W[1] * (Q[3] + W[3]);
+}
+
+/* HLLC (Toro 1994), reading R-HLLC, written in the wave-sum form
+ * F = (F_L + F_R)/2 - (|S_L|(Q*_L - Q_L) + |S*|(Q*_R - Q*_L) + |S_R|(Q_R - Q*_R))/2
+ * which is the canonical form of eq. (eqn:Riemann). */
+void orc_hllc(const double WL[4], const double WR[4], const double FL[4],
+              const double FR[4], double gamma, double F[4])
+{
+    double QL[4], QR[4];
+    prim_to_cons(WL, gamma, QL);
+    prim_to_cons(WR, gamma, QR);
+    double rl = WL[0], ul = WL[1], vl = WL[2], pl = WL[3];
+    double rr = WR[0], ur = WR[1], vr = WR[2], pr = WR[3];
+    double cl = sqrt(gamma * pl / rl);
+    double cr = sqrt(gamma * pr / rr);
+    double hl = (QL[3] + pl) / rl;
+    double hr = (QR[3] + pr) / rr;
+    /* Roe averages */
+    double sl_ = sqrt(rl), sr_ = sqrt(rr);
+    double ut = (sl_ * ul + sr_ * ur) / (sl_ + sr_);
+    double vt = (sl_ * vl + sr_ * vr) / (sl_ + sr_);
+    double ht = (sl_ * hl + sr_ * hr) / (sl_ + sr_);
+    double ct = sqrt((gamma - 1.0) * (ht - 0.5 * (ut * ut + vt * vt)));
+    /* Einfeldt bounds */
+    double SL = fmin(ul - cl, ut - ct);
+    double SR = fmax(ur + cr, ut + ct);
+    double Ss = (pr - pl + rl * ul * (SL - ul) - rr * ur * (SR - ur))
+              / (rl * (SL - ul) - rr * (SR - ur));
+    double QsL[4], QsR[4];
+    double kl = rl * (SL - ul) / (SL - Ss);
+    QsL[0] = kl;
+    QsL[1] = kl * Ss;
+    QsL[2] = kl * vl;
+    QsL[3] = kl * (QL[3] / rl + (Ss - ul) * (Ss + pl / (rl * (SL - ul))));
+    double kr = rr * (SR - ur) / (SR - Ss);
+    QsR[0] = kr;
+    QsR[1] = kr * Ss;
+    QsR[2] = kr * vr;
+    QsR[3] = kr * (QR[3] / rr + (Ss - ur) * (Ss + pr / (rr * (SR - ur))));
+    for (int m = 0; m < 4; ++m) {
+        double diss = fabs(SL) * (QsL[m] - QL[m]) + fabs(Ss) * (QsR[m] - QsL[m])
+                    + fabs(SR) * (QR[m] - QsR[m]);
+        F[m] = 0.5 * (FL[m] + FR[m]) - 0.5 * diss;
+    }
+}
+
+/* Everything the flux at one interface j+1/2 reads, gathered along the
+ * normal.  Offsets are relative to cell j.                                */
+typedef struct {
+    double W[4][10];   /* (rho, un, ut, p) at offsets -4..5 (index m+4)     */
+    double G[4][6];    /* Delta_n * d/dn of W at offsets -2..3 (index m+2)  */
+    double T[2], GT[2];        /* T and Delta_n dT/dn at offsets 0, 1       */
+    double dun_t[2], dut_t[2]; /* d un/dt, d ut/dt (true derivatives) at 0,1 */
+    double psi[6];     /* detector at offsets -2..3                         */
+    double dn;         /* normal spacing                                    */
+} orc_line;
+
+/* Characteristic projection (reading R-CHAR) of primitive vectors for the
+ * normal Jacobian at mean density rb and sound speed cb.  Rows of L:
+ *   (0, -rb/2cb, 0, 1/2cb^2), (1, 0, 0, -1/cb^2), (0, 0, 1, 0), (0, rb/2cb, 0, 1/2cb^2) */
+static void char_fwd(const double U[4], double rb, double cb, double Wc[4])
+{
+    Wc[0] = -rb / (2.0 * cb) * U[1] + U[3] / (2.0 * cb * cb);
+    Wc[1] = U[0] - U[3] / (cb * cb);
+    Wc[2] = U[2];
+    Wc[3] = rb / (2.0 * cb) * U[1] + U[3] / (2.0 * cb * cb);
+}
+
+/* Columns of R = L^{-1}: (1, -cb/rb, 0, cb^2), (1,0,0,0), (0,0,1,0), (1, cb/rb, 0, cb^2). */
+static void char_bwd(const double Wc[4], double rb, double cb, double U[4])
+{
+    U[0] = Wc[0] + Wc[1] + Wc[3];
+    U[1] = cb / rb * (Wc[3] - Wc[0]);
+    U[2] = Wc[2];
+    U[3] = cb * cb * (Wc[0] + Wc[3]);
+}
+
+/* Flux through one interface (rotated frame). Returns sigma in *sig_out. */
+static void line_flux(const orc_line *L, const orc_cfg *c, double Fout[4], int *sig_out,
+                      int *nlimited)
+{
+    const double gamma = c->gamma;
+    /* eq. (buffer): psi_{j+1/2} = min(psi_{j-2..j+3}); sigma = 0 iff < psi_c */
+    double pmin = L->psi[0];
+    for (int k = 1; k < 6; ++k) pmin = fmin(pmin, L->psi[k]);
+    int sigma = (pmin < PSI_C) ? 0 : 1;
+    if (c->force_sigma == 0 || c->force_sigma == 1) sigma = c->force_sigma;
+    *sig_out = sigma;
+
+    double WL[4], WR[4], FL[4], FR[4];
+    int use_mp = (sigma == 0) || (c->mp_mode == 1);
+    if (!use_mp) {
+        /* Sec. 2.2: unlimited GRB states, eq. (eqn:grb), on primitives */
+        for (int m = 0; m < 4; ++m) {
+            WL[m] = grb_left(&L->W[m][4], &L->G[m][2]);
+            WR[m] = grb_right(&L->W[m][4], &L->G[m][2]);
+        }
+    } else {
+        /* Sec. 2.3: MEG7 in characteristic variables (R-CHAR) */
+        double rb = 0.5 * (L->W[0][4] + L->W[0][5]);
+        double pb = 0.5 * (L->W[3][4] + L->W[3][5]);
+        double cb = sqrt(gamma * pb / rb);
+        double cw[4][6], cg[4][6];
+        for (int k = 0; k < 6; ++k) {
+            double u[4], w[4], g[4], wg[4];
+            for (int m = 0; m < 4; ++m) { u[m] = L->W[m][k + 2]; g[m] = L->G[m][k]; }
+            char_fwd(u, rb, cb, w);
+            char_fwd(g, rb, cb, wg);
+            for (int m = 0; m < 4; ++m) { cw[m][k] = w[m]; cg[m][k] = wg[m]; }
+        }
+        double wl[4], wr[4];
+        for (int m = 0; m < 4; ++m) {
+            int la = 0, lb = 0;
+            wl[m] = orc_meg7_left(&cw[m][2], &cg[m][2], &la);
+            wr[m] = orc_meg7_right(&cw[m][2], &cg[m][2], &lb);
+            if (nlimited) *nlimited += la + lb;
+        }
+        char_bwd(wl, rb, cb, WL);
+        char_bwd(wr, rb, cb, WR);
+    }
+    if (sigma == 1) {
+        /* eqs. (flux-full), (flux-right) on f = F^c(U) at cell centres */
+        double f[4][10];
+        for (int k = 0; k < 10; ++k) {
+            double w[4], ff[4];
+            for (int m = 0; m < 4; ++m) w[m] = L->W[m][k];
+            conv_flux(w, gamma, ff);
+            for (int m = 0; m < 4; ++m) f[m][k] = ff[m];
+        }
+        for (int m = 0; m < 4; ++m) {
+            FL[m] = flux_left(&f[m][4]);
+            FR[m] = flux_right(&f[m][4]);
+        }
+    } else {
+        conv_flux(WL, gamma, FL);   /* F(Q_L) */
+        conv_flux(WR, gamma, FR);   /* F(Q_R) */
+    }
+    double Fc[4];
+    orc_hllc(WL, WR, FL, FR, gamma, Fc);
+
+    /* Sec. 2.1 viscous flux (R-VISC). */
+    double Fv[4] = {0.0, 0.0, 0.0, 0.0};
+    if (c->mu > 0.0) {
+        const double mu = c->mu, dn = L->dn;
+        /* eq. (eqn:alphad) with Phi' = dn dPhi/dn:
+         * dn*(dPhi/dn)_{j+1/2} = (Phi'_j + Phi'_{j+1})/2
+         *                        + alpha_v/2 (Phi_{j+1} - Phi'_{j+1}/2 - Phi_j - Phi'_j/2) */
+        double un0 = L->W[1][4], un1 = L->W[1][5];
+        double ut0 = L->W[2][4], ut1 = L->W[2][5];
+        double gun0 = L->G[1][2], gun1 = L->G[1][3];
+        double gut0 = L->G[2][2], gut1 = L->G[2][3];
+        double dun_n = (0.5 * (gun0 + gun1)
+                        + 0.5 * ALPHA_V * (un1 - 0.5 * gun1 - un0 - 0.5 * gun0)) / dn;
+        double dut_n = (0.5 * (gut0 + gut1)
+                        + 0.5 * ALPHA_V * (ut1 - 0.5 * gut1 - ut0 - 0.5 * gut0)) / dn;
+        double dT_n = (0.5 * (L->GT[0] + L->GT[1])
+                       + 0.5 * ALPHA_V * (L->T[1] - 0.5 * L->GT[1] - L->T[0] - 0.5 * L->GT[0])) / dn;
+        double dun_t = 0.5 * (L->dun_t[0] + L->dun_t[1]);
+        double dut_t = 0.5 * (L->dut_t[0] + L->dut_t[1]);
+        double unf = 0.5 * (un0 + un1), utf = 0.5 * (ut0 + ut1);
+        /* eq. (eqn:visc) in the normal frame */
+        double tnn = 2.0 / 3.0 * mu * (2.0 * dun_n - dut_t);
+        double tnt = mu * (dut_n + dun_t);
+        double qn = -mu / (c->Pr * (gamma - 1.0)) * dT_n;
+        Fv[1] = -tnn;
+        Fv[2] = -tnt;
+        Fv[3] = -(tnn * unf + tnt * utf) + qn;
+    }
+    for (int m = 0; m < 4; ++m) Fout[m] = Fc[m] + Fv[m];
+}
+
+/* ---------------------------------------------------------------------- */
+/* Grid-level residual.                                                    */
+/* ---------------------------------------------------------------------- */
+static int bc_index(int k, int n, int bc)
+{
+    if (bc == ORC_BC_PERIODIC) {
+        k %= n;
+        if (k < 0) k += n;
+        return k;
+    }
+    return k < 0 ? 0 : (k >= n ? n - 1 : k);
+}
+
+typedef struct {
+    int NX, NY;                 /* padded sizes */
+    double *W[4];               /* rho, u, v, p on the padded grid */
+    double *T;
+    double *Gx[5], *Gy[5];      /* Delta x d/dx, Delta y d/dy of rho,u,v,p,T */
+    double *psix, *psiy;
+} orc_fields;
+
+static void fields_free(orc_fields *F)
+{
+    for (int m = 0; m < 4; ++m) free(F->W[m]);
+    free(F->T);
+    for (int m = 0; m < 5; ++m) { free(F->Gx[m]); free(F->Gy[m]); }
+    free(F->psix); free(F->psiy);
+}
+
+static int fields_build(const orc_cfg *c, const double *Q, orc_fields *F)
+{
+    const int nx = c->nx, ny = c->ny;
+    const int NX = nx + 2 * NG, NY = ny + 2 * NG;
+    const size_t np = (size_t)NX * NY;
+    const size_t n = (size_t)nx * ny;
+    memset(F, 0, sizeof(*F));
+    F->NX = NX; F->NY = NY;
+    for (int m = 0; m < 4; ++m) F->W[m] = (double *)calloc(np, sizeof(double));
+    F->T = (double *)calloc(np, sizeof(double));
+    for (int m = 0; m < 5; ++m) {
+        F->Gx[m] = (double *)calloc(np, sizeof(double));
+        F->Gy[m] = (double *)calloc(np, sizeof(double));
+    }
+    F->psix = (double *)calloc(np, sizeof(double));
+    F->psiy = (double *)calloc(np, sizeof(double));
+    for (int m = 0; m < 4; ++m) if (!F->W[m]) return -1;
+    if (!F->T || !F->psix || !F->psiy) return -1;
+    for (int m = 0; m < 5; ++m) if (!F->Gx[m] || !F->Gy[m]) return -1;
+
+    const double gamma = c->gamma;
+    /* ghost cells (R-BC) and primitives, eq. (eqn:pressure), T (R-T) */
+#pragma omp parallel for schedule(static)
+    for (int I = 0; I < NY; ++I) {
+        int i = bc_index(I - NG, ny, c->bc_y);
+        for (int J = 0; J < NX; ++J) {
+            int j = bc_index(J - NG, nx, c->bc_x);
+            size_t s = (size_t)i * nx + j;
+            double rho = Q[s], mx = Q[n + s], my = Q[2 * n + s], E = Q[3 * n + s];
+            double u = mx / rho, v = my / rho;
+            double p = (gamma - 1.0) * (E - rho * (u * u + v * v) / 2.0);
+            size_t P = (size_t)I * NX + J;
+            F->W[0][P] = rho; F->W[1][P] = u; F->W[2][P] = v; F->W[3][P] = p;
+            F->T[P] = gamma * p / rho;
+        }
+    }
+    double *src[5] = {F->W[0], F->W[1], F->W[2], F->W[3], F->T};
+    /* eq. (eqn:six): gradients, computed once and shared */
+#pragma omp parallel for schedule(static)
+    for (int I = 0; I < NY; ++I) {
+        for (int J = 0; J < NX; ++J) {
+            size_t P = (size_t)I * NX + J;
+            for (int m = 0; m < 5; ++m) {
+                double px[7], py[7];
+                int okx = (J >= 3 && J < NX - 3), oky = (I >= 3 && I < NY - 3);
+                for (int k = -3; k <= 3; ++k) {
+                    px[k + 3] = okx ? src[m][P + k] : 0.0;
+                    py[k + 3] = oky ? src[m][P + (ptrdiff_t)k * NX] : 0.0;
+                }
+                F->Gx[m][P] = okx ? orc_grad6(px) : 0.0;
+                F->Gy[m][P] = oky ? orc_grad6(py) : 0.0;
+            }
+            /* detector on density, one per direction */
+            const double *r = F->W[0];
+            F->psix[P] = (J >= 2 && J < NX - 2)
+                ? orc_psi(r[P - 2], r[P - 1], r[P], r[P + 1], r[P + 2]) : 1.0;
+            F->psiy[P] = (I >= 2 && I < NY - 2)
+                ? orc_psi(r[P - 2 * NX], r[P - NX], r[P], r[P + NX], r[P + 2 * NX]) : 1.0;
+        }
+    }
+    return 0;
+}
+
+/* Gather the line for x-interface (j+1/2, i), j in [-1, nx-1]. */
+static void gather_x(const orc_cfg *c, const orc_fields *F, int i, int j, orc_line *L)
+{
+    const int NX = F->NX;
+    size_t P0 = (size_t)(i + NG) * NX + (j + NG);
+    const int perm[4] = {0, 1, 2, 3}; /* (rho, u, v, p) -> (rho, un=u, ut=v, p) */
+    for (int m = 0; m < 4; ++m) {
+        for (int k = -4; k <= 5; ++k) L->W[m][k + 4] = F->W[perm[m]][P0 + k];
+        for (int k = -2; k <= 3; ++k) L->G[m][k + 2] = F->Gx[perm[m]][P0 + k];
+    }
+    for (int k = 0; k < 2; ++k) {
+        L->T[k] = F->T[P0 + k];
+        L->GT[k] = F->Gx[4][P0 + k];
+        L->dun_t[k] = F->Gy[1][P0 + k] / ((c->y1 - c->y0) / c->ny);
+        L->dut_t[k] = F->Gy[2][P0 + k] / ((c->y1 - c->y0) / c->ny);
+    }
+    for (int k = -2; k <= 3; ++k) L->psi[k + 2] = F->psix[P0 + k];
+    L->dn = (c->x1 - c->x0) / c->nx;
+}
+
+/* Gather the line for y-interface (j, i+1/2), i in [-1, ny-1]. */
+static void gather_y(const orc_cfg *c, const orc_fields *F, int i, int j, orc_line *L)
+{
+    const int NX = F->NX;
+    size_t P0 = (size_t)(i + NG) * NX + (j + NG);
+    const int perm[4] = {0, 2, 1, 3}; /* (rho, u, v, p) -> (rho, un=v, ut=u, p) */
+    for (int m = 0; m < 4; ++m) {
+        for (int k = -4; k <= 5; ++k) L->W[m][k + 4] = F->W[perm[m]][P0 + (ptrdiff_t)k * NX];
+        for (int k = -2; k <= 3; ++k) L->G[m][k + 2] = F->Gy[perm[m]][P0 + (ptrdiff_t)k * NX];
+    }
+    for (int k = 0; k < 2; ++k) {
+        L->T[k] = F->T[P0 + (size_t)k * NX];
+        L->GT[k] = F->Gy[4][P0 + (size_t)k * NX];
+        L->dun_t[k] = F->Gx[2][P0 + (size_t)k * NX] / ((c->x1 - c->x0) / c->nx);
+        L->dut_t[k] = F->Gx[1][P0 + (size_t)k * NX] / ((c->x1 - c->x0) / c->nx);
+    }
+    for (int k = -2; k <= 3; ++k) L->psi[k + 2] = F->psiy[P0 + (ptrdiff_t)k * NX];
+    L->dn = (c->y1 - c->y0) / c->ny;
+}
+
+static int cfg_ok(const orc_cfg *c)
+{
+    return c && c->nx >= 2 * NG && c->ny >= 2 * NG && c->gamma > 1.0 && c->mu >= 0.0
+        && c->Pr > 0.0 && c->x1 > c->x0 && c->y1 > c->y0;
+}
+
+/* eqs. (eqn-differencing_residual), (deriv): Res = -dF/dx - dG/dy.
+ * Q, Res: SoA [4][ny][nx], x fastest.  sig_x: [ny][nx+1] (interface j+1/2 at
+ * column j+1), sig_y: [ny+1][nx] (interface i+1/2 at row i+1); may be NULL.
+ * Returns the number of MP-limited components (diagnostic) or -1. */
+long orc_residual(const orc_cfg *c, const double *Q, double *Res, uint8_t *sig_x,
+                  uint8_t *sig_y)
+{
+    if (!cfg_ok(c)) return -1;
+    const int nx = c->nx, ny = c->ny;
+    const size_t n = (size_t)nx * ny;
+    orc_fields F;
+    if (fields_build(c, Q, &F) != 0) { fields_free(&F); return -1; }
+    double *Fx = (double *)malloc(sizeof(double) * 4 * (size_t)ny * (nx + 1));
+    double *Fy = (double *)malloc(sizeof(double) * 4 * (size_t)(ny + 1) * nx);
+    if (!Fx || !Fy) { free(Fx); free(Fy); fields_free(&F); return -1; }
+    const size_t nfx = (size_t)ny * (nx + 1), nfy = (size_t)(ny + 1) * nx;
+    long nlim = 0;
+
+#pragma omp parallel for schedule(static) reduction(+ : nlim)
+    for (int i = 0; i < ny; ++i) {
+        for (int j = -1; j < nx; ++j) {
+            orc_line L; double f[4]; int sg; int nl = 0;
+            gather_x(c, &F, i, j, &L);
+            line_flux(&L, c, f, &sg, &nl);
+            nlim += nl;
+            size_t s = (size_t)i * (nx + 1) + (j + 1);
+            for (int m = 0; m < 4; ++m) Fx[m * nfx + s] = f[m];
+            if (sig_x) sig_x[s] = (uint8_t)sg;
+        }
+    }
+#pragma omp parallel for schedule(static) reduction(+ : nlim)
+    for (int i = -1; i < ny; ++i) {
+        for (int j = 0; j < nx; ++j) {
+            orc_line L; double f[4]; int sg; int nl = 0;
+            gather_y(c, &F, i, j, &L);
+            line_flux(&L, c, f, &sg, &nl);
+            nlim += nl;
+            size_t s = (size_t)(i + 1) * nx + j;
+            /* rotate back: (rho, rho v, rho u, E) -> (rho, rho u, rho v, E) */
+            Fy[0 * nfy + s] = f[0];
+            Fy[1 * nfy + s] = f[2];
+            Fy[2 * nfy + s] = f[1];
+            Fy[3 * nfy + s] = f[3];
+            if (sig_y) sig_y[s] = (uint8_t)sg;
+        }
+    }
+    const double dx = (c->x1 - c->x0) / nx, dy = (c->y1 - c->y0) / ny;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < ny; ++i) {
+        for (int j = 0; j < nx; ++j) {
+            size_t s = (size_t)i * nx + j;
+            for (int m = 0; m < 4; ++m) {
+                double dFdx = (Fx[m * nfx + (size_t)i * (nx + 1) + j + 1]
+                               - Fx[m * nfx + (size_t)i * (nx + 1) + j]) / dx;
+                double dGdy = (Fy[m * nfy + (size_t)(i + 1) * nx + j]
+                               - Fy[m * nfy + (size_t)i * nx + j]) / dy;
+                Res[m * n + s] = -dFdx - dGdy;
+            }
+        }
+    }
+    free(Fx); free(Fy);
+    fields_free(&F);
+    return nlim;
+}
+
+/* eq. (rk): one stage of the third-order TVD Runge-Kutta scheme.
+ * stage 1: Qout = Qn + dt R(Qn)            (Qk must equal Qn)
+ * stage 2: Qout = 3/4 Qn + 1/4 Qk + 1/4 dt R(Qk)
+ * stage 3: Qout = 1/3 Qn + 2/3 Qk + 2/3 dt R(Qk)                          */
+long orc_rk_stage(const orc_cfg *c, int stage, double dt, const double *Qn,
+                  const double *Qk, double *Qout, uint8_t *sig_x, uint8_t *sig_y)
+{
+    if (!cfg_ok(c) || stage < 1 || stage > 3) return -1;
+    const size_t N = 4 * (size_t)c->nx * c->ny;
+    double *R = (double *)malloc(sizeof(double) * N);
+    if (!R) return -1;
+    long nl = orc_residual(c, Qk, R, sig_x, sig_y);
+    if (nl < 0) { free(R); return -1; }
+#pragma omp parallel for schedule(static)
+    for (size_t s = 0; s < N; ++s) {
+        if (stage == 1)
+            Qout[s] = Qn[s] + dt * R[s];
+        else if (stage == 2)
+            Qout[s] = 3.0 / 4.0 * Qn[s] + 1.0 / 4.0 * Qk[s] + 1.0 / 4.0 * dt * R[s];
+        else
+            Qout[s] = 1.0 / 3.0 * Qn[s] + 2.0 / 3.0 * Qk[s] + 2.0 / 3.0 * dt * R[s];
+    }
+    free(R);
+    return nl;
+}
+
+/* Sec. 2.5 time step:
+ * dt = CFL min( (1/alpha_v) min(dx^2/nu, dy^2/nu), min(dx/(|u|+c), dy/(|v|+c)) ) */
+double orc_dt(const orc_cfg *c, const double *Q, double cfl)
+{
+    if (!cfg_ok(c)) return -1.0;
+    const int nx = c->nx, ny = c->ny;
+    const size_t n = (size_t)nx * ny;
+    const double dx = (c->x1 - c->x0) / nx, dy = (c->y1 - c->y0) / ny;
+    const double gamma = c->gamma;
+    double conv = INFINITY, visc = INFINITY;
+#pragma omp parallel for schedule(static) reduction(min : conv, visc)
+    for (size_t s = 0; s < n; ++s) {
+        double rho = Q[s], u = Q[n + s] / rho, v = Q[2 * n + s] / rho;
+        double p = (gamma - 1.0) * (Q[3 * n + s] - rho * (u * u + v * v) / 2.0);
+        double cs = sqrt(gamma * p / rho);
+        conv = fmin(conv, fmin(dx / (fabs(u) + cs), dy / (fabs(v) + cs)));
+        if (c->mu > 0.0) {
+            double nu = c->mu / rho;
+            visc = fmin(visc, fmin(dx * dx / nu, dy * dy / nu));
+        }
+    }
+    return cfl * fmin(visc / ALPHA_V, conv);
+}
+
+/* One full SSP-RK3 step with dt from Qn (for trajectories in tests):
+ * Q is advanced in place; returns dt. */
+double orc_step(const orc_cfg *c, double *Q, double cfl)
+{
+    const size_t N = 4 * (size_t)c->nx * c->ny;
+    double dt = orc_dt(c, Q, cfl);
+    double *Q1 = (double *)malloc(sizeof(double) * N);
+    double *Q2 = (double *)malloc(sizeof(double) * N);
+    if (!Q1 || !Q2 || dt <= 0.0) { free(Q1); free(Q2); return -1.0; }
+    orc_rk_stage(c, 1, dt, Q, Q, Q1, NULL, NULL);
+    orc_rk_stage(c, 2, dt, Q, Q1, Q2, NULL, NULL);
+    orc_rk_stage(c, 3, dt, Q, Q2, Q1, NULL, NULL);
+    memcpy(Q, Q1, sizeof(double) * N);
+    free(Q1); free(Q2);
+    return dt;
+}
+
+/* Per-interface flux evaluation for unit tests: W/G arrays as in orc_line. */
+void orc_line_flux(const double *W40, const double *G24, const double *T2, const double *GT2,
+                   const double *dun_t2, const double *dut_t2, const double *psi6,
+                   double dn, const orc_cfg *c, double F[4], int *sigma)
+{
+    orc_line L;
+    for (int m = 0; m < 4; ++m) {
+        for (int k = 0; k < 10; ++k) L.W[m][k] = W40[m * 10 + k];
+        for (int k = 0; k < 6; ++k) L.G[m][k] = G24[m * 6 + k];
+    }
+    for (int k = 0; k < 2; ++k) {
+        L.T[k] = T2[k]; L.GT[k] = GT2[k]; L.dun_t[k] = dun_t2[k]; L.dut_t[k] = dut_t2[k];
+    }
+    for (int k = 0; k < 6; ++k) L.psi[k] = psi6[k];
+    L.dn = dn;
+    line_flux(&L, c, F, sigma, NULL);
+}
+
+/* Plain detector flags chi = [psi_x < psi_c or psi_y < psi_c] per cell
+ * (the per-cell label the learned detector is trained on), psi_x/psi_y
+ * exported too (any pointer may be NULL). */
+int orc_cell_flags(const orc_cfg *c, const double *Q, uint8_t *chi, double *psix,
+                   double *psiy)
+{
+    if (!cfg_ok(c)) return -1;
+    orc_fields F;
+    if (fields_build(c, Q, &F) != 0) { fields_free(&F); return -1; }
+    const int nx = c->nx, ny = c->ny;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < ny; ++i)
+        for (int j = 0; j < nx; ++j) {
+            size_t P = (size_t)(i + NG) * F.NX + (j + NG);
+            size_t s = (size_t)i * nx + j;
+            if (psix) psix[s] = F.psix[P];
+            if (psiy) psiy[s] = F.psiy[P];
+            if (chi) chi[s] = (uint8_t)((F.psix[P] < PSI_C) || (F.psiy[P] < PSI_C));
+        }
+    fields_free(&F);
+    return 0;
+}

@@ -1,0 +1,185 @@
+"""ctypes front end of the C oracle (test infrastructure only).
+
+Arrays are numpy float64, structure of arrays [4][ny][nx] with x fastest:
+Q = (rho, rho u, rho v, E).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from .build import ensure_built
+
+BC_PERIODIC = 0
+BC_TRANSMISSIVE = 1
+
+
+class OrcCfg(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int), ("ny", C.c_int),
+        ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+        ("bc_x", C.c_int), ("bc_y", C.c_int),
+        ("gamma", C.c_double), ("mu", C.c_double), ("Pr", C.c_double),
+        ("mp_mode", C.c_int), ("force_sigma", C.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = ensure_built()
+        L = C.CDLL(path)
+        dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        up = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+        L.orc_residual.restype = C.c_long
+        L.orc_residual.argtypes = [C.POINTER(OrcCfg), dp, dp, C.c_void_p, C.c_void_p]
+        L.orc_rk_stage.restype = C.c_long
+        L.orc_rk_stage.argtypes = [C.POINTER(OrcCfg), C.c_int, C.c_double, dp, dp, dp,
+                                   C.c_void_p, C.c_void_p]
+        L.orc_dt.restype = C.c_double
+        L.orc_dt.argtypes = [C.POINTER(OrcCfg), dp, C.c_double]
+        L.orc_step.restype = C.c_double
+        L.orc_step.argtypes = [C.POINTER(OrcCfg), dp, C.c_double]
+        L.orc_detector_eps.restype = C.c_double
+        L.orc_detector_eps.argtypes = []
+        L.orc_psi.restype = C.c_double
+        L.orc_psi.argtypes = [C.c_double] * 5
+        L.orc_grad6.restype = C.c_double
+        L.orc_grad6.argtypes = [dp]
+        L.orc_table.restype = C.c_int
+        L.orc_table.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.orc_apply_interface.restype = None
+        L.orc_apply_interface.argtypes = [dp, dp, dp]
+        L.orc_meg7_left.restype = C.c_double
+        L.orc_meg7_left.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int)]
+        L.orc_meg7_right.restype = C.c_double
+        L.orc_meg7_right.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int)]
+        L.orc_hllc.restype = None
+        L.orc_hllc.argtypes = [dp, dp, dp, dp, C.c_double, dp]
+        L.orc_line_flux.restype = None
+        L.orc_line_flux.argtypes = [dp, dp, dp, dp, dp, dp, dp, C.c_double,
+                                    C.POINTER(OrcCfg), dp, C.POINTER(C.c_int)]
+        L.orc_cell_flags.restype = C.c_int
+        L.orc_cell_flags.argtypes = [C.POINTER(OrcCfg), dp, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def make_cfg(nx, ny, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc_x=BC_PERIODIC, bc_y=BC_PERIODIC,
+             gamma=1.4, mu=0.0, Pr=0.72, mp_mode=0, force_sigma=-1):
+    return OrcCfg(nx, ny, x0, x1, y0, y1, bc_x, bc_y, gamma, mu, Pr, mp_mode, force_sigma)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def residual(cfg, Q, want_flags=False):
+    """Res = Res(Q) (eq. eqn-differencing_residual).  Returns Res or
+    (Res, sig_x [ny][nx+1], sig_y [ny+1][nx], n_mp_limited)."""
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    R = np.empty_like(Q)
+    sx = np.zeros((cfg.ny, cfg.nx + 1), np.uint8) if want_flags else None
+    sy = np.zeros((cfg.ny + 1, cfg.nx), np.uint8) if want_flags else None
+    nl = lib().orc_residual(C.byref(cfg), Q, R, _ptr(sx), _ptr(sy))
+    if nl < 0:
+        raise ValueError("oracle residual: bad configuration")
+    if want_flags:
+        return R, sx, sy, nl
+    return R
+
+
+def rk_stage(cfg, stage, dt, Qn, Qk, want_flags=False):
+    Qn = np.ascontiguousarray(Qn, dtype=np.float64)
+    Qk = np.ascontiguousarray(Qk, dtype=np.float64)
+    out = np.empty_like(Qn)
+    sx = np.zeros((cfg.ny, cfg.nx + 1), np.uint8) if want_flags else None
+    sy = np.zeros((cfg.ny + 1, cfg.nx), np.uint8) if want_flags else None
+    nl = lib().orc_rk_stage(C.byref(cfg), stage, dt, Qn, Qk, out, _ptr(sx), _ptr(sy))
+    if nl < 0:
+        raise ValueError("oracle rk stage: bad arguments")
+    if want_flags:
+        return out, sx, sy
+    return out
+
+
+def dt(cfg, Q, cfl):
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    return lib().orc_dt(C.byref(cfg), Q, cfl)
+
+
+def step(cfg, Q, cfl):
+    """One SSP-RK3 step in place; returns dt."""
+    assert Q.flags.c_contiguous and Q.dtype == np.float64
+    return lib().orc_step(C.byref(cfg), Q, cfl)
+
+
+def detector_eps():
+    return lib().orc_detector_eps()
+
+
+def psi(rm2, rm1, r0, rp1, rp2):
+    return lib().orc_psi(rm2, rm1, r0, rp1, rp2)
+
+
+def grad6(p7):
+    return lib().orc_grad6(np.ascontiguousarray(p7, dtype=np.float64))
+
+
+def table(which):
+    num = (C.c_int * 16)()
+    den = C.c_int()
+    n = lib().orc_table(which, num, C.byref(den))
+    return [num[k] for k in range(n)], den.value
+
+
+def apply_interface(v10, g6):
+    out = np.empty(4)
+    lib().orc_apply_interface(np.ascontiguousarray(v10, np.float64),
+                              np.ascontiguousarray(g6, np.float64), out)
+    return out
+
+
+def meg7_left(p6, g6):
+    """MEG7 left value at j+1/2; p6, g6 hold offsets -2..3 (cell j at index 2)."""
+    p = np.ascontiguousarray(p6, np.float64)
+    g = np.ascontiguousarray(g6, np.float64)
+    lim = C.c_int()
+    v = lib().orc_meg7_left(p.ctypes.data + 16, g.ctypes.data + 16, C.byref(lim))
+    return v, lim.value
+
+
+def meg7_right(p6, g6):
+    p = np.ascontiguousarray(p6, np.float64)
+    g = np.ascontiguousarray(g6, np.float64)
+    lim = C.c_int()
+    v = lib().orc_meg7_right(p.ctypes.data + 16, g.ctypes.data + 16, C.byref(lim))
+    return v, lim.value
+
+
+def hllc(WL, WR, FL, FR, gamma=1.4):
+    out = np.empty(4)
+    lib().orc_hllc(*[np.ascontiguousarray(a, np.float64) for a in (WL, WR, FL, FR)],
+                   gamma, out)
+    return out
+
+
+def cell_flags(cfg, Q):
+    """Per-cell plain detector label chi and psi_x, psi_y."""
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    chi = np.zeros((cfg.ny, cfg.nx), np.uint8)
+    px = np.zeros((cfg.ny, cfg.nx))
+    py = np.zeros((cfg.ny, cfg.nx))
+    if lib().orc_cell_flags(C.byref(cfg), Q, _ptr(chi), _ptr(px), _ptr(py)) != 0:
+        raise ValueError("oracle cell flags: bad configuration")
+    return chi, px, py
+
+
+def threads():
+    """OpenMP threads the oracle will use (OMP_NUM_THREADS or all cores)."""
+    v = os.environ.get("OMP_NUM_THREADS")
+    return int(v) if v else os.cpu_count()

@@ -1,0 +1,199 @@
+"""Seeded synthetic initial data for the MEG7 hot path.
+
+This module only builds initial states.  It holds none of the scheme's
+arithmetic: it is shared by the CPU oracle tests and the GPU path so both
+see the same bits.  Every state is returned as a float64 numpy array
+Q[4][ny][nx] = (rho, rho u, rho v, E), x fastest, with
+E = p/(gamma-1) + rho (u^2+v^2)/2 (the ideal-gas law of Sec. 1), and a
+``Problem`` record holding the domain, boundary types and fluid constants.
+
+Families
+  vortex     isentropic vortex of the order-of-accuracy example (strength 5,
+             Gaussian profile, free stream rho=u=v=p=1), periodic.
+  riemann    four-quadrant Riemann problem in the layout of the paper's 2D
+             Riemann example (split at (0.8, 0.8)), states drawn from a seed,
+             transmissive boundaries.
+  shear      periodic double shear layer, tanh profile +/-0.5, Mach 0.3,
+             seeded sinusoidal perturbation on modes 1-8, Re = 1e4, Pr = 0.72.
+"""
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+BC_PERIODIC = 0
+BC_TRANSMISSIVE = 1
+GAMMA = 1.4
+
+
+@dataclass
+class Problem:
+    family: str
+    nx: int
+    ny: int
+    x0: float
+    x1: float
+    y0: float
+    y1: float
+    bc_x: int
+    bc_y: int
+    gamma: float
+    mu: float
+    Pr: float
+    cfl: float
+    seed: int = 0
+    Q: np.ndarray = field(default=None, repr=False)
+
+    @property
+    def dx(self):
+        return (self.x1 - self.x0) / self.nx
+
+    @property
+    def dy(self):
+        return (self.y1 - self.y0) / self.ny
+
+    def geometry(self):
+        return (self.x0, self.x1, self.y0, self.y1, self.bc_x, self.bc_y)
+
+
+def cell_centres(nx, ny, x0, x1, y0, y1):
+    x = x0 + (np.arange(nx) + 0.5) * (x1 - x0) / nx
+    y = y0 + (np.arange(ny) + 0.5) * (y1 - y0) / ny
+    return np.meshgrid(x, y, indexing="xy")
+
+
+def prim_to_state(rho, u, v, p, gamma=GAMMA):
+    """Stack primitive fields into the conservative SoA layout."""
+    Q = np.empty((4,) + rho.shape, np.float64)
+    Q[0] = rho
+    Q[1] = rho * u
+    Q[2] = rho * v
+    Q[3] = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    return Q
+
+
+# ---------------------------------------------------------------- vortex ---
+def vortex_fields(X, Y, xc, yc, eps=5.0, gamma=GAMMA, period=None):
+    """Isentropic vortex (order-of-accuracy example of Sec. 3) centred at
+    (xc, yc); with ``period`` = (Lx, Ly) the nearest periodic image is used."""
+    dx = X - xc
+    dy = Y - yc
+    if period is not None:
+        Lx, Ly = period
+        dx = dx - Lx * np.round(dx / Lx)
+        dy = dy - Ly * np.round(dy / Ly)
+    r2 = dx * dx + dy * dy
+    T = 1.0 - (gamma - 1.0) * eps * eps / (8.0 * gamma * math.pi ** 2) * np.exp(1.0 - r2)
+    rho = T ** (1.0 / (gamma - 1.0))
+    p = rho ** gamma
+    g = eps / (2.0 * math.pi) * np.exp(0.5 * (1.0 - r2))
+    u = 1.0 - g * dy
+    v = 1.0 + g * dx
+    return rho, u, v, p
+
+
+def vortex(n, L=10.0, t=0.0, cfl=0.5, eps=5.0, ny=None, x0=0.0):
+    """Vortex on [x0, x0+L]^2, centre at the box centre advected by (1,1) for
+    time t (exact solution of the Euler equations)."""
+    ny = n if ny is None else ny
+    X, Y = cell_centres(n, ny, x0, x0 + L, x0, x0 + L)
+    c = x0 + 0.5 * L
+    rho, u, v, p = vortex_fields(X, Y, c + t, c + t, eps=eps, period=(L, L))
+    P = Problem("vortex", n, ny, x0, x0 + L, x0, x0 + L, BC_PERIODIC, BC_PERIODIC,
+                GAMMA, 0.0, 0.72, cfl)
+    P.Q = prim_to_state(rho, u, v, p)
+    return P
+
+
+# --------------------------------------------------------------- riemann ---
+def riemann_states(seed):
+    """Quadrant states in the order NE, NW, SW, SE; each quadrant draws
+    rho~U[0.1,1.5], u~U[-0.8,0.8], v~U[-0.8,0.8], p~U[0.03,1.5] in that order
+    from numpy.random.default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(4):
+        rho = rng.uniform(0.1, 1.5)
+        u = rng.uniform(-0.8, 0.8)
+        v = rng.uniform(-0.8, 0.8)
+        p = rng.uniform(0.03, 1.5)
+        out.append((rho, u, v, p))
+    return out
+
+
+def paper_riemann_states():
+    """The configuration printed for the paper's 2D Riemann example."""
+    s = 4.0 / math.sqrt(11.0)
+    return [(1.5, 0.0, 0.0, 1.5), (33.0 / 62.0, s, 0.0, 0.3),
+            (77.0 / 558.0, s, s, 9.0 / 310.0), (33.0 / 62.0, 0.0, s, 0.3)]
+
+
+def riemann(n, seed=0, cfl=0.2, ny=None, states=None, split=(0.8, 0.8)):
+    ny = n if ny is None else ny
+    X, Y = cell_centres(n, ny, 0.0, 1.0, 0.0, 1.0)
+    st = riemann_states(seed) if states is None else states
+    xs, ys = split
+    quad = np.where(X > xs, np.where(Y > ys, 0, 3), np.where(Y > ys, 1, 2))
+    arr = np.array(st, np.float64)          # [4 quadrants][rho,u,v,p]
+    rho, u, v, p = (arr[quad, k] for k in range(4))
+    P = Problem("riemann", n, ny, 0.0, 1.0, 0.0, 1.0, BC_TRANSMISSIVE, BC_TRANSMISSIVE,
+                GAMMA, 0.0, 0.72, cfl, seed)
+    P.Q = prim_to_state(rho, u, v, p)
+    return P
+
+
+# ----------------------------------------------------------------- shear ---
+def shear(n, seed=0, cfl=0.2, ny=None, delta=0.02, mach=0.3, Re=1.0e4, Pr=0.72,
+          amp=1.0e-2, modes=8):
+    ny = n if ny is None else ny
+    X, Y = cell_centres(n, ny, 0.0, 1.0, 0.0, 1.0)
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.0, 1.0, modes)
+    a = a / a.sum()
+    phi = rng.uniform(0.0, 2.0 * math.pi, modes)
+    u = np.where(Y < 0.5, 0.5 * np.tanh((Y - 0.25) / delta),
+                 0.5 * np.tanh((0.75 - Y) / delta))
+    env = np.exp(-((Y - 0.25) / 0.05) ** 2) + np.exp(-((Y - 0.75) / 0.05) ** 2)
+    v = np.zeros_like(X)
+    for k in range(modes):
+        v += a[k] * np.sin(2.0 * math.pi * (k + 1) * X + phi[k])
+    v = amp * v * env
+    rho = np.ones_like(X)
+    c = 0.5 / mach
+    p = rho * c * c / GAMMA
+    mu = 1.0 * 1.0 * 1.0 / Re          # rho * delta U * L / Re
+    P = Problem("shear", n, ny, 0.0, 1.0, 0.0, 1.0, BC_PERIODIC, BC_PERIODIC,
+                GAMMA, mu, Pr, cfl, seed)
+    P.Q = prim_to_state(rho, u, v, p)
+    return P
+
+
+# ------------------------------------------------------------------ misc ---
+def free_stream(n, rho=1.0, u=0.3, v=-0.2, p=0.7, bc=BC_PERIODIC, mu=0.0, ny=None):
+    ny = n if ny is None else ny
+    shape = (ny, n)
+    P = Problem("free", n, ny, 0.0, 1.0, 0.0, 1.0, bc, bc, GAMMA, mu, 0.72, 0.2)
+    P.Q = prim_to_state(np.full(shape, rho), np.full(shape, u), np.full(shape, v),
+                        np.full(shape, p))
+    return P
+
+
+def make(family, n, seed=0, **kw):
+    if family == "vortex":
+        return vortex(n, **kw)
+    if family == "riemann":
+        return riemann(n, seed=seed, **kw)
+    if family == "shear":
+        return shear(n, seed=seed, **kw)
+    raise ValueError(family)
+
+
+def batch_spec(nprob=512, seed=0, nmin=64, nmax=768):
+    """Sizes and families of the batched workload: side n ~ U{nmin..nmax}
+    (square grids), family uniform over {vortex, riemann, shear}, per-problem
+    seed 10000 + index."""
+    rng = np.random.default_rng(seed)
+    sides = rng.integers(nmin, nmax + 1, nprob)
+    fams = rng.integers(0, 3, nprob)
+    names = ("vortex", "riemann", "shear")
+    return [(names[f], int(s), 10000 + k) for k, (f, s) in enumerate(zip(fams, sides))]
