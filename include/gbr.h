@@ -1,0 +1,125 @@
+/*
+ * gbr.h -- C ABI of the MI355X (gfx950) implementation of the MEG7
+ * gradient-based reconstruction hot path (Chamarthi, arXiv 2305.00762):
+ * the conservative residual of the 2D compressible Navier-Stokes equations
+ * and the SSP Runge-Kutta stage update, on device-resident
+ * structure-of-arrays state.
+ *
+ * Conventions shared by every call
+ *   - State arrays Q, Res, Qn, Qk, Qout are device pointers to float64 SoA
+ *     [4][ny][nx], x fastest: Q = (rho, rho u, rho v, E) (paper Sec. 1,
+ *     eq. CNS-base).  They are owned by the caller, must not overlap unless
+ *     stated, and are only accessed during the call's stream work.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All calls are asynchronous and stream ordered; argument errors are
+ *     reported before anything is enqueued.
+ *   - Every call returns GBR_OK (0) or a negative GBR_E* code; no exception
+ *     or abort crosses the ABI.  A context is used by one host thread at a
+ *     time; contexts are independent.
+ *   - Device faults cannot be reported asynchronously: gbr_check()
+ *     synchronises the stream and reports GBR_ESTATE if a kernel saw a
+ *     non-finite value or a non-positive density or pressure.
+ */
+#ifndef GBR_H
+#define GBR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GBR_OK = 0,
+    GBR_EINVAL = -1,       /* bad argument                                   */
+    GBR_ENOMEM = -2,       /* device allocation failed                       */
+    GBR_EDEVICE = -3,      /* HIP runtime error                              */
+    GBR_ESTATE = -4,       /* non-finite / non-positive rho or p seen        */
+    GBR_EUNSUPPORTED = -5  /* option not available in this build             */
+};
+
+enum { GBR_BC_PERIODIC = 0, GBR_BC_TRANSMISSIVE = 1 };
+enum { GBR_RECON_PRIM = 0 };
+enum { GBR_MP_FLAGGED = 0 };
+enum { GBR_PREC_FP64 = 0, GBR_PREC_FP32_BULK = 1 };
+enum { GBR_DET_PLAIN = 0, GBR_DET_MLP = 1 };
+
+typedef struct gbr_ctx gbr_ctx;
+
+/* Human-readable text of a status code (static storage). */
+const char *gbr_strerror(int status);
+
+/* Version string of the library (static storage). */
+const char *gbr_version(void);
+
+/* Create a context for an nx x ny grid (paper Sec. 1: uniform Cartesian
+ * cells, values at cell centres) with ratio of specific heats gamma
+ * (eq. eqn:pressure), constant dynamic viscosity mu (mu = 0: Euler) and
+ * Prandtl number Pr (eq. eqn:visc).  Requires nx, ny >= 12 (twice the
+ * 6-cell stencil reach), gamma > 1, mu >= 0, Pr > 0.  Allocates only
+ * context scratch on the current HIP device; the default geometry is
+ * [0,1]^2, periodic, and the default scheme is primitive reconstruction,
+ * MP limiting at flagged interfaces, FP64, plain detector.  *out receives
+ * the context (NULL on error). */
+int gbr_init(int nx, int ny, double gamma, double mu, double Pr, gbr_ctx **out);
+
+/* Release a context and its scratch (NULL is accepted). */
+int gbr_destroy(gbr_ctx *ctx);
+
+/* Domain [x0,x1] x [y0,y1] (cell sizes dx = (x1-x0)/nx, dy = (y1-y0)/ny) and
+ * boundary type per direction: GBR_BC_PERIODIC, or GBR_BC_TRANSMISSIVE
+ * (ghost cells copy the nearest interior cell). */
+int gbr_set_geometry(gbr_ctx *ctx, double x0, double x1, double y0, double y1,
+                     int bc_x, int bc_y);
+
+/* Scheme options: recon = GBR_RECON_PRIM (MEG7-prim, Sec. 2.2), mp_mode =
+ * GBR_MP_FLAGGED (MP limiter in characteristic variables at interfaces the
+ * detector flags, Secs. 2.3-2.4), precision = GBR_PREC_FP64 or
+ * GBR_PREC_FP32_BULK (gradients, reconstruction and fluxes in float32 with
+ * FP64 state, stage update and flux differencing), detector = GBR_DET_PLAIN
+ * (density detector, Sec. 2.4) or GBR_DET_MLP (learned detector, needs
+ * gbr_mlp_set_weights).  Unsupported combinations return GBR_EUNSUPPORTED
+ * and leave the scheme unchanged. */
+int gbr_set_scheme(gbr_ctx *ctx, int recon, int mp_mode, int precision, int detector);
+
+/* Res = Res(Q), the semi-discrete right-hand side of eq.
+ * (eqn-differencing_residual) with the flux differences of eq. (deriv).
+ * Q and Res: device [4][ny][nx]; must not overlap. */
+int gbr_residual(gbr_ctx *ctx, const double *Q, double *Res, void *stream);
+
+/* One stage of the third-order TVD Runge-Kutta scheme, eq. (rk):
+ *   stage 1: Qout = Qn + dt Res(Qn)                      (pass Qk == Qn)
+ *   stage 2: Qout = 3/4 Qn + 1/4 Qk + 1/4 dt Res(Qk)
+ *   stage 3: Qout = 1/3 Qn + 2/3 Qk + 2/3 dt Res(Qk)
+ * dt_dev: device pointer to one double (e.g. written by gbr_compute_dt), read
+ * on the device, so a whole step needs no host synchronisation.
+ * Qout must not overlap Qn or Qk. */
+int gbr_rk_stage(gbr_ctx *ctx, int stage, const double *dt_dev, const double *Qn,
+                 const double *Qk, double *Qout, void *stream);
+
+/* The time step of Sec. 2.5:
+ *   dt = cfl * min( (1/alpha_v) min(dx^2/nu, dy^2/nu), min(dx/(|u|+c), dy/(|v|+c)) )
+ * over all cells of Q, alpha_v = 4, nu = mu/rho, c = sqrt(gamma p/rho);
+ * written to the device double *dt_dev.  cfl > 0. */
+int gbr_compute_dt(gbr_ctx *ctx, const double *Q, double cfl, double *dt_dev,
+                   void *stream);
+
+/* Flag export (debugging and parity): when enabled, every residual or stage
+ * call records the detector outcome sigma (1 = smooth, 0 = flagged) of each
+ * interface in context buffers.  gbr_get_flags copies the last call's flags
+ * to sig_x [ny][nx+1] (x-interface j+1/2 of row i at [i][j+1]) and sig_y
+ * [ny+1][nx] (y-interface i+1/2 of column j at [i+1][j]); each may be a host
+ * or a device pointer, or NULL. */
+int gbr_export_flags(gbr_ctx *ctx, int enable);
+int gbr_get_flags(gbr_ctx *ctx, uint8_t *sig_x, uint8_t *sig_y, void *stream);
+
+/* Synchronise `stream`, return GBR_ESTATE if any kernel since the last check
+ * saw a non-finite value or rho <= 0 or p <= 0 in an interior cell, and
+ * clear that record. */
+int gbr_check(gbr_ctx *ctx, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GBR_H */

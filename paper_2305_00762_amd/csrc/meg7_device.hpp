@@ -1,0 +1,173 @@
+// Device-side building blocks of the MEG7 scheme (Chamarthi, arXiv
+// 2305.00762) for gfx950, in a frame rotated to the interface normal:
+// primitive vector W = (rho, un, ut, p), conservative (rho, rho un, rho ut, E).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gbr {
+
+// Constants of the scheme.
+constexpr double kAlphaV = 4.0;   // alpha-damping coefficient, Sec. 2.1 eq. (eqn:alphad)
+constexpr double kXiMP = 7.0;     // MP parameter xi, Sec. 2.3 eq. (eqn:alpha)
+constexpr double kMPTol = 1e-40;  // MP activation threshold, eq. (eqn:hocus/mp5Condition)
+constexpr double kPsiC = 0.5;     // detector threshold psi_c, Sec. 2.4 eq. (buffer)
+constexpr double kXiDet = 1e-3;   // detector xi, eq. (buffer)
+// eq. (buffer): eps = 0.9 psi_c / (1 - 0.9 psi_c) xi^2 (folded with IEEE rounding)
+constexpr double kDetEps = (0.9 * kPsiC) / (1.0 - 0.9 * kPsiC) * (kXiDet * kXiDet);
+
+// Sixth-order central first derivative, eq. (eqn:six), scaled by the
+// spacing: returns dx * dPhi/dx from Phi_{-3..3} (pm3 .. p3).
+__device__ __forceinline__ double grad6(double pm3, double pm2, double pm1, double p1,
+                                        double p2, double p3) {
+  return (45.0 * (p1 - pm1) - 9.0 * (p2 - pm2) + (p3 - pm3)) * (1.0 / 60.0);
+}
+
+// Density detector psi of Sec. 2.4 with eps in numerator and denominator.
+// Evaluated with one rounding per operation in a fixed order (no FMA
+// contraction) and an IEEE division, so that the decision psi < psi_c is
+// reproducible bit for bit.
+__device__ __attribute__((noinline)) double detector_psi(double rm2, double rm1, double r0,
+                                                         double rp1, double rp2) {
+#pragma clang fp contract(off)
+  double a = fabs(r0 - rm1) + fabs((r0 - 2.0 * rm1) + rm2);
+  double b = fabs(r0 - rp1) + fabs((r0 - 2.0 * rp1) + rp2);
+  double num = (2.0 * a) * b + kDetEps;
+  double den = (a * a + b * b) + kDetEps;
+  return num / den;
+}
+
+__device__ __forceinline__ double minmod(double a, double b) {
+  // (sign a + sign b)/2 * min(|a|,|b|), eq. (eqn:alpha)
+  double m = fmin(fabs(a), fabs(b));
+  return (a > 0.0 && b > 0.0) ? m : ((a < 0.0 && b < 0.0) ? -m : 0.0);
+}
+
+// GRB interface states, eq. (eqn:grb).  v[k] = Phi_{j+k-2} (k=0..5),
+// g[k] = Phi'_{j+k-2} (Phi' = dx dPhi/dx).
+__device__ __forceinline__ double grb_left(const double* v, const double* g) {
+  constexpr double s = 1.0 / 840.0;
+  return (3.0 * s) * (v[0] + v[4]) + (178.0 * s) * (v[1] + v[3]) + (478.0 * s) * v[2] +
+         (420.0 * s) * g[2] + (60.0 * s) * (g[1] - g[3]);
+}
+__device__ __forceinline__ double grb_right(const double* v, const double* g) {
+  constexpr double s = 1.0 / 840.0;
+  return (3.0 * s) * (v[1] + v[5]) + (178.0 * s) * (v[2] + v[4]) + (478.0 * s) * v[3] -
+         (420.0 * s) * g[3] + (60.0 * s) * (g[2] - g[4]);
+}
+
+// MP curvature d of eq. (eqn:mp-procedure) at the centre of v[-1..1], g[-1..1].
+__device__ __forceinline__ double mp_curv(double vm, double v0, double vp, double gm,
+                                          double gp) {
+  return 2.0 * (vp - 2.0 * v0 + vm) - 0.5 * (gp - gm);
+}
+
+// MEG7 left and right values at j+1/2 of one characteristic component
+// (Sec. 2.3): GRB value, the activation test, and the MP bounds.  v, g hold
+// offsets -2..3 around cell j.  The right value is the mirror image.
+__device__ __forceinline__ void meg7_pair(const double* v, const double* g, double& outL,
+                                          double& outR) {
+  const double dm1 = mp_curv(v[0], v[1], v[2], g[0], g[2]);
+  const double d0 = mp_curv(v[1], v[2], v[3], g[1], g[3]);
+  const double dp1 = mp_curv(v[2], v[3], v[4], g[2], g[4]);
+  const double dp2 = mp_curv(v[3], v[4], v[5], g[3], g[5]);
+  const double md = 0.5 * (v[2] + v[3]) - 0.5 * minmod(d0, dp1);
+  {
+    double phi = grb_left(v, g);
+    double pmp = v[2] + minmod(v[3] - v[2], kXiMP * (v[2] - v[1]));
+    if ((phi - v[2]) * (phi - pmp) > kMPTol) {
+      double ul = v[2] + kXiMP * (v[2] - v[1]);
+      double lc = 0.5 * (3.0 * v[2] - v[1]) + (4.0 / 3.0) * minmod(d0, dm1);
+      double lo = fmax(fmin(v[2], fmin(v[3], md)), fmin(v[2], fmin(ul, lc)));
+      double hi = fmin(fmax(v[2], fmax(v[3], md)), fmax(v[2], fmax(ul, lc)));
+      phi = phi + minmod(lo - phi, hi - phi);
+    }
+    outL = phi;
+  }
+  {
+    double phi = grb_right(v, g);
+    double pmp = v[3] + minmod(v[2] - v[3], kXiMP * (v[3] - v[4]));
+    if ((phi - v[3]) * (phi - pmp) > kMPTol) {
+      double ul = v[3] + kXiMP * (v[3] - v[4]);
+      double lc = 0.5 * (3.0 * v[3] - v[4]) + (4.0 / 3.0) * minmod(dp1, dp2);
+      double lo = fmax(fmin(v[3], fmin(v[2], md)), fmin(v[3], fmin(ul, lc)));
+      double hi = fmin(fmax(v[3], fmax(v[2], md)), fmax(v[3], fmax(ul, lc)));
+      phi = phi + minmod(lo - phi, hi - phi);
+    }
+    outR = phi;
+  }
+}
+
+// Normal convective flux of the state W (Sec. 1 flux vectors, rotated).
+__device__ __forceinline__ void conv_flux(const double W[4], double g1inv, double F[4]) {
+  const double E = W[3] * g1inv + 0.5 * W[0] * (W[1] * W[1] + W[2] * W[2]);
+  const double m = W[0] * W[1];
+  F[0] = m;
+  F[1] = m * W[1] + W[3];
+  F[2] = m * W[2];
+  F[3] = W[1] * (E + W[3]);
+}
+
+// HLLC with Einfeldt (Roe-average) bounds in the wave-sum form
+//   F = (F_L + F_R)/2 - (|S_L|(Q*_L - Q_L) + |S*|(Q*_R - Q*_L) + |S_R|(Q_R - Q*_R))/2
+// which is the canonical form of eq. (eqn:Riemann); F_L, F_R come from the
+// reconstruction (flux reconstruction in smooth regions, F(Q) at flags).
+__device__ __forceinline__ void hllc(const double WL[4], const double WR[4], const double FL[4],
+                                     const double FR[4], double gamma, double g1inv,
+                                     double F[4]) {
+  const double rl = WL[0], ul = WL[1], vl = WL[2], pl = WL[3];
+  const double rr = WR[0], ur = WR[1], vr = WR[2], pr = WR[3];
+  const double irl = 1.0 / rl, irr = 1.0 / rr;
+  const double El = pl * g1inv + 0.5 * rl * (ul * ul + vl * vl);
+  const double Er = pr * g1inv + 0.5 * rr * (ur * ur + vr * vr);
+  const double cl = sqrt(gamma * pl * irl), cr = sqrt(gamma * pr * irr);
+  const double hl = (El + pl) * irl, hr = (Er + pr) * irr;
+  const double sl = sqrt(rl), sr = sqrt(rr);
+  const double iss = 1.0 / (sl + sr);
+  const double ut = (sl * ul + sr * ur) * iss;
+  const double vt = (sl * vl + sr * vr) * iss;
+  const double ht = (sl * hl + sr * hr) * iss;
+  const double ct = sqrt((gamma - 1.0) * (ht - 0.5 * (ut * ut + vt * vt)));
+  const double SL = fmin(ul - cl, ut - ct);
+  const double SR = fmax(ur + cr, ut + ct);
+  const double ml = rl * (SL - ul), mr = rr * (SR - ur);
+  const double Ss = (pr - pl + ml * ul - mr * ur) / (ml - mr);
+  const double kl = ml / (SL - Ss), kr = mr / (SR - Ss);
+  const double QL[4] = {rl, rl * ul, rl * vl, El};
+  const double QR[4] = {rr, rr * ur, rr * vr, Er};
+  const double QsL[4] = {kl, kl * Ss, kl * vl, kl * (El * irl + (Ss - ul) * (Ss + pl / ml))};
+  const double QsR[4] = {kr, kr * Ss, kr * vr, kr * (Er * irr + (Ss - ur) * (Ss + pr / mr))};
+  const double aL = fabs(SL), aS = fabs(Ss), aR = fabs(SR);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const double diss = aL * (QsL[m] - QL[m]) + aS * (QsR[m] - QsL[m]) + aR * (QR[m] - QsR[m]);
+    F[m] = 0.5 * (FL[m] + FR[m]) - 0.5 * diss;
+  }
+}
+
+// Viscous interface flux (Sec. 2.1) added to F: normal derivatives of un,
+// ut, T by alpha-damping (eq. eqn:alphad, alpha_v = 4) from the shared
+// gradients, tangential derivatives and velocities as two-cell means.
+// g* are spacing-scaled normal gradients, d*_t true tangential derivatives.
+__device__ __forceinline__ void viscous_add(double un0, double un1, double ut0, double ut1,
+                                            double T0, double T1, double gun0, double gun1,
+                                            double gut0, double gut1, double gT0, double gT1,
+                                            double dunt0, double dunt1, double dutt0,
+                                            double dutt1, double inv_dn, double mu,
+                                            double kq, double F[4]) {
+  // dn * dPhi/dn at j+1/2 = (g0+g1)/2 + alpha_v/2 (Phi1 - g1/2 - Phi0 - g0/2)
+  const double a2 = 0.5 * kAlphaV;
+  const double dun = (0.5 * (gun0 + gun1) + a2 * (un1 - 0.5 * gun1 - un0 - 0.5 * gun0)) * inv_dn;
+  const double dut = (0.5 * (gut0 + gut1) + a2 * (ut1 - 0.5 * gut1 - ut0 - 0.5 * gut0)) * inv_dn;
+  const double dT = (0.5 * (gT0 + gT1) + a2 * (T1 - 0.5 * gT1 - T0 - 0.5 * gT0)) * inv_dn;
+  const double dunt = 0.5 * (dunt0 + dunt1), dutt = 0.5 * (dutt0 + dutt1);
+  const double unf = 0.5 * (un0 + un1), utf = 0.5 * (ut0 + ut1);
+  const double tnn = (2.0 / 3.0) * mu * (2.0 * dun - dutt);
+  const double tnt = mu * (dut + dunt);
+  const double qn = -kq * dT;  // kq = mu / (Pr (gamma - 1))
+  F[1] -= tnn;
+  F[2] -= tnt;
+  F[3] += -(tnn * unf + tnt * utf) + qn;
+}
+
+}  // namespace gbr

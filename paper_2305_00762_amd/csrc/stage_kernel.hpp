@@ -1,0 +1,414 @@
+// Fused MEG7 residual + SSP-RK3 stage kernel for gfx950 (FP64 path).
+//
+// One workgroup owns a TX x TY tile of cells.  It stages the tile plus a
+// 6-cell halo of primitive variables in LDS once (periodic wrap or
+// transmissive clamp in the index math), then sweeps x and y:
+//   pass 1 (per cell):      shared sixth-order gradients (eq. eqn:six),
+//                           density detector (Sec. 2.4), cell-centre fluxes,
+//                           tangential derivatives for the viscous terms;
+//   pass 2 (per interface): sigma from the 6-cell buffer; smooth interfaces
+//                           take GRB states + flux reconstruction + HLLC +
+//                           viscous flux at once; flagged ones are compacted
+//                           with a wavefront ballot into an LDS queue;
+//   pass 3 (queue):         characteristic MP (MEG7) states, F(Q), HLLC;
+//   pass 4 (per cell):      flux differences accumulated in registers.
+// The x sweep runs in sub-blocks of SX rows, the y sweep in sub-blocks of SY
+// columns, so the per-sweep buffers stay small.  The stage update (or the
+// residual store) follows in registers with one coalesced FP64 store.
+#pragma once
+#include "meg7_device.hpp"
+
+namespace gbr {
+
+enum : int { MODE_RESIDUAL = 0, MODE_STAGE1 = 1, MODE_STAGE2 = 2, MODE_STAGE3 = 3 };
+enum : unsigned { STATUS_BAD_STATE = 1u };
+
+struct StageParams {
+  const double* __restrict__ Qk;  // state the residual is evaluated on
+  const double* __restrict__ Qn;  // Q^n (stages 2, 3)
+  double* __restrict__ out;       // Res or Q^(k+1)
+  const double* __restrict__ dt;  // device scalar (stages)
+  uint8_t* sigx;                  // optional flag export [ny][nx+1]
+  uint8_t* sigy;                  // optional flag export [ny+1][nx]
+  unsigned* status;
+  int nx, ny, bcx, bcy;
+  int tiles_x, ntiles;
+  double inv_dx, inv_dy;
+  double gamma, g1inv, mu, kq;    // kq = mu / (Pr (gamma-1))
+  int mode;
+};
+
+__device__ __forceinline__ int bc_index(int k, int n, int bc) {
+  if (bc == 0) {
+    k %= n;
+    return k < 0 ? k + n : k;
+  }
+  return k < 0 ? 0 : (k >= n ? n - 1 : k);
+}
+
+template <int TX_, int TY_, int SX_, int SY_, int NT_, bool VISC_>
+struct TileCfg {
+  static constexpr int TX = TX_, TY = TY_, SX = SX_, SY = SY_, NT = NT_;
+  static constexpr bool VISC = VISC_;
+  static constexpr int H = 6;
+  static constexpr int RX = TX + 2 * H, RY = TY + 2 * H, RS = RX * RY;
+  static constexpr int NF = VISC ? 5 : 4;
+  static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+  template <int N, int NL>
+  struct Phase {
+    static constexpr int WD = N + 6, WF = N + 10, WE = N + 2, WFL = N + 1;
+    static constexpr int D = NF * NL * WD;
+    static constexpr int F = 4 * NL * (WF > WFL ? WF : WFL);
+    static constexpr int E = VISC ? 2 * NL * WE : 0;
+    static constexpr int TOT = D + F + E;
+  };
+  using PX = Phase<TX, SX>;
+  using PY = Phase<TY, SY>;
+  static constexpr int PH = cmax(PX::TOT, PY::TOT);
+  static constexpr int CHI = cmax(SX * PX::WD, SY * PY::WD);
+  static constexpr int QMAX = cmax(SX * PX::WFL, SY * PY::WFL);
+  static constexpr int CPT = (TX * TY + NT - 1) / NT;
+  static constexpr int LDS_BYTES = 8 * (NF * RS + PH) + CHI + 2 * QMAX + 16;
+};
+
+// Shared-memory views handed to the sweep.
+struct Lds {
+  double* U;
+  double* ph;
+  unsigned char* chi;
+  unsigned short* queue;
+  int* qcount;
+};
+
+template <class C, int DIR>
+__device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0, int tx0,
+                                      int ty0, double (&res)[C::CPT][4]) {
+  constexpr bool X = (DIR == 0);
+  constexpr int N = X ? C::TX : C::TY;
+  constexpr int NL = X ? C::SX : C::SY;
+  constexpr int NLINES = X ? C::TY : C::TX;
+  using PH = typename C::template Phase<N, NL>;
+  constexpr int WD = PH::WD, WF = PH::WF, WE = PH::WE, WFL = PH::WFL;
+  constexpr int RS = C::RS, RX = C::RX, H = C::H, NT = C::NT, NF = C::NF;
+  constexpr int SN = X ? 1 : RX;  // normal stride in the LDS tile
+  constexpr int ST = X ? RX : 1;  // tangential stride
+  constexpr int FN = X ? 1 : 2;   // field holding the normal velocity
+  constexpr int FT = X ? 2 : 1;   // field holding the tangential velocity
+  constexpr int IPT = (NL * WFL + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  const int nl = (NLINES - l0) < NL ? (NLINES - l0) : NL;
+  const double inv_dn = X ? P.inv_dx : P.inv_dy;
+  const double inv_dt = X ? P.inv_dy : P.inv_dx;
+
+  double* sD = L.ph;                       // [NF][NL x WD]  normal gradients (rotated order)
+  double* sF = sD + NF * NL * WD;          // [4][NL x WF]   cell fluxes; later [4][NL x WFL] interface fluxes
+  constexpr int FSTR = (WF > WFL ? WF : WFL) * NL;
+  double* sE = sF + 4 * FSTR;              // [2][NL x WE]   tangential derivatives of un, ut
+  // buffer index: lines fastest for y (lanes walk along x), positions fastest for x
+  auto bidx = [](int line, int p, int W) { return X ? line * W + p : p * NL + line; };
+  auto ridx = [&](int line, int pos) {
+    const int lx = X ? pos : l0 + line;
+    const int ly = X ? l0 + line : pos;
+    return (ly + H) * RX + (lx + H);
+  };
+  const int rot[5] = {0, FN, FT, 3, 4};
+
+  // ---- pass 1: per-cell quantities ----------------------------------------
+  for (int t = tid; t < NL * WF; t += NT) {
+    const int line = X ? t / WF : t % NL;
+    const int p = X ? t % WF : t / NL;
+    if (line >= nl) continue;
+    const int pos = p - 5;
+    const int r = ridx(line, pos);
+    const double* U = L.U;
+    {
+      const double W[4] = {U[r], U[FN * RS + r], U[FT * RS + r], U[3 * RS + r]};
+      double f[4];
+      conv_flux(W, P.g1inv, f);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) sF[m * FSTR + bidx(line, p, WF)] = f[m];
+    }
+    if (pos >= -3 && pos < N + 3) {
+      const int pd = pos + 3;
+#pragma unroll
+      for (int m = 0; m < NF; ++m) {
+        const double* u = U + rot[m] * RS + r;
+        sD[m * NL * WD + bidx(line, pd, WD)] =
+            grad6(u[-3 * SN], u[-2 * SN], u[-SN], u[SN], u[2 * SN], u[3 * SN]);
+      }
+      const double* rho = U + r;
+      const double psi = detector_psi(rho[-2 * SN], rho[-SN], rho[0], rho[SN], rho[2 * SN]);
+      L.chi[bidx(line, pd, WD)] = (psi < kPsiC) ? 1 : 0;
+    }
+    if (C::VISC && pos >= -1 && pos < N + 1) {
+      const int pe = pos + 1;
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const double* u = U + (m == 0 ? FN : FT) * RS + r;
+        sE[m * NL * WE + bidx(line, pe, WE)] =
+            grad6(u[-3 * ST], u[-2 * ST], u[-ST], u[ST], u[2 * ST], u[3 * ST]) * inv_dt;
+      }
+    }
+  }
+  if (tid == 0) *L.qcount = 0;
+  __syncthreads();
+
+  // ---- pass 2: interfaces, smooth branch; ballot-compact the flagged ------
+  double fsm[IPT][4];
+  bool has[IPT];
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    has[k] = false;
+    const int t = tid + k * NT;
+    bool flagged = false;
+    if (t < NL * WFL) {
+      const int line = X ? t / WFL : t % NL;
+      const int p = X ? t % WFL : t / NL;
+      const int pos = p - 1;  // interface pos + 1/2
+      if (line < nl) {
+        bool sigma = true;
+#pragma unroll
+        for (int q = 1; q <= 6; ++q) sigma = sigma && (L.chi[bidx(line, pos + q, WD)] == 0);
+        if (X) {
+          const int gi = ty0 + l0 + line, gj = tx0 + pos;
+          if (P.sigx && gi < P.ny && gj < P.nx) P.sigx[(size_t)gi * (P.nx + 1) + gj + 1] = sigma;
+        } else {
+          const int gj = tx0 + l0 + line, gi = ty0 + pos;
+          if (P.sigy && gj < P.nx && gi < P.ny) P.sigy[(size_t)(gi + 1) * P.nx + gj] = sigma;
+        }
+        flagged = !sigma;
+        if (sigma) {
+          const int r = ridx(line, pos);
+          double WL[4], WR[4], FL[4], FR[4];
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const double* u = L.U + rot[m] * RS + r;
+            double v[6], g[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) v[q] = u[(q - 2) * SN];
+#pragma unroll
+            for (int q = 1; q < 5; ++q) g[q] = sD[m * NL * WD + bidx(line, pos + q + 1, WD)];
+            g[0] = g[5] = 0.0;
+            WL[m] = grb_left(v, g);
+            WR[m] = grb_right(v, g);
+            // eqs. (flux-full), (flux-right) on the cell fluxes f_{j-4..j+5}
+            double f[10];
+#pragma unroll
+            for (int q = 0; q < 10; ++q) f[q] = sF[m * FSTR + bidx(line, pos + q + 1, WF)];
+            constexpr double s = 1.0 / 840.0;
+            FL[m] = (-s) * (f[0] + f[8]) + (2.0 * s) * f[1] + (22.0 * s) * f[2] +
+                    (-146.0 * s) * f[3] + (568.0 * s) * f[4] + (484.0 * s) * f[5] +
+                    (-104.0 * s) * f[6] + (16.0 * s) * f[7];
+            FR[m] = (-s) * (f[1] + f[9]) + (16.0 * s) * f[2] + (-104.0 * s) * f[3] +
+                    (484.0 * s) * f[4] + (568.0 * s) * f[5] + (-146.0 * s) * f[6] +
+                    (22.0 * s) * f[7] + (2.0 * s) * f[8];
+          }
+          hllc(WL, WR, FL, FR, P.gamma, P.g1inv, fsm[k]);
+          if (C::VISC) {
+            const double* U = L.U;
+            const int b0 = bidx(line, pos + 3, WD), b1 = bidx(line, pos + 4, WD);
+            viscous_add(U[FN * RS + r], U[FN * RS + r + SN], U[FT * RS + r], U[FT * RS + r + SN],
+                        U[4 * RS + r], U[4 * RS + r + SN], sD[1 * NL * WD + b0],
+                        sD[1 * NL * WD + b1], sD[2 * NL * WD + b0], sD[2 * NL * WD + b1],
+                        sD[4 * NL * WD + b0], sD[4 * NL * WD + b1],
+                        sE[0 * NL * WE + bidx(line, pos + 1, WE)],
+                        sE[0 * NL * WE + bidx(line, pos + 2, WE)],
+                        sE[1 * NL * WE + bidx(line, pos + 1, WE)],
+                        sE[1 * NL * WE + bidx(line, pos + 2, WE)], inv_dn, P.mu, P.kq, fsm[k]);
+          }
+          has[k] = true;
+        }
+      }
+    }
+    // wavefront ballot: append the flagged interfaces of this wave to the queue
+    const unsigned long long ball = __ballot(flagged);
+    if (ball) {
+      const int lane = __lane_id();
+      int base = 0;
+      if (lane == 0) base = atomicAdd(L.qcount, (int)__popcll(ball));
+      base = __shfl(base, 0);
+      if (flagged) {
+        const int rank = (int)__popcll(ball & ((1ull << lane) - 1ull));
+        L.queue[base + rank] = (unsigned short)t;
+      }
+    }
+  }
+  __syncthreads();  // every read of the cell fluxes is done: the buffer becomes the flux buffer
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    if (has[k]) {
+      const int t = tid + k * NT;
+      const int line = X ? t / WFL : t % NL;
+      const int p = X ? t % WFL : t / NL;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) sF[m * FSTR + bidx(line, p, WFL)] = fsm[k][m];
+    }
+  }
+
+  // ---- pass 3: compacted shock branch (characteristic MEG7, F(Q)) --------
+  const int nq = *L.qcount;
+  for (int qi = tid; qi < nq; qi += NT) {
+    const int t = L.queue[qi];
+    const int line = X ? t / WFL : t % NL;
+    const int p = X ? t % WFL : t / NL;
+    const int pos = p - 1;
+    const int r = ridx(line, pos);
+    const double* U = L.U;
+    // mean-state primitive eigenvectors of the normal Jacobian
+    const double rb = 0.5 * (U[r] + U[r + SN]);
+    const double pb = 0.5 * (U[3 * RS + r] + U[3 * RS + r + SN]);
+    const double cb = sqrt(P.gamma * pb / rb);
+    const double h2c = 0.5 / cb, ic2 = 1.0 / (cb * cb), h2c2 = 0.5 * ic2;
+    double cv[4][6], cg[4][6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const int rq = r + (q - 2) * SN;
+      const double w0 = U[rq], w1 = U[FN * RS + rq], w2 = U[FT * RS + rq], w3 = U[3 * RS + rq];
+      const int bq = bidx(line, pos + q + 1, WD);
+      const double g0 = sD[bq], g1 = sD[NL * WD + bq], g2 = sD[2 * NL * WD + bq],
+                   g3 = sD[3 * NL * WD + bq];
+      cv[0][q] = -rb * h2c * w1 + h2c2 * w3;
+      cv[1][q] = w0 - ic2 * w3;
+      cv[2][q] = w2;
+      cv[3][q] = rb * h2c * w1 + h2c2 * w3;
+      cg[0][q] = -rb * h2c * g1 + h2c2 * g3;
+      cg[1][q] = g0 - ic2 * g3;
+      cg[2][q] = g2;
+      cg[3][q] = rb * h2c * g1 + h2c2 * g3;
+    }
+    double cl[4], cr[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) meg7_pair(cv[m], cg[m], cl[m], cr[m]);
+    const double cor = cb / rb, c2 = cb * cb;
+    const double WL[4] = {cl[0] + cl[1] + cl[3], cor * (cl[3] - cl[0]), cl[2], c2 * (cl[0] + cl[3])};
+    const double WR[4] = {cr[0] + cr[1] + cr[3], cor * (cr[3] - cr[0]), cr[2], c2 * (cr[0] + cr[3])};
+    double FL[4], FR[4], F[4];
+    conv_flux(WL, P.g1inv, FL);
+    conv_flux(WR, P.g1inv, FR);
+    hllc(WL, WR, FL, FR, P.gamma, P.g1inv, F);
+    if (C::VISC) {
+      const int b0 = bidx(line, pos + 3, WD), b1 = bidx(line, pos + 4, WD);
+      viscous_add(U[FN * RS + r], U[FN * RS + r + SN], U[FT * RS + r], U[FT * RS + r + SN],
+                  U[4 * RS + r], U[4 * RS + r + SN], sD[1 * NL * WD + b0], sD[1 * NL * WD + b1],
+                  sD[2 * NL * WD + b0], sD[2 * NL * WD + b1], sD[4 * NL * WD + b0],
+                  sD[4 * NL * WD + b1], sE[0 * NL * WE + bidx(line, pos + 1, WE)],
+                  sE[0 * NL * WE + bidx(line, pos + 2, WE)],
+                  sE[1 * NL * WE + bidx(line, pos + 1, WE)],
+                  sE[1 * NL * WE + bidx(line, pos + 2, WE)], inv_dn, P.mu, P.kq, F);
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) sF[m * FSTR + bidx(line, p, WFL)] = F[m];
+  }
+  __syncthreads();
+
+  // ---- pass 4: flux differences, eq. (deriv) -------------------------------
+#pragma unroll
+  for (int k = 0; k < C::CPT; ++k) {
+    const int c = tid + k * NT;
+    if (c < C::TX * C::TY) {
+      const int lx = c % C::TX, ly = c / C::TX;
+      const int line = (X ? ly : lx) - l0;
+      const int pos = X ? lx : ly;
+      if (line >= 0 && line < nl) {
+        const int bp = bidx(line, pos + 1, WFL), bm = bidx(line, pos, WFL);
+        const double d0 = sF[0 * FSTR + bp] - sF[0 * FSTR + bm];
+        const double d1 = sF[1 * FSTR + bp] - sF[1 * FSTR + bm];
+        const double d2 = sF[2 * FSTR + bp] - sF[2 * FSTR + bm];
+        const double d3 = sF[3 * FSTR + bp] - sF[3 * FSTR + bm];
+        res[k][0] -= d0 * inv_dn;
+        res[k][FN] -= d1 * inv_dn;
+        res[k][FT] -= d2 * inv_dn;
+        res[k][3] -= d3 * inv_dn;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <class C>
+__global__ __launch_bounds__(C::NT) void meg7_stage_kernel(StageParams P) {
+  __shared__ double sU[C::NF * C::RS];
+  __shared__ double sPh[C::PH];
+  __shared__ unsigned char sChi[C::CHI];
+  __shared__ unsigned short sQueue[C::QMAX];
+  __shared__ int sQCount;
+  constexpr int TX = C::TX, TY = C::TY, H = C::H, RX = C::RX, RS = C::RS, NT = C::NT;
+  const int tid = threadIdx.x;
+
+  // XCD-aware tile order: workgroups are dealt to the 8 XCDs round-robin, so
+  // give each XCD one contiguous run of tiles (halo rows shared in its L2).
+  int tile;
+  {
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int xcd = b & 7, idx = b >> 3;
+    const int per = nb >> 3, rem = nb & 7;
+    tile = xcd * per + (xcd < rem ? xcd : rem) + idx;
+  }
+  if (tile >= P.ntiles) return;
+  const int tx0 = (tile % P.tiles_x) * TX;
+  const int ty0 = (tile / P.tiles_x) * TY;
+  const size_t n = (size_t)P.nx * P.ny;
+
+  // ---- stage Q^(k) + halo as primitives in LDS ------------------------------
+  bool bad = false;
+  for (int c = tid; c < RS; c += NT) {
+    const int ly = c / RX - H, lx = c % RX - H;
+    const int gi = bc_index(ty0 + ly, P.ny, P.bcy);
+    const int gj = bc_index(tx0 + lx, P.nx, P.bcx);
+    const size_t s = (size_t)gi * P.nx + gj;
+    const double r = P.Qk[s], mx = P.Qk[n + s], my = P.Qk[2 * n + s], E = P.Qk[3 * n + s];
+    const double ir = 1.0 / r;
+    const double u = mx * ir, v = my * ir;
+    const double p = (P.gamma - 1.0) * (E - 0.5 * r * (u * u + v * v));
+    sU[c] = r;
+    sU[RS + c] = u;
+    sU[2 * RS + c] = v;
+    sU[3 * RS + c] = p;
+    if (C::VISC) sU[4 * RS + c] = P.gamma * p * ir;
+    const bool interior = lx >= 0 && lx < TX && ly >= 0 && ly < TY && tx0 + lx < P.nx &&
+                          ty0 + ly < P.ny;
+    if (interior && !(r > 0.0 && p > 0.0 && isfinite(E) && isfinite(mx) && isfinite(my) &&
+                      isfinite(r)))
+      bad = true;
+  }
+  if (bad) atomicOr(P.status, STATUS_BAD_STATE);
+  __syncthreads();
+
+  const Lds L{sU, sPh, sChi, sQueue, &sQCount};
+  double res[C::CPT][4];
+#pragma unroll
+  for (int k = 0; k < C::CPT; ++k)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) res[k][m] = 0.0;
+
+  for (int l0 = 0; l0 < TY; l0 += C::SX) sweep<C, 0>(P, L, l0, tx0, ty0, res);
+  for (int l0 = 0; l0 < TX; l0 += C::SY) sweep<C, 1>(P, L, l0, tx0, ty0, res);
+
+  // ---- residual store or SSP-RK3 stage update, eq. (rk) ----------------------
+  const double dt = (P.mode == MODE_RESIDUAL) ? 0.0 : *P.dt;
+#pragma unroll
+  for (int k = 0; k < C::CPT; ++k) {
+    const int c = tid + k * NT;
+    if (c >= TX * TY) continue;
+    const int gj = tx0 + c % TX, gi = ty0 + c / TX;
+    if (gj >= P.nx || gi >= P.ny) continue;
+    const size_t s = (size_t)gi * P.nx + gj;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const size_t o = m * n + s;
+      const double R = res[k][m];
+      double q;
+      if (P.mode == MODE_RESIDUAL)
+        q = R;
+      else if (P.mode == MODE_STAGE1)
+        q = P.Qn[o] + dt * R;
+      else if (P.mode == MODE_STAGE2)
+        q = 0.75 * P.Qn[o] + 0.25 * P.Qk[o] + (0.25 * dt) * R;
+      else
+        q = (1.0 / 3.0) * P.Qn[o] + (2.0 / 3.0) * P.Qk[o] + ((2.0 / 3.0) * dt) * R;
+      P.out[o] = q;
+    }
+  }
+}
+
+}  // namespace gbr

@@ -1,0 +1,158 @@
+"""ctypes binding of libgbr.so (argument marshalling only).
+
+Every function forwards to the C entry point of the same name declared in
+include/gbr.h.  Device arrays are passed as torch tensors (float64, CUDA/HIP
+device, contiguous, [4][ny][nx]) or as raw integer device addresses; streams
+as torch.cuda.Stream, a raw hipStream_t integer, or None (current stream).
+The library must be built (``python -m paper_2305_00762_amd.build`` or
+``__graft_entry__.build()``); there is no fallback: a missing library is an
+error.
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgbr.so")
+
+GBR_OK = 0
+GBR_EINVAL = -1
+GBR_ENOMEM = -2
+GBR_EDEVICE = -3
+GBR_ESTATE = -4
+GBR_EUNSUPPORTED = -5
+GBR_BC_PERIODIC = 0
+GBR_BC_TRANSMISSIVE = 1
+GBR_RECON_PRIM = 0
+GBR_MP_FLAGGED = 0
+GBR_PREC_FP64 = 0
+GBR_PREC_FP32_BULK = 1
+GBR_DET_PLAIN = 0
+GBR_DET_MLP = 1
+
+# every symbol include/gbr.h declares, with (restype, argtypes)
+_vp, _i, _d = C.c_void_p, C.c_int, C.c_double
+SIGNATURES = {
+    "gbr_strerror": (C.c_char_p, [_i]),
+    "gbr_version": (C.c_char_p, []),
+    "gbr_init": (_i, [_i, _i, _d, _d, _d, C.POINTER(_vp)]),
+    "gbr_destroy": (_i, [_vp]),
+    "gbr_set_geometry": (_i, [_vp, _d, _d, _d, _d, _i, _i]),
+    "gbr_set_scheme": (_i, [_vp, _i, _i, _i, _i]),
+    "gbr_residual": (_i, [_vp, _vp, _vp, _vp]),
+    "gbr_rk_stage": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
+    "gbr_compute_dt": (_i, [_vp, _vp, _d, _vp, _vp]),
+    "gbr_export_flags": (_i, [_vp, _i]),
+    "gbr_get_flags": (_i, [_vp, _vp, _vp, _vp]),
+    "gbr_check": (_i, [_vp, _vp]),
+}
+
+_lib = None
+
+
+class GbrError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+def load(path=LIB_PATH):
+    """Load libgbr.so; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built: run __graft_entry__.build() "
+                               "(the HIP library is required; there is no CPU fallback)")
+        L = C.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(code):
+    return load().gbr_strerror(code).decode()
+
+
+def version():
+    return load().gbr_version().decode()
+
+
+def _addr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if hasattr(x, "ctypes"):
+        return x.ctypes.data
+    raise TypeError(f"cannot take the address of {type(x)}")
+
+
+def _stream(s):
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _check(code, where):
+    if code != GBR_OK:
+        raise GbrError(code, where)
+    return code
+
+
+def gbr_init(nx, ny, gamma, mu, Pr):
+    h = C.c_void_p()
+    _check(load().gbr_init(nx, ny, gamma, mu, Pr, C.byref(h)), "gbr_init")
+    return h.value
+
+
+def gbr_destroy(ctx):
+    return _check(load().gbr_destroy(ctx), "gbr_destroy")
+
+
+def gbr_set_geometry(ctx, x0, x1, y0, y1, bc_x, bc_y):
+    return _check(load().gbr_set_geometry(ctx, x0, x1, y0, y1, bc_x, bc_y), "gbr_set_geometry")
+
+
+def gbr_set_scheme(ctx, recon=GBR_RECON_PRIM, mp_mode=GBR_MP_FLAGGED,
+                   precision=GBR_PREC_FP64, detector=GBR_DET_PLAIN):
+    return _check(load().gbr_set_scheme(ctx, recon, mp_mode, precision, detector),
+                  "gbr_set_scheme")
+
+
+def gbr_residual(ctx, Q, Res, stream=None):
+    return _check(load().gbr_residual(ctx, _addr(Q), _addr(Res), _stream(stream)),
+                  "gbr_residual")
+
+
+def gbr_rk_stage(ctx, stage, dt_dev, Qn, Qk, Qout, stream=None):
+    return _check(load().gbr_rk_stage(ctx, stage, _addr(dt_dev), _addr(Qn), _addr(Qk),
+                                      _addr(Qout), _stream(stream)), "gbr_rk_stage")
+
+
+def gbr_compute_dt(ctx, Q, cfl, dt_dev, stream=None):
+    return _check(load().gbr_compute_dt(ctx, _addr(Q), cfl, _addr(dt_dev), _stream(stream)),
+                  "gbr_compute_dt")
+
+
+def gbr_export_flags(ctx, enable=True):
+    return _check(load().gbr_export_flags(ctx, 1 if enable else 0), "gbr_export_flags")
+
+
+def gbr_get_flags(ctx, sig_x, sig_y, stream=None):
+    return _check(load().gbr_get_flags(ctx, _addr(sig_x), _addr(sig_y), _stream(stream)),
+                  "gbr_get_flags")
+
+
+def gbr_check(ctx, stream=None):
+    """Returns the status code (GBR_OK or GBR_ESTATE) without raising on ESTATE."""
+    code = load().gbr_check(ctx, _stream(stream))
+    if code not in (GBR_OK, GBR_ESTATE):
+        raise GbrError(code, "gbr_check")
+    return code

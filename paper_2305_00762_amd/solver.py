@@ -1,0 +1,78 @@
+"""Thin driver over the C ABI: device buffers from torch, SSP-RK3 steps.
+
+All arithmetic of a step runs in the library's HIP kernels: this module only
+allocates device memory, holds the stream and calls gbr_compute_dt and
+gbr_rk_stage three times per step.
+"""
+import numpy as np
+
+from . import gbr
+
+
+class Solver:
+    def __init__(self, problem, device="cuda", stream=None, export_flags=False,
+                 precision=gbr.GBR_PREC_FP64, detector=gbr.GBR_DET_PLAIN):
+        import torch
+        self.torch = torch
+        self.p = problem
+        self.device = device
+        self.stream = stream
+        self.ctx = gbr.gbr_init(problem.nx, problem.ny, problem.gamma, problem.mu, problem.Pr)
+        gbr.gbr_set_geometry(self.ctx, *problem.geometry())
+        gbr.gbr_set_scheme(self.ctx, gbr.GBR_RECON_PRIM, gbr.GBR_MP_FLAGGED, precision, detector)
+        if export_flags:
+            gbr.gbr_export_flags(self.ctx, True)
+        shape = (4, problem.ny, problem.nx)
+        self.Q = torch.empty(shape, dtype=torch.float64, device=device)
+        self.Q1 = torch.empty_like(self.Q)
+        self.Q2 = torch.empty_like(self.Q)
+        self.dt = torch.zeros(1, dtype=torch.float64, device=device)
+        if problem.Q is not None:
+            self.set_state(problem.Q)
+
+    def close(self):
+        if self.ctx:
+            gbr.gbr_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, Q):
+        self.Q.copy_(self.torch.from_numpy(np.ascontiguousarray(Q, np.float64)))
+
+    def state(self):
+        self.torch.cuda.synchronize()
+        return self.Q.cpu().numpy()
+
+    def residual(self, Q=None):
+        Q = self.Q if Q is None else Q
+        R = self.torch.empty_like(Q)
+        gbr.gbr_residual(self.ctx, Q, R, self.stream)
+        return R
+
+    def compute_dt(self, cfl=None):
+        gbr.gbr_compute_dt(self.ctx, self.Q, self.p.cfl if cfl is None else cfl, self.dt,
+                           self.stream)
+        return self.dt
+
+    def step(self, cfl=None):
+        """One SSP-RK3 step: dt from Q^n on the device, three stage kernels.
+        Q holds Q^{n+1} afterwards; no host synchronisation."""
+        self.compute_dt(cfl)
+        gbr.gbr_rk_stage(self.ctx, 1, self.dt, self.Q, self.Q, self.Q1, self.stream)
+        gbr.gbr_rk_stage(self.ctx, 2, self.dt, self.Q, self.Q1, self.Q2, self.stream)
+        gbr.gbr_rk_stage(self.ctx, 3, self.dt, self.Q, self.Q2, self.Q1, self.stream)
+        self.Q, self.Q1 = self.Q1, self.Q
+
+    def flags(self):
+        sx = np.zeros((self.p.ny, self.p.nx + 1), np.uint8)
+        sy = np.zeros((self.p.ny + 1, self.p.nx), np.uint8)
+        gbr.gbr_get_flags(self.ctx, sx, sy, self.stream)
+        return sx, sy
+
+    def check(self):
+        return gbr.gbr_check(self.ctx, self.stream)
