@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--workload", default="riemann1024", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--tiling", default="auto",
+                    help="tile variant index, or 'auto' (gbr_autotune on the initial state)")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one device copy of this many MiB first (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -102,6 +106,18 @@ def main():
     Qs = [torch.from_numpy(P.Q).to(dev) for _ in range(3)]
     dt = torch.zeros(1, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
+    if a.tiling == "auto":
+        gbr.gbr_autotune(ctx, Qs[0], 5, sh)
+    else:
+        gbr.gbr_set_tiling(ctx, int(a.tiling))
+    tiling = gbr.gbr_get_tiling(ctx)
+    if a.calib_copy_mb:
+        # a plain copy of known size: reads and writes calib_copy_mb MiB once
+        src = torch.ones(a.calib_copy_mb << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def one_step(Q, Q1, Q2, ev=None):
         gbr.gbr_compute_dt(ctx, Q, P.cfl, dt, sh)
@@ -160,7 +176,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": a.workload, "description": desc, "nx": P.nx, "ny": P.ny,
                    "precision": "fp64", "detector": "plain",
-                   "step": "device dt + 3 fused residual/stage launches"},
+                   "step": "device dt + 3 fused residual/stage launches",
+                   "tile": f"{tiling[1]}x{tiling[2]}"},
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,

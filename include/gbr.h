@@ -114,6 +114,18 @@ int gbr_compute_dt(gbr_ctx *ctx, const double *Q, double cfl, double *dt_dev,
 int gbr_export_flags(gbr_ctx *ctx, int enable);
 int gbr_get_flags(gbr_ctx *ctx, uint8_t *sig_x, uint8_t *sig_y, void *stream);
 
+/* Tile shapes of the stage kernel.  gbr_tiling_count() is the number of
+ * compiled shapes; gbr_set_tiling selects one (0 = default 31x15 cells per
+ * workgroup); gbr_get_tiling reports the shape in use (the viscous form falls
+ * back to variant 0 where a shape has no viscous build).  gbr_autotune times
+ * every shape on the residual of the device state Q (reps launches each,
+ * enqueued on `stream` and synchronised) and keeps the fastest; it allocates
+ * and frees one scratch array of the size of Q. */
+int gbr_tiling_count(void);
+int gbr_set_tiling(gbr_ctx *ctx, int variant);
+int gbr_get_tiling(gbr_ctx *ctx, int *variant, int *tile_x, int *tile_y);
+int gbr_autotune(gbr_ctx *ctx, const double *Q, int reps, void *stream);
+
 /* Synchronise `stream`, return GBR_ESTATE if any kernel since the last check
  * saw a non-finite value or rho <= 0 or p <= 0 in an interior cell, and
  * clear that record. */

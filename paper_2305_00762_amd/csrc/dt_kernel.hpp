@@ -1,40 +1,45 @@
-// CFL time step of Sec. 2.5, reduced on the device.
+// CFL time step of Sec. 2.5, reduced on the device in two passes.
 //
 // Per cell: conv = min(dx/(|u|+c), dy/(|v|+c)) and visc = min(dx^2/nu, dy^2/nu)
 // (nu = mu/rho), each evaluated with one rounding per operation and IEEE
-// division / square root, so the result does not depend on the reduction
-// order.  The minima are exact: positive doubles order like their bit
-// patterns, so a 64-bit unsigned atomic min over the bits is exact and
-// order independent.  dt = cfl * min(visc / alpha_v, conv).
+// division / square root.  Pass 1: every workgroup reduces its cells to one
+// (conv, visc) pair in a fixed grid-stride pattern; pass 2: one workgroup
+// reduces the pairs and writes dt = cfl * min(visc / alpha_v, conv).  A min
+// is exact, so the result is bit-identical to any other evaluation order; no
+// atomics are used.  A bad cell (non-finite, rho <= 0, p <= 0) is recorded
+// in the status word, since fmin would otherwise drop a NaN.
 #pragma once
 #include "meg7_device.hpp"
 
 namespace gbr {
 
+constexpr int kDtBlocks = 512;   // pass-1 workgroups (partials kept in context scratch)
+constexpr int kDtThreads = 256;
+
 struct DtParams {
   const double* __restrict__ Q;
-  unsigned long long* mins;  // [2]: conv, visc (bit patterns)
+  double* partial;   // [2][kDtBlocks]
   double* dt;
   unsigned* status;
   int nx, ny;
   double dx, dy, gamma, mu, cfl;
 };
 
-__global__ void dt_init_kernel(unsigned long long* mins) {
-  if (threadIdx.x < 2) mins[threadIdx.x] = 0x7ff0000000000000ull;  // +inf
-}
-
-__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+__device__ __forceinline__ double block_min(double v, double* red) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const unsigned long long w = __shfl_xor(v, o);
-    v = w < v ? w : v;
-  }
-  return v;
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if (__lane_id() == 0) red[w] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int k = 1; k < (int)(blockDim.x >> 6); ++k) r = fmin(r, red[k]);
+  return r;
 }
 
-__global__ __launch_bounds__(256) void dt_reduce_kernel(DtParams P) {
+__global__ __launch_bounds__(kDtThreads) void dt_reduce_kernel(DtParams P) {
 #pragma clang fp contract(off)
+  __shared__ double red[kDtThreads / 64];
   const size_t n = (size_t)P.nx * P.ny;
   double conv = __builtin_inf(), visc = __builtin_inf();
   bool bad = false;
@@ -44,7 +49,6 @@ __global__ __launch_bounds__(256) void dt_reduce_kernel(DtParams P) {
     const double u = P.Q[n + s] / rho, v = P.Q[2 * n + s] / rho;
     const double p = (P.gamma - 1.0) * (P.Q[3 * n + s] - rho * (u * u + v * v) / 2.0);
     const double c = sqrt(P.gamma * p / rho);
-    // fmin drops NaN, so a bad cell is recorded explicitly
     if (!(rho > 0.0) || !(p > 0.0) || !isfinite(c) || !isfinite(u) || !isfinite(v)) bad = true;
     conv = fmin(conv, fmin(P.dx / (fabs(u) + c), P.dy / (fabs(v) + c)));
     if (P.mu > 0.0) {
@@ -53,24 +57,27 @@ __global__ __launch_bounds__(256) void dt_reduce_kernel(DtParams P) {
     }
   }
   if (bad) atomicOr(P.status, 1u);
-  unsigned long long bc = __double_as_longlong(conv), bv = __double_as_longlong(visc);
-  // a NaN (bad state) must not be hidden by the min: map it to the smallest key
-  if (conv != conv) bc = 0ull;
-  if (visc != visc) bv = 0ull;
-  bc = wave_min_u64(bc);
-  bv = wave_min_u64(bv);
-  if (__lane_id() == 0) {
-    atomicMin(&P.mins[0], bc);
-    atomicMin(&P.mins[1], bv);
+  conv = block_min(conv, red);
+  visc = block_min(visc, red);
+  if (threadIdx.x == 0) {
+    P.partial[blockIdx.x] = conv;
+    P.partial[kDtBlocks + blockIdx.x] = visc;
   }
 }
 
-__global__ void dt_finish_kernel(const unsigned long long* mins, double* dt, double cfl,
-                                 unsigned* status) {
+__global__ __launch_bounds__(kDtThreads) void dt_finish_kernel(const double* partial, int nblk,
+                                                               double* dt, double cfl,
+                                                               unsigned* status) {
 #pragma clang fp contract(off)
+  __shared__ double red[kDtThreads / 64];
+  double conv = __builtin_inf(), visc = __builtin_inf();
+  for (int k = threadIdx.x; k < nblk; k += blockDim.x) {
+    conv = fmin(conv, partial[k]);
+    visc = fmin(visc, partial[kDtBlocks + k]);
+  }
+  conv = block_min(conv, red);
+  visc = block_min(visc, red);
   if (threadIdx.x == 0) {
-    const double conv = __longlong_as_double(mins[0]);
-    const double visc = __longlong_as_double(mins[1]);
     const double d = cfl * fmin(visc / kAlphaV, conv);
     *dt = d;
     if (!(d > 0.0) || !isfinite(d)) atomicOr(status, 2u);

@@ -13,13 +13,33 @@ namespace {
 
 using namespace gbr;
 
-// Tile shapes of the FP64 stage kernel (cells per workgroup TX x TY,
-// x-sweep sub-blocks of SX rows, y-sweep sub-blocks of SY columns, 256
-// threads).  (TX+1)*SX = SY*(TY+1) = 256 interfaces per pass.
-using CfgEuler = TileCfg<31, 15, 8, 16, 256, false>;
-using CfgVisc = TileCfg<31, 15, 8, 16, 256, true>;
-static_assert(CfgEuler::LDS_BYTES <= 80 * 1024, "two workgroups per CU");
-static_assert(CfgVisc::LDS_BYTES <= 80 * 1024, "two workgroups per CU");
+template <class C>
+void launch_cfg(const StageParams& P, hipStream_t s) {
+  static_assert(C::LDS_BYTES <= 160 * 1024, "LDS per workgroup");
+  hipLaunchKernelGGL(meg7_stage_kernel<C>, dim3(P.ntiles), dim3(C::NT), 0, s, P);
+}
+
+// Tile shapes of the stage kernel: TX x TY cells per workgroup, x sweep in
+// sub-blocks of SX rows, y sweep in sub-blocks of SY columns, 256 threads.
+// Shapes trade halo recomputation (small tiles) against LDS per workgroup
+// (workgroups per CU); gbr_autotune times them on the caller's state.
+struct TileVariant {
+  int tx, ty;
+  void (*euler)(const StageParams&, hipStream_t);
+  void (*visc)(const StageParams&, hipStream_t);  // null: use variant 0
+  const char* name;
+};
+const TileVariant kVariants[] = {
+    // 32 x-interfaces per row, 16 y-interfaces per column; 2 workgroups/CU
+    {31, 15, launch_cfg<TileCfg<31, 15, 15, 16, 256, false>>,
+     launch_cfg<TileCfg<31, 15, 8, 16, 256, true>>, "31x15"},
+    // 16 interfaces per line both ways; 3 (Euler) / 2 (viscous) workgroups/CU
+    {15, 15, launch_cfg<TileCfg<15, 15, 15, 15, 256, false>>,
+     launch_cfg<TileCfg<15, 15, 15, 15, 256, true>>, "15x15"},
+    // 64 x-interfaces per row, 8 y-interfaces per column (Euler only)
+    {63, 7, launch_cfg<TileCfg<63, 7, 7, 32, 256, false>>, nullptr, "63x7"},
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 }  // namespace
 
@@ -32,9 +52,10 @@ struct gbr_ctx {
   int device;
   int export_flags;
   unsigned* d_status;         // [4]
-  unsigned long long* d_mins; // [2]
+  double* d_partial;          // [2][kDtBlocks] time-step partial minima
   uint8_t* d_sigx;
   uint8_t* d_sigy;
+  int tiling;                 // index into kVariants
 };
 
 extern "C" {
@@ -69,12 +90,12 @@ int gbr_init(int nx, int ny, double gamma, double mu, double Pr, gbr_ctx** out) 
   c->precision = GBR_PREC_FP64; c->detector = GBR_DET_PLAIN;
   if (hipGetDevice(&c->device) != hipSuccess) { delete c; return GBR_EDEVICE; }
   if (hipMalloc(&c->d_status, 4 * sizeof(unsigned)) != hipSuccess) { delete c; return GBR_ENOMEM; }
-  if (hipMalloc(&c->d_mins, 2 * sizeof(unsigned long long)) != hipSuccess) {
+  if (hipMalloc(&c->d_partial, 2 * kDtBlocks * sizeof(double)) != hipSuccess) {
     (void)hipFree(c->d_status); delete c; return GBR_ENOMEM;
   }
   if (hipMemset(c->d_status, 0, 4 * sizeof(unsigned)) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
-    (void)hipFree(c->d_status); (void)hipFree(c->d_mins); delete c; return GBR_EDEVICE;
+    (void)hipFree(c->d_status); (void)hipFree(c->d_partial); delete c; return GBR_EDEVICE;
   }
   *out = c;
   return GBR_OK;
@@ -84,7 +105,7 @@ int gbr_destroy(gbr_ctx* c) {
   if (!c) return GBR_OK;
   (void)hipDeviceSynchronize();
   (void)hipFree(c->d_status);
-  (void)hipFree(c->d_mins);
+  (void)hipFree(c->d_partial);
   if (c->d_sigx) (void)hipFree(c->d_sigx);
   if (c->d_sigy) (void)hipFree(c->d_sigy);
   delete c;
@@ -160,14 +181,65 @@ static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn
   P.kq = c->mu / (c->Pr * (c->gamma - 1.0));
   P.mode = mode;
   const bool visc = c->mu > 0.0;
-  const int TX = CfgEuler::TX, TY = CfgEuler::TY;
-  P.tiles_x = (c->nx + TX - 1) / TX;
-  P.ntiles = P.tiles_x * ((c->ny + TY - 1) / TY);
-  if (visc)
-    hipLaunchKernelGGL(meg7_stage_kernel<CfgVisc>, dim3(P.ntiles), dim3(CfgVisc::NT), 0, s, P);
-  else
-    hipLaunchKernelGGL(meg7_stage_kernel<CfgEuler>, dim3(P.ntiles), dim3(CfgEuler::NT), 0, s, P);
+  const TileVariant* v = &kVariants[c->tiling];
+  if (visc && !v->visc) v = &kVariants[0];
+  P.tiles_x = (c->nx + v->tx - 1) / v->tx;
+  P.ntiles = P.tiles_x * ((c->ny + v->ty - 1) / v->ty);
+  (visc ? v->visc : v->euler)(P, s);
   return hip_ok(hipGetLastError());
+}
+
+int gbr_tiling_count(void) { return kNumVariants; }
+
+int gbr_set_tiling(gbr_ctx* c, int variant) {
+  if (!c || variant < 0 || variant >= kNumVariants) return GBR_EINVAL;
+  c->tiling = variant;
+  return GBR_OK;
+}
+
+int gbr_get_tiling(gbr_ctx* c, int* variant, int* tile_x, int* tile_y) {
+  if (!c) return GBR_EINVAL;
+  const TileVariant* v = &kVariants[c->tiling];
+  if (c->mu > 0.0 && !v->visc) v = &kVariants[0];
+  if (variant) *variant = (int)(v - kVariants);
+  if (tile_x) *tile_x = v->tx;
+  if (tile_y) *tile_y = v->ty;
+  return GBR_OK;
+}
+
+int gbr_autotune(gbr_ctx* c, const double* Q, int reps, void* stream) {
+  if (!c || !Q || reps < 1) return GBR_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  double* tmp = nullptr;
+  if (hipMalloc(&tmp, sizeof(double) * 4 * (size_t)c->nx * c->ny) != hipSuccess) return GBR_ENOMEM;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipFree(tmp);
+    return GBR_EDEVICE;
+  }
+  const int saved = c->tiling, flags = c->export_flags;
+  c->export_flags = 0;
+  int best = saved, rc = GBR_OK;
+  float best_ms = 1e30f;
+  for (int v = 0; v < kNumVariants && rc == GBR_OK; ++v) {
+    if (c->mu > 0.0 && !kVariants[v].visc) continue;
+    c->tiling = v;
+    rc = launch_stage(c, MODE_RESIDUAL, nullptr, Q, Q, tmp, s);  // warm-up
+    if (rc != GBR_OK) break;
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps && rc == GBR_OK; ++r) rc = launch_stage(c, MODE_RESIDUAL, nullptr, Q, Q, tmp, s);
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) { rc = GBR_EDEVICE; break; }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best_ms) { best_ms = ms; best = v; }
+  }
+  c->tiling = (rc == GBR_OK) ? best : saved;
+  c->export_flags = flags;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(tmp);
+  return rc;
 }
 
 int gbr_residual(gbr_ctx* c, const double* Q, double* Res, void* stream) {
@@ -188,16 +260,16 @@ int gbr_compute_dt(gbr_ctx* c, const double* Q, double cfl, double* dt_dev, void
   if (!c || !Q || !dt_dev || !(cfl > 0.0)) return GBR_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   DtParams P{};
-  P.Q = Q; P.mins = c->d_mins; P.dt = dt_dev; P.status = c->d_status; P.nx = c->nx; P.ny = c->ny;
+  P.Q = Q; P.partial = c->d_partial; P.dt = dt_dev; P.status = c->d_status;
+  P.nx = c->nx; P.ny = c->ny;
   P.dx = (c->x1 - c->x0) / c->nx; P.dy = (c->y1 - c->y0) / c->ny;
   P.gamma = c->gamma; P.mu = c->mu; P.cfl = cfl;
   const size_t n = (size_t)c->nx * c->ny;
-  int blocks = (int)((n + 255) / 256);
-  if (blocks > 2048) blocks = 2048;
-  hipLaunchKernelGGL(dt_init_kernel, dim3(1), dim3(64), 0, s, c->d_mins);
-  hipLaunchKernelGGL(dt_reduce_kernel, dim3(blocks), dim3(256), 0, s, P);
-  hipLaunchKernelGGL(dt_finish_kernel, dim3(1), dim3(64), 0, s, c->d_mins, dt_dev, cfl,
-                     c->d_status);
+  size_t want = (n + kDtThreads - 1) / kDtThreads;
+  const int blocks = (int)(want < (size_t)kDtBlocks ? want : (size_t)kDtBlocks);
+  hipLaunchKernelGGL(dt_reduce_kernel, dim3(blocks), dim3(kDtThreads), 0, s, P);
+  hipLaunchKernelGGL(dt_finish_kernel, dim3(1), dim3(kDtThreads), 0, s, c->d_partial, blocks,
+                     dt_dev, cfl, c->d_status);
   return hip_ok(hipGetLastError());
 }
 

@@ -16,6 +16,30 @@ constexpr double kXiDet = 1e-3;   // detector xi, eq. (buffer)
 // eq. (buffer): eps = 0.9 psi_c / (1 - 0.9 psi_c) xi^2 (folded with IEEE rounding)
 constexpr double kDetEps = (0.9 * kPsiC) / (1.0 - 0.9 * kPsiC) * (kXiDet * kXiDet);
 
+// Reciprocal and reciprocal square root: hardware estimate refined by two
+// Newton steps (full FP64 accuracy up to the last bit or two; positive,
+// normal arguments only).  Used for the Riemann-solver arithmetic, never
+// for the detector decision.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+__device__ __forceinline__ double sqrt_nr(double x) {
+  const double y = rsq_nr(x);
+  const double s = x * y;
+  return fma(0.5 * y, fma(-s, s, x), s);
+}
+
 // Sixth-order central first derivative, eq. (eqn:six), scaled by the
 // spacing: returns dx * dPhi/dx from Phi_{-3..3} (pm3 .. p3).
 __device__ __forceinline__ double grad6(double pm3, double pm2, double pm1, double p1,
@@ -27,7 +51,7 @@ __device__ __forceinline__ double grad6(double pm3, double pm2, double pm1, doub
 // Evaluated with one rounding per operation in a fixed order (no FMA
 // contraction) and an IEEE division, so that the decision psi < psi_c is
 // reproducible bit for bit.
-__device__ __attribute__((noinline)) double detector_psi(double rm2, double rm1, double r0,
+__device__ __forceinline__ double detector_psi(double rm2, double rm1, double r0,
                                                          double rp1, double rp2) {
 #pragma clang fp contract(off)
   double a = fabs(r0 - rm1) + fabs((r0 - 2.0 * rm1) + rm2);
@@ -110,38 +134,38 @@ __device__ __forceinline__ void conv_flux(const double W[4], double g1inv, doubl
 
 // HLLC with Einfeldt (Roe-average) bounds in the wave-sum form
 //   F = (F_L + F_R)/2 - (|S_L|(Q*_L - Q_L) + |S*|(Q*_R - Q*_L) + |S_R|(Q_R - Q*_R))/2
-// which is the canonical form of eq. (eqn:Riemann); F_L, F_R come from the
-// reconstruction (flux reconstruction in smooth regions, F(Q) at flags).
-__device__ __forceinline__ void hllc(const double WL[4], const double WR[4], const double FL[4],
-                                     const double FR[4], double gamma, double g1inv,
-                                     double F[4]) {
+// which is the canonical form of eq. (eqn:Riemann).  Only the mean
+// Fm = (F_L + F_R)/2 of the reconstructed fluxes enters, so callers pass it.
+__device__ __forceinline__ void hllc(const double WL[4], const double WR[4], const double Fm[4],
+                                     double gamma, double g1inv, double F[4]) {
   const double rl = WL[0], ul = WL[1], vl = WL[2], pl = WL[3];
   const double rr = WR[0], ur = WR[1], vr = WR[2], pr = WR[3];
-  const double irl = 1.0 / rl, irr = 1.0 / rr;
+  const double yl = rsq_nr(rl), yr = rsq_nr(rr);
+  const double sl = rl * yl, sr = rr * yr;          // sqrt(rho)
+  const double irl = yl * yl, irr = yr * yr;        // 1/rho
   const double El = pl * g1inv + 0.5 * rl * (ul * ul + vl * vl);
   const double Er = pr * g1inv + 0.5 * rr * (ur * ur + vr * vr);
-  const double cl = sqrt(gamma * pl * irl), cr = sqrt(gamma * pr * irr);
+  const double cl = sqrt_nr(gamma * pl * irl), cr = sqrt_nr(gamma * pr * irr);
   const double hl = (El + pl) * irl, hr = (Er + pr) * irr;
-  const double sl = sqrt(rl), sr = sqrt(rr);
-  const double iss = 1.0 / (sl + sr);
+  const double iss = rcp_nr(sl + sr);
   const double ut = (sl * ul + sr * ur) * iss;
   const double vt = (sl * vl + sr * vr) * iss;
   const double ht = (sl * hl + sr * hr) * iss;
-  const double ct = sqrt((gamma - 1.0) * (ht - 0.5 * (ut * ut + vt * vt)));
+  const double ct = sqrt_nr((gamma - 1.0) * (ht - 0.5 * (ut * ut + vt * vt)));
   const double SL = fmin(ul - cl, ut - ct);
   const double SR = fmax(ur + cr, ut + ct);
   const double ml = rl * (SL - ul), mr = rr * (SR - ur);
-  const double Ss = (pr - pl + ml * ul - mr * ur) / (ml - mr);
-  const double kl = ml / (SL - Ss), kr = mr / (SR - Ss);
+  const double Ss = (pr - pl + ml * ul - mr * ur) * rcp_nr(ml - mr);
+  const double kl = ml * rcp_nr(SL - Ss), kr = mr * rcp_nr(SR - Ss);
   const double QL[4] = {rl, rl * ul, rl * vl, El};
   const double QR[4] = {rr, rr * ur, rr * vr, Er};
-  const double QsL[4] = {kl, kl * Ss, kl * vl, kl * (El * irl + (Ss - ul) * (Ss + pl / ml))};
-  const double QsR[4] = {kr, kr * Ss, kr * vr, kr * (Er * irr + (Ss - ur) * (Ss + pr / mr))};
+  const double QsL[4] = {kl, kl * Ss, kl * vl, kl * (El * irl + (Ss - ul) * (Ss + pl * rcp_nr(ml)))};
+  const double QsR[4] = {kr, kr * Ss, kr * vr, kr * (Er * irr + (Ss - ur) * (Ss + pr * rcp_nr(mr)))};
   const double aL = fabs(SL), aS = fabs(Ss), aR = fabs(SR);
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const double diss = aL * (QsL[m] - QL[m]) + aS * (QsR[m] - QsL[m]) + aR * (QR[m] - QsR[m]);
-    F[m] = 0.5 * (FL[m] + FR[m]) - 0.5 * diss;
+    F[m] = Fm[m] - 0.5 * diss;
   }
 }
 

@@ -38,17 +38,22 @@ struct StageParams {
   int mode;
 };
 
+// Ghost cells by index: periodic wrap or transmissive clamp.  The offsets
+// reach at most one tile plus the halo past the grid, so the wrap loops run
+// at most once for any grid of 12 or more cells per tile extent.
 __device__ __forceinline__ int bc_index(int k, int n, int bc) {
   if (bc == 0) {
-    k %= n;
-    return k < 0 ? k + n : k;
+    while (k < 0) k += n;
+    while (k >= n) k -= n;
+    return k;
   }
   return k < 0 ? 0 : (k >= n ? n - 1 : k);
 }
 
-template <int TX_, int TY_, int SX_, int SY_, int NT_, bool VISC_>
+template <int TX_, int TY_, int SX_, int SY_, int NT_, bool VISC_, int MINW_ = 2>
 struct TileCfg {
   static constexpr int TX = TX_, TY = TY_, SX = SX_, SY = SY_, NT = NT_;
+  static constexpr int MINW = MINW_;  // waves per SIMD the register budget must allow
   static constexpr bool VISC = VISC_;
   static constexpr int H = 6;
   static constexpr int RX = TX + 2 * H, RY = TY + 2 * H, RS = RX * RY;
@@ -114,7 +119,11 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
   const int rot[5] = {0, FN, FT, 3, 4};
 
   // ---- pass 1: per-cell quantities ----------------------------------------
-  for (int t = tid; t < NL * WF; t += NT) {
+  constexpr int P1R = (NL * WF + NT - 1) / NT;
+#pragma unroll
+  for (int k1 = 0; k1 < P1R; ++k1) {
+    const int t = tid + k1 * NT;
+    if (t >= NL * WF) break;
     const int line = X ? t / WF : t % NL;
     const int p = X ? t % WF : t / NL;
     if (line >= nl) continue;
@@ -179,7 +188,7 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
         flagged = !sigma;
         if (sigma) {
           const int r = ridx(line, pos);
-          double WL[4], WR[4], FL[4], FR[4];
+          double WL[4], WR[4], Fm[4];
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
             const double* u = L.U + rot[m] * RS + r;
@@ -192,18 +201,16 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
             WL[m] = grb_left(v, g);
             WR[m] = grb_right(v, g);
             // eqs. (flux-full), (flux-right) on the cell fluxes f_{j-4..j+5}
+            // (F(f_L) + F(f_R))/2: the sum of eqs. (flux-full) and (flux-right)
+            // is symmetric about the interface, so pairs are added first
             double f[10];
 #pragma unroll
             for (int q = 0; q < 10; ++q) f[q] = sF[m * FSTR + bidx(line, pos + q + 1, WF)];
-            constexpr double s = 1.0 / 840.0;
-            FL[m] = (-s) * (f[0] + f[8]) + (2.0 * s) * f[1] + (22.0 * s) * f[2] +
-                    (-146.0 * s) * f[3] + (568.0 * s) * f[4] + (484.0 * s) * f[5] +
-                    (-104.0 * s) * f[6] + (16.0 * s) * f[7];
-            FR[m] = (-s) * (f[1] + f[9]) + (16.0 * s) * f[2] + (-104.0 * s) * f[3] +
-                    (484.0 * s) * f[4] + (568.0 * s) * f[5] + (-146.0 * s) * f[6] +
-                    (22.0 * s) * f[7] + (2.0 * s) * f[8];
+            constexpr double s = 1.0 / 1680.0;
+            Fm[m] = (1052.0 * s) * (f[4] + f[5]) - (250.0 * s) * (f[3] + f[6]) +
+                    (38.0 * s) * (f[2] + f[7]) + s * (f[1] + f[8]) - s * (f[0] + f[9]);
           }
-          hllc(WL, WR, FL, FR, P.gamma, P.g1inv, fsm[k]);
+          hllc(WL, WR, Fm, P.gamma, P.g1inv, fsm[k]);
           if (C::VISC) {
             const double* U = L.U;
             const int b0 = bidx(line, pos + 3, WD), b1 = bidx(line, pos + 4, WD);
@@ -257,8 +264,10 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
     // mean-state primitive eigenvectors of the normal Jacobian
     const double rb = 0.5 * (U[r] + U[r + SN]);
     const double pb = 0.5 * (U[3 * RS + r] + U[3 * RS + r + SN]);
-    const double cb = sqrt(P.gamma * pb / rb);
-    const double h2c = 0.5 / cb, ic2 = 1.0 / (cb * cb), h2c2 = 0.5 * ic2;
+    const double irb = rcp_nr(rb);
+    const double cb = sqrt_nr(P.gamma * pb * irb);
+    const double icb = rcp_nr(cb);
+    const double h2c = 0.5 * icb, ic2 = icb * icb, h2c2 = 0.5 * ic2;
     double cv[4][6], cg[4][6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
@@ -279,13 +288,15 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
     double cl[4], cr[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) meg7_pair(cv[m], cg[m], cl[m], cr[m]);
-    const double cor = cb / rb, c2 = cb * cb;
+    const double cor = cb * irb, c2 = cb * cb;
     const double WL[4] = {cl[0] + cl[1] + cl[3], cor * (cl[3] - cl[0]), cl[2], c2 * (cl[0] + cl[3])};
     const double WR[4] = {cr[0] + cr[1] + cr[3], cor * (cr[3] - cr[0]), cr[2], c2 * (cr[0] + cr[3])};
-    double FL[4], FR[4], F[4];
+    double FL[4], FR[4], Fm[4], F[4];
     conv_flux(WL, P.g1inv, FL);
     conv_flux(WR, P.g1inv, FR);
-    hllc(WL, WR, FL, FR, P.gamma, P.g1inv, F);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) Fm[m] = 0.5 * (FL[m] + FR[m]);
+    hllc(WL, WR, Fm, P.gamma, P.g1inv, F);
     if (C::VISC) {
       const int b0 = bidx(line, pos + 3, WD), b1 = bidx(line, pos + 4, WD);
       viscous_add(U[FN * RS + r], U[FN * RS + r + SN], U[FT * RS + r], U[FT * RS + r + SN],
@@ -326,7 +337,7 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
 }
 
 template <class C>
-__global__ __launch_bounds__(C::NT) void meg7_stage_kernel(StageParams P) {
+__global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel(StageParams P) {
   __shared__ double sU[C::NF * C::RS];
   __shared__ double sPh[C::PH];
   __shared__ unsigned char sChi[C::CHI];
@@ -350,26 +361,43 @@ __global__ __launch_bounds__(C::NT) void meg7_stage_kernel(StageParams P) {
   const size_t n = (size_t)P.nx * P.ny;
 
   // ---- stage Q^(k) + halo as primitives in LDS ------------------------------
+  // All global loads of the tile are issued before any is consumed, so the
+  // memory latency is paid once rather than once per round.
+  constexpr int LR = (RS + NT - 1) / NT;
+  double q[LR][4];
+#pragma unroll
+  for (int k = 0; k < LR; ++k) {
+    const int c = tid + k * NT;
+    if (c < RS) {
+      const int ly = c / RX - H, lx = c % RX - H;
+      const int gi = bc_index(ty0 + ly, P.ny, P.bcy);
+      const int gj = bc_index(tx0 + lx, P.nx, P.bcx);
+      const size_t s = (size_t)gi * P.nx + gj;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) q[k][m] = P.Qk[m * n + s];
+    }
+  }
   bool bad = false;
-  for (int c = tid; c < RS; c += NT) {
-    const int ly = c / RX - H, lx = c % RX - H;
-    const int gi = bc_index(ty0 + ly, P.ny, P.bcy);
-    const int gj = bc_index(tx0 + lx, P.nx, P.bcx);
-    const size_t s = (size_t)gi * P.nx + gj;
-    const double r = P.Qk[s], mx = P.Qk[n + s], my = P.Qk[2 * n + s], E = P.Qk[3 * n + s];
-    const double ir = 1.0 / r;
-    const double u = mx * ir, v = my * ir;
-    const double p = (P.gamma - 1.0) * (E - 0.5 * r * (u * u + v * v));
-    sU[c] = r;
-    sU[RS + c] = u;
-    sU[2 * RS + c] = v;
-    sU[3 * RS + c] = p;
-    if (C::VISC) sU[4 * RS + c] = P.gamma * p * ir;
-    const bool interior = lx >= 0 && lx < TX && ly >= 0 && ly < TY && tx0 + lx < P.nx &&
-                          ty0 + ly < P.ny;
-    if (interior && !(r > 0.0 && p > 0.0 && isfinite(E) && isfinite(mx) && isfinite(my) &&
-                      isfinite(r)))
-      bad = true;
+#pragma unroll
+  for (int k = 0; k < LR; ++k) {
+    const int c = tid + k * NT;
+    if (c < RS) {
+      const int ly = c / RX - H, lx = c % RX - H;
+      const double r = q[k][0], mx = q[k][1], my = q[k][2], E = q[k][3];
+      const double ir = rcp_nr(r);
+      const double u = mx * ir, v = my * ir;
+      const double p = (P.gamma - 1.0) * (E - 0.5 * r * (u * u + v * v));
+      sU[c] = r;
+      sU[RS + c] = u;
+      sU[2 * RS + c] = v;
+      sU[3 * RS + c] = p;
+      if (C::VISC) sU[4 * RS + c] = P.gamma * p * ir;
+      const bool interior = lx >= 0 && lx < TX && ly >= 0 && ly < TY && tx0 + lx < P.nx &&
+                            ty0 + ly < P.ny;
+      if (interior && !(r > 0.0 && p > 0.0 && isfinite(E) && isfinite(mx) && isfinite(my) &&
+                        isfinite(r)))
+        bad = true;
+    }
   }
   if (bad) atomicOr(P.status, STATUS_BAD_STATE);
   __syncthreads();
@@ -386,27 +414,37 @@ __global__ __launch_bounds__(C::NT) void meg7_stage_kernel(StageParams P) {
 
   // ---- residual store or SSP-RK3 stage update, eq. (rk) ----------------------
   const double dt = (P.mode == MODE_RESIDUAL) ? 0.0 : *P.dt;
+  double qn[C::CPT][4], qk[C::CPT][4];
+  bool own[C::CPT];
+  size_t so[C::CPT];
 #pragma unroll
   for (int k = 0; k < C::CPT; ++k) {
     const int c = tid + k * NT;
-    if (c >= TX * TY) continue;
     const int gj = tx0 + c % TX, gi = ty0 + c / TX;
-    if (gj >= P.nx || gi >= P.ny) continue;
-    const size_t s = (size_t)gi * P.nx + gj;
+    own[k] = c < TX * TY && gj < P.nx && gi < P.ny;
+    so[k] = (size_t)gi * P.nx + gj;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const size_t o = m * n + s;
+      qn[k][m] = (own[k] && P.mode != MODE_RESIDUAL) ? P.Qn[m * n + so[k]] : 0.0;
+      qk[k][m] = (own[k] && P.mode >= MODE_STAGE2) ? P.Qk[m * n + so[k]] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < C::CPT; ++k) {
+    if (!own[k]) continue;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
       const double R = res[k][m];
-      double q;
+      double v;
       if (P.mode == MODE_RESIDUAL)
-        q = R;
+        v = R;
       else if (P.mode == MODE_STAGE1)
-        q = P.Qn[o] + dt * R;
+        v = qn[k][m] + dt * R;
       else if (P.mode == MODE_STAGE2)
-        q = 0.75 * P.Qn[o] + 0.25 * P.Qk[o] + (0.25 * dt) * R;
+        v = 0.75 * qn[k][m] + 0.25 * qk[k][m] + (0.25 * dt) * R;
       else
-        q = (1.0 / 3.0) * P.Qn[o] + (2.0 / 3.0) * P.Qk[o] + ((2.0 / 3.0) * dt) * R;
-      P.out[o] = q;
+        v = (1.0 / 3.0) * qn[k][m] + (2.0 / 3.0) * qk[k][m] + ((2.0 / 3.0) * dt) * R;
+      P.out[m * n + so[k]] = v;
     }
   }
 }

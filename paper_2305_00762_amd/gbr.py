@@ -44,6 +44,10 @@ SIGNATURES = {
     "gbr_export_flags": (_i, [_vp, _i]),
     "gbr_get_flags": (_i, [_vp, _vp, _vp, _vp]),
     "gbr_check": (_i, [_vp, _vp]),
+    "gbr_tiling_count": (_i, []),
+    "gbr_set_tiling": (_i, [_vp, _i]),
+    "gbr_get_tiling": (_i, [_vp, C.POINTER(_i), C.POINTER(_i), C.POINTER(_i)]),
+    "gbr_autotune": (_i, [_vp, _vp, _i, _vp]),
 }
 
 _lib = None
@@ -156,3 +160,23 @@ def gbr_check(ctx, stream=None):
     if code not in (GBR_OK, GBR_ESTATE):
         raise GbrError(code, "gbr_check")
     return code
+
+
+def gbr_tiling_count():
+    return load().gbr_tiling_count()
+
+
+def gbr_set_tiling(ctx, variant):
+    return _check(load().gbr_set_tiling(ctx, variant), "gbr_set_tiling")
+
+
+def gbr_get_tiling(ctx):
+    """Returns (variant, tile_x, tile_y)."""
+    v, tx, ty = C.c_int(), C.c_int(), C.c_int()
+    _check(load().gbr_get_tiling(ctx, C.byref(v), C.byref(tx), C.byref(ty)), "gbr_get_tiling")
+    return v.value, tx.value, ty.value
+
+
+def gbr_autotune(ctx, Q, reps=3, stream=None):
+    _check(load().gbr_autotune(ctx, _addr(Q), reps, _stream(stream)), "gbr_autotune")
+    return gbr_get_tiling(ctx)

@@ -19,8 +19,8 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-12
 
 
-def check_residual(name, P):
-    R, sx, sy, st = gpu_residual(P)
+def check_residual(name, P, tiling=None):
+    R, sx, sy, st = gpu_residual(P, tiling=tiling)
     Ro, sxo, syo, nlim = O.residual(ocfg(P), P.Q, want_flags=True)
     e = res_err(R, Ro, P)
     nflag = int((sxo == 0).sum() + (syo == 0).sum())
@@ -232,3 +232,32 @@ def test_argument_errors():
     with pytest.raises(gbr.GbrError):
         gbr.gbr_residual(ctx, Q, Q)
     gbr.gbr_destroy(ctx)
+
+
+@pytest.mark.parametrize("tiling", [0, 1, 2])
+def test_tile_variants(tiling):
+    """Every compiled tile shape gives the same flags and residual."""
+    for P in (PB.riemann(100, seed=1, ny=77), PB.vortex(40)):
+        check_residual(f"tiling{tiling} {P.family}", P, tiling=tiling)
+    P = PB.shear(70, seed=2, ny=45)
+    P.mu = 2e-3
+    check_residual(f"tiling{tiling} viscous", P, tiling=tiling)
+    P = PB.riemann(12, seed=4, ny=12)
+    P.bc_x = P.bc_y = PB.BC_PERIODIC
+    check_residual(f"tiling{tiling} 12x12 periodic", P, tiling=tiling)
+
+
+def test_autotune_picks_a_variant():
+    from paper_2305_00762_amd import gbr
+    from paper_2305_00762_amd.solver import Solver
+    torch = require_gpu()
+    P = PB.riemann(256, seed=0)
+    S = Solver(P)
+    v, tx, ty = gbr.gbr_autotune(S.ctx, S.Q, 2)
+    assert 0 <= v < gbr.gbr_tiling_count() and tx > 0 and ty > 0
+    report("autotune riemann256", variant=v, tile=f"{tx}x{ty}")
+    R = S.residual()
+    torch.cuda.synchronize()
+    Ro = O.residual(ocfg(P), P.Q)
+    assert (res_err(R.cpu().numpy(), Ro, P) <= TOL).all()
+    S.close()
