@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--workload", default="riemann1024", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--tiling", default="auto",
                     help="tile variant index, or 'auto' (gbr_autotune on the initial state)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -103,6 +104,8 @@ def main():
     sh = stream.cuda_stream
     ctx = gbr.gbr_init(P.nx, P.ny, P.gamma, P.mu, P.Pr)
     gbr.gbr_set_geometry(ctx, *P.geometry())
+    prec = gbr.GBR_PREC_FP32_BULK if a.precision == "fp32" else gbr.GBR_PREC_FP64
+    gbr.gbr_set_scheme(ctx, gbr.GBR_RECON_PRIM, gbr.GBR_MP_FLAGGED, prec, gbr.GBR_DET_PLAIN)
     Qs = [torch.from_numpy(P.Q).to(dev) for _ in range(3)]
     dt = torch.zeros(1, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
@@ -172,10 +175,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if a.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": a.workload, "description": desc, "nx": P.nx, "ny": P.ny,
-                   "precision": "fp64", "detector": "plain",
+                   "precision": a.precision, "detector": "plain",
                    "step": "device dt + 3 fused residual/stage launches",
                    "tile": f"{tiling[1]}x{tiling[2]}"},
         "roofline": {
@@ -185,7 +188,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "meg7_stage_kernel (FP64)",
+            "kernel": "meg7_stage_kernel" + ("_f32" if a.precision == "fp32" else "") + f" ({a.precision})",
             "avg_launch_ms": stage_total_s * 1e3 / launches,
             "stage_ms": stage_ms,
             "bytes_per_cell_stage": 256.0 / 3.0,

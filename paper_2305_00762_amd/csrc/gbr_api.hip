@@ -7,6 +7,7 @@
 
 #include "../../include/gbr.h"
 #include "dt_kernel.hpp"
+#include "stage_f32.hpp"
 #include "stage_kernel.hpp"
 
 namespace {
@@ -18,6 +19,12 @@ void launch_cfg(const StageParams& P, hipStream_t s) {
   static_assert(C::LDS_BYTES <= 160 * 1024, "LDS per workgroup");
   hipLaunchKernelGGL(meg7_stage_kernel<C>, dim3(P.ntiles), dim3(C::NT), 0, s, P);
 }
+template <class C>
+void launch_cfg_f32(const StageParams& P, hipStream_t s) {
+  static_assert(F32Cfg<C>::LDS_BYTES <= 160 * 1024, "LDS per workgroup");
+  hipLaunchKernelGGL(meg7_stage_kernel_f32<C>, dim3(P.ntiles), dim3(C::NT), 0, s, P);
+}
+using LaunchFn = void (*)(const StageParams&, hipStream_t);
 
 // Tile shapes of the stage kernel: TX x TY cells per workgroup, x sweep in
 // sub-blocks of SX rows, y sweep in sub-blocks of SY columns, 256 threads.
@@ -25,19 +32,27 @@ void launch_cfg(const StageParams& P, hipStream_t s) {
 // (workgroups per CU); gbr_autotune times them on the caller's state.
 struct TileVariant {
   int tx, ty;
-  void (*euler)(const StageParams&, hipStream_t);
-  void (*visc)(const StageParams&, hipStream_t);  // null: use variant 0
+  LaunchFn euler, visc;       // FP64; null: no build for this shape (use variant 0)
+  LaunchFn euler32, visc32;   // FP32 bulk
   const char* name;
 };
 const TileVariant kVariants[] = {
     // 32 x-interfaces per row, 16 y-interfaces per column; 2 workgroups/CU
     {31, 15, launch_cfg<TileCfg<31, 15, 15, 16, 256, false>>,
-     launch_cfg<TileCfg<31, 15, 8, 16, 256, true>>, "31x15"},
+     launch_cfg<TileCfg<31, 15, 8, 16, 256, true>>,
+     launch_cfg_f32<TileCfg<31, 15, 15, 16, 256, false>>,
+     launch_cfg_f32<TileCfg<31, 15, 8, 16, 256, true>>, "31x15"},
     // 16 interfaces per line both ways; 3 (Euler) / 2 (viscous) workgroups/CU
     {15, 15, launch_cfg<TileCfg<15, 15, 15, 15, 256, false>>,
-     launch_cfg<TileCfg<15, 15, 15, 15, 256, true>>, "15x15"},
+     launch_cfg<TileCfg<15, 15, 15, 15, 256, true>>,
+     launch_cfg_f32<TileCfg<15, 15, 15, 15, 256, false>>,
+     launch_cfg_f32<TileCfg<15, 15, 15, 15, 256, true>>, "15x15"},
     // 64 x-interfaces per row, 8 y-interfaces per column (Euler only)
-    {63, 7, launch_cfg<TileCfg<63, 7, 7, 32, 256, false>>, nullptr, "63x7"},
+    {63, 7, launch_cfg<TileCfg<63, 7, 7, 32, 256, false>>, nullptr,
+     launch_cfg_f32<TileCfg<63, 7, 7, 32, 256, false>>, nullptr, "63x7"},
+    // 31x8 / 15x16 interface blocks sized for 3 workgroups per CU in FP32 bulk
+    {30, 15, launch_cfg<TileCfg<30, 15, 15, 15, 256, false>>, nullptr,
+     launch_cfg_f32<TileCfg<30, 15, 8, 15, 256, false, 3>>, nullptr, "30x15"},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -72,7 +87,7 @@ const char* gbr_strerror(int s) {
   }
 }
 
-const char* gbr_version(void) { return "gbr-mi355x 0.1 (gfx950, MEG7-prim FP64)"; }
+const char* gbr_version(void) { return "gbr-mi355x 0.2 (gfx950, MEG7-prim FP64 / FP32-bulk)"; }
 
 static int hip_ok(hipError_t e) { return e == hipSuccess ? GBR_OK : GBR_EDEVICE; }
 
@@ -125,7 +140,7 @@ int gbr_set_geometry(gbr_ctx* c, double x0, double x1, double y0, double y1, int
 int gbr_set_scheme(gbr_ctx* c, int recon, int mp_mode, int precision, int detector) {
   if (!c) return GBR_EINVAL;
   if (recon != GBR_RECON_PRIM || mp_mode != GBR_MP_FLAGGED) return GBR_EUNSUPPORTED;
-  if (precision != GBR_PREC_FP64) return GBR_EUNSUPPORTED;
+  if (precision != GBR_PREC_FP64 && precision != GBR_PREC_FP32_BULK) return GBR_EUNSUPPORTED;
   if (detector != GBR_DET_PLAIN) return GBR_EUNSUPPORTED;
   c->recon = recon; c->mp_mode = mp_mode; c->precision = precision; c->detector = detector;
   return GBR_OK;
@@ -185,7 +200,9 @@ static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn
   if (visc && !v->visc) v = &kVariants[0];
   P.tiles_x = (c->nx + v->tx - 1) / v->tx;
   P.ntiles = P.tiles_x * ((c->ny + v->ty - 1) / v->ty);
-  (visc ? v->visc : v->euler)(P, s);
+  LaunchFn fn = (c->precision == GBR_PREC_FP32_BULK) ? (visc ? v->visc32 : v->euler32)
+                                                       : (visc ? v->visc : v->euler);
+  fn(P, s);
   return hip_ok(hipGetLastError());
 }
 

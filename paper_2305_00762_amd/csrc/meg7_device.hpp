@@ -122,6 +122,52 @@ __device__ __forceinline__ void meg7_pair(const double* v, const double* g, doub
   }
 }
 
+// Characteristic MEG7 states at an interface (Secs. 2.3, 2.4, flagged
+// branch).  Wf(q, f) / Gf(q, f) return rotated primitive field f and its
+// normal gradient (spacing-scaled) at offset q-2 (q = 0..5) from cell j.
+// Eigenvectors of the primitive normal Jacobian are taken at the mean density
+// and pressure of cells j, j+1.  Each characteristic field combines two
+// primitive fields (rows of L: (u_n, p), (rho, p), (u_t), (u_n, p)); the four
+// fields are limited one at a time in a rolled loop that reads only its two
+// primitive fields, which keeps the register footprint small, and are
+// projected back by accumulating the columns of R.
+template <class FW, class FG>
+__device__ __forceinline__ void meg7_char_states(FW Wf, FG Gf, double gamma, double WLo[4],
+                                                 double WRo[4]) {
+  const double rb = 0.5 * (Wf(2, 0) + Wf(3, 0));
+  const double pb = 0.5 * (Wf(2, 3) + Wf(3, 3));
+  const double irb = rcp_nr(rb);
+  const double cb = sqrt_nr(gamma * pb * irb);
+  const double icb = rcp_nr(cb);
+  const double h2c = 0.5 * icb, ic2 = icb * icb, h2c2 = 0.5 * ic2;
+  const double cor = cb * irb, c2 = cb * cb;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) { WLo[m] = 0.0; WRo[m] = 0.0; }
+#pragma unroll 1
+  for (int m = 0; m < 4; ++m) {
+    // row m of L as ca * field fa + cb_ * field fb
+    const int fa = (m == 1) ? 0 : ((m == 2) ? 2 : 1);
+    const int fb = (m == 2) ? 2 : 3;
+    const double ca = (m == 0) ? -rb * h2c : ((m == 3) ? rb * h2c : 1.0);
+    const double cbv = (m == 1) ? -ic2 : ((m == 2) ? 0.0 : h2c2);
+    double cv[6], cg[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      cv[q] = ca * Wf(q, fa) + cbv * Wf(q, fb);
+      cg[q] = ca * Gf(q, fa) + cbv * Gf(q, fb);
+    }
+    double cl, cr;
+    meg7_pair(cv, cg, cl, cr);
+    // column m of R = L^{-1}: (1,-c/rho,0,c^2), (1,0,0,0), (0,0,1,0), (1,c/rho,0,c^2)
+    const double b0 = (m == 2) ? 0.0 : 1.0;
+    const double b1 = (m == 0) ? -cor : ((m == 3) ? cor : 0.0);
+    const double b2 = (m == 2) ? 1.0 : 0.0;
+    const double b3 = (m == 0 || m == 3) ? c2 : 0.0;
+    WLo[0] += b0 * cl; WLo[1] += b1 * cl; WLo[2] += b2 * cl; WLo[3] += b3 * cl;
+    WRo[0] += b0 * cr; WRo[1] += b1 * cr; WRo[2] += b2 * cr; WRo[3] += b3 * cr;
+  }
+}
+
 // Normal convective flux of the state W (Sec. 1 flux vectors, rotated).
 __device__ __forceinline__ void conv_flux(const double W[4], double g1inv, double F[4]) {
   const double E = W[3] * g1inv + 0.5 * W[0] * (W[1] * W[1] + W[2] * W[2]);
@@ -130,6 +176,23 @@ __device__ __forceinline__ void conv_flux(const double W[4], double g1inv, doubl
   F[1] = m * W[1] + W[3];
   F[2] = m * W[2];
   F[3] = W[1] * (E + W[3]);
+}
+
+// Jump of the normal convective flux between states Wm and Wp, F(Wp) - F(Wm),
+// written on the primitive jumps so that it is exactly zero for equal states
+// and carries no cancellation of the flux magnitudes.
+__device__ __forceinline__ void conv_flux_jump(const double Wm[4], const double Wp[4],
+                                               double g1inv, double dF[4]) {
+  const double dr = Wp[0] - Wm[0], du = Wp[1] - Wm[1], dv = Wp[2] - Wm[2], dp = Wp[3] - Wm[3];
+  const double mp = Wp[0] * Wp[1];
+  const double dm = Wp[0] * du + Wm[1] * dr;  // jump of rho un
+  const double Em = Wm[3] * g1inv + 0.5 * Wm[0] * (Wm[1] * Wm[1] + Wm[2] * Wm[2]);
+  const double dE = dp * g1inv + 0.5 * (dr * (Wm[1] * Wm[1] + Wm[2] * Wm[2]) +
+                                        Wp[0] * (du * (Wp[1] + Wm[1]) + dv * (Wp[2] + Wm[2])));
+  dF[0] = dm;
+  dF[1] = mp * du + Wm[1] * dm + dp;
+  dF[2] = mp * dv + Wm[2] * dm;
+  dF[3] = Wp[1] * (dE + dp) + (Em + Wm[3]) * du;
 }
 
 // HLLC with Einfeldt (Roe-average) bounds in the wave-sum form

@@ -1,0 +1,383 @@
+// FP32-bulk form of the fused MEG7 residual + stage kernel.
+//
+// The conserved state, the LDS tile of primitives, the detector (so the flags
+// are the FP64 flags), the shock branch and the flux differencing stay in
+// FP64.  The smooth-interface work -- GRB reconstruction, flux reconstruction,
+// the Riemann solver, the viscous flux -- runs in FP32 on small local
+// quantities only, so its rounding scales with the local variation of the
+// solution rather than with its magnitude:
+//   * per cell edge: jumps dU = U_{k+1} - U_k and df = f_{k+1} - f_k, formed
+//     in FP64 (df on the primitive jumps) and rounded to FP32; per cell:
+//     gradients Phi' (FP32);
+//   * GRB states as corrections: U^L = U_j + cL, U^R = U_{j+1} + cR, with cL, cR
+//     written on gradients and edge jumps (eq. eqn:grb minus U_j, using that
+//     its value weights sum to 840), and U^R - U^L = dU_{j+1/2} + cR - cL;
+//   * the mean reconstructed flux minus the central flux
+//     B = (f_j + f_{j+1})/2 as a stencil on edge jumps (eqs. flux-full,
+//     flux-right minus B: the weights sum to zero);
+//   * HLLC written on the jumps (every wave jump is proportional to
+//     S* - u_L or S* - u_R, themselves formed from dp and du).
+// Each interface flux is F = B + d with d in FP32; the divergence is formed in
+// FP64 as (f_{j+1} - f_{j-1})/2 + (d_{j+1/2} - d_{j-1/2}).
+#pragma once
+#include "stage_kernel.hpp"
+
+namespace gbr {
+
+__device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rsqf(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float sqrtf_fast(float x) { return x * __builtin_amdgcn_rsqf(x); }
+
+// HLLC (Einfeldt bounds) dissipation |S_L|(Q*_L-Q_L) + |S*|(Q*_R-Q*_L) +
+// |S_R|(Q_R-Q*_R) from the left/right primitive states and their jump
+// dW = W_R - W_L, every jump evaluated as a product of small quantities.
+__device__ __forceinline__ void hllc_diss_f32(const float WL[4], const float WR[4],
+                                              const float dW[4], float gamma, float g1inv,
+                                              float diss[4]) {
+  const float rl = WL[0], ul = WL[1], vl = WL[2], pl = WL[3];
+  const float rr = WR[0], ur = WR[1], vr = WR[2], pr = WR[3];
+  const float dr = dW[0], du = dW[1], dv = dW[2], dp = dW[3];
+  const float yl = rsqf(rl), yr = rsqf(rr);
+  const float sl = rl * yl, sr = rr * yr, irl = yl * yl, irr = yr * yr;
+  const float kl2 = ul * ul + vl * vl, kr2 = ur * ur + vr * vr;
+  const float El = pl * g1inv + 0.5f * rl * kl2;
+  const float Er = pr * g1inv + 0.5f * rr * kr2;
+  const float cl = sqrtf_fast(gamma * pl * irl), cr = sqrtf_fast(gamma * pr * irr);
+  const float hl = (El + pl) * irl, hr = (Er + pr) * irr;
+  const float iss = rcpf(sl + sr);
+  const float ut = (sl * ul + sr * ur) * iss;
+  const float vt = (sl * vl + sr * vr) * iss;
+  const float ht = (sl * hl + sr * hr) * iss;
+  const float ct = sqrtf_fast((gamma - 1.0f) * (ht - 0.5f * (ut * ut + vt * vt)));
+  const float SL = fminf(ul - cl, ut - ct);
+  const float SR = fmaxf(ur + cr, ut + ct);
+  const float ml = rl * (SL - ul), mr = rr * (SR - ur);
+  const float iden = rcpf(ml - mr);
+  const float aL = (dp - du * mr) * iden;   // S* - u_L
+  const float aR = (dp - du * ml) * iden;   // S* - u_R
+  const float Ss = ul + aL;
+  const float iL = rcpf(SL - Ss), iR = rcpf(SR - Ss);
+  const float gl = rl * aL * iL, gr = rr * aR * iR;
+  // Q*_L - Q_L and Q_R - Q*_R
+  const float dQL[4] = {gl, gl * SL, gl * vl, aL * iL * (El + pl + ml * Ss)};
+  const float dQR[4] = {-gr, -gr * SR, -gr * vr, -aR * iR * (Er + pr + mr * Ss)};
+  // Q_R - Q_L from the primitive jumps
+  const float dQ[4] = {dr, rr * du + ul * dr, rr * dv + vl * dr,
+                       dp * g1inv + 0.5f * (dr * kl2 + rr * (du * (ur + ul) + dv * (vr + vl)))};
+  const float aSL = fabsf(SL), aSS = fabsf(Ss), aSR = fabsf(SR);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) diss[m] = aSL * dQL[m] + aSS * (dQ[m] - dQR[m] - dQL[m]) + aSR * dQR[m];
+}
+
+template <int N, int NL, int NF>
+struct PhaseF32 {
+  // positions: gradients k in [-3, N+3); edge jumps dU at k+1/2, k in [-3, N+2);
+  // flux jumps df at k+1/2, k in [-5, N+4); tangential derivatives k in [-1, N+1)
+  static constexpr int WD = N + 6, WU = N + 5, WG = N + 9, WE = N + 2, WFL = N + 1, WP = N + 10;
+  static constexpr int TOT(bool visc) {
+    return NF * NL * WD + NF * NL * WU + 4 * NL * (WG > WFL ? WG : WFL) + (visc ? 2 * NL * WE : 0);
+  }
+};
+
+template <class C>
+struct F32Cfg {
+  using PX = PhaseF32<C::TX, C::SX, C::NF>;
+  using PY = PhaseF32<C::TY, C::SY, C::NF>;
+  static constexpr int PH = C::cmax(PX::TOT(C::VISC), PY::TOT(C::VISC));  // floats
+  static constexpr int LDS_BYTES = 8 * C::NF * C::RS + 4 * PH + C::CHI + 2 * C::QMAX + 16;
+};
+
+struct LdsF32 {
+  double* U;
+  float* ph;
+  unsigned char* chi;
+  unsigned short* queue;
+  int* qcount;
+};
+
+template <class C, int DIR>
+__device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L, int l0, int tx0,
+                                          int ty0, double (&res)[C::CPT][4]) {
+  constexpr bool X = (DIR == 0);
+  constexpr int N = X ? C::TX : C::TY;
+  constexpr int NL = X ? C::SX : C::SY;
+  constexpr int NLINES = X ? C::TY : C::TX;
+  using PH = PhaseF32<N, NL, C::NF>;
+  constexpr int WD = PH::WD, WU = PH::WU, WG = PH::WG, WE = PH::WE, WFL = PH::WFL, WP = PH::WP;
+  constexpr int RS = C::RS, RX = C::RX, H = C::H, NT = C::NT, NF = C::NF;
+  constexpr int SN = X ? 1 : RX, ST = X ? RX : 1;
+  constexpr int FN = X ? 1 : 2, FT = X ? 2 : 1;
+  constexpr int IPT = (NL * WFL + NT - 1) / NT;
+  constexpr int GSTR = (WG > WFL ? WG : WFL) * NL;
+  const int tid = threadIdx.x;
+  const int nl = (NLINES - l0) < NL ? (NLINES - l0) : NL;
+  const double inv_dn = X ? P.inv_dx : P.inv_dy;
+  const double inv_dt = X ? P.inv_dy : P.inv_dx;
+  const float gammaf = (float)P.gamma, g1invf = (float)P.g1inv;
+
+  float* sD = L.ph;                  // [NF][NL x WD]   gradients Phi' (rotated order)
+  float* sDU = sD + NF * NL * WD;    // [NF][NL x WU]   edge jumps of the primitives
+  float* sDF = sDU + NF * NL * WU;   // [4][NL x WG]    edge jumps of the cell fluxes; then d
+  float* sE = sDF + 4 * GSTR;        // [2][NL x WE]    tangential derivatives of un, ut
+  auto bidx = [](int line, int p, int W) { return X ? line * W + p : p * NL + line; };
+  auto ridx = [&](int line, int pos) {
+    const int lx = X ? pos : l0 + line;
+    const int ly = X ? l0 + line : pos;
+    return (ly + H) * RX + (lx + H);
+  };
+  const int rot[5] = {0, FN, FT, 3, 4};
+  const double* U = L.U;
+  auto wrot = [&](int r, double W[4]) {
+    W[0] = U[r]; W[1] = U[FN * RS + r]; W[2] = U[FT * RS + r]; W[3] = U[3 * RS + r];
+  };
+
+  // ---- pass 1: per cell and per edge, from the FP64 tile ----------------------
+  constexpr int P1R = (NL * WP + NT - 1) / NT;
+#pragma unroll
+  for (int k1 = 0; k1 < P1R; ++k1) {
+    const int t = tid + k1 * NT;
+    if (t >= NL * WP) break;
+    const int line = X ? t / WP : t % NL;
+    const int p = X ? t % WP : t / NL;
+    if (line >= nl) continue;
+    const int k = p - 5;
+    const int r = ridx(line, k);
+    if (k < N + 4) {
+      double W0[4], W1[4], df[4];
+      wrot(r, W0);
+      wrot(r + SN, W1);
+      conv_flux_jump(W0, W1, P.g1inv, df);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) sDF[m * GSTR + bidx(line, p, WG)] = (float)df[m];
+    }
+    if (k >= -3 && k < N + 2) {
+#pragma unroll
+      for (int m = 0; m < NF; ++m) {
+        const double* u = U + rot[m] * RS + r;
+        sDU[m * NL * WU + bidx(line, k + 3, WU)] = (float)(u[SN] - u[0]);
+      }
+    }
+    if (k >= -3 && k < N + 3) {
+#pragma unroll
+      for (int m = 0; m < NF; ++m) {
+        const double* u = U + rot[m] * RS + r;
+        sD[m * NL * WD + bidx(line, k + 3, WD)] =
+            (float)grad6(u[-3 * SN], u[-2 * SN], u[-SN], u[SN], u[2 * SN], u[3 * SN]);
+      }
+      const double* rho = U + r;
+      const double psi = detector_psi(rho[-2 * SN], rho[-SN], rho[0], rho[SN], rho[2 * SN]);
+      L.chi[bidx(line, k + 3, WD)] = (psi < kPsiC) ? 1 : 0;
+    }
+    if (C::VISC && k >= -1 && k < N + 1) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const double* u = U + (m == 0 ? FN : FT) * RS + r;
+        sE[m * NL * WE + bidx(line, k + 1, WE)] =
+            (float)(grad6(u[-3 * ST], u[-2 * ST], u[-ST], u[ST], u[2 * ST], u[3 * ST]) * inv_dt);
+      }
+    }
+  }
+  if (tid == 0) *L.qcount = 0;
+  __syncthreads();
+
+  // ---- pass 2: smooth interfaces in FP32; ballot-compact the flagged ----------
+  float dsm[IPT][4];
+  bool has[IPT];
+#pragma unroll
+  for (int kk = 0; kk < IPT; ++kk) {
+    has[kk] = false;
+    const int t = tid + kk * NT;
+    bool flagged = false;
+    if (t < NL * WFL) {
+      const int line = X ? t / WFL : t % NL;
+      const int p = X ? t % WFL : t / NL;
+      const int pos = p - 1;
+      if (line < nl) {
+        bool sigma = true;
+#pragma unroll
+        for (int q = 1; q <= 6; ++q) sigma = sigma && (L.chi[bidx(line, pos + q, WD)] == 0);
+        if (X) {
+          const int gi = ty0 + l0 + line, gj = tx0 + pos;
+          if (P.sigx && gi < P.ny && gj < P.nx) P.sigx[(size_t)gi * (P.nx + 1) + gj + 1] = sigma;
+        } else {
+          const int gj = tx0 + l0 + line, gi = ty0 + pos;
+          if (P.sigy && gj < P.nx && gi < P.ny) P.sigy[(size_t)(gi + 1) * P.nx + gj] = sigma;
+        }
+        flagged = !sigma;
+        if (sigma) {
+          const int r = ridx(line, pos);
+          float WL[4], WR[4], dW[4], dF[4];
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            // edge jumps e[q] at (pos-2+q)+1/2, q = 0..4; gradients g[q] at pos-1+q
+            float e[5], g[4];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) e[q] = sDU[m * NL * WU + bidx(line, pos + 1 + q, WU)];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) g[q] = sD[m * NL * WD + bidx(line, pos + 2 + q, WD)];
+            constexpr float s = 1.0f / 840.0f;
+            const float cL = s * (420.0f * g[1] + 60.0f * (g[0] - g[2]) +
+                                  181.0f * (e[2] - e[1]) + 3.0f * (e[3] - e[0]));
+            const float cR = s * (-420.0f * g[2] + 60.0f * (g[1] - g[3]) +
+                                  181.0f * (e[3] - e[2]) + 3.0f * (e[4] - e[1]));
+            const double* u = U + rot[m] * RS + r;
+            WL[m] = (float)u[0] + cL;
+            WR[m] = (float)u[SN] + cR;
+            dW[m] = e[2] + (cR - cL);
+            // mean reconstructed flux minus (f_j + f_{j+1})/2 on flux edge jumps
+            // h[q] at (pos-4+q)+1/2, q = 0..8
+            float h[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) h[q] = sDF[m * GSTR + bidx(line, pos + 1 + q, WG)];
+            constexpr float w = 1.0f / 1680.0f;
+            dF[m] = w * (212.0f * (h[3] - h[5]) - 38.0f * (h[2] - h[6]) + (h[0] - h[8]));
+          }
+          float diss[4];
+          hllc_diss_f32(WL, WR, dW, gammaf, g1invf, diss);
+#pragma unroll
+          for (int m = 0; m < 4; ++m) dsm[kk][m] = dF[m] - 0.5f * diss[m];
+          if (C::VISC) {
+            const int b0 = bidx(line, pos + 3, WD), b1 = bidx(line, pos + 4, WD);
+            const int be = bidx(line, pos + 3, WU);
+            const float gun0 = sD[1 * NL * WD + b0], gun1 = sD[1 * NL * WD + b1];
+            const float gut0 = sD[2 * NL * WD + b0], gut1 = sD[2 * NL * WD + b1];
+            const float gT0 = sD[4 * NL * WD + b0], gT1 = sD[4 * NL * WD + b1];
+            const float jun = sDU[1 * NL * WU + be], jut = sDU[2 * NL * WU + be];
+            const float jT = sDU[4 * NL * WU + be];
+            const float a2 = 0.5f * (float)kAlphaV, idn = (float)inv_dn;
+            const float dun = (0.5f * (gun0 + gun1) + a2 * (jun - 0.5f * (gun0 + gun1))) * idn;
+            const float dut = (0.5f * (gut0 + gut1) + a2 * (jut - 0.5f * (gut0 + gut1))) * idn;
+            const float dT = (0.5f * (gT0 + gT1) + a2 * (jT - 0.5f * (gT0 + gT1))) * idn;
+            const float dunt = 0.5f * (sE[0 * NL * WE + bidx(line, pos + 1, WE)] +
+                                       sE[0 * NL * WE + bidx(line, pos + 2, WE)]);
+            const float dutt = 0.5f * (sE[1 * NL * WE + bidx(line, pos + 1, WE)] +
+                                       sE[1 * NL * WE + bidx(line, pos + 2, WE)]);
+            const float unf = 0.5f * ((float)U[FN * RS + r] + (float)U[FN * RS + r + SN]);
+            const float utf = 0.5f * ((float)U[FT * RS + r] + (float)U[FT * RS + r + SN]);
+            const float muf = (float)P.mu;
+            const float tnn = (2.0f / 3.0f) * muf * (2.0f * dun - dutt);
+            const float tnt = muf * (dut + dunt);
+            const float qn = -(float)P.kq * dT;
+            dsm[kk][1] -= tnn;
+            dsm[kk][2] -= tnt;
+            dsm[kk][3] += -(tnn * unf + tnt * utf) + qn;
+          }
+          has[kk] = true;
+        }
+      }
+    }
+    const unsigned long long ball = __ballot(flagged);
+    if (ball) {
+      const int lane = __lane_id();
+      int base = 0;
+      if (lane == 0) base = atomicAdd(L.qcount, (int)__popcll(ball));
+      base = __shfl(base, 0);
+      if (flagged) {
+        const int rank = (int)__popcll(ball & ((1ull << lane) - 1ull));
+        L.queue[base + rank] = (unsigned short)t;
+      }
+    }
+  }
+  __syncthreads();  // edge flux jumps consumed: the buffer now holds d per interface
+#pragma unroll
+  for (int kk = 0; kk < IPT; ++kk) {
+    if (has[kk]) {
+      const int t = tid + kk * NT;
+      const int line = X ? t / WFL : t % NL;
+      const int p = X ? t % WFL : t / NL;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) sDF[m * GSTR + bidx(line, p, WFL)] = dsm[kk][m];
+    }
+  }
+
+  // ---- pass 3: flagged interfaces in FP64 (characteristic MEG7, F(Q)) -------
+  const int nq = *L.qcount;
+  for (int qi = tid; qi < nq; qi += NT) {
+    const int t = L.queue[qi];
+    const int line = X ? t / WFL : t % NL;
+    const int p = X ? t % WFL : t / NL;
+    const int pos = p - 1;
+    const int r = ridx(line, pos);
+    double WL[4], WR[4];
+    meg7_char_states(
+        [&](int q, int f) { return U[rot[f] * RS + r + (q - 2) * SN]; },
+        [&](int q, int f) { return (double)sD[f * NL * WD + bidx(line, pos + q + 1, WD)]; },
+        P.gamma, WL, WR);
+    double FL[4], FR[4], Fm[4], F[4], W0[4], W1[4], f0[4], f1[4];
+    conv_flux(WL, P.g1inv, FL);
+    conv_flux(WR, P.g1inv, FR);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) Fm[m] = 0.5 * (FL[m] + FR[m]);
+    hllc(WL, WR, Fm, P.gamma, P.g1inv, F);
+    if (C::VISC) {
+      const int b0 = bidx(line, pos + 3, WD), b1 = bidx(line, pos + 4, WD);
+      viscous_add(U[FN * RS + r], U[FN * RS + r + SN], U[FT * RS + r], U[FT * RS + r + SN],
+                  U[4 * RS + r], U[4 * RS + r + SN], sD[1 * NL * WD + b0], sD[1 * NL * WD + b1],
+                  sD[2 * NL * WD + b0], sD[2 * NL * WD + b1], sD[4 * NL * WD + b0],
+                  sD[4 * NL * WD + b1], sE[0 * NL * WE + bidx(line, pos + 1, WE)],
+                  sE[0 * NL * WE + bidx(line, pos + 2, WE)],
+                  sE[1 * NL * WE + bidx(line, pos + 1, WE)],
+                  sE[1 * NL * WE + bidx(line, pos + 2, WE)], inv_dn, P.mu, P.kq, F);
+    }
+    wrot(r, W0);
+    wrot(r + SN, W1);
+    conv_flux(W0, P.g1inv, f0);
+    conv_flux(W1, P.g1inv, f1);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) sDF[m * GSTR + bidx(line, p, WFL)] = (float)(F[m] - 0.5 * (f0[m] + f1[m]));
+  }
+  __syncthreads();
+
+  // ---- pass 4: divergence in FP64: (f_{j+1} - f_{j-1})/2 + d_{j+1/2} - d_{j-1/2}
+#pragma unroll
+  for (int k = 0; k < C::CPT; ++k) {
+    const int c = tid + k * NT;
+    if (c < C::TX * C::TY) {
+      const int lx = c % C::TX, ly = c / C::TX;
+      const int line = (X ? ly : lx) - l0;
+      const int pos = X ? lx : ly;
+      if (line >= 0 && line < nl) {
+        const int r = ridx(line, pos);
+        double Wm[4], Wp[4], dfc[4];
+        wrot(r - SN, Wm);
+        wrot(r + SN, Wp);
+        conv_flux_jump(Wm, Wp, P.g1inv, dfc);
+        const int bp = bidx(line, pos + 1, WFL), bm = bidx(line, pos, WFL);
+        double d[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          d[m] = 0.5 * dfc[m] + ((double)sDF[m * GSTR + bp] - (double)sDF[m * GSTR + bm]);
+        res[k][0] -= d[0] * inv_dn;
+        res[k][FN] -= d[1] * inv_dn;
+        res[k][FT] -= d[2] * inv_dn;
+        res[k][3] -= d[3] * inv_dn;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <class C>
+__global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel_f32(StageParams P) {
+  using F = F32Cfg<C>;
+  __shared__ double sU[C::NF * C::RS];
+  __shared__ float sPh[F::PH];
+  __shared__ unsigned char sChi[C::CHI];
+  __shared__ unsigned short sQueue[C::QMAX];
+  __shared__ int sQCount;
+  int tx0, ty0;
+  if (!tile_origin(P, C::TX, C::TY, tx0, ty0)) return;
+  stage_load<C>(P, sU, tx0, ty0);
+  __syncthreads();
+  const LdsF32 L{sU, sPh, sChi, sQueue, &sQCount};
+  double res[C::CPT][4];
+#pragma unroll
+  for (int k = 0; k < C::CPT; ++k)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) res[k][m] = 0.0;
+  for (int l0 = 0; l0 < C::TY; l0 += C::SX) sweep_f32<C, 0>(P, L, l0, tx0, ty0, res);
+  for (int l0 = 0; l0 < C::TX; l0 += C::SY) sweep_f32<C, 1>(P, L, l0, tx0, ty0, res);
+  stage_store<C>(P, res, tx0, ty0);
+}
+
+}  // namespace gbr

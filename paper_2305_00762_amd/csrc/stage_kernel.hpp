@@ -261,36 +261,11 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
     const int pos = p - 1;
     const int r = ridx(line, pos);
     const double* U = L.U;
-    // mean-state primitive eigenvectors of the normal Jacobian
-    const double rb = 0.5 * (U[r] + U[r + SN]);
-    const double pb = 0.5 * (U[3 * RS + r] + U[3 * RS + r + SN]);
-    const double irb = rcp_nr(rb);
-    const double cb = sqrt_nr(P.gamma * pb * irb);
-    const double icb = rcp_nr(cb);
-    const double h2c = 0.5 * icb, ic2 = icb * icb, h2c2 = 0.5 * ic2;
-    double cv[4][6], cg[4][6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const int rq = r + (q - 2) * SN;
-      const double w0 = U[rq], w1 = U[FN * RS + rq], w2 = U[FT * RS + rq], w3 = U[3 * RS + rq];
-      const int bq = bidx(line, pos + q + 1, WD);
-      const double g0 = sD[bq], g1 = sD[NL * WD + bq], g2 = sD[2 * NL * WD + bq],
-                   g3 = sD[3 * NL * WD + bq];
-      cv[0][q] = -rb * h2c * w1 + h2c2 * w3;
-      cv[1][q] = w0 - ic2 * w3;
-      cv[2][q] = w2;
-      cv[3][q] = rb * h2c * w1 + h2c2 * w3;
-      cg[0][q] = -rb * h2c * g1 + h2c2 * g3;
-      cg[1][q] = g0 - ic2 * g3;
-      cg[2][q] = g2;
-      cg[3][q] = rb * h2c * g1 + h2c2 * g3;
-    }
-    double cl[4], cr[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) meg7_pair(cv[m], cg[m], cl[m], cr[m]);
-    const double cor = cb * irb, c2 = cb * cb;
-    const double WL[4] = {cl[0] + cl[1] + cl[3], cor * (cl[3] - cl[0]), cl[2], c2 * (cl[0] + cl[3])};
-    const double WR[4] = {cr[0] + cr[1] + cr[3], cor * (cr[3] - cr[0]), cr[2], c2 * (cr[0] + cr[3])};
+    double WL[4], WR[4];
+    meg7_char_states(
+        [&](int q, int f) { return U[rot[f] * RS + r + (q - 2) * SN]; },
+        [&](int q, int f) { return sD[f * NL * WD + bidx(line, pos + q + 1, WD)]; },
+        P.gamma, WL, WR);
     double FL[4], FR[4], Fm[4], F[4];
     conv_flux(WL, P.g1inv, FL);
     conv_flux(WR, P.g1inv, FR);
@@ -336,34 +311,30 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
   __syncthreads();
 }
 
+// Tile owned by this workgroup.  Workgroups are dealt to the 8 XCDs
+// round-robin, so each XCD gets one contiguous run of tiles (halo rows shared
+// in its L2).  Returns false for a workgroup past the last tile.
+__device__ __forceinline__ bool tile_origin(const StageParams& P, int TX, int TY, int& tx0,
+                                            int& ty0) {
+  const int b = blockIdx.x, nb = gridDim.x;
+  const int xcd = b & 7, idx = b >> 3;
+  const int per = nb >> 3, rem = nb & 7;
+  const int tile = xcd * per + (xcd < rem ? xcd : rem) + idx;
+  if (tile >= P.ntiles) return false;
+  tx0 = (tile % P.tiles_x) * TX;
+  ty0 = (tile / P.tiles_x) * TY;
+  return true;
+}
+
+// Stage Q^(k) of the tile plus its 6-cell halo as primitives (rho, u, v, p
+// [, T = gamma p / rho]) in LDS.  All global loads are issued before any is
+// consumed, so the memory latency is paid once rather than once per round.
 template <class C>
-__global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel(StageParams P) {
-  __shared__ double sU[C::NF * C::RS];
-  __shared__ double sPh[C::PH];
-  __shared__ unsigned char sChi[C::CHI];
-  __shared__ unsigned short sQueue[C::QMAX];
-  __shared__ int sQCount;
-  constexpr int TX = C::TX, TY = C::TY, H = C::H, RX = C::RX, RS = C::RS, NT = C::NT;
-  const int tid = threadIdx.x;
-
-  // XCD-aware tile order: workgroups are dealt to the 8 XCDs round-robin, so
-  // give each XCD one contiguous run of tiles (halo rows shared in its L2).
-  int tile;
-  {
-    const int b = blockIdx.x, nb = gridDim.x;
-    const int xcd = b & 7, idx = b >> 3;
-    const int per = nb >> 3, rem = nb & 7;
-    tile = xcd * per + (xcd < rem ? xcd : rem) + idx;
-  }
-  if (tile >= P.ntiles) return;
-  const int tx0 = (tile % P.tiles_x) * TX;
-  const int ty0 = (tile / P.tiles_x) * TY;
-  const size_t n = (size_t)P.nx * P.ny;
-
-  // ---- stage Q^(k) + halo as primitives in LDS ------------------------------
-  // All global loads of the tile are issued before any is consumed, so the
-  // memory latency is paid once rather than once per round.
+__device__ __forceinline__ void stage_load(const StageParams& P, double* sU, int tx0, int ty0) {
+  constexpr int RS = C::RS, RX = C::RX, H = C::H, NT = C::NT, TX = C::TX, TY = C::TY;
   constexpr int LR = (RS + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  const size_t n = (size_t)P.nx * P.ny;
   double q[LR][4];
 #pragma unroll
   for (int k = 0; k < LR; ++k) {
@@ -400,19 +371,17 @@ __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel(StageParams 
     }
   }
   if (bad) atomicOr(P.status, STATUS_BAD_STATE);
-  __syncthreads();
+}
 
-  const Lds L{sU, sPh, sChi, sQueue, &sQCount};
-  double res[C::CPT][4];
-#pragma unroll
-  for (int k = 0; k < C::CPT; ++k)
-#pragma unroll
-    for (int m = 0; m < 4; ++m) res[k][m] = 0.0;
-
-  for (int l0 = 0; l0 < TY; l0 += C::SX) sweep<C, 0>(P, L, l0, tx0, ty0, res);
-  for (int l0 = 0; l0 < TX; l0 += C::SY) sweep<C, 1>(P, L, l0, tx0, ty0, res);
-
-  // ---- residual store or SSP-RK3 stage update, eq. (rk) ----------------------
+// Residual store or SSP-RK3 stage update, eq. (rk), for the cells this
+// thread owns (c = tid + k NT, row-major in the tile); one coalesced FP64
+// store per conserved variable.
+template <class C>
+__device__ __forceinline__ void stage_store(const StageParams& P, const double (&res)[C::CPT][4],
+                                            int tx0, int ty0) {
+  constexpr int TX = C::TX, TY = C::TY, NT = C::NT;
+  const int tid = threadIdx.x;
+  const size_t n = (size_t)P.nx * P.ny;
   const double dt = (P.mode == MODE_RESIDUAL) ? 0.0 : *P.dt;
   double qn[C::CPT][4], qk[C::CPT][4];
   bool own[C::CPT];
@@ -447,6 +416,28 @@ __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel(StageParams 
       P.out[m * n + so[k]] = v;
     }
   }
+}
+
+template <class C>
+__global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel(StageParams P) {
+  __shared__ double sU[C::NF * C::RS];
+  __shared__ double sPh[C::PH];
+  __shared__ unsigned char sChi[C::CHI];
+  __shared__ unsigned short sQueue[C::QMAX];
+  __shared__ int sQCount;
+  int tx0, ty0;
+  if (!tile_origin(P, C::TX, C::TY, tx0, ty0)) return;
+  stage_load<C>(P, sU, tx0, ty0);
+  __syncthreads();
+  const Lds L{sU, sPh, sChi, sQueue, &sQCount};
+  double res[C::CPT][4];
+#pragma unroll
+  for (int k = 0; k < C::CPT; ++k)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) res[k][m] = 0.0;
+  for (int l0 = 0; l0 < C::TY; l0 += C::SX) sweep<C, 0>(P, L, l0, tx0, ty0, res);
+  for (int l0 = 0; l0 < C::TX; l0 += C::SY) sweep<C, 1>(P, L, l0, tx0, ty0, res);
+  stage_store<C>(P, res, tx0, ty0);
 }
 
 }  // namespace gbr
