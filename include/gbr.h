@@ -126,6 +126,58 @@ int gbr_set_tiling(gbr_ctx *ctx, int variant);
 int gbr_get_tiling(gbr_ctx *ctx, int *variant, int *tile_x, int *tile_y);
 int gbr_autotune(gbr_ctx *ctx, const double *Q, int reps, void *stream);
 
+/* ---- Learned discontinuity detector ------------------------------------
+ * A small network stands in for the density detector of Sec. 2.4 (which
+ * supplies its training labels and remains the fallback for low-margin cells):
+ * features per cell = four 7-point stencils (rho and p along x and along y),
+ * each normalised as (s - mean) / ((max - min) + 1e-3) in float32 and rounded
+ * to bfloat16 (28 values, padded to 32); MLP 28 -> 32 -> 32 -> 1 with ReLU,
+ * bf16 weights, float32 accumulation on the matrix cores; output a logit,
+ * chi = [logit > 0].
+ *
+ * Parameters (float32, host arrays): w[1952] = W1 [32 out][28 in] row-major,
+ * then W2 [32][32], then w3 [32]; b[65] = b1 [32], b2 [32], b3. */
+typedef struct gbr_mlp gbr_mlp;
+
+/* Create / destroy a network object (parameters, Adam moments, scratch for
+ * batches of up to 65536 cells) on the current device. */
+int gbr_mlp_create(gbr_mlp **out);
+int gbr_mlp_destroy(gbr_mlp *m);
+
+/* Upload parameters (host w[1952], b[65]; resets the Adam state) / download
+ * the float32 master parameters (either pointer may be NULL).  Synchronous. */
+int gbr_mlp_set_params(gbr_mlp *m, const float *w, const float *b);
+int gbr_mlp_get_params(gbr_mlp *m, float *w, float *b);
+
+/* Features of every cell of the device state Q of `ctx`'s grid: feat = device
+ * [ny*nx][32] bf16 bit patterns (row = cell i*nx + j), and, if chi is not NULL,
+ * the plain label chi = [psi_x < psi_c or psi_y < psi_c] (device [ny*nx]). */
+int gbr_mlp_features(gbr_ctx *ctx, const double *Q, uint16_t *feat, uint8_t *chi,
+                     void *stream);
+
+/* Logits of n feature rows (device feat [n][32] -> device logits [n]). */
+int gbr_mlp_forward(gbr_mlp *m, const uint16_t *feat, int n, float *logits, void *stream);
+
+/* Gradient of the mean binary cross-entropy over the batch cells idx[batch]
+ * (device int32 indices into feat/labels; 1 <= batch <= 65536): grad = device
+ * float32 [2018] = d/dw [1952], d/db [65], then the summed (not averaged)
+ * loss.  Deterministic (fixed-order reduction). */
+int gbr_mlp_grad(gbr_mlp *m, const uint16_t *feat, const uint8_t *labels, const int *idx,
+                 int batch, float *grad, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
+ * gradient of the batch, learning rate lr; loss (device or host float, may be
+ * NULL) receives the batch's summed loss. */
+int gbr_mlp_train_step(gbr_mlp *m, const uint16_t *feat, const uint8_t *labels, const int *idx,
+                       int batch, float lr, float *loss, void *stream);
+
+/* Use the network's current weights as the detector of `ctx` (copied), with
+ * plain-detector fallback where |logit| < margin; select it with
+ * gbr_set_scheme(..., GBR_DET_MLP).  gbr_mlp_stats reports the cells the
+ * stage kernels evaluated and how many fell back (and optionally resets). */
+int gbr_set_mlp_detector(gbr_ctx *ctx, const gbr_mlp *m, float margin, void *stream);
+int gbr_mlp_stats(gbr_ctx *ctx, unsigned *evaluated, unsigned *fallbacks, int reset);
+
 /* Synchronise `stream`, return GBR_ESTATE if any kernel since the last check
  * saw a non-finite value or rho <= 0 or p <= 0 in an interior cell, and
  * clear that record. */

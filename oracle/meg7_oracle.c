@@ -363,7 +363,7 @@ static void char_bwd(const double Wc[4], double rb, double cb, double U[4])
 
 /* Flux through one interface (rotated frame). Returns sigma in *sig_out. */
 static void line_flux(const orc_line *L, const orc_cfg *c, double Fout[4], int *sig_out,
-                      int *nlimited)
+                      int *nlimited, int sig_given)
 {
     const double gamma = c->gamma;
     /* eq. (buffer): psi_{j+1/2} = min(psi_{j-2..j+3}); sigma = 0 iff < psi_c */
@@ -371,6 +371,7 @@ static void line_flux(const orc_line *L, const orc_cfg *c, double Fout[4], int *
     for (int k = 1; k < 6; ++k) pmin = fmin(pmin, L->psi[k]);
     int sigma = (pmin < PSI_C) ? 0 : 1;
     if (c->force_sigma == 0 || c->force_sigma == 1) sigma = c->force_sigma;
+    if (sig_given == 0 || sig_given == 1) sigma = sig_given;
     *sig_out = sigma;
 
     double WL[4], WR[4], FL[4], FR[4];
@@ -597,8 +598,8 @@ static int cfg_ok(const orc_cfg *c)
  * Q, Res: SoA [4][ny][nx], x fastest.  sig_x: [ny][nx+1] (interface j+1/2 at
  * column j+1), sig_y: [ny+1][nx] (interface i+1/2 at row i+1); may be NULL.
  * Returns the number of MP-limited components (diagnostic) or -1. */
-long orc_residual(const orc_cfg *c, const double *Q, double *Res, uint8_t *sig_x,
-                  uint8_t *sig_y)
+static long residual_impl(const orc_cfg *c, const double *Q, double *Res, uint8_t *sig_x,
+                          uint8_t *sig_y, const uint8_t *gx, const uint8_t *gy)
 {
     if (!cfg_ok(c)) return -1;
     const int nx = c->nx, ny = c->ny;
@@ -616,7 +617,7 @@ long orc_residual(const orc_cfg *c, const double *Q, double *Res, uint8_t *sig_x
         for (int j = -1; j < nx; ++j) {
             orc_line L; double f[4]; int sg; int nl = 0;
             gather_x(c, &F, i, j, &L);
-            line_flux(&L, c, f, &sg, &nl);
+            line_flux(&L, c, f, &sg, &nl, gx ? gx[(size_t)i * (nx + 1) + (j + 1)] : -1);
             nlim += nl;
             size_t s = (size_t)i * (nx + 1) + (j + 1);
             for (int m = 0; m < 4; ++m) Fx[m * nfx + s] = f[m];
@@ -628,7 +629,7 @@ long orc_residual(const orc_cfg *c, const double *Q, double *Res, uint8_t *sig_x
         for (int j = 0; j < nx; ++j) {
             orc_line L; double f[4]; int sg; int nl = 0;
             gather_y(c, &F, i, j, &L);
-            line_flux(&L, c, f, &sg, &nl);
+            line_flux(&L, c, f, &sg, &nl, gy ? gy[(size_t)(i + 1) * nx + j] : -1);
             nlim += nl;
             size_t s = (size_t)(i + 1) * nx + j;
             /* rotate back: (rho, rho v, rho u, E) -> (rho, rho u, rho v, E) */
@@ -656,6 +657,22 @@ long orc_residual(const orc_cfg *c, const double *Q, double *Res, uint8_t *sig_x
     free(Fx); free(Fy);
     fields_free(&F);
     return nlim;
+}
+
+long orc_residual(const orc_cfg *c, const double *Q, double *Res, uint8_t *sig_x,
+                  uint8_t *sig_y)
+{
+    return residual_impl(c, Q, Res, sig_x, sig_y, NULL, NULL);
+}
+
+/* The residual with the interface flags sigma given ([ny][nx+1] and
+ * [ny+1][nx], layouts as above) instead of taken from the density detector:
+ * the hybrid flux of Sec. 2.4 with any detector in place of eq. (buffer). */
+long orc_residual_sigma(const orc_cfg *c, const double *Q, double *Res, const uint8_t *sig_x,
+                        const uint8_t *sig_y)
+{
+    if (!sig_x || !sig_y) return -1;
+    return residual_impl(c, Q, Res, NULL, NULL, sig_x, sig_y);
 }
 
 /* eq. (rk): one stage of the third-order TVD Runge-Kutta scheme.
@@ -740,7 +757,7 @@ void orc_line_flux(const double *W40, const double *G24, const double *T2, const
     }
     for (int k = 0; k < 6; ++k) L.psi[k] = psi6[k];
     L.dn = dn;
-    line_flux(&L, c, F, sigma, NULL);
+    line_flux(&L, c, F, sigma, NULL, -1);
 }
 
 /* Plain detector flags chi = [psi_x < psi_c or psi_y < psi_c] per cell

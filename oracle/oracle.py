@@ -36,6 +36,8 @@ def lib():
         up = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
         L.orc_residual.restype = C.c_long
         L.orc_residual.argtypes = [C.POINTER(OrcCfg), dp, dp, C.c_void_p, C.c_void_p]
+        L.orc_residual_sigma.restype = C.c_long
+        L.orc_residual_sigma.argtypes = [C.POINTER(OrcCfg), dp, dp, up, up]
         L.orc_rk_stage.restype = C.c_long
         L.orc_rk_stage.argtypes = [C.POINTER(OrcCfg), C.c_int, C.c_double, dp, dp, dp,
                                    C.c_void_p, C.c_void_p]
@@ -91,6 +93,33 @@ def residual(cfg, Q, want_flags=False):
     if want_flags:
         return R, sx, sy, nl
     return R
+
+
+def residual_sigma(cfg, Q, sig_x, sig_y):
+    """Residual with given interface flags (sig_x [ny][nx+1], sig_y [ny+1][nx])."""
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    R = np.empty_like(Q)
+    sx = np.ascontiguousarray(sig_x, np.uint8)
+    sy = np.ascontiguousarray(sig_y, np.uint8)
+    if lib().orc_residual_sigma(C.byref(cfg), Q, R, sx, sy) < 0:
+        raise ValueError("oracle residual: bad arguments")
+    return R
+
+
+def sigma_from_cells(chi, bc_x, bc_y):
+    """Interface flags from per-cell flags chi [ny][nx]: sigma = 0 where any
+    cell of the 6-cell buffer (j-2..j+3 along the interface normal) is
+    flagged (the buffer of eq. buffer applied to a per-cell detector)."""
+    ny, nx = chi.shape
+    sx = np.ones((ny, nx + 1), np.uint8)
+    sy = np.ones((ny + 1, nx), np.uint8)
+    for j in range(-1, nx):
+        cols = [k % nx if bc_x == 0 else min(max(k, 0), nx - 1) for k in range(j - 2, j + 4)]
+        sx[:, j + 1] = (chi[:, cols].max(axis=1) == 0)
+    for i in range(-1, ny):
+        rows = [k % ny if bc_y == 0 else min(max(k, 0), ny - 1) for k in range(i - 2, i + 4)]
+        sy[i + 1, :] = (chi[rows, :].max(axis=0) == 0)
+    return sx, sy
 
 
 def rk_stage(cfg, stage, dt, Qn, Qk, want_flags=False):

@@ -7,6 +7,7 @@
 
 #include "../../include/gbr.h"
 #include "dt_kernel.hpp"
+#include "mlp_kernels.hpp"
 #include "stage_f32.hpp"
 #include "stage_kernel.hpp"
 
@@ -14,15 +15,15 @@ namespace {
 
 using namespace gbr;
 
-template <class C>
+template <class C, bool MLP = false>
 void launch_cfg(const StageParams& P, hipStream_t s) {
   static_assert(C::LDS_BYTES <= 160 * 1024, "LDS per workgroup");
-  hipLaunchKernelGGL(meg7_stage_kernel<C>, dim3(P.ntiles), dim3(C::NT), 0, s, P);
+  hipLaunchKernelGGL((meg7_stage_kernel<C, MLP>), dim3(P.ntiles), dim3(C::NT), 0, s, P);
 }
-template <class C>
+template <class C, bool MLP = false>
 void launch_cfg_f32(const StageParams& P, hipStream_t s) {
   static_assert(F32Cfg<C>::LDS_BYTES <= 160 * 1024, "LDS per workgroup");
-  hipLaunchKernelGGL(meg7_stage_kernel_f32<C>, dim3(P.ntiles), dim3(C::NT), 0, s, P);
+  hipLaunchKernelGGL((meg7_stage_kernel_f32<C, MLP>), dim3(P.ntiles), dim3(C::NT), 0, s, P);
 }
 using LaunchFn = void (*)(const StageParams&, hipStream_t);
 
@@ -32,27 +33,36 @@ using LaunchFn = void (*)(const StageParams&, hipStream_t);
 // (workgroups per CU); gbr_autotune times them on the caller's state.
 struct TileVariant {
   int tx, ty;
-  LaunchFn euler, visc;       // FP64; null: no build for this shape (use variant 0)
-  LaunchFn euler32, visc32;   // FP32 bulk
+  LaunchFn fn[2][2][2];   // [precision FP64/FP32-bulk][viscous][learned detector]; null: no build
   const char* name;
 };
+using E31 = TileCfg<31, 15, 15, 16, 256, false>;
+using V31 = TileCfg<31, 15, 8, 16, 256, true>;
+using E15 = TileCfg<15, 15, 15, 15, 256, false>;
+using V15 = TileCfg<15, 15, 15, 15, 256, true>;
 const TileVariant kVariants[] = {
     // 32 x-interfaces per row, 16 y-interfaces per column; 2 workgroups/CU
-    {31, 15, launch_cfg<TileCfg<31, 15, 15, 16, 256, false>>,
-     launch_cfg<TileCfg<31, 15, 8, 16, 256, true>>,
-     launch_cfg_f32<TileCfg<31, 15, 15, 16, 256, false>>,
-     launch_cfg_f32<TileCfg<31, 15, 8, 16, 256, true>>, "31x15"},
-    // 16 interfaces per line both ways; 3 (Euler) / 2 (viscous) workgroups/CU
-    {15, 15, launch_cfg<TileCfg<15, 15, 15, 15, 256, false>>,
-     launch_cfg<TileCfg<15, 15, 15, 15, 256, true>>,
-     launch_cfg_f32<TileCfg<15, 15, 15, 15, 256, false>>,
-     launch_cfg_f32<TileCfg<15, 15, 15, 15, 256, true>>, "15x15"},
-    // 64 x-interfaces per row, 8 y-interfaces per column (Euler only)
-    {63, 7, launch_cfg<TileCfg<63, 7, 7, 32, 256, false>>, nullptr,
-     launch_cfg_f32<TileCfg<63, 7, 7, 32, 256, false>>, nullptr, "63x7"},
+    {31, 15,
+     {{{launch_cfg<E31>, launch_cfg<E31, true>}, {launch_cfg<V31>, launch_cfg<V31, true>}},
+      {{launch_cfg_f32<E31>, launch_cfg_f32<E31, true>},
+       {launch_cfg_f32<V31>, launch_cfg_f32<V31, true>}}},
+     "31x15"},
+    // 16 interfaces per line both ways; 3-4 workgroups/CU
+    {15, 15,
+     {{{launch_cfg<E15>, launch_cfg<E15, true>}, {launch_cfg<V15>, launch_cfg<V15, true>}},
+      {{launch_cfg_f32<E15>, launch_cfg_f32<E15, true>},
+       {launch_cfg_f32<V15>, launch_cfg_f32<V15, true>}}},
+     "15x15"},
+    // 64 x-interfaces per row, 8 y-interfaces per column (Euler, plain detector)
+    {63, 7,
+     {{{launch_cfg<TileCfg<63, 7, 7, 32, 256, false>>, nullptr}, {nullptr, nullptr}},
+      {{launch_cfg_f32<TileCfg<63, 7, 7, 32, 256, false>>, nullptr}, {nullptr, nullptr}}},
+     "63x7"},
     // 31x8 / 15x16 interface blocks sized for 3 workgroups per CU in FP32 bulk
-    {30, 15, launch_cfg<TileCfg<30, 15, 15, 15, 256, false>>, nullptr,
-     launch_cfg_f32<TileCfg<30, 15, 8, 15, 256, false, 3>>, nullptr, "30x15"},
+    {30, 15,
+     {{{launch_cfg<TileCfg<30, 15, 15, 15, 256, false>>, nullptr}, {nullptr, nullptr}},
+      {{launch_cfg_f32<TileCfg<30, 15, 8, 15, 256, false, 3>>, nullptr}, {nullptr, nullptr}}},
+     "30x15"},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -71,6 +81,24 @@ struct gbr_ctx {
   uint8_t* d_sigx;
   uint8_t* d_sigy;
   int tiling;                 // index into kVariants
+  // learned detector: inference image (bf16 W1, W2; float w3, biases)
+  unsigned short* d_mlp_w;    // [2][32][32]
+  float* d_mlp_f;             // [32 + 65]
+  float mlp_margin;
+  int mlp_ready;
+  unsigned* d_mlp_count;      // [2]
+};
+
+struct gbr_mlp {
+  int device;
+  float* d_master;            // [kMlpNP] float32 parameters (weights, then biases)
+  float* d_m;                 // Adam moments
+  float* d_v;
+  unsigned short* d_w;        // bf16 inference image [2][32][32]
+  float* d_f;                 // [32 + 65]
+  float* d_partial;           // [kMlpMaxBlocks][kMlpNP + 1]
+  float* d_grad;              // [kMlpNP + 1]
+  int t;                      // Adam step count
 };
 
 extern "C" {
@@ -123,6 +151,9 @@ int gbr_destroy(gbr_ctx* c) {
   (void)hipFree(c->d_partial);
   if (c->d_sigx) (void)hipFree(c->d_sigx);
   if (c->d_sigy) (void)hipFree(c->d_sigy);
+  if (c->d_mlp_w) (void)hipFree(c->d_mlp_w);
+  if (c->d_mlp_f) (void)hipFree(c->d_mlp_f);
+  if (c->d_mlp_count) (void)hipFree(c->d_mlp_count);
   delete c;
   return GBR_OK;
 }
@@ -141,7 +172,8 @@ int gbr_set_scheme(gbr_ctx* c, int recon, int mp_mode, int precision, int detect
   if (!c) return GBR_EINVAL;
   if (recon != GBR_RECON_PRIM || mp_mode != GBR_MP_FLAGGED) return GBR_EUNSUPPORTED;
   if (precision != GBR_PREC_FP64 && precision != GBR_PREC_FP32_BULK) return GBR_EUNSUPPORTED;
-  if (detector != GBR_DET_PLAIN) return GBR_EUNSUPPORTED;
+  if (detector != GBR_DET_PLAIN && detector != GBR_DET_MLP) return GBR_EUNSUPPORTED;
+  if (detector == GBR_DET_MLP && !c->mlp_ready) return GBR_EINVAL;
   c->recon = recon; c->mp_mode = mp_mode; c->precision = precision; c->detector = detector;
   return GBR_OK;
 }
@@ -195,14 +227,22 @@ static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn
   P.gamma = c->gamma; P.g1inv = 1.0 / (c->gamma - 1.0); P.mu = c->mu;
   P.kq = c->mu / (c->Pr * (c->gamma - 1.0));
   P.mode = mode;
-  const bool visc = c->mu > 0.0;
+  const int visc = c->mu > 0.0 ? 1 : 0;
+  const int prec = c->precision == GBR_PREC_FP32_BULK ? 1 : 0;
+  const int det = c->detector == GBR_DET_MLP ? 1 : 0;
+  if (det) {
+    P.mlp.W1 = c->d_mlp_w;
+    P.mlp.W2 = c->d_mlp_w + kMlpH * kMlpIn;
+    P.mlp.w3 = c->d_mlp_f;
+    P.mlp.b = c->d_mlp_f + kMlpH;
+    P.mlp_margin = c->mlp_margin;
+    P.mlp_count = c->d_mlp_count;
+  }
   const TileVariant* v = &kVariants[c->tiling];
-  if (visc && !v->visc) v = &kVariants[0];
+  if (!v->fn[prec][visc][det]) v = &kVariants[0];
   P.tiles_x = (c->nx + v->tx - 1) / v->tx;
   P.ntiles = P.tiles_x * ((c->ny + v->ty - 1) / v->ty);
-  LaunchFn fn = (c->precision == GBR_PREC_FP32_BULK) ? (visc ? v->visc32 : v->euler32)
-                                                       : (visc ? v->visc : v->euler);
-  fn(P, s);
+  v->fn[prec][visc][det](P, s);
   return hip_ok(hipGetLastError());
 }
 
@@ -217,7 +257,9 @@ int gbr_set_tiling(gbr_ctx* c, int variant) {
 int gbr_get_tiling(gbr_ctx* c, int* variant, int* tile_x, int* tile_y) {
   if (!c) return GBR_EINVAL;
   const TileVariant* v = &kVariants[c->tiling];
-  if (c->mu > 0.0 && !v->visc) v = &kVariants[0];
+  const int visc = c->mu > 0.0 ? 1 : 0, prec = c->precision == GBR_PREC_FP32_BULK ? 1 : 0;
+  const int det = c->detector == GBR_DET_MLP ? 1 : 0;
+  if (!v->fn[prec][visc][det]) v = &kVariants[0];
   if (variant) *variant = (int)(v - kVariants);
   if (tile_x) *tile_x = v->tx;
   if (tile_y) *tile_y = v->ty;
@@ -238,8 +280,10 @@ int gbr_autotune(gbr_ctx* c, const double* Q, int reps, void* stream) {
   c->export_flags = 0;
   int best = saved, rc = GBR_OK;
   float best_ms = 1e30f;
+  const int visc = c->mu > 0.0 ? 1 : 0, prec = c->precision == GBR_PREC_FP32_BULK ? 1 : 0;
+  const int det = c->detector == GBR_DET_MLP ? 1 : 0;
   for (int v = 0; v < kNumVariants && rc == GBR_OK; ++v) {
-    if (c->mu > 0.0 && !kVariants[v].visc) continue;
+    if (!kVariants[v].fn[prec][visc][det]) continue;
     c->tiling = v;
     rc = launch_stage(c, MODE_RESIDUAL, nullptr, Q, Q, tmp, s);  // warm-up
     if (rc != GBR_OK) break;
@@ -288,6 +332,162 @@ int gbr_compute_dt(gbr_ctx* c, const double* Q, double cfl, double* dt_dev, void
   hipLaunchKernelGGL(dt_finish_kernel, dim3(1), dim3(kDtThreads), 0, s, c->d_partial, blocks,
                      dt_dev, cfl, c->d_status);
   return hip_ok(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Learned detector.
+static constexpr int kMlpMaxBatch = 1 << 16;
+static constexpr int kMlpMaxBlocks = kMlpMaxBatch / 256;
+
+int gbr_mlp_create(gbr_mlp** out) {
+  if (!out) return GBR_EINVAL;
+  *out = nullptr;
+  gbr_mlp* m = new (std::nothrow) gbr_mlp();
+  if (!m) return GBR_ENOMEM;
+  if (hipGetDevice(&m->device) != hipSuccess) { delete m; return GBR_EDEVICE; }
+  bool ok = hipMalloc(&m->d_master, kMlpNP * sizeof(float)) == hipSuccess &&
+            hipMalloc(&m->d_m, kMlpNP * sizeof(float)) == hipSuccess &&
+            hipMalloc(&m->d_v, kMlpNP * sizeof(float)) == hipSuccess &&
+            hipMalloc(&m->d_w, 2 * kMlpH * kMlpIn * sizeof(unsigned short)) == hipSuccess &&
+            hipMalloc(&m->d_f, (kMlpH + kMlpNB) * sizeof(float)) == hipSuccess &&
+            hipMalloc(&m->d_partial, (size_t)kMlpMaxBlocks * (kMlpNP + 1) * sizeof(float)) == hipSuccess &&
+            hipMalloc(&m->d_grad, (kMlpNP + 1) * sizeof(float)) == hipSuccess;
+  if (!ok) { gbr_mlp_destroy(m); return GBR_ENOMEM; }
+  if (hipMemset(m->d_w, 0, 2 * kMlpH * kMlpIn * sizeof(unsigned short)) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    gbr_mlp_destroy(m);
+    return GBR_EDEVICE;
+  }
+  *out = m;
+  return GBR_OK;
+}
+
+int gbr_mlp_destroy(gbr_mlp* m) {
+  if (!m) return GBR_OK;
+  (void)hipDeviceSynchronize();
+  for (void* p : {(void*)m->d_master, (void*)m->d_m, (void*)m->d_v, (void*)m->d_w, (void*)m->d_f,
+                  (void*)m->d_partial, (void*)m->d_grad})
+    if (p) (void)hipFree(p);
+  delete m;
+  return GBR_OK;
+}
+
+int gbr_mlp_set_params(gbr_mlp* m, const float* w, const float* b) {
+  if (!m || !w || !b) return GBR_EINVAL;
+  if (hipMemcpy(m->d_master, w, kMlpNW * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->d_master + kMlpNW, b, kMlpNB * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(m->d_m, 0, kMlpNP * sizeof(float)) != hipSuccess ||
+      hipMemset(m->d_v, 0, kMlpNP * sizeof(float)) != hipSuccess)
+    return GBR_EDEVICE;
+  m->t = 0;
+  hipLaunchKernelGGL(mlp_publish_kernel, dim3((kMlpNP + 255) / 256), dim3(256), 0, 0, m->d_master,
+                     m->d_w, m->d_w + kMlpH * kMlpIn, m->d_f, m->d_f + kMlpH);
+  return hip_ok(hipDeviceSynchronize());
+}
+
+int gbr_mlp_get_params(gbr_mlp* m, float* w, float* b) {
+  if (!m) return GBR_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return GBR_EDEVICE;
+  if (w && hipMemcpy(w, m->d_master, kMlpNW * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+    return GBR_EDEVICE;
+  if (b && hipMemcpy(b, m->d_master + kMlpNW, kMlpNB * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+    return GBR_EDEVICE;
+  return GBR_OK;
+}
+
+static MlpImage mlp_image(const gbr_mlp* m) {
+  MlpImage M;
+  M.W1 = m->d_w;
+  M.W2 = m->d_w + kMlpH * kMlpIn;
+  M.w3 = m->d_f;
+  M.b = m->d_f + kMlpH;
+  return M;
+}
+
+int gbr_mlp_features(gbr_ctx* c, const double* Q, uint16_t* feat, uint8_t* chi, void* stream) {
+  if (!c || !Q || !feat) return GBR_EINVAL;
+  MlpFeatParams P{};
+  P.Q = Q; P.feat = feat; P.chi = chi;
+  P.nx = c->nx; P.ny = c->ny; P.bcx = c->bcx; P.bcy = c->bcy; P.gamma = c->gamma;
+  const size_t n = (size_t)c->nx * c->ny;
+  hipLaunchKernelGGL(mlp_features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, P);
+  return hip_ok(hipGetLastError());
+}
+
+int gbr_mlp_forward(gbr_mlp* m, const uint16_t* feat, int n, float* logits, void* stream) {
+  if (!m || !feat || !logits || n <= 0) return GBR_EINVAL;
+  hipLaunchKernelGGL(mlp_forward_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                     mlp_image(m), feat, n, logits);
+  return hip_ok(hipGetLastError());
+}
+
+int gbr_mlp_grad(gbr_mlp* m, const uint16_t* feat, const uint8_t* labels, const int* idx,
+                 int batch, float* grad, void* stream) {
+  if (!m || !feat || !labels || !idx || !grad) return GBR_EINVAL;
+  if (batch <= 0 || batch > kMlpMaxBatch) return GBR_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  MlpGradParams P;
+  P.M = mlp_image(m);
+  P.feat = feat; P.label = labels; P.idx = idx; P.batch = batch; P.partial = m->d_partial;
+  const int nblk = (batch + 255) / 256;
+  hipLaunchKernelGGL(mlp_grad_kernel, dim3(nblk), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(mlp_sum_kernel, dim3((kMlpNP + 1 + 255) / 256), dim3(256), 0, s,
+                     (const float*)m->d_partial, nblk, grad);
+  return hip_ok(hipGetLastError());
+}
+
+int gbr_mlp_train_step(gbr_mlp* m, const uint16_t* feat, const uint8_t* labels, const int* idx,
+                       int batch, float lr, float* loss, void* stream) {
+  if (!(lr > 0.f)) return GBR_EINVAL;
+  int rc = gbr_mlp_grad(m, feat, labels, idx, batch, m ? m->d_grad : nullptr, stream);
+  if (rc != GBR_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  m->t += 1;
+  AdamParams A;
+  A.grad = m->d_grad; A.master = m->d_master; A.m = m->d_m; A.v = m->d_v;
+  A.W1 = m->d_w; A.W2 = m->d_w + kMlpH * kMlpIn; A.w3 = m->d_f; A.b = m->d_f + kMlpH;
+  A.lr = lr; A.beta1 = 0.9f; A.beta2 = 0.999f; A.eps = 1e-8f;
+  A.bc1 = 1.0f - powf(0.9f, (float)m->t);
+  A.bc2 = 1.0f - powf(0.999f, (float)m->t);
+  hipLaunchKernelGGL(mlp_adam_kernel, dim3((kMlpNP + 255) / 256), dim3(256), 0, s, A);
+  if (loss && hipMemcpyAsync(loss, m->d_grad + kMlpNP, sizeof(float), hipMemcpyDefault, s) != hipSuccess)
+    return GBR_EDEVICE;
+  return hip_ok(hipGetLastError());
+}
+
+int gbr_set_mlp_detector(gbr_ctx* c, const gbr_mlp* m, float margin, void* stream) {
+  if (!c || !m || !(margin >= 0.f)) return GBR_EINVAL;
+  if (!c->d_mlp_w) {
+    if (hipMalloc(&c->d_mlp_w, 2 * kMlpH * kMlpIn * sizeof(unsigned short)) != hipSuccess ||
+        hipMalloc(&c->d_mlp_f, (kMlpH + kMlpNB) * sizeof(float)) != hipSuccess ||
+        hipMalloc(&c->d_mlp_count, 2 * sizeof(unsigned)) != hipSuccess)
+      return GBR_ENOMEM;
+    if (hipMemset(c->d_mlp_count, 0, 2 * sizeof(unsigned)) != hipSuccess) return GBR_EDEVICE;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(c->d_mlp_w, m->d_w, 2 * kMlpH * kMlpIn * sizeof(unsigned short),
+                     hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(c->d_mlp_f, m->d_f, (kMlpH + kMlpNB) * sizeof(float), hipMemcpyDeviceToDevice,
+                     s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return GBR_EDEVICE;
+  c->mlp_margin = margin;
+  c->mlp_ready = 1;
+  return GBR_OK;
+}
+
+int gbr_mlp_stats(gbr_ctx* c, unsigned* evaluated, unsigned* fallbacks, int reset) {
+  if (!c || !c->d_mlp_count) return GBR_EINVAL;
+  unsigned h[2];
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(h, c->d_mlp_count, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+    return GBR_EDEVICE;
+  if (evaluated) *evaluated = h[0];
+  if (fallbacks) *fallbacks = h[1];
+  if (reset && (hipMemset(c->d_mlp_count, 0, sizeof(h)) != hipSuccess || hipDeviceSynchronize() != hipSuccess))
+    return GBR_EDEVICE;
+  return GBR_OK;
 }
 
 }  // extern "C"

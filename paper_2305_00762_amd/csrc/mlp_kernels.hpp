@@ -1,0 +1,475 @@
+// Learned discontinuity detector: per-cell features, an MLP 28 -> 32 -> 32 -> 1
+// (bf16 weights, fp32 accumulation on the matrix cores), its training
+// (forward, backward, Adam) and its inference.
+//
+// Matrix-core layout.  v_mfma_f32_16x16x16_bf16 multiplies a 16x16 A (M x K)
+// by a 16x16 B (K x N).  In a wave, lane l = 16 g + r (g = 0..3, r = 0..15)
+// supplies A[r][4g..4g+3] and B[4g..4g+3][r] and receives D[4g..4g+3][r].
+// The network is evaluated transposed, hidden = W x^T: A is a weight block
+// (rows = neurons), B an activation block (columns = 16 cells).  The output of
+// one layer (lane holds neurons 4g..4g+3 of cell r) is then exactly the B
+// operand of the next layer, so activations never leave registers.
+#pragma once
+#include "meg7_device.hpp"
+
+namespace gbr {
+
+constexpr int kMlpF = 28;             // features
+constexpr int kMlpIn = 32;            // padded input width
+constexpr int kMlpH = 32;             // hidden width
+constexpr int kMlpNW = kMlpH * kMlpF + kMlpH * kMlpH + kMlpH;   // 1952 weights
+constexpr int kMlpNB = 2 * kMlpH + 1;                            // 65 biases
+constexpr int kMlpNP = kMlpNW + kMlpNB;                          // 2017 parameters
+constexpr int kMlpWB = 2 * kMlpH * kMlpIn + kMlpH;               // bf16 inference image
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// float32 -> bfloat16, round to nearest even (finite inputs)
+__device__ __forceinline__ unsigned short f2bf(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
+
+__device__ __forceinline__ v4s pack4(float a, float b, float c, float d) {
+  v4s r;
+  r[0] = (short)f2bf(a); r[1] = (short)f2bf(b); r[2] = (short)f2bf(c); r[3] = (short)f2bf(d);
+  return r;
+}
+
+// Features of one cell.  val(s, o) returns, in FP64, the stencil value at
+// offset o (-3..3) of stencil s: 0 rho along x, 1 p along x, 2 rho along y,
+// 3 p along y.  Each stencil is taken to float32 and normalised as
+// (s_k - mean) / ((max - min) + 1e-3) with a fixed operation order (sum left
+// to right, mean = sum * fl(1/7), one IEEE reciprocal), then rounded to bf16.
+template <class FV>
+__device__ __forceinline__ void mlp_cell_features(FV val, unsigned short out[kMlpIn]) {
+#pragma clang fp contract(off)
+  int col = 0;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    float v[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) v[k] = (float)val(s, k - 3);
+    float tot = v[0];
+#pragma unroll
+    for (int k = 1; k < 7; ++k) tot = tot + v[k];
+    const float mean = tot * (1.0f / 7.0f);
+    float mx = v[0], mn = v[0];
+#pragma unroll
+    for (int k = 1; k < 7; ++k) { mx = fmaxf(mx, v[k]); mn = fminf(mn, v[k]); }
+    const float r = 1.0f / ((mx - mn) + 1e-3f);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) out[col++] = f2bf((v[k] - mean) * r);
+  }
+#pragma unroll
+  for (int k = kMlpF; k < kMlpIn; ++k) out[k] = 0;
+}
+
+// Inference image of the network: bf16 W1 [32][32] (inputs 28..31 zero), bf16
+// W2 [32][32], then float32 w3 [32] (bf16-valued), b1 [32], b2 [32], b3.
+struct MlpImage {
+  const unsigned short* W1;
+  const unsigned short* W2;
+  const float* w3;
+  const float* b;   // [65]
+};
+
+// Per-lane weight fragments and bias/output weights in the D layout.
+struct MlpFrags {
+  v4s a1[2][2], a2[2][2];   // [neuron block][k step]
+  float b1[2][4], b2[2][4], w3[2][4];
+  float b3;
+};
+
+__device__ __forceinline__ void mlp_load_frags(const MlpImage& M, MlpFrags& F) {
+  const int l = __lane_id(), r = l & 15, g = l >> 4;
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const int n = 16 * nb + r, k = 16 * ks + 4 * g;
+      F.a1[nb][ks] = *reinterpret_cast<const v4s*>(M.W1 + n * kMlpIn + k);
+      F.a2[nb][ks] = *reinterpret_cast<const v4s*>(M.W2 + n * kMlpH + k);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int n = 16 * nb + 4 * g + i;
+      F.b1[nb][i] = M.b[n];
+      F.b2[nb][i] = M.b[kMlpH + n];
+      F.w3[nb][i] = M.w3[n];
+    }
+  }
+  F.b3 = M.b[2 * kMlpH];
+}
+
+// Forward pass of 16 cells whose bf16 B fragments (k steps 0, 1) are x0, x1.
+// Returns the logit of cell r = lane & 15 (the same in the four lanes of a
+// column); a1/a2 (pre-activations) and h (bf16 h1 fragments) on request.
+struct MlpFwdState {
+  v4f a1[2], a2[2];
+  v4s h[2];
+};
+__device__ __forceinline__ float mlp_forward16(const MlpFrags& F, v4s x0, v4s x1, MlpFwdState* st) {
+  v4f d1[2], d2[2];
+  v4s h[2];
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    v4f c = {0.f, 0.f, 0.f, 0.f};
+    c = mfma16(F.a1[nb][0], x0, c);
+    c = mfma16(F.a1[nb][1], x1, c);
+    d1[nb] = c;
+    float hv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) hv[i] = fmaxf(c[i] + F.b1[nb][i], 0.f);
+    h[nb] = pack4(hv[0], hv[1], hv[2], hv[3]);
+  }
+  float part = 0.f;
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    v4f c = {0.f, 0.f, 0.f, 0.f};
+    c = mfma16(F.a2[nb][0], h[0], c);
+    c = mfma16(F.a2[nb][1], h[1], c);
+    d2[nb] = c;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) part += F.w3[nb][i] * fmaxf(c[i] + F.b2[nb][i], 0.f);
+  }
+  part += __shfl_xor(part, 16);
+  part += __shfl_xor(part, 32);
+  if (st) {
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) { st->a1[nb] = d1[nb]; st->a2[nb] = d2[nb]; st->h[nb] = h[nb]; }
+  }
+  return part + F.b3;
+}
+
+// ---------------------------------------------------------------------------
+// Features and plain labels of a whole grid (training data, evaluation).
+struct MlpFeatParams {
+  const double* Q;
+  unsigned short* feat;   // [n][32]
+  uint8_t* chi;           // [n] or null: plain label [psi_x < psi_c or psi_y < psi_c]
+  int nx, ny, bcx, bcy;
+  double gamma;
+};
+
+__device__ __forceinline__ int wrap_bc(int k, int n, int bc) {
+  if (bc == 0) {
+    while (k < 0) k += n;
+    while (k >= n) k -= n;
+    return k;
+  }
+  return k < 0 ? 0 : (k >= n ? n - 1 : k);
+}
+
+__global__ __launch_bounds__(256) void mlp_features_kernel(MlpFeatParams P) {
+  const size_t n = (size_t)P.nx * P.ny;
+  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int i = (int)(c / P.nx), j = (int)(c % P.nx);
+  auto cell = [&](int ii, int jj, int want_p) -> double {
+    const size_t s = (size_t)wrap_bc(ii, P.ny, P.bcy) * P.nx + wrap_bc(jj, P.nx, P.bcx);
+    const double r = P.Q[s];
+    if (!want_p) return r;
+    const double u = P.Q[n + s] / r, v = P.Q[2 * n + s] / r;
+    return (P.gamma - 1.0) * (P.Q[3 * n + s] - r * (u * u + v * v) / 2.0);
+  };
+  unsigned short f[kMlpIn];
+  mlp_cell_features(
+      [&](int s, int o) {
+        return (s < 2) ? cell(i, j + o, s & 1) : cell(i + o, j, s & 1);
+      },
+      f);
+  uint4* dst = reinterpret_cast<uint4*>(P.feat + c * kMlpIn);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    uint4 w;
+    w.x = f[8 * q + 0] | ((unsigned)f[8 * q + 1] << 16);
+    w.y = f[8 * q + 2] | ((unsigned)f[8 * q + 3] << 16);
+    w.z = f[8 * q + 4] | ((unsigned)f[8 * q + 5] << 16);
+    w.w = f[8 * q + 6] | ((unsigned)f[8 * q + 7] << 16);
+    dst[q] = w;
+  }
+  if (P.chi) {
+    const double px = detector_psi(cell(i, j - 2, 0), cell(i, j - 1, 0), cell(i, j, 0),
+                                   cell(i, j + 1, 0), cell(i, j + 2, 0));
+    const double py = detector_psi(cell(i - 2, j, 0), cell(i - 1, j, 0), cell(i, j, 0),
+                                   cell(i + 1, j, 0), cell(i + 2, j, 0));
+    P.chi[c] = (px < kPsiC || py < kPsiC) ? 1 : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inference over a feature array: logits[c] for c < n.  One wave per 64 cells.
+__global__ __launch_bounds__(256) void mlp_forward_kernel(MlpImage M, const unsigned short* feat,
+                                                          int n, float* logits) {
+  MlpFrags F;
+  mlp_load_frags(M, F);
+  const int l = __lane_id(), r = l & 15, g = l >> 4;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    const int c = wave * 64 + cb * 16 + r;
+    const int cc = c < n ? c : n - 1;
+    const v4s x0 = *reinterpret_cast<const v4s*>(feat + (size_t)cc * kMlpIn + 4 * g);
+    const v4s x1 = *reinterpret_cast<const v4s*>(feat + (size_t)cc * kMlpIn + 16 + 4 * g);
+    const float z = mlp_forward16(F, x0, x1, nullptr);
+    if (g == 0 && c < n) logits[c] = z;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Training: per workgroup of 256 threads, 256 batch cells (64 per wave):
+// forward, BCE-with-logits loss, backward; the workgroup's gradient sum is
+// written to partial[blockIdx.x][0..2016] and its loss sum to [2017].
+struct MlpGradParams {
+  MlpImage M;
+  const unsigned short* feat;   // [N][32]
+  const uint8_t* label;         // [N]
+  const int* idx;               // [batch]
+  int batch;
+  float* partial;               // [nblocks][kMlpNP + 1]
+};
+
+__global__ __launch_bounds__(256) void mlp_grad_kernel(MlpGradParams P) {
+  __shared__ unsigned short sT[4][2][16 * kMlpIn];   // per wave: [0] dh rows, [1] activation rows
+  __shared__ float sRed[4][kMlpNP + 1];
+  const int l = __lane_id(), r = l & 15, g = l >> 4, w = threadIdx.x >> 6;
+  MlpFrags F;
+  mlp_load_frags(P.M, F);
+  // A operand of dh1^T = W2^T dh2^T: lane holds W2[16 ks + 4 g + i][16 mb + r]
+  v4s a2t[2][2];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        a2t[mb][ks][i] = (short)P.M.W2[(16 * ks + 4 * g + i) * kMlpH + 16 * mb + r];
+  const float invB = 1.0f / (float)P.batch;
+
+  v4f gW1[2][2], gW2[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      gW1[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
+      gW2[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
+    }
+  float gw3[2][4], gb1[2][4], gb2[2][4], gb3 = 0.f, lsum = 0.f;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { gw3[a][i] = 0.f; gb1[a][i] = 0.f; gb2[a][i] = 0.f; }
+
+  unsigned short* sDh = sT[w][0];
+  unsigned short* sAct = sT[w][1];
+#pragma unroll 1
+  for (int cb = 0; cb < 4; ++cb) {
+    const int bi = blockIdx.x * 256 + w * 64 + cb * 16 + r;
+    const bool valid = bi < P.batch;
+    const int cell = P.idx[valid ? bi : 0];
+    const unsigned short* xr = P.feat + (size_t)cell * kMlpIn;
+    const v4s x0 = *reinterpret_cast<const v4s*>(xr + 4 * g);
+    const v4s x1 = *reinterpret_cast<const v4s*>(xr + 16 + 4 * g);
+    MlpFwdState st;
+    const float z = mlp_forward16(F, x0, x1, &st);
+    const float y = valid ? (float)P.label[cell] : 0.f;
+    // mean BCE with logits; dz = (sigmoid(z) - y) / B
+    const float dz = valid ? (1.0f / (1.0f + __expf(-z)) - y) * invB : 0.f;
+    if (g == 0 && valid) lsum += fmaxf(z, 0.f) - z * y + __logf(1.0f + __expf(-fabsf(z)));
+    // output layer and dh2 (D layout: lane holds neurons 16 nb + 4 g + i of cell r)
+    float dh2[2][4];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float a2 = st.a2[nb][i] + F.b2[nb][i];
+        const float h2 = fmaxf(a2, 0.f);
+        gw3[nb][i] += dz * h2;
+        dh2[nb][i] = (a2 > 0.f) ? dz * F.w3[nb][i] : 0.f;
+        gb2[nb][i] += dh2[nb][i];
+      }
+    gb3 += (g == 0) ? dz : 0.f;
+    v4s dh2p[2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) dh2p[nb] = pack4(dh2[nb][0], dh2[nb][1], dh2[nb][2], dh2[nb][3]);
+    // dh1^T = W2^T dh2^T, masked by the layer-1 activation
+    v4s dh1p[2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      v4f c = {0.f, 0.f, 0.f, 0.f};
+      c = mfma16(a2t[mb][0], dh2p[0], c);
+      c = mfma16(a2t[mb][1], dh2p[1], c);
+      float d[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        d[i] = (st.a1[mb][i] + F.b1[mb][i] > 0.f) ? c[i] : 0.f;
+        gb1[mb][i] += d[i];
+      }
+      dh1p[mb] = pack4(d[0], d[1], d[2], d[3]);
+    }
+    // weight gradients need the cells as the reduction dimension: stage the
+    // 16-cell blocks of dh2 and h1 (then dh1 and x) row-wise in LDS and read
+    // them back transposed.
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        sDh[r * kMlpIn + 16 * nb + 4 * g + i] = (unsigned short)dh2p[nb][i];
+        sAct[r * kMlpIn + 16 * nb + 4 * g + i] = (unsigned short)st.h[nb][i];
+      }
+    __syncthreads();
+    // dW2[n2][k] += sum_c dh2[c][n2] h1[c][k]: A = dh2^T, B = h1 (K = cells)
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      v4s a;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = (short)sDh[(4 * g + i) * kMlpIn + 16 * mb + r];
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        v4s b;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b[i] = (short)sAct[(4 * g + i) * kMlpIn + 16 * nb + r];
+        gW2[mb][nb] = mfma16(a, b, gW2[mb][nb]);
+      }
+    }
+    __syncthreads();
+    // dW1[n1][k] += sum_c dh1[c][n1] x[c][k]
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sDh[r * kMlpIn + 16 * mb + 4 * g + i] = (unsigned short)dh1p[mb][i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      sAct[r * kMlpIn + 4 * g + i] = (unsigned short)x0[i];
+      sAct[r * kMlpIn + 16 + 4 * g + i] = (unsigned short)x1[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      v4s a;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = (short)sDh[(4 * g + i) * kMlpIn + 16 * mb + r];
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        v4s b;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b[i] = (short)sAct[(4 * g + i) * kMlpIn + 16 * nb + r];
+        gW1[mb][nb] = mfma16(a, b, gW1[mb][nb]);
+      }
+    }
+    __syncthreads();
+  }
+  // reduce the per-lane partial sums over the 16 cells of each lane column
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        gw3[a][i] += __shfl_xor(gw3[a][i], o);
+        gb1[a][i] += __shfl_xor(gb1[a][i], o);
+        gb2[a][i] += __shfl_xor(gb2[a][i], o);
+      }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    gb3 += __shfl_xor(gb3, o);
+    lsum += __shfl_xor(lsum, o);
+  }
+  float* red = sRed[w];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * mb + 4 * g + i, col = 16 * nb + r;
+        if (col < kMlpF) red[row * kMlpF + col] = gW1[mb][nb][i];
+        red[kMlpH * kMlpF + row * kMlpH + col] = gW2[mb][nb][i];
+      }
+  if (r == 0) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int nn = 16 * a + 4 * g + i;
+        red[kMlpH * kMlpF + kMlpH * kMlpH + nn] = gw3[a][i];
+        red[kMlpNW + nn] = gb1[a][i];
+        red[kMlpNW + kMlpH + nn] = gb2[a][i];
+      }
+  }
+  if (l == 0) {
+    red[kMlpNW + 2 * kMlpH] = gb3;
+    red[kMlpNP] = lsum;
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < kMlpNP + 1; p += 256)
+    P.partial[(size_t)blockIdx.x * (kMlpNP + 1) + p] =
+        ((sRed[0][p] + sRed[1][p]) + sRed[2][p]) + sRed[3][p];
+}
+
+// Sum of the workgroup partials in a fixed order: grad[p] (and loss at kMlpNP).
+__global__ __launch_bounds__(256) void mlp_sum_kernel(const float* partial, int nblk, float* out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > kMlpNP) return;
+  float s = 0.f;
+  for (int b = 0; b < nblk; ++b) s += partial[(size_t)b * (kMlpNP + 1) + p];
+  out[p] = s;
+}
+
+// Adam step on the float32 master parameters [2017] (weights then biases) and
+// refresh of the bf16 inference image.
+struct AdamParams {
+  const float* grad;   // [kMlpNP + 1]
+  float* master;       // [kMlpNP]
+  float* m;
+  float* v;
+  unsigned short* W1;  // [32][32]
+  unsigned short* W2;  // [32][32]
+  float* w3;           // [32]
+  float* b;            // [65]
+  float lr, beta1, beta2, eps, bc1, bc2;   // bc = 1 - beta^t
+};
+
+__device__ __forceinline__ void mlp_publish(int p, float w, unsigned short* W1, unsigned short* W2,
+                                            float* w3, float* b) {
+  if (p < kMlpH * kMlpF) {
+    W1[(p / kMlpF) * kMlpIn + p % kMlpF] = f2bf(w);
+  } else if (p < kMlpH * kMlpF + kMlpH * kMlpH) {
+    W2[p - kMlpH * kMlpF] = f2bf(w);
+  } else if (p < kMlpNW) {
+    w3[p - kMlpH * kMlpF - kMlpH * kMlpH] = bf2f(f2bf(w));
+  } else {
+    b[p - kMlpNW] = w;
+  }
+}
+
+__global__ __launch_bounds__(256) void mlp_adam_kernel(AdamParams A) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kMlpNP) return;
+  const float gr = A.grad[p];
+  const float m = A.beta1 * A.m[p] + (1.f - A.beta1) * gr;
+  const float v = A.beta2 * A.v[p] + (1.f - A.beta2) * gr * gr;
+  A.m[p] = m;
+  A.v[p] = v;
+  const float w = A.master[p] - A.lr * (m / A.bc1) / (sqrtf(v / A.bc2) + A.eps);
+  A.master[p] = w;
+  mlp_publish(p, w, A.W1, A.W2, A.w3, A.b);
+}
+
+// Publish a full parameter vector (after a host upload): zero the padding too.
+__global__ __launch_bounds__(256) void mlp_publish_kernel(const float* master, unsigned short* W1,
+                                                          unsigned short* W2, float* w3, float* b) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < kMlpH * (kMlpIn - kMlpF)) W1[(p / (kMlpIn - kMlpF)) * kMlpIn + kMlpF + p % (kMlpIn - kMlpF)] = 0;
+  if (p < kMlpNP) mlp_publish(p, master[p], W1, W2, w3, b);
+}
+
+}  // namespace gbr

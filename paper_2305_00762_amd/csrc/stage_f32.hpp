@@ -93,9 +93,10 @@ struct LdsF32 {
   unsigned char* chi;
   unsigned short* queue;
   int* qcount;
+  const unsigned char* chif;
 };
 
-template <class C, int DIR>
+template <class C, int DIR, bool DETMLP>
 __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L, int l0, int tx0,
                                           int ty0, double (&res)[C::CPT][4]) {
   constexpr bool X = (DIR == 0);
@@ -164,9 +165,13 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
         sD[m * NL * WD + bidx(line, k + 3, WD)] =
             (float)grad6(u[-3 * SN], u[-2 * SN], u[-SN], u[SN], u[2 * SN], u[3 * SN]);
       }
-      const double* rho = U + r;
-      const double psi = detector_psi(rho[-2 * SN], rho[-SN], rho[0], rho[SN], rho[2 * SN]);
-      L.chi[bidx(line, k + 3, WD)] = (psi < kPsiC) ? 1 : 0;
+      if (DETMLP) {
+        L.chi[bidx(line, k + 3, WD)] = L.chif[mlp_chi_index<C>(X ? k : l0 + line, X ? l0 + line : k)];
+      } else {
+        const double* rho = U + r;
+        const double psi = detector_psi(rho[-2 * SN], rho[-SN], rho[0], rho[SN], rho[2 * SN]);
+        L.chi[bidx(line, k + 3, WD)] = (psi < kPsiC) ? 1 : 0;
+      }
     }
     if (C::VISC && k >= -1 && k < N + 1) {
 #pragma unroll
@@ -357,26 +362,29 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
   __syncthreads();
 }
 
-template <class C>
+template <class C, bool DETMLP>
 __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel_f32(StageParams P) {
   using F = F32Cfg<C>;
+  constexpr int PHS = F::PH > C::NT * kMlpIn / 2 ? F::PH : C::NT * kMlpIn / 2;
   __shared__ double sU[C::NF * C::RS];
-  __shared__ float sPh[F::PH];
+  __shared__ float sPh[DETMLP ? PHS : F::PH];
   __shared__ unsigned char sChi[C::CHI];
   __shared__ unsigned short sQueue[C::QMAX];
+  __shared__ unsigned char sChiF[DETMLP ? (C::TX + 6) * (C::TY + 6) : 1];
   __shared__ int sQCount;
   int tx0, ty0;
   if (!tile_origin(P, C::TX, C::TY, tx0, ty0)) return;
   stage_load<C>(P, sU, tx0, ty0);
   __syncthreads();
-  const LdsF32 L{sU, sPh, sChi, sQueue, &sQCount};
+  if (DETMLP) mlp_tile_flags<C>(P, sU, reinterpret_cast<unsigned short*>(sPh), sChiF);
+  const LdsF32 L{sU, sPh, sChi, sQueue, &sQCount, sChiF};
   double res[C::CPT][4];
 #pragma unroll
   for (int k = 0; k < C::CPT; ++k)
 #pragma unroll
     for (int m = 0; m < 4; ++m) res[k][m] = 0.0;
-  for (int l0 = 0; l0 < C::TY; l0 += C::SX) sweep_f32<C, 0>(P, L, l0, tx0, ty0, res);
-  for (int l0 = 0; l0 < C::TX; l0 += C::SY) sweep_f32<C, 1>(P, L, l0, tx0, ty0, res);
+  for (int l0 = 0; l0 < C::TY; l0 += C::SX) sweep_f32<C, 0, DETMLP>(P, L, l0, tx0, ty0, res);
+  for (int l0 = 0; l0 < C::TX; l0 += C::SY) sweep_f32<C, 1, DETMLP>(P, L, l0, tx0, ty0, res);
   stage_store<C>(P, res, tx0, ty0);
 }
 

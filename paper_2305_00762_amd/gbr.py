@@ -48,6 +48,16 @@ SIGNATURES = {
     "gbr_set_tiling": (_i, [_vp, _i]),
     "gbr_get_tiling": (_i, [_vp, C.POINTER(_i), C.POINTER(_i), C.POINTER(_i)]),
     "gbr_autotune": (_i, [_vp, _vp, _i, _vp]),
+    "gbr_mlp_create": (_i, [C.POINTER(_vp)]),
+    "gbr_mlp_destroy": (_i, [_vp]),
+    "gbr_mlp_set_params": (_i, [_vp, _vp, _vp]),
+    "gbr_mlp_get_params": (_i, [_vp, _vp, _vp]),
+    "gbr_mlp_features": (_i, [_vp, _vp, _vp, _vp, _vp]),
+    "gbr_mlp_forward": (_i, [_vp, _vp, _i, _vp, _vp]),
+    "gbr_mlp_grad": (_i, [_vp, _vp, _vp, _vp, _i, _vp, _vp]),
+    "gbr_mlp_train_step": (_i, [_vp, _vp, _vp, _vp, _i, C.c_float, _vp, _vp]),
+    "gbr_set_mlp_detector": (_i, [_vp, _vp, C.c_float, _vp]),
+    "gbr_mlp_stats": (_i, [_vp, C.POINTER(C.c_uint), C.POINTER(C.c_uint), _i]),
 }
 
 _lib = None
@@ -180,3 +190,64 @@ def gbr_get_tiling(ctx):
 def gbr_autotune(ctx, Q, reps=3, stream=None):
     _check(load().gbr_autotune(ctx, _addr(Q), reps, _stream(stream)), "gbr_autotune")
     return gbr_get_tiling(ctx)
+
+
+MLP_NW = 1952
+MLP_NB = 65
+
+
+def gbr_mlp_create():
+    h = C.c_void_p()
+    _check(load().gbr_mlp_create(C.byref(h)), "gbr_mlp_create")
+    return h.value
+
+
+def gbr_mlp_destroy(m):
+    return _check(load().gbr_mlp_destroy(m), "gbr_mlp_destroy")
+
+
+def gbr_mlp_set_params(m, w, b):
+    import numpy as np
+    w = np.ascontiguousarray(w, np.float32)
+    b = np.ascontiguousarray(b, np.float32)
+    assert w.size == MLP_NW and b.size == MLP_NB
+    return _check(load().gbr_mlp_set_params(m, w.ctypes.data, b.ctypes.data), "gbr_mlp_set_params")
+
+
+def gbr_mlp_get_params(m):
+    import numpy as np
+    w = np.empty(MLP_NW, np.float32)
+    b = np.empty(MLP_NB, np.float32)
+    _check(load().gbr_mlp_get_params(m, w.ctypes.data, b.ctypes.data), "gbr_mlp_get_params")
+    return w, b
+
+
+def gbr_mlp_features(ctx, Q, feat, chi=None, stream=None):
+    return _check(load().gbr_mlp_features(ctx, _addr(Q), _addr(feat), _addr(chi), _stream(stream)),
+                  "gbr_mlp_features")
+
+
+def gbr_mlp_forward(m, feat, n, logits, stream=None):
+    return _check(load().gbr_mlp_forward(m, _addr(feat), n, _addr(logits), _stream(stream)),
+                  "gbr_mlp_forward")
+
+
+def gbr_mlp_grad(m, feat, labels, idx, batch, grad, stream=None):
+    return _check(load().gbr_mlp_grad(m, _addr(feat), _addr(labels), _addr(idx), batch,
+                                      _addr(grad), _stream(stream)), "gbr_mlp_grad")
+
+
+def gbr_mlp_train_step(m, feat, labels, idx, batch, lr, loss=None, stream=None):
+    return _check(load().gbr_mlp_train_step(m, _addr(feat), _addr(labels), _addr(idx), batch, lr,
+                                            _addr(loss), _stream(stream)), "gbr_mlp_train_step")
+
+
+def gbr_set_mlp_detector(ctx, m, margin, stream=None):
+    return _check(load().gbr_set_mlp_detector(ctx, m, margin, _stream(stream)),
+                  "gbr_set_mlp_detector")
+
+
+def gbr_mlp_stats(ctx, reset=False):
+    ev, fb = C.c_uint(), C.c_uint()
+    _check(load().gbr_mlp_stats(ctx, C.byref(ev), C.byref(fb), 1 if reset else 0), "gbr_mlp_stats")
+    return ev.value, fb.value

@@ -197,3 +197,30 @@ def batch_spec(nprob=512, seed=0, nmin=64, nmax=768):
     fams = rng.integers(0, 3, nprob)
     names = ("vortex", "riemann", "shear")
     return [(names[f], int(s), 10000 + k) for k, (f, s) in enumerate(zip(fams, sides))]
+
+
+def mlp_init_params(seed, nf=28, nh=32):
+    """Initial parameters of the learned detector (28 -> 32 -> 32 -> 1):
+    He-uniform weights in the order W1 [32][28], W2 [32][32], w3 [32], all
+    float32, and zero biases [65]; drawn from numpy.random.default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    w = np.concatenate([rng.uniform(-1, 1, nh * nf) * np.sqrt(6.0 / nf),
+                        rng.uniform(-1, 1, nh * nh) * np.sqrt(6.0 / nh),
+                        rng.uniform(-1, 1, nh) * np.sqrt(6.0 / nh)]).astype(np.float32)
+    return w, np.zeros(nh + nh + 1, np.float32)
+
+
+def balanced_batches(labels, batch, nbatches, seed):
+    """Index arrays for balanced minibatches: half of each batch drawn from the
+    cells labelled 1 and half from the cells labelled 0 (with replacement),
+    from numpy.random.default_rng(seed); returns int32 [nbatches][batch]."""
+    rng = np.random.default_rng(seed)
+    pos = np.flatnonzero(labels)
+    neg = np.flatnonzero(labels == 0)
+    out = np.empty((nbatches, batch), np.int32)
+    h = batch // 2
+    for k in range(nbatches):
+        a = pos[rng.integers(0, len(pos), h)] if len(pos) else neg[rng.integers(0, len(neg), h)]
+        b = neg[rng.integers(0, len(neg), batch - h)] if len(neg) else pos[rng.integers(0, len(pos), batch - h)]
+        out[k] = rng.permutation(np.concatenate([a, b]))
+    return out

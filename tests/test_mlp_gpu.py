@@ -1,0 +1,187 @@
+"""Learned detector on the GPU vs its CPU oracle (through the C ABI).
+
+* features bit-exact (fixed float32 operation order, IEEE reciprocal, bf16
+  round-to-nearest-even on both sides) and plain labels bit-exact;
+* logits within 1e-3 (1 + |z|) (FP32 matrix-core accumulation vs FP64 on the
+  same bf16 operands; a bf16 tie of h1 may round differently);
+* gradient of the mean BCE within 2e-2 per parameter block, norm-wise (bf16
+  rounding points of dh2, dh1 as matrix-unit operands);
+* one Adam step matches the oracle's Adam on the GPU gradient;
+* the fused detector in the stage kernels: with every cell falling back
+  (margin = inf) the interface flags are the 6-cell buffer of the plain
+  per-cell labels, bit for bit, and the residual matches the oracle run with
+  those flags; with margin 0 the flags follow the network, and the residual
+  matches the oracle run with the GPU's flags.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.mlp as M
+from paper_2305_00762_amd import gbr
+from paper_2305_00762_amd import problems as PB
+from gpu_util import ocfg, report, require_gpu, res_err
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_features(P):
+    torch = require_gpu()
+    ctx = gbr.gbr_init(P.nx, P.ny, P.gamma, P.mu, P.Pr)
+    gbr.gbr_set_geometry(ctx, *P.geometry())
+    Q = torch.from_numpy(P.Q).cuda()
+    n = P.nx * P.ny
+    feat = torch.empty((n, 32), dtype=torch.int16, device="cuda")
+    chi = torch.empty(n, dtype=torch.uint8, device="cuda")
+    gbr.gbr_mlp_features(ctx, Q, feat, chi)
+    torch.cuda.synchronize()
+    gbr.gbr_destroy(ctx)
+    return feat.cpu().numpy().view(np.uint16), chi.cpu().numpy()
+
+
+@pytest.mark.parametrize("fam", ["riemann", "shear", "vortex"])
+def test_features_and_labels_bit_exact(fam):
+    P = PB.make(fam, 70, seed=4, ny=50) if fam != "vortex" else PB.vortex(48)
+    f, chi = gpu_features(P)
+    fo = M.features(P.Q, P.bc_x, P.bc_y, P.gamma)
+    chio, _, _ = O.cell_flags(ocfg(P), P.Q)
+    report(f"features {fam}", mismatch=int((f != fo).sum()), chi_mismatch=int((chi != chio.ravel()).sum()))
+    assert (f == fo).all()
+    assert (chi == chio.ravel()).all()
+
+
+def make_net(seed):
+    torch = require_gpu()
+    w, b = PB.mlp_init_params(seed)
+    b = b + np.float32(0.05) * np.random.default_rng(seed).standard_normal(65).astype(np.float32)
+    m = gbr.gbr_mlp_create()
+    gbr.gbr_mlp_set_params(m, w, b)
+    return m, w, b
+
+
+def test_forward_matches_oracle():
+    torch = require_gpu()
+    P = PB.riemann(60, seed=2, ny=50)
+    f, _ = gpu_features(P)
+    m, w, b = make_net(1)
+    n = f.shape[0]
+    tf = torch.from_numpy(f.view(np.int16)).cuda()
+    z = torch.empty(n, dtype=torch.float32, device="cuda")
+    gbr.gbr_mlp_forward(m, tf, n, z)
+    torch.cuda.synchronize()
+    zg = z.cpu().numpy().astype(np.float64)
+    zo = M.forward(f, M.bf16_round(w), b)
+    err = np.abs(zg - zo) / (1 + np.abs(zo))
+    report("mlp forward", max_err=err.max(), median=np.median(err))
+    assert err.max() <= 1e-3 and np.median(err) <= 1e-5
+    gbr.gbr_mlp_destroy(m)
+
+
+@pytest.mark.parametrize("batch", [1000, 4096])
+def test_gradient_matches_oracle(batch):
+    torch = require_gpu()
+    P = PB.riemann(96, seed=3)
+    f, chi = gpu_features(P)
+    m, w, b = make_net(2)
+    idx = PB.balanced_batches(chi, batch, 1, seed=9)[0]
+    tf = torch.from_numpy(f.view(np.int16)).cuda()
+    tl = torch.from_numpy(chi).cuda()
+    ti = torch.from_numpy(idx).cuda()
+    g = torch.empty(2018, dtype=torch.float32, device="cuda")
+    gbr.gbr_mlp_grad(m, tf, tl, ti, batch, g)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    loss, dw, db = M.loss_and_grad(f[idx], chi[idx], w, b, round_ops=True)
+    blocks = {"W1": (0, 896), "W2": (896, 1920), "w3": (1920, 1952)}
+    for name, (a, e) in blocks.items():
+        rel = np.linalg.norm(g[a:e] - dw[a:e]) / np.linalg.norm(dw[a:e])
+        report(f"grad {name} B={batch}", rel=rel)
+        assert rel <= 2e-2, (name, rel)
+    relb = np.linalg.norm(g[1952:2017] - db) / np.linalg.norm(db)
+    assert relb <= 2e-2
+    assert abs(g[2017] / batch - loss) <= 1e-4 * abs(loss)
+    gbr.gbr_mlp_destroy(m)
+
+
+def test_adam_step_and_training_reduces_loss():
+    torch = require_gpu()
+    P = PB.riemann(128, seed=5)
+    f, chi = gpu_features(P)
+    m, w, b = make_net(3)
+    batches = PB.balanced_batches(chi, 2048, 300, seed=11)
+    tf = torch.from_numpy(f.view(np.int16)).cuda()
+    tl = torch.from_numpy(chi).cuda()
+    ti = torch.from_numpy(batches).cuda()
+    g = torch.empty(2018, dtype=torch.float32, device="cuda")
+    gbr.gbr_mlp_grad(m, tf, tl, ti[0], 2048, g)
+    torch.cuda.synchronize()
+    gh = g.cpu().numpy().astype(np.float64)[:2017]
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    gbr.gbr_mlp_train_step(m, tf, tl, ti[0], 2048, 1e-3, loss)
+    w1, b1 = gbr.gbr_mlp_get_params(m)
+    p0 = np.concatenate([w, b]).astype(np.float64)
+    pe, _, _ = M.adam(p0, gh, np.zeros(2017), np.zeros(2017), 1, 1e-3)
+    assert np.allclose(np.concatenate([w1, b1]), pe, rtol=1e-6, atol=1e-7)
+    first = float(loss.cpu()[0]) / 2048
+    for k in range(1, 300):
+        gbr.gbr_mlp_train_step(m, tf, tl, ti[k], 2048, 3e-3, loss)
+    torch.cuda.synchronize()
+    last = float(loss.cpu()[0]) / 2048
+    report("training", first_loss=first, last_loss=last)
+    assert last < 0.5 * first
+    gbr.gbr_mlp_destroy(m)
+
+
+def fused(P, m, margin, precision):
+    from paper_2305_00762_amd.solver import Solver
+    torch = require_gpu()
+    S = Solver(P, export_flags=True, precision=precision)
+    gbr.gbr_set_mlp_detector(S.ctx, m, margin)
+    gbr.gbr_set_scheme(S.ctx, gbr.GBR_RECON_PRIM, gbr.GBR_MP_FLAGGED, precision, gbr.GBR_DET_MLP)
+    R = S.residual()
+    torch.cuda.synchronize()
+    sx, sy = S.flags()
+    ev, fb = gbr.gbr_mlp_stats(S.ctx, reset=True)
+    out = R.cpu().numpy()
+    S.close()
+    return out, sx, sy, ev, fb
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("tiling", [0, 1])
+def test_fused_detector_all_fallback(precision, tiling):
+    m, w, b = make_net(4)
+    for P in (PB.riemann(90, seed=6, ny=70), PB.shear(64, seed=1, ny=48)):
+        from paper_2305_00762_amd.solver import Solver
+        R, sx, sy, ev, fb = fused(P, m, 1e30, precision)
+        chi, _, _ = O.cell_flags(ocfg(P), P.Q)
+        ex, ey = O.sigma_from_cells(chi, P.bc_x, P.bc_y)
+        assert ev > 0 and fb == ev
+        assert (sx == ex).all() and (sy == ey).all()
+        Ro = O.residual_sigma(ocfg(P), P.Q, ex, ey)
+        tol = 1e-12 if precision == 0 else 1e-6
+        assert (res_err(R, Ro, P) <= tol).all()
+    gbr.gbr_mlp_destroy(m)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fused_detector_network_decides(precision):
+    m, w, b = make_net(5)
+    P = PB.riemann(90, seed=7, ny=70)
+    R, sx, sy, ev, fb = fused(P, m, 0.0, precision)
+    assert fb == 0
+    # the oracle network on the oracle features decides the same cells
+    # wherever its logit is clear of zero
+    f = M.features(P.Q, P.bc_x, P.bc_y)
+    zo = M.forward(f, M.bf16_round(w), b).reshape(P.ny, P.nx)
+    chi_o = (zo > 0).astype(np.uint8)
+    ex, ey = O.sigma_from_cells(chi_o, P.bc_x, P.bc_y)
+    clear = np.abs(zo) > 1e-2
+    report("fused margin0", flag_mismatch=int((sx != ex).sum() + (sy != ey).sum()),
+           unclear_cells=int((~clear).sum()))
+    if clear.all():
+        assert (sx == ex).all() and (sy == ey).all()
+    Ro = O.residual_sigma(ocfg(P), P.Q, sx, sy)
+    tol = 1e-12 if precision == 0 else 1e-6
+    assert (res_err(R, Ro, P) <= tol).all()
+    gbr.gbr_mlp_destroy(m)
