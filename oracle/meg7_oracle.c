@@ -44,6 +44,12 @@
  *          means; mu constant.
  *   R-BC   Ghost cells (6 layers): periodic wrap or zeroth-order copy
  *          (transmissive).
+ *   R-POS  A reconstructed interface state with non-positive density or
+ *          pressure (or a non-finite one) -- which characteristic MP limiting
+ *          does not exclude where discontinuities interact -- is replaced by
+ *          the first-order state: U_L = U_j, U_R = U_{j+1}, F_L = F(U_j),
+ *          F_R = F(U_{j+1}).  The paper prescribes no positivity treatment
+ *          for these cases.
  *   R-MPG  In eq. (eqn:mp-procedure) the hat on Phi_{j-1} and the mixed
  *          i/j subscripts are typesetting slips: plain Phi_{j-1}, index j.
  *          The MP xi (=7) and the detector xi (=1e-3) are different
@@ -421,6 +427,12 @@ static void line_flux(const orc_line *L, const orc_cfg *c, double Fout[4], int *
     } else {
         conv_flux(WL, gamma, FL);   /* F(Q_L) */
         conv_flux(WR, gamma, FR);   /* F(Q_R) */
+    }
+    /* reading R-POS: first-order states where the reconstruction is unphysical */
+    if (!(WL[0] > 0.0 && WL[3] > 0.0 && WR[0] > 0.0 && WR[3] > 0.0)) {
+        for (int m = 0; m < 4; ++m) { WL[m] = L->W[m][4]; WR[m] = L->W[m][5]; }
+        conv_flux(WL, gamma, FL);
+        conv_flux(WR, gamma, FR);
     }
     double Fc[4];
     orc_hllc(WL, WR, FL, FR, gamma, Fc);

@@ -237,6 +237,16 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
             constexpr float w = 1.0f / 1680.0f;
             dF[m] = w * (212.0f * (h[3] - h[5]) - 38.0f * (h[2] - h[6]) + (h[0] - h[8]));
           }
+          if (!(WL[0] > 0.f && WL[3] > 0.f && WR[0] > 0.f && WR[3] > 0.f)) {
+            // unphysical reconstruction: first-order states, central flux
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+              WL[m] = (float)U[rot[m] * RS + r];
+              WR[m] = (float)U[rot[m] * RS + r + SN];
+              dW[m] = sDU[m * NL * WU + bidx(line, pos + 3, WU)];
+              dF[m] = 0.f;
+            }
+          }
           float diss[4];
           hllc_diss_f32(WL, WR, dW, gammaf, g1invf, diss);
 #pragma unroll
@@ -308,6 +318,10 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
         [&](int q, int f) { return U[rot[f] * RS + r + (q - 2) * SN]; },
         [&](int q, int f) { return (double)sD[f * NL * WD + bidx(line, pos + q + 1, WD)]; },
         P.gamma, WL, WR);
+    if (!(WL[0] > 0.0 && WL[3] > 0.0 && WR[0] > 0.0 && WR[3] > 0.0)) {
+      wrot(r, WL);
+      wrot(r + SN, WR);
+    }
     double FL[4], FR[4], Fm[4], F[4], W0[4], W1[4], f0[4], f1[4];
     conv_flux(WL, P.g1inv, FL);
     conv_flux(WR, P.g1inv, FR);

@@ -297,6 +297,19 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
             Fm[m] = (1052.0 * s) * (f[4] + f[5]) - (250.0 * s) * (f[3] + f[6]) +
                     (38.0 * s) * (f[2] + f[7]) + s * (f[1] + f[8]) - s * (f[0] + f[9]);
           }
+          if (!(WL[0] > 0.0 && WL[3] > 0.0 && WR[0] > 0.0 && WR[3] > 0.0)) {
+            // unphysical reconstruction: first-order states and fluxes
+            double f0[4], f1[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+              WL[m] = L.U[rot[m] * RS + r];
+              WR[m] = L.U[rot[m] * RS + r + SN];
+            }
+            conv_flux(WL, P.g1inv, f0);
+            conv_flux(WR, P.g1inv, f1);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) Fm[m] = 0.5 * (f0[m] + f1[m]);
+          }
           hllc(WL, WR, Fm, P.gamma, P.g1inv, fsm[k]);
           if (C::VISC) {
             const double* U = L.U;
@@ -353,6 +366,13 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
         [&](int q, int f) { return U[rot[f] * RS + r + (q - 2) * SN]; },
         [&](int q, int f) { return sD[f * NL * WD + bidx(line, pos + q + 1, WD)]; },
         P.gamma, WL, WR);
+    if (!(WL[0] > 0.0 && WL[3] > 0.0 && WR[0] > 0.0 && WR[3] > 0.0)) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        WL[m] = U[rot[m] * RS + r];
+        WR[m] = U[rot[m] * RS + r + SN];
+      }
+    }
     double FL[4], FR[4], Fm[4], F[4];
     conv_flux(WL, P.g1inv, FL);
     conv_flux(WR, P.g1inv, FR);

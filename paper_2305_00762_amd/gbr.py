@@ -70,9 +70,18 @@ class GbrError(RuntimeError):
 
 
 def load(path=LIB_PATH):
-    """Load libgbr.so; raises if it is not built."""
+    """Load libgbr.so; raises if it is not built.
+
+    torch is imported first: torch ships its own HIP runtime under the same
+    soname (libamdhip64.so.7) as the system one libgbr.so is linked against,
+    and the first one loaded serves the whole process.  Loading torch's first
+    keeps one runtime, the one that owns torch's device memory and streams."""
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(path):
             raise RuntimeError(f"{path} is not built: run __graft_entry__.build() "
                                "(the HIP library is required; there is no CPU fallback)")

@@ -261,3 +261,24 @@ def test_autotune_picks_a_variant():
     Ro = O.residual(ocfg(P), P.Q)
     assert (res_err(R.cpu().numpy(), Ro, P) <= TOL).all()
     S.close()
+
+
+def test_positivity_fallback_trajectory():
+    """Seeded Riemann problem whose interacting discontinuities make the
+    characteristic MP states unphysical at step 21: the first-order fallback
+    (both sides) keeps it running, and GPU and oracle agree through it."""
+    from paper_2305_00762_amd.solver import Solver
+    require_gpu()
+    P = PB.riemann(128, seed=1008)
+    cfg = ocfg(P)
+    S = Solver(P)
+    Q = P.Q.copy()
+    for _ in range(25):
+        O.step(cfg, Q, P.cfl)
+        S.step()
+    G = S.state()
+    assert np.isfinite(Q).all() and S.check() == 0
+    e = relerr(G, Q)
+    report("riemann128 seed1008 25 steps", relerr=e.max())
+    assert (e <= TOL).all(), e
+    S.close()
