@@ -173,10 +173,14 @@ int gbr_mlp_train_step(gbr_mlp *m, const uint16_t *feat, const uint8_t *labels, 
 
 /* Use the network's current weights as the detector of `ctx` (copied), with
  * plain-detector fallback where |logit| < margin; select it with
- * gbr_set_scheme(..., GBR_DET_MLP).  gbr_mlp_stats reports the cells the
- * stage kernels evaluated and how many fell back (and optionally resets). */
+ * gbr_set_scheme(..., GBR_DET_MLP).  With it selected, every residual or
+ * stage call first evaluates the network once per cell of the grid into a
+ * per-cell flag map owned by the context (nx*ny bytes, allocated here), which
+ * the stage kernel's sigma buffers read.  gbr_mlp_stats reports the cells
+ * evaluated since the last reset and how many of them fell back to the plain
+ * detector (synchronises the device; optionally resets both counts). */
 int gbr_set_mlp_detector(gbr_ctx *ctx, const gbr_mlp *m, float margin, void *stream);
-int gbr_mlp_stats(gbr_ctx *ctx, unsigned *evaluated, unsigned *fallbacks, int reset);
+int gbr_mlp_stats(gbr_ctx *ctx, uint64_t *evaluated, uint64_t *fallbacks, int reset);
 
 /* Synchronise `stream`, return GBR_ESTATE if any kernel since the last check
  * saw a non-finite value or rho <= 0 or p <= 0 in an interior cell, and

@@ -55,13 +55,21 @@ const TileVariant kVariants[] = {
      "15x15"},
     // 64 x-interfaces per row, 8 y-interfaces per column (Euler, plain detector)
     {63, 7,
-     {{{launch_cfg<TileCfg<63, 7, 7, 32, 256, false>>, nullptr}, {nullptr, nullptr}},
-      {{launch_cfg_f32<TileCfg<63, 7, 7, 32, 256, false>>, nullptr}, {nullptr, nullptr}}},
+     {{{launch_cfg<TileCfg<63, 7, 7, 32, 256, false>>,
+        launch_cfg<TileCfg<63, 7, 7, 32, 256, false>, true>},
+       {nullptr, nullptr}},
+      {{launch_cfg_f32<TileCfg<63, 7, 7, 32, 256, false>>,
+        launch_cfg_f32<TileCfg<63, 7, 7, 32, 256, false>, true>},
+       {nullptr, nullptr}}},
      "63x7"},
     // 31x8 / 15x16 interface blocks sized for 3 workgroups per CU in FP32 bulk
     {30, 15,
-     {{{launch_cfg<TileCfg<30, 15, 15, 15, 256, false>>, nullptr}, {nullptr, nullptr}},
-      {{launch_cfg_f32<TileCfg<30, 15, 8, 15, 256, false, 3>>, nullptr}, {nullptr, nullptr}}},
+     {{{launch_cfg<TileCfg<30, 15, 15, 15, 256, false>>,
+        launch_cfg<TileCfg<30, 15, 15, 15, 256, false>, true>},
+       {nullptr, nullptr}},
+      {{launch_cfg_f32<TileCfg<30, 15, 8, 15, 256, false, 3>>,
+        launch_cfg_f32<TileCfg<30, 15, 8, 15, 256, false, 3>, true>},
+       {nullptr, nullptr}}},
      "30x15"},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
@@ -86,7 +94,9 @@ struct gbr_ctx {
   float* d_mlp_f;             // [32 + 65]
   float mlp_margin;
   int mlp_ready;
-  unsigned* d_mlp_count;      // [2]
+  uint8_t* d_chimap;          // [ny][nx] learned-detector flag per cell
+  unsigned long long* d_mlp_fb;   // plain fallbacks of the learned detector
+  unsigned long long mlp_evaluated;
 };
 
 struct gbr_mlp {
@@ -153,7 +163,8 @@ int gbr_destroy(gbr_ctx* c) {
   if (c->d_sigy) (void)hipFree(c->d_sigy);
   if (c->d_mlp_w) (void)hipFree(c->d_mlp_w);
   if (c->d_mlp_f) (void)hipFree(c->d_mlp_f);
-  if (c->d_mlp_count) (void)hipFree(c->d_mlp_count);
+  if (c->d_chimap) (void)hipFree(c->d_chimap);
+  if (c->d_mlp_fb) (void)hipFree(c->d_mlp_fb);
   delete c;
   return GBR_OK;
 }
@@ -231,12 +242,20 @@ static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn
   const int prec = c->precision == GBR_PREC_FP32_BULK ? 1 : 0;
   const int det = c->detector == GBR_DET_MLP ? 1 : 0;
   if (det) {
-    P.mlp.W1 = c->d_mlp_w;
-    P.mlp.W2 = c->d_mlp_w + kMlpH * kMlpIn;
-    P.mlp.w3 = c->d_mlp_f;
-    P.mlp.b = c->d_mlp_f + kMlpH;
-    P.mlp_margin = c->mlp_margin;
-    P.mlp_count = c->d_mlp_count;
+    MlpChiParams M{};
+    M.Q = Qk; M.chi = c->d_chimap; M.nfb = c->d_mlp_fb;
+    M.M.W1 = c->d_mlp_w;
+    M.M.W2 = c->d_mlp_w + kMlpH * kMlpIn;
+    M.M.w3 = c->d_mlp_f;
+    M.M.b = c->d_mlp_f + kMlpH;
+    M.margin = c->mlp_margin;
+    M.nx = c->nx; M.ny = c->ny; M.bcx = c->bcx; M.bcy = c->bcy;
+    M.tiles_x = (c->nx + kChiTX - 1) / kChiTX;
+    M.gamma = c->gamma;
+    const int nblk = M.tiles_x * ((c->ny + kChiTY - 1) / kChiTY);
+    hipLaunchKernelGGL(mlp_chi_kernel, dim3(nblk), dim3(256), 0, s, M);
+    c->mlp_evaluated += (unsigned long long)c->nx * c->ny;
+    P.chimap = c->d_chimap;
   }
   const TileVariant* v = &kVariants[c->tiling];
   if (!v->fn[prec][visc][det]) v = &kVariants[0];
@@ -461,9 +480,11 @@ int gbr_set_mlp_detector(gbr_ctx* c, const gbr_mlp* m, float margin, void* strea
   if (!c->d_mlp_w) {
     if (hipMalloc(&c->d_mlp_w, 2 * kMlpH * kMlpIn * sizeof(unsigned short)) != hipSuccess ||
         hipMalloc(&c->d_mlp_f, (kMlpH + kMlpNB) * sizeof(float)) != hipSuccess ||
-        hipMalloc(&c->d_mlp_count, 2 * sizeof(unsigned)) != hipSuccess)
+        hipMalloc(&c->d_chimap, (size_t)c->nx * c->ny) != hipSuccess ||
+        hipMalloc(&c->d_mlp_fb, sizeof(unsigned long long)) != hipSuccess)
       return GBR_ENOMEM;
-    if (hipMemset(c->d_mlp_count, 0, 2 * sizeof(unsigned)) != hipSuccess) return GBR_EDEVICE;
+    if (hipMemset(c->d_mlp_fb, 0, sizeof(unsigned long long)) != hipSuccess) return GBR_EDEVICE;
+    c->mlp_evaluated = 0;
   }
   hipStream_t s = (hipStream_t)stream;
   if (hipMemcpyAsync(c->d_mlp_w, m->d_w, 2 * kMlpH * kMlpIn * sizeof(unsigned short),
@@ -477,16 +498,19 @@ int gbr_set_mlp_detector(gbr_ctx* c, const gbr_mlp* m, float margin, void* strea
   return GBR_OK;
 }
 
-int gbr_mlp_stats(gbr_ctx* c, unsigned* evaluated, unsigned* fallbacks, int reset) {
-  if (!c || !c->d_mlp_count) return GBR_EINVAL;
-  unsigned h[2];
+int gbr_mlp_stats(gbr_ctx* c, uint64_t* evaluated, uint64_t* fallbacks, int reset) {
+  if (!c || !c->d_mlp_fb) return GBR_EINVAL;
+  unsigned long long h = 0;
   if (hipDeviceSynchronize() != hipSuccess ||
-      hipMemcpy(h, c->d_mlp_count, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+      hipMemcpy(&h, c->d_mlp_fb, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
     return GBR_EDEVICE;
-  if (evaluated) *evaluated = h[0];
-  if (fallbacks) *fallbacks = h[1];
-  if (reset && (hipMemset(c->d_mlp_count, 0, sizeof(h)) != hipSuccess || hipDeviceSynchronize() != hipSuccess))
-    return GBR_EDEVICE;
+  if (evaluated) *evaluated = c->mlp_evaluated;
+  if (fallbacks) *fallbacks = h;
+  if (reset) {
+    c->mlp_evaluated = 0;
+    if (hipMemset(c->d_mlp_fb, 0, sizeof(h)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+      return GBR_EDEVICE;
+  }
   return GBR_OK;
 }
 

@@ -168,6 +168,16 @@ __device__ __forceinline__ int wrap_bc(int k, int n, int bc) {
   return k < 0 ? 0 : (k >= n ? n - 1 : k);
 }
 
+// Pressure of a cell as the features define it: u = (rho u)/rho and v by
+// IEEE division, p = (gamma-1) (E - rho (u u + v v) / 2), every product and
+// sum rounded on its own.
+__device__ __forceinline__ double mlp_cell_pressure(double r, double mx, double my, double E,
+                                                    double gamma) {
+#pragma clang fp contract(off)
+  const double u = mx / r, v = my / r;
+  return (gamma - 1.0) * (E - r * (u * u + v * v) / 2.0);
+}
+
 __global__ __launch_bounds__(256) void mlp_features_kernel(MlpFeatParams P) {
   const size_t n = (size_t)P.nx * P.ny;
   const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -177,8 +187,7 @@ __global__ __launch_bounds__(256) void mlp_features_kernel(MlpFeatParams P) {
     const size_t s = (size_t)wrap_bc(ii, P.ny, P.bcy) * P.nx + wrap_bc(jj, P.nx, P.bcx);
     const double r = P.Q[s];
     if (!want_p) return r;
-    const double u = P.Q[n + s] / r, v = P.Q[2 * n + s] / r;
-    return (P.gamma - 1.0) * (P.Q[3 * n + s] - r * (u * u + v * v) / 2.0);
+    return mlp_cell_pressure(r, P.Q[n + s], P.Q[2 * n + s], P.Q[3 * n + s], P.gamma);
   };
   unsigned short f[kMlpIn];
   mlp_cell_features(
@@ -202,6 +211,114 @@ __global__ __launch_bounds__(256) void mlp_features_kernel(MlpFeatParams P) {
     const double py = detector_psi(cell(i - 2, j, 0), cell(i - 1, j, 0), cell(i, j, 0),
                                    cell(i + 1, j, 0), cell(i + 2, j, 0));
     P.chi[c] = (px < kPsiC || py < kPsiC) ? 1 : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-cell flag map of the learned detector, chi[c] for every grid cell: the
+// logit's sign where |logit| >= margin, else the plain label
+// [psi_x < psi_c or psi_y < psi_c].  One workgroup per 64 x 16 block of
+// cells: the block plus a 3-cell halo of rho (FP64 and float32) and p
+// (float32) is staged in LDS once (ghost cells by wrap or clamp), then four
+// rounds of 256 cells each compute their features (one cell per thread),
+// stage them as bf16 rows and run the network on the matrix cores; a wave
+// evaluates exactly its own 64 cells, so the logit of lane l's cell lands in
+// lane l and the byte store is coalesced.
+struct MlpChiParams {
+  const double* Q;
+  uint8_t* chi;                 // [ny][nx]
+  unsigned long long* nfb;      // plain fallbacks (summed)
+  MlpImage M;
+  float margin;
+  int nx, ny, bcx, bcy, tiles_x;
+  double gamma;
+};
+constexpr int kChiTX = 64, kChiTY = 16;
+constexpr int kChiRX = kChiTX + 6, kChiRY = kChiTY + 6, kChiRS = kChiRX * kChiRY;
+constexpr int kChiRow = kMlpIn + 4;   // bf16 row stride in LDS (72 B: conflict-free b64 reads)
+
+__global__ __launch_bounds__(256) void mlp_chi_kernel(MlpChiParams P) {
+  __shared__ double sR[kChiRS];
+  __shared__ float sF[2][kChiRS];
+  __shared__ unsigned short sX[256 * kChiRow];
+  __shared__ unsigned sFb[4];
+  const int tid = threadIdx.x, l = __lane_id(), g = l >> 4, w = tid >> 6;
+  const int tx0 = (blockIdx.x % P.tiles_x) * kChiTX, ty0 = (blockIdx.x / P.tiles_x) * kChiTY;
+  const size_t n = (size_t)P.nx * P.ny;
+  constexpr int LR = (kChiRS + 255) / 256;
+  double q[LR][4];
+#pragma unroll
+  for (int k = 0; k < LR; ++k) {
+    const int c = tid + 256 * k;
+    if (c < kChiRS) {
+      const size_t s = (size_t)wrap_bc(ty0 + c / kChiRX - 3, P.ny, P.bcy) * P.nx +
+                       wrap_bc(tx0 + c % kChiRX - 3, P.nx, P.bcx);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) q[k][m] = P.Q[m * n + s];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < LR; ++k) {
+    const int c = tid + 256 * k;
+    if (c < kChiRS) {
+      sR[c] = q[k][0];
+      sF[0][c] = (float)q[k][0];
+      sF[1][c] = (float)mlp_cell_pressure(q[k][0], q[k][1], q[k][2], q[k][3], P.gamma);
+    }
+  }
+  MlpFrags F;
+  mlp_load_frags(P.M, F);
+  __syncthreads();
+  unsigned nfb = 0;
+  for (int rnd = 0; rnd < kChiTY / 4; ++rnd) {
+    const int lx = tid & 63, ly = 4 * rnd + w;
+    const int rc = (ly + 3) * kChiRX + lx + 3;
+    {
+      unsigned short f[kMlpIn];
+      mlp_cell_features(
+          [&](int s, int o) { return (double)sF[s & 1][rc + o * ((s < 2) ? 1 : kChiRX)]; }, f);
+      uint2* dst = reinterpret_cast<uint2*>(sX + tid * kChiRow);
+#pragma unroll
+      for (int q2 = 0; q2 < 8; ++q2)
+        dst[q2] = make_uint2(f[4 * q2] | ((unsigned)f[4 * q2 + 1] << 16),
+                             f[4 * q2 + 2] | ((unsigned)f[4 * q2 + 3] << 16));
+    }
+    __syncthreads();
+    float zl = 0.f;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const int row = w * 64 + cb * 16 + (l & 15);
+      const v4s x0 = *reinterpret_cast<const v4s*>(sX + row * kChiRow + 4 * g);
+      const v4s x1 = *reinterpret_cast<const v4s*>(sX + row * kChiRow + 16 + 4 * g);
+      const float z = mlp_forward16(F, x0, x1, nullptr);
+      if (cb == g) zl = z;
+    }
+    const int gj = tx0 + lx, gi = ty0 + ly;
+    if (gj < P.nx && gi < P.ny) {
+      unsigned char chi;
+      if (fabsf(zl) >= P.margin) {
+        chi = zl > 0.f ? 1 : 0;
+      } else {
+        const double* rho = sR + rc;
+        const double px = detector_psi(rho[-2], rho[-1], rho[0], rho[1], rho[2]);
+        const double py =
+            detector_psi(rho[-2 * kChiRX], rho[-kChiRX], rho[0], rho[kChiRX], rho[2 * kChiRX]);
+        chi = (px < kPsiC || py < kPsiC) ? 1 : 0;
+        ++nfb;
+      }
+      P.chi[(size_t)gi * P.nx + gj] = chi;
+    }
+    __syncthreads();
+  }
+  if (P.nfb) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) nfb += __shfl_xor(nfb, o);
+    if (l == 0) sFb[w] = nfb;
+    __syncthreads();
+    if (tid == 0) {
+      const unsigned t = (sFb[0] + sFb[1]) + (sFb[2] + sFb[3]);
+      if (t) atomicAdd(P.nfb, (unsigned long long)t);
+    }
   }
 }
 

@@ -379,9 +379,8 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
 template <class C, bool DETMLP>
 __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel_f32(StageParams P) {
   using F = F32Cfg<C>;
-  constexpr int PHS = F::PH > C::NT * kMlpIn / 2 ? F::PH : C::NT * kMlpIn / 2;
   __shared__ double sU[C::NF * C::RS];
-  __shared__ float sPh[DETMLP ? PHS : F::PH];
+  __shared__ float sPh[F::PH];
   __shared__ unsigned char sChi[C::CHI];
   __shared__ unsigned short sQueue[C::QMAX];
   __shared__ unsigned char sChiF[DETMLP ? (C::TX + 6) * (C::TY + 6) : 1];
@@ -389,8 +388,8 @@ __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel_f32(StagePar
   int tx0, ty0;
   if (!tile_origin(P, C::TX, C::TY, tx0, ty0)) return;
   stage_load<C>(P, sU, tx0, ty0);
+  if (DETMLP) load_chimap<C>(P, sChiF, tx0, ty0);
   __syncthreads();
-  if (DETMLP) mlp_tile_flags<C>(P, sU, reinterpret_cast<unsigned short*>(sPh), sChiF);
   const LdsF32 L{sU, sPh, sChi, sQueue, &sQCount, sChiF};
   double res[C::CPT][4];
 #pragma unroll

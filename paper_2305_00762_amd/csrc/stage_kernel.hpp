@@ -17,7 +17,6 @@
 // residual store) follows in registers with one coalesced FP64 store.
 #pragma once
 #include "meg7_device.hpp"
-#include "mlp_kernels.hpp"
 
 namespace gbr {
 
@@ -37,9 +36,7 @@ struct StageParams {
   double inv_dx, inv_dy;
   double gamma, g1inv, mu, kq;    // kq = mu / (Pr (gamma-1))
   int mode;
-  MlpImage mlp;                   // learned detector (detector = MLP)
-  float mlp_margin;               // |logit| below this: plain detector decides
-  unsigned* mlp_count;            // [2]: cells evaluated, plain fallbacks (optional)
+  const uint8_t* chimap;          // learned-detector flag per cell [ny][nx] (detector = MLP)
 };
 
 // Ghost cells by index: periodic wrap or transmissive clamp.  The offsets
@@ -97,74 +94,17 @@ __device__ __forceinline__ int mlp_chi_index(int lx, int ly) {
   return (ly + 3) * (C::TX + 6) + (lx + 3);
 }
 
-// Learned detector over the tile cells the sigma buffers read, [-3, TX+3) x
-// [-3, TY+3): features from the FP64 tile (rho = field 0, p = field 3), the
-// MLP on the matrix cores in chunks of NT cells staged as bf16 rows in `stg`
-// (NT x 32), and chi = [logit > 0] where |logit| >= margin, else the plain
-// density detector in both directions.  Called by all threads.
+// Learned-detector flags of the tile cells the sigma buffers read,
+// [-3, TX+3) x [-3, TY+3), from the per-cell flag map (ghost cells take the
+// flag of the cell they copy: periodic wrap or transmissive clamp).
 template <class C>
-__device__ __forceinline__ void mlp_tile_flags(const StageParams& P, const double* sU,
-                                               unsigned short* stg, unsigned char* chif) {
+__device__ __forceinline__ void load_chimap(const StageParams& P, unsigned char* chif, int tx0,
+                                            int ty0) {
   constexpr int W6 = C::TX + 6, NC = (C::TX + 6) * (C::TY + 6);
-  constexpr int RS = C::RS, RX = C::RX, H = C::H, NT = C::NT;
-  const int tid = threadIdx.x, l = __lane_id(), r = l & 15, g = l >> 4, w = tid >> 6;
-  MlpFrags F;
-  mlp_load_frags(P.mlp, F);
-  unsigned nfb = 0, nev = 0;
-  for (int base = 0; base < NC; base += NT) {
-    const int c = base + tid;
-    if (c < NC) {
-      const int rr = (c / W6 - 3 + H) * RX + (c % W6 - 3 + H);
-      unsigned short f[kMlpIn];
-      mlp_cell_features(
-          [&](int s, int o) { return sU[((s & 1) ? 3 * RS : 0) + rr + o * ((s < 2) ? 1 : RX)]; }, f);
-      uint4* dst = reinterpret_cast<uint4*>(stg + tid * kMlpIn);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        uint4 v;
-        v.x = f[8 * q + 0] | ((unsigned)f[8 * q + 1] << 16);
-        v.y = f[8 * q + 2] | ((unsigned)f[8 * q + 3] << 16);
-        v.z = f[8 * q + 4] | ((unsigned)f[8 * q + 5] << 16);
-        v.w = f[8 * q + 6] | ((unsigned)f[8 * q + 7] << 16);
-        dst[q] = v;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-      const int row = w * 64 + cb * 16 + r;
-      const v4s x0 = *reinterpret_cast<const v4s*>(stg + row * kMlpIn + 4 * g);
-      const v4s x1 = *reinterpret_cast<const v4s*>(stg + row * kMlpIn + 16 + 4 * g);
-      const float z = mlp_forward16(F, x0, x1, nullptr);
-      const int cc = base + row;
-      if (g == 0 && cc < NC) {
-        unsigned char chi;
-        ++nev;
-        if (fabsf(z) >= P.mlp_margin) {
-          chi = z > 0.f ? 1 : 0;
-        } else {
-          const int rr = (cc / W6 - 3 + H) * RX + (cc % W6 - 3 + H);
-          const double* rho = sU + rr;
-          const double px = detector_psi(rho[-2], rho[-1], rho[0], rho[1], rho[2]);
-          const double py = detector_psi(rho[-2 * RX], rho[-RX], rho[0], rho[RX], rho[2 * RX]);
-          chi = (px < kPsiC || py < kPsiC) ? 1 : 0;
-          ++nfb;
-        }
-        chif[cc] = chi;
-      }
-    }
-    __syncthreads();
-  }
-  if (P.mlp_count) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      nev += __shfl_xor(nev, o);
-      nfb += __shfl_xor(nfb, o);
-    }
-    if (l == 0) {
-      atomicAdd(&P.mlp_count[0], nev);
-      atomicAdd(&P.mlp_count[1], nfb);
-    }
+  for (int c = threadIdx.x; c < NC; c += C::NT) {
+    const int gi = bc_index(ty0 + c / W6 - 3, P.ny, P.bcy);
+    const int gj = bc_index(tx0 + c % W6 - 3, P.nx, P.bcx);
+    chif[c] = P.chimap[(size_t)gi * P.nx + gj];
   }
 }
 
@@ -527,9 +467,8 @@ __device__ __forceinline__ void stage_store(const StageParams& P, const double (
 
 template <class C, bool DETMLP>
 __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel(StageParams P) {
-  constexpr int PHS = C::PH > C::NT * kMlpIn / 4 ? C::PH : C::NT * kMlpIn / 4;
   __shared__ double sU[C::NF * C::RS];
-  __shared__ double sPh[DETMLP ? PHS : C::PH];
+  __shared__ double sPh[C::PH];
   __shared__ unsigned char sChi[C::CHI];
   __shared__ unsigned short sQueue[C::QMAX];
   __shared__ unsigned char sChiF[DETMLP ? (C::TX + 6) * (C::TY + 6) : 1];
@@ -537,8 +476,8 @@ __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel(StageParams 
   int tx0, ty0;
   if (!tile_origin(P, C::TX, C::TY, tx0, ty0)) return;
   stage_load<C>(P, sU, tx0, ty0);
+  if (DETMLP) load_chimap<C>(P, sChiF, tx0, ty0);
   __syncthreads();
-  if (DETMLP) mlp_tile_flags<C>(P, sU, reinterpret_cast<unsigned short*>(sPh), sChiF);
   const Lds L{sU, sPh, sChi, sQueue, &sQCount, sChiF};
   double res[C::CPT][4];
 #pragma unroll

@@ -57,7 +57,7 @@ SIGNATURES = {
     "gbr_mlp_grad": (_i, [_vp, _vp, _vp, _vp, _i, _vp, _vp]),
     "gbr_mlp_train_step": (_i, [_vp, _vp, _vp, _vp, _i, C.c_float, _vp, _vp]),
     "gbr_set_mlp_detector": (_i, [_vp, _vp, C.c_float, _vp]),
-    "gbr_mlp_stats": (_i, [_vp, C.POINTER(C.c_uint), C.POINTER(C.c_uint), _i]),
+    "gbr_mlp_stats": (_i, [_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), _i]),
 }
 
 _lib = None
@@ -257,6 +257,6 @@ def gbr_set_mlp_detector(ctx, m, margin, stream=None):
 
 
 def gbr_mlp_stats(ctx, reset=False):
-    ev, fb = C.c_uint(), C.c_uint()
+    ev, fb = C.c_uint64(), C.c_uint64()
     _check(load().gbr_mlp_stats(ctx, C.byref(ev), C.byref(fb), 1 if reset else 0), "gbr_mlp_stats")
     return ev.value, fb.value
