@@ -1,12 +1,22 @@
 """Throughput of the MEG7 hot path on one MI355X: cell-stage updates/s.
 
-A step is one SSP-RK3 time step of the whole hot path on the workload: the
-device time step (CFL reduction) and three fused residual + stage-update
-launches.  Inputs are resident in HBM before the timed region.  Prints ONE
-JSON line (see the keys below).
+A step is one SSP-RK3 time step of the whole hot path on one grid: the device
+time step (CFL reduction) and three stage calls, each the learned detector's
+per-cell flag map (when selected) and the fused residual + stage-update
+kernel.  Inputs are resident in HBM before the timed region.
+
+The headline path is FP32 bulk arithmetic with the learned detector (FP64
+state and stage update); the plain FP64 path runs the same steps from the
+same initial state beside it, and the line reports both throughputs, their
+ratio, and the L1/Linf difference per conserved variable between the two
+final states.  The CPU oracle runs a bounded sample (whole steps on the full
+grid) as the cpu_baseline leg, and the headline path's state after the same
+number of steps is compared with it (L1/Linf per variable).
+
+Prints ONE JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload riemann1024]
-                  [--no-cpu-baseline]
+                  [--path fp32_mlp|fp32|fp64] [--no-cpu-baseline] [--no-compare]
 """
 import argparse
 import json
@@ -19,55 +29,156 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-stage updates/s, FP32+MLP-detector vs FP64 plain, at stated L1 error"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-FP64_VECTOR_PEAK_TF = 78.6     # MI355X FP64 vector, published
 
-# algorithmic HBM bytes per cell and launch: read Q^(k) (32 B), write Q^(k+1)
-# (32 B), and Q^n (32 B) in stages 2 and 3.
+# Algorithmic HBM bytes per cell of one stage launch: read Q^(k) (32 B),
+# write Q^(k+1) (32 B), and Q^n (32 B) in stages 2 and 3; 256/3 B on average.
 BYTES_PER_CELL_STAGE = {1: 64.0, 2: 96.0, 3: 96.0}
 
 WORKLOADS = {
-    # name: (family, n, seed, description)
-    "riemann1024": ("riemann", 1024, 0,
-                    "2D Euler four-quadrant Riemann problem, 1024x1024, seed 0, transmissive, "
-                    "FP64 plain method, CFL 0.2"),
-    "vortex64": ("vortex", 64, 0, "2D Euler isentropic vortex 64x64 periodic, CFL 0.5"),
-    "shear2048": ("shear", 2048, 0,
-                  "2D Navier-Stokes periodic shear layer 2048x2048, Re 1e4, Pr 0.72, CFL 0.2"),
+    # name: (family, n, seed, steps, description)
+    "riemann1024": ("riemann", 1024, 0, 200,
+                    "2D Euler four-quadrant Riemann problem, 1024x1024, quadrant states from "
+                    "seed 0, transmissive, CFL 0.2"),
+    "vortex64": ("vortex", 64, 0, 10, "2D Euler isentropic vortex 64x64 periodic, CFL 0.5"),
+    "shear2048": ("shear", 2048, 0, 100,
+                  "2D Navier-Stokes periodic shear layer 2048x2048, Re 1e4, Pr 0.72, Mach 0.3, "
+                  "CFL 0.2"),
+    "riemann4096": ("riemann", 4096, 5000, 50,
+                    "2D Euler four-quadrant Riemann problem, 4096x4096, seed 5000, transmissive, "
+                    "CFL 0.2"),
+}
+
+PATHS = {
+    # name: (precision, learned detector, dtype, kernel name)
+    "fp32_mlp": ("fp32", True, "f32+f64", "meg7_stage_kernel_f32<mlp>"),
+    "fp32": ("fp32", False, "f32+f64", "meg7_stage_kernel_f32"),
+    "fp64": ("fp64", False, "f64", "meg7_stage_kernel"),
 }
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: the workload's step count)")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="riemann1024", choices=sorted(WORKLOADS))
+    ap.add_argument("--path", default="fp32_mlp", choices=sorted(PATHS))
+    ap.add_argument("--weights", default=None, help="detector weights (.npz)")
+    ap.add_argument("--margin", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--tiling", default="auto",
-                    help="tile variant index, or 'auto' (gbr_autotune on the initial state)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the plain FP64 run beside the headline path")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
+    ap.add_argument("--tiling", default="auto",
+                    help="tile variant index, or 'auto' (gbr_autotune on the initial state)")
     return ap.parse_args()
 
 
 def load_traffic(kernel, workload):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, if any."""
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if any
+    (a line 'bytes_per_launch = <value>')."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.txt")
     if not os.path.exists(path):
         return None
-    vals = {}
     for line in open(path):
-        if "=" in line and line.strip().startswith("bytes_per_launch"):
-            k, v = line.split("=", 1)
-            vals[k.strip()] = float(v.split()[0])
-    return vals.get("bytes_per_launch")
+        if line.strip().startswith("bytes_per_launch") and "=" in line:
+            return float(line.split("=", 1)[1].split()[0])
+    return None
 
 
-def cpu_baseline(P, seconds):
+class Path:
+    """One configured context and its three state buffers."""
+
+    def __init__(self, P, path, stream, tiling, weights, margin):
+        import torch
+        from paper_2305_00762_amd import gbr
+        self.gbr, self.P, self.stream = gbr, P, stream
+        prec_name, mlp, self.dtype, self.kernel = PATHS[path]
+        self.ctx = gbr.gbr_init(P.nx, P.ny, P.gamma, P.mu, P.Pr)
+        gbr.gbr_set_geometry(self.ctx, *P.geometry())
+        prec = gbr.GBR_PREC_FP32_BULK if prec_name == "fp32" else gbr.GBR_PREC_FP64
+        self.net = None
+        det = gbr.GBR_DET_PLAIN
+        if mlp:
+            from paper_2305_00762_amd import detector as D
+            self.net = D.load(weights or D.DEFAULT_WEIGHTS)
+            gbr.gbr_set_mlp_detector(self.ctx, self.net, D.DEFAULT_MARGIN if margin is None else margin,
+                                     stream.cuda_stream)
+            det = gbr.GBR_DET_MLP
+        gbr.gbr_set_scheme(self.ctx, gbr.GBR_RECON_PRIM, gbr.GBR_MP_FLAGGED, prec, det)
+        dev = torch.device("cuda:0")
+        self.Q = [torch.from_numpy(P.Q).to(dev) for _ in range(3)]
+        self.dt = torch.zeros(1, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        if tiling == "auto":
+            gbr.gbr_autotune(self.ctx, self.Q[0], 5, stream.cuda_stream)
+        else:
+            gbr.gbr_set_tiling(self.ctx, int(tiling))
+        self.tile = gbr.gbr_get_tiling(self.ctx)
+
+    def reset(self):
+        import torch
+        for q in self.Q:
+            q.copy_(torch.from_numpy(self.P.Q))
+        torch.cuda.synchronize()
+
+    def step(self):
+        """One SSP-RK3 step on self.stream; Q^{n+1} ends in self.Q[0]."""
+        g, sh = self.gbr, self.stream.cuda_stream
+        Q, Q1, Q2 = self.Q
+        g.gbr_compute_dt(self.ctx, Q, self.P.cfl, self.dt, sh)
+        g.gbr_rk_stage(self.ctx, 1, self.dt, Q, Q, Q1, sh)
+        g.gbr_rk_stage(self.ctx, 2, self.dt, Q, Q1, Q2, sh)
+        g.gbr_rk_stage(self.ctx, 3, self.dt, Q, Q2, Q1, sh)
+        self.Q = [Q1, Q, Q2]
+
+    def run(self, warmup, steps, timing=False):
+        """warmup untimed steps, then `steps` timed ones; returns total ms of
+        the timed steps (and the kernel timings when asked)."""
+        import torch
+        g, sh = self.gbr, self.stream.cuda_stream
+        with torch.cuda.stream(self.stream):
+            for _ in range(warmup):
+                self.step()
+        self.stream.synchronize()
+        if g.gbr_check(self.ctx, sh) != g.GBR_OK:
+            raise RuntimeError("device reported a bad state during warmup")
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        if timing:
+            g.gbr_timing(self.ctx, True)
+        with torch.cuda.stream(self.stream):
+            start.record(self.stream)
+            for _ in range(steps):
+                self.step()
+            stop.record(self.stream)
+        self.stream.synchronize()
+        torch.cuda.synchronize()
+        kt = None
+        if timing:
+            kt = g.gbr_timing_read(self.ctx)
+            g.gbr_timing(self.ctx, False)
+        self.status = g.gbr_check(self.ctx, sh)
+        return start.elapsed_time(stop), kt
+
+    def close(self):
+        self.gbr.gbr_destroy(self.ctx)
+        if self.net is not None:
+            self.gbr.gbr_mlp_destroy(self.net)
+
+
+def diff(Qa, Qb):
+    d = (Qa - Qb).abs().reshape(4, -1)
+    return ([float(v) for v in d.mean(dim=1).cpu()], [float(v) for v in d.max(dim=1).values.cpu()])
+
+
+def cpu_baseline(P, seconds, max_steps=50):
     """The CPU oracle on a bounded sample of the same workload: whole SSP-RK3
-    steps on the full grid until about `seconds` of host time have passed."""
+    steps on the full grid from the initial state until about `seconds` of
+    host time have passed.  Returns (record, state after the sample, steps)."""
     import numpy as np
     import oracle as O
     cfg = O.make_cfg(P.nx, P.ny, *P.geometry(), gamma=P.gamma, mu=P.mu, Pr=P.Pr)
@@ -77,110 +188,74 @@ def cpu_baseline(P, seconds):
         O.step(cfg, Q, P.cfl)
         steps += 1
         el = time.perf_counter() - t0
-        if el >= seconds or steps >= 50:
+        if el >= seconds or steps >= max_steps:
             break
     cells = P.nx * P.ny * 3 * steps
-    return {"value": cells / el, "unit": "cell-stage updates/s", "cores": O.threads(),
-            "kind": "oracle",
-            "sample": f"{steps} SSP-RK3 steps ({cells} cell-stages) of the same workload, "
-                      f"{el:.1f} s"}
+    rec = {"value": cells / el, "unit": "cell-stage updates/s", "cores": O.threads(),
+           "kind": "oracle",
+           "sample": f"{steps} whole SSP-RK3 steps of the same workload from its initial "
+                     f"state ({cells} cell-stages) in {el:.1f} s"}
+    return rec, Q, steps
 
 
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (the multi-GPU decomposition is "
-              "a design in DESIGN.md, not built); use --gpus 1", file=sys.stderr)
+        print("bench.py: runs on one GPU only; the decomposition over several GPUs (halo "
+              "exchange per stage, one min-reduction of the time step) is designed, not "
+              "built; use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2305_00762_amd import gbr
     from paper_2305_00762_amd import problems as PB
 
-    fam, n, seed, desc = WORKLOADS[a.workload]
+    fam, n, seed, wsteps, desc = WORKLOADS[a.workload]
+    steps = a.steps if a.steps is not None else wsteps
     P = PB.make(fam, n, seed=seed) if fam != "vortex" else PB.vortex(n, cfl=0.5)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+    torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
-    sh = stream.cuda_stream
-    ctx = gbr.gbr_init(P.nx, P.ny, P.gamma, P.mu, P.Pr)
-    gbr.gbr_set_geometry(ctx, *P.geometry())
-    prec = gbr.GBR_PREC_FP32_BULK if a.precision == "fp32" else gbr.GBR_PREC_FP64
-    gbr.gbr_set_scheme(ctx, gbr.GBR_RECON_PRIM, gbr.GBR_MP_FLAGGED, prec, gbr.GBR_DET_PLAIN)
-    Qs = [torch.from_numpy(P.Q).to(dev) for _ in range(3)]
-    dt = torch.zeros(1, dtype=torch.float64, device=dev)
-    torch.cuda.synchronize()
-    if a.tiling == "auto":
-        gbr.gbr_autotune(ctx, Qs[0], 5, sh)
-    else:
-        gbr.gbr_set_tiling(ctx, int(a.tiling))
-    tiling = gbr.gbr_get_tiling(ctx)
+    cells = P.nx * P.ny
+
     if a.calib_copy_mb:
         # a plain copy of known size: reads and writes calib_copy_mb MiB once
-        src = torch.ones(a.calib_copy_mb << 17, dtype=torch.float64, device=dev)
+        src = torch.ones(a.calib_copy_mb << 17, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    head = Path(P, a.path, stream, a.tiling, a.weights, a.margin)
+    total_ms, (det_ms, stage_ms, launches) = head.run(a.warmup, steps, timing=True)
+    value = cells * 3 * steps / (total_ms * 1e-3)
+    Qhead = head.Q[0].clone()
+    status = gbr.strerror(head.status)
+    fb_rate = None
+    if head.net is not None:
+        ev, fb = gbr.gbr_mlp_stats(head.ctx, reset=True)
+        fb_rate = fb / max(ev, 1)
 
-    def one_step(Q, Q1, Q2, ev=None):
-        gbr.gbr_compute_dt(ctx, Q, P.cfl, dt, sh)
-        for st, (src, dst) in enumerate(((Q, Q1), (Q1, Q2), (Q2, Q1)), start=1):
-            if ev is not None:
-                ev[st][0].record(stream)
-            gbr.gbr_rk_stage(ctx, st, dt, Q, src, dst, sh)
-            if ev is not None:
-                ev[st][1].record(stream)
-        return Q1, Q, Q2        # Q^{n+1} is in Q1
-
-    Q, Q1, Q2 = Qs
-    with torch.cuda.stream(stream):
-        for _ in range(a.warmup):
-            Q, Q1, Q2 = one_step(Q, Q1, Q2)
-    stream.synchronize()
-    if gbr.gbr_check(ctx, sh) != gbr.GBR_OK:
-        raise RuntimeError("device reported a bad state during warmup")
-
-    # timed region: K whole steps, events around every stage launch
-    evs = [[None, None]] + [[[torch.cuda.Event(enable_timing=True) for _ in range(2)]
-                             for _ in range(a.steps)] for _ in range(3)]
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    with torch.cuda.stream(stream):
-        start.record(stream)
-        for k in range(a.steps):
-            ev = [None] + [evs[s][k] for s in (1, 2, 3)]
-            Q, Q1, Q2 = one_step(Q, Q1, Q2, ev)
-        stop.record(stream)
-    stream.synchronize()
-    torch.cuda.synchronize()
-    total_ms = start.elapsed_time(stop)
-    status = gbr.gbr_check(ctx, sh)
-    cells = P.nx * P.ny
-    value = cells * 3 * a.steps / (total_ms * 1e-3)
-
-    stage_ms = {s: sum(e[0].elapsed_time(e[1]) for e in evs[s]) / a.steps for s in (1, 2, 3)}
-    launches = 3 * a.steps
-    stage_total_s = sum(stage_ms.values()) * a.steps * 1e-3
-    alg_bytes = sum(BYTES_PER_CELL_STAGE[s] for s in (1, 2, 3)) * cells * a.steps
-    achieved = alg_bytes / stage_total_s / 1e9
-    traffic = load_traffic("meg7_stage_fp64", a.workload)
+    # roofline of the dominant kernel (the stage kernel): algorithmic bytes of
+    # the timed launches over their summed duration from the library's events
+    alg_bytes = sum(BYTES_PER_CELL_STAGE.values()) * cells * steps
+    achieved = alg_bytes / (stage_ms * 1e-3) / 1e9
+    kname = head.kernel.replace("<mlp>", "_mlp")
+    traffic = load_traffic(kname, a.workload)
     out = {
         "metric": METRIC,
         "value": value,
         "unit": "cell-stage updates/s",
         "n_gpus": 1,
-        "steps": a.steps,
+        "steps": steps,
         "warmup": a.warmup,
-        "ms_per_step": total_ms / a.steps,
+        "ms_per_step": total_ms / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if a.precision == "fp64" else "f32+f64",
+        "dtype": head.dtype,
         "data": "synthetic",
         "config": {"workload": a.workload, "description": desc, "nx": P.nx, "ny": P.ny,
-                   "precision": a.precision, "detector": "plain",
-                   "step": "device dt + 3 fused residual/stage launches",
-                   "tile": f"{tiling[1]}x{tiling[2]}"},
+                   "path": a.path, "tile": f"{head.tile[1]}x{head.tile[2]}",
+                   "step": "device dt + 3 x (learned-detector flag map if selected + fused "
+                           "residual/stage kernel)"},
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,
@@ -188,16 +263,42 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "meg7_stage_kernel" + ("_f32" if a.precision == "fp32" else "") + f" ({a.precision})",
-            "avg_launch_ms": stage_total_s * 1e3 / launches,
-            "stage_ms": stage_ms,
+            "kernel": head.kernel,
+            "avg_launch_us": stage_ms * 1e3 / max(launches, 1),
             "bytes_per_cell_stage": 256.0 / 3.0,
         },
-        "status": gbr.strerror(status),
+        "kernels_us_per_launch": {"stage": stage_ms * 1e3 / max(launches, 1),
+                                  "detector_flag_map": det_ms * 1e3 / max(launches, 1)},
+        # flag map: reads Q (32 B) and writes one byte per cell
+        "detector_flag_map_GBs": (33.0 * cells * launches / (det_ms * 1e-3) / 1e9
+                                  if det_ms > 0 else None),
+        "status": status,
     }
-    gbr.gbr_destroy(ctx)
+    if fb_rate is not None:
+        out["detector_fallback_rate"] = fb_rate
+
+    if not a.no_compare and a.path != "fp64":
+        base = Path(P, "fp64", stream, a.tiling, None, None)
+        bms, _ = base.run(a.warmup, steps)
+        bval = cells * 3 * steps / (bms * 1e-3)
+        l1, linf = diff(Qhead, base.Q[0])
+        out["fp64_plain"] = {"value": bval, "ms_per_step": bms / steps,
+                             "tile": f"{base.tile[1]}x{base.tile[2]}",
+                             "status": gbr.strerror(base.status)}
+        out["speedup_vs_fp64_plain"] = value / bval
+        out["error_vs_fp64_plain"] = {"after_steps": a.warmup + steps, "L1": l1, "Linf": linf,
+                                      "vars": ["rho", "rho_u", "rho_v", "E"]}
+        base.close()
+
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(P, a.cpu_seconds)
+        rec, Qo, osteps = cpu_baseline(P, a.cpu_seconds)
+        out["cpu_baseline"] = rec
+        head.reset()
+        head.run(osteps, 0)
+        l1, linf = diff(head.Q[0].cpu(), torch.from_numpy(Qo))
+        out["error_vs_oracle"] = {"after_steps": osteps, "L1": l1, "Linf": linf,
+                                  "vars": ["rho", "rho_u", "rho_v", "E"]}
+    head.close()
     print(json.dumps(out), flush=True)
 
 

@@ -114,6 +114,17 @@ int gbr_compute_dt(gbr_ctx *ctx, const double *Q, double cfl, double *dt_dev,
 int gbr_export_flags(gbr_ctx *ctx, int enable);
 int gbr_get_flags(gbr_ctx *ctx, uint8_t *sig_x, uint8_t *sig_y, void *stream);
 
+/* Kernel timing.  With timing enabled, every residual or stage call records
+ * three HIP events on its stream: before the learned detector's flag-map
+ * kernel (detector = MLP; otherwise no kernel runs there), before the stage
+ * kernel and after it.  gbr_timing_read waits for the last recorded event and
+ * returns the summed durations (milliseconds) of the flag-map and stage
+ * kernels and the number of calls since timing was enabled or last read,
+ * then starts a new count.  Events are created by the context as needed and
+ * reused; gbr_timing(ctx, 0) stops recording. */
+int gbr_timing(gbr_ctx *ctx, int enable);
+int gbr_timing_read(gbr_ctx *ctx, double *detector_ms, double *stage_ms, uint64_t *launches);
+
 /* Tile shapes of the stage kernel.  gbr_tiling_count() is the number of
  * compiled shapes; gbr_set_tiling selects one (0 = default 31x15 cells per
  * workgroup); gbr_get_tiling reports the shape in use (the viscous form falls
@@ -149,9 +160,12 @@ int gbr_mlp_destroy(gbr_mlp *m);
 int gbr_mlp_set_params(gbr_mlp *m, const float *w, const float *b);
 int gbr_mlp_get_params(gbr_mlp *m, float *w, float *b);
 
-/* Features of every cell of the device state Q of `ctx`'s grid: feat = device
- * [ny*nx][32] bf16 bit patterns (row = cell i*nx + j), and, if chi is not NULL,
- * the plain label chi = [psi_x < psi_c or psi_y < psi_c] (device [ny*nx]). */
+/* Features of every cell of the device state Q of `ctx`'s grid, for the
+ * network's evaluation along x and along y (Sec. 2.4 works dimension by
+ * dimension): feat = device [2][ny*nx][32] bf16 bit patterns, rows
+ * [0, n) along x and [n, 2n) along y (row = cell i*nx + j); and, if chi is not
+ * NULL, the directional plain labels chi = device [2][ny*nx]:
+ * [psi_x < psi_c] then [psi_y < psi_c]. */
 int gbr_mlp_features(gbr_ctx *ctx, const double *Q, uint16_t *feat, uint8_t *chi,
                      void *stream);
 
@@ -176,9 +190,12 @@ int gbr_mlp_train_step(gbr_mlp *m, const uint16_t *feat, const uint8_t *labels, 
  * gbr_set_scheme(..., GBR_DET_MLP).  With it selected, every residual or
  * stage call first evaluates the network once per cell of the grid into a
  * per-cell flag map owned by the context (nx*ny bytes, allocated here), which
- * the stage kernel's sigma buffers read.  gbr_mlp_stats reports the cells
- * evaluated since the last reset and how many of them fell back to the plain
- * detector (synchronises the device; optionally resets both counts). */
+ * the stage kernel's sigma buffers read (the network is evaluated along x
+ * and along y, each flag feeding the buffer of its direction).
+ * gbr_mlp_stats reports the network evaluations since the last reset (two
+ * per cell and call: along x and along y) and how many of them fell back to
+ * the plain detector (synchronises the device; optionally resets both
+ * counts). */
 int gbr_set_mlp_detector(gbr_ctx *ctx, const gbr_mlp *m, float margin, void *stream);
 int gbr_mlp_stats(gbr_ctx *ctx, uint64_t *evaluated, uint64_t *fallbacks, int reset);
 

@@ -21,8 +21,7 @@
  *               the detector and eq. (buffer)          -> hybrid flux
  *   Sec. 2.5    eq. (rk) and the CFL time step          -> time integration
  *
- * Readings taken where the paper is silent or garbled (all listed in
- * the design doc):
+ * Readings taken where the paper is silent or garbled:
  *   R-T    T := gamma p / rho, so that q = -mu/(Pr(gamma-1)) dT/dx matches
  *          kappa = Cp mu / Pr (Cp cancels).
  *   R-DET  psi = (2ab + eps) / (a^2 + b^2 + eps): the printed psi omits the

@@ -1,11 +1,14 @@
 """Oracle of the learned discontinuity detector (test infrastructure only).
 
-A small MLP stands in for the density detector of Sec. 2.4: its label is
-the plain detector's per-cell outcome chi = [psi_x < psi_c or psi_y < psi_c]
-(computed by the C oracle), its input 28 per-cell features:
+A small MLP stands in for the density detector of Sec. 2.4.  That detector
+works dimension by dimension (psi^x from x-lines flags x-interfaces, psi^y
+from y-lines flags y-interfaces), so the network is applied once per
+direction d of a cell: its label is the plain per-cell outcome
+chi^d = [psi^d < psi_c] (computed by the C oracle), its input 28 features:
 
-  four 7-point stencils, in this order: rho along x, p along x, rho along y,
-  p along y (offsets -3..3, ghost cells as in the scheme), each taken to
+  four 7-point stencils, normal direction first: rho along d, p along d, rho
+  along the other direction, p along it (offsets -3..3, ghost cells as in the
+  scheme; for d = x this is rho_x, p_x, rho_y, p_y), each taken to
   float32 and normalised as (s_k - mean) * r with
       sum  = ((((((s0+s1)+s2)+s3)+s4)+s5)+s6),  mean = sum * float32(1/7),
       r    = 1 / ((max - min) + 1e-3)           (IEEE float32 division),
@@ -61,14 +64,18 @@ def primitives(Q, gamma=1.4):
     return rho, p
 
 
-def features(Q, bc_x, bc_y, gamma=1.4):
-    """Per-cell features [ny*nx][32] as bf16 bit patterns (uint16)."""
+def features(Q, bc_x, bc_y, gamma=1.4, direction=0):
+    """Per-cell features [ny*nx][32] as bf16 bit patterns (uint16) for the
+    evaluation along x (direction 0) or y (direction 1)."""
     rho, p = primitives(Q, gamma)
     ny, nx = rho.shape
     out = np.zeros((ny, nx, NIN), np.float32)
     one7 = np.float32(1.0 / 7.0)
     col = 0
-    for field, axis, bc in ((rho, 1, bc_x), (p, 1, bc_x), (rho, 0, bc_y), (p, 0, bc_y)):
+    groups = [(rho, 1, bc_x), (p, 1, bc_x), (rho, 0, bc_y), (p, 0, bc_y)]
+    if direction == 1:
+        groups = groups[2:] + groups[:2]
+    for field, axis, bc in groups:
         s = [_ghost(field, axis, k - 3, bc).astype(np.float32) for k in range(7)]
         tot = s[0]
         for k in range(1, 7):
@@ -82,6 +89,11 @@ def features(Q, bc_x, bc_y, gamma=1.4):
             out[:, :, col] = ((s[k] - mean).astype(np.float32) * r).astype(np.float32)
             col += 1
     return bf16_bits(out.reshape(ny * nx, NIN))
+
+
+def labels(psi_x, psi_y, psi_c=0.5):
+    """Directional plain labels (chi^x, chi^y) from the detector values."""
+    return (psi_x < psi_c).astype(np.uint8), (psi_y < psi_c).astype(np.uint8)
 
 
 def unpack(w, b):

@@ -106,19 +106,21 @@ def residual_sigma(cfg, Q, sig_x, sig_y):
     return R
 
 
-def sigma_from_cells(chi, bc_x, bc_y):
-    """Interface flags from per-cell flags chi [ny][nx]: sigma = 0 where any
-    cell of the 6-cell buffer (j-2..j+3 along the interface normal) is
-    flagged (the buffer of eq. buffer applied to a per-cell detector)."""
-    ny, nx = chi.shape
+def sigma_from_cells(chi_x, chi_y, bc_x, bc_y):
+    """Interface flags from per-cell directional flags chi_x, chi_y [ny][nx]:
+    sigma^x = 0 where any cell of the 6-cell buffer j-2..j+3 along x has
+    chi_x set, sigma^y likewise from chi_y along y (the buffer of
+    eq. buffer applied to per-cell flags; ghost cells take the flag of the
+    cell they copy)."""
+    ny, nx = chi_x.shape
     sx = np.ones((ny, nx + 1), np.uint8)
     sy = np.ones((ny + 1, nx), np.uint8)
     for j in range(-1, nx):
         cols = [k % nx if bc_x == 0 else min(max(k, 0), nx - 1) for k in range(j - 2, j + 4)]
-        sx[:, j + 1] = (chi[:, cols].max(axis=1) == 0)
+        sx[:, j + 1] = (chi_x[:, cols].max(axis=1) == 0)
     for i in range(-1, ny):
         rows = [k % ny if bc_y == 0 else min(max(k, 0), ny - 1) for k in range(i - 2, i + 4)]
-        sy[i + 1, :] = (chi[rows, :].max(axis=0) == 0)
+        sy[i + 1, :] = (chi_y[rows, :].max(axis=0) == 0)
     return sx, sy
 
 

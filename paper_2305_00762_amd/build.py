@@ -1,7 +1,8 @@
 """Build the C-ABI library libgbr.so (HIP, gfx950) in-tree.
 
 hipcc -O3 --offload-arch=gfx950; packed FP32 instructions are switched off
-(-Xclang -target-feature -Xclang -packed-fp32-ops) for every HIP source.
+(-Xclang -target-feature -Xclang -packed-fp32-ops) for every HIP source, and
+matrix-core instructions take their accumulators in VGPRs.
 """
 import os
 import subprocess
@@ -16,6 +17,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # matrix-core results in VGPRs (no accumulator-register copies)
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1",
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <new>
+#include <vector>
 
 #include "../../include/gbr.h"
 #include "dt_kernel.hpp"
@@ -97,6 +98,12 @@ struct gbr_ctx {
   uint8_t* d_chimap;          // [ny][nx] learned-detector flag per cell
   unsigned long long* d_mlp_fb;   // plain fallbacks of the learned detector
   unsigned long long mlp_evaluated;
+  // kernel timing (gbr_timing): events recorded around every launch of a
+  // residual or stage call, three per call: before the learned detector's
+  // flag map, before the stage kernel, after it
+  int timing;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used;
 };
 
 struct gbr_mlp {
@@ -165,6 +172,7 @@ int gbr_destroy(gbr_ctx* c) {
   if (c->d_mlp_f) (void)hipFree(c->d_mlp_f);
   if (c->d_chimap) (void)hipFree(c->d_chimap);
   if (c->d_mlp_fb) (void)hipFree(c->d_mlp_fb);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   delete c;
   return GBR_OK;
 }
@@ -241,6 +249,19 @@ static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn
   const int visc = c->mu > 0.0 ? 1 : 0;
   const int prec = c->precision == GBR_PREC_FP32_BULK ? 1 : 0;
   const int det = c->detector == GBR_DET_MLP ? 1 : 0;
+  hipEvent_t* tev = nullptr;
+  if (c->timing) {
+    if (c->ev_used + 3 > c->ev.size()) {
+      for (int k = 0; k < 3 * 64; ++k) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return GBR_EDEVICE;
+        c->ev.push_back(e);
+      }
+    }
+    tev = &c->ev[c->ev_used];
+    c->ev_used += 3;
+    if (hipEventRecord(tev[0], s) != hipSuccess) return GBR_EDEVICE;
+  }
   if (det) {
     MlpChiParams M{};
     M.Q = Qk; M.chi = c->d_chimap; M.nfb = c->d_mlp_fb;
@@ -254,15 +275,43 @@ static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn
     M.gamma = c->gamma;
     const int nblk = M.tiles_x * ((c->ny + kChiTY - 1) / kChiTY);
     hipLaunchKernelGGL(mlp_chi_kernel, dim3(nblk), dim3(256), 0, s, M);
-    c->mlp_evaluated += (unsigned long long)c->nx * c->ny;
+    c->mlp_evaluated += 2ull * c->nx * c->ny;   // along x and along y
     P.chimap = c->d_chimap;
   }
   const TileVariant* v = &kVariants[c->tiling];
   if (!v->fn[prec][visc][det]) v = &kVariants[0];
   P.tiles_x = (c->nx + v->tx - 1) / v->tx;
   P.ntiles = P.tiles_x * ((c->ny + v->ty - 1) / v->ty);
+  if (tev && hipEventRecord(tev[1], s) != hipSuccess) return GBR_EDEVICE;
   v->fn[prec][visc][det](P, s);
+  if (tev && hipEventRecord(tev[2], s) != hipSuccess) return GBR_EDEVICE;
   return hip_ok(hipGetLastError());
+}
+
+int gbr_timing(gbr_ctx* c, int enable) {
+  if (!c) return GBR_EINVAL;
+  c->timing = enable ? 1 : 0;
+  c->ev_used = 0;
+  return GBR_OK;
+}
+
+int gbr_timing_read(gbr_ctx* c, double* detector_ms, double* stage_ms, uint64_t* launches) {
+  if (!c) return GBR_EINVAL;
+  double d = 0.0, st = 0.0;
+  for (size_t k = 0; k + 3 <= c->ev_used; k += 3) {
+    float a = 0.f, b = 0.f;
+    if (hipEventSynchronize(c->ev[k + 2]) != hipSuccess ||
+        hipEventElapsedTime(&a, c->ev[k], c->ev[k + 1]) != hipSuccess ||
+        hipEventElapsedTime(&b, c->ev[k + 1], c->ev[k + 2]) != hipSuccess)
+      return GBR_EDEVICE;
+    d += a;
+    st += b;
+  }
+  if (detector_ms) *detector_ms = d;
+  if (stage_ms) *stage_ms = st;
+  if (launches) *launches = c->ev_used / 3;
+  c->ev_used = 0;
+  return GBR_OK;
 }
 
 int gbr_tiling_count(void) { return kNumVariants; }
@@ -295,8 +344,9 @@ int gbr_autotune(gbr_ctx* c, const double* Q, int reps, void* stream) {
     (void)hipFree(tmp);
     return GBR_EDEVICE;
   }
-  const int saved = c->tiling, flags = c->export_flags;
+  const int saved = c->tiling, flags = c->export_flags, timing = c->timing;
   c->export_flags = 0;
+  c->timing = 0;
   int best = saved, rc = GBR_OK;
   float best_ms = 1e30f;
   const int visc = c->mu > 0.0 ? 1 : 0, prec = c->precision == GBR_PREC_FP32_BULK ? 1 : 0;
@@ -316,6 +366,7 @@ int gbr_autotune(gbr_ctx* c, const double* Q, int reps, void* stream) {
   }
   c->tiling = (rc == GBR_OK) ? best : saved;
   c->export_flags = flags;
+  c->timing = timing;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(tmp);
@@ -428,7 +479,7 @@ int gbr_mlp_features(gbr_ctx* c, const double* Q, uint16_t* feat, uint8_t* chi, 
   MlpFeatParams P{};
   P.Q = Q; P.feat = feat; P.chi = chi;
   P.nx = c->nx; P.ny = c->ny; P.bcx = c->bcx; P.bcy = c->bcy; P.gamma = c->gamma;
-  const size_t n = (size_t)c->nx * c->ny;
+  const size_t n = (size_t)c->nx * c->ny;   // one thread per cell, both directions
   hipLaunchKernelGGL(mlp_features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                      (hipStream_t)stream, P);
   return hip_ok(hipGetLastError());

@@ -43,14 +43,26 @@ __device__ __forceinline__ v4s pack4(float a, float b, float c, float d) {
   return r;
 }
 
-// Features of one cell.  val(s, o) returns, in FP64, the stencil value at
-// offset o (-3..3) of stencil s: 0 rho along x, 1 p along x, 2 rho along y,
-// 3 p along y.  Each stencil is taken to float32 and normalised as
+// float32 pair -> packed bf16 pair (low half = a), round to nearest even, by
+// the hardware conversion (same result as f2bf for finite values).
+__device__ __forceinline__ unsigned cvt_pk_bf16(float a, float b) {
+  typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+  bf2 r;
+  r[0] = (__bf16)a;
+  r[1] = (__bf16)b;
+  return __builtin_bit_cast(unsigned, r);
+}
+
+// Features of one cell.  val(s, o) returns the stencil value at offset o
+// (-3..3) of stencil s: 0 rho along x, 1 p along x, 2 rho along y, 3 p along
+// y.  Each stencil is taken to float32 and normalised as
 // (s_k - mean) / ((max - min) + 1e-3) with a fixed operation order (sum left
 // to right, mean = sum * fl(1/7), one IEEE reciprocal), then rounded to bf16.
+// out[j] holds features 2j (low half) and 2j+1; out[14], out[15] are zero.
 template <class FV>
-__device__ __forceinline__ void mlp_cell_features(FV val, unsigned short out[kMlpIn]) {
+__device__ __forceinline__ void mlp_cell_features(FV val, unsigned out[kMlpIn / 2]) {
 #pragma clang fp contract(off)
+  float f[kMlpF];
   int col = 0;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
@@ -66,10 +78,12 @@ __device__ __forceinline__ void mlp_cell_features(FV val, unsigned short out[kMl
     for (int k = 1; k < 7; ++k) { mx = fmaxf(mx, v[k]); mn = fminf(mn, v[k]); }
     const float r = 1.0f / ((mx - mn) + 1e-3f);
 #pragma unroll
-    for (int k = 0; k < 7; ++k) out[col++] = f2bf((v[k] - mean) * r);
+    for (int k = 0; k < 7; ++k) f[col++] = (v[k] - mean) * r;
   }
 #pragma unroll
-  for (int k = kMlpF; k < kMlpIn; ++k) out[k] = 0;
+  for (int j = 0; j < kMlpF / 2; ++j) out[j] = cvt_pk_bf16(f[2 * j], f[2 * j + 1]);
+  out[kMlpF / 2] = 0;
+  out[kMlpF / 2 + 1] = 0;
 }
 
 // Inference image of the network: bf16 W1 [32][32] (inputs 28..31 zero), bf16
@@ -107,6 +121,89 @@ __device__ __forceinline__ void mlp_load_frags(const MlpImage& M, MlpFrags& F) {
     }
   }
   F.b3 = M.b[2 * kMlpH];
+}
+
+// Inference on the K = 32 matrix instruction (v_mfma_f32_16x16x32_bf16):
+// lane l = 16 g + r supplies 8 bf16 of row r of A and of column r of B, for
+// one group of 8 K indices per g, and receives D[4g..4g+3][r] as before.
+// Which K indices a (g, element) slot stands for does not matter as long as A
+// and B fill the slot with the same index: the slot of lane group g, element
+// e holds feature 8g + e in layer 1 and hidden neuron 16 (e / 4) + 4 g + e % 4
+// in layer 2 -- exactly the layer-1 output the lane already holds, so the
+// hidden activations go from the accumulator to the next B operand in
+// registers.  The biases initialise the accumulators.
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// max(x, 0) on the bit pattern: negative floats are negative integers, so one
+// integer max (no NaN canonicalisation of the float max in IEEE mode).
+__device__ __forceinline__ float relu(float x) {
+  return __int_as_float(max(__float_as_int(x), 0));
+}
+
+__device__ __forceinline__ v4f mfma32(v8s a, v8s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
+                                                 __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
+
+// The evaluation along y feeds the same staged (x-order) features: its input
+// is the x-order vector with the two stencil halves (features 0..13 and
+// 14..27) swapped, so W1 with its columns swapped the same way (a1y) gives
+// the y-evaluation's first layer.
+struct MlpInfer {
+  v8s a1[2], a1y[2], a2[2];   // [neuron block]
+  v4f b1[2], b2[2];   // biases of neurons 16 nb + 4 g + i
+  float w3[2][4];
+  float b3;
+};
+
+__device__ __forceinline__ void mlp_load_infer(const MlpImage& M, MlpInfer& F) {
+  const int l = __lane_id(), r = l & 15, g = l >> 4;
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    const int n = 16 * nb + r;
+    F.a1[nb] = *reinterpret_cast<const v8s*>(M.W1 + n * kMlpIn + 8 * g);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = 8 * g + e;
+      F.a1y[nb][e] = (short)M.W1[n * kMlpIn + (k < kMlpF ? (k + kMlpF / 2) % kMlpF : k)];
+    }
+    const v4s lo = *reinterpret_cast<const v4s*>(M.W2 + n * kMlpH + 4 * g);
+    const v4s hi = *reinterpret_cast<const v4s*>(M.W2 + n * kMlpH + 16 + 4 * g);
+    F.a2[nb] = (v8s){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int m = 16 * nb + 4 * g + i;
+      F.b1[nb][i] = M.b[m];
+      F.b2[nb][i] = M.b[kMlpH + m];
+      F.w3[nb][i] = M.w3[m];
+    }
+  }
+  F.b3 = M.b[2 * kMlpH];
+}
+
+// Logit of the 16 cells whose features (slot layout above) lanes hold in x;
+// cell r = lane & 15 (the same value in the four lanes of a column).  ydir:
+// evaluate along y from the x-order features.
+__device__ __forceinline__ float mlp_infer16(const MlpInfer& F, v8s x, bool ydir = false) {
+  unsigned hp[4];
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    const v4f c = mfma32(ydir ? F.a1y[nb] : F.a1[nb], x, F.b1[nb]);
+    hp[2 * nb] = cvt_pk_bf16(relu(c[0]), relu(c[1]));
+    hp[2 * nb + 1] = cvt_pk_bf16(relu(c[2]), relu(c[3]));
+  }
+  const v8s h = __builtin_bit_cast(v8s, (uint4){hp[0], hp[1], hp[2], hp[3]});
+  float part = 0.f;
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    const v4f c = mfma32(F.a2[nb], h, F.b2[nb]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) part += F.w3[nb][i] * relu(c[i]);
+  }
+  part += __shfl_xor(part, 16);
+  part += __shfl_xor(part, 32);
+  return part + F.b3;
 }
 
 // Forward pass of 16 cells whose bf16 B fragments (k steps 0, 1) are x0, x1.
@@ -150,11 +247,13 @@ __device__ __forceinline__ float mlp_forward16(const MlpFrags& F, v4s x0, v4s x1
 }
 
 // ---------------------------------------------------------------------------
-// Features and plain labels of a whole grid (training data, evaluation).
+// Features and plain labels of a whole grid (training data, evaluation), for
+// both directions: rows [0, n) are the evaluations along x, rows [n, 2n) those
+// along y (the same four stencil groups, y-groups first).
 struct MlpFeatParams {
   const double* Q;
-  unsigned short* feat;   // [n][32]
-  uint8_t* chi;           // [n] or null: plain label [psi_x < psi_c or psi_y < psi_c]
+  unsigned short* feat;   // [2][n][32]
+  uint8_t* chi;           // [2][n] or null: plain labels [psi_x < psi_c], [psi_y < psi_c]
   int nx, ny, bcx, bcy;
   double gamma;
 };
@@ -189,45 +288,49 @@ __global__ __launch_bounds__(256) void mlp_features_kernel(MlpFeatParams P) {
     if (!want_p) return r;
     return mlp_cell_pressure(r, P.Q[n + s], P.Q[2 * n + s], P.Q[3 * n + s], P.gamma);
   };
-  unsigned short f[kMlpIn];
+  unsigned f[kMlpIn / 2];
   mlp_cell_features(
       [&](int s, int o) {
         return (s < 2) ? cell(i, j + o, s & 1) : cell(i + o, j, s & 1);
       },
       f);
-  uint4* dst = reinterpret_cast<uint4*>(P.feat + c * kMlpIn);
+  uint4* dx = reinterpret_cast<uint4*>(P.feat + c * kMlpIn);
+  uint4* dy = reinterpret_cast<uint4*>(P.feat + (n + c) * kMlpIn);
+  unsigned fy[kMlpIn / 2];
+#pragma unroll
+  for (int k = 0; k < kMlpF / 2; ++k) fy[k] = f[(k + kMlpF / 4) % (kMlpF / 2)];
+  fy[kMlpF / 2] = 0;
+  fy[kMlpF / 2 + 1] = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    uint4 w;
-    w.x = f[8 * q + 0] | ((unsigned)f[8 * q + 1] << 16);
-    w.y = f[8 * q + 2] | ((unsigned)f[8 * q + 3] << 16);
-    w.z = f[8 * q + 4] | ((unsigned)f[8 * q + 5] << 16);
-    w.w = f[8 * q + 6] | ((unsigned)f[8 * q + 7] << 16);
-    dst[q] = w;
+    dx[q] = make_uint4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
+    dy[q] = make_uint4(fy[4 * q], fy[4 * q + 1], fy[4 * q + 2], fy[4 * q + 3]);
   }
   if (P.chi) {
     const double px = detector_psi(cell(i, j - 2, 0), cell(i, j - 1, 0), cell(i, j, 0),
                                    cell(i, j + 1, 0), cell(i, j + 2, 0));
     const double py = detector_psi(cell(i - 2, j, 0), cell(i - 1, j, 0), cell(i, j, 0),
                                    cell(i + 1, j, 0), cell(i + 2, j, 0));
-    P.chi[c] = (px < kPsiC || py < kPsiC) ? 1 : 0;
+    P.chi[c] = px < kPsiC ? 1 : 0;
+    P.chi[n + c] = py < kPsiC ? 1 : 0;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Per-cell flag map of the learned detector, chi[c] for every grid cell: the
+// Per-cell flag map of the learned detector, chi[c] for every grid cell:
+// bit 0 from the evaluation along x, bit 1 from the one along y, each the
 // logit's sign where |logit| >= margin, else the plain label
-// [psi_x < psi_c or psi_y < psi_c].  One workgroup per 64 x 16 block of
-// cells: the block plus a 3-cell halo of rho (FP64 and float32) and p
-// (float32) is staged in LDS once (ghost cells by wrap or clamp), then four
+// [psi^d < psi_c] from the FP64 density.  One workgroup per
+// 64 x 16 block of cells: the block plus a 3-cell halo of rho and p (float32)
+// is staged in LDS once (ghost cells by wrap or clamp), then four
 // rounds of 256 cells each compute their features (one cell per thread),
 // stage them as bf16 rows and run the network on the matrix cores; a wave
 // evaluates exactly its own 64 cells, so the logit of lane l's cell lands in
 // lane l and the byte store is coalesced.
 struct MlpChiParams {
   const double* Q;
-  uint8_t* chi;                 // [ny][nx]
-  unsigned long long* nfb;      // plain fallbacks (summed)
+  uint8_t* chi;                 // [ny][nx]: bit 0 chi^x, bit 1 chi^y
+  unsigned long long* nfb;      // plain fallbacks (summed over both directions)
   MlpImage M;
   float margin;
   int nx, ny, bcx, bcy, tiles_x;
@@ -235,24 +338,32 @@ struct MlpChiParams {
 };
 constexpr int kChiTX = 64, kChiTY = 16;
 constexpr int kChiRX = kChiTX + 6, kChiRY = kChiTY + 6, kChiRS = kChiRX * kChiRY;
-constexpr int kChiRow = kMlpIn + 4;   // bf16 row stride in LDS (72 B: conflict-free b64 reads)
+constexpr int kChiRow = 5;            // uint4 per staged feature row (80 B: conflict-free)
 
 __global__ __launch_bounds__(256) void mlp_chi_kernel(MlpChiParams P) {
-  __shared__ double sR[kChiRS];
   __shared__ float sF[2][kChiRS];
-  __shared__ unsigned short sX[256 * kChiRow];
+  __shared__ uint4 sX[256 * kChiRow];
   __shared__ unsigned sFb[4];
   const int tid = threadIdx.x, l = __lane_id(), g = l >> 4, w = tid >> 6;
   const int tx0 = (blockIdx.x % P.tiles_x) * kChiTX, ty0 = (blockIdx.x / P.tiles_x) * kChiTY;
   const size_t n = (size_t)P.nx * P.ny;
   constexpr int LR = (kChiRS + 255) / 256;
+  // ghost cells: on grids of at least one block plus halo a single wrap (or
+  // a clamp) suffices; smaller grids take the general loop
+  const bool one = P.nx >= kChiRX && P.ny >= kChiRY;
+  auto gwrap = [&](int k, int nn, int bc) {
+    if (!one) return wrap_bc(k, nn, bc);
+    if (bc != 0) return min(max(k, 0), nn - 1);
+    k = k < 0 ? k + nn : k;
+    return k >= nn ? k - nn : k;
+  };
   double q[LR][4];
 #pragma unroll
   for (int k = 0; k < LR; ++k) {
     const int c = tid + 256 * k;
     if (c < kChiRS) {
-      const size_t s = (size_t)wrap_bc(ty0 + c / kChiRX - 3, P.ny, P.bcy) * P.nx +
-                       wrap_bc(tx0 + c % kChiRX - 3, P.nx, P.bcx);
+      const size_t s = (size_t)gwrap(ty0 + c / kChiRX - 3, P.ny, P.bcy) * P.nx +
+                       gwrap(tx0 + c % kChiRX - 3, P.nx, P.bcx);
 #pragma unroll
       for (int m = 0; m < 4; ++m) q[k][m] = P.Q[m * n + s];
     }
@@ -261,54 +372,65 @@ __global__ __launch_bounds__(256) void mlp_chi_kernel(MlpChiParams P) {
   for (int k = 0; k < LR; ++k) {
     const int c = tid + 256 * k;
     if (c < kChiRS) {
-      sR[c] = q[k][0];
       sF[0][c] = (float)q[k][0];
       sF[1][c] = (float)mlp_cell_pressure(q[k][0], q[k][1], q[k][2], q[k][3], P.gamma);
     }
   }
-  MlpFrags F;
-  mlp_load_frags(P.M, F);
+  MlpInfer F;
+  mlp_load_infer(P.M, F);
   __syncthreads();
   unsigned nfb = 0;
+  // Wave w evaluates rows 4 rnd + w; it stages and reads back only its own 64
+  // feature rows, so the hand-off needs a wave-scope fence, not a barrier.
   for (int rnd = 0; rnd < kChiTY / 4; ++rnd) {
     const int lx = tid & 63, ly = 4 * rnd + w;
     const int rc = (ly + 3) * kChiRX + lx + 3;
     {
-      unsigned short f[kMlpIn];
+      unsigned f[kMlpIn / 2];
       mlp_cell_features(
-          [&](int s, int o) { return (double)sF[s & 1][rc + o * ((s < 2) ? 1 : kChiRX)]; }, f);
-      uint2* dst = reinterpret_cast<uint2*>(sX + tid * kChiRow);
+          [&](int s, int o) { return sF[s & 1][rc + o * ((s < 2) ? 1 : kChiRX)]; }, f);
 #pragma unroll
-      for (int q2 = 0; q2 < 8; ++q2)
-        dst[q2] = make_uint2(f[4 * q2] | ((unsigned)f[4 * q2 + 1] << 16),
-                             f[4 * q2 + 2] | ((unsigned)f[4 * q2 + 3] << 16));
+      for (int c4 = 0; c4 < 4; ++c4)
+        sX[tid * kChiRow + c4] = make_uint4(f[4 * c4], f[4 * c4 + 1], f[4 * c4 + 2], f[4 * c4 + 3]);
     }
-    __syncthreads();
-    float zl = 0.f;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float zx = 0.f, zy = 0.f;
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
-      const int row = w * 64 + cb * 16 + (l & 15);
-      const v4s x0 = *reinterpret_cast<const v4s*>(sX + row * kChiRow + 4 * g);
-      const v4s x1 = *reinterpret_cast<const v4s*>(sX + row * kChiRow + 16 + 4 * g);
-      const float z = mlp_forward16(F, x0, x1, nullptr);
-      if (cb == g) zl = z;
+      const v8s v = __builtin_bit_cast(v8s, sX[(w * 64 + cb * 16 + (l & 15)) * kChiRow + g]);
+      const float z0 = mlp_infer16(F, v, false);
+      const float z1 = mlp_infer16(F, v, true);
+      if (cb == g) { zx = z0; zy = z1; }
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int gj = tx0 + lx, gi = ty0 + ly;
     if (gj < P.nx && gi < P.ny) {
-      unsigned char chi;
-      if (fabsf(zl) >= P.margin) {
-        chi = zl > 0.f ? 1 : 0;
+      // plain label along a direction from the FP64 density (the fallback is
+      // rare: read the density from memory)
+      auto rho = [&](int di, int dj) {
+        return P.Q[(size_t)wrap_bc(gi + di, P.ny, P.bcy) * P.nx + wrap_bc(gj + dj, P.nx, P.bcx)];
+      };
+      unsigned chi = 0;
+      if (fabsf(zx) >= P.margin) {
+        chi |= zx > 0.f ? 1u : 0u;
       } else {
-        const double* rho = sR + rc;
-        const double px = detector_psi(rho[-2], rho[-1], rho[0], rho[1], rho[2]);
-        const double py =
-            detector_psi(rho[-2 * kChiRX], rho[-kChiRX], rho[0], rho[kChiRX], rho[2 * kChiRX]);
-        chi = (px < kPsiC || py < kPsiC) ? 1 : 0;
+        const double px = detector_psi(rho(0, -2), rho(0, -1), rho(0, 0), rho(0, 1), rho(0, 2));
+        chi |= px < kPsiC ? 1u : 0u;
         ++nfb;
       }
-      P.chi[(size_t)gi * P.nx + gj] = chi;
+      if (fabsf(zy) >= P.margin) {
+        chi |= zy > 0.f ? 2u : 0u;
+      } else {
+        const double py = detector_psi(rho(-2, 0), rho(-1, 0), rho(0, 0), rho(1, 0), rho(2, 0));
+        chi |= py < kPsiC ? 2u : 0u;
+        ++nfb;
+      }
+      P.chi[(size_t)gi * P.nx + gj] = (uint8_t)chi;
     }
-    __syncthreads();
   }
   if (P.nfb) {
 #pragma unroll
@@ -326,17 +448,16 @@ __global__ __launch_bounds__(256) void mlp_chi_kernel(MlpChiParams P) {
 // Inference over a feature array: logits[c] for c < n.  One wave per 64 cells.
 __global__ __launch_bounds__(256) void mlp_forward_kernel(MlpImage M, const unsigned short* feat,
                                                           int n, float* logits) {
-  MlpFrags F;
-  mlp_load_frags(M, F);
+  MlpInfer F;
+  mlp_load_infer(M, F);
   const int l = __lane_id(), r = l & 15, g = l >> 4;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) {
     const int c = wave * 64 + cb * 16 + r;
     const int cc = c < n ? c : n - 1;
-    const v4s x0 = *reinterpret_cast<const v4s*>(feat + (size_t)cc * kMlpIn + 4 * g);
-    const v4s x1 = *reinterpret_cast<const v4s*>(feat + (size_t)cc * kMlpIn + 16 + 4 * g);
-    const float z = mlp_forward16(F, x0, x1, nullptr);
+    const v8s x = *reinterpret_cast<const v8s*>(feat + (size_t)cc * kMlpIn + 8 * g);
+    const float z = mlp_infer16(F, x);
     if (g == 0 && c < n) logits[c] = z;
   }
 }

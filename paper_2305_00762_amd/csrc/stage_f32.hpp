@@ -166,7 +166,8 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
             (float)grad6(u[-3 * SN], u[-2 * SN], u[-SN], u[SN], u[2 * SN], u[3 * SN]);
       }
       if (DETMLP) {
-        L.chi[bidx(line, k + 3, WD)] = L.chif[mlp_chi_index<C>(X ? k : l0 + line, X ? l0 + line : k)];
+        L.chi[bidx(line, k + 3, WD)] =
+            (L.chif[mlp_chi_index<C>(X ? k : l0 + line, X ? l0 + line : k)] >> DIR) & 1;
       } else {
         const double* rho = U + r;
         const double psi = detector_psi(rho[-2 * SN], rho[-SN], rho[0], rho[SN], rho[2 * SN]);

@@ -36,7 +36,7 @@ struct StageParams {
   double inv_dx, inv_dy;
   double gamma, g1inv, mu, kq;    // kq = mu / (Pr (gamma-1))
   int mode;
-  const uint8_t* chimap;          // learned-detector flag per cell [ny][nx] (detector = MLP)
+  const uint8_t* chimap;          // learned-detector flags per cell [ny][nx]: bit 0 x, bit 1 y
 };
 
 // Ghost cells by index: periodic wrap or transmissive clamp.  The offsets
@@ -84,7 +84,7 @@ struct Lds {
   unsigned char* chi;
   unsigned short* queue;
   int* qcount;
-  const unsigned char* chif;   // per-cell learned-detector flags (detector = MLP)
+  const unsigned char* chif;   // per-cell learned-detector flags (bit 0 x, bit 1 y)
 };
 
 // Index of tile cell (lx, ly), lx in [-3, TX+3), ly in [-3, TY+3), in the
@@ -169,7 +169,8 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
             grad6(u[-3 * SN], u[-2 * SN], u[-SN], u[SN], u[2 * SN], u[3 * SN]);
       }
       if (DETMLP) {
-        L.chi[bidx(line, pd, WD)] = L.chif[mlp_chi_index<C>(X ? pos : l0 + line, X ? l0 + line : pos)];
+        L.chi[bidx(line, pd, WD)] =
+            (L.chif[mlp_chi_index<C>(X ? pos : l0 + line, X ? l0 + line : pos)] >> DIR) & 1;
       } else {
         const double* rho = U + r;
         const double psi = detector_psi(rho[-2 * SN], rho[-SN], rho[0], rho[SN], rho[2 * SN]);

@@ -4,17 +4,22 @@ Everything numeric runs in the library's kernels (features, labels, forward,
 backward, Adam, the stage kernels); this module only orchestrates:
 
   training set   seeded four-quadrant Riemann runs advanced with the plain
-                 FP64 method; features and plain labels of every cell of the
-                 snapshot (default: 40 runs, seeds 1000-1039, 512^2, step 100);
-  training       balanced minibatches (half flagged, half smooth cells) drawn
-                 from numpy.random.default_rng(seed), Adam, cosine learning
-                 rate decay;
+                 FP64 method; features and directional plain labels of every
+                 cell of a snapshot, one sample per cell and direction
+                 (default: 48 runs, seeds 1000-1047, 512^2, run k snapshotted
+                 after the k-th entry, cyclically, of 1..200 steps: 1.26e7
+                 cells, 2.5e7 samples);
+  training       minibatches of 8192: half flagged samples, 30 % smooth
+                 samples within 3 cells of a flagged one (hard negatives),
+                 the rest other smooth samples, drawn from
+                 numpy.random.default_rng(seed); Adam, cosine learning-rate
+                 decay, 40000 steps;
   evaluation     fresh-seed fields (Riemann seed 5000, shear layer seed 5001,
-                 4096^2, 50 steps): the FP32-bulk + learned-detector path
-                 against the plain FP64 path -- flag mismatch (false
-                 negatives/positives of the network against the plain label
-                 on the same state), fallback rate, L1/Linf per conserved
-                 variable, throughput of both.
+                 4096^2, 50 steps): the FP32-bulk path with the plain and with
+                 the learned detector against the plain FP64 path -- flag
+                 mismatch (false negatives/positives of the network against
+                 the plain labels on the same state, both directions),
+                 fallback rate, L1/Linf per conserved variable, throughputs.
 
   python -m paper_2305_00762_amd.detector train [--out FILE] [--runs 40] ...
   python -m paper_2305_00762_amd.detector eval  [--weights FILE] [--n 4096] ...
@@ -33,7 +38,7 @@ from . import problems as PB
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "meg7_detector.npz")
-DEFAULT_MARGIN = 2.0
+DEFAULT_MARGIN = 24.0
 
 
 def _torch():
@@ -43,37 +48,65 @@ def _torch():
     return torch
 
 
-def training_set(n=512, seeds=range(1000, 1040), steps=100, log=None):
-    """Features [R*n*n][32] (bf16 bits as int16) and plain labels [R*n*n] on
-    the device, from R seeded Riemann runs at step `steps`."""
+def training_set(n=512, seeds=range(1000, 1040), steps=(100,), log=None, spread=False):
+    """Features [S*2*n*n][32] (bf16 bits as int16) and directional plain
+    labels [S*2*n*n] on the device, from seeded Riemann runs snapshotted after
+    each count in `steps` (S = runs x snapshots; per snapshot: the n*n
+    evaluations along x, then those along y).  spread: run k takes one
+    snapshot only, after steps[k % len(steps)] steps (S = runs)."""
     from .solver import Solver
     torch = _torch()
     seeds = list(seeds)
-    cells = n * n
-    feat = torch.empty((len(seeds) * cells, 32), dtype=torch.int16, device="cuda")
-    lab = torch.empty(len(seeds) * cells, dtype=torch.uint8, device="cuda")
-    for k, seed in enumerate(seeds):
+    steps = sorted(steps)
+    cells = 2 * n * n
+    total = len(seeds) * (1 if spread else len(steps)) * cells
+    feat = torch.empty((total, 32), dtype=torch.int16, device="cuda")
+    lab = torch.empty(total, dtype=torch.uint8, device="cuda")
+    k = 0
+    for r, seed in enumerate(seeds):
         S = Solver(PB.riemann(n, seed=seed))
-        for _ in range(steps):
-            S.step()
-        gbr.gbr_mlp_features(S.ctx, S.Q, feat[k * cells:], lab[k * cells:])
+        done = 0
+        for st in ([steps[r % len(steps)]] if spread else steps):
+            for _ in range(st - done):
+                S.step()
+            done = st
+            gbr.gbr_mlp_features(S.ctx, S.Q, feat[k * cells:], lab[k * cells:])
+            k += 1
         if S.check() != gbr.GBR_OK:
             raise RuntimeError(f"bad state in training run seed {seed}")
         S.close()
         if log:
-            log(f"training run {k + 1}/{len(seeds)} (seed {seed})")
+            log(f"training run seed {seed}: snapshot(s) after {done} steps")
     torch.cuda.synchronize()
     return feat, lab
 
 
-def train(feat, lab, steps=3000, batch=4096, lr=3e-3, seed=0, init_seed=0, log=None):
-    """Train a new network; returns (handle, per-step mean losses)."""
+def near_mask(labels, n, width=3):
+    """Cells within `width` cells, along their own direction, of a labelled
+    cell (per 2*n*n block: x-evaluations then y-evaluations)."""
+    lab = labels.reshape(-1, 2, n, n).astype(bool)
+    near = np.zeros_like(lab)
+    for k in range(-width, width + 1):
+        near[:, 0] |= np.roll(lab[:, 0], k, axis=2)
+        near[:, 1] |= np.roll(lab[:, 1], k, axis=1)
+    return near.reshape(-1)
+
+
+def train(feat, lab, steps=3000, batch=4096, lr=3e-3, seed=0, init_seed=0, log=None,
+          near=None, frac_near=0.25):
+    """Train a new network; returns (handle, per-step mean losses).  With a
+    `near` mask, a quarter of every batch are hard negatives (smooth cells
+    next to a flagged one)."""
     torch = _torch()
     m = gbr.gbr_mlp_create()
     w, b = PB.mlp_init_params(init_seed)
     gbr.gbr_mlp_set_params(m, w, b)
     labels = lab.cpu().numpy()
-    idx = torch.from_numpy(PB.balanced_batches(labels, batch, steps, seed)).cuda()
+    if near is None:
+        idx = PB.balanced_batches(labels, batch, steps, seed)
+    else:
+        idx = PB.hard_batches(labels, near, batch, steps, seed, frac_near)
+    idx = torch.from_numpy(idx).cuda()
     loss = torch.zeros(steps, dtype=torch.float32, device="cuda")
     for k in range(steps):
         rate = lr * 0.5 * (1.0 + math.cos(math.pi * k / steps))
@@ -100,9 +133,11 @@ def load(path=DEFAULT_WEIGHTS):
 
 def flag_rates(m, ctx, Q, n_cells, margin):
     """Network decision (with plain fallback below the margin) against the
-    plain label on the same state: (false-negative rate, false-positive rate,
-    overall mismatch, fallback rate, flagged fraction)."""
+    plain label on the same state, over both directions of every cell:
+    (false-negative rate, false-positive rate, overall mismatch, fallback
+    rate, flagged fraction)."""
     torch = _torch()
+    n_cells = 2 * n_cells
     feat = torch.empty((n_cells, 32), dtype=torch.int16, device="cuda")
     chi = torch.empty(n_cells, dtype=torch.uint8, device="cuda")
     z = torch.empty(n_cells, dtype=torch.float32, device="cuda")
@@ -183,11 +218,16 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("train")
     t.add_argument("--out", default=DEFAULT_WEIGHTS)
-    t.add_argument("--runs", type=int, default=40)
+    t.add_argument("--runs", type=int, default=48)
     t.add_argument("--n", type=int, default=512)
-    t.add_argument("--run-steps", type=int, default=100)
-    t.add_argument("--steps", type=int, default=3000)
-    t.add_argument("--batch", type=int, default=4096)
+    t.add_argument("--run-steps", default="1,2,3,4,6,8,12,16,24,32,48,64,96,128,160,200",
+                   help="comma-separated snapshot step counts")
+    t.add_argument("--steps", type=int, default=40000)
+    t.add_argument("--all-snapshots", action="store_true",
+                   help="every run takes every snapshot (default: one per run, cycling)")
+    t.add_argument("--hard", type=float, default=0.3,
+                   help="fraction of each batch drawn from hard negatives (0: balanced only)")
+    t.add_argument("--batch", type=int, default=8192)
     t.add_argument("--lr", type=float, default=3e-3)
     e = sub.add_parser("eval")
     e.add_argument("--weights", default=DEFAULT_WEIGHTS)
@@ -198,11 +238,16 @@ def main(argv=None):
     log = lambda s: print(s, flush=True)
     if a.cmd == "train":
         t0 = time.time()
-        feat, lab = training_set(a.n, range(1000, 1000 + a.runs), a.run_steps, log)
-        log(f"training set: {feat.shape[0]} cells, flagged fraction {float(lab.float().mean()):.4f}")
-        m, losses = train(feat, lab, a.steps, a.batch, a.lr, log=log)
-        save(m, a.out, {"runs": a.runs, "n": a.n, "run_steps": a.run_steps, "steps": a.steps,
-                        "batch": a.batch, "lr": a.lr, "final_loss": float(losses[-20:].mean())})
+        snaps = [int(v) for v in str(a.run_steps).split(",")]
+        feat, lab = training_set(a.n, range(1000, 1000 + a.runs), snaps, log,
+                                 spread=not a.all_snapshots)
+        log(f"training set: {feat.shape[0]} samples, flagged fraction {float(lab.float().mean()):.4f}")
+        near = near_mask(lab.cpu().numpy(), a.n) if a.hard > 0 else None
+        m, losses = train(feat, lab, a.steps, a.batch, a.lr, log=log, near=near, frac_near=a.hard)
+        save(m, a.out, {"runs": a.runs, "n": a.n, "run_steps": snaps, "spread": not a.all_snapshots,
+                        "steps": a.steps,
+                        "batch": a.batch, "lr": a.lr, "hard": a.hard,
+                        "final_loss": float(losses[-20:].mean())})
         log(f"saved {a.out} ({time.time() - t0:.1f} s)")
     else:
         m = load(a.weights)

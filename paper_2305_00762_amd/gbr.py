@@ -57,6 +57,9 @@ SIGNATURES = {
     "gbr_mlp_grad": (_i, [_vp, _vp, _vp, _vp, _i, _vp, _vp]),
     "gbr_mlp_train_step": (_i, [_vp, _vp, _vp, _vp, _i, C.c_float, _vp, _vp]),
     "gbr_set_mlp_detector": (_i, [_vp, _vp, C.c_float, _vp]),
+    "gbr_timing": (_i, [_vp, _i]),
+    "gbr_timing_read": (_i, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                             C.POINTER(C.c_uint64)]),
     "gbr_mlp_stats": (_i, [_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), _i]),
 }
 
@@ -260,3 +263,14 @@ def gbr_mlp_stats(ctx, reset=False):
     ev, fb = C.c_uint64(), C.c_uint64()
     _check(load().gbr_mlp_stats(ctx, C.byref(ev), C.byref(fb), 1 if reset else 0), "gbr_mlp_stats")
     return ev.value, fb.value
+
+
+def gbr_timing(ctx, enable=True):
+    return _check(load().gbr_timing(ctx, 1 if enable else 0), "gbr_timing")
+
+
+def gbr_timing_read(ctx):
+    """(flag-map ms, stage ms, calls) summed since timing was enabled or read."""
+    d, st, n = C.c_double(), C.c_double(), C.c_uint64()
+    _check(load().gbr_timing_read(ctx, C.byref(d), C.byref(st), C.byref(n)), "gbr_timing_read")
+    return d.value, st.value, n.value

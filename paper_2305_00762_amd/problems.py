@@ -224,3 +224,28 @@ def balanced_batches(labels, batch, nbatches, seed):
         b = neg[rng.integers(0, len(neg), batch - h)] if len(neg) else pos[rng.integers(0, len(pos), batch - h)]
         out[k] = rng.permutation(np.concatenate([a, b]))
     return out
+
+
+def hard_batches(labels, near, batch, nbatches, seed, frac_near=0.25):
+    """Index arrays for minibatches with hard negatives: half of each batch
+    from the cells labelled 1, `frac_near` of it from the cells labelled 0 that
+    lie near a labelled cell (mask `near`), the rest from the other cells
+    labelled 0 (each with replacement), from numpy.random.default_rng(seed);
+    returns int32 [nbatches][batch]."""
+    rng = np.random.default_rng(seed)
+    labels = np.asarray(labels)
+    pos = np.flatnonzero(labels)
+    hard = np.flatnonzero((labels == 0) & near)
+    easy = np.flatnonzero((labels == 0) & ~near)
+    pools = [p for p in (pos, hard, easy)]
+    h = batch // 2
+    k = int(batch * frac_near)
+    sizes = (h, k, batch - h - k)
+    out = np.empty((nbatches, batch), np.int32)
+    for b in range(nbatches):
+        parts = []
+        for pool, size in zip(pools, sizes):
+            src = pool if len(pool) else np.flatnonzero(labels == 0)
+            parts.append(src[rng.integers(0, len(src), size)])
+        out[b] = rng.permutation(np.concatenate(parts))
+    return out

@@ -1,17 +1,18 @@
 """Learned detector on the GPU vs its CPU oracle (through the C ABI).
 
-* features bit-exact (fixed float32 operation order, IEEE reciprocal, bf16
-  round-to-nearest-even on both sides) and plain labels bit-exact;
+* features of both directions bit-exact (fixed float32 operation order,
+  IEEE reciprocal, bf16 round-to-nearest-even on both sides) and the
+  directional plain labels bit-exact;
 * logits within 1e-3 (1 + |z|) (FP32 matrix-core accumulation vs FP64 on the
   same bf16 operands; a bf16 tie of h1 may round differently);
 * gradient of the mean BCE within 2e-2 per parameter block, norm-wise (bf16
   rounding points of dh2, dh1 as matrix-unit operands);
 * one Adam step matches the oracle's Adam on the GPU gradient;
-* the fused detector in the stage kernels: with every cell falling back
-  (margin = inf) the interface flags are the 6-cell buffer of the plain
-  per-cell labels, bit for bit, and the residual matches the oracle run with
-  those flags; with margin 0 the flags follow the network, and the residual
-  matches the oracle run with the GPU's flags.
+* the learned detector in the stage calls: with every evaluation falling
+  back (margin = inf) the interface flags are those of the plain method, bit
+  for bit, and the residual matches the oracle's; with margin 0 the flags
+  follow the network along each direction, and the residual matches the
+  oracle run with the GPU's flags.
 """
 import numpy as np
 import pytest
@@ -30,7 +31,7 @@ def gpu_features(P):
     ctx = gbr.gbr_init(P.nx, P.ny, P.gamma, P.mu, P.Pr)
     gbr.gbr_set_geometry(ctx, *P.geometry())
     Q = torch.from_numpy(P.Q).cuda()
-    n = P.nx * P.ny
+    n = 2 * P.nx * P.ny
     feat = torch.empty((n, 32), dtype=torch.int16, device="cuda")
     chi = torch.empty(n, dtype=torch.uint8, device="cuda")
     gbr.gbr_mlp_features(ctx, Q, feat, chi)
@@ -43,11 +44,12 @@ def gpu_features(P):
 def test_features_and_labels_bit_exact(fam):
     P = PB.make(fam, 70, seed=4, ny=50) if fam != "vortex" else PB.vortex(48)
     f, chi = gpu_features(P)
-    fo = M.features(P.Q, P.bc_x, P.bc_y, P.gamma)
-    chio, _, _ = O.cell_flags(ocfg(P), P.Q)
-    report(f"features {fam}", mismatch=int((f != fo).sum()), chi_mismatch=int((chi != chio.ravel()).sum()))
+    fo = np.concatenate([M.features(P.Q, P.bc_x, P.bc_y, P.gamma, direction=d) for d in (0, 1)])
+    _, px, py = O.cell_flags(ocfg(P), P.Q)
+    chio = np.concatenate([c.ravel() for c in M.labels(px, py)])
+    report(f"features {fam}", mismatch=int((f != fo).sum()), chi_mismatch=int((chi != chio).sum()))
     assert (f == fo).all()
-    assert (chi == chio.ravel()).all()
+    assert (chi == chio).all()
 
 
 def make_net(seed):
@@ -154,11 +156,9 @@ def test_fused_detector_all_fallback(precision, tiling):
     for P in (PB.riemann(90, seed=6, ny=70), PB.shear(64, seed=1, ny=48)):
         from paper_2305_00762_amd.solver import Solver
         R, sx, sy, ev, fb = fused(P, m, 1e30, precision)
-        chi, _, _ = O.cell_flags(ocfg(P), P.Q)
-        ex, ey = O.sigma_from_cells(chi, P.bc_x, P.bc_y)
-        assert ev > 0 and fb == ev
+        Ro, ex, ey, _ = O.residual(ocfg(P), P.Q, want_flags=True)
+        assert ev == 2 * P.nx * P.ny and fb == ev
         assert (sx == ex).all() and (sy == ey).all()
-        Ro = O.residual_sigma(ocfg(P), P.Q, ex, ey)
         tol = 1e-12 if precision == 0 else 1e-6
         assert (res_err(R, Ro, P) <= tol).all()
     gbr.gbr_mlp_destroy(m)
@@ -172,11 +172,11 @@ def test_fused_detector_network_decides(precision):
     assert fb == 0
     # the oracle network on the oracle features decides the same cells
     # wherever its logit is clear of zero
-    f = M.features(P.Q, P.bc_x, P.bc_y)
-    zo = M.forward(f, M.bf16_round(w), b).reshape(P.ny, P.nx)
-    chi_o = (zo > 0).astype(np.uint8)
-    ex, ey = O.sigma_from_cells(chi_o, P.bc_x, P.bc_y)
-    clear = np.abs(zo) > 1e-2
+    zo = [M.forward(M.features(P.Q, P.bc_x, P.bc_y, direction=d), M.bf16_round(w),
+                    b).reshape(P.ny, P.nx) for d in (0, 1)]
+    ex, ey = O.sigma_from_cells((zo[0] > 0).astype(np.uint8), (zo[1] > 0).astype(np.uint8),
+                                P.bc_x, P.bc_y)
+    clear = (np.abs(zo[0]) > 1e-2) & (np.abs(zo[1]) > 1e-2)
     report("fused margin0", flag_mismatch=int((sx != ex).sum() + (sy != ey).sum()),
            unclear_cells=int((~clear).sum()))
     if clear.all():

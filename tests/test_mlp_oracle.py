@@ -106,3 +106,34 @@ def test_features_step_closed_form():
     assert np.abs(f[:, :, 14:21]).max() <= 2e-4        # rho along y is constant
     assert np.abs(f[:, :, 7:14]).max() <= 2e-4 and np.abs(f[:, :, 21:28]).max() <= 2e-4
     assert (f[:, :, 28:] == 0).all()
+
+
+def test_features_y_direction_is_the_transposed_x_direction():
+    """Evaluating along y equals evaluating the transposed field (x <-> y,
+    u <-> v) along x, transposed back."""
+    P = PB.riemann(18, seed=3, ny=14)
+    Qt = np.stack([P.Q[0].T, P.Q[2].T, P.Q[1].T, P.Q[3].T])
+    fy = M.features(P.Q, P.bc_x, P.bc_y, direction=1).reshape(14, 18, 32)
+    fx_t = M.features(Qt, P.bc_y, P.bc_x, direction=0).reshape(18, 14, 32)
+    assert (fy == fx_t.transpose(1, 0, 2)).all()
+    fx = M.features(P.Q, P.bc_x, P.bc_y, direction=0).reshape(14, 18, 32)
+    assert (fx[:, :, :14] == fy[:, :, 14:28]).all() and (fx[:, :, 14:28] == fy[:, :, :14]).all()
+
+
+@pytest.mark.parametrize("fam,bc", [("riemann", None), ("shear", None), ("riemann", 0)])
+def test_directional_labels_reproduce_the_method_flags(fam, bc):
+    """The 6-cell buffer over the directional per-cell labels gives exactly
+    the interface flags of the oracle's residual (eq. buffer): with correct
+    labels the learned detector leaves the method unchanged."""
+    import oracle as O
+    P = PB.make(fam, 40, seed=11, ny=30)
+    if bc is not None:
+        P.bc_x = P.bc_y = bc
+    cfg = O.make_cfg(P.nx, P.ny, *P.geometry(), gamma=P.gamma, mu=P.mu, Pr=P.Pr)
+    _, sx, sy, _ = O.residual(cfg, P.Q, want_flags=True)
+    _, px, py = O.cell_flags(cfg, P.Q)
+    cx, cy = M.labels(px, py)
+    ex, ey = O.sigma_from_cells(cx, cy, P.bc_x, P.bc_y)
+    assert (ex == sx).all() and (ey == sy).all()
+    if fam == "riemann":
+        assert sx.min() == 0 and sy.min() == 0     # the case does flag

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from paper_2305_00762_amd import gbr
 from paper_2305_00762_amd import problems as PB
 from gpu_util import gpu_residual, ocfg, relerr, report, require_gpu, res_err
 
@@ -281,4 +282,23 @@ def test_positivity_fallback_trajectory():
     e = relerr(G, Q)
     report("riemann128 seed1008 25 steps", relerr=e.max())
     assert (e <= TOL).all(), e
+    S.close()
+
+
+def test_timing_hook_counts_launches():
+    """gbr_timing records one flag-map/stage event triple per stage call."""
+    torch = require_gpu()
+    from paper_2305_00762_amd.solver import Solver
+    P = PB.riemann(64, seed=2, ny=48)
+    S = Solver(P)
+    gbr.gbr_timing(S.ctx, True)
+    S.step()
+    S.step()
+    torch.cuda.synchronize()
+    det_ms, stage_ms, n = gbr.gbr_timing_read(S.ctx)
+    assert n == 6 and stage_ms > 0.0 and det_ms >= 0.0
+    assert gbr.gbr_timing_read(S.ctx)[2] == 0
+    gbr.gbr_timing(S.ctx, False)
+    S.step()
+    assert gbr.gbr_timing_read(S.ctx)[2] == 0
     S.close()
