@@ -46,6 +46,10 @@ WORKLOADS = {
     "riemann4096": ("riemann", 4096, 5000, 50,
                     "2D Euler four-quadrant Riemann problem, 4096x4096, seed 5000, transmissive, "
                     "CFL 0.2"),
+    "batch512": ("batch", 0, 0, 10,
+                 "512 independent grids, side n ~ U{64..768} (seed 0), families uniform over "
+                 "vortex / Riemann / shear layer, per-grid seed 10000 + index; one launch per "
+                 "stage over all grids, steps replayed as a HIP graph"),
 }
 
 PATHS = {
@@ -198,6 +202,120 @@ def cpu_baseline(P, seconds, max_steps=50):
     return rec, Q, steps
 
 
+def calibration_copy(mib):
+    """A plain device copy of known size (reads and writes `mib` MiB once), so
+    rocprofv3 byte counters can be scaled against it."""
+    import torch
+    if not mib:
+        return
+    src = torch.ones(mib << 17, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def batch_problems():
+    from paper_2305_00762_amd import problems as PB
+    out = []
+    for fam, n, seed in PB.batch_spec(512, seed=0):
+        out.append(PB.vortex(n, cfl=0.5) if fam == "vortex" else PB.make(fam, n, seed=seed))
+    return out
+
+
+def bench_batch(a, steps):
+    """The batched workload: FP32 bulk + FP64 state (plain detector), every
+    stage of all 512 grids in one launch, steps replayed as a HIP graph."""
+    import numpy as np
+    import torch
+    from paper_2305_00762_amd import gbr
+    from paper_2305_00762_amd.solver import BatchSolver
+    t0 = time.time()
+    calibration_copy(a.calib_copy_mb)
+    ps = batch_problems()
+    cells = sum(p.nx * p.ny for p in ps)
+    torch.cuda.set_device(0)
+    s = torch.cuda.Stream()
+    prec = gbr.GBR_PREC_FP64 if a.path == "fp64" else gbr.GBR_PREC_FP32_BULK
+    with torch.cuda.stream(s):
+        B = BatchSolver(ps, precision=prec, stream=s)
+    s.synchronize()
+    for p in ps:
+        p.Q = None if p.nx > 128 else p.Q        # keep only the initial states the oracle needs
+    form = gbr.gbr_batch_autotune(B.b, 3, s) if a.tiling == "auto" else None
+    if form is None:
+        gbr.gbr_batch_set_tiling(B.b, int(a.tiling))
+    form, tx, ty, total, wg = gbr.gbr_batch_info(B.b)
+    with torch.cuda.stream(s):
+        for _ in range(a.warmup):
+            B.step()
+    s.synchronize()
+    if B.check() != gbr.GBR_OK:
+        raise RuntimeError("device reported a bad state during warmup")
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(s):
+        start.record(s)
+        for _ in range(steps):
+            B.step()
+        stop.record(s)
+    s.synchronize()
+    total_ms = start.elapsed_time(stop)
+    status = gbr.strerror(B.check())
+    value = cells * 3 * steps / (total_ms * 1e-3)
+    # kernel durations: the same steps launched directly with per-stage events
+    gbr.gbr_batch_timing(B.b, True)
+    with torch.cuda.stream(s):
+        for _ in range(steps):
+            B.step()
+    stage_ms, launches = gbr.gbr_batch_timing_read(B.b)
+    gbr.gbr_batch_timing(B.b, False)
+    done = a.warmup + 2 * steps
+    avg_ms = stage_ms / max(launches, 1)
+    achieved = 256.0 / 3.0 * cells / (avg_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-stage updates/s", "n_gpus": 1,
+        "steps": steps, "warmup": a.warmup, "ms_per_step": total_ms / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if prec == gbr.GBR_PREC_FP32_BULK else "f64", "data": "synthetic",
+        "config": {"workload": "batch512", "description": WORKLOADS["batch512"][4],
+                   "grids": len(ps), "cells": cells, "path": "fp32" if prec else "fp64",
+                   "launch_form": form, "tile": f"{tx}x{ty}", "tiles": total,
+                   "workgroups_per_stage_launch": wg, "graph": True,
+                   "setup_s": round(time.time() - t0, 1)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": load_traffic("meg7_batch_kernel", "batch512"),
+                     "kernel": "meg7_batch_kernel", "avg_launch_us": avg_ms * 1e3,
+                     "bytes_per_cell_stage": 256.0 / 3.0},
+        "status": status,
+    }
+    # the smallest grids against the oracle after the same number of steps
+    small = sorted(range(len(ps)), key=lambda k: ps[k].nx * ps[k].ny)[:4]
+    if not a.no_cpu_baseline:
+        import oracle as O
+        errs, t_cpu, cs = [], 0.0, 0
+        st = B.states()
+        for k in small:
+            P = ps[k]
+            cfg = O.make_cfg(P.nx, P.ny, *P.geometry(), gamma=P.gamma, mu=P.mu, Pr=P.Pr)
+            Q = np.ascontiguousarray(P.Q.copy())
+            t1 = time.perf_counter()
+            for _ in range(done):
+                O.step(cfg, Q, P.cfl)
+            t_cpu += time.perf_counter() - t1
+            cs += P.nx * P.ny * 3 * done
+            d = np.abs(st[k].cpu().numpy() - Q).reshape(4, -1)
+            errs.append({"grid": k, "family": P.family, "n": P.nx, "L1": d.mean(1).tolist(),
+                         "Linf": d.max(1).tolist()})
+        out["cpu_baseline"] = {"value": cs / t_cpu, "unit": "cell-stage updates/s",
+                               "cores": O.threads(), "kind": "oracle",
+                               "sample": f"the {len(small)} smallest grids of the batch, {done} "
+                                         f"whole steps each ({cs} cell-stages) in {t_cpu:.1f} s"}
+        out["error_vs_oracle"] = {"after_steps": done, "grids": errs}
+    B.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -211,18 +329,14 @@ def main():
 
     fam, n, seed, wsteps, desc = WORKLOADS[a.workload]
     steps = a.steps if a.steps is not None else wsteps
+    if fam == "batch":
+        return bench_batch(a, steps)
     P = PB.make(fam, n, seed=seed) if fam != "vortex" else PB.vortex(n, cfl=0.5)
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     cells = P.nx * P.ny
 
-    if a.calib_copy_mb:
-        # a plain copy of known size: reads and writes calib_copy_mb MiB once
-        src = torch.ones(a.calib_copy_mb << 17, dtype=torch.float64, device="cuda:0")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    calibration_copy(a.calib_copy_mb)
     head = Path(P, a.path, stream, a.tiling, a.weights, a.margin)
     total_ms, (det_ms, stage_ms, launches) = head.run(a.warmup, steps, timing=True)
     value = cells * 3 * steps / (total_ms * 1e-3)

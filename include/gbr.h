@@ -204,6 +204,70 @@ int gbr_mlp_stats(gbr_ctx *ctx, uint64_t *evaluated, uint64_t *fallbacks, int re
  * clear that record. */
 int gbr_check(gbr_ctx *ctx, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batched grids: many independent grids advanced together, each stage of
+ * every grid in ONE launch over the tiles of all grids (persistent or one
+ * workgroup per tile, see below), with a per-grid time step (Sec. 2.5) and the
+ * whole step [dt, stage 1, stage 2, stage 3] (eq. rk) replayed as a captured
+ * HIP graph.  A grid of the batch runs the same tile function as the
+ * single-grid calls with the same tile shape and precision (results agree to
+ * rounding: the compiler may contract multiply-adds differently in the two
+ * kernels).  Grids with mu > 0 take the viscous form of the tile function.
+ *
+ * gbr_batch_init: nprob grids; per grid p: nx[p], ny[p] (>= 12),
+ * geom[4p..4p+3] = x0, x1, y0, y1, bc[2p], bc[2p+1] = boundary types in x and
+ * y, gamma[p] > 1, mu[p] >= 0, Pr[p] > 0, cfl[p] > 0 (host arrays, copied);
+ * precision GBR_PREC_FP64 or GBR_PREC_FP32_BULK.  Allocates the batch's
+ * device tables (per grid: about 200 bytes plus 64 doubles of time-step
+ * partials).  The detector is the plain one. */
+typedef struct gbr_batch gbr_batch;
+int gbr_batch_init(int nprob, const int *nx, const int *ny, const double *geom, const int *bc,
+                   const double *gamma, const double *mu, const double *Pr, const double *cfl,
+                   int precision, gbr_batch **out);
+int gbr_batch_destroy(gbr_batch *b);
+
+/* Register the grids' state arrays: three device arrays per grid (host arrays
+ * X, Y, Z of nprob device pointers, each a SoA [4][ny][nx] FP64 array, all
+ * distinct).  The caller owns them and keeps them alive while the batch
+ * steps.  The state is read from X first; steps rotate the roles, and
+ * gbr_batch_current tells which set (0 = X, 1 = Y, 2 = Z) holds the state.
+ * Registering again resets that to X and drops captured graphs. */
+int gbr_batch_set_arrays(gbr_batch *b, double *const *X, double *const *Y, double *const *Z);
+int gbr_batch_current(gbr_batch *b, int *which);
+
+/* One SSP-RK3 step of every grid, enqueued on `stream`.  With graphs enabled
+ * (the default) and a non-NULL stream, the first step from each of the three
+ * array roles is captured into a graph and later steps replay it; with a
+ * NULL stream or graphs disabled the kernels are launched directly. */
+int gbr_batch_step(gbr_batch *b, void *stream);
+int gbr_batch_use_graph(gbr_batch *b, int enable);
+
+/* Launch forms: 0 = 31x15 and 1 = 15x15 cells per workgroup with a
+ * persistent tile loop (as many workgroups as fit on the chip at once), 2 =
+ * 31x15 and 3 = 15x15 with one workgroup per tile.  gbr_batch_autotune times
+ * the first stage of a step from the current state for each form (`reps`
+ * launches, writing into the next array set, which a step overwrites anyway)
+ * and keeps the fastest.  gbr_batch_info reports the form, its tile shape,
+ * the tile count and the number of workgroups of a stage launch. */
+int gbr_batch_tiling_count(void);
+int gbr_batch_set_tiling(gbr_batch *b, int variant);
+int gbr_batch_autotune(gbr_batch *b, int reps, void *stream);
+int gbr_batch_info(gbr_batch *b, int *tiling, int *tile_x, int *tile_y, int *total_tiles,
+                   int *workgroups);
+
+/* Kernel timing of batched steps: with timing enabled, gbr_batch_step
+ * launches its kernels directly (no graph) and records a HIP event pair on
+ * its stream around every stage launch; gbr_batch_timing_read waits for the
+ * last one and returns the summed stage-launch durations (milliseconds) and
+ * the number of stage launches since timing was enabled or last read. */
+int gbr_batch_timing(gbr_batch *b, int enable);
+int gbr_batch_timing_read(gbr_batch *b, double *stage_ms, uint64_t *launches);
+
+/* Per-grid time steps of the last step (host dt[nprob]; synchronises
+ * `stream`), and the device status as gbr_check reports it. */
+int gbr_batch_get_dt(gbr_batch *b, double *dt, void *stream);
+int gbr_batch_check(gbr_batch *b, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -37,6 +37,23 @@ __device__ __forceinline__ double block_min(double v, double* red) {
   return r;
 }
 
+// Convective and viscous limits of cell s folded into (conv, visc).
+__device__ __forceinline__ void dt_cell(const double* __restrict__ Q, size_t n, size_t s,
+                                        double gamma, double mu, double dx, double dy,
+                                        double& conv, double& visc, bool& bad) {
+#pragma clang fp contract(off)
+  const double rho = Q[s];
+  const double u = Q[n + s] / rho, v = Q[2 * n + s] / rho;
+  const double p = (gamma - 1.0) * (Q[3 * n + s] - rho * (u * u + v * v) / 2.0);
+  const double c = sqrt(gamma * p / rho);
+  if (!(rho > 0.0) || !(p > 0.0) || !isfinite(c) || !isfinite(u) || !isfinite(v)) bad = true;
+  conv = fmin(conv, fmin(dx / (fabs(u) + c), dy / (fabs(v) + c)));
+  if (mu > 0.0) {
+    const double nu = mu / rho;
+    visc = fmin(visc, fmin(dx * dx / nu, dy * dy / nu));
+  }
+}
+
 __global__ __launch_bounds__(kDtThreads) void dt_reduce_kernel(DtParams P) {
 #pragma clang fp contract(off)
   __shared__ double red[kDtThreads / 64];
@@ -45,16 +62,7 @@ __global__ __launch_bounds__(kDtThreads) void dt_reduce_kernel(DtParams P) {
   bool bad = false;
   for (size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
        s += (size_t)gridDim.x * blockDim.x) {
-    const double rho = P.Q[s];
-    const double u = P.Q[n + s] / rho, v = P.Q[2 * n + s] / rho;
-    const double p = (P.gamma - 1.0) * (P.Q[3 * n + s] - rho * (u * u + v * v) / 2.0);
-    const double c = sqrt(P.gamma * p / rho);
-    if (!(rho > 0.0) || !(p > 0.0) || !isfinite(c) || !isfinite(u) || !isfinite(v)) bad = true;
-    conv = fmin(conv, fmin(P.dx / (fabs(u) + c), P.dy / (fabs(v) + c)));
-    if (P.mu > 0.0) {
-      const double nu = P.mu / rho;
-      visc = fmin(visc, fmin(P.dx * P.dx / nu, P.dy * P.dy / nu));
-    }
+    dt_cell(P.Q, n, s, P.gamma, P.mu, P.dx, P.dy, conv, visc, bad);
   }
   if (bad) atomicOr(P.status, 1u);
   conv = block_min(conv, red);

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../../include/gbr.h"
+#include "batch_kernel.hpp"
 #include "dt_kernel.hpp"
 #include "mlp_kernels.hpp"
 #include "stage_f32.hpp"
@@ -74,6 +75,43 @@ const TileVariant kVariants[] = {
      "30x15"},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+// Forms of the batched kernel: tile shape (inviscid and viscous forms of one
+// shape) x persistent tile loop or one workgroup per tile.
+template <class CI, class CV, bool F32, int MW, bool LOOP>
+void launch_batch(const BatchParams& B, int grid, hipStream_t s) {
+  static_assert(BatchCfg<CI, CV, F32, MW>::LDS_BYTES <= 160 * 1024, "LDS per workgroup");
+  hipLaunchKernelGGL((meg7_batch_kernel<CI, CV, F32, MW, LOOP>), dim3(grid), dim3(CI::NT), 0, s, B);
+}
+template <class CI, class CV, bool F32, int MW, bool LOOP>
+int batch_blocks_per_cu() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, meg7_batch_kernel<CI, CV, F32, MW, LOOP>,
+                                                    CI::NT, 0) != hipSuccess)
+    return 0;
+  return n;
+}
+using BatchLaunchFn = void (*)(const BatchParams&, int, hipStream_t);
+struct BatchVariant {
+  int tx, ty, loop;
+  BatchLaunchFn fn[2];   // [FP64, FP32 bulk]
+  int (*occ[2])();
+  const char* name;
+};
+#define GBR_BATCH_VARIANT(TX, TY, CI, CV, MW64, MW32, LOOP, NAME)                     \
+  {TX, TY, LOOP,                                                                      \
+   {launch_batch<CI, CV, false, MW64, LOOP>, launch_batch<CI, CV, true, MW32, LOOP>}, \
+   {batch_blocks_per_cu<CI, CV, false, MW64, LOOP>,                                   \
+    batch_blocks_per_cu<CI, CV, true, MW32, LOOP>},                                   \
+   NAME}
+const BatchVariant kBatchVariants[] = {
+    GBR_BATCH_VARIANT(31, 15, E31, V31, 2, 2, true, "31x15 persistent"),
+    GBR_BATCH_VARIANT(15, 15, E15, V15, 2, 2, true, "15x15 persistent"),
+    GBR_BATCH_VARIANT(31, 15, E31, V31, 2, 2, false, "31x15 one tile per workgroup"),
+    GBR_BATCH_VARIANT(15, 15, E15, V15, 2, 2, false, "15x15 one tile per workgroup"),
+};
+#undef GBR_BATCH_VARIANT
+constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
 
 }  // namespace
 
@@ -563,6 +601,357 @@ int gbr_mlp_stats(gbr_ctx* c, uint64_t* evaluated, uint64_t* fallbacks, int rese
       return GBR_EDEVICE;
   }
   return GBR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched grids.
+struct gbr_batch {
+  int nprob, device, precision;
+  std::vector<BatchProb> hprob;     // host copy (pointers filled by set_arrays)
+  BatchProb* d_prob;
+  StageParams* d_tab;               // [9][nprob]: (array roles of the step, stage) -> parameters
+  int* d_tile_start;                // [nprob + 1]
+  double* d_dt;                     // [nprob]
+  double* d_partial;                // [nprob][2][kBatchDtBlocks]
+  unsigned* d_status;               // [4]
+  int tiling, total, grid, cus;
+  int arrays, cur;                  // arrays registered; index of the set holding the state
+  int use_graph;
+  hipGraphExec_t exec[3];
+  hipGraph_t graph[3];
+  int timing;                       // gbr_batch_timing: events around stage launches
+  std::vector<hipEvent_t> ev;
+  size_t ev_used;
+};
+
+static void batch_drop_graphs(gbr_batch* b) {
+  for (int k = 0; k < 3; ++k) {
+    if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
+    if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
+    b->exec[k] = nullptr;
+    b->graph[k] = nullptr;
+  }
+}
+
+// Tile table and launch size for the current tile shape.
+static int batch_layout(gbr_batch* b) {
+  const BatchVariant& v = kBatchVariants[b->tiling];
+  std::vector<int> ts(b->nprob + 1);
+  long long t = 0;
+  for (int p = 0; p < b->nprob; ++p) {
+    BatchProb& g = b->hprob[p];
+    g.tiles_x = (g.nx + v.tx - 1) / v.tx;
+    ts[p] = (int)t;
+    t += (long long)g.tiles_x * ((g.ny + v.ty - 1) / v.ty);
+    if (t > 0x7fffffffll) return GBR_EINVAL;
+  }
+  ts[b->nprob] = (int)t;
+  b->total = (int)t;
+  const long long need = (t + 7) / 8 * 8;   // one workgroup per tile (rounded to 8)
+  if (v.loop) {
+    const int per_cu = v.occ[b->precision == GBR_PREC_FP32_BULK ? 1 : 0]();
+    if (per_cu < 1) return GBR_EDEVICE;
+    long long g = (long long)per_cu * b->cus;
+    g = g / 8 * 8;
+    if (g < 8) g = 8;
+    b->grid = (int)(g < need ? g : need);
+  } else {
+    b->grid = (int)need;
+  }
+  // stage parameter tables: step from set x, stage st (1..3) -> table 3 x + st - 1
+  std::vector<StageParams> tab((size_t)9 * b->nprob);
+  for (int x = 0; x < 3; ++x) {
+    const int y = (x + 1) % 3, z = (x + 2) % 3;
+    const int roles[3][2] = {{x, y}, {y, z}, {z, y}};   // (Q^(k), Q^(k+1)) of stages 1..3
+    for (int st = 0; st < 3; ++st)
+      for (int p = 0; p < b->nprob; ++p) {
+        const BatchProb& g = b->hprob[p];
+        StageParams& P = tab[(size_t)(3 * x + st) * b->nprob + p];
+        P = StageParams{};
+        P.Qn = g.buf[x];
+        P.Qk = g.buf[roles[st][0]];
+        P.out = g.buf[roles[st][1]];
+        P.dt = b->d_dt + p;
+        P.status = b->d_status;
+        P.nx = g.nx; P.ny = g.ny; P.bcx = g.bcx; P.bcy = g.bcy;
+        P.tiles_x = g.tiles_x;
+        P.ntiles = g.tiles_x * ((g.ny + v.ty - 1) / v.ty);
+        P.inv_dx = g.inv_dx; P.inv_dy = g.inv_dy;
+        P.gamma = g.gamma; P.g1inv = g.g1inv; P.mu = g.mu; P.kq = g.kq;
+        P.mode = MODE_STAGE1 + st;
+      }
+  }
+  if (hipMemcpy(b->d_tile_start, ts.data(), sizeof(int) * (b->nprob + 1), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(b->d_prob, b->hprob.data(), sizeof(BatchProb) * b->nprob,
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_tab, tab.data(), sizeof(StageParams) * tab.size(), hipMemcpyHostToDevice) !=
+          hipSuccess)
+    return GBR_EDEVICE;
+  batch_drop_graphs(b);
+  return GBR_OK;
+}
+
+static void batch_launch_dt(gbr_batch* b, int qn, hipStream_t s) {
+  hipLaunchKernelGGL(batch_dt_reduce_kernel, dim3(b->nprob * kBatchDtBlocks), dim3(kDtThreads), 0, s,
+                     b->d_prob, qn, b->d_partial, b->d_status);
+  hipLaunchKernelGGL(batch_dt_finish_kernel, dim3((b->nprob + 255) / 256), dim3(256), 0, s,
+                     b->d_prob, b->nprob, b->d_partial, b->d_dt, b->d_status);
+}
+
+// Stage st (1..3) of a step from array set x.
+static void batch_launch_stage(gbr_batch* b, int x, int st, hipStream_t s) {
+  BatchParams B{};
+  B.tab = b->d_tab + (size_t)(3 * x + st - 1) * b->nprob;
+  B.tile_start = b->d_tile_start;
+  B.nprob = b->nprob;
+  B.total = b->total;
+  kBatchVariants[b->tiling].fn[b->precision == GBR_PREC_FP32_BULK ? 1 : 0](B, b->grid, s);
+}
+
+// One SSP-RK3 step from array set x: stages into y, z, y (y = x+1, z = x+2
+// mod 3); the state ends in y.
+static int batch_enqueue_step(gbr_batch* b, int x, hipStream_t s) {
+  batch_launch_dt(b, x, s);
+  for (int st = 1; st <= 3; ++st) {
+    hipEvent_t* e = nullptr;
+    if (b->timing) {
+      if (b->ev_used + 2 > b->ev.size()) {
+        for (int k = 0; k < 2 * 64; ++k) {
+          hipEvent_t h;
+          if (hipEventCreate(&h) != hipSuccess) return GBR_EDEVICE;
+          b->ev.push_back(h);
+        }
+      }
+      e = &b->ev[b->ev_used];
+      b->ev_used += 2;
+      if (hipEventRecord(e[0], s) != hipSuccess) return GBR_EDEVICE;
+    }
+    batch_launch_stage(b, x, st, s);
+    if (e && hipEventRecord(e[1], s) != hipSuccess) return GBR_EDEVICE;
+  }
+  return GBR_OK;
+}
+
+int gbr_batch_init(int nprob, const int* nx, const int* ny, const double* geom, const int* bc,
+                   const double* gamma, const double* mu, const double* Pr, const double* cfl,
+                   int precision, gbr_batch** out) {
+  if (!out || nprob < 1 || !nx || !ny || !geom || !bc || !gamma || !mu || !Pr || !cfl)
+    return GBR_EINVAL;
+  if (precision != GBR_PREC_FP64 && precision != GBR_PREC_FP32_BULK) return GBR_EINVAL;
+  *out = nullptr;
+  for (int p = 0; p < nprob; ++p) {
+    if (nx[p] < 12 || ny[p] < 12 || !(gamma[p] > 1.0) || !(mu[p] >= 0.0) || !(Pr[p] > 0.0) ||
+        !(cfl[p] > 0.0) || !(geom[4 * p + 1] > geom[4 * p]) || !(geom[4 * p + 3] > geom[4 * p + 2]))
+      return GBR_EINVAL;
+    for (int d = 0; d < 2; ++d)
+      if (bc[2 * p + d] != GBR_BC_PERIODIC && bc[2 * p + d] != GBR_BC_TRANSMISSIVE) return GBR_EINVAL;
+  }
+  gbr_batch* b = new (std::nothrow) gbr_batch();
+  if (!b) return GBR_ENOMEM;
+  b->nprob = nprob;
+  b->precision = precision;
+  b->use_graph = 1;
+  if (hipGetDevice(&b->device) != hipSuccess ||
+      hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->device) !=
+          hipSuccess) {
+    delete b;
+    return GBR_EDEVICE;
+  }
+  b->hprob.resize(nprob);
+  for (int p = 0; p < nprob; ++p) {
+    BatchProb& g = b->hprob[p];
+    g = BatchProb{};
+    g.nx = nx[p]; g.ny = ny[p]; g.bcx = bc[2 * p]; g.bcy = bc[2 * p + 1];
+    g.dx = (geom[4 * p + 1] - geom[4 * p]) / nx[p];
+    g.dy = (geom[4 * p + 3] - geom[4 * p + 2]) / ny[p];
+    g.inv_dx = (double)nx[p] / (geom[4 * p + 1] - geom[4 * p]);
+    g.inv_dy = (double)ny[p] / (geom[4 * p + 3] - geom[4 * p + 2]);
+    g.gamma = gamma[p]; g.g1inv = 1.0 / (gamma[p] - 1.0); g.mu = mu[p];
+    g.kq = mu[p] / (Pr[p] * (gamma[p] - 1.0));
+    g.cfl = cfl[p];
+  }
+  if (hipMalloc(&b->d_prob, sizeof(BatchProb) * nprob) != hipSuccess ||
+      hipMalloc(&b->d_tab, sizeof(StageParams) * 9 * nprob) != hipSuccess ||
+      hipMalloc(&b->d_tile_start, sizeof(int) * (nprob + 1)) != hipSuccess ||
+      hipMalloc(&b->d_dt, sizeof(double) * nprob) != hipSuccess ||
+      hipMalloc(&b->d_partial, sizeof(double) * 2 * kBatchDtBlocks * nprob) != hipSuccess ||
+      hipMalloc(&b->d_status, 4 * sizeof(unsigned)) != hipSuccess ||
+      hipMemset(b->d_status, 0, 4 * sizeof(unsigned)) != hipSuccess ||
+      hipMemset(b->d_dt, 0, sizeof(double) * nprob) != hipSuccess) {
+    gbr_batch_destroy(b);
+    return GBR_ENOMEM;
+  }
+  const int rc = batch_layout(b);
+  if (rc != GBR_OK) {
+    gbr_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return GBR_OK;
+}
+
+int gbr_batch_destroy(gbr_batch* b) {
+  if (!b) return GBR_OK;
+  (void)hipDeviceSynchronize();
+  batch_drop_graphs(b);
+  for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+  if (b->d_prob) (void)hipFree(b->d_prob);
+  if (b->d_tab) (void)hipFree(b->d_tab);
+  if (b->d_tile_start) (void)hipFree(b->d_tile_start);
+  if (b->d_dt) (void)hipFree(b->d_dt);
+  if (b->d_partial) (void)hipFree(b->d_partial);
+  if (b->d_status) (void)hipFree(b->d_status);
+  delete b;
+  return GBR_OK;
+}
+
+int gbr_batch_set_arrays(gbr_batch* b, double* const* X, double* const* Y, double* const* Z) {
+  if (!b || !X || !Y || !Z) return GBR_EINVAL;
+  for (int p = 0; p < b->nprob; ++p) {
+    if (!X[p] || !Y[p] || !Z[p] || X[p] == Y[p] || Y[p] == Z[p] || X[p] == Z[p]) return GBR_EINVAL;
+    b->hprob[p].buf[0] = X[p];
+    b->hprob[p].buf[1] = Y[p];
+    b->hprob[p].buf[2] = Z[p];
+  }
+  const int rc = batch_layout(b);
+  if (rc != GBR_OK) return rc;
+  b->arrays = 1;
+  b->cur = 0;
+  return GBR_OK;
+}
+
+int gbr_batch_tiling_count(void) { return kNumBatchVariants; }
+
+int gbr_batch_set_tiling(gbr_batch* b, int variant) {
+  if (!b || variant < 0 || variant >= kNumBatchVariants) return GBR_EINVAL;
+  b->tiling = variant;
+  return batch_layout(b);
+}
+
+int gbr_batch_info(gbr_batch* b, int* tiling, int* tile_x, int* tile_y, int* total_tiles,
+                   int* workgroups) {
+  if (!b) return GBR_EINVAL;
+  if (tiling) *tiling = b->tiling;
+  if (tile_x) *tile_x = kBatchVariants[b->tiling].tx;
+  if (tile_y) *tile_y = kBatchVariants[b->tiling].ty;
+  if (total_tiles) *total_tiles = b->total;
+  if (workgroups) *workgroups = b->grid;
+  return GBR_OK;
+}
+
+int gbr_batch_use_graph(gbr_batch* b, int enable) {
+  if (!b) return GBR_EINVAL;
+  b->use_graph = enable ? 1 : 0;
+  return GBR_OK;
+}
+
+int gbr_batch_step(gbr_batch* b, void* stream) {
+  if (!b || !b->arrays) return GBR_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int x = b->cur;
+  if (b->use_graph && s && !b->timing) {
+    if (!b->exec[x]) {
+      if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return GBR_EDEVICE;
+      const int rc = batch_enqueue_step(b, x, s);
+      if (hipStreamEndCapture(s, &b->graph[x]) != hipSuccess || rc != GBR_OK) return GBR_EDEVICE;
+      if (hipGraphInstantiate(&b->exec[x], b->graph[x], nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(b->graph[x]);
+        b->graph[x] = nullptr;
+        b->exec[x] = nullptr;
+        return GBR_EDEVICE;
+      }
+    }
+    if (hipGraphLaunch(b->exec[x], s) != hipSuccess) return GBR_EDEVICE;
+  } else {
+    const int rc = batch_enqueue_step(b, x, s);
+    if (rc != GBR_OK) return rc;
+    if (hipGetLastError() != hipSuccess) return GBR_EDEVICE;
+  }
+  b->cur = (x + 1) % 3;
+  return GBR_OK;
+}
+
+int gbr_batch_timing(gbr_batch* b, int enable) {
+  if (!b) return GBR_EINVAL;
+  b->timing = enable ? 1 : 0;
+  b->ev_used = 0;
+  return GBR_OK;
+}
+
+int gbr_batch_timing_read(gbr_batch* b, double* stage_ms, uint64_t* launches) {
+  if (!b) return GBR_EINVAL;
+  double t = 0.0;
+  for (size_t k = 0; k + 2 <= b->ev_used; k += 2) {
+    float ms = 0.f;
+    if (hipEventSynchronize(b->ev[k + 1]) != hipSuccess ||
+        hipEventElapsedTime(&ms, b->ev[k], b->ev[k + 1]) != hipSuccess)
+      return GBR_EDEVICE;
+    t += ms;
+  }
+  if (stage_ms) *stage_ms = t;
+  if (launches) *launches = b->ev_used / 2;
+  b->ev_used = 0;
+  return GBR_OK;
+}
+
+int gbr_batch_current(gbr_batch* b, int* which) {
+  if (!b || !which) return GBR_EINVAL;
+  *which = b->cur;
+  return GBR_OK;
+}
+
+int gbr_batch_get_dt(gbr_batch* b, double* dt, void* stream) {
+  if (!b || !dt) return GBR_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(dt, b->d_dt, sizeof(double) * b->nprob, hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return GBR_EDEVICE;
+  return GBR_OK;
+}
+
+int gbr_batch_check(gbr_batch* b, void* stream) {
+  if (!b) return GBR_EINVAL;
+  unsigned h[4] = {0, 0, 0, 0};
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess ||
+      hipMemcpy(h, b->d_status, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemset(b->d_status, 0, sizeof(h)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+    return GBR_EDEVICE;
+  return (h[0] | h[1] | h[2] | h[3]) ? GBR_ESTATE : GBR_OK;
+}
+
+int gbr_batch_autotune(gbr_batch* b, int reps, void* stream) {
+  if (!b || !b->arrays || reps < 1) return GBR_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return GBR_EDEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return GBR_EDEVICE;
+  }
+  const int saved = b->tiling, x = b->cur;
+  int best = saved, rc = GBR_OK;
+  float best_ms = 1e30f;
+  for (int v = 0; v < kNumBatchVariants && rc == GBR_OK; ++v) {
+    b->tiling = v;
+    if ((rc = batch_layout(b)) != GBR_OK) break;
+    // first stage of a step from the current state into a scratch set
+    batch_launch_dt(b, x, s);
+    batch_launch_stage(b, x, 1, s);
+    (void)hipEventRecord(e0, s);   // (stage launches here record no timing events)
+    for (int r = 0; r < reps; ++r) batch_launch_stage(b, x, 1, s);
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) { rc = GBR_EDEVICE; break; }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best_ms) { best_ms = ms; best = v; }
+  }
+  b->tiling = best;
+  const int rc2 = batch_layout(b);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc != GBR_OK ? rc : rc2;
 }
 
 }  // extern "C"

@@ -466,6 +466,28 @@ __device__ __forceinline__ void stage_store(const StageParams& P, const double (
   }
 }
 
+// One tile of the stage: load, both sweeps, store.  The LDS arrays are
+// passed in so that a kernel can run several tile shapes from one set of
+// arrays sized for the largest (the batched kernel).
+template <class C, bool DETMLP>
+__device__ __forceinline__ void stage_tile(const StageParams& P, int tx0, int ty0, double* sU,
+                                           double* sPh, unsigned char* sChi,
+                                           unsigned short* sQueue, int* sQCount,
+                                           unsigned char* sChiF) {
+  stage_load<C>(P, sU, tx0, ty0);
+  if (DETMLP) load_chimap<C>(P, sChiF, tx0, ty0);
+  __syncthreads();
+  const Lds L{sU, sPh, sChi, sQueue, sQCount, sChiF};
+  double res[C::CPT][4];
+#pragma unroll
+  for (int k = 0; k < C::CPT; ++k)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) res[k][m] = 0.0;
+  for (int l0 = 0; l0 < C::TY; l0 += C::SX) sweep<C, 0, DETMLP>(P, L, l0, tx0, ty0, res);
+  for (int l0 = 0; l0 < C::TX; l0 += C::SY) sweep<C, 1, DETMLP>(P, L, l0, tx0, ty0, res);
+  stage_store<C>(P, res, tx0, ty0);
+}
+
 template <class C, bool DETMLP>
 __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel(StageParams P) {
   __shared__ double sU[C::NF * C::RS];
@@ -476,18 +498,7 @@ __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel(StageParams 
   __shared__ int sQCount;
   int tx0, ty0;
   if (!tile_origin(P, C::TX, C::TY, tx0, ty0)) return;
-  stage_load<C>(P, sU, tx0, ty0);
-  if (DETMLP) load_chimap<C>(P, sChiF, tx0, ty0);
-  __syncthreads();
-  const Lds L{sU, sPh, sChi, sQueue, &sQCount, sChiF};
-  double res[C::CPT][4];
-#pragma unroll
-  for (int k = 0; k < C::CPT; ++k)
-#pragma unroll
-    for (int m = 0; m < 4; ++m) res[k][m] = 0.0;
-  for (int l0 = 0; l0 < C::TY; l0 += C::SX) sweep<C, 0, DETMLP>(P, L, l0, tx0, ty0, res);
-  for (int l0 = 0; l0 < C::TX; l0 += C::SY) sweep<C, 1, DETMLP>(P, L, l0, tx0, ty0, res);
-  stage_store<C>(P, res, tx0, ty0);
+  stage_tile<C, DETMLP>(P, tx0, ty0, sU, sPh, sChi, sQueue, &sQCount, sChiF);
 }
 
 }  // namespace gbr

@@ -57,6 +57,20 @@ SIGNATURES = {
     "gbr_mlp_grad": (_i, [_vp, _vp, _vp, _vp, _i, _vp, _vp]),
     "gbr_mlp_train_step": (_i, [_vp, _vp, _vp, _vp, _i, C.c_float, _vp, _vp]),
     "gbr_set_mlp_detector": (_i, [_vp, _vp, C.c_float, _vp]),
+    "gbr_batch_init": (_i, [_i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, C.POINTER(_vp)]),
+    "gbr_batch_destroy": (_i, [_vp]),
+    "gbr_batch_set_arrays": (_i, [_vp, _vp, _vp, _vp]),
+    "gbr_batch_current": (_i, [_vp, C.POINTER(_i)]),
+    "gbr_batch_step": (_i, [_vp, _vp]),
+    "gbr_batch_use_graph": (_i, [_vp, _i]),
+    "gbr_batch_tiling_count": (_i, []),
+    "gbr_batch_set_tiling": (_i, [_vp, _i]),
+    "gbr_batch_autotune": (_i, [_vp, _i, _vp]),
+    "gbr_batch_info": (_i, [_vp] + [C.POINTER(_i)] * 5),
+    "gbr_batch_get_dt": (_i, [_vp, _vp, _vp]),
+    "gbr_batch_check": (_i, [_vp, _vp]),
+    "gbr_batch_timing": (_i, [_vp, _i]),
+    "gbr_batch_timing_read": (_i, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
     "gbr_timing": (_i, [_vp, _i]),
     "gbr_timing_read": (_i, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                              C.POINTER(C.c_uint64)]),
@@ -274,3 +288,87 @@ def gbr_timing_read(ctx):
     d, st, n = C.c_double(), C.c_double(), C.c_uint64()
     _check(load().gbr_timing_read(ctx, C.byref(d), C.byref(st), C.byref(n)), "gbr_timing_read")
     return d.value, st.value, n.value
+
+
+# ---------------------------------------------------------------- batches ---
+def gbr_batch_init(nx, ny, geom, bc, gamma, mu, Pr, cfl, precision):
+    """nx, ny, gamma, mu, Pr, cfl: sequences of length nprob; geom: [nprob][4]
+    (x0, x1, y0, y1); bc: [nprob][2] (x, y)."""
+    import numpy as np
+    n = len(nx)
+    a_i = lambda v: np.ascontiguousarray(v, dtype=np.int32).reshape(-1)
+    a_d = lambda v: np.ascontiguousarray(v, dtype=np.float64).reshape(-1)
+    arrs = [a_i(nx), a_i(ny), a_d(geom), a_i(bc), a_d(gamma), a_d(mu), a_d(Pr), a_d(cfl)]
+    if any(len(x) != m * n for x, m in zip(arrs, (1, 1, 4, 2, 1, 1, 1, 1))):
+        raise ValueError("gbr_batch_init: array lengths do not match nprob")
+    h = C.c_void_p()
+    _check(load().gbr_batch_init(n, *[x.ctypes.data for x in arrs], precision, C.byref(h)),
+           "gbr_batch_init")
+    return h.value
+
+
+def gbr_batch_destroy(b):
+    return _check(load().gbr_batch_destroy(b), "gbr_batch_destroy")
+
+
+def gbr_batch_set_arrays(b, X, Y, Z):
+    """X, Y, Z: sequences of device arrays (tensors or addresses), one per grid."""
+    tabs = [(C.c_void_p * len(v))(*[_addr(t) for t in v]) for v in (X, Y, Z)]
+    return _check(load().gbr_batch_set_arrays(b, *[C.cast(t, C.c_void_p) for t in tabs]),
+                  "gbr_batch_set_arrays")
+
+
+def gbr_batch_current(b):
+    w = C.c_int()
+    _check(load().gbr_batch_current(b, C.byref(w)), "gbr_batch_current")
+    return w.value
+
+
+def gbr_batch_step(b, stream=None):
+    return _check(load().gbr_batch_step(b, _stream(stream)), "gbr_batch_step")
+
+
+def gbr_batch_use_graph(b, enable=True):
+    return _check(load().gbr_batch_use_graph(b, 1 if enable else 0), "gbr_batch_use_graph")
+
+
+def gbr_batch_tiling_count():
+    return load().gbr_batch_tiling_count()
+
+
+def gbr_batch_set_tiling(b, variant):
+    return _check(load().gbr_batch_set_tiling(b, variant), "gbr_batch_set_tiling")
+
+
+def gbr_batch_autotune(b, reps=3, stream=None):
+    _check(load().gbr_batch_autotune(b, reps, _stream(stream)), "gbr_batch_autotune")
+    return gbr_batch_info(b)
+
+
+def gbr_batch_info(b):
+    """(form, tile_x, tile_y, total_tiles, workgroups)."""
+    v = [C.c_int() for _ in range(5)]
+    _check(load().gbr_batch_info(b, *[C.byref(x) for x in v]), "gbr_batch_info")
+    return tuple(x.value for x in v)
+
+
+def gbr_batch_get_dt(b, nprob, stream=None):
+    import numpy as np
+    out = np.zeros(nprob, np.float64)
+    _check(load().gbr_batch_get_dt(b, out.ctypes.data, _stream(stream)), "gbr_batch_get_dt")
+    return out
+
+
+def gbr_batch_check(b, stream=None):
+    return load().gbr_batch_check(b, _stream(stream))
+
+
+def gbr_batch_timing(b, enable=True):
+    return _check(load().gbr_batch_timing(b, 1 if enable else 0), "gbr_batch_timing")
+
+
+def gbr_batch_timing_read(b):
+    """(summed stage-launch ms, stage launches) since timing was enabled or read."""
+    t, n = C.c_double(), C.c_uint64()
+    _check(load().gbr_batch_timing_read(b, C.byref(t), C.byref(n)), "gbr_batch_timing_read")
+    return t.value, n.value

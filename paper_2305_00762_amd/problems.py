@@ -188,15 +188,29 @@ def make(family, n, seed=0, **kw):
     raise ValueError(family)
 
 
+# Four-quadrant draws (seeds) of the batched workload whose corner expansion
+# drives the density to zero within 40 steps: the method has no positivity
+# limiter and produces NaN there, in the CPU oracle as on the GPU.  The batch
+# replaces each by seed + 100000; tests/test_inputs.py re-derives the set.
+BATCH_VACUUM_SEEDS = frozenset({10092, 10205})
+
+
 def batch_spec(nprob=512, seed=0, nmin=64, nmax=768):
     """Sizes and families of the batched workload: side n ~ U{nmin..nmax}
     (square grids), family uniform over {vortex, riemann, shear}, per-problem
-    seed 10000 + index."""
+    seed 10000 + index (a Riemann seed in BATCH_VACUUM_SEEDS takes
+    seed + 100000 instead)."""
     rng = np.random.default_rng(seed)
     sides = rng.integers(nmin, nmax + 1, nprob)
     fams = rng.integers(0, 3, nprob)
     names = ("vortex", "riemann", "shear")
-    return [(names[f], int(s), 10000 + k) for k, (f, s) in enumerate(zip(fams, sides))]
+    out = []
+    for k, (f, s) in enumerate(zip(fams, sides)):
+        sd = 10000 + k
+        if names[f] == "riemann" and sd in BATCH_VACUUM_SEEDS:
+            sd += 100000
+        out.append((names[f], int(s), sd))
+    return out
 
 
 def mlp_init_params(seed, nf=28, nh=32):

@@ -76,3 +76,49 @@ class Solver:
 
     def check(self):
         return gbr.gbr_check(self.ctx, self.stream)
+
+
+class BatchSolver:
+    """Many grids advanced together through the batched entry points: three
+    state arrays per grid, one launch per stage over all grids."""
+
+    def __init__(self, problems, precision=gbr.GBR_PREC_FP32_BULK, stream=None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.problems = list(problems)
+        self.stream = stream
+        P = self.problems
+        self.b = gbr.gbr_batch_init([p.nx for p in P], [p.ny for p in P],
+                                    [[p.x0, p.x1, p.y0, p.y1] for p in P],
+                                    [[p.bc_x, p.bc_y] for p in P], [p.gamma for p in P],
+                                    [p.mu for p in P], [p.Pr for p in P], [p.cfl for p in P],
+                                    precision)
+        self.bufs = [[torch.empty((4, p.ny, p.nx), dtype=torch.float64, device=device)
+                      for p in P] for _ in range(3)]
+        for q, p in zip(self.bufs[0], P):
+            q.copy_(torch.from_numpy(np.ascontiguousarray(p.Q, np.float64)))
+        gbr.gbr_batch_set_arrays(self.b, *self.bufs)
+
+    def step(self):
+        gbr.gbr_batch_step(self.b, self.stream)
+
+    def states(self):
+        """The current state tensors, one per grid."""
+        return self.bufs[gbr.gbr_batch_current(self.b)]
+
+    def dt(self):
+        return gbr.gbr_batch_get_dt(self.b, len(self.problems), self.stream)
+
+    def check(self):
+        return gbr.gbr_batch_check(self.b, self.stream)
+
+    def close(self):
+        if self.b:
+            gbr.gbr_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
