@@ -110,6 +110,9 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
   constexpr int FN = X ? 1 : 2, FT = X ? 2 : 1;
   constexpr int IPT = (NL * WFL + NT - 1) / NT;
   constexpr int GSTR = (WG > WFL ? WG : WFL) * NL;
+  // interface values: odd row stride (pass 4 reads across lines in y)
+  constexpr int WFS = WFL | 1;
+  static_assert(WFS <= WG, "interface rows fit the buffer");
   const int tid = threadIdx.x;
   const int nl = (NLINES - l0) < NL ? (NLINES - l0) : NL;
   const double inv_dn = X ? P.inv_dx : P.inv_dy;
@@ -120,7 +123,7 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
   float* sDU = sD + NF * NL * WD;    // [NF][NL x WU]   edge jumps of the primitives
   float* sDF = sDU + NF * NL * WU;   // [4][NL x WG]    edge jumps of the cell fluxes; then d
   float* sE = sDF + 4 * GSTR;        // [2][NL x WE]    tangential derivatives of un, ut
-  auto bidx = [](int line, int p, int W) { return X ? line * W + p : p * NL + line; };
+  auto bidx = [](int line, int p, int W) { return line * W + p; };
   auto ridx = [&](int line, int pos) {
     const int lx = X ? pos : l0 + line;
     const int ly = X ? l0 + line : pos;
@@ -138,8 +141,8 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
   for (int k1 = 0; k1 < P1R; ++k1) {
     const int t = tid + k1 * NT;
     if (t >= NL * WP) break;
-    const int line = X ? t / WP : t % NL;
-    const int p = X ? t % WP : t / NL;
+    const int line = t / WP;
+    const int p = t % WP;
     if (line >= nl) continue;
     const int k = p - 5;
     const int r = ridx(line, k);
@@ -195,8 +198,8 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
     const int t = tid + kk * NT;
     bool flagged = false;
     if (t < NL * WFL) {
-      const int line = X ? t / WFL : t % NL;
-      const int p = X ? t % WFL : t / NL;
+      const int line = t / WFL;
+      const int p = t % WFL;
       const int pos = p - 1;
       if (line < nl) {
         bool sigma = true;
@@ -299,10 +302,10 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
   for (int kk = 0; kk < IPT; ++kk) {
     if (has[kk]) {
       const int t = tid + kk * NT;
-      const int line = X ? t / WFL : t % NL;
-      const int p = X ? t % WFL : t / NL;
+      const int line = t / WFL;
+      const int p = t % WFL;
 #pragma unroll
-      for (int m = 0; m < 4; ++m) sDF[m * GSTR + bidx(line, p, WFL)] = dsm[kk][m];
+      for (int m = 0; m < 4; ++m) sDF[m * GSTR + bidx(line, p, WFS)] = dsm[kk][m];
     }
   }
 
@@ -310,8 +313,8 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
   const int nq = *L.qcount;
   for (int qi = tid; qi < nq; qi += NT) {
     const int t = L.queue[qi];
-    const int line = X ? t / WFL : t % NL;
-    const int p = X ? t % WFL : t / NL;
+    const int line = t / WFL;
+    const int p = t % WFL;
     const int pos = p - 1;
     const int r = ridx(line, pos);
     double WL[4], WR[4];
@@ -344,7 +347,7 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
     conv_flux(W0, P.g1inv, f0);
     conv_flux(W1, P.g1inv, f1);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) sDF[m * GSTR + bidx(line, p, WFL)] = (float)(F[m] - 0.5 * (f0[m] + f1[m]));
+    for (int m = 0; m < 4; ++m) sDF[m * GSTR + bidx(line, p, WFS)] = (float)(F[m] - 0.5 * (f0[m] + f1[m]));
   }
   __syncthreads();
 
@@ -362,7 +365,7 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
         wrot(r - SN, Wm);
         wrot(r + SN, Wp);
         conv_flux_jump(Wm, Wp, P.g1inv, dfc);
-        const int bp = bidx(line, pos + 1, WFL), bm = bidx(line, pos, WFL);
+        const int bp = bidx(line, pos + 1, WFS), bm = bidx(line, pos, WFS);
         double d[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m)

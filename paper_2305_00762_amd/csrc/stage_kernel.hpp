@@ -131,9 +131,15 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
   double* sD = L.ph;                       // [NF][NL x WD]  normal gradients (rotated order)
   double* sF = sD + NF * NL * WD;          // [4][NL x WF]   cell fluxes; later [4][NL x WFL] interface fluxes
   constexpr int FSTR = (WF > WFL ? WF : WFL) * NL;
+  // interface values: odd row stride, so pass 4 (lanes across lines in the
+  // y sweep) reads distinct banks
+  constexpr int WFS = WFL | 1;
+  static_assert(WFS <= WF, "interface rows fit the flux buffer");
   double* sE = sF + 4 * FSTR;              // [2][NL x WE]   tangential derivatives of un, ut
-  // buffer index: lines fastest for y (lanes walk along x), positions fastest for x
-  auto bidx = [](int line, int p, int W) { return X ? line * W + p : p * NL + line; };
+  // buffer index and thread mapping: positions fastest in both sweeps (in the
+  // y sweep consecutive lanes then step RX doubles apart in the tile, an odd
+  // stride, so the FP64 tile reads fall in distinct banks)
+  auto bidx = [](int line, int p, int W) { return line * W + p; };
   auto ridx = [&](int line, int pos) {
     const int lx = X ? pos : l0 + line;
     const int ly = X ? l0 + line : pos;
@@ -147,8 +153,8 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
   for (int k1 = 0; k1 < P1R; ++k1) {
     const int t = tid + k1 * NT;
     if (t >= NL * WF) break;
-    const int line = X ? t / WF : t % NL;
-    const int p = X ? t % WF : t / NL;
+    const int line = t / WF;
+    const int p = t % WF;
     if (line >= nl) continue;
     const int pos = p - 5;
     const int r = ridx(line, pos);
@@ -199,8 +205,8 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
     const int t = tid + k * NT;
     bool flagged = false;
     if (t < NL * WFL) {
-      const int line = X ? t / WFL : t % NL;
-      const int p = X ? t % WFL : t / NL;
+      const int line = t / WFL;
+      const int p = t % WFL;
       const int pos = p - 1;  // interface pos + 1/2
       if (line < nl) {
         bool sigma = true;
@@ -286,10 +292,10 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
   for (int k = 0; k < IPT; ++k) {
     if (has[k]) {
       const int t = tid + k * NT;
-      const int line = X ? t / WFL : t % NL;
-      const int p = X ? t % WFL : t / NL;
+      const int line = t / WFL;
+      const int p = t % WFL;
 #pragma unroll
-      for (int m = 0; m < 4; ++m) sF[m * FSTR + bidx(line, p, WFL)] = fsm[k][m];
+      for (int m = 0; m < 4; ++m) sF[m * FSTR + bidx(line, p, WFS)] = fsm[k][m];
     }
   }
 
@@ -297,8 +303,8 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
   const int nq = *L.qcount;
   for (int qi = tid; qi < nq; qi += NT) {
     const int t = L.queue[qi];
-    const int line = X ? t / WFL : t % NL;
-    const int p = X ? t % WFL : t / NL;
+    const int line = t / WFL;
+    const int p = t % WFL;
     const int pos = p - 1;
     const int r = ridx(line, pos);
     const double* U = L.U;
@@ -331,7 +337,7 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
                   sE[1 * NL * WE + bidx(line, pos + 2, WE)], inv_dn, P.mu, P.kq, F);
     }
 #pragma unroll
-    for (int m = 0; m < 4; ++m) sF[m * FSTR + bidx(line, p, WFL)] = F[m];
+    for (int m = 0; m < 4; ++m) sF[m * FSTR + bidx(line, p, WFS)] = F[m];
   }
   __syncthreads();
 
@@ -344,7 +350,7 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
       const int line = (X ? ly : lx) - l0;
       const int pos = X ? lx : ly;
       if (line >= 0 && line < nl) {
-        const int bp = bidx(line, pos + 1, WFL), bm = bidx(line, pos, WFL);
+        const int bp = bidx(line, pos + 1, WFS), bm = bidx(line, pos, WFS);
         const double d0 = sF[0 * FSTR + bp] - sF[0 * FSTR + bm];
         const double d1 = sF[1 * FSTR + bp] - sF[1 * FSTR + bm];
         const double d2 = sF[2 * FSTR + bp] - sF[2 * FSTR + bm];
