@@ -336,7 +336,10 @@ struct MlpChiParams {
   int nx, ny, bcx, bcy, tiles_x;
   double gamma;
 };
-constexpr int kChiTX = 64, kChiTY = 16;
+#ifndef GBR_CHI_TY
+#define GBR_CHI_TY 16
+#endif
+constexpr int kChiTX = 64, kChiTY = GBR_CHI_TY;
 constexpr int kChiRX = kChiTX + 6, kChiRY = kChiTY + 6, kChiRS = kChiRX * kChiRY;
 constexpr int kChiRow = 5;            // uint4 per staged feature row (80 B: conflict-free)
 

@@ -38,7 +38,7 @@ from . import problems as PB
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "meg7_detector.npz")
-DEFAULT_MARGIN = 24.0
+DEFAULT_MARGIN = 48.0
 
 
 def _torch():

@@ -6,16 +6,15 @@ training seeds) advanced with the plain FP64 method:
 
 * raw agreement with the plain detector's directional labels (margin 0,
   the network decides everything): the trained network's balanced error
-  (mean of its false-negative and false-positive rates) is at most 15 %
-  (this field is 256^2, half the training resolution), the untrained
-  network's (its initial weights) at least 25 %;
+  (mean of its false-negative and false-positive rates) is at most 15 %,
+  the untrained network's (its initial weights) at least 25 %;
 * as the method uses it (default margin, plain fallback below it): the
   trained network decides at least 90 % of the evaluations itself and its
   decisions disagree with the plain labels on at most 0.1 % of all
   evaluations, while the untrained one falls back on more than half (there
   the method is the plain detector plus the network's cost);
-* the solution: FP32-bulk steps with the learned detector stay within L1
-  density 1e-5 of the same steps with the plain detector, and the learned
+* the solution: 20 FP32-bulk steps with the learned detector stay within L1
+  density 1e-6 of the same steps with the plain detector, and the learned
   path's fallback count matches the evaluations it reports.
 """
 import numpy as np
@@ -37,7 +36,7 @@ def test_trained_network_gain():
     torch = require_gpu()
     from paper_2305_00762_amd import detector as D
     from paper_2305_00762_amd.solver import Solver
-    n = 256
+    n = 512
     P = PB.riemann(n, seed=7000)
     S = Solver(P)
     for _ in range(30):
@@ -70,15 +69,15 @@ def test_trained_network_gain():
             gbr.gbr_set_mlp_detector(R.ctx, det, D.DEFAULT_MARGIN)
             gbr.gbr_set_scheme(R.ctx, gbr.GBR_RECON_PRIM, gbr.GBR_MP_FLAGGED,
                                gbr.GBR_PREC_FP32_BULK, gbr.GBR_DET_MLP)
-        for _ in range(40):
+        for _ in range(20):
             R.step()
         assert R.check() == gbr.GBR_OK
         if det is not None:
             ev, fb = gbr.gbr_mlp_stats(R.ctx, reset=True)
-            assert ev == 2 * n * n * 3 * 40 and fb <= 0.10 * ev
+            assert ev == 2 * n * n * 3 * 20 and fb <= 0.10 * ev
         runs[name] = R.Q.clone()
         R.close()
     l1 = (runs["learned"] - runs["plain"]).abs().reshape(4, -1).mean(dim=1).cpu().numpy()
-    report("learned vs plain detector, 40 steps", L1=l1.tolist())
-    assert l1[0] <= 1e-5
+    report("learned vs plain detector, 20 steps", L1=l1.tolist())
+    assert l1[0] <= 1e-6
     gbr.gbr_mlp_destroy(trained)
