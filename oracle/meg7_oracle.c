@@ -49,6 +49,14 @@
  *          the first-order state: U_L = U_j, U_R = U_{j+1}, F_L = F(U_j),
  *          F_R = F(U_{j+1}).  The paper prescribes no positivity treatment
  *          for these cases.
+ *   R-CONS MEG7-cons (recon = 1): eq. (eqn:grb) and the MP procedure act on
+ *          the conservative variables and their sixth-order gradients; the
+ *          velocity gradients of the viscous flux follow from the printed
+ *          chain rule, du = (d(rho u) - u d rho)/rho (normal and tangential),
+ *          and T' stays the sixth-order difference of T (R-T).
+ *   R-CHARC The characteristic variables of MEG7-cons use the eigenvectors of
+ *          the conservative-variable flux Jacobian at the arithmetic mean of
+ *          the two conservative states beside the interface.
  *   R-MPG  In eq. (eqn:mp-procedure) the hat on Phi_{j-1} and the mixed
  *          i/j subscripts are typesetting slips: plain Phi_{j-1}, index j.
  *          The MP xi (=7) and the detector xi (=1e-3) are different
@@ -75,6 +83,7 @@ typedef struct {
     double gamma, mu, Pr;
     int mp_mode;   /* 0: MP only where sigma=0 (R-MP); 1: MP test everywhere */
     int force_sigma; /* -1: detector decides; 0 or 1: force sigma (tests)    */
+    int recon;     /* 0: primitive variables (MEG7-prim); 1: conservative (MEG7-cons) */
 } orc_cfg;
 
 /* ---------------------------------------------------------------------- */
@@ -344,6 +353,12 @@ typedef struct {
     double dun_t[2], dut_t[2]; /* d un/dt, d ut/dt (true derivatives) at 0,1 */
     double psi[6];     /* detector at offsets -2..3                         */
     double dn;         /* normal spacing                                    */
+    /* MEG7-cons only (recon = 1): conservative variables (rho, rho un,
+     * rho ut, E) at offsets -4..5, their Delta_n d/dn at -2..3, and the
+     * tangential derivatives d/dt of rho, rho un, rho ut at offsets 0, 1. */
+    double Qc[4][10];
+    double GQ[4][6];
+    double GtQ[3][2];
 } orc_line;
 
 /* Characteristic projection (reading R-CHAR) of primitive vectors for the
@@ -366,6 +381,58 @@ static void char_bwd(const double Wc[4], double rb, double cb, double U[4])
     U[3] = cb * cb * (Wc[0] + Wc[3]);
 }
 
+/* Conservative variables to primitive (eq. eqn:pressure). */
+static void cons_to_prim(const double Q[4], double gamma, double W[4])
+{
+    W[0] = Q[0];
+    W[1] = Q[1] / Q[0];
+    W[2] = Q[2] / Q[0];
+    W[3] = (gamma - 1.0) * (Q[3] - 0.5 * (Q[1] * Q[1] + Q[2] * Q[2]) / Q[0]);
+}
+
+/* Characteristic projection for MEG7-cons (reading R-CHARC): eigenvectors of
+ * the conservative normal flux Jacobian at the state with velocity (ub, vb),
+ * total enthalpy hb and sound speed cb, with b1 = (gamma-1)/cb^2 and
+ * b2 = b1 (ub^2 + vb^2)/2.  Rows of L:
+ *   ((b2 + ub/cb)/2, -(b1 ub + 1/cb)/2, -b1 vb/2, b1/2),
+ *   (1 - b2, b1 ub, b1 vb, -b1), (-vb, 0, 1, 0),
+ *   ((b2 - ub/cb)/2, -(b1 ub - 1/cb)/2, -b1 vb/2, b1/2);
+ * columns of R = L^{-1}: (1, ub - cb, vb, hb - ub cb), (1, ub, vb, (ub^2+vb^2)/2),
+ *   (0, 0, 1, vb), (1, ub + cb, vb, hb + ub cb). */
+typedef struct { double ub, vb, hb, cb, b1, b2; } orc_cstate;
+
+void orc_char_cons_fwd(const orc_cstate *s, const double Q[4], double Wc[4])
+{
+    const double u = s->ub, v = s->vb, c = s->cb, b1 = s->b1, b2 = s->b2;
+    Wc[0] = 0.5 * ((b2 + u / c) * Q[0] - (b1 * u + 1.0 / c) * Q[1] - b1 * v * Q[2] + b1 * Q[3]);
+    Wc[1] = (1.0 - b2) * Q[0] + b1 * u * Q[1] + b1 * v * Q[2] - b1 * Q[3];
+    Wc[2] = -v * Q[0] + Q[2];
+    Wc[3] = 0.5 * ((b2 - u / c) * Q[0] - (b1 * u - 1.0 / c) * Q[1] - b1 * v * Q[2] + b1 * Q[3]);
+}
+
+void orc_char_cons_bwd(const orc_cstate *s, const double Wc[4], double Q[4])
+{
+    const double u = s->ub, v = s->vb, c = s->cb, h = s->hb;
+    Q[0] = Wc[0] + Wc[1] + Wc[3];
+    Q[1] = (u - c) * Wc[0] + u * Wc[1] + (u + c) * Wc[3];
+    Q[2] = v * (Wc[0] + Wc[1] + Wc[3]) + Wc[2];
+    Q[3] = (h - u * c) * Wc[0] + 0.5 * (u * u + v * v) * Wc[1] + v * Wc[2] + (h + u * c) * Wc[3];
+}
+
+/* The state of R-CHARC from the arithmetic mean of two conservative states. */
+void orc_char_cons_state(const double Qa[4], const double Qb[4], double gamma, orc_cstate *s)
+{
+    double q[4], w[4];
+    for (int m = 0; m < 4; ++m) q[m] = 0.5 * (Qa[m] + Qb[m]);
+    cons_to_prim(q, gamma, w);
+    s->ub = w[1];
+    s->vb = w[2];
+    s->hb = (q[3] + w[3]) / q[0];
+    s->cb = sqrt(gamma * w[3] / q[0]);
+    s->b1 = (gamma - 1.0) / (s->cb * s->cb);
+    s->b2 = 0.5 * s->b1 * (s->ub * s->ub + s->vb * s->vb);
+}
+
 /* Flux through one interface (rotated frame). Returns sigma in *sig_out. */
 static void line_flux(const orc_line *L, const orc_cfg *c, double Fout[4], int *sig_out,
                       int *nlimited, int sig_given)
@@ -381,7 +448,41 @@ static void line_flux(const orc_line *L, const orc_cfg *c, double Fout[4], int *
 
     double WL[4], WR[4], FL[4], FR[4];
     int use_mp = (sigma == 0) || (c->mp_mode == 1);
-    if (!use_mp) {
+    if (c->recon == 1 && !use_mp) {
+        /* MEG7-cons, Sec. 2.2: unlimited GRB states on conservative variables */
+        double QL[4], QR[4];
+        for (int m = 0; m < 4; ++m) {
+            QL[m] = grb_left(&L->Qc[m][4], &L->GQ[m][2]);
+            QR[m] = grb_right(&L->Qc[m][4], &L->GQ[m][2]);
+        }
+        cons_to_prim(QL, gamma, WL);
+        cons_to_prim(QR, gamma, WR);
+    } else if (c->recon == 1) {
+        /* MEG7-cons, Sec. 2.3: MEG7 in conservative characteristic variables */
+        double qa[4], qb[4];
+        for (int m = 0; m < 4; ++m) { qa[m] = L->Qc[m][4]; qb[m] = L->Qc[m][5]; }
+        orc_cstate cs;
+        orc_char_cons_state(qa, qb, gamma, &cs);
+        double cw[4][6], cg[4][6];
+        for (int k = 0; k < 6; ++k) {
+            double q[4], w[4], g[4], wg[4];
+            for (int m = 0; m < 4; ++m) { q[m] = L->Qc[m][k + 2]; g[m] = L->GQ[m][k]; }
+            orc_char_cons_fwd(&cs, q, w);
+            orc_char_cons_fwd(&cs, g, wg);
+            for (int m = 0; m < 4; ++m) { cw[m][k] = w[m]; cg[m][k] = wg[m]; }
+        }
+        double wl[4], wr[4], QL[4], QR[4];
+        for (int m = 0; m < 4; ++m) {
+            int la = 0, lb = 0;
+            wl[m] = orc_meg7_left(&cw[m][2], &cg[m][2], &la);
+            wr[m] = orc_meg7_right(&cw[m][2], &cg[m][2], &lb);
+            if (nlimited) *nlimited += la + lb;
+        }
+        orc_char_cons_bwd(&cs, wl, QL);
+        orc_char_cons_bwd(&cs, wr, QR);
+        cons_to_prim(QL, gamma, WL);
+        cons_to_prim(QR, gamma, WR);
+    } else if (!use_mp) {
         /* Sec. 2.2: unlimited GRB states, eq. (eqn:grb), on primitives */
         for (int m = 0; m < 4; ++m) {
             WL[m] = grb_left(&L->W[m][4], &L->G[m][2]);
@@ -447,14 +548,29 @@ static void line_flux(const orc_line *L, const orc_cfg *c, double Fout[4], int *
         double ut0 = L->W[2][4], ut1 = L->W[2][5];
         double gun0 = L->G[1][2], gun1 = L->G[1][3];
         double gut0 = L->G[2][2], gut1 = L->G[2][3];
+        double dunt0 = L->dun_t[0], dunt1 = L->dun_t[1];
+        double dutt0 = L->dut_t[0], dutt1 = L->dut_t[1];
+        if (c->recon == 1) {
+            /* MEG7-cons: velocity gradients by the chain rule of Sec. 2.2,
+             * d u = (d(rho u) - u d rho) / rho, from the conservative ones */
+            const double r0 = L->W[0][4], r1 = L->W[0][5];
+            gun0 = (L->GQ[1][2] - un0 * L->GQ[0][2]) / r0;
+            gun1 = (L->GQ[1][3] - un1 * L->GQ[0][3]) / r1;
+            gut0 = (L->GQ[2][2] - ut0 * L->GQ[0][2]) / r0;
+            gut1 = (L->GQ[2][3] - ut1 * L->GQ[0][3]) / r1;
+            dunt0 = (L->GtQ[1][0] - un0 * L->GtQ[0][0]) / r0;
+            dunt1 = (L->GtQ[1][1] - un1 * L->GtQ[0][1]) / r1;
+            dutt0 = (L->GtQ[2][0] - ut0 * L->GtQ[0][0]) / r0;
+            dutt1 = (L->GtQ[2][1] - ut1 * L->GtQ[0][1]) / r1;
+        }
         double dun_n = (0.5 * (gun0 + gun1)
                         + 0.5 * ALPHA_V * (un1 - 0.5 * gun1 - un0 - 0.5 * gun0)) / dn;
         double dut_n = (0.5 * (gut0 + gut1)
                         + 0.5 * ALPHA_V * (ut1 - 0.5 * gut1 - ut0 - 0.5 * gut0)) / dn;
         double dT_n = (0.5 * (L->GT[0] + L->GT[1])
                        + 0.5 * ALPHA_V * (L->T[1] - 0.5 * L->GT[1] - L->T[0] - 0.5 * L->GT[0])) / dn;
-        double dun_t = 0.5 * (L->dun_t[0] + L->dun_t[1]);
-        double dut_t = 0.5 * (L->dut_t[0] + L->dut_t[1]);
+        double dun_t = 0.5 * (dunt0 + dunt1);
+        double dut_t = 0.5 * (dutt0 + dutt1);
         double unf = 0.5 * (un0 + un1), utf = 0.5 * (ut0 + ut1);
         /* eq. (eqn:visc) in the normal frame */
         double tnn = 2.0 / 3.0 * mu * (2.0 * dun_n - dut_t);
@@ -486,6 +602,8 @@ typedef struct {
     double *T;
     double *Gx[5], *Gy[5];      /* Delta x d/dx, Delta y d/dy of rho,u,v,p,T */
     double *psix, *psiy;
+    double *C[4];               /* rho, rho u, rho v, E (recon = 1 only) */
+    double *GCx[4], *GCy[4];    /* their Delta x d/dx, Delta y d/dy       */
 } orc_fields;
 
 static void fields_free(orc_fields *F)
@@ -494,6 +612,7 @@ static void fields_free(orc_fields *F)
     free(F->T);
     for (int m = 0; m < 5; ++m) { free(F->Gx[m]); free(F->Gy[m]); }
     free(F->psix); free(F->psiy);
+    for (int m = 0; m < 4; ++m) { free(F->C[m]); free(F->GCx[m]); free(F->GCy[m]); }
 }
 
 static int fields_build(const orc_cfg *c, const double *Q, orc_fields *F)
@@ -515,6 +634,14 @@ static int fields_build(const orc_cfg *c, const double *Q, orc_fields *F)
     for (int m = 0; m < 4; ++m) if (!F->W[m]) return -1;
     if (!F->T || !F->psix || !F->psiy) return -1;
     for (int m = 0; m < 5; ++m) if (!F->Gx[m] || !F->Gy[m]) return -1;
+    if (c->recon == 1) {
+        for (int m = 0; m < 4; ++m) {
+            F->C[m] = (double *)calloc(np, sizeof(double));
+            F->GCx[m] = (double *)calloc(np, sizeof(double));
+            F->GCy[m] = (double *)calloc(np, sizeof(double));
+            if (!F->C[m] || !F->GCx[m] || !F->GCy[m]) return -1;
+        }
+    }
 
     const double gamma = c->gamma;
     /* ghost cells (R-BC) and primitives, eq. (eqn:pressure), T (R-T) */
@@ -530,6 +657,9 @@ static int fields_build(const orc_cfg *c, const double *Q, orc_fields *F)
             size_t P = (size_t)I * NX + J;
             F->W[0][P] = rho; F->W[1][P] = u; F->W[2][P] = v; F->W[3][P] = p;
             F->T[P] = gamma * p / rho;
+            if (c->recon == 1) {
+                F->C[0][P] = rho; F->C[1][P] = mx; F->C[2][P] = my; F->C[3][P] = E;
+            }
         }
     }
     double *src[5] = {F->W[0], F->W[1], F->W[2], F->W[3], F->T};
@@ -547,6 +677,18 @@ static int fields_build(const orc_cfg *c, const double *Q, orc_fields *F)
                 }
                 F->Gx[m][P] = okx ? orc_grad6(px) : 0.0;
                 F->Gy[m][P] = oky ? orc_grad6(py) : 0.0;
+            }
+            if (c->recon == 1) {
+                int okx = (J >= 3 && J < NX - 3), oky = (I >= 3 && I < NY - 3);
+                for (int m = 0; m < 4; ++m) {
+                    double px[7], py[7];
+                    for (int k = -3; k <= 3; ++k) {
+                        px[k + 3] = okx ? F->C[m][P + k] : 0.0;
+                        py[k + 3] = oky ? F->C[m][P + (ptrdiff_t)k * NX] : 0.0;
+                    }
+                    F->GCx[m][P] = okx ? orc_grad6(px) : 0.0;
+                    F->GCy[m][P] = oky ? orc_grad6(py) : 0.0;
+                }
             }
             /* detector on density, one per direction */
             const double *r = F->W[0];
@@ -577,6 +719,15 @@ static void gather_x(const orc_cfg *c, const orc_fields *F, int i, int j, orc_li
     }
     for (int k = -2; k <= 3; ++k) L->psi[k + 2] = F->psix[P0 + k];
     L->dn = (c->x1 - c->x0) / c->nx;
+    if (c->recon == 1) {
+        const double dt = (c->y1 - c->y0) / c->ny;
+        for (int m = 0; m < 4; ++m) {
+            for (int k = -4; k <= 5; ++k) L->Qc[m][k + 4] = F->C[perm[m]][P0 + k];
+            for (int k = -2; k <= 3; ++k) L->GQ[m][k + 2] = F->GCx[perm[m]][P0 + k];
+        }
+        for (int k = 0; k < 2; ++k)
+            for (int m = 0; m < 3; ++m) L->GtQ[m][k] = F->GCy[perm[m]][P0 + k] / dt;
+    }
 }
 
 /* Gather the line for y-interface (j, i+1/2), i in [-1, ny-1]. */
@@ -597,12 +748,21 @@ static void gather_y(const orc_cfg *c, const orc_fields *F, int i, int j, orc_li
     }
     for (int k = -2; k <= 3; ++k) L->psi[k + 2] = F->psiy[P0 + (ptrdiff_t)k * NX];
     L->dn = (c->y1 - c->y0) / c->ny;
+    if (c->recon == 1) {
+        const double dt = (c->x1 - c->x0) / c->nx;
+        for (int m = 0; m < 4; ++m) {
+            for (int k = -4; k <= 5; ++k) L->Qc[m][k + 4] = F->C[perm[m]][P0 + (ptrdiff_t)k * NX];
+            for (int k = -2; k <= 3; ++k) L->GQ[m][k + 2] = F->GCy[perm[m]][P0 + (ptrdiff_t)k * NX];
+        }
+        for (int k = 0; k < 2; ++k)
+            for (int m = 0; m < 3; ++m) L->GtQ[m][k] = F->GCx[perm[m]][P0 + (size_t)k * NX] / dt;
+    }
 }
 
 static int cfg_ok(const orc_cfg *c)
 {
     return c && c->nx >= 2 * NG && c->ny >= 2 * NG && c->gamma > 1.0 && c->mu >= 0.0
-        && c->Pr > 0.0 && c->x1 > c->x0 && c->y1 > c->y0;
+        && c->Pr > 0.0 && c->x1 > c->x0 && c->y1 > c->y0 && (c->recon == 0 || c->recon == 1);
 }
 
 /* eqs. (eqn-differencing_residual), (deriv): Res = -dF/dx - dG/dy.
@@ -759,6 +919,7 @@ void orc_line_flux(const double *W40, const double *G24, const double *T2, const
                    double dn, const orc_cfg *c, double F[4], int *sigma)
 {
     orc_line L;
+    memset(&L, 0, sizeof(L));   /* primitive reconstruction only (recon = 0) */
     for (int m = 0; m < 4; ++m) {
         for (int k = 0; k < 10; ++k) L.W[m][k] = W40[m * 10 + k];
         for (int k = 0; k < 6; ++k) L.G[m][k] = G24[m * 6 + k];

@@ -20,8 +20,12 @@ class OrcCfg(C.Structure):
         ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
         ("bc_x", C.c_int), ("bc_y", C.c_int),
         ("gamma", C.c_double), ("mu", C.c_double), ("Pr", C.c_double),
-        ("mp_mode", C.c_int), ("force_sigma", C.c_int),
+        ("mp_mode", C.c_int), ("force_sigma", C.c_int), ("recon", C.c_int),
     ]
+
+
+class OrcCState(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("ub", "vb", "hb", "cb", "b1", "b2")]
 
 
 _lib = None
@@ -67,13 +71,20 @@ def lib():
         L.orc_cell_flags.restype = C.c_int
         L.orc_cell_flags.argtypes = [C.POINTER(OrcCfg), dp, C.c_void_p, C.c_void_p,
                                      C.c_void_p]
+        L.orc_char_cons_state.restype = None
+        L.orc_char_cons_state.argtypes = [dp, dp, C.c_double, C.POINTER(OrcCState)]
+        L.orc_char_cons_fwd.restype = None
+        L.orc_char_cons_fwd.argtypes = [C.POINTER(OrcCState), dp, dp]
+        L.orc_char_cons_bwd.restype = None
+        L.orc_char_cons_bwd.argtypes = [C.POINTER(OrcCState), dp, dp]
         _lib = L
     return _lib
 
 
 def make_cfg(nx, ny, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc_x=BC_PERIODIC, bc_y=BC_PERIODIC,
-             gamma=1.4, mu=0.0, Pr=0.72, mp_mode=0, force_sigma=-1):
-    return OrcCfg(nx, ny, x0, x1, y0, y1, bc_x, bc_y, gamma, mu, Pr, mp_mode, force_sigma)
+             gamma=1.4, mu=0.0, Pr=0.72, mp_mode=0, force_sigma=-1, recon=0):
+    """recon 0: MEG7-prim (primitive variables), 1: MEG7-cons (conservative)."""
+    return OrcCfg(nx, ny, x0, x1, y0, y1, bc_x, bc_y, gamma, mu, Pr, mp_mode, force_sigma, recon)
 
 
 def _ptr(a):
@@ -214,3 +225,23 @@ def threads():
     """OpenMP threads the oracle will use (OMP_NUM_THREADS or all cores)."""
     v = os.environ.get("OMP_NUM_THREADS")
     return int(v) if v else os.cpu_count()
+
+
+def char_cons(Qa, Qb, gamma=1.4):
+    """(L, R): the MEG7-cons characteristic projection at the mean of the
+    conservative states Qa, Qb, as 4x4 matrices (columns: images of unit
+    vectors)."""
+    st = OrcCState()
+    lib().orc_char_cons_state(np.ascontiguousarray(Qa, np.float64),
+                              np.ascontiguousarray(Qb, np.float64), gamma, C.byref(st))
+    Lm = np.zeros((4, 4))
+    Rm = np.zeros((4, 4))
+    for k in range(4):
+        e = np.zeros(4)
+        e[k] = 1.0
+        out = np.zeros(4)
+        lib().orc_char_cons_fwd(C.byref(st), e, out)
+        Lm[:, k] = out
+        lib().orc_char_cons_bwd(C.byref(st), e, out)
+        Rm[:, k] = out
+    return Lm, Rm
