@@ -16,7 +16,7 @@ number of steps is compared with it (L1/Linf per variable).
 Prints ONE JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload riemann1024]
-                  [--path fp32_mlp|fp32|fp64] [--no-cpu-baseline] [--no-compare]
+                  [--path fp32_mlp|fp32|fp64|fp64_cons] [--no-cpu-baseline] [--no-compare]
 """
 import argparse
 import json
@@ -53,10 +53,12 @@ WORKLOADS = {
 }
 
 PATHS = {
-    # name: (precision, learned detector, dtype, kernel name)
-    "fp32_mlp": ("fp32", True, "f32+f64", "meg7_stage_kernel_f32<mlp>"),
-    "fp32": ("fp32", False, "f32+f64", "meg7_stage_kernel_f32"),
-    "fp64": ("fp64", False, "f64", "meg7_stage_kernel"),
+    # name: (precision, learned detector, dtype, kernel name, conservative reconstruction)
+    "fp32_mlp": ("fp32", True, "f32+f64", "meg7_stage_kernel_f32<mlp>", False),
+    "fp32": ("fp32", False, "f32+f64", "meg7_stage_kernel_f32", False),
+    "fp64": ("fp64", False, "f64", "meg7_stage_kernel", False),
+    # MEG7-cons (Table 2): GRB and the MP procedure on conservative variables
+    "fp64_cons": ("fp64", False, "f64", "meg7_stage_kernel<cons>", True),
 }
 
 
@@ -100,7 +102,7 @@ class Path:
         import torch
         from paper_2305_00762_amd import gbr
         self.gbr, self.P, self.stream = gbr, P, stream
-        prec_name, mlp, self.dtype, self.kernel = PATHS[path]
+        prec_name, mlp, self.dtype, self.kernel, self.cons = PATHS[path]
         self.ctx = gbr.gbr_init(P.nx, P.ny, P.gamma, P.mu, P.Pr)
         gbr.gbr_set_geometry(self.ctx, *P.geometry())
         prec = gbr.GBR_PREC_FP32_BULK if prec_name == "fp32" else gbr.GBR_PREC_FP64
@@ -112,7 +114,8 @@ class Path:
             gbr.gbr_set_mlp_detector(self.ctx, self.net, D.DEFAULT_MARGIN if margin is None else margin,
                                      stream.cuda_stream)
             det = gbr.GBR_DET_MLP
-        gbr.gbr_set_scheme(self.ctx, gbr.GBR_RECON_PRIM, gbr.GBR_MP_FLAGGED, prec, det)
+        recon = gbr.GBR_RECON_CONS if self.cons else gbr.GBR_RECON_PRIM
+        gbr.gbr_set_scheme(self.ctx, recon, gbr.GBR_MP_FLAGGED, prec, det)
         dev = torch.device("cuda:0")
         self.Q = [torch.from_numpy(P.Q).to(dev) for _ in range(3)]
         self.dt = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -179,13 +182,13 @@ def diff(Qa, Qb):
     return ([float(v) for v in d.mean(dim=1).cpu()], [float(v) for v in d.max(dim=1).values.cpu()])
 
 
-def cpu_baseline(P, seconds, max_steps=50):
+def cpu_baseline(P, seconds, max_steps=50, recon=0):
     """The CPU oracle on a bounded sample of the same workload: whole SSP-RK3
     steps on the full grid from the initial state until about `seconds` of
     host time have passed.  Returns (record, state after the sample, steps)."""
     import numpy as np
     import oracle as O
-    cfg = O.make_cfg(P.nx, P.ny, *P.geometry(), gamma=P.gamma, mu=P.mu, Pr=P.Pr)
+    cfg = O.make_cfg(P.nx, P.ny, *P.geometry(), gamma=P.gamma, mu=P.mu, Pr=P.Pr, recon=recon)
     Q = np.ascontiguousarray(P.Q.copy())
     steps, t0 = 0, time.perf_counter()
     while True:
@@ -236,6 +239,9 @@ def bench_batch(a, steps):
     cells = sum(p.nx * p.ny for p in ps)
     torch.cuda.set_device(0)
     s = torch.cuda.Stream()
+    if PATHS[a.path][4]:
+        print("bench.py: batched grids run MEG7-prim; use --path fp64 or fp32", file=sys.stderr)
+        sys.exit(2)
     prec = gbr.GBR_PREC_FP64 if a.path == "fp64" else gbr.GBR_PREC_FP32_BULK
     with torch.cuda.stream(s):
         B = BatchSolver(ps, precision=prec, stream=s)
@@ -338,7 +344,13 @@ def main():
 
     calibration_copy(a.calib_copy_mb)
     head = Path(P, a.path, stream, a.tiling, a.weights, a.margin)
-    total_ms, (det_ms, stage_ms, launches) = head.run(a.warmup, steps, timing=True)
+    # kernel pass: the same warm-up and steps with HIP events around every
+    # launch (per-kernel durations for the roofline); the events add gaps
+    # between launches, so the throughput comes from a second pass over the
+    # same work from the same initial state without them
+    ev_ms, (det_ms, stage_ms, launches) = head.run(a.warmup, steps, timing=True)
+    head.reset()
+    total_ms, _ = head.run(a.warmup, steps)
     value = cells * 3 * steps / (total_ms * 1e-3)
     Qhead = head.Q[0].clone()
     status = gbr.strerror(head.status)
@@ -351,7 +363,7 @@ def main():
     # the timed launches over their summed duration from the library's events
     alg_bytes = sum(BYTES_PER_CELL_STAGE.values()) * cells * steps
     achieved = alg_bytes / (stage_ms * 1e-3) / 1e9
-    kname = head.kernel.replace("<mlp>", "_mlp")
+    kname = head.kernel.replace("<mlp>", "_mlp").replace("<cons>", "_cons")
     traffic = load_traffic(kname, a.workload)
     out = {
         "metric": METRIC,
@@ -381,11 +393,13 @@ def main():
             "avg_launch_us": stage_ms * 1e3 / max(launches, 1),
             "bytes_per_cell_stage": 256.0 / 3.0,
         },
+        "ms_per_step_with_kernel_events": ev_ms / steps,
         "kernels_us_per_launch": {"stage": stage_ms * 1e3 / max(launches, 1),
-                                  "detector_flag_map": det_ms * 1e3 / max(launches, 1)},
+                                  "detector_flag_map": (det_ms * 1e3 / max(launches, 1)
+                                                        if head.net is not None else None)},
         # flag map: reads Q (32 B) and writes one byte per cell
         "detector_flag_map_GBs": (33.0 * cells * launches / (det_ms * 1e-3) / 1e9
-                                  if det_ms > 0 else None),
+                                  if det_ms > 0 and head.net is not None else None),
         "status": status,
     }
     if fb_rate is not None:
@@ -405,7 +419,7 @@ def main():
         base.close()
 
     if not a.no_cpu_baseline:
-        rec, Qo, osteps = cpu_baseline(P, a.cpu_seconds)
+        rec, Qo, osteps = cpu_baseline(P, a.cpu_seconds, recon=1 if head.cons else 0)
         out["cpu_baseline"] = rec
         head.reset()
         head.run(osteps, 0)

@@ -40,7 +40,7 @@ enum {
 };
 
 enum { GBR_BC_PERIODIC = 0, GBR_BC_TRANSMISSIVE = 1 };
-enum { GBR_RECON_PRIM = 0 };
+enum { GBR_RECON_PRIM = 0, GBR_RECON_CONS = 1 };
 enum { GBR_MP_FLAGGED = 0 };
 enum { GBR_PREC_FP64 = 0, GBR_PREC_FP32_BULK = 1 };
 enum { GBR_DET_PLAIN = 0, GBR_DET_MLP = 1 };
@@ -73,10 +73,16 @@ int gbr_destroy(gbr_ctx *ctx);
 int gbr_set_geometry(gbr_ctx *ctx, double x0, double x1, double y0, double y1,
                      int bc_x, int bc_y);
 
-/* Scheme options: recon = GBR_RECON_PRIM (MEG7-prim, Sec. 2.2), mp_mode =
- * GBR_MP_FLAGGED (MP limiter in characteristic variables at interfaces the
- * detector flags, Secs. 2.3-2.4), precision = GBR_PREC_FP64 or
- * GBR_PREC_FP32_BULK (gradients, reconstruction and fluxes in float32 with
+/* Scheme options: recon = GBR_RECON_PRIM (MEG7-prim, Sec. 2.2: GRB and the
+ * MP procedure on the primitive variables) or GBR_RECON_CONS (MEG7-cons,
+ * Secs. 2.2-2.3 and Table 2: GRB and the MP procedure on the conservative
+ * variables and their sixth-order gradients, characteristic projection with
+ * the eigenvectors of the conservative flux Jacobian at the mean of the two
+ * cells beside the interface, velocity gradients of the viscous flux by the
+ * chain rule; FP64 with the plain detector only, on the 31x15 and 15x15
+ * tilings), mp_mode = GBR_MP_FLAGGED (MP limiter in characteristic variables
+ * at interfaces the detector flags, Secs. 2.3-2.4), precision = GBR_PREC_FP64
+ * or GBR_PREC_FP32_BULK (gradients, reconstruction and fluxes in float32 with
  * FP64 state, stage update and flux differencing), detector = GBR_DET_PLAIN
  * (density detector, Sec. 2.4) or GBR_DET_MLP (learned detector, needs
  * gbr_mlp_set_weights).  Unsupported combinations return GBR_EUNSUPPORTED

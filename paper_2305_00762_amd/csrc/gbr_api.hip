@@ -17,10 +17,10 @@ namespace {
 
 using namespace gbr;
 
-template <class C, bool MLP = false>
+template <class C, bool MLP = false, bool CONS = false>
 void launch_cfg(const StageParams& P, hipStream_t s) {
   static_assert(C::LDS_BYTES <= 160 * 1024, "LDS per workgroup");
-  hipLaunchKernelGGL((meg7_stage_kernel<C, MLP>), dim3(P.ntiles), dim3(C::NT), 0, s, P);
+  hipLaunchKernelGGL((meg7_stage_kernel<C, MLP, CONS>), dim3(P.ntiles), dim3(C::NT), 0, s, P);
 }
 template <class C, bool MLP = false>
 void launch_cfg_f32(const StageParams& P, hipStream_t s) {
@@ -37,6 +37,7 @@ struct TileVariant {
   int tx, ty;
   LaunchFn fn[2][2][2];   // [precision FP64/FP32-bulk][viscous][learned detector]; null: no build
   const char* name;
+  LaunchFn cons[2];       // MEG7-cons, FP64 with the plain detector: [viscous]; null: no build
 };
 using E31 = TileCfg<31, 15, 15, 16, 256, false>;
 using V31 = TileCfg<31, 15, 8, 16, 256, true>;
@@ -48,13 +49,15 @@ const TileVariant kVariants[] = {
      {{{launch_cfg<E31>, launch_cfg<E31, true>}, {launch_cfg<V31>, launch_cfg<V31, true>}},
       {{launch_cfg_f32<E31>, launch_cfg_f32<E31, true>},
        {launch_cfg_f32<V31>, launch_cfg_f32<V31, true>}}},
-     "31x15"},
+     "31x15",
+     {launch_cfg<E31, false, true>, launch_cfg<V31, false, true>}},
     // 16 interfaces per line both ways; 3-4 workgroups/CU
     {15, 15,
      {{{launch_cfg<E15>, launch_cfg<E15, true>}, {launch_cfg<V15>, launch_cfg<V15, true>}},
       {{launch_cfg_f32<E15>, launch_cfg_f32<E15, true>},
        {launch_cfg_f32<V15>, launch_cfg_f32<V15, true>}}},
-     "15x15"},
+     "15x15",
+     {launch_cfg<E15, false, true>, launch_cfg<V15, false, true>}},
     // 64 x-interfaces per row, 8 y-interfaces per column (Euler, plain detector)
     {63, 7,
      {{{launch_cfg<TileCfg<63, 7, 7, 32, 256, false>>,
@@ -63,7 +66,8 @@ const TileVariant kVariants[] = {
       {{launch_cfg_f32<TileCfg<63, 7, 7, 32, 256, false>>,
         launch_cfg_f32<TileCfg<63, 7, 7, 32, 256, false>, true>},
        {nullptr, nullptr}}},
-     "63x7"},
+     "63x7",
+     {nullptr, nullptr}},
     // 31x8 / 15x16 interface blocks sized for 3 workgroups per CU in FP32 bulk
     {30, 15,
      {{{launch_cfg<TileCfg<30, 15, 15, 15, 256, false>>,
@@ -72,7 +76,8 @@ const TileVariant kVariants[] = {
       {{launch_cfg_f32<TileCfg<30, 15, 8, 15, 256, false, 3>>,
         launch_cfg_f32<TileCfg<30, 15, 8, 15, 256, false, 3>, true>},
        {nullptr, nullptr}}},
-     "30x15"},
+     "30x15",
+     {nullptr, nullptr}},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -227,9 +232,12 @@ int gbr_set_geometry(gbr_ctx* c, double x0, double x1, double y0, double y1, int
 
 int gbr_set_scheme(gbr_ctx* c, int recon, int mp_mode, int precision, int detector) {
   if (!c) return GBR_EINVAL;
-  if (recon != GBR_RECON_PRIM || mp_mode != GBR_MP_FLAGGED) return GBR_EUNSUPPORTED;
+  if (recon != GBR_RECON_PRIM && recon != GBR_RECON_CONS) return GBR_EUNSUPPORTED;
+  if (mp_mode != GBR_MP_FLAGGED) return GBR_EUNSUPPORTED;
   if (precision != GBR_PREC_FP64 && precision != GBR_PREC_FP32_BULK) return GBR_EUNSUPPORTED;
   if (detector != GBR_DET_PLAIN && detector != GBR_DET_MLP) return GBR_EUNSUPPORTED;
+  if (recon == GBR_RECON_CONS && (precision != GBR_PREC_FP64 || detector != GBR_DET_PLAIN))
+    return GBR_EUNSUPPORTED;
   if (detector == GBR_DET_MLP && !c->mlp_ready) return GBR_EINVAL;
   c->recon = recon; c->mp_mode = mp_mode; c->precision = precision; c->detector = detector;
   return GBR_OK;
@@ -271,6 +279,17 @@ int gbr_check(gbr_ctx* c, void* stream) {
   return (h[0] | h[1] | h[2] | h[3]) ? GBR_ESTATE : GBR_OK;
 }
 
+// Launcher of tile variant v for the context's scheme, or null where the
+// variant has no build for it.
+static LaunchFn variant_fn(const gbr_ctx* c, int v) {
+  const int visc = c->mu > 0.0 ? 1 : 0;
+  if (c->recon == GBR_RECON_CONS) return kVariants[v].cons[visc];
+  const int prec = c->precision == GBR_PREC_FP32_BULK ? 1 : 0;
+  const int det = c->detector == GBR_DET_MLP ? 1 : 0;
+  return kVariants[v].fn[prec][visc][det];
+}
+static int active_variant(const gbr_ctx* c) { return variant_fn(c, c->tiling) ? c->tiling : 0; }
+
 static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn,
                         const double* Qk, double* out, hipStream_t s) {
   StageParams P{};
@@ -284,8 +303,6 @@ static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn
   P.gamma = c->gamma; P.g1inv = 1.0 / (c->gamma - 1.0); P.mu = c->mu;
   P.kq = c->mu / (c->Pr * (c->gamma - 1.0));
   P.mode = mode;
-  const int visc = c->mu > 0.0 ? 1 : 0;
-  const int prec = c->precision == GBR_PREC_FP32_BULK ? 1 : 0;
   const int det = c->detector == GBR_DET_MLP ? 1 : 0;
   hipEvent_t* tev = nullptr;
   if (c->timing) {
@@ -316,12 +333,12 @@ static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn
     c->mlp_evaluated += 2ull * c->nx * c->ny;   // along x and along y
     P.chimap = c->d_chimap;
   }
-  const TileVariant* v = &kVariants[c->tiling];
-  if (!v->fn[prec][visc][det]) v = &kVariants[0];
+  const int vi = active_variant(c);
+  const TileVariant* v = &kVariants[vi];
   P.tiles_x = (c->nx + v->tx - 1) / v->tx;
   P.ntiles = P.tiles_x * ((c->ny + v->ty - 1) / v->ty);
   if (tev && hipEventRecord(tev[1], s) != hipSuccess) return GBR_EDEVICE;
-  v->fn[prec][visc][det](P, s);
+  variant_fn(c, vi)(P, s);
   if (tev && hipEventRecord(tev[2], s) != hipSuccess) return GBR_EDEVICE;
   return hip_ok(hipGetLastError());
 }
@@ -362,10 +379,7 @@ int gbr_set_tiling(gbr_ctx* c, int variant) {
 
 int gbr_get_tiling(gbr_ctx* c, int* variant, int* tile_x, int* tile_y) {
   if (!c) return GBR_EINVAL;
-  const TileVariant* v = &kVariants[c->tiling];
-  const int visc = c->mu > 0.0 ? 1 : 0, prec = c->precision == GBR_PREC_FP32_BULK ? 1 : 0;
-  const int det = c->detector == GBR_DET_MLP ? 1 : 0;
-  if (!v->fn[prec][visc][det]) v = &kVariants[0];
+  const TileVariant* v = &kVariants[active_variant(c)];
   if (variant) *variant = (int)(v - kVariants);
   if (tile_x) *tile_x = v->tx;
   if (tile_y) *tile_y = v->ty;
@@ -387,10 +401,8 @@ int gbr_autotune(gbr_ctx* c, const double* Q, int reps, void* stream) {
   c->timing = 0;
   int best = saved, rc = GBR_OK;
   float best_ms = 1e30f;
-  const int visc = c->mu > 0.0 ? 1 : 0, prec = c->precision == GBR_PREC_FP32_BULK ? 1 : 0;
-  const int det = c->detector == GBR_DET_MLP ? 1 : 0;
   for (int v = 0; v < kNumVariants && rc == GBR_OK; ++v) {
-    if (!kVariants[v].fn[prec][visc][det]) continue;
+    if (!variant_fn(c, v)) continue;
     c->tiling = v;
     rc = launch_stage(c, MODE_RESIDUAL, nullptr, Q, Q, tmp, s);  // warm-up
     if (rc != GBR_OK) break;

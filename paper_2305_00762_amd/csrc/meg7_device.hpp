@@ -168,6 +168,81 @@ __device__ __forceinline__ void meg7_char_states(FW Wf, FG Gf, double gamma, dou
   }
 }
 
+// Conservative (rho, rho un, rho ut, E) to primitive (rho, un, ut, p),
+// eq. (eqn:pressure).  A non-positive density gives a non-positive or NaN
+// result, which the positivity test of the callers rejects.
+__device__ __forceinline__ void cons_to_prim(const double Q[4], double gamma, double W[4]) {
+  const double ir = rcp_nr(Q[0]);
+  W[0] = Q[0];
+  W[1] = Q[1] * ir;
+  W[2] = Q[2] * ir;
+  W[3] = (gamma - 1.0) * (Q[3] - 0.5 * (Q[1] * W[1] + Q[2] * W[2]));
+}
+
+// Characteristic MEG7 states of MEG7-cons (Sec. 2.3 on conservative
+// variables).  Qf(q, f) / Gf(q, f) return rotated conservative field f and its
+// normal gradient (spacing-scaled) at offset q-2 from cell j.  The
+// eigenvectors are those of the conservative normal flux Jacobian at the
+// arithmetic mean of the conservative states of cells j and j+1, with
+// b1 = (gamma-1)/c^2, b2 = b1 (u^2+v^2)/2.  Rows of L:
+//   ((b2 + u/c)/2, -(b1 u + 1/c)/2, -b1 v/2, b1/2), (1 - b2, b1 u, b1 v, -b1),
+//   (-v, 0, 1, 0), ((b2 - u/c)/2, -(b1 u - 1/c)/2, -b1 v/2, b1/2);
+// columns of R = L^{-1}: (1, u-c, v, H-uc), (1, u, v, (u^2+v^2)/2), (0, 0, 1, v),
+//   (1, u+c, v, H+uc).  Every row reads all four fields, so the rows are
+// limited one at a time in a rolled loop and projected back column by column.
+template <class FQ, class FG>
+__device__ __forceinline__ void meg7_char_states_cons(FQ Qf, FG Gf, double gamma,
+                                                      double QLo[4], double QRo[4]) {
+  const double q0 = 0.5 * (Qf(2, 0) + Qf(3, 0)), q1 = 0.5 * (Qf(2, 1) + Qf(3, 1));
+  const double q2 = 0.5 * (Qf(2, 2) + Qf(3, 2)), q3 = 0.5 * (Qf(2, 3) + Qf(3, 3));
+  const double iq0 = rcp_nr(q0);
+  const double ub = q1 * iq0, vb = q2 * iq0;
+  const double ke = 0.5 * (ub * ub + vb * vb);
+  const double pb = (gamma - 1.0) * (q3 - q0 * ke);
+  const double hb = (q3 + pb) * iq0;
+  const double cb = sqrt_nr(gamma * pb * iq0);
+  const double icb = rcp_nr(cb);
+  const double b1 = (gamma - 1.0) * icb * icb, b2 = b1 * ke;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) { QLo[m] = 0.0; QRo[m] = 0.0; }
+#pragma unroll 1
+  for (int m = 0; m < 4; ++m) {
+    // the field reads do not depend on m: keep them inside the loop (an empty
+    // asm with a memory clobber stops the compiler hoisting all 48 of them)
+    __asm__ volatile("" ::: "memory");
+    const double sg = (m == 0) ? 1.0 : -1.0;   // u/c and 1/c enter rows 0 and 3 with opposite signs
+    double l0, l1, l2, l3;
+    if (m == 1) {
+      l0 = 1.0 - b2; l1 = b1 * ub; l2 = b1 * vb; l3 = -b1;
+    } else if (m == 2) {
+      l0 = -vb; l1 = 0.0; l2 = 1.0; l3 = 0.0;
+    } else {
+      l0 = 0.5 * (b2 + sg * ub * icb);
+      l1 = -0.5 * (b1 * ub + sg * icb);
+      l2 = -0.5 * b1 * vb;
+      l3 = 0.5 * b1;
+    }
+    double cv[6], cg[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      cv[q] = l0 * Qf(q, 0) + l1 * Qf(q, 1) + l2 * Qf(q, 2) + l3 * Qf(q, 3);
+      cg[q] = l0 * Gf(q, 0) + l1 * Gf(q, 1) + l2 * Gf(q, 2) + l3 * Gf(q, 3);
+    }
+    double cl, cr;
+    meg7_pair(cv, cg, cl, cr);
+    double r0, r1, r2, r3;
+    if (m == 1) {
+      r0 = 1.0; r1 = ub; r2 = vb; r3 = ke;
+    } else if (m == 2) {
+      r0 = 0.0; r1 = 0.0; r2 = 1.0; r3 = vb;
+    } else {
+      r0 = 1.0; r1 = ub - sg * cb; r2 = vb; r3 = hb - sg * ub * cb;
+    }
+    QLo[0] += r0 * cl; QLo[1] += r1 * cl; QLo[2] += r2 * cl; QLo[3] += r3 * cl;
+    QRo[0] += r0 * cr; QRo[1] += r1 * cr; QRo[2] += r2 * cr; QRo[3] += r3 * cr;
+  }
+}
+
 // Normal convective flux of the state W (Sec. 1 flux vectors, rotated).
 __device__ __forceinline__ void conv_flux(const double W[4], double g1inv, double F[4]) {
   const double E = W[3] * g1inv + 0.5 * W[0] * (W[1] * W[1] + W[2] * W[2]);

@@ -108,7 +108,7 @@ __device__ __forceinline__ void load_chimap(const StageParams& P, unsigned char*
   }
 }
 
-template <class C, int DIR, bool DETMLP>
+template <class C, int DIR, bool DETMLP, bool CONS>
 __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0, int tx0,
                                       int ty0, double (&res)[C::CPT][4]) {
   constexpr bool X = (DIR == 0);
@@ -146,6 +146,41 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
     return (ly + H) * RX + (lx + H);
   };
   const int rot[5] = {0, FN, FT, 3, 4};
+  // MEG7-cons: the tile holds (rho, rho u, rho v, E [, T]); primitives of a
+  // cell are formed on the fly, as in the tile load of MEG7-prim
+  auto prim_at = [&](int r, double(&W)[4]) {
+    const double* U = L.U;
+    const double rho = U[r], ir = rcp_nr(rho);
+    W[0] = rho;
+    W[1] = U[FN * RS + r] * ir;
+    W[2] = U[FT * RS + r] * ir;
+    W[3] = (P.gamma - 1.0) * (U[3 * RS + r] - 0.5 * rho * (W[1] * W[1] + W[2] * W[2]));
+  };
+  // viscous flux of interface (line, pos + 1/2) added to F
+  auto visc_at = [&](int line, int pos, int r, double* F) {
+    const double* U = L.U;
+    const int b0 = bidx(line, pos + 3, WD), b1 = bidx(line, pos + 4, WD);
+    const int e0 = bidx(line, pos + 1, WE), e1 = bidx(line, pos + 2, WE);
+    const double* D1 = sD + 1 * NL * WD;
+    const double* D2 = sD + 2 * NL * WD;
+    const double* D4 = sD + 4 * NL * WD;
+    if (CONS) {
+      // velocity gradients by the chain rule d u = (d(rho u) - u d rho) / rho
+      const double* D0 = sD;
+      const double ir0 = rcp_nr(U[r]), ir1 = rcp_nr(U[r + SN]);
+      const double un0 = U[FN * RS + r] * ir0, un1 = U[FN * RS + r + SN] * ir1;
+      const double ut0 = U[FT * RS + r] * ir0, ut1 = U[FT * RS + r + SN] * ir1;
+      viscous_add(un0, un1, ut0, ut1, U[4 * RS + r], U[4 * RS + r + SN],
+                  (D1[b0] - un0 * D0[b0]) * ir0, (D1[b1] - un1 * D0[b1]) * ir1,
+                  (D2[b0] - ut0 * D0[b0]) * ir0, (D2[b1] - ut1 * D0[b1]) * ir1, D4[b0], D4[b1],
+                  sE[e0], sE[e1], sE[NL * WE + e0], sE[NL * WE + e1], inv_dn, P.mu, P.kq, F);
+    } else {
+      viscous_add(U[FN * RS + r], U[FN * RS + r + SN], U[FT * RS + r], U[FT * RS + r + SN],
+                  U[4 * RS + r], U[4 * RS + r + SN], D1[b0], D1[b1], D2[b0], D2[b1], D4[b0],
+                  D4[b1], sE[e0], sE[e1], sE[NL * WE + e0], sE[NL * WE + e1], inv_dn, P.mu,
+                  P.kq, F);
+    }
+  };
 
   // ---- pass 1: per-cell quantities ----------------------------------------
   constexpr int P1R = (NL * WF + NT - 1) / NT;
@@ -160,7 +195,12 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
     const int r = ridx(line, pos);
     const double* U = L.U;
     {
-      const double W[4] = {U[r], U[FN * RS + r], U[FT * RS + r], U[3 * RS + r]};
+      double W[4];
+      if (CONS) {
+        prim_at(r, W);
+      } else {
+        W[0] = U[r]; W[1] = U[FN * RS + r]; W[2] = U[FT * RS + r]; W[3] = U[3 * RS + r];
+      }
       double f[4];
       conv_flux(W, P.g1inv, f);
 #pragma unroll
@@ -183,7 +223,20 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
         L.chi[bidx(line, pd, WD)] = (psi < kPsiC) ? 1 : 0;
       }
     }
-    if (C::VISC && pos >= -1 && pos < N + 1) {
+    if (C::VISC && CONS && pos >= -1 && pos < N + 1) {
+      // tangential derivatives of un, ut by the chain rule
+      const int pe = pos + 1;
+      const double* ur = U + r;
+      const double* un = U + FN * RS + r;
+      const double* ut = U + FT * RS + r;
+      const double gr = grad6(ur[-3 * ST], ur[-2 * ST], ur[-ST], ur[ST], ur[2 * ST], ur[3 * ST]) * inv_dt;
+      const double gn = grad6(un[-3 * ST], un[-2 * ST], un[-ST], un[ST], un[2 * ST], un[3 * ST]) * inv_dt;
+      const double gt = grad6(ut[-3 * ST], ut[-2 * ST], ut[-ST], ut[ST], ut[2 * ST], ut[3 * ST]) * inv_dt;
+      const double ir = rcp_nr(ur[0]);
+      sE[bidx(line, pe, WE)] = (gn - (un[0] * ir) * gr) * ir;
+      sE[NL * WE + bidx(line, pe, WE)] = (gt - (ut[0] * ir) * gr) * ir;
+    }
+    if (C::VISC && !CONS && pos >= -1 && pos < N + 1) {
       const int pe = pos + 1;
 #pragma unroll
       for (int m = 0; m < 2; ++m) {
@@ -244,13 +297,25 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
             Fm[m] = (1052.0 * s) * (f[4] + f[5]) - (250.0 * s) * (f[3] + f[6]) +
                     (38.0 * s) * (f[2] + f[7]) + s * (f[1] + f[8]) - s * (f[0] + f[9]);
           }
+          if (CONS) {
+            // the GRB states above are conservative: to primitives
+            const double QL[4] = {WL[0], WL[1], WL[2], WL[3]};
+            const double QR[4] = {WR[0], WR[1], WR[2], WR[3]};
+            cons_to_prim(QL, P.gamma, WL);
+            cons_to_prim(QR, P.gamma, WR);
+          }
           if (!(WL[0] > 0.0 && WL[3] > 0.0 && WR[0] > 0.0 && WR[3] > 0.0)) {
             // unphysical reconstruction: first-order states and fluxes
             double f0[4], f1[4];
+            if (CONS) {
+              prim_at(r, WL);
+              prim_at(r + SN, WR);
+            } else {
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-              WL[m] = L.U[rot[m] * RS + r];
-              WR[m] = L.U[rot[m] * RS + r + SN];
+              for (int m = 0; m < 4; ++m) {
+                WL[m] = L.U[rot[m] * RS + r];
+                WR[m] = L.U[rot[m] * RS + r + SN];
+              }
             }
             conv_flux(WL, P.g1inv, f0);
             conv_flux(WR, P.g1inv, f1);
@@ -258,18 +323,7 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
             for (int m = 0; m < 4; ++m) Fm[m] = 0.5 * (f0[m] + f1[m]);
           }
           hllc(WL, WR, Fm, P.gamma, P.g1inv, fsm[k]);
-          if (C::VISC) {
-            const double* U = L.U;
-            const int b0 = bidx(line, pos + 3, WD), b1 = bidx(line, pos + 4, WD);
-            viscous_add(U[FN * RS + r], U[FN * RS + r + SN], U[FT * RS + r], U[FT * RS + r + SN],
-                        U[4 * RS + r], U[4 * RS + r + SN], sD[1 * NL * WD + b0],
-                        sD[1 * NL * WD + b1], sD[2 * NL * WD + b0], sD[2 * NL * WD + b1],
-                        sD[4 * NL * WD + b0], sD[4 * NL * WD + b1],
-                        sE[0 * NL * WE + bidx(line, pos + 1, WE)],
-                        sE[0 * NL * WE + bidx(line, pos + 2, WE)],
-                        sE[1 * NL * WE + bidx(line, pos + 1, WE)],
-                        sE[1 * NL * WE + bidx(line, pos + 2, WE)], inv_dn, P.mu, P.kq, fsm[k]);
-          }
+          if (C::VISC) visc_at(line, pos, r, fsm[k]);
           has[k] = true;
         }
       }
@@ -309,15 +363,26 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
     const int r = ridx(line, pos);
     const double* U = L.U;
     double WL[4], WR[4];
-    meg7_char_states(
-        [&](int q, int f) { return U[rot[f] * RS + r + (q - 2) * SN]; },
-        [&](int q, int f) { return sD[f * NL * WD + bidx(line, pos + q + 1, WD)]; },
-        P.gamma, WL, WR);
+    auto Vf = [&](int q, int f) { return U[rot[f] * RS + r + (q - 2) * SN]; };
+    auto Gf = [&](int q, int f) { return sD[f * NL * WD + bidx(line, pos + q + 1, WD)]; };
+    if (CONS) {
+      double QL[4], QR[4];
+      meg7_char_states_cons(Vf, Gf, P.gamma, QL, QR);
+      cons_to_prim(QL, P.gamma, WL);
+      cons_to_prim(QR, P.gamma, WR);
+    } else {
+      meg7_char_states(Vf, Gf, P.gamma, WL, WR);
+    }
     if (!(WL[0] > 0.0 && WL[3] > 0.0 && WR[0] > 0.0 && WR[3] > 0.0)) {
+      if (CONS) {
+        prim_at(r, WL);
+        prim_at(r + SN, WR);
+      } else {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        WL[m] = U[rot[m] * RS + r];
-        WR[m] = U[rot[m] * RS + r + SN];
+        for (int m = 0; m < 4; ++m) {
+          WL[m] = U[rot[m] * RS + r];
+          WR[m] = U[rot[m] * RS + r + SN];
+        }
       }
     }
     double FL[4], FR[4], Fm[4], F[4];
@@ -326,16 +391,7 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
 #pragma unroll
     for (int m = 0; m < 4; ++m) Fm[m] = 0.5 * (FL[m] + FR[m]);
     hllc(WL, WR, Fm, P.gamma, P.g1inv, F);
-    if (C::VISC) {
-      const int b0 = bidx(line, pos + 3, WD), b1 = bidx(line, pos + 4, WD);
-      viscous_add(U[FN * RS + r], U[FN * RS + r + SN], U[FT * RS + r], U[FT * RS + r + SN],
-                  U[4 * RS + r], U[4 * RS + r + SN], sD[1 * NL * WD + b0], sD[1 * NL * WD + b1],
-                  sD[2 * NL * WD + b0], sD[2 * NL * WD + b1], sD[4 * NL * WD + b0],
-                  sD[4 * NL * WD + b1], sE[0 * NL * WE + bidx(line, pos + 1, WE)],
-                  sE[0 * NL * WE + bidx(line, pos + 2, WE)],
-                  sE[1 * NL * WE + bidx(line, pos + 1, WE)],
-                  sE[1 * NL * WE + bidx(line, pos + 2, WE)], inv_dn, P.mu, P.kq, F);
-    }
+    if (C::VISC) visc_at(line, pos, r, F);
 #pragma unroll
     for (int m = 0; m < 4; ++m) sF[m * FSTR + bidx(line, p, WFS)] = F[m];
   }
@@ -381,9 +437,9 @@ __device__ __forceinline__ bool tile_origin(const StageParams& P, int TX, int TY
 }
 
 // Stage Q^(k) of the tile plus its 6-cell halo as primitives (rho, u, v, p
-// [, T = gamma p / rho]) in LDS.  All global loads are issued before any is
+// [, T = gamma p / rho]) in LDS; MEG7-cons keeps (rho, rho u, rho v, E [, T]).  All global loads are issued before any is
 // consumed, so the memory latency is paid once rather than once per round.
-template <class C>
+template <class C, bool CONS = false>
 __device__ __forceinline__ void stage_load(const StageParams& P, double* sU, int tx0, int ty0) {
   constexpr int RS = C::RS, RX = C::RX, H = C::H, NT = C::NT, TX = C::TX, TY = C::TY;
   constexpr int LR = (RS + NT - 1) / NT;
@@ -413,9 +469,9 @@ __device__ __forceinline__ void stage_load(const StageParams& P, double* sU, int
       const double u = mx * ir, v = my * ir;
       const double p = (P.gamma - 1.0) * (E - 0.5 * r * (u * u + v * v));
       sU[c] = r;
-      sU[RS + c] = u;
-      sU[2 * RS + c] = v;
-      sU[3 * RS + c] = p;
+      sU[RS + c] = CONS ? mx : u;
+      sU[2 * RS + c] = CONS ? my : v;
+      sU[3 * RS + c] = CONS ? E : p;
       if (C::VISC) sU[4 * RS + c] = P.gamma * p * ir;
       const bool interior = lx >= 0 && lx < TX && ly >= 0 && ly < TY && tx0 + lx < P.nx &&
                             ty0 + ly < P.ny;
@@ -475,12 +531,12 @@ __device__ __forceinline__ void stage_store(const StageParams& P, const double (
 // One tile of the stage: load, both sweeps, store.  The LDS arrays are
 // passed in so that a kernel can run several tile shapes from one set of
 // arrays sized for the largest (the batched kernel).
-template <class C, bool DETMLP>
+template <class C, bool DETMLP, bool CONS = false>
 __device__ __forceinline__ void stage_tile(const StageParams& P, int tx0, int ty0, double* sU,
                                            double* sPh, unsigned char* sChi,
                                            unsigned short* sQueue, int* sQCount,
                                            unsigned char* sChiF) {
-  stage_load<C>(P, sU, tx0, ty0);
+  stage_load<C, CONS>(P, sU, tx0, ty0);
   if (DETMLP) load_chimap<C>(P, sChiF, tx0, ty0);
   __syncthreads();
   const Lds L{sU, sPh, sChi, sQueue, sQCount, sChiF};
@@ -489,12 +545,12 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int tx0, int ty
   for (int k = 0; k < C::CPT; ++k)
 #pragma unroll
     for (int m = 0; m < 4; ++m) res[k][m] = 0.0;
-  for (int l0 = 0; l0 < C::TY; l0 += C::SX) sweep<C, 0, DETMLP>(P, L, l0, tx0, ty0, res);
-  for (int l0 = 0; l0 < C::TX; l0 += C::SY) sweep<C, 1, DETMLP>(P, L, l0, tx0, ty0, res);
+  for (int l0 = 0; l0 < C::TY; l0 += C::SX) sweep<C, 0, DETMLP, CONS>(P, L, l0, tx0, ty0, res);
+  for (int l0 = 0; l0 < C::TX; l0 += C::SY) sweep<C, 1, DETMLP, CONS>(P, L, l0, tx0, ty0, res);
   stage_store<C>(P, res, tx0, ty0);
 }
 
-template <class C, bool DETMLP>
+template <class C, bool DETMLP, bool CONS = false>
 __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel(StageParams P) {
   __shared__ double sU[C::NF * C::RS];
   __shared__ double sPh[C::PH];
@@ -504,7 +560,7 @@ __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel(StageParams 
   __shared__ int sQCount;
   int tx0, ty0;
   if (!tile_origin(P, C::TX, C::TY, tx0, ty0)) return;
-  stage_tile<C, DETMLP>(P, tx0, ty0, sU, sPh, sChi, sQueue, &sQCount, sChiF);
+  stage_tile<C, DETMLP, CONS>(P, tx0, ty0, sU, sPh, sChi, sQueue, &sQCount, sChiF);
 }
 
 }  // namespace gbr

@@ -23,6 +23,7 @@ GBR_EUNSUPPORTED = -5
 GBR_BC_PERIODIC = 0
 GBR_BC_TRANSMISSIVE = 1
 GBR_RECON_PRIM = 0
+GBR_RECON_CONS = 1
 GBR_MP_FLAGGED = 0
 GBR_PREC_FP64 = 0
 GBR_PREC_FP32_BULK = 1
