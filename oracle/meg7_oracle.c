@@ -57,6 +57,14 @@
  *   R-CHARC The characteristic variables of MEG7-cons use the eigenvectors of
  *          the conservative-variable flux Jacobian at the arithmetic mean of
  *          the two conservative states beside the interface.
+ *   R-G4   The fourth-order GRB (order = 4) is the subset alpha = 4, beta = 0
+ *          of eqs. (good_6tth-order_scheme_flux), (alpha-beta) with the same
+ *          sixth-order gradients.  It replaces the interface states of eq.
+ *          (eqn:grb) wherever they enter (the unlimited states of the smooth
+ *          branch and the value the MP procedure starts from) and the flux
+ *          reconstruction by eq. (fourth); F(f_R) is the mirror image of
+ *          eq. (fourth), as eq. (flux-right) mirrors eq. (flux-full).  The
+ *          detector, the MP bounds, HLLC and the viscous flux are unchanged.
  *   R-MPG  In eq. (eqn:mp-procedure) the hat on Phi_{j-1} and the mixed
  *          i/j subscripts are typesetting slips: plain Phi_{j-1}, index j.
  *          The MP xi (=7) and the detector xi (=1e-3) are different
@@ -84,6 +92,7 @@ typedef struct {
     int mp_mode;   /* 0: MP only where sigma=0 (R-MP); 1: MP test everywhere */
     int force_sigma; /* -1: detector decides; 0 or 1: force sigma (tests)    */
     int recon;     /* 0: primitive variables (MEG7-prim); 1: conservative (MEG7-cons) */
+    int order;     /* 7: the seventh-order GRB of Sec. 2.2; 4: its fourth-order subset */
 } orc_cfg;
 
 /* ---------------------------------------------------------------------- */
@@ -202,6 +211,74 @@ static double flux_right(const double *f)
             + 484.0 * f[0] - 104.0 * f[-1] + 16.0 * f[-2] - f[-3]) / 840.0;
 }
 
+/* The two-parameter family of Sec. 2.2, written out in the paper's order
+ * (used for the fourth-order subset, and by tests at any alpha, beta).
+ * p, g point at cell j; p[-2..2] and g[-1..1] are read.                   */
+
+/* eq. (alpha-beta): one-sided values at interface k+1/2 (p, g at cell k). */
+static void ab_face_states(const double *p, const double *g, double beta, double *PL,
+                           double *PR)
+{
+    *PL = p[0] + 0.5 * g[0] + beta * (p[1] - 2.0 * p[0] + p[-1]);
+    *PR = p[1] - 0.5 * g[1] + beta * (p[2] - 2.0 * p[1] + p[0]);
+}
+
+/* eq. (good_6tth-order_scheme_flux), times Delta x: the gradient at k+1/2. */
+static double ab_face_grad(const double *p, const double *g, double alpha, double beta)
+{
+    double PL, PR;
+    ab_face_states(p, g, beta, &PL, &PR);
+    return 0.5 * (g[0] + g[1]) + 0.5 * alpha * (PR - PL);
+}
+
+/* eq. (eqn:how-second), times Delta x^2: the second derivative in cell j. */
+static double ab_second(const double *p, const double *g, double alpha, double beta)
+{
+    return ab_face_grad(p, g, alpha, beta) - ab_face_grad(p - 1, g - 1, alpha, beta);
+}
+
+/* eq. (eqn:lingrb): left and right states at j+1/2. */
+static double grb_ab_left(const double *p, const double *g, double alpha, double beta)
+{
+    return p[0] + 0.5 * g[0] + ab_second(p, g, alpha, beta) / 12.0;
+}
+static double grb_ab_right(const double *p, const double *g, double alpha, double beta)
+{
+    return p[1] - 0.5 * g[1] + ab_second(p + 1, g + 1, alpha, beta) / 12.0;
+}
+
+/* eq. (fourth): F(f_L) of the fourth-order GRB at j+1/2 from f[-4..4]. */
+static double flux4_left(const double *f)
+{
+    return (1050.0 * f[0] - 309.0 * f[-1] + 64.0 * f[-2] - 3.0 * f[-3] - f[-4]
+            + 771.0 * f[1] - 152.0 * f[2] + 21.0 * f[3] - f[4]) / 1440.0;
+}
+
+/* Mirror image of eq. (fourth): F(f_R) at j+1/2 from f[-3..5]. */
+static double flux4_right(const double *f)
+{
+    return (1050.0 * f[1] - 309.0 * f[2] + 64.0 * f[3] - 3.0 * f[4] - f[5]
+            + 771.0 * f[0] - 152.0 * f[-1] + 21.0 * f[-2] - f[-3]) / 1440.0;
+}
+
+/* Interface states and flux reconstruction of the selected order. */
+static double grb_L(int order, const double *p, const double *g)
+{
+    return order == 4 ? grb_ab_left(p, g, 4.0, 0.0) : grb_left(p, g);
+}
+static double grb_R(int order, const double *p, const double *g)
+{
+    return order == 4 ? grb_ab_right(p, g, 4.0, 0.0) : grb_right(p, g);
+}
+static double flux_L(int order, const double *f)
+{
+    return order == 4 ? flux4_left(f) : flux_left(f);
+}
+static double flux_R(int order, const double *f)
+{
+    return order == 4 ? flux4_right(f) : flux_right(f);
+}
+
 /* Exported stencil applications for the polynomial / symbol tests. */
 void orc_apply_interface(const double *v10, const double *g6, double out[4])
 {
@@ -212,6 +289,23 @@ void orc_apply_interface(const double *v10, const double *g6, double out[4])
     out[1] = grb_right(v10 + 4, g6 + 2);
     out[2] = flux_left(v10 + 4);
     out[3] = flux_right(v10 + 4);
+}
+
+/* As orc_apply_interface for the fourth-order subset (order 4). */
+void orc_apply_interface4(const double *v10, const double *g6, double out[4])
+{
+    out[0] = grb_L(4, v10 + 4, g6 + 2);
+    out[1] = grb_R(4, v10 + 4, g6 + 2);
+    out[2] = flux_L(4, v10 + 4);
+    out[3] = flux_R(4, v10 + 4);
+}
+
+/* GRB states of the two-parameter family at any (alpha, beta): out = {L, R}. */
+void orc_apply_interface_ab(const double *v10, const double *g6, double alpha, double beta,
+                            double out[2])
+{
+    out[0] = grb_ab_left(v10 + 4, g6 + 2, alpha, beta);
+    out[1] = grb_ab_right(v10 + 4, g6 + 2, alpha, beta);
 }
 
 static double minmod(double a, double b)
@@ -232,11 +326,12 @@ static double mp_curv(const double *p, const double *g)
     return 2.0 * (p[1] - 2.0 * p[0] + p[-1]) - 0.5 * (g[1] - g[-1]);
 }
 
-/* Sec. 2.3: MEG7 left value at j+1/2 for one scalar component.
- * p, g point at cell j; p[-2..3], g[-2..3] are read. */
-double orc_meg7_left(const double *p, const double *g, int *limited)
+/* Sec. 2.3: MEG7 left value at j+1/2 for one scalar component, starting
+ * from the GRB state of the given order.  p, g point at cell j; p[-2..3],
+ * g[-2..3] are read. */
+static double meg7_left_o(int order, const double *p, const double *g, int *limited)
 {
-    double phi = grb_left(p, g);
+    double phi = grb_L(order, p, g);
     double phi_mp = p[0] + minmod(p[1] - p[0], XI_MP * (p[0] - p[-1]));
     if ((phi - p[0]) * (phi - phi_mp) <= MP_TOL) {
         if (limited) *limited = 0;
@@ -254,10 +349,10 @@ double orc_meg7_left(const double *p, const double *g, int *limited)
     return phi + minmod(pmin - phi, pmax - phi);
 }
 
-/* Mirror image of orc_meg7_left: right value at j+1/2 (p, g point at j). */
-double orc_meg7_right(const double *p, const double *g, int *limited)
+/* Mirror image of meg7_left_o: right value at j+1/2 (p, g point at j). */
+static double meg7_right_o(int order, const double *p, const double *g, int *limited)
 {
-    double phi = grb_right(p, g);
+    double phi = grb_R(order, p, g);
     double phi_mp = p[1] + minmod(p[0] - p[1], XI_MP * (p[1] - p[2]));
     if ((phi - p[1]) * (phi - phi_mp) <= MP_TOL) {
         if (limited) *limited = 0;
@@ -273,6 +368,16 @@ double orc_meg7_right(const double *p, const double *g, int *limited)
     double pmax = fmin(max3(p[1], p[0], md), max3(p[1], ul, lc));
     if (limited) *limited = 1;
     return phi + minmod(pmin - phi, pmax - phi);
+}
+
+/* The seventh-order MEG7 values (exported for the tests). */
+double orc_meg7_left(const double *p, const double *g, int *limited)
+{
+    return meg7_left_o(7, p, g, limited);
+}
+double orc_meg7_right(const double *p, const double *g, int *limited)
+{
+    return meg7_right_o(7, p, g, limited);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -452,8 +557,8 @@ static void line_flux(const orc_line *L, const orc_cfg *c, double Fout[4], int *
         /* MEG7-cons, Sec. 2.2: unlimited GRB states on conservative variables */
         double QL[4], QR[4];
         for (int m = 0; m < 4; ++m) {
-            QL[m] = grb_left(&L->Qc[m][4], &L->GQ[m][2]);
-            QR[m] = grb_right(&L->Qc[m][4], &L->GQ[m][2]);
+            QL[m] = grb_L(c->order, &L->Qc[m][4], &L->GQ[m][2]);
+            QR[m] = grb_R(c->order, &L->Qc[m][4], &L->GQ[m][2]);
         }
         cons_to_prim(QL, gamma, WL);
         cons_to_prim(QR, gamma, WR);
@@ -474,8 +579,8 @@ static void line_flux(const orc_line *L, const orc_cfg *c, double Fout[4], int *
         double wl[4], wr[4], QL[4], QR[4];
         for (int m = 0; m < 4; ++m) {
             int la = 0, lb = 0;
-            wl[m] = orc_meg7_left(&cw[m][2], &cg[m][2], &la);
-            wr[m] = orc_meg7_right(&cw[m][2], &cg[m][2], &lb);
+            wl[m] = meg7_left_o(c->order, &cw[m][2], &cg[m][2], &la);
+            wr[m] = meg7_right_o(c->order, &cw[m][2], &cg[m][2], &lb);
             if (nlimited) *nlimited += la + lb;
         }
         orc_char_cons_bwd(&cs, wl, QL);
@@ -485,8 +590,8 @@ static void line_flux(const orc_line *L, const orc_cfg *c, double Fout[4], int *
     } else if (!use_mp) {
         /* Sec. 2.2: unlimited GRB states, eq. (eqn:grb), on primitives */
         for (int m = 0; m < 4; ++m) {
-            WL[m] = grb_left(&L->W[m][4], &L->G[m][2]);
-            WR[m] = grb_right(&L->W[m][4], &L->G[m][2]);
+            WL[m] = grb_L(c->order, &L->W[m][4], &L->G[m][2]);
+            WR[m] = grb_R(c->order, &L->W[m][4], &L->G[m][2]);
         }
     } else {
         /* Sec. 2.3: MEG7 in characteristic variables (R-CHAR) */
@@ -504,8 +609,8 @@ static void line_flux(const orc_line *L, const orc_cfg *c, double Fout[4], int *
         double wl[4], wr[4];
         for (int m = 0; m < 4; ++m) {
             int la = 0, lb = 0;
-            wl[m] = orc_meg7_left(&cw[m][2], &cg[m][2], &la);
-            wr[m] = orc_meg7_right(&cw[m][2], &cg[m][2], &lb);
+            wl[m] = meg7_left_o(c->order, &cw[m][2], &cg[m][2], &la);
+            wr[m] = meg7_right_o(c->order, &cw[m][2], &cg[m][2], &lb);
             if (nlimited) *nlimited += la + lb;
         }
         char_bwd(wl, rb, cb, WL);
@@ -521,8 +626,8 @@ static void line_flux(const orc_line *L, const orc_cfg *c, double Fout[4], int *
             for (int m = 0; m < 4; ++m) f[m][k] = ff[m];
         }
         for (int m = 0; m < 4; ++m) {
-            FL[m] = flux_left(&f[m][4]);
-            FR[m] = flux_right(&f[m][4]);
+            FL[m] = flux_L(c->order, &f[m][4]);
+            FR[m] = flux_R(c->order, &f[m][4]);
         }
     } else {
         conv_flux(WL, gamma, FL);   /* F(Q_L) */
@@ -762,7 +867,8 @@ static void gather_y(const orc_cfg *c, const orc_fields *F, int i, int j, orc_li
 static int cfg_ok(const orc_cfg *c)
 {
     return c && c->nx >= 2 * NG && c->ny >= 2 * NG && c->gamma > 1.0 && c->mu >= 0.0
-        && c->Pr > 0.0 && c->x1 > c->x0 && c->y1 > c->y0 && (c->recon == 0 || c->recon == 1);
+        && c->Pr > 0.0 && c->x1 > c->x0 && c->y1 > c->y0 && (c->recon == 0 || c->recon == 1)
+        && (c->order == 7 || c->order == 4);
 }
 
 /* eqs. (eqn-differencing_residual), (deriv): Res = -dF/dx - dG/dy.

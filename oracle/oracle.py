@@ -20,7 +20,7 @@ class OrcCfg(C.Structure):
         ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
         ("bc_x", C.c_int), ("bc_y", C.c_int),
         ("gamma", C.c_double), ("mu", C.c_double), ("Pr", C.c_double),
-        ("mp_mode", C.c_int), ("force_sigma", C.c_int), ("recon", C.c_int),
+        ("mp_mode", C.c_int), ("force_sigma", C.c_int), ("recon", C.c_int), ("order", C.c_int),
     ]
 
 
@@ -59,6 +59,10 @@ def lib():
         L.orc_table.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.orc_apply_interface.restype = None
         L.orc_apply_interface.argtypes = [dp, dp, dp]
+        L.orc_apply_interface4.restype = None
+        L.orc_apply_interface4.argtypes = [dp, dp, dp]
+        L.orc_apply_interface_ab.restype = None
+        L.orc_apply_interface_ab.argtypes = [dp, dp, C.c_double, C.c_double, dp]
         L.orc_meg7_left.restype = C.c_double
         L.orc_meg7_left.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int)]
         L.orc_meg7_right.restype = C.c_double
@@ -82,9 +86,11 @@ def lib():
 
 
 def make_cfg(nx, ny, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc_x=BC_PERIODIC, bc_y=BC_PERIODIC,
-             gamma=1.4, mu=0.0, Pr=0.72, mp_mode=0, force_sigma=-1, recon=0):
-    """recon 0: MEG7-prim (primitive variables), 1: MEG7-cons (conservative)."""
-    return OrcCfg(nx, ny, x0, x1, y0, y1, bc_x, bc_y, gamma, mu, Pr, mp_mode, force_sigma, recon)
+             gamma=1.4, mu=0.0, Pr=0.72, mp_mode=0, force_sigma=-1, recon=0, order=7):
+    """recon 0: MEG7-prim (primitive variables), 1: MEG7-cons (conservative);
+    order 7: the seventh-order GRB, 4: its fourth-order subset (alpha=4, beta=0)."""
+    return OrcCfg(nx, ny, x0, x1, y0, y1, bc_x, bc_y, gamma, mu, Pr, mp_mode, force_sigma, recon,
+                  order)
 
 
 def _ptr(a):
@@ -179,10 +185,21 @@ def table(which):
     return [num[k] for k in range(n)], den.value
 
 
-def apply_interface(v10, g6):
+def apply_interface(v10, g6, order=7):
+    """{GRB left, GRB right, F(f_L), F(f_R)} at j+1/2 from values at offsets
+    -4..5 and gradients at -2..3, for the seventh-order GRB or its
+    fourth-order subset."""
     out = np.empty(4)
-    lib().orc_apply_interface(np.ascontiguousarray(v10, np.float64),
-                              np.ascontiguousarray(g6, np.float64), out)
+    fn = lib().orc_apply_interface4 if order == 4 else lib().orc_apply_interface
+    fn(np.ascontiguousarray(v10, np.float64), np.ascontiguousarray(g6, np.float64), out)
+    return out
+
+
+def apply_interface_ab(v10, g6, alpha, beta):
+    """GRB left and right states at j+1/2 of the two-parameter family."""
+    out = np.empty(2)
+    lib().orc_apply_interface_ab(np.ascontiguousarray(v10, np.float64),
+                                 np.ascontiguousarray(g6, np.float64), alpha, beta, out)
     return out
 
 

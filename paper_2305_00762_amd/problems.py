@@ -15,6 +15,8 @@ Families
              transmissive boundaries.
   shear      periodic double shear layer, tanh profile +/-0.5, Mach 0.3,
              seeded sinusoidal perturbation on modes 1-8, Re = 1e4, Pr = 0.72.
+  taylor_green  inviscid 2D Taylor-Green vortex (the z = 0 plane of the
+             paper's Taylor-Green initial state), periodic on [0, 2 pi)^2.
 """
 from dataclasses import dataclass, field
 import math
@@ -168,6 +170,25 @@ def shear(n, seed=0, cfl=0.2, ny=None, delta=0.02, mach=0.3, Re=1.0e4, Pr=0.72,
     return P
 
 
+# ------------------------------------------------------------ taylor-green ---
+def taylor_green(n, cfl=0.5, ny=None, p0=100.0):
+    """Inviscid Taylor-Green vortex in 2D: the z = 0 plane of the initial state
+    of the paper's Taylor-Green comparison (rho = 1, u = sin x cos y,
+    v = -cos x sin y, p = p0 + (3 (cos 2x + cos 2y) - 2)/16) on [0, 2 pi)^2,
+    periodic.  Mach number about 0.085 at p0 = 100."""
+    ny = n if ny is None else ny
+    L = 2.0 * math.pi
+    X, Y = cell_centres(n, ny, 0.0, L, 0.0, L)
+    rho = np.ones_like(X)
+    u = np.sin(X) * np.cos(Y)
+    v = -np.cos(X) * np.sin(Y)
+    p = p0 + (3.0 * (np.cos(2.0 * X) + np.cos(2.0 * Y)) - 2.0) / 16.0
+    P = Problem("taylor_green", n, ny, 0.0, L, 0.0, L, BC_PERIODIC, BC_PERIODIC,
+                GAMMA, 0.0, 0.72, cfl)
+    P.Q = prim_to_state(rho, u, v, p)
+    return P
+
+
 # ------------------------------------------------------------------ misc ---
 def free_stream(n, rho=1.0, u=0.3, v=-0.2, p=0.7, bc=BC_PERIODIC, mu=0.0, ny=None):
     ny = n if ny is None else ny
@@ -185,6 +206,8 @@ def make(family, n, seed=0, **kw):
         return riemann(n, seed=seed, **kw)
     if family == "shear":
         return shear(n, seed=seed, **kw)
+    if family == "taylor_green":
+        return taylor_green(n, **kw)
     raise ValueError(family)
 
 
