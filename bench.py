@@ -46,6 +46,10 @@ WORKLOADS = {
     "riemann4096": ("riemann", 4096, 5000, 50,
                     "2D Euler four-quadrant Riemann problem, 4096x4096, seed 5000, transmissive, "
                     "CFL 0.2"),
+    "taylor_green64": ("taylor_green", 64, 0, 2600,
+                       "2D inviscid Taylor-Green vortex 64x64 on [0, 2 pi)^2 (the z = 0 plane of the "
+                       "paper's Taylor-Green initial state, Mach ~0.085), periodic, CFL 0.5; 2600 "
+                       "steps reach t ~ 10"),
     "batch512": ("batch", 0, 0, 10,
                  "512 independent grids, side n ~ U{64..768} (seed 0), families uniform over "
                  "vortex / Riemann / shear layer, per-grid seed 10000 + index; one launch per "
@@ -53,12 +57,15 @@ WORKLOADS = {
 }
 
 PATHS = {
-    # name: (precision, learned detector, dtype, kernel name, conservative reconstruction)
-    "fp32_mlp": ("fp32", True, "f32+f64", "meg7_stage_kernel_f32<mlp>", False),
-    "fp32": ("fp32", False, "f32+f64", "meg7_stage_kernel_f32", False),
-    "fp64": ("fp64", False, "f64", "meg7_stage_kernel", False),
+    # name: (precision, learned detector, dtype, kernel name, conservative
+    #        reconstruction, GRB order)
+    "fp32_mlp": ("fp32", True, "f32+f64", "meg7_stage_kernel_f32<mlp>", False, 7),
+    "fp32": ("fp32", False, "f32+f64", "meg7_stage_kernel_f32", False, 7),
+    "fp64": ("fp64", False, "f64", "meg7_stage_kernel", False, 7),
     # MEG7-cons (Table 2): GRB and the MP procedure on conservative variables
-    "fp64_cons": ("fp64", False, "f64", "meg7_stage_kernel<cons>", True),
+    "fp64_cons": ("fp64", False, "f64", "meg7_stage_kernel<cons>", True, 7),
+    # the fourth-order GRB subset (alpha = 4, beta = 0; eq. fourth)
+    "fp64_g4": ("fp64", False, "f64", "meg7_stage_kernel<g4>", False, 4),
 }
 
 
@@ -102,7 +109,7 @@ class Path:
         import torch
         from paper_2305_00762_amd import gbr
         self.gbr, self.P, self.stream = gbr, P, stream
-        prec_name, mlp, self.dtype, self.kernel, self.cons = PATHS[path]
+        prec_name, mlp, self.dtype, self.kernel, self.cons, order = PATHS[path]
         self.ctx = gbr.gbr_init(P.nx, P.ny, P.gamma, P.mu, P.Pr)
         gbr.gbr_set_geometry(self.ctx, *P.geometry())
         prec = gbr.GBR_PREC_FP32_BULK if prec_name == "fp32" else gbr.GBR_PREC_FP64
@@ -116,8 +123,12 @@ class Path:
             det = gbr.GBR_DET_MLP
         recon = gbr.GBR_RECON_CONS if self.cons else gbr.GBR_RECON_PRIM
         gbr.gbr_set_scheme(self.ctx, recon, gbr.GBR_MP_FLAGGED, prec, det)
+        if order != 7:
+            gbr.gbr_set_order(self.ctx, order)
+        self.order = order
         dev = torch.device("cuda:0")
         self.Q = [torch.from_numpy(P.Q).to(dev) for _ in range(3)]
+        self.Q0 = self.Q[0].clone()
         self.dt = torch.zeros(1, dtype=torch.float64, device=dev)
         torch.cuda.synchronize()
         if tiling == "auto":
@@ -177,18 +188,23 @@ class Path:
             self.gbr.gbr_mlp_destroy(self.net)
 
 
+def kinetic_energy(Q):
+    return float((0.5 * (Q[1] * Q[1] + Q[2] * Q[2]) / Q[0]).mean())
+
+
 def diff(Qa, Qb):
     d = (Qa - Qb).abs().reshape(4, -1)
     return ([float(v) for v in d.mean(dim=1).cpu()], [float(v) for v in d.max(dim=1).values.cpu()])
 
 
-def cpu_baseline(P, seconds, max_steps=50, recon=0):
+def cpu_baseline(P, seconds, max_steps=50, recon=0, order=7):
     """The CPU oracle on a bounded sample of the same workload: whole SSP-RK3
     steps on the full grid from the initial state until about `seconds` of
     host time have passed.  Returns (record, state after the sample, steps)."""
     import numpy as np
     import oracle as O
-    cfg = O.make_cfg(P.nx, P.ny, *P.geometry(), gamma=P.gamma, mu=P.mu, Pr=P.Pr, recon=recon)
+    cfg = O.make_cfg(P.nx, P.ny, *P.geometry(), gamma=P.gamma, mu=P.mu, Pr=P.Pr, recon=recon,
+                     order=order)
     Q = np.ascontiguousarray(P.Q.copy())
     steps, t0 = 0, time.perf_counter()
     while True:
@@ -239,8 +255,9 @@ def bench_batch(a, steps):
     cells = sum(p.nx * p.ny for p in ps)
     torch.cuda.set_device(0)
     s = torch.cuda.Stream()
-    if PATHS[a.path][4]:
-        print("bench.py: batched grids run MEG7-prim; use --path fp64 or fp32", file=sys.stderr)
+    if PATHS[a.path][4] or PATHS[a.path][5] != 7:
+        print("bench.py: batched grids run seventh-order MEG7-prim; use --path fp64 or fp32",
+              file=sys.stderr)
         sys.exit(2)
     prec = gbr.GBR_PREC_FP64 if a.path == "fp64" else gbr.GBR_PREC_FP32_BULK
     with torch.cuda.stream(s):
@@ -363,7 +380,7 @@ def main():
     # the timed launches over their summed duration from the library's events
     alg_bytes = sum(BYTES_PER_CELL_STAGE.values()) * cells * steps
     achieved = alg_bytes / (stage_ms * 1e-3) / 1e9
-    kname = head.kernel.replace("<mlp>", "_mlp").replace("<cons>", "_cons")
+    kname = head.kernel.replace("<mlp>", "_mlp").replace("<cons>", "_cons").replace("<g4>", "_g4")
     traffic = load_traffic(kname, a.workload)
     out = {
         "metric": METRIC,
@@ -416,10 +433,16 @@ def main():
         out["speedup_vs_fp64_plain"] = value / bval
         out["error_vs_fp64_plain"] = {"after_steps": a.warmup + steps, "L1": l1, "Linf": linf,
                                       "vars": ["rho", "rho_u", "rho_v", "E"]}
+        if fam == "taylor_green":
+            # kinetic-energy budget of the inviscid vortex: KE(t)/KE(0) of both paths
+            out["kinetic_energy_ratio"] = {"after_steps": a.warmup + steps,
+                                           a.path: kinetic_energy(Qhead) / kinetic_energy(head.Q0),
+                                           "fp64": kinetic_energy(base.Q[0]) / kinetic_energy(head.Q0)}
         base.close()
 
     if not a.no_cpu_baseline:
-        rec, Qo, osteps = cpu_baseline(P, a.cpu_seconds, recon=1 if head.cons else 0)
+        rec, Qo, osteps = cpu_baseline(P, a.cpu_seconds, recon=1 if head.cons else 0,
+                                       order=head.order)
         out["cpu_baseline"] = rec
         head.reset()
         head.run(osteps, 0)

@@ -89,6 +89,19 @@ int gbr_set_geometry(gbr_ctx *ctx, double x0, double x1, double y0, double y1,
  * and leave the scheme unchanged. */
 int gbr_set_scheme(gbr_ctx *ctx, int recon, int mp_mode, int precision, int detector);
 
+/* GRB order: 7 (default; eq. eqn:grb and the flux reconstruction of eqs.
+ * flux-full, flux-right) or 4, the fourth-order subset alpha = 4, beta = 0 of
+ * eqs. (good_6tth-order_scheme_flux), (alpha-beta) with the same sixth-order
+ * gradients (Sec. 2.2 remark on the fourth-order scheme; the flux
+ * reconstruction of eq. (fourth) and its mirror image).  The order replaces
+ * the GRB states wherever they enter (smooth branch and the value the MP
+ * procedure starts from) and the flux reconstruction; detector, MP bounds,
+ * HLLC and viscous flux are unchanged.  Order 4 runs in FP64 with the plain
+ * detector, in either variable set, on the 31x15 and 15x15 tilings; otherwise
+ * GBR_EUNSUPPORTED (the scheme is left unchanged).  GBR_EINVAL for an order
+ * other than 7 or 4. */
+int gbr_set_order(gbr_ctx *ctx, int order);
+
 /* Res = Res(Q), the semi-discrete right-hand side of eq.
  * (eqn-differencing_residual) with the flux differences of eq. (deriv).
  * Q and Res: device [4][ny][nx]; must not overlap. */

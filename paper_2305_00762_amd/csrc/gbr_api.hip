@@ -17,10 +17,11 @@ namespace {
 
 using namespace gbr;
 
-template <class C, bool MLP = false, bool CONS = false>
+template <class C, bool MLP = false, bool CONS = false, int ORD = 7>
 void launch_cfg(const StageParams& P, hipStream_t s) {
   static_assert(C::LDS_BYTES <= 160 * 1024, "LDS per workgroup");
-  hipLaunchKernelGGL((meg7_stage_kernel<C, MLP, CONS>), dim3(P.ntiles), dim3(C::NT), 0, s, P);
+  hipLaunchKernelGGL((meg7_stage_kernel<C, MLP, CONS, ORD>), dim3(P.ntiles), dim3(C::NT), 0, s,
+                     P);
 }
 template <class C, bool MLP = false>
 void launch_cfg_f32(const StageParams& P, hipStream_t s) {
@@ -38,6 +39,7 @@ struct TileVariant {
   LaunchFn fn[2][2][2];   // [precision FP64/FP32-bulk][viscous][learned detector]; null: no build
   const char* name;
   LaunchFn cons[2];       // MEG7-cons, FP64 with the plain detector: [viscous]; null: no build
+  LaunchFn g4[2][2];      // fourth-order GRB, FP64 with the plain detector: [cons][viscous]
 };
 using E31 = TileCfg<31, 15, 15, 16, 256, false>;
 using V31 = TileCfg<31, 15, 8, 16, 256, true>;
@@ -50,14 +52,18 @@ const TileVariant kVariants[] = {
       {{launch_cfg_f32<E31>, launch_cfg_f32<E31, true>},
        {launch_cfg_f32<V31>, launch_cfg_f32<V31, true>}}},
      "31x15",
-     {launch_cfg<E31, false, true>, launch_cfg<V31, false, true>}},
+     {launch_cfg<E31, false, true>, launch_cfg<V31, false, true>},
+     {{launch_cfg<E31, false, false, 4>, launch_cfg<V31, false, false, 4>},
+      {launch_cfg<E31, false, true, 4>, launch_cfg<V31, false, true, 4>}}},
     // 16 interfaces per line both ways; 3-4 workgroups/CU
     {15, 15,
      {{{launch_cfg<E15>, launch_cfg<E15, true>}, {launch_cfg<V15>, launch_cfg<V15, true>}},
       {{launch_cfg_f32<E15>, launch_cfg_f32<E15, true>},
        {launch_cfg_f32<V15>, launch_cfg_f32<V15, true>}}},
      "15x15",
-     {launch_cfg<E15, false, true>, launch_cfg<V15, false, true>}},
+     {launch_cfg<E15, false, true>, launch_cfg<V15, false, true>},
+     {{launch_cfg<E15, false, false, 4>, launch_cfg<V15, false, false, 4>},
+      {launch_cfg<E15, false, true, 4>, launch_cfg<V15, false, true, 4>}}},
     // 64 x-interfaces per row, 8 y-interfaces per column (Euler, plain detector)
     {63, 7,
      {{{launch_cfg<TileCfg<63, 7, 7, 32, 256, false>>,
@@ -67,7 +73,8 @@ const TileVariant kVariants[] = {
         launch_cfg_f32<TileCfg<63, 7, 7, 32, 256, false>, true>},
        {nullptr, nullptr}}},
      "63x7",
-     {nullptr, nullptr}},
+     {nullptr, nullptr},
+     {{nullptr, nullptr}, {nullptr, nullptr}}},
     // 31x8 / 15x16 interface blocks sized for 3 workgroups per CU in FP32 bulk
     {30, 15,
      {{{launch_cfg<TileCfg<30, 15, 15, 15, 256, false>>,
@@ -77,7 +84,8 @@ const TileVariant kVariants[] = {
         launch_cfg_f32<TileCfg<30, 15, 8, 15, 256, false, 3>, true>},
        {nullptr, nullptr}}},
      "30x15",
-     {nullptr, nullptr}},
+     {nullptr, nullptr},
+     {{nullptr, nullptr}, {nullptr, nullptr}}},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -126,6 +134,7 @@ struct gbr_ctx {
   double x0, x1, y0, y1;
   int bcx, bcy;
   int recon, mp_mode, precision, detector;
+  int order;                  // GRB order: 7 or 4
   int device;
   int export_flags;
   unsigned* d_status;         // [4]
@@ -189,7 +198,7 @@ int gbr_init(int nx, int ny, double gamma, double mu, double Pr, gbr_ctx** out) 
   c->nx = nx; c->ny = ny; c->gamma = gamma; c->mu = mu; c->Pr = Pr;
   c->x0 = 0.0; c->x1 = 1.0; c->y0 = 0.0; c->y1 = 1.0;
   c->bcx = c->bcy = GBR_BC_PERIODIC;
-  c->recon = GBR_RECON_PRIM; c->mp_mode = GBR_MP_FLAGGED;
+  c->recon = GBR_RECON_PRIM; c->mp_mode = GBR_MP_FLAGGED; c->order = 7;
   c->precision = GBR_PREC_FP64; c->detector = GBR_DET_PLAIN;
   if (hipGetDevice(&c->device) != hipSuccess) { delete c; return GBR_EDEVICE; }
   if (hipMalloc(&c->d_status, 4 * sizeof(unsigned)) != hipSuccess) { delete c; return GBR_ENOMEM; }
@@ -236,10 +245,20 @@ int gbr_set_scheme(gbr_ctx* c, int recon, int mp_mode, int precision, int detect
   if (mp_mode != GBR_MP_FLAGGED) return GBR_EUNSUPPORTED;
   if (precision != GBR_PREC_FP64 && precision != GBR_PREC_FP32_BULK) return GBR_EUNSUPPORTED;
   if (detector != GBR_DET_PLAIN && detector != GBR_DET_MLP) return GBR_EUNSUPPORTED;
-  if (recon == GBR_RECON_CONS && (precision != GBR_PREC_FP64 || detector != GBR_DET_PLAIN))
+  if ((recon == GBR_RECON_CONS || c->order == 4) &&
+      (precision != GBR_PREC_FP64 || detector != GBR_DET_PLAIN))
     return GBR_EUNSUPPORTED;
   if (detector == GBR_DET_MLP && !c->mlp_ready) return GBR_EINVAL;
   c->recon = recon; c->mp_mode = mp_mode; c->precision = precision; c->detector = detector;
+  return GBR_OK;
+}
+
+int gbr_set_order(gbr_ctx* c, int order) {
+  if (!c) return GBR_EINVAL;
+  if (order != 7 && order != 4) return GBR_EINVAL;
+  if (order == 4 && (c->precision != GBR_PREC_FP64 || c->detector != GBR_DET_PLAIN))
+    return GBR_EUNSUPPORTED;
+  c->order = order;
   return GBR_OK;
 }
 
@@ -283,6 +302,7 @@ int gbr_check(gbr_ctx* c, void* stream) {
 // variant has no build for it.
 static LaunchFn variant_fn(const gbr_ctx* c, int v) {
   const int visc = c->mu > 0.0 ? 1 : 0;
+  if (c->order == 4) return kVariants[v].g4[c->recon == GBR_RECON_CONS ? 1 : 0][visc];
   if (c->recon == GBR_RECON_CONS) return kVariants[v].cons[visc];
   const int prec = c->precision == GBR_PREC_FP32_BULK ? 1 : 0;
   const int det = c->detector == GBR_DET_MLP ? 1 : 0;

@@ -80,6 +80,46 @@ __device__ __forceinline__ double grb_right(const double* v, const double* g) {
          (420.0 * s) * g[3] + (60.0 * s) * (g[2] - g[4]);
 }
 
+// Fourth-order GRB states: the subset alpha = 4, beta = 0 of eqs.
+// (good_6tth-order_scheme_flux), (alpha-beta) put into eq. (eqn:lingrb),
+//   Phi^L = (4 (Phi_{j-1} + Phi_{j+1}) + 16 Phi_j + Phi'_{j-1} + 12 Phi'_j - Phi'_{j+1}) / 24
+// and its mirror image for Phi^R at j+1/2.  Same v, g layout as grb_left.
+__device__ __forceinline__ double grb4_left(const double* v, const double* g) {
+  constexpr double s = 1.0 / 24.0;
+  return (4.0 * s) * (v[1] + v[3]) + (16.0 * s) * v[2] + (12.0 * s) * g[2] + s * (g[1] - g[3]);
+}
+__device__ __forceinline__ double grb4_right(const double* v, const double* g) {
+  constexpr double s = 1.0 / 24.0;
+  return (4.0 * s) * (v[2] + v[4]) + (16.0 * s) * v[3] - (12.0 * s) * g[3] + s * (g[2] - g[4]);
+}
+
+// GRB states of the selected order: 7 (eq. eqn:grb) or 4 (the subset above).
+template <int ORD>
+__device__ __forceinline__ double grb_l(const double* v, const double* g) {
+  return ORD == 4 ? grb4_left(v, g) : grb_left(v, g);
+}
+template <int ORD>
+__device__ __forceinline__ double grb_r(const double* v, const double* g) {
+  return ORD == 4 ? grb4_right(v, g) : grb_right(v, g);
+}
+
+// Mean of the reconstructed cell fluxes, (F(f_L) + F(f_R))/2 at j+1/2, from
+// f[q] = f_{j+q-4} (q = 0..9).  The sum of a left stencil and its mirror image
+// is symmetric about the interface, so pairs are added first:
+//   order 7, eqs. (flux-full), (flux-right): (1052, -250, 38, 1, -1) / 1680;
+//   order 4, eq. (fourth) and its mirror:    (1821, -461, 85, -4, -1) / 2880.
+template <int ORD>
+__device__ __forceinline__ double flux_mean(const double* f) {
+  if (ORD == 4) {
+    constexpr double s = 1.0 / 2880.0;
+    return (1821.0 * s) * (f[4] + f[5]) - (461.0 * s) * (f[3] + f[6]) +
+           (85.0 * s) * (f[2] + f[7]) - (4.0 * s) * (f[1] + f[8]) - s * (f[0] + f[9]);
+  }
+  constexpr double s = 1.0 / 1680.0;
+  return (1052.0 * s) * (f[4] + f[5]) - (250.0 * s) * (f[3] + f[6]) +
+         (38.0 * s) * (f[2] + f[7]) + s * (f[1] + f[8]) - s * (f[0] + f[9]);
+}
+
 // MP curvature d of eq. (eqn:mp-procedure) at the centre of v[-1..1], g[-1..1].
 __device__ __forceinline__ double mp_curv(double vm, double v0, double vp, double gm,
                                           double gp) {
@@ -87,8 +127,10 @@ __device__ __forceinline__ double mp_curv(double vm, double v0, double vp, doubl
 }
 
 // MEG7 left and right values at j+1/2 of one characteristic component
-// (Sec. 2.3): GRB value, the activation test, and the MP bounds.  v, g hold
-// offsets -2..3 around cell j.  The right value is the mirror image.
+// (Sec. 2.3): GRB value (of order ORD), the activation test, and the MP
+// bounds.  v, g hold offsets -2..3 around cell j.  The right value is the
+// mirror image.
+template <int ORD = 7>
 __device__ __forceinline__ void meg7_pair(const double* v, const double* g, double& outL,
                                           double& outR) {
   const double dm1 = mp_curv(v[0], v[1], v[2], g[0], g[2]);
@@ -97,7 +139,7 @@ __device__ __forceinline__ void meg7_pair(const double* v, const double* g, doub
   const double dp2 = mp_curv(v[3], v[4], v[5], g[3], g[5]);
   const double md = 0.5 * (v[2] + v[3]) - 0.5 * minmod(d0, dp1);
   {
-    double phi = grb_left(v, g);
+    double phi = grb_l<ORD>(v, g);
     double pmp = v[2] + minmod(v[3] - v[2], kXiMP * (v[2] - v[1]));
     if ((phi - v[2]) * (phi - pmp) > kMPTol) {
       double ul = v[2] + kXiMP * (v[2] - v[1]);
@@ -109,7 +151,7 @@ __device__ __forceinline__ void meg7_pair(const double* v, const double* g, doub
     outL = phi;
   }
   {
-    double phi = grb_right(v, g);
+    double phi = grb_r<ORD>(v, g);
     double pmp = v[3] + minmod(v[2] - v[3], kXiMP * (v[3] - v[4]));
     if ((phi - v[3]) * (phi - pmp) > kMPTol) {
       double ul = v[3] + kXiMP * (v[3] - v[4]);
@@ -131,7 +173,7 @@ __device__ __forceinline__ void meg7_pair(const double* v, const double* g, doub
 // fields are limited one at a time in a rolled loop that reads only its two
 // primitive fields, which keeps the register footprint small, and are
 // projected back by accumulating the columns of R.
-template <class FW, class FG>
+template <int ORD = 7, class FW, class FG>
 __device__ __forceinline__ void meg7_char_states(FW Wf, FG Gf, double gamma, double WLo[4],
                                                  double WRo[4]) {
   const double rb = 0.5 * (Wf(2, 0) + Wf(3, 0));
@@ -157,7 +199,7 @@ __device__ __forceinline__ void meg7_char_states(FW Wf, FG Gf, double gamma, dou
       cg[q] = ca * Gf(q, fa) + cbv * Gf(q, fb);
     }
     double cl, cr;
-    meg7_pair(cv, cg, cl, cr);
+    meg7_pair<ORD>(cv, cg, cl, cr);
     // column m of R = L^{-1}: (1,-c/rho,0,c^2), (1,0,0,0), (0,0,1,0), (1,c/rho,0,c^2)
     const double b0 = (m == 2) ? 0.0 : 1.0;
     const double b1 = (m == 0) ? -cor : ((m == 3) ? cor : 0.0);
@@ -190,7 +232,7 @@ __device__ __forceinline__ void cons_to_prim(const double Q[4], double gamma, do
 // columns of R = L^{-1}: (1, u-c, v, H-uc), (1, u, v, (u^2+v^2)/2), (0, 0, 1, v),
 //   (1, u+c, v, H+uc).  Every row reads all four fields, so the rows are
 // limited one at a time in a rolled loop and projected back column by column.
-template <class FQ, class FG>
+template <int ORD = 7, class FQ, class FG>
 __device__ __forceinline__ void meg7_char_states_cons(FQ Qf, FG Gf, double gamma,
                                                       double QLo[4], double QRo[4]) {
   const double q0 = 0.5 * (Qf(2, 0) + Qf(3, 0)), q1 = 0.5 * (Qf(2, 1) + Qf(3, 1));
@@ -229,7 +271,7 @@ __device__ __forceinline__ void meg7_char_states_cons(FQ Qf, FG Gf, double gamma
       cg[q] = l0 * Gf(q, 0) + l1 * Gf(q, 1) + l2 * Gf(q, 2) + l3 * Gf(q, 3);
     }
     double cl, cr;
-    meg7_pair(cv, cg, cl, cr);
+    meg7_pair<ORD>(cv, cg, cl, cr);
     double r0, r1, r2, r3;
     if (m == 1) {
       r0 = 1.0; r1 = ub; r2 = vb; r3 = ke;

@@ -108,7 +108,7 @@ __device__ __forceinline__ void load_chimap(const StageParams& P, unsigned char*
   }
 }
 
-template <class C, int DIR, bool DETMLP, bool CONS>
+template <class C, int DIR, bool DETMLP, bool CONS, int ORD>
 __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0, int tx0,
                                       int ty0, double (&res)[C::CPT][4]) {
   constexpr bool X = (DIR == 0);
@@ -285,17 +285,13 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
 #pragma unroll
             for (int q = 1; q < 5; ++q) g[q] = sD[m * NL * WD + bidx(line, pos + q + 1, WD)];
             g[0] = g[5] = 0.0;
-            WL[m] = grb_left(v, g);
-            WR[m] = grb_right(v, g);
-            // eqs. (flux-full), (flux-right) on the cell fluxes f_{j-4..j+5}
-            // (F(f_L) + F(f_R))/2: the sum of eqs. (flux-full) and (flux-right)
-            // is symmetric about the interface, so pairs are added first
+            WL[m] = grb_l<ORD>(v, g);
+            WR[m] = grb_r<ORD>(v, g);
+            // (F(f_L) + F(f_R))/2 on the cell fluxes f_{j-4..j+5}
             double f[10];
 #pragma unroll
             for (int q = 0; q < 10; ++q) f[q] = sF[m * FSTR + bidx(line, pos + q + 1, WF)];
-            constexpr double s = 1.0 / 1680.0;
-            Fm[m] = (1052.0 * s) * (f[4] + f[5]) - (250.0 * s) * (f[3] + f[6]) +
-                    (38.0 * s) * (f[2] + f[7]) + s * (f[1] + f[8]) - s * (f[0] + f[9]);
+            Fm[m] = flux_mean<ORD>(f);
           }
           if (CONS) {
             // the GRB states above are conservative: to primitives
@@ -367,11 +363,11 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
     auto Gf = [&](int q, int f) { return sD[f * NL * WD + bidx(line, pos + q + 1, WD)]; };
     if (CONS) {
       double QL[4], QR[4];
-      meg7_char_states_cons(Vf, Gf, P.gamma, QL, QR);
+      meg7_char_states_cons<ORD>(Vf, Gf, P.gamma, QL, QR);
       cons_to_prim(QL, P.gamma, WL);
       cons_to_prim(QR, P.gamma, WR);
     } else {
-      meg7_char_states(Vf, Gf, P.gamma, WL, WR);
+      meg7_char_states<ORD>(Vf, Gf, P.gamma, WL, WR);
     }
     if (!(WL[0] > 0.0 && WL[3] > 0.0 && WR[0] > 0.0 && WR[3] > 0.0)) {
       if (CONS) {
@@ -531,7 +527,7 @@ __device__ __forceinline__ void stage_store(const StageParams& P, const double (
 // One tile of the stage: load, both sweeps, store.  The LDS arrays are
 // passed in so that a kernel can run several tile shapes from one set of
 // arrays sized for the largest (the batched kernel).
-template <class C, bool DETMLP, bool CONS = false>
+template <class C, bool DETMLP, bool CONS = false, int ORD = 7>
 __device__ __forceinline__ void stage_tile(const StageParams& P, int tx0, int ty0, double* sU,
                                            double* sPh, unsigned char* sChi,
                                            unsigned short* sQueue, int* sQCount,
@@ -545,12 +541,14 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int tx0, int ty
   for (int k = 0; k < C::CPT; ++k)
 #pragma unroll
     for (int m = 0; m < 4; ++m) res[k][m] = 0.0;
-  for (int l0 = 0; l0 < C::TY; l0 += C::SX) sweep<C, 0, DETMLP, CONS>(P, L, l0, tx0, ty0, res);
-  for (int l0 = 0; l0 < C::TX; l0 += C::SY) sweep<C, 1, DETMLP, CONS>(P, L, l0, tx0, ty0, res);
+  for (int l0 = 0; l0 < C::TY; l0 += C::SX)
+    sweep<C, 0, DETMLP, CONS, ORD>(P, L, l0, tx0, ty0, res);
+  for (int l0 = 0; l0 < C::TX; l0 += C::SY)
+    sweep<C, 1, DETMLP, CONS, ORD>(P, L, l0, tx0, ty0, res);
   stage_store<C>(P, res, tx0, ty0);
 }
 
-template <class C, bool DETMLP, bool CONS = false>
+template <class C, bool DETMLP, bool CONS = false, int ORD = 7>
 __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel(StageParams P) {
   __shared__ double sU[C::NF * C::RS];
   __shared__ double sPh[C::PH];
@@ -560,7 +558,7 @@ __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel(StageParams 
   __shared__ int sQCount;
   int tx0, ty0;
   if (!tile_origin(P, C::TX, C::TY, tx0, ty0)) return;
-  stage_tile<C, DETMLP, CONS>(P, tx0, ty0, sU, sPh, sChi, sQueue, &sQCount, sChiF);
+  stage_tile<C, DETMLP, CONS, ORD>(P, tx0, ty0, sU, sPh, sChi, sQueue, &sQCount, sChiF);
 }
 
 }  // namespace gbr

@@ -39,6 +39,7 @@ SIGNATURES = {
     "gbr_destroy": (_i, [_vp]),
     "gbr_set_geometry": (_i, [_vp, _d, _d, _d, _d, _i, _i]),
     "gbr_set_scheme": (_i, [_vp, _i, _i, _i, _i]),
+    "gbr_set_order": (_i, [_vp, _i]),
     "gbr_residual": (_i, [_vp, _vp, _vp, _vp]),
     "gbr_rk_stage": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
     "gbr_compute_dt": (_i, [_vp, _vp, _d, _vp, _vp]),
@@ -165,6 +166,10 @@ def gbr_set_scheme(ctx, recon=GBR_RECON_PRIM, mp_mode=GBR_MP_FLAGGED,
                    precision=GBR_PREC_FP64, detector=GBR_DET_PLAIN):
     return _check(load().gbr_set_scheme(ctx, recon, mp_mode, precision, detector),
                   "gbr_set_scheme")
+
+
+def gbr_set_order(ctx, order):
+    return _check(load().gbr_set_order(ctx, order), "gbr_set_order")
 
 
 def gbr_residual(ctx, Q, Res, stream=None):

@@ -12,7 +12,7 @@ from . import gbr
 class Solver:
     def __init__(self, problem, device="cuda", stream=None, export_flags=False,
                  precision=gbr.GBR_PREC_FP64, detector=gbr.GBR_DET_PLAIN,
-                 recon=gbr.GBR_RECON_PRIM):
+                 recon=gbr.GBR_RECON_PRIM, order=7):
         import torch
         self.torch = torch
         self.p = problem
@@ -21,6 +21,8 @@ class Solver:
         self.ctx = gbr.gbr_init(problem.nx, problem.ny, problem.gamma, problem.mu, problem.Pr)
         gbr.gbr_set_geometry(self.ctx, *problem.geometry())
         gbr.gbr_set_scheme(self.ctx, recon, gbr.GBR_MP_FLAGGED, precision, detector)
+        if order != 7:
+            gbr.gbr_set_order(self.ctx, order)
         if export_flags:
             gbr.gbr_export_flags(self.ctx, True)
         shape = (4, problem.ny, problem.nx)
