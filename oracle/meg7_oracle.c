@@ -65,6 +65,22 @@
  *          reconstruction by eq. (fourth); F(f_R) is the mirror image of
  *          eq. (fourth), as eq. (flux-right) mirrors eq. (flux-full).  The
  *          detector, the MP bounds, HLLC and the viscous flux are unchanged.
+ *   R-WALL Boundaries beyond periodic and transmissive (the paper refers to the
+ *          usual ghost-cell treatment of its test cases): a reflecting wall
+ *          mirrors the cells about the wall and negates the normal velocity;
+ *          an adiabatic no-slip wall mirrors and negates both velocity
+ *          components; an inflow side holds a fixed state in all six ghost
+ *          layers.  A side may switch kind at a point that moves with time
+ *          (the double Mach reflection).  In a corner ghost cell the mirror
+ *          and sign rules of both sides compose; a fixed state of the x side
+ *          takes precedence over one of the y side.  Runge-Kutta stage k
+ *          evaluates the boundary at t + c_k dt, c = (0, 1, 1/2).
+ *   R-SSHLLC The shock-stable HLLC the paper cites for the double Mach
+ *          reflection (Fleischmann et al.) is taken as its low-Mach-limited
+ *          form: the two acoustic-wave terms of the wave-sum form are scaled by
+ *          phi = sin(pi/2 min(1, Ma/0.1)), Ma = max(|u_L|/c_L, |u_R|/c_R) of
+ *          the normal velocities; the contact term and the wave-speed bounds
+ *          are those of R-HLLC.
  *   R-MPG  In eq. (eqn:mp-procedure) the hat on Phi_{j-1} and the mixed
  *          i/j subscripts are typesetting slips: plain Phi_{j-1}, index j.
  *          The MP xi (=7) and the detector xi (=1e-3) are different
@@ -82,7 +98,18 @@
 
 #define NG 6 /* ghost layers: the shock branch reaches Phi_{j-5..j+6} */
 
-enum { ORC_BC_PERIODIC = 0, ORC_BC_TRANSMISSIVE = 1 };
+enum { ORC_BC_PERIODIC = 0, ORC_BC_TRANSMISSIVE = 1, ORC_BC_REFLECT = 2, ORC_BC_NOSLIP = 3,
+       ORC_BC_INFLOW = 4 };
+
+/* One side of the domain (reading R-WALL): two segments along the side,
+ * segment 0 where the tangential cell-centre coordinate is below
+ * split0 + split_speed * t, segment 1 elsewhere; each with a boundary kind
+ * and, for ORC_BC_INFLOW, a fixed primitive state (rho, u, v, p). */
+typedef struct {
+    int kind[2];
+    double state[2][4];
+    double split0, split_speed;
+} orc_side;
 
 typedef struct {
     int nx, ny;
@@ -93,11 +120,16 @@ typedef struct {
     int force_sigma; /* -1: detector decides; 0 or 1: force sigma (tests)    */
     int recon;     /* 0: primitive variables (MEG7-prim); 1: conservative (MEG7-cons) */
     int order;     /* 7: the seventh-order GRB of Sec. 2.2; 4: its fourth-order subset */
+    int riemann;   /* 0: HLLC (R-HLLC); 1: shock-stable HLLC (R-SSHLLC) */
+    int use_sides; /* 0: bc_x / bc_y on both sides; 1: the side table below */
+    double t;      /* time of the state a residual is evaluated on (moving segments) */
+    orc_side side[4];  /* left (x0), right (x1), bottom (y0), top (y1) */
 } orc_cfg;
 
 /* ---------------------------------------------------------------------- */
 /* Constants of the paper.                                                 */
 /* ---------------------------------------------------------------------- */
+static const double PI = 3.14159265358979323846;
 static const double ALPHA_V = 4.0;      /* eq. (eqn:alphad): alpha_v = 4            */
 static const double XI_MP = 7.0;        /* eq. (eqn:alpha): xi = 7                  */
 static const double MP_TOL = 1e-40;     /* eq. (eqn:hocus/mp5Condition)             */
@@ -408,8 +440,8 @@ static void conv_flux(const double W[4], double gamma, double F[4])
 /* HLLC (Toro 1994), reading R-HLLC, written in the wave-sum form
  * F = (F_L + F_R)/2 - (|S_L|(Q*_L - Q_L) + |S*|(Q*_R - Q*_L) + |S_R|(Q_R - Q*_R))/2
  * which is the canonical form of eq. (eqn:Riemann). */
-void orc_hllc(const double WL[4], const double WR[4], const double FL[4],
-              const double FR[4], double gamma, double F[4])
+static void hllc_impl(const double WL[4], const double WR[4], const double FL[4],
+                      const double FR[4], double gamma, int riemann, double F[4])
 {
     double QL[4], QR[4];
     prim_to_cons(WL, gamma, QL);
@@ -442,11 +474,29 @@ void orc_hllc(const double WL[4], const double WR[4], const double FL[4],
     QsR[1] = kr * Ss;
     QsR[2] = kr * vr;
     QsR[3] = kr * (QR[3] / rr + (Ss - ur) * (Ss + pr / (rr * (SR - ur))));
+    /* reading R-SSHLLC: the acoustic-wave terms scaled by phi at low Mach */
+    double phi = 1.0;
+    if (riemann == 1) {
+        double ma = fmax(fabs(ul) / cl, fabs(ur) / cr);
+        phi = sin(0.5 * PI * fmin(1.0, ma / 0.1));
+    }
     for (int m = 0; m < 4; ++m) {
-        double diss = fabs(SL) * (QsL[m] - QL[m]) + fabs(Ss) * (QsR[m] - QsL[m])
-                    + fabs(SR) * (QR[m] - QsR[m]);
+        double diss = phi * fabs(SL) * (QsL[m] - QL[m]) + fabs(Ss) * (QsR[m] - QsL[m])
+                    + phi * fabs(SR) * (QR[m] - QsR[m]);
         F[m] = 0.5 * (FL[m] + FR[m]) - 0.5 * diss;
     }
+}
+
+void orc_hllc(const double WL[4], const double WR[4], const double FL[4],
+              const double FR[4], double gamma, double F[4])
+{
+    hllc_impl(WL, WR, FL, FR, gamma, 0, F);
+}
+
+void orc_hllc_ss(const double WL[4], const double WR[4], const double FL[4],
+                 const double FR[4], double gamma, double F[4])
+{
+    hllc_impl(WL, WR, FL, FR, gamma, 1, F);
 }
 
 /* Everything the flux at one interface j+1/2 reads, gathered along the
@@ -640,7 +690,7 @@ static void line_flux(const orc_line *L, const orc_cfg *c, double Fout[4], int *
         conv_flux(WR, gamma, FR);
     }
     double Fc[4];
-    orc_hllc(WL, WR, FL, FR, gamma, Fc);
+    hllc_impl(WL, WR, FL, FR, gamma, c->riemann, Fc);
 
     /* Sec. 2.1 viscous flux (R-VISC). */
     double Fv[4] = {0.0, 0.0, 0.0, 0.0};
@@ -701,6 +751,73 @@ static int bc_index(int k, int n, int bc)
     return k < 0 ? 0 : (k >= n ? n - 1 : k);
 }
 
+/* Reading R-WALL.  For raw index k along an axis (0: x, 1: y), the kind of
+ * the side that governs it (-1 inside the grid), that side's fixed state,
+ * and the source index: wrap (periodic), mirror about the wall (reflect,
+ * no-slip; clamped into the grid where the overhang exceeds the grid), or
+ * the nearest cell (transmissive, inflow).  tang is the cell-centre
+ * coordinate along the side, tb the boundary time. */
+static int side_rule(const orc_cfg *c, int axis, int k, double tang, double tb,
+                     const double **state)
+{
+    const int n = axis == 0 ? c->nx : c->ny;
+    *state = NULL;
+    if (k >= 0 && k < n) return -1;
+    int kind;
+    if (!c->use_sides) {
+        kind = axis == 0 ? c->bc_x : c->bc_y;
+    } else {
+        const orc_side *S = &c->side[2 * axis + (k >= n ? 1 : 0)];
+        const int seg = (tang < S->split0 + S->split_speed * tb) ? 0 : 1;
+        kind = S->kind[seg];
+        *state = S->state[seg];
+    }
+    return kind;
+}
+
+static int source_index(int kind, int k, int n)
+{
+    if (kind < 0) return k;
+    if (kind == ORC_BC_PERIODIC) return bc_index(k, n, ORC_BC_PERIODIC);
+    if (kind == ORC_BC_REFLECT || kind == ORC_BC_NOSLIP) {
+        int m = k < 0 ? -1 - k : 2 * n - 1 - k;
+        return m < 0 ? 0 : (m >= n ? n - 1 : m);
+    }
+    return k < 0 ? 0 : (k >= n ? n - 1 : k);
+}
+
+/* Primitive and conservative values of (possibly ghost) cell (i, j) at
+ * boundary time tb (reading R-WALL). */
+static void cell_values(const orc_cfg *c, const double *Q, int i, int j, double tb,
+                        double W[4], double Cc[4])
+{
+    const int nx = c->nx, ny = c->ny;
+    const size_t n = (size_t)nx * ny;
+    const double dx = (c->x1 - c->x0) / nx, dy = (c->y1 - c->y0) / ny;
+    const double xc = c->x0 + ((double)j + 0.5) * dx;
+    const double yc = c->y0 + ((double)i + 0.5) * dy;
+    const double *sx, *sy;
+    const int kx = side_rule(c, 0, j, yc, tb, &sx);
+    const int ky = side_rule(c, 1, i, xc, tb, &sy);
+    const size_t s = (size_t)source_index(ky, i, ny) * nx + source_index(kx, j, nx);
+    double rho = Q[s], mx = Q[n + s], my = Q[2 * n + s], E = Q[3 * n + s];
+    /* mirror rules: a reflecting wall negates the normal momentum, a no-slip
+     * wall both components; the rules of the two sides of a corner compose */
+    if (kx == ORC_BC_REFLECT || kx == ORC_BC_NOSLIP) mx = -mx;
+    if (kx == ORC_BC_NOSLIP) my = -my;
+    if (ky == ORC_BC_REFLECT || ky == ORC_BC_NOSLIP) my = -my;
+    if (ky == ORC_BC_NOSLIP) mx = -mx;
+    double u = mx / rho, v = my / rho;
+    double p = (c->gamma - 1.0) * (E - rho * (u * u + v * v) / 2.0);
+    W[0] = rho; W[1] = u; W[2] = v; W[3] = p;
+    Cc[0] = rho; Cc[1] = mx; Cc[2] = my; Cc[3] = E;
+    const double *fixed = kx == ORC_BC_INFLOW ? sx : (ky == ORC_BC_INFLOW ? sy : NULL);
+    if (fixed) {
+        for (int m = 0; m < 4; ++m) W[m] = fixed[m];
+        prim_to_cons(W, c->gamma, Cc);
+    }
+}
+
 typedef struct {
     int NX, NY;                 /* padded sizes */
     double *W[4];               /* rho, u, v, p on the padded grid */
@@ -725,7 +842,6 @@ static int fields_build(const orc_cfg *c, const double *Q, orc_fields *F)
     const int nx = c->nx, ny = c->ny;
     const int NX = nx + 2 * NG, NY = ny + 2 * NG;
     const size_t np = (size_t)NX * NY;
-    const size_t n = (size_t)nx * ny;
     memset(F, 0, sizeof(*F));
     F->NX = NX; F->NY = NY;
     for (int m = 0; m < 4; ++m) F->W[m] = (double *)calloc(np, sizeof(double));
@@ -752,19 +868,14 @@ static int fields_build(const orc_cfg *c, const double *Q, orc_fields *F)
     /* ghost cells (R-BC) and primitives, eq. (eqn:pressure), T (R-T) */
 #pragma omp parallel for schedule(static)
     for (int I = 0; I < NY; ++I) {
-        int i = bc_index(I - NG, ny, c->bc_y);
         for (int J = 0; J < NX; ++J) {
-            int j = bc_index(J - NG, nx, c->bc_x);
-            size_t s = (size_t)i * nx + j;
-            double rho = Q[s], mx = Q[n + s], my = Q[2 * n + s], E = Q[3 * n + s];
-            double u = mx / rho, v = my / rho;
-            double p = (gamma - 1.0) * (E - rho * (u * u + v * v) / 2.0);
+            double W[4], Cc[4];
+            cell_values(c, Q, I - NG, J - NG, c->t, W, Cc);
             size_t P = (size_t)I * NX + J;
-            F->W[0][P] = rho; F->W[1][P] = u; F->W[2][P] = v; F->W[3][P] = p;
-            F->T[P] = gamma * p / rho;
-            if (c->recon == 1) {
-                F->C[0][P] = rho; F->C[1][P] = mx; F->C[2][P] = my; F->C[3][P] = E;
-            }
+            for (int m = 0; m < 4; ++m) F->W[m][P] = W[m];
+            F->T[P] = gamma * W[3] / W[0];
+            if (c->recon == 1)
+                for (int m = 0; m < 4; ++m) F->C[m][P] = Cc[m];
         }
     }
     double *src[5] = {F->W[0], F->W[1], F->W[2], F->W[3], F->T};
@@ -864,11 +975,28 @@ static void gather_y(const orc_cfg *c, const orc_fields *F, int i, int j, orc_li
     }
 }
 
+static int sides_ok(const orc_cfg *c)
+{
+    if (!c->use_sides) return 1;
+    for (int a = 0; a < 2; ++a) {
+        int nper = 0;
+        for (int sd = 2 * a; sd < 2 * a + 2; ++sd)
+            for (int g = 0; g < 2; ++g) {
+                const int k = c->side[sd].kind[g];
+                if (k < ORC_BC_PERIODIC || k > ORC_BC_INFLOW) return 0;
+                nper += (k == ORC_BC_PERIODIC);
+            }
+        if (nper != 0 && nper != 4) return 0;   /* periodic: all of both sides of an axis */
+    }
+    return 1;
+}
+
 static int cfg_ok(const orc_cfg *c)
 {
     return c && c->nx >= 2 * NG && c->ny >= 2 * NG && c->gamma > 1.0 && c->mu >= 0.0
         && c->Pr > 0.0 && c->x1 > c->x0 && c->y1 > c->y0 && (c->recon == 0 || c->recon == 1)
-        && (c->order == 7 || c->order == 4);
+        && (c->order == 7 || c->order == 4) && (c->riemann == 0 || c->riemann == 1)
+        && sides_ok(c);
 }
 
 /* eqs. (eqn-differencing_residual), (deriv): Res = -dF/dx - dG/dy.
@@ -963,7 +1091,11 @@ long orc_rk_stage(const orc_cfg *c, int stage, double dt, const double *Qn,
     const size_t N = 4 * (size_t)c->nx * c->ny;
     double *R = (double *)malloc(sizeof(double) * N);
     if (!R) return -1;
-    long nl = orc_residual(c, Qk, R, sig_x, sig_y);
+    /* reading R-WALL: the boundary of stage k at t + c_k dt, c = (0, 1, 1/2) */
+    const double ck[3] = {0.0, 1.0, 0.5};
+    orc_cfg cs = *c;
+    cs.t = c->t + ck[stage - 1] * dt;
+    long nl = orc_residual(&cs, Qk, R, sig_x, sig_y);
     if (nl < 0) { free(R); return -1; }
 #pragma omp parallel for schedule(static)
     for (size_t s = 0; s < N; ++s) {
@@ -1003,8 +1135,8 @@ double orc_dt(const orc_cfg *c, const double *Q, double cfl)
 }
 
 /* One full SSP-RK3 step with dt from Qn (for trajectories in tests):
- * Q is advanced in place; returns dt. */
-double orc_step(const orc_cfg *c, double *Q, double cfl)
+ * Q is advanced in place and c->t by dt; returns dt. */
+double orc_step(orc_cfg *c, double *Q, double cfl)
 {
     const size_t N = 4 * (size_t)c->nx * c->ny;
     double dt = orc_dt(c, Q, cfl);
@@ -1016,6 +1148,7 @@ double orc_step(const orc_cfg *c, double *Q, double cfl)
     orc_rk_stage(c, 3, dt, Q, Q2, Q1, NULL, NULL);
     memcpy(Q, Q1, sizeof(double) * N);
     free(Q1); free(Q2);
+    c->t += dt;
     return dt;
 }
 

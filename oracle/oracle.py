@@ -4,6 +4,7 @@ Arrays are numpy float64, structure of arrays [4][ny][nx] with x fastest:
 Q = (rho, rho u, rho v, E).
 """
 import ctypes as C
+import math
 import os
 
 import numpy as np
@@ -14,6 +15,13 @@ BC_PERIODIC = 0
 BC_TRANSMISSIVE = 1
 
 
+class OrcSide(C.Structure):
+    """One side of the domain: segment 0 where the tangential cell-centre
+    coordinate is below split0 + split_speed * t, segment 1 elsewhere."""
+    _fields_ = [("kind", C.c_int * 2), ("state", (C.c_double * 4) * 2),
+                ("split0", C.c_double), ("split_speed", C.c_double)]
+
+
 class OrcCfg(C.Structure):
     _fields_ = [
         ("nx", C.c_int), ("ny", C.c_int),
@@ -21,7 +29,25 @@ class OrcCfg(C.Structure):
         ("bc_x", C.c_int), ("bc_y", C.c_int),
         ("gamma", C.c_double), ("mu", C.c_double), ("Pr", C.c_double),
         ("mp_mode", C.c_int), ("force_sigma", C.c_int), ("recon", C.c_int), ("order", C.c_int),
+        ("riemann", C.c_int), ("use_sides", C.c_int), ("t", C.c_double),
+        ("side", OrcSide * 4),
     ]
+
+
+BC_REFLECT, BC_NOSLIP, BC_INFLOW = 2, 3, 4
+
+
+def side(kind, state=None, kind1=None, state1=None, split0=math.inf, split_speed=0.0):
+    """A side with one kind, or two segments split at split0 + split_speed t."""
+    S = OrcSide()
+    k1 = kind if kind1 is None else kind1
+    S.kind[0], S.kind[1] = kind, k1
+    for g, st in enumerate((state, state1 if kind1 is not None else state)):
+        if st is not None:
+            for m in range(4):
+                S.state[g][m] = st[m]
+    S.split0, S.split_speed = split0, split_speed
+    return S
 
 
 class OrcCState(C.Structure):
@@ -69,6 +95,8 @@ def lib():
         L.orc_meg7_right.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int)]
         L.orc_hllc.restype = None
         L.orc_hllc.argtypes = [dp, dp, dp, dp, C.c_double, dp]
+        L.orc_hllc_ss.restype = None
+        L.orc_hllc_ss.argtypes = [dp, dp, dp, dp, C.c_double, dp]
         L.orc_line_flux.restype = None
         L.orc_line_flux.argtypes = [dp, dp, dp, dp, dp, dp, dp, C.c_double,
                                     C.POINTER(OrcCfg), dp, C.POINTER(C.c_int)]
@@ -86,11 +114,19 @@ def lib():
 
 
 def make_cfg(nx, ny, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc_x=BC_PERIODIC, bc_y=BC_PERIODIC,
-             gamma=1.4, mu=0.0, Pr=0.72, mp_mode=0, force_sigma=-1, recon=0, order=7):
+             gamma=1.4, mu=0.0, Pr=0.72, mp_mode=0, force_sigma=-1, recon=0, order=7,
+             riemann=0, sides=None, t=0.0):
     """recon 0: MEG7-prim (primitive variables), 1: MEG7-cons (conservative);
-    order 7: the seventh-order GRB, 4: its fourth-order subset (alpha=4, beta=0)."""
-    return OrcCfg(nx, ny, x0, x1, y0, y1, bc_x, bc_y, gamma, mu, Pr, mp_mode, force_sigma, recon,
-                  order)
+    order 7: the seventh-order GRB, 4: its fourth-order subset (alpha=4, beta=0);
+    riemann 0: HLLC, 1: shock-stable HLLC; sides: four OrcSide (left, right,
+    bottom, top) replacing bc_x / bc_y; t: time of the state (moving sides)."""
+    cfg = OrcCfg(nx, ny, x0, x1, y0, y1, bc_x, bc_y, gamma, mu, Pr, mp_mode, force_sigma, recon,
+                 order, riemann, 0, t)
+    if sides is not None:
+        cfg.use_sides = 1
+        for k in range(4):
+            cfg.side[k] = sides[k]
+    return cfg
 
 
 def _ptr(a):
@@ -220,10 +256,11 @@ def meg7_right(p6, g6):
     return v, lim.value
 
 
-def hllc(WL, WR, FL, FR, gamma=1.4):
+def hllc(WL, WR, FL, FR, gamma=1.4, riemann=0):
+    """HLLC flux (riemann 0) or its shock-stable form (riemann 1)."""
     out = np.empty(4)
-    lib().orc_hllc(*[np.ascontiguousarray(a, np.float64) for a in (WL, WR, FL, FR)],
-                   gamma, out)
+    fn = lib().orc_hllc_ss if riemann == 1 else lib().orc_hllc
+    fn(*[np.ascontiguousarray(a, np.float64) for a in (WL, WR, FL, FR)], gamma, out)
     return out
 
 

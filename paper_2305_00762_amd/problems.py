@@ -17,6 +17,10 @@ Families
              seeded sinusoidal perturbation on modes 1-8, Re = 1e4, Pr = 0.72.
   taylor_green  inviscid 2D Taylor-Green vortex (the z = 0 plane of the
              paper's Taylor-Green initial state), periodic on [0, 2 pi)^2.
+  double_mach   the paper's double Mach reflection (walls, inflow, moving
+             top boundary), 1024 x 256.
+  viscous_shock_tube  the paper's viscous shock tube (no-slip walls), Re =
+             1000, 1280 x 640.
 """
 from dataclasses import dataclass, field
 import math
@@ -25,6 +29,9 @@ import numpy as np
 
 BC_PERIODIC = 0
 BC_TRANSMISSIVE = 1
+BC_REFLECT = 2      # slip wall: mirror, normal velocity negated
+BC_NOSLIP = 3       # adiabatic no-slip wall: mirror, both velocity components negated
+BC_INFLOW = 4       # fixed state in the ghost layers
 GAMMA = 1.4
 
 
@@ -45,6 +52,13 @@ class Problem:
     cfl: float
     seed: int = 0
     Q: np.ndarray = field(default=None, repr=False)
+    # optional per-side boundaries (left, right, bottom, top), each
+    # (kind, state, kind1, state1, split0, split_speed): kind on the part of the
+    # side whose tangential cell-centre coordinate is below split0 + split_speed t,
+    # kind1 beyond; states are primitive (rho, u, v, p) for BC_INFLOW
+    sides: list = None
+    riemann: int = 0        # 1: the shock-stable HLLC
+    t_final: float = None
 
     @property
     def dx(self):
@@ -189,6 +203,59 @@ def taylor_green(n, cfl=0.5, ny=None, p0=100.0):
     return P
 
 
+# -------------------------------------------------- wall-bounded problems ---
+def single_side(kind, state=None):
+    return (kind, state, kind, state, math.inf, 0.0)
+
+
+def double_mach(nx=1024, ny=None, cfl=0.2):
+    """Double Mach reflection (Woodward and Colella) as the paper sets it up:
+    [0, 4] x [0, 1], a Mach-10 shock at 60 degrees to the wall through
+    (1/6, 0); post-shock (8, 8.25 cos 30, -8.25 sin 30, 116.5), pre-shock
+    (1.4, 0, 0, 1).  Boundaries: post-shock inflow on the left, transmissive
+    on the right, on the bottom the post-shock state for x < 1/6 and a
+    reflecting wall beyond, on the top the exact shock motion (post-shock
+    state left of 1/6 + (1 + 20 t)/sqrt 3, pre-shock right of it).  The
+    shock-stable HLLC, t = 0.2."""
+    ny = nx // 4 if ny is None else ny
+    X, Y = cell_centres(nx, ny, 0.0, 4.0, 0.0, 1.0)
+    post = (8.0, 8.25 * math.cos(math.pi / 6.0), -8.25 * math.sin(math.pi / 6.0), 116.5)
+    pre = (1.4, 0.0, 0.0, 1.0)
+    behind = X < 1.0 / 6.0 + Y / math.tan(math.pi / 3.0)
+    rho, u, v, p = (np.where(behind, a, b) for a, b in zip(post, pre))
+    P = Problem("double_mach", nx, ny, 0.0, 4.0, 0.0, 1.0, BC_TRANSMISSIVE, BC_TRANSMISSIVE,
+                GAMMA, 0.0, 0.72, cfl)
+    P.Q = prim_to_state(rho, u, v, p)
+    s3 = math.sqrt(3.0)
+    P.sides = [single_side(BC_INFLOW, post), single_side(BC_TRANSMISSIVE),
+               (BC_INFLOW, post, BC_REFLECT, None, 1.0 / 6.0, 0.0),
+               (BC_INFLOW, post, BC_INFLOW, pre, 1.0 / 6.0 + 1.0 / s3, 20.0 / s3)]
+    P.riemann = 1
+    P.t_final = 0.2
+    return P
+
+
+def viscous_shock_tube(nx=1280, ny=None, cfl=0.2, Re=1000.0, Pr=0.73):
+    """Viscous shock tube (Daru and Tenaud) as the paper sets it up:
+    [0, 1] x [0, 0.5], (120, 0, 0, 120/gamma) for x < 0.5 and
+    (1.2, 0, 0, 1.2/gamma) beyond, mu = 1/Re with Re = 1000; adiabatic no-slip
+    walls left, right and bottom, a symmetry plane (reflecting) on top;
+    t = 1."""
+    ny = nx // 2 if ny is None else ny
+    X, Y = cell_centres(nx, ny, 0.0, 1.0, 0.0, 0.5)
+    left = X < 0.5
+    rho = np.where(left, 120.0, 1.2)
+    p = rho / GAMMA
+    z = np.zeros_like(X)
+    P = Problem("viscous_shock_tube", nx, ny, 0.0, 1.0, 0.0, 0.5, BC_TRANSMISSIVE,
+                BC_TRANSMISSIVE, GAMMA, 1.0 / Re, Pr, cfl)
+    P.Q = prim_to_state(rho, z, z, p)
+    P.sides = [single_side(BC_NOSLIP), single_side(BC_NOSLIP), single_side(BC_NOSLIP),
+               single_side(BC_REFLECT)]
+    P.t_final = 1.0
+    return P
+
+
 # ------------------------------------------------------------------ misc ---
 def free_stream(n, rho=1.0, u=0.3, v=-0.2, p=0.7, bc=BC_PERIODIC, mu=0.0, ny=None):
     ny = n if ny is None else ny
@@ -208,6 +275,10 @@ def make(family, n, seed=0, **kw):
         return shear(n, seed=seed, **kw)
     if family == "taylor_green":
         return taylor_green(n, **kw)
+    if family == "double_mach":
+        return double_mach(n, **kw)
+    if family == "viscous_shock_tube":
+        return viscous_shock_tube(n, **kw)
     raise ValueError(family)
 
 

@@ -14,6 +14,9 @@ def require_gpu():
 
 
 def ocfg(P, **kw):
+    if P.sides is not None:
+        kw.setdefault("sides", [O.side(*s) for s in P.sides])
+        kw.setdefault("riemann", P.riemann)
     return O.make_cfg(P.nx, P.ny, *P.geometry(), gamma=P.gamma, mu=P.mu, Pr=P.Pr, **kw)
 
 
