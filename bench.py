@@ -50,6 +50,14 @@ WORKLOADS = {
                        "2D inviscid Taylor-Green vortex 64x64 on [0, 2 pi)^2 (the z = 0 plane of the "
                        "paper's Taylor-Green initial state, Mach ~0.085), periodic, CFL 0.5; 2600 "
                        "steps reach t ~ 10"),
+    "double_mach": ("double_mach", 1024, 0, None,
+                    "Double Mach reflection 1024x256 on [0,4]x[0,1] (Mach-10 shock at 60 degrees, "
+                    "reflecting wall, inflow, exact moving top boundary, shock-stable HLLC), run "
+                    "from t = 0 to t = 0.2, CFL 0.2"),
+    "viscous_shock_tube": ("viscous_shock_tube", 1280, 0, None,
+                           "Viscous shock tube 1280x640 on [0,1]x[0,0.5], Re 1000, Pr 0.73, "
+                           "adiabatic no-slip walls and a symmetry plane, run from t = 0 to t = 1, "
+                           "CFL 0.2"),
     "batch512": ("batch", 0, 0, 10,
                  "512 independent grids, side n ~ U{64..768} (seed 0), families uniform over "
                  "vortex / Riemann / shear layer, per-grid seed 10000 + index; one launch per "
@@ -126,6 +134,10 @@ class Path:
         if order != 7:
             gbr.gbr_set_order(self.ctx, order)
         self.order = order
+        if P.sides is not None:
+            gbr.gbr_set_sides(self.ctx, P.sides)
+        if P.riemann:
+            gbr.gbr_set_riemann(self.ctx, P.riemann)
         dev = torch.device("cuda:0")
         self.Q = [torch.from_numpy(P.Q).to(dev) for _ in range(3)]
         self.Q0 = self.Q[0].clone()
@@ -142,6 +154,7 @@ class Path:
         for q in self.Q:
             q.copy_(torch.from_numpy(self.P.Q))
         torch.cuda.synchronize()
+        self.gbr.gbr_set_time(self.ctx, 0.0)
 
     def step(self):
         """One SSP-RK3 step on self.stream; Q^{n+1} ends in self.Q[0]."""
@@ -151,6 +164,8 @@ class Path:
         g.gbr_rk_stage(self.ctx, 1, self.dt, Q, Q, Q1, sh)
         g.gbr_rk_stage(self.ctx, 2, self.dt, Q, Q1, Q2, sh)
         g.gbr_rk_stage(self.ctx, 3, self.dt, Q, Q2, Q1, sh)
+        if self.P.sides is not None:
+            g.gbr_advance_time(self.ctx, self.dt, sh)
         self.Q = [Q1, Q, Q2]
 
     def run(self, warmup, steps, timing=False):
@@ -182,6 +197,35 @@ class Path:
         self.status = g.gbr_check(self.ctx, sh)
         return start.elapsed_time(stop), kt
 
+    def run_to(self, t_final, chunk=250):
+        """Whole steps from the current state until the device clock reaches
+        t_final (the last step passes it by less than one dt).  The clock and
+        the last dt are read after each batch of steps; a batch is at most
+        `chunk` steps and at most the steps the last dt says remain, so the
+        batches shrink to single steps near the end.  Returns (ms, steps)."""
+        import torch
+        g, sh = self.gbr, self.stream.cuda_stream
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        steps, batch = 0, chunk
+        with torch.cuda.stream(self.stream):
+            start.record(self.stream)
+            while True:
+                for _ in range(batch):
+                    self.step()
+                steps += batch
+                self.stream.synchronize()
+                t = g.gbr_get_time(self.ctx)
+                if t >= t_final:
+                    break
+                dt = float(self.dt.item())
+                batch = max(1, min(chunk, int((t_final - t) / dt)))
+            stop.record(self.stream)
+        self.stream.synchronize()
+        torch.cuda.synchronize()
+        self.status = g.gbr_check(self.ctx, sh)
+        return start.elapsed_time(stop), steps
+
     def close(self):
         self.gbr.gbr_destroy(self.ctx)
         if self.net is not None:
@@ -204,7 +248,8 @@ def cpu_baseline(P, seconds, max_steps=50, recon=0, order=7):
     import numpy as np
     import oracle as O
     cfg = O.make_cfg(P.nx, P.ny, *P.geometry(), gamma=P.gamma, mu=P.mu, Pr=P.Pr, recon=recon,
-                     order=order)
+                     order=order, riemann=P.riemann,
+                     sides=[O.side(*sd) for sd in P.sides] if P.sides is not None else None)
     Q = np.ascontiguousarray(P.Q.copy())
     steps, t0 = 0, time.perf_counter()
     while True:
@@ -361,16 +406,31 @@ def main():
 
     calibration_copy(a.calib_copy_mb)
     head = Path(P, a.path, stream, a.tiling, a.weights, a.margin)
-    # kernel pass: the same warm-up and steps with HIP events around every
-    # launch (per-kernel durations for the roofline); the events add gaps
-    # between launches, so the throughput comes from a second pass over the
-    # same work from the same initial state without them
-    ev_ms, (det_ms, stage_ms, launches) = head.run(a.warmup, steps, timing=True)
-    head.reset()
-    total_ms, _ = head.run(a.warmup, steps)
+    t_final = P.t_final if steps is None else None
+    if t_final is not None:
+        # the whole run of the test case: warm-up steps, then from the
+        # initial state at t = 0 until the device clock reaches t_final,
+        # timed; the kernel pass repeats the same number of steps
+        head.run(a.warmup, 0)
+        head.reset()
+        total_ms, steps = head.run_to(t_final)
+        Qhead = head.Q[0].clone()
+        t_reached = gbr.gbr_get_time(head.ctx)
+        status_ok = head.status
+        head.reset()
+        ev_ms, (det_ms, stage_ms, launches) = head.run(0, steps, timing=True)
+    else:
+        # kernel pass: the same warm-up and steps with HIP events around every
+        # launch (per-kernel durations for the roofline); the events add gaps
+        # between launches, so the throughput comes from a second pass over the
+        # same work from the same initial state without them
+        ev_ms, (det_ms, stage_ms, launches) = head.run(a.warmup, steps, timing=True)
+        head.reset()
+        total_ms, _ = head.run(a.warmup, steps)
+        Qhead = head.Q[0].clone()
+        status_ok = head.status
     value = cells * 3 * steps / (total_ms * 1e-3)
-    Qhead = head.Q[0].clone()
-    status = gbr.strerror(head.status)
+    status = gbr.strerror(status_ok)
     fb_rate = None
     if head.net is not None:
         ev, fb = gbr.gbr_mlp_stats(head.ctx, reset=True)
@@ -419,19 +479,33 @@ def main():
                                   if det_ms > 0 and head.net is not None else None),
         "status": status,
     }
+    if t_final is not None:
+        out["time_to_solution_s"] = total_ms * 1e-3
+        out["t_final"] = t_final
+        out["t_reached"] = t_reached
     if fb_rate is not None:
         out["detector_fallback_rate"] = fb_rate
 
     if not a.no_compare and a.path != "fp64":
         base = Path(P, "fp64", stream, a.tiling, None, None)
-        bms, _ = base.run(a.warmup, steps)
-        bval = cells * 3 * steps / (bms * 1e-3)
+        if t_final is not None:
+            base.run(a.warmup, 0)
+            base.reset()
+            bms, bsteps = base.run_to(t_final)
+        else:
+            bsteps = steps
+            bms, _ = base.run(a.warmup, steps)
+        bval = cells * 3 * bsteps / (bms * 1e-3)
         l1, linf = diff(Qhead, base.Q[0])
-        out["fp64_plain"] = {"value": bval, "ms_per_step": bms / steps,
+        out["fp64_plain"] = {"value": bval, "ms_per_step": bms / bsteps,
                              "tile": f"{base.tile[1]}x{base.tile[2]}",
                              "status": gbr.strerror(base.status)}
+        if t_final is not None:
+            out["fp64_plain"].update({"steps": bsteps, "time_to_solution_s": bms * 1e-3})
+            out["time_to_solution_ratio_vs_fp64_plain"] = total_ms / bms
         out["speedup_vs_fp64_plain"] = value / bval
-        out["error_vs_fp64_plain"] = {"after_steps": a.warmup + steps, "L1": l1, "Linf": linf,
+        after = f"t = {t_final}" if t_final is not None else a.warmup + steps
+        out["error_vs_fp64_plain"] = {"after_steps": after, "L1": l1, "Linf": linf,
                                       "vars": ["rho", "rho_u", "rho_v", "E"]}
         if fam == "taylor_green":
             # kinetic-energy budget of the inviscid vortex: KE(t)/KE(0) of both paths

@@ -39,7 +39,21 @@ enum {
     GBR_EUNSUPPORTED = -5  /* option not available in this build             */
 };
 
-enum { GBR_BC_PERIODIC = 0, GBR_BC_TRANSMISSIVE = 1 };
+enum { GBR_BC_PERIODIC = 0, GBR_BC_TRANSMISSIVE = 1, GBR_BC_REFLECT = 2, GBR_BC_NOSLIP = 3,
+       GBR_BC_INFLOW = 4 };
+enum { GBR_RIEMANN_HLLC = 0, GBR_RIEMANN_HLLC_SS = 1 };
+
+/* One side of the domain for gbr_set_sides.  The side is split into two
+ * segments: segment 0 where the cell-centre coordinate along the side is
+ * below split0 + split_speed * t (t: the context's device time), segment 1
+ * elsewhere (split0 = +inf: one segment).  kind[g] is one of GBR_BC_*;
+ * state[g] = (rho, u, v, p) is the fixed primitive state of a GBR_BC_INFLOW
+ * segment (ignored otherwise). */
+typedef struct {
+    int kind[2];
+    double state[2][4];
+    double split0, split_speed;
+} gbr_side;
 enum { GBR_RECON_PRIM = 0, GBR_RECON_CONS = 1 };
 enum { GBR_MP_FLAGGED = 0 };
 enum { GBR_PREC_FP64 = 0, GBR_PREC_FP32_BULK = 1 };
@@ -69,7 +83,8 @@ int gbr_destroy(gbr_ctx *ctx);
 
 /* Domain [x0,x1] x [y0,y1] (cell sizes dx = (x1-x0)/nx, dy = (y1-y0)/ny) and
  * boundary type per direction: GBR_BC_PERIODIC, or GBR_BC_TRANSMISSIVE
- * (ghost cells copy the nearest interior cell). */
+ * (ghost cells copy the nearest interior cell).  Clears any side table set
+ * by gbr_set_sides. */
 int gbr_set_geometry(gbr_ctx *ctx, double x0, double x1, double y0, double y1,
                      int bc_x, int bc_y);
 
@@ -89,6 +104,42 @@ int gbr_set_geometry(gbr_ctx *ctx, double x0, double x1, double y0, double y1,
  * and leave the scheme unchanged. */
 int gbr_set_scheme(gbr_ctx *ctx, int recon, int mp_mode, int precision, int detector);
 
+/* Boundaries by side, for the paper's wall-bounded test cases (the double
+ * Mach reflection and the viscous shock tube of Sec. 3).  sides: host array
+ * of four gbr_side, in the order left (x0), right (x1), bottom (y0), top
+ * (y1), copied before return; NULL returns to the per-direction types of
+ * gbr_set_geometry.  Kinds: GBR_BC_PERIODIC (both segments of both sides of
+ * an axis, or none), GBR_BC_TRANSMISSIVE (nearest interior cell),
+ * GBR_BC_REFLECT (slip wall: the six ghost layers mirror the interior about
+ * the wall with the normal momentum negated), GBR_BC_NOSLIP (adiabatic
+ * no-slip wall: mirrored, both momentum components negated), GBR_BC_INFLOW
+ * (the fixed state in every ghost layer).  In a corner ghost cell the mirror
+ * and sign rules of both sides compose; a fixed state of the x side takes
+ * precedence over one of the y side.  Runge-Kutta stage k evaluates the
+ * boundary at t + c_k dt, c = (0, 1, 1/2).  FP64 with the plain detector only
+ * (GBR_EUNSUPPORTED otherwise); GBR_EINVAL for an unknown kind, a periodic
+ * kind on only part of an axis, a non-positive or non-finite inflow state, or
+ * a NaN split. */
+int gbr_set_sides(gbr_ctx *ctx, const gbr_side *sides);
+
+/* Riemann solver: GBR_RIEMANN_HLLC (default; eq. eqn:Riemann with Einfeldt
+ * bounds) or GBR_RIEMANN_HLLC_SS, the shock-stable HLLC the paper uses for
+ * the double Mach reflection, in its low-Mach-limited form: the two acoustic
+ * wave terms of the HLLC dissipation scaled by
+ * phi = sin(pi/2 min(1, Ma/0.1)), Ma = max(|u_L|/c_L, |u_R|/c_R) of the
+ * normal velocities.  FP64 with the plain detector and the seventh-order GRB,
+ * in either variable set, on the 31x15 and 15x15 tilings (GBR_EUNSUPPORTED
+ * otherwise). */
+int gbr_set_riemann(gbr_ctx *ctx, int kind);
+
+/* The context's device time, read by boundary segments that move
+ * (split_speed != 0).  gbr_set_time and gbr_get_time are synchronous;
+ * gbr_advance_time enqueues t += *dt_dev on the stream (call it once per
+ * step, after the third stage, with the step's device time step). */
+int gbr_set_time(gbr_ctx *ctx, double t);
+int gbr_get_time(gbr_ctx *ctx, double *t);
+int gbr_advance_time(gbr_ctx *ctx, const double *dt_dev, void *stream);
+
 /* GRB order: 7 (default; eq. eqn:grb and the flux reconstruction of eqs.
  * flux-full, flux-right) or 4, the fourth-order subset alpha = 4, beta = 0 of
  * eqs. (good_6tth-order_scheme_flux), (alpha-beta) with the same sixth-order
@@ -97,7 +148,7 @@ int gbr_set_scheme(gbr_ctx *ctx, int recon, int mp_mode, int precision, int dete
  * the GRB states wherever they enter (smooth branch and the value the MP
  * procedure starts from) and the flux reconstruction; detector, MP bounds,
  * HLLC and viscous flux are unchanged.  Order 4 runs in FP64 with the plain
- * detector, in either variable set, on the 31x15 and 15x15 tilings; otherwise
+ * detector and HLLC, in either variable set, on the 31x15 and 15x15 tilings; otherwise
  * GBR_EUNSUPPORTED (the scheme is left unchanged).  GBR_EINVAL for an order
  * other than 7 or 4. */
 int gbr_set_order(gbr_ctx *ctx, int order);

@@ -92,4 +92,9 @@ __global__ __launch_bounds__(kDtThreads) void dt_finish_kernel(const double* par
   }
 }
 
+// t += dt on the device (the clock of moving boundary segments).
+__global__ void advance_time_kernel(double* t, const double* dt) {
+  if (threadIdx.x == 0) *t = *t + *dt;
+}
+
 }  // namespace gbr

@@ -3,6 +3,7 @@
 // enqueueing anything and maps HIP errors to GBR_EDEVICE.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <new>
 #include <vector>
 
@@ -17,11 +18,11 @@ namespace {
 
 using namespace gbr;
 
-template <class C, bool MLP = false, bool CONS = false, int ORD = 7>
+template <class C, bool MLP = false, bool CONS = false, int ORD = 7, bool LM = false>
 void launch_cfg(const StageParams& P, hipStream_t s) {
   static_assert(C::LDS_BYTES <= 160 * 1024, "LDS per workgroup");
-  hipLaunchKernelGGL((meg7_stage_kernel<C, MLP, CONS, ORD>), dim3(P.ntiles), dim3(C::NT), 0, s,
-                     P);
+  hipLaunchKernelGGL((meg7_stage_kernel<C, MLP, CONS, ORD, LM>), dim3(P.ntiles), dim3(C::NT), 0,
+                     s, P);
 }
 template <class C, bool MLP = false>
 void launch_cfg_f32(const StageParams& P, hipStream_t s) {
@@ -40,6 +41,7 @@ struct TileVariant {
   const char* name;
   LaunchFn cons[2];       // MEG7-cons, FP64 with the plain detector: [viscous]; null: no build
   LaunchFn g4[2][2];      // fourth-order GRB, FP64 with the plain detector: [cons][viscous]
+  LaunchFn ss[2][2];      // shock-stable HLLC, seventh order, FP64, plain: [cons][viscous]
 };
 using E31 = TileCfg<31, 15, 15, 16, 256, false>;
 using V31 = TileCfg<31, 15, 8, 16, 256, true>;
@@ -54,7 +56,9 @@ const TileVariant kVariants[] = {
      "31x15",
      {launch_cfg<E31, false, true>, launch_cfg<V31, false, true>},
      {{launch_cfg<E31, false, false, 4>, launch_cfg<V31, false, false, 4>},
-      {launch_cfg<E31, false, true, 4>, launch_cfg<V31, false, true, 4>}}},
+      {launch_cfg<E31, false, true, 4>, launch_cfg<V31, false, true, 4>}},
+     {{launch_cfg<E31, false, false, 7, true>, launch_cfg<V31, false, false, 7, true>},
+      {launch_cfg<E31, false, true, 7, true>, launch_cfg<V31, false, true, 7, true>}}},
     // 16 interfaces per line both ways; 3-4 workgroups/CU
     {15, 15,
      {{{launch_cfg<E15>, launch_cfg<E15, true>}, {launch_cfg<V15>, launch_cfg<V15, true>}},
@@ -63,7 +67,9 @@ const TileVariant kVariants[] = {
      "15x15",
      {launch_cfg<E15, false, true>, launch_cfg<V15, false, true>},
      {{launch_cfg<E15, false, false, 4>, launch_cfg<V15, false, false, 4>},
-      {launch_cfg<E15, false, true, 4>, launch_cfg<V15, false, true, 4>}}},
+      {launch_cfg<E15, false, true, 4>, launch_cfg<V15, false, true, 4>}},
+     {{launch_cfg<E15, false, false, 7, true>, launch_cfg<V15, false, false, 7, true>},
+      {launch_cfg<E15, false, true, 7, true>, launch_cfg<V15, false, true, 7, true>}}},
     // 64 x-interfaces per row, 8 y-interfaces per column (Euler, plain detector)
     {63, 7,
      {{{launch_cfg<TileCfg<63, 7, 7, 32, 256, false>>,
@@ -74,6 +80,7 @@ const TileVariant kVariants[] = {
        {nullptr, nullptr}}},
      "63x7",
      {nullptr, nullptr},
+     {{nullptr, nullptr}, {nullptr, nullptr}},
      {{nullptr, nullptr}, {nullptr, nullptr}}},
     // 31x8 / 15x16 interface blocks sized for 3 workgroups per CU in FP32 bulk
     {30, 15,
@@ -85,6 +92,7 @@ const TileVariant kVariants[] = {
        {nullptr, nullptr}}},
      "30x15",
      {nullptr, nullptr},
+     {{nullptr, nullptr}, {nullptr, nullptr}},
      {{nullptr, nullptr}, {nullptr, nullptr}}},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
@@ -135,6 +143,10 @@ struct gbr_ctx {
   int bcx, bcy;
   int recon, mp_mode, precision, detector;
   int order;                  // GRB order: 7 or 4
+  int riemann;                // 0: HLLC, 1: shock-stable HLLC
+  int use_sides;              // 1: the side table d_sides replaces bcx / bcy
+  SideDev* d_sides;           // [4] left, right, bottom, top
+  double* d_time;             // device time of Q^n (moving boundary segments)
   int device;
   int export_flags;
   unsigned* d_status;         // [4]
@@ -205,9 +217,18 @@ int gbr_init(int nx, int ny, double gamma, double mu, double Pr, gbr_ctx** out) 
   if (hipMalloc(&c->d_partial, 2 * kDtBlocks * sizeof(double)) != hipSuccess) {
     (void)hipFree(c->d_status); delete c; return GBR_ENOMEM;
   }
+  if (hipMalloc(&c->d_sides, 4 * sizeof(SideDev)) != hipSuccess) {
+    (void)hipFree(c->d_status); (void)hipFree(c->d_partial); delete c; return GBR_ENOMEM;
+  }
+  if (hipMalloc(&c->d_time, sizeof(double)) != hipSuccess) {
+    (void)hipFree(c->d_status); (void)hipFree(c->d_partial); (void)hipFree(c->d_sides);
+    delete c; return GBR_ENOMEM;
+  }
   if (hipMemset(c->d_status, 0, 4 * sizeof(unsigned)) != hipSuccess ||
+      hipMemset(c->d_time, 0, sizeof(double)) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
-    (void)hipFree(c->d_status); (void)hipFree(c->d_partial); delete c; return GBR_EDEVICE;
+    (void)hipFree(c->d_status); (void)hipFree(c->d_partial); (void)hipFree(c->d_sides);
+    (void)hipFree(c->d_time); delete c; return GBR_EDEVICE;
   }
   *out = c;
   return GBR_OK;
@@ -218,6 +239,8 @@ int gbr_destroy(gbr_ctx* c) {
   (void)hipDeviceSynchronize();
   (void)hipFree(c->d_status);
   (void)hipFree(c->d_partial);
+  (void)hipFree(c->d_sides);
+  (void)hipFree(c->d_time);
   if (c->d_sigx) (void)hipFree(c->d_sigx);
   if (c->d_sigy) (void)hipFree(c->d_sigy);
   if (c->d_mlp_w) (void)hipFree(c->d_mlp_w);
@@ -236,7 +259,67 @@ int gbr_set_geometry(gbr_ctx* c, double x0, double x1, double y0, double y1, int
       (bc_y != GBR_BC_PERIODIC && bc_y != GBR_BC_TRANSMISSIVE))
     return GBR_EINVAL;
   c->x0 = x0; c->x1 = x1; c->y0 = y0; c->y1 = y1; c->bcx = bc_x; c->bcy = bc_y;
+  c->use_sides = 0;
   return GBR_OK;
+}
+
+int gbr_set_sides(gbr_ctx* c, const gbr_side* sides) {
+  if (!c) return GBR_EINVAL;
+  if (!sides) { c->use_sides = 0; return GBR_OK; }
+  for (int a = 0; a < 2; ++a) {
+    int nper = 0;
+    for (int sd = 2 * a; sd < 2 * a + 2; ++sd)
+      for (int g = 0; g < 2; ++g) {
+        const int k = sides[sd].kind[g];
+        if (k < GBR_BC_PERIODIC || k > GBR_BC_INFLOW) return GBR_EINVAL;
+        nper += (k == GBR_BC_PERIODIC);
+        if (k == GBR_BC_INFLOW) {
+          const double* st = sides[sd].state[g];
+          if (!(st[0] > 0.0) || !(st[3] > 0.0) || !std::isfinite(st[1]) || !std::isfinite(st[2]) ||
+              !std::isfinite(st[0]) || !std::isfinite(st[3]))
+            return GBR_EINVAL;
+        }
+      }
+    if (nper != 0 && nper != 4) return GBR_EINVAL;
+    for (int sd = 2 * a; sd < 2 * a + 2; ++sd)
+      if (std::isnan(sides[sd].split0) || !std::isfinite(sides[sd].split_speed)) return GBR_EINVAL;
+  }
+  if (c->precision != GBR_PREC_FP64 || c->detector != GBR_DET_PLAIN) return GBR_EUNSUPPORTED;
+  static_assert(sizeof(SideDev) == sizeof(gbr_side), "side layout");
+  if (hipMemcpy(c->d_sides, sides, 4 * sizeof(SideDev), hipMemcpyHostToDevice) != hipSuccess)
+    return GBR_EDEVICE;
+  c->use_sides = 1;
+  return GBR_OK;
+}
+
+int gbr_set_riemann(gbr_ctx* c, int kind) {
+  if (!c || (kind != GBR_RIEMANN_HLLC && kind != GBR_RIEMANN_HLLC_SS)) return GBR_EINVAL;
+  if (kind == GBR_RIEMANN_HLLC_SS &&
+      (c->precision != GBR_PREC_FP64 || c->detector != GBR_DET_PLAIN || c->order != 7))
+    return GBR_EUNSUPPORTED;
+  c->riemann = kind;
+  return GBR_OK;
+}
+
+int gbr_set_time(gbr_ctx* c, double t) {
+  if (!c || !std::isfinite(t)) return GBR_EINVAL;
+  if (hipMemcpy(c->d_time, &t, sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return GBR_EDEVICE;
+  return GBR_OK;
+}
+
+int gbr_get_time(gbr_ctx* c, double* t) {
+  if (!c || !t) return GBR_EINVAL;
+  if (hipMemcpy(t, c->d_time, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    return GBR_EDEVICE;
+  return GBR_OK;
+}
+
+int gbr_advance_time(gbr_ctx* c, const double* dt_dev, void* stream) {
+  if (!c || !dt_dev) return GBR_EINVAL;
+  hipLaunchKernelGGL(advance_time_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, c->d_time,
+                     dt_dev);
+  return hip_ok(hipGetLastError());
 }
 
 int gbr_set_scheme(gbr_ctx* c, int recon, int mp_mode, int precision, int detector) {
@@ -245,7 +328,7 @@ int gbr_set_scheme(gbr_ctx* c, int recon, int mp_mode, int precision, int detect
   if (mp_mode != GBR_MP_FLAGGED) return GBR_EUNSUPPORTED;
   if (precision != GBR_PREC_FP64 && precision != GBR_PREC_FP32_BULK) return GBR_EUNSUPPORTED;
   if (detector != GBR_DET_PLAIN && detector != GBR_DET_MLP) return GBR_EUNSUPPORTED;
-  if ((recon == GBR_RECON_CONS || c->order == 4) &&
+  if ((recon == GBR_RECON_CONS || c->order == 4 || c->use_sides || c->riemann) &&
       (precision != GBR_PREC_FP64 || detector != GBR_DET_PLAIN))
     return GBR_EUNSUPPORTED;
   if (detector == GBR_DET_MLP && !c->mlp_ready) return GBR_EINVAL;
@@ -256,7 +339,8 @@ int gbr_set_scheme(gbr_ctx* c, int recon, int mp_mode, int precision, int detect
 int gbr_set_order(gbr_ctx* c, int order) {
   if (!c) return GBR_EINVAL;
   if (order != 7 && order != 4) return GBR_EINVAL;
-  if (order == 4 && (c->precision != GBR_PREC_FP64 || c->detector != GBR_DET_PLAIN))
+  if (order == 4 && (c->precision != GBR_PREC_FP64 || c->detector != GBR_DET_PLAIN ||
+                     c->riemann != GBR_RIEMANN_HLLC))
     return GBR_EUNSUPPORTED;
   c->order = order;
   return GBR_OK;
@@ -302,6 +386,8 @@ int gbr_check(gbr_ctx* c, void* stream) {
 // variant has no build for it.
 static LaunchFn variant_fn(const gbr_ctx* c, int v) {
   const int visc = c->mu > 0.0 ? 1 : 0;
+  if (c->riemann == GBR_RIEMANN_HLLC_SS)
+    return kVariants[v].ss[c->recon == GBR_RECON_CONS ? 1 : 0][visc];
   if (c->order == 4) return kVariants[v].g4[c->recon == GBR_RECON_CONS ? 1 : 0][visc];
   if (c->recon == GBR_RECON_CONS) return kVariants[v].cons[visc];
   const int prec = c->precision == GBR_PREC_FP32_BULK ? 1 : 0;
@@ -323,6 +409,12 @@ static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn
   P.gamma = c->gamma; P.g1inv = 1.0 / (c->gamma - 1.0); P.mu = c->mu;
   P.kq = c->mu / (c->Pr * (c->gamma - 1.0));
   P.mode = mode;
+  P.sides = c->use_sides ? c->d_sides : nullptr;
+  P.tnow = c->d_time;
+  // boundary time of stage k: t + c_k dt, c = (0, 1, 1/2)
+  P.tc = mode == MODE_STAGE2 ? 1.0 : (mode == MODE_STAGE3 ? 0.5 : 0.0);
+  P.x0 = c->x0; P.y0 = c->y0;
+  P.dx = (c->x1 - c->x0) / c->nx; P.dy = (c->y1 - c->y0) / c->ny;
   const int det = c->detector == GBR_DET_MLP ? 1 : 0;
   hipEvent_t* tev = nullptr;
   if (c->timing) {

@@ -312,10 +312,32 @@ __device__ __forceinline__ void conv_flux_jump(const double Wm[4], const double 
   dF[3] = Wp[1] * (dE + dp) + (Em + Wm[3]) * du;
 }
 
+// sin(x) for x in [0, pi/2]: its Taylor series to x^21 (truncation below
+// 3e-16 on that interval), in Horner form on x^2.  Small in registers, unlike
+// the library sine, so it can sit inside the Riemann solver.
+__device__ __forceinline__ double sin_quarter(double x) {
+  const double z = x * x;
+  double t = 1.0 / 51090942171709440000.0;          // 1/21!
+  t = fma(t, -z, 1.0 / 121645100408832000.0);        // 1/19!
+  t = fma(t, -z, 1.0 / 355687428096000.0);           // 1/17!
+  t = fma(t, -z, 1.0 / 1307674368000.0);             // 1/15!
+  t = fma(t, -z, 1.0 / 6227020800.0);                // 1/13!
+  t = fma(t, -z, 1.0 / 39916800.0);                  // 1/11!
+  t = fma(t, -z, 1.0 / 362880.0);                    // 1/9!
+  t = fma(t, -z, 1.0 / 5040.0);                      // 1/7!
+  t = fma(t, -z, 1.0 / 120.0);                       // 1/5!
+  t = fma(t, -z, 1.0 / 6.0);                         // 1/3!
+  t = fma(t, -z, 1.0);
+  return x * t;
+}
+
 // HLLC with Einfeldt (Roe-average) bounds in the wave-sum form
-//   F = (F_L + F_R)/2 - (|S_L|(Q*_L - Q_L) + |S*|(Q*_R - Q*_L) + |S_R|(Q_R - Q*_R))/2
+//   F = (F_L + F_R)/2 - (phi |S_L|(Q*_L - Q_L) + |S*|(Q*_R - Q*_L) + phi |S_R|(Q_R - Q*_R))/2
 // which is the canonical form of eq. (eqn:Riemann).  Only the mean
 // Fm = (F_L + F_R)/2 of the reconstructed fluxes enters, so callers pass it.
+// phi = 1 for HLLC; the shock-stable (low-Mach-limited) form takes
+// phi = sin(pi/2 min(1, Ma/0.1)), Ma = max(|u_L|/c_L, |u_R|/c_R).
+template <bool LOW_MACH = false>
 __device__ __forceinline__ void hllc(const double WL[4], const double WR[4], const double Fm[4],
                                      double gamma, double g1inv, double F[4]) {
   const double rl = WL[0], ul = WL[1], vl = WL[2], pl = WL[3];
@@ -341,7 +363,12 @@ __device__ __forceinline__ void hllc(const double WL[4], const double WR[4], con
   const double QR[4] = {rr, rr * ur, rr * vr, Er};
   const double QsL[4] = {kl, kl * Ss, kl * vl, kl * (El * irl + (Ss - ul) * (Ss + pl * rcp_nr(ml)))};
   const double QsR[4] = {kr, kr * Ss, kr * vr, kr * (Er * irr + (Ss - ur) * (Ss + pr * rcp_nr(mr)))};
-  const double aL = fabs(SL), aS = fabs(Ss), aR = fabs(SR);
+  double phi = 1.0;
+  if (LOW_MACH) {
+    const double ma = fmax(fabs(ul) / cl, fabs(ur) / cr);
+    if (ma < 0.1) phi = sin_quarter((0.5 * 3.14159265358979323846) * (ma / 0.1));
+  }
+  const double aL = phi * fabs(SL), aS = fabs(Ss), aR = phi * fabs(SR);
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const double diss = aL * (QsL[m] - QL[m]) + aS * (QsR[m] - QsL[m]) + aR * (QR[m] - QsR[m]);

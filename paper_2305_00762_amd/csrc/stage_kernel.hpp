@@ -22,6 +22,16 @@ namespace gbr {
 
 enum : int { MODE_RESIDUAL = 0, MODE_STAGE1 = 1, MODE_STAGE2 = 2, MODE_STAGE3 = 3 };
 enum : unsigned { STATUS_BAD_STATE = 1u };
+enum : int { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECT = 2, BC_NOSLIP = 3, BC_INFLOW = 4 };
+
+// One side of the domain (same layout as gbr_side): segment 0 where the
+// tangential cell-centre coordinate is below split0 + split_speed t, segment
+// 1 beyond; a kind per segment and, for BC_INFLOW, a primitive state.
+struct SideDev {
+  int kind[2];
+  double state[2][4];
+  double split0, split_speed;
+};
 
 struct StageParams {
   const double* __restrict__ Qk;  // state the residual is evaluated on
@@ -37,6 +47,11 @@ struct StageParams {
   double gamma, g1inv, mu, kq;    // kq = mu / (Pr (gamma-1))
   int mode;
   const uint8_t* chimap;          // learned-detector flags per cell [ny][nx]: bit 0 x, bit 1 y
+  // boundaries by side (left, right, bottom, top); null: bcx / bcy on both sides
+  const SideDev* __restrict__ sides;
+  const double* tnow;             // device time of Q^n (moving boundary segments)
+  double tc;                      // stage abscissa: boundary time = tnow + tc dt
+  double x0, y0, dx, dy;          // cell-centre coordinates of the boundary segments
 };
 
 // Ghost cells by index: periodic wrap or transmissive clamp.  The offsets
@@ -108,7 +123,7 @@ __device__ __forceinline__ void load_chimap(const StageParams& P, unsigned char*
   }
 }
 
-template <class C, int DIR, bool DETMLP, bool CONS, int ORD>
+template <class C, int DIR, bool DETMLP, bool CONS, int ORD, bool LM>
 __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0, int tx0,
                                       int ty0, double (&res)[C::CPT][4]) {
   constexpr bool X = (DIR == 0);
@@ -318,7 +333,7 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
 #pragma unroll
             for (int m = 0; m < 4; ++m) Fm[m] = 0.5 * (f0[m] + f1[m]);
           }
-          hllc(WL, WR, Fm, P.gamma, P.g1inv, fsm[k]);
+          hllc<LM>(WL, WR, Fm, P.gamma, P.g1inv, fsm[k]);
           if (C::VISC) visc_at(line, pos, r, fsm[k]);
           has[k] = true;
         }
@@ -386,7 +401,7 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
     conv_flux(WR, P.g1inv, FR);
 #pragma unroll
     for (int m = 0; m < 4; ++m) Fm[m] = 0.5 * (FL[m] + FR[m]);
-    hllc(WL, WR, Fm, P.gamma, P.g1inv, F);
+    hllc<LM>(WL, WR, Fm, P.gamma, P.g1inv, F);
     if (C::VISC) visc_at(line, pos, r, F);
 #pragma unroll
     for (int m = 0; m < 4; ++m) sF[m * FSTR + bidx(line, p, WFS)] = F[m];
@@ -435,45 +450,130 @@ __device__ __forceinline__ bool tile_origin(const StageParams& P, int TX, int TY
 // Stage Q^(k) of the tile plus its 6-cell halo as primitives (rho, u, v, p
 // [, T = gamma p / rho]) in LDS; MEG7-cons keeps (rho, rho u, rho v, E [, T]).  All global loads are issued before any is
 // consumed, so the memory latency is paid once rather than once per round.
+// Boundary rules of a ghost cell at raw index k along an axis (0: x, 1: y)
+// from the side table: the side's kind at the cell's segment (-1 inside the
+// grid), the segment, and the source index -- wrap (periodic), mirror about
+// the wall (reflecting, no-slip; clamped where a ragged tile overhangs the
+// grid by more than the grid), or the nearest cell.
+__device__ __forceinline__ int side_kind(const StageParams& P, int axis, int k, double tang,
+                                         double tb, int& side, int& seg, int& src) {
+#pragma clang fp contract(off)
+  const int n = axis == 0 ? P.nx : P.ny;
+  src = k;
+  side = 2 * axis + (k >= n ? 1 : 0);
+  seg = 0;
+  if (k >= 0 && k < n) return -1;
+  const SideDev& S = P.sides[side];
+  seg = (tang < S.split0 + S.split_speed * tb) ? 0 : 1;
+  const int kind = S.kind[seg];
+  if (kind == BC_PERIODIC) {
+    src = bc_index(k, n, 0);
+  } else if (kind == BC_REFLECT || kind == BC_NOSLIP) {
+    const int m = k < 0 ? -1 - k : 2 * n - 1 - k;
+    src = m < 0 ? 0 : (m >= n ? n - 1 : m);
+  } else {
+    src = k < 0 ? 0 : (k >= n ? n - 1 : k);
+  }
+  return kind;
+}
+
+// Sign and fixed-state rules of a ghost cell, packed: bit 0 negate rho u,
+// bit 1 negate rho v, bit 2 fixed state, bits 3-4 its side, bit 5 its segment.
+__device__ __forceinline__ unsigned ghost_op(int kx, int ky, int sx, int gx, int sy, int gy) {
+  unsigned op = 0;
+  if (kx == BC_REFLECT || kx == BC_NOSLIP) op ^= 1u;
+  if (kx == BC_NOSLIP) op ^= 2u;
+  if (ky == BC_REFLECT || ky == BC_NOSLIP) op ^= 2u;
+  if (ky == BC_NOSLIP) op ^= 1u;
+  if (kx == BC_INFLOW)
+    op |= 4u | ((unsigned)sx << 3) | ((unsigned)gx << 5);
+  else if (ky == BC_INFLOW)
+    op |= 4u | ((unsigned)sy << 3) | ((unsigned)gy << 5);
+  return op;
+}
+
 template <class C, bool CONS = false>
 __device__ __forceinline__ void stage_load(const StageParams& P, double* sU, int tx0, int ty0) {
   constexpr int RS = C::RS, RX = C::RX, H = C::H, NT = C::NT, TX = C::TX, TY = C::TY;
   constexpr int LR = (RS + NT - 1) / NT;
   const int tid = threadIdx.x;
   const size_t n = (size_t)P.nx * P.ny;
-  double q[LR][4];
-#pragma unroll
-  for (int k = 0; k < LR; ++k) {
-    const int c = tid + k * NT;
-    if (c < RS) {
-      const int ly = c / RX - H, lx = c % RX - H;
-      const int gi = bc_index(ty0 + ly, P.ny, P.bcy);
-      const int gj = bc_index(tx0 + lx, P.nx, P.bcx);
-      const size_t s = (size_t)gi * P.nx + gj;
-#pragma unroll
-      for (int m = 0; m < 4; ++m) q[k][m] = P.Qk[m * n + s];
-    }
-  }
   bool bad = false;
+  // one cell of the tile: conservative values (ghost rules applied) to the
+  // staged variables; op as packed by ghost_op
+  auto put = [&](int c, double r, double mx, double my, double E, unsigned op) {
+    const int ly = c / RX - H, lx = c % RX - H;
+    if (op & 1u) mx = -mx;
+    if (op & 2u) my = -my;
+    double ir = rcp_nr(r);
+    double u = mx * ir, v = my * ir;
+    double p = (P.gamma - 1.0) * (E - 0.5 * r * (u * u + v * v));
+    if (op & 4u) {
+      // fixed (inflow) state: primitives as given, conservative from them
+      const double* st = P.sides[(op >> 3) & 3u].state[(op >> 5) & 1u];
+      r = st[0]; u = st[1]; v = st[2]; p = st[3];
+      ir = rcp_nr(r);
+      mx = r * u; my = r * v;
+      E = p * P.g1inv + 0.5 * r * (u * u + v * v);
+    }
+    sU[c] = r;
+    sU[RS + c] = CONS ? mx : u;
+    sU[2 * RS + c] = CONS ? my : v;
+    sU[3 * RS + c] = CONS ? E : p;
+    if (C::VISC) sU[4 * RS + c] = P.gamma * p * ir;
+    const bool interior = lx >= 0 && lx < TX && ly >= 0 && ly < TY && tx0 + lx < P.nx &&
+                          ty0 + ly < P.ny;
+    if (interior && !(r > 0.0 && p > 0.0 && isfinite(E) && isfinite(mx) && isfinite(my) &&
+                      isfinite(r)))
+      bad = true;
+  };
+  // the side table matters only where the tile's halo reaches past the grid
+  const bool walls = P.sides != nullptr &&
+                     !(tx0 >= H && ty0 >= H && tx0 + TX + H <= P.nx && ty0 + TY + H <= P.ny);
+  if (!walls) {
+    // all global loads issued before any is consumed: the memory latency is
+    // paid once rather than once per round
+    double q[LR][4];
 #pragma unroll
-  for (int k = 0; k < LR; ++k) {
-    const int c = tid + k * NT;
-    if (c < RS) {
+    for (int k = 0; k < LR; ++k) {
+      const int c = tid + k * NT;
+      if (c < RS) {
+        const int ly = c / RX - H, lx = c % RX - H;
+        const int gi = bc_index(ty0 + ly, P.ny, P.bcy);
+        const int gj = bc_index(tx0 + lx, P.nx, P.bcx);
+        const size_t s = (size_t)gi * P.nx + gj;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) q[k][m] = P.Qk[m * n + s];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < LR; ++k) {
+      const int c = tid + k * NT;
+      if (c < RS) put(c, q[k][0], q[k][1], q[k][2], q[k][3], 0u);
+    }
+  } else {
+    // boundary tiles with a side table: one cell at a time
+    double tb;
+    {
+#pragma clang fp contract(off)
+      tb = *P.tnow + (P.tc != 0.0 ? P.tc * *P.dt : 0.0);
+    }
+#pragma unroll 1
+    for (int c = tid; c < RS; c += NT) {
       const int ly = c / RX - H, lx = c % RX - H;
-      const double r = q[k][0], mx = q[k][1], my = q[k][2], E = q[k][3];
-      const double ir = rcp_nr(r);
-      const double u = mx * ir, v = my * ir;
-      const double p = (P.gamma - 1.0) * (E - 0.5 * r * (u * u + v * v));
-      sU[c] = r;
-      sU[RS + c] = CONS ? mx : u;
-      sU[2 * RS + c] = CONS ? my : v;
-      sU[3 * RS + c] = CONS ? E : p;
-      if (C::VISC) sU[4 * RS + c] = P.gamma * p * ir;
-      const bool interior = lx >= 0 && lx < TX && ly >= 0 && ly < TY && tx0 + lx < P.nx &&
-                            ty0 + ly < P.ny;
-      if (interior && !(r > 0.0 && p > 0.0 && isfinite(E) && isfinite(mx) && isfinite(my) &&
-                        isfinite(r)))
-        bad = true;
+      const int i = ty0 + ly, j = tx0 + lx;
+      double xc, yc;
+      {
+#pragma clang fp contract(off)
+        xc = P.x0 + ((double)j + 0.5) * P.dx;
+        yc = P.y0 + ((double)i + 0.5) * P.dy;
+      }
+      int sx, gx, sy, gy, gi, gj;
+      const int kx = side_kind(P, 0, j, yc, tb, sx, gx, gj);
+      const int ky = side_kind(P, 1, i, xc, tb, sy, gy, gi);
+      const size_t s = (size_t)gi * P.nx + gj;
+      put(c, P.Qk[s], P.Qk[n + s], P.Qk[2 * n + s], P.Qk[3 * n + s],
+          ghost_op(kx, ky, sx, gx, sy, gy));
     }
   }
   if (bad) atomicOr(P.status, STATUS_BAD_STATE);
@@ -527,7 +627,7 @@ __device__ __forceinline__ void stage_store(const StageParams& P, const double (
 // One tile of the stage: load, both sweeps, store.  The LDS arrays are
 // passed in so that a kernel can run several tile shapes from one set of
 // arrays sized for the largest (the batched kernel).
-template <class C, bool DETMLP, bool CONS = false, int ORD = 7>
+template <class C, bool DETMLP, bool CONS = false, int ORD = 7, bool LM = false>
 __device__ __forceinline__ void stage_tile(const StageParams& P, int tx0, int ty0, double* sU,
                                            double* sPh, unsigned char* sChi,
                                            unsigned short* sQueue, int* sQCount,
@@ -542,13 +642,13 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int tx0, int ty
 #pragma unroll
     for (int m = 0; m < 4; ++m) res[k][m] = 0.0;
   for (int l0 = 0; l0 < C::TY; l0 += C::SX)
-    sweep<C, 0, DETMLP, CONS, ORD>(P, L, l0, tx0, ty0, res);
+    sweep<C, 0, DETMLP, CONS, ORD, LM>(P, L, l0, tx0, ty0, res);
   for (int l0 = 0; l0 < C::TX; l0 += C::SY)
-    sweep<C, 1, DETMLP, CONS, ORD>(P, L, l0, tx0, ty0, res);
+    sweep<C, 1, DETMLP, CONS, ORD, LM>(P, L, l0, tx0, ty0, res);
   stage_store<C>(P, res, tx0, ty0);
 }
 
-template <class C, bool DETMLP, bool CONS = false, int ORD = 7>
+template <class C, bool DETMLP, bool CONS = false, int ORD = 7, bool LM = false>
 __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel(StageParams P) {
   __shared__ double sU[C::NF * C::RS];
   __shared__ double sPh[C::PH];
@@ -558,7 +658,7 @@ __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel(StageParams 
   __shared__ int sQCount;
   int tx0, ty0;
   if (!tile_origin(P, C::TX, C::TY, tx0, ty0)) return;
-  stage_tile<C, DETMLP, CONS, ORD>(P, tx0, ty0, sU, sPh, sChi, sQueue, &sQCount, sChiF);
+  stage_tile<C, DETMLP, CONS, ORD, LM>(P, tx0, ty0, sU, sPh, sChi, sQueue, &sQCount, sChiF);
 }
 
 }  // namespace gbr

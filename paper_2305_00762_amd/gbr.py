@@ -22,6 +22,11 @@ GBR_ESTATE = -4
 GBR_EUNSUPPORTED = -5
 GBR_BC_PERIODIC = 0
 GBR_BC_TRANSMISSIVE = 1
+GBR_BC_REFLECT = 2
+GBR_BC_NOSLIP = 3
+GBR_BC_INFLOW = 4
+GBR_RIEMANN_HLLC = 0
+GBR_RIEMANN_HLLC_SS = 1
 GBR_RECON_PRIM = 0
 GBR_RECON_CONS = 1
 GBR_MP_FLAGGED = 0
@@ -40,6 +45,11 @@ SIGNATURES = {
     "gbr_set_geometry": (_i, [_vp, _d, _d, _d, _d, _i, _i]),
     "gbr_set_scheme": (_i, [_vp, _i, _i, _i, _i]),
     "gbr_set_order": (_i, [_vp, _i]),
+    "gbr_set_sides": (_i, [_vp, _vp]),
+    "gbr_set_riemann": (_i, [_vp, _i]),
+    "gbr_set_time": (_i, [_vp, _d]),
+    "gbr_get_time": (_i, [_vp, C.POINTER(C.c_double)]),
+    "gbr_advance_time": (_i, [_vp, _vp, _vp]),
     "gbr_residual": (_i, [_vp, _vp, _vp, _vp]),
     "gbr_rk_stage": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
     "gbr_compute_dt": (_i, [_vp, _vp, _d, _vp, _vp]),
@@ -170,6 +180,46 @@ def gbr_set_scheme(ctx, recon=GBR_RECON_PRIM, mp_mode=GBR_MP_FLAGGED,
 
 def gbr_set_order(ctx, order):
     return _check(load().gbr_set_order(ctx, order), "gbr_set_order")
+
+
+class GbrSide(C.Structure):
+    """gbr_side of include/gbr.h."""
+    _fields_ = [("kind", C.c_int * 2), ("state", (C.c_double * 4) * 2),
+                ("split0", C.c_double), ("split_speed", C.c_double)]
+
+
+def gbr_set_sides(ctx, sides):
+    """sides: four (kind, state, kind1, state1, split0, split_speed) tuples
+    (left, right, bottom, top), or None."""
+    if sides is None:
+        return _check(load().gbr_set_sides(ctx, None), "gbr_set_sides")
+    arr = (GbrSide * 4)()
+    for k, (k0, s0, k1, s1, split0, speed) in enumerate(sides):
+        arr[k].kind[0], arr[k].kind[1] = k0, k1
+        for g, st in enumerate((s0, s1)):
+            if st is not None:
+                for m in range(4):
+                    arr[k].state[g][m] = st[m]
+        arr[k].split0, arr[k].split_speed = split0, speed
+    return _check(load().gbr_set_sides(ctx, C.cast(arr, C.c_void_p)), "gbr_set_sides")
+
+
+def gbr_set_riemann(ctx, kind):
+    return _check(load().gbr_set_riemann(ctx, kind), "gbr_set_riemann")
+
+
+def gbr_set_time(ctx, t):
+    return _check(load().gbr_set_time(ctx, t), "gbr_set_time")
+
+
+def gbr_get_time(ctx):
+    t = C.c_double()
+    _check(load().gbr_get_time(ctx, C.byref(t)), "gbr_get_time")
+    return t.value
+
+
+def gbr_advance_time(ctx, dt, stream=None):
+    return _check(load().gbr_advance_time(ctx, _addr(dt), _stream(stream)), "gbr_advance_time")
 
 
 def gbr_residual(ctx, Q, Res, stream=None):

@@ -23,6 +23,10 @@ class Solver:
         gbr.gbr_set_scheme(self.ctx, recon, gbr.GBR_MP_FLAGGED, precision, detector)
         if order != 7:
             gbr.gbr_set_order(self.ctx, order)
+        if getattr(problem, "sides", None) is not None:
+            gbr.gbr_set_sides(self.ctx, problem.sides)
+        if getattr(problem, "riemann", 0):
+            gbr.gbr_set_riemann(self.ctx, problem.riemann)
         if export_flags:
             gbr.gbr_export_flags(self.ctx, True)
         shape = (4, problem.ny, problem.nx)
@@ -63,13 +67,19 @@ class Solver:
         return self.dt
 
     def step(self, cfl=None):
-        """One SSP-RK3 step: dt from Q^n on the device, three stage kernels.
-        Q holds Q^{n+1} afterwards; no host synchronisation."""
+        """One SSP-RK3 step: dt from Q^n on the device, three stage kernels,
+        the device clock advanced by dt.  Q holds Q^{n+1} afterwards; no host
+        synchronisation."""
         self.compute_dt(cfl)
         gbr.gbr_rk_stage(self.ctx, 1, self.dt, self.Q, self.Q, self.Q1, self.stream)
         gbr.gbr_rk_stage(self.ctx, 2, self.dt, self.Q, self.Q1, self.Q2, self.stream)
         gbr.gbr_rk_stage(self.ctx, 3, self.dt, self.Q, self.Q2, self.Q1, self.stream)
+        gbr.gbr_advance_time(self.ctx, self.dt, self.stream)
         self.Q, self.Q1 = self.Q1, self.Q
+
+    def time(self):
+        self.torch.cuda.synchronize()
+        return gbr.gbr_get_time(self.ctx)
 
     def flags(self):
         sx = np.zeros((self.p.ny, self.p.nx + 1), np.uint8)
