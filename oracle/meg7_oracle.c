@@ -1193,3 +1193,382 @@ int orc_cell_flags(const orc_cfg *c, const double *Q, uint8_t *chi, double *psix
     fields_free(&F);
     return 0;
 }
+
+/* ====================================================================== */
+/* Three dimensions (the paper's 3D Taylor-Green comparison): the Euler     */
+/* equations with conservative variables (rho, rho u, rho v, rho w, E),     */
+/* discretised dimension by dimension exactly as in 2D.  Reading R-3D: the  */
+/* rotated frame of direction d holds (rho, u_n, u_t1, u_t2, p) with the    */
+/* tangential components taken cyclically (x: v, w; y: w, u; z: u, v); the  */
+/* characteristic projection adds the identity row of the second           */
+/* tangential velocity to R-CHAR; HLLC (R-HLLC) carries both tangential     */
+/* momenta.  Inviscid only.                                                 */
+/* ====================================================================== */
+
+typedef struct {
+    int nx, ny, nz;
+    double x0, x1, y0, y1, z0, z1;
+    int bc[3];
+    double gamma;
+    int order;
+} orc3_cfg;
+
+static int cfg3_ok(const orc3_cfg *c)
+{
+    return c && c->nx >= 2 * NG && c->ny >= 2 * NG && c->nz >= 2 * NG && c->gamma > 1.0
+        && c->x1 > c->x0 && c->y1 > c->y0 && c->z1 > c->z0
+        && (c->order == 7 || c->order == 4)
+        && c->bc[0] >= 0 && c->bc[0] <= 1 && c->bc[1] >= 0 && c->bc[1] <= 1
+        && c->bc[2] >= 0 && c->bc[2] <= 1;
+}
+
+/* eq. (eqn:pressure) inverted, 3D rotated frame. */
+static void prim_to_cons3(const double W[5], double gamma, double Q[5])
+{
+    Q[0] = W[0];
+    Q[1] = W[0] * W[1];
+    Q[2] = W[0] * W[2];
+    Q[3] = W[0] * W[3];
+    Q[4] = W[4] / (gamma - 1.0) + 0.5 * W[0] * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]);
+}
+
+/* The convective flux along the normal. */
+static void conv_flux3(const double W[5], double gamma, double F[5])
+{
+    double Q[5];
+    prim_to_cons3(W, gamma, Q);
+    F[0] = W[0] * W[1];
+    F[1] = W[0] * W[1] * W[1] + W[4];
+    F[2] = W[0] * W[1] * W[2];
+    F[3] = W[0] * W[1] * W[3];
+    F[4] = W[1] * (Q[4] + W[4]);
+}
+
+/* HLLC, reading R-HLLC, in 3D. */
+static void hllc3(const double WL[5], const double WR[5], const double FL[5],
+                  const double FR[5], double gamma, double F[5])
+{
+    double QL[5], QR[5];
+    prim_to_cons3(WL, gamma, QL);
+    prim_to_cons3(WR, gamma, QR);
+    double rl = WL[0], ul = WL[1], pl = WL[4];
+    double rr = WR[0], ur = WR[1], pr = WR[4];
+    double cl = sqrt(gamma * pl / rl);
+    double cr = sqrt(gamma * pr / rr);
+    double hl = (QL[4] + pl) / rl;
+    double hr = (QR[4] + pr) / rr;
+    double sl_ = sqrt(rl), sr_ = sqrt(rr);
+    double ut = (sl_ * ul + sr_ * ur) / (sl_ + sr_);
+    double vt = (sl_ * WL[2] + sr_ * WR[2]) / (sl_ + sr_);
+    double wt = (sl_ * WL[3] + sr_ * WR[3]) / (sl_ + sr_);
+    double ht = (sl_ * hl + sr_ * hr) / (sl_ + sr_);
+    double ct = sqrt((gamma - 1.0) * (ht - 0.5 * (ut * ut + vt * vt + wt * wt)));
+    double SL = fmin(ul - cl, ut - ct);
+    double SR = fmax(ur + cr, ut + ct);
+    double Ss = (pr - pl + rl * ul * (SL - ul) - rr * ur * (SR - ur))
+              / (rl * (SL - ul) - rr * (SR - ur));
+    double QsL[5], QsR[5];
+    double kl = rl * (SL - ul) / (SL - Ss);
+    QsL[0] = kl;
+    QsL[1] = kl * Ss;
+    QsL[2] = kl * WL[2];
+    QsL[3] = kl * WL[3];
+    QsL[4] = kl * (QL[4] / rl + (Ss - ul) * (Ss + pl / (rl * (SL - ul))));
+    double kr = rr * (SR - ur) / (SR - Ss);
+    QsR[0] = kr;
+    QsR[1] = kr * Ss;
+    QsR[2] = kr * WR[2];
+    QsR[3] = kr * WR[3];
+    QsR[4] = kr * (QR[4] / rr + (Ss - ur) * (Ss + pr / (rr * (SR - ur))));
+    for (int m = 0; m < 5; ++m) {
+        double diss = fabs(SL) * (QsL[m] - QL[m]) + fabs(Ss) * (QsR[m] - QsL[m])
+                    + fabs(SR) * (QR[m] - QsR[m]);
+        F[m] = 0.5 * (FL[m] + FR[m]) - 0.5 * diss;
+    }
+}
+
+/* R-CHAR with the second tangential velocity (row and column of identity). */
+static void char_fwd3(const double U[5], double rb, double cb, double Wc[5])
+{
+    Wc[0] = -rb / (2.0 * cb) * U[1] + U[4] / (2.0 * cb * cb);
+    Wc[1] = U[0] - U[4] / (cb * cb);
+    Wc[2] = U[2];
+    Wc[3] = U[3];
+    Wc[4] = rb / (2.0 * cb) * U[1] + U[4] / (2.0 * cb * cb);
+}
+
+static void char_bwd3(const double Wc[5], double rb, double cb, double U[5])
+{
+    U[0] = Wc[0] + Wc[1] + Wc[4];
+    U[1] = cb / rb * (Wc[4] - Wc[0]);
+    U[2] = Wc[2];
+    U[3] = Wc[3];
+    U[4] = cb * cb * (Wc[0] + Wc[4]);
+}
+
+/* Everything the flux at one interface j+1/2 reads along its normal. */
+typedef struct {
+    double W[5][10];   /* (rho, un, ut1, ut2, p) at offsets -4..5 */
+    double G[5][6];    /* their Delta_n d/dn at offsets -2..3      */
+    double psi[6];     /* detector at offsets -2..3               */
+} orc3_line;
+
+static void line_flux3(const orc3_line *L, const orc3_cfg *c, double Fout[5], int *sig_out)
+{
+    const double gamma = c->gamma;
+    double pmin = L->psi[0];
+    for (int k = 1; k < 6; ++k) pmin = fmin(pmin, L->psi[k]);
+    const int sigma = (pmin < PSI_C) ? 0 : 1;       /* eq. (buffer) */
+    *sig_out = sigma;
+    double WL[5], WR[5], FL[5], FR[5];
+    if (sigma) {
+        for (int m = 0; m < 5; ++m) {
+            WL[m] = grb_L(c->order, &L->W[m][4], &L->G[m][2]);
+            WR[m] = grb_R(c->order, &L->W[m][4], &L->G[m][2]);
+        }
+        double f[5][10];
+        for (int k = 0; k < 10; ++k) {
+            double w[5], ff[5];
+            for (int m = 0; m < 5; ++m) w[m] = L->W[m][k];
+            conv_flux3(w, gamma, ff);
+            for (int m = 0; m < 5; ++m) f[m][k] = ff[m];
+        }
+        for (int m = 0; m < 5; ++m) {
+            FL[m] = flux_L(c->order, &f[m][4]);
+            FR[m] = flux_R(c->order, &f[m][4]);
+        }
+    } else {
+        double rb = 0.5 * (L->W[0][4] + L->W[0][5]);
+        double pb = 0.5 * (L->W[4][4] + L->W[4][5]);
+        double cb = sqrt(gamma * pb / rb);
+        double cw[5][6], cg[5][6];
+        for (int k = 0; k < 6; ++k) {
+            double u[5], w[5], g[5], wg[5];
+            for (int m = 0; m < 5; ++m) { u[m] = L->W[m][k + 2]; g[m] = L->G[m][k]; }
+            char_fwd3(u, rb, cb, w);
+            char_fwd3(g, rb, cb, wg);
+            for (int m = 0; m < 5; ++m) { cw[m][k] = w[m]; cg[m][k] = wg[m]; }
+        }
+        double wl[5], wr[5];
+        for (int m = 0; m < 5; ++m) {
+            wl[m] = meg7_left_o(c->order, &cw[m][2], &cg[m][2], NULL);
+            wr[m] = meg7_right_o(c->order, &cw[m][2], &cg[m][2], NULL);
+        }
+        char_bwd3(wl, rb, cb, WL);
+        char_bwd3(wr, rb, cb, WR);
+        conv_flux3(WL, gamma, FL);
+        conv_flux3(WR, gamma, FR);
+    }
+    /* reading R-POS */
+    if (!(WL[0] > 0.0 && WL[4] > 0.0 && WR[0] > 0.0 && WR[4] > 0.0)) {
+        for (int m = 0; m < 5; ++m) { WL[m] = L->W[m][4]; WR[m] = L->W[m][5]; }
+        conv_flux3(WL, gamma, FL);
+        conv_flux3(WR, gamma, FR);
+    }
+    hllc3(WL, WR, FL, FR, gamma, Fout);
+}
+
+/* Padded primitive fields, gradients and detector values (periodic wrap or
+ * transmissive clamp per axis, NG ghost layers). */
+typedef struct {
+    int NX, NY, NZ;
+    double *W[5];
+    double *G[3][5];
+    double *psi[3];
+} orc3_fields;
+
+static void fields3_free(orc3_fields *F)
+{
+    for (int m = 0; m < 5; ++m) {
+        free(F->W[m]);
+        for (int d = 0; d < 3; ++d) free(F->G[d][m]);
+    }
+    for (int d = 0; d < 3; ++d) free(F->psi[d]);
+}
+
+static int fields3_build(const orc3_cfg *c, const double *Q, orc3_fields *F)
+{
+    const int nx = c->nx, ny = c->ny, nz = c->nz;
+    const int NX = nx + 2 * NG, NY = ny + 2 * NG, NZ = nz + 2 * NG;
+    const size_t np = (size_t)NX * NY * NZ, n = (size_t)nx * ny * nz;
+    memset(F, 0, sizeof(*F));
+    F->NX = NX; F->NY = NY; F->NZ = NZ;
+    for (int m = 0; m < 5; ++m) {
+        F->W[m] = (double *)calloc(np, sizeof(double));
+        if (!F->W[m]) return -1;
+        for (int d = 0; d < 3; ++d) {
+            F->G[d][m] = (double *)calloc(np, sizeof(double));
+            if (!F->G[d][m]) return -1;
+        }
+    }
+    for (int d = 0; d < 3; ++d) {
+        F->psi[d] = (double *)calloc(np, sizeof(double));
+        if (!F->psi[d]) return -1;
+    }
+    const double gamma = c->gamma;
+#pragma omp parallel for schedule(static)
+    for (int K = 0; K < NZ; ++K) {
+        const int k = bc_index(K - NG, nz, c->bc[2]);
+        for (int I = 0; I < NY; ++I) {
+            const int i = bc_index(I - NG, ny, c->bc[1]);
+            for (int J = 0; J < NX; ++J) {
+                const int j = bc_index(J - NG, nx, c->bc[0]);
+                const size_t s = ((size_t)k * ny + i) * nx + j;
+                double rho = Q[s], mx = Q[n + s], my = Q[2 * n + s], mz = Q[3 * n + s];
+                double E = Q[4 * n + s];
+                double u = mx / rho, v = my / rho, w = mz / rho;
+                double p = (gamma - 1.0) * (E - rho * (u * u + v * v + w * w) / 2.0);
+                const size_t P = ((size_t)K * NY + I) * NX + J;
+                F->W[0][P] = rho; F->W[1][P] = u; F->W[2][P] = v; F->W[3][P] = w;
+                F->W[4][P] = p;
+            }
+        }
+    }
+    const ptrdiff_t stride[3] = {1, NX, (ptrdiff_t)NX * NY};
+    const int ext[3] = {NX, NY, NZ};
+#pragma omp parallel for schedule(static)
+    for (int K = 0; K < NZ; ++K)
+        for (int I = 0; I < NY; ++I)
+            for (int J = 0; J < NX; ++J) {
+                const size_t P = ((size_t)K * NY + I) * NX + J;
+                const int idx[3] = {J, I, K};
+                for (int d = 0; d < 3; ++d) {
+                    const int ok6 = idx[d] >= 3 && idx[d] < ext[d] - 3;
+                    for (int m = 0; m < 5; ++m) {
+                        double p7[7];
+                        for (int q = -3; q <= 3; ++q)
+                            p7[q + 3] = ok6 ? F->W[m][P + q * stride[d]] : 0.0;
+                        F->G[d][m][P] = ok6 ? orc_grad6(p7) : 0.0;
+                    }
+                    const double *r = F->W[0];
+                    const ptrdiff_t sd = stride[d];
+                    F->psi[d][P] = (idx[d] >= 2 && idx[d] < ext[d] - 2)
+                        ? orc_psi(r[P - 2 * sd], r[P - sd], r[P], r[P + sd], r[P + 2 * sd]) : 1.0;
+                }
+            }
+    return 0;
+}
+
+/* Residual in 3D: Res = -dF/dx - dG/dy - dH/dz.  Q, Res: [5][nz][ny][nx].
+ * sig_d (optional): interface flags, the interface below cell index c along d
+ * at position c of an array one longer along d. */
+long orc3_residual(const orc3_cfg *c, const double *Q, double *Res, uint8_t *sig_x,
+                   uint8_t *sig_y, uint8_t *sig_z)
+{
+    if (!cfg3_ok(c)) return -1;
+    const int nx = c->nx, ny = c->ny, nz = c->nz;
+    const size_t n = (size_t)nx * ny * nz;
+    orc3_fields F;
+    if (fields3_build(c, Q, &F) != 0) { fields3_free(&F); return -1; }
+    const int NX = F.NX, NY = F.NY;
+    const ptrdiff_t stride[3] = {1, NX, (ptrdiff_t)NX * NY};
+    const double dl[3] = {(c->x1 - c->x0) / nx, (c->y1 - c->y0) / ny, (c->z1 - c->z0) / nz};
+    /* cyclic rotation: direction d -> (rho, u_d, u_{d+1}, u_{d+2}, p) */
+    const int perm[3][5] = {{0, 1, 2, 3, 4}, {0, 2, 3, 1, 4}, {0, 3, 1, 2, 4}};
+    uint8_t *sig[3] = {sig_x, sig_y, sig_z};
+    for (size_t s = 0; s < 5 * n; ++s) Res[s] = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const int ext[3] = {nx, ny, nz};
+        int fe[3] = {nx, ny, nz};
+        fe[d] += 1;                           /* interfaces along d */
+        const size_t nf = (size_t)fe[0] * fe[1] * fe[2];
+        double *Fl = (double *)malloc(sizeof(double) * 5 * nf);
+        if (!Fl) { fields3_free(&F); return -1; }
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < fe[2]; ++k)
+            for (int i = 0; i < fe[1]; ++i)
+                for (int j = 0; j < fe[0]; ++j) {
+                    /* interface below cell (j, i, k) along d, i.e. between
+                     * cell index c-1 and c: the cell left of it is c-1 */
+                    int idx[3] = {j, i, k};
+                    idx[d] -= 1;
+                    const size_t P0 = ((size_t)(idx[2] + NG) * NY + (idx[1] + NG)) * NX
+                                    + (idx[0] + NG);
+                    orc3_line L;
+                    for (int m = 0; m < 5; ++m) {
+                        for (int q = -4; q <= 5; ++q)
+                            L.W[m][q + 4] = F.W[perm[d][m]][P0 + q * stride[d]];
+                        for (int q = -2; q <= 3; ++q)
+                            L.G[m][q + 2] = F.G[d][perm[d][m]][P0 + q * stride[d]];
+                    }
+                    for (int q = -2; q <= 3; ++q) L.psi[q + 2] = F.psi[d][P0 + q * stride[d]];
+                    double f[5]; int sg;
+                    line_flux3(&L, c, f, &sg);
+                    const size_t s = ((size_t)k * fe[1] + i) * fe[0] + j;
+                    for (int m = 0; m < 5; ++m) Fl[(size_t)perm[d][m] * nf + s] = f[m];
+                    if (sig[d]) sig[d][s] = (uint8_t)sg;
+                }
+        (void)ext;
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < nz; ++k)
+            for (int i = 0; i < ny; ++i)
+                for (int j = 0; j < nx; ++j) {
+                    int up[3] = {j, i, k};
+                    up[d] += 1;
+                    const size_t sm = ((size_t)k * fe[1] + i) * fe[0] + j;
+                    const size_t sp = ((size_t)up[2] * fe[1] + up[1]) * fe[0] + up[0];
+                    const size_t s = ((size_t)k * ny + i) * nx + j;
+                    for (int m = 0; m < 5; ++m)
+                        Res[m * n + s] -= (Fl[m * nf + sp] - Fl[m * nf + sm]) / dl[d];
+                }
+        free(Fl);
+    }
+    fields3_free(&F);
+    return 0;
+}
+
+/* eq. (rk) in 3D (as orc_rk_stage). */
+long orc3_rk_stage(const orc3_cfg *c, int stage, double dt, const double *Qn, const double *Qk,
+                   double *Qout, uint8_t *sig_x, uint8_t *sig_y, uint8_t *sig_z)
+{
+    if (!cfg3_ok(c) || stage < 1 || stage > 3) return -1;
+    const size_t N = 5 * (size_t)c->nx * c->ny * c->nz;
+    double *R = (double *)malloc(sizeof(double) * N);
+    if (!R) return -1;
+    if (orc3_residual(c, Qk, R, sig_x, sig_y, sig_z) < 0) { free(R); return -1; }
+#pragma omp parallel for schedule(static)
+    for (size_t s = 0; s < N; ++s) {
+        if (stage == 1)
+            Qout[s] = Qn[s] + dt * R[s];
+        else if (stage == 2)
+            Qout[s] = 3.0 / 4.0 * Qn[s] + 1.0 / 4.0 * Qk[s] + 1.0 / 4.0 * dt * R[s];
+        else
+            Qout[s] = 1.0 / 3.0 * Qn[s] + 2.0 / 3.0 * Qk[s] + 2.0 / 3.0 * dt * R[s];
+    }
+    free(R);
+    return 0;
+}
+
+/* Sec. 2.5 time step in 3D (inviscid). */
+double orc3_dt(const orc3_cfg *c, const double *Q, double cfl)
+{
+    if (!cfg3_ok(c)) return -1.0;
+    const size_t n = (size_t)c->nx * c->ny * c->nz;
+    const double dx = (c->x1 - c->x0) / c->nx, dy = (c->y1 - c->y0) / c->ny;
+    const double dz = (c->z1 - c->z0) / c->nz;
+    const double gamma = c->gamma;
+    double conv = INFINITY;
+#pragma omp parallel for schedule(static) reduction(min : conv)
+    for (size_t s = 0; s < n; ++s) {
+        double rho = Q[s], u = Q[n + s] / rho, v = Q[2 * n + s] / rho, w = Q[3 * n + s] / rho;
+        double p = (gamma - 1.0) * (Q[4 * n + s] - rho * (u * u + v * v + w * w) / 2.0);
+        double cs = sqrt(gamma * p / rho);
+        conv = fmin(conv, fmin(dx / (fabs(u) + cs), fmin(dy / (fabs(v) + cs), dz / (fabs(w) + cs))));
+    }
+    return cfl * conv;
+}
+
+double orc3_step(const orc3_cfg *c, double *Q, double cfl)
+{
+    const size_t N = 5 * (size_t)c->nx * c->ny * c->nz;
+    double dt = orc3_dt(c, Q, cfl);
+    double *Q1 = (double *)malloc(sizeof(double) * N);
+    double *Q2 = (double *)malloc(sizeof(double) * N);
+    if (!Q1 || !Q2 || dt <= 0.0) { free(Q1); free(Q2); return -1.0; }
+    orc3_rk_stage(c, 1, dt, Q, Q, Q1, NULL, NULL, NULL);
+    orc3_rk_stage(c, 2, dt, Q, Q1, Q2, NULL, NULL, NULL);
+    orc3_rk_stage(c, 3, dt, Q, Q2, Q1, NULL, NULL, NULL);
+    memcpy(Q, Q1, sizeof(double) * N);
+    free(Q1); free(Q2);
+    return dt;
+}

@@ -50,6 +50,16 @@ def side(kind, state=None, kind1=None, state1=None, split0=math.inf, split_speed
     return S
 
 
+class Orc3Cfg(C.Structure):
+    """3D Euler configuration (inviscid)."""
+    _fields_ = [
+        ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+        ("z0", C.c_double), ("z1", C.c_double),
+        ("bc", C.c_int * 3), ("gamma", C.c_double), ("order", C.c_int),
+    ]
+
+
 class OrcCState(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("ub", "vb", "hb", "cb", "b1", "b2")]
 
@@ -75,6 +85,16 @@ def lib():
         L.orc_dt.argtypes = [C.POINTER(OrcCfg), dp, C.c_double]
         L.orc_step.restype = C.c_double
         L.orc_step.argtypes = [C.POINTER(OrcCfg), dp, C.c_double]
+        L.orc3_residual.restype = C.c_long
+        L.orc3_residual.argtypes = [C.POINTER(Orc3Cfg), dp, dp, C.c_void_p, C.c_void_p,
+                                    C.c_void_p]
+        L.orc3_rk_stage.restype = C.c_long
+        L.orc3_rk_stage.argtypes = [C.POINTER(Orc3Cfg), C.c_int, C.c_double, dp, dp, dp,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc3_dt.restype = C.c_double
+        L.orc3_dt.argtypes = [C.POINTER(Orc3Cfg), dp, C.c_double]
+        L.orc3_step.restype = C.c_double
+        L.orc3_step.argtypes = [C.POINTER(Orc3Cfg), dp, C.c_double]
         L.orc_detector_eps.restype = C.c_double
         L.orc_detector_eps.argtypes = []
         L.orc_psi.restype = C.c_double
@@ -299,3 +319,46 @@ def char_cons(Qa, Qb, gamma=1.4):
         lib().orc_char_cons_bwd(C.byref(st), e, out)
         Rm[:, k] = out
     return Lm, Rm
+
+
+# ---------------------------------------------------------------- 3D ---
+def make_cfg3(nx, ny, nz, x0=0.0, x1=1.0, y0=0.0, y1=1.0, z0=0.0, z1=1.0,
+              bc=(BC_PERIODIC, BC_PERIODIC, BC_PERIODIC), gamma=1.4, order=7):
+    cfg = Orc3Cfg(nx, ny, nz, x0, x1, y0, y1, z0, z1)
+    for d in range(3):
+        cfg.bc[d] = bc[d]
+    cfg.gamma, cfg.order = gamma, order
+    return cfg
+
+
+def residual3(cfg, Q, want_flags=False):
+    """3D Euler residual; Q [5][nz][ny][nx] = (rho, rho u, rho v, rho w, E).
+    With want_flags: also the interface flags along x [nz][ny][nx+1], along y
+    [nz][ny+1][nx] and along z [nz+1][ny][nx]."""
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    R = np.empty_like(Q)
+    nx, ny, nz = cfg.nx, cfg.ny, cfg.nz
+    sig = [np.zeros((nz, ny, nx + 1), np.uint8), np.zeros((nz, ny + 1, nx), np.uint8),
+           np.zeros((nz + 1, ny, nx), np.uint8)] if want_flags else [None] * 3
+    if lib().orc3_residual(C.byref(cfg), Q, R, *[_ptr(x) for x in sig]) < 0:
+        raise ValueError("oracle 3D residual: bad arguments")
+    return (R, *sig) if want_flags else R
+
+
+def rk_stage3(cfg, stage, dt, Qn, Qk):
+    Qn = np.ascontiguousarray(Qn, dtype=np.float64)
+    Qk = np.ascontiguousarray(Qk, dtype=np.float64)
+    out = np.empty_like(Qn)
+    if lib().orc3_rk_stage(C.byref(cfg), stage, dt, Qn, Qk, out, None, None, None) < 0:
+        raise ValueError("oracle 3D rk stage: bad arguments")
+    return out
+
+
+def dt3(cfg, Q, cfl):
+    return lib().orc3_dt(C.byref(cfg), np.ascontiguousarray(Q, dtype=np.float64), cfl)
+
+
+def step3(cfg, Q, cfl):
+    """One SSP-RK3 step in place; returns dt."""
+    assert Q.flags.c_contiguous and Q.dtype == np.float64
+    return lib().orc3_step(C.byref(cfg), Q, cfl)

@@ -357,3 +357,88 @@ def hard_batches(labels, near, batch, nbatches, seed, frac_near=0.25):
             parts.append(src[rng.integers(0, len(src), size)])
         out[b] = rng.permutation(np.concatenate(parts))
     return out
+
+
+# -------------------------------------------------------------------- 3D ---
+@dataclass
+class Problem3:
+    """A 3D Euler problem: Q[5][nz][ny][nx] = (rho, rho u, rho v, rho w, E),
+    x fastest, E = p/(gamma-1) + rho (u^2+v^2+w^2)/2."""
+    family: str
+    nx: int
+    ny: int
+    nz: int
+    lo: tuple
+    hi: tuple
+    bc: tuple
+    gamma: float
+    cfl: float
+    seed: int = 0
+    Q: np.ndarray = field(default=None, repr=False)
+    t_final: float = None
+
+    def geometry(self):
+        return (self.lo[0], self.hi[0], self.lo[1], self.hi[1], self.lo[2], self.hi[2])
+
+
+def cell_centres3(n, lo, hi):
+    ax = [lo[d] + (np.arange(n[d]) + 0.5) * (hi[d] - lo[d]) / n[d] for d in range(3)]
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return X, Y, Z
+
+
+def prim_to_state3(rho, u, v, w, p, gamma=GAMMA):
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    return np.ascontiguousarray(np.stack([rho, rho * u, rho * v, rho * w, E]), dtype=np.float64)
+
+
+def taylor_green3d(n, cfl=0.2, p0=100.0):
+    """The paper's inviscid Taylor-Green vortex on [0, 2 pi)^3, periodic:
+    rho = 1, u = sin x cos y cos z, v = -cos x sin y cos z, w = 0,
+    p = p0 + ((cos 2z + 2)(cos 2x + cos 2y) - 2)/16; run to t = 10."""
+    L = 2.0 * math.pi
+    X, Y, Z = cell_centres3((n, n, n), (0.0, 0.0, 0.0), (L, L, L))
+    rho = np.ones_like(X)
+    u = np.sin(X) * np.cos(Y) * np.cos(Z)
+    v = -np.cos(X) * np.sin(Y) * np.cos(Z)
+    w = np.zeros_like(X)
+    p = p0 + ((np.cos(2.0 * Z) + 2.0) * (np.cos(2.0 * X) + np.cos(2.0 * Y)) - 2.0) / 16.0
+    P = Problem3("taylor_green3d", n, n, n, (0.0, 0.0, 0.0), (L, L, L),
+                 (BC_PERIODIC,) * 3, GAMMA, cfl)
+    P.Q = prim_to_state3(rho, u, v, w, p)
+    P.t_final = 10.0
+    return P
+
+
+def advected_wave3d(n, amp=0.2):
+    """rho = 1 + amp sin(x + y + z), u = v = w = 1, p = 1 on [0, 2 pi)^3,
+    periodic: an exact solution translating along (1, 1, 1), so
+    dQ/dt = -(d/dx + d/dy + d/dz) Q exactly."""
+    L = 2.0 * math.pi
+    X, Y, Z = cell_centres3((n, n, n), (0.0, 0.0, 0.0), (L, L, L))
+    rho = 1.0 + amp * np.sin(X + Y + Z)
+    one = np.ones_like(X)
+    P = Problem3("advected_wave3d", n, n, n, (0.0, 0.0, 0.0), (L, L, L),
+                 (BC_PERIODIC,) * 3, GAMMA, 0.5)
+    P.Q = prim_to_state3(rho, one, one, one, one)
+    return P
+
+
+def riemann3d(n, seed=0, ny=None, nz=None, cfl=0.2, split=(0.6, 0.55, 0.5)):
+    """Eight-octant Riemann problem on [0,1]^3, transmissive: octant states
+    (bit 0: x > split x, bit 1: y > split y, bit 2: z > split z) draw
+    rho~U[0.1,1.5], u, v, w~U[-0.8,0.8], p~U[0.03,1.5] in that order from
+    numpy.random.default_rng(seed), octant after octant."""
+    ny = n if ny is None else ny
+    nz = n if nz is None else nz
+    X, Y, Z = cell_centres3((n, ny, nz), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    rng = np.random.default_rng(seed)
+    st = np.array([[rng.uniform(0.1, 1.5), rng.uniform(-0.8, 0.8), rng.uniform(-0.8, 0.8),
+                    rng.uniform(-0.8, 0.8), rng.uniform(0.03, 1.5)] for _ in range(8)])
+    octant = ((X > split[0]).astype(int) + 2 * (Y > split[1]).astype(int)
+              + 4 * (Z > split[2]).astype(int))
+    rho, u, v, w, p = (st[octant, k] for k in range(5))
+    P = Problem3("riemann3d", n, ny, nz, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0),
+                 (BC_TRANSMISSIVE,) * 3, GAMMA, cfl, seed)
+    P.Q = prim_to_state3(rho, u, v, w, p)
+    return P
