@@ -34,6 +34,13 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 # write Q^(k+1) (32 B), and Q^n (32 B) in stages 2 and 3; 256/3 B on average.
 BYTES_PER_CELL_STAGE = {1: 64.0, 2: 96.0, 3: 96.0}
 
+# 3D (40 B per cell state): the x sweep reads Q^(k) and writes the residual
+# accumulator (80 B), the y sweep reads Q^(k) and the accumulator and writes it
+# (120 B), the z sweep reads Q^(k) and the accumulator, writes the result and
+# reads Q^n (stage 1) or Q^n and Q^(k) (stages 2, 3) for the update:
+# 120 + (40 + 80 + 80)/3 B.  Per cell-stage on average:
+BYTES_PER_CELL_STAGE_3D = 80.0 + 120.0 + 120.0 + 200.0 / 3.0
+
 WORKLOADS = {
     # name: (family, n, seed, steps, description)
     "riemann1024": ("riemann", 1024, 0, 200,
@@ -58,6 +65,10 @@ WORKLOADS = {
                            "Viscous shock tube 1280x640 on [0,1]x[0,0.5], Re 1000, Pr 0.73, "
                            "adiabatic no-slip walls and a symmetry plane, run from t = 0 to t = 1, "
                            "CFL 0.2"),
+    "taylor_green3d": ("taylor_green3d", 64, 0, None,
+                       "Inviscid Taylor-Green vortex 64^3 on [0, 2 pi)^3 (the paper's 3D case), "
+                       "periodic, CFL 0.2, run from t = 0 to t = 10; kinetic energy and enstrophy "
+                       "at t = 1..10"),
     "batch512": ("batch", 0, 0, 10,
                  "512 independent grids, side n ~ U{64..768} (seed 0), families uniform over "
                  "vortex / Riemann / shear layer, per-grid seed 10000 + index; one launch per "
@@ -287,6 +298,148 @@ def batch_problems():
     return out
 
 
+def tg_diagnostics(Q, dx):
+    """Kinetic energy <rho |u|^2 / 2> and enstrophy <rho |curl u|^2 / 2> of a
+    periodic 3D state (host numpy; curl by second-order central differences)."""
+    import numpy as np
+    r = Q[0]
+    u, v, w = Q[1] / r, Q[2] / r, Q[3] / r
+    d = lambda f, ax: (np.roll(f, -1, axis=ax) - np.roll(f, 1, axis=ax)) / (2.0 * dx)
+    # array axes (z, y, x) = (0, 1, 2)
+    wx = d(w, 1) - d(v, 0)
+    wy = d(u, 0) - d(w, 2)
+    wz = d(v, 2) - d(u, 1)
+    ke = float((0.5 * r * (u * u + v * v + w * w)).mean())
+    ens = float((0.5 * r * (wx * wx + wy * wy + wz * wz)).mean())
+    return ke, ens
+
+
+def bench_3d(a, n):
+    """The paper's 3D case: inviscid Taylor-Green vortex, 64^3, t = 0..10, at
+    the requested GRB order with the other order run beside it: whole-run time,
+    throughput, the sweep kernels' roofline, and the kinetic energy and
+    enstrophy histories (the paper's comparison of fourth- and seventh-order
+    GRB)."""
+    import numpy as np
+    import torch
+    from paper_2305_00762_amd import gbr
+    from paper_2305_00762_amd import problems as PB
+    from paper_2305_00762_amd.solver import Solver3
+    torch.cuda.set_device(0)
+    s = torch.cuda.Stream()
+    P = PB.taylor_green3d(n)
+    cells = P.nx * P.ny * P.nz
+    dx = 2.0 * np.pi / n
+    head_order = 4 if a.path == "fp64_g4" else 7
+    calibration_copy(a.calib_copy_mb)
+
+    def history(order):
+        """Steps to t = 10 with diagnostics at t = 1..10 (device time summed on
+        the stream, read after batches that shrink near each target)."""
+        with torch.cuda.stream(s):
+            S = Solver3(P, stream=s, order=order)
+            tacc = torch.zeros(1, dtype=torch.float64, device="cuda")
+        k0 = tg_diagnostics(P.Q, dx)
+        hist, steps, batch = [], 0, 50
+        for target in range(1, 11):
+            while True:
+                with torch.cuda.stream(s):
+                    for _ in range(batch):
+                        S.step()
+                        tacc.add_(S.dt)
+                steps += batch
+                s.synchronize()
+                t = float(tacc.item())
+                if t >= target:
+                    break
+                batch = max(1, min(50, int((target - t) / float(S.dt.item()))))
+            ke, ens = tg_diagnostics(S.state(), dx)
+            hist.append({"t": t, "ke_ratio": ke / k0[0], "enstrophy_ratio": ens / k0[1]})
+            batch = 50
+        status = gbr.strerror(S.check())
+        S.close()
+        return hist, steps, status
+
+    def timed(order, steps):
+        with torch.cuda.stream(s):
+            S = Solver3(P, stream=s, order=order)
+            for _ in range(a.warmup):
+                S.step()
+        s.synchronize()
+        S.Q.copy_(torch.from_numpy(P.Q))
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(s):
+            start.record(s)
+            for _ in range(steps):
+                S.step()
+            stop.record(s)
+        s.synchronize()
+        ms = start.elapsed_time(stop)
+        # kernel pass: 200 steps with events around every stage's three sweeps
+        gbr.gbr3_timing(S.ctx, True)
+        with torch.cuda.stream(s):
+            for _ in range(200):
+                S.step()
+        sweep_ms, calls = gbr.gbr3_timing_read(S.ctx)
+        gbr.gbr3_timing(S.ctx, False)
+        st = gbr.strerror(S.check())
+        S.close()
+        return ms, sweep_ms / max(calls, 1), st
+
+    out_orders = {}
+    for order in ([head_order] + ([11 - head_order] if not a.no_compare else [])):
+        hist, steps, st = history(order)
+        ms, stage_ms, st2 = timed(order, steps)
+        out_orders[order] = {"steps_to_t10": steps, "time_to_solution_s": ms * 1e-3,
+                             "value": cells * 3 * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+                             "stage_us": stage_ms * 1e3, "history": hist,
+                             "status": st if st == st2 else f"{st}/{st2}"}
+    h = out_orders[head_order]
+    achieved = BYTES_PER_CELL_STAGE_3D * cells / (h["stage_us"] * 1e-6) / 1e9
+    out = {
+        "metric": METRIC, "value": h["value"], "unit": "cell-stage updates/s", "n_gpus": 1,
+        "steps": h["steps_to_t10"], "warmup": a.warmup, "ms_per_step": h["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "taylor_green3d", "description": WORKLOADS["taylor_green3d"][4],
+                   "nx": n, "ny": n, "nz": n, "order": head_order,
+                   "step": "device dt + 3 x (x, y, z line-sweep kernels)"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "meg7_sweep3_kernel (x, y, z per stage)",
+                     "avg_launch_us": h["stage_us"],
+                     "bytes_per_cell_stage": BYTES_PER_CELL_STAGE_3D},
+        "time_to_solution_s": h["time_to_solution_s"],
+        "status": h["status"],
+        "orders": {str(k): v for k, v in out_orders.items()},
+    }
+    if not a.no_cpu_baseline:
+        import oracle as O
+        cfg = O.make_cfg3(n, n, n, *P.geometry(), bc=P.bc, gamma=P.gamma, order=head_order)
+        Q = np.ascontiguousarray(P.Q.copy())
+        t0, k = time.perf_counter(), 0
+        while time.perf_counter() - t0 < a.cpu_seconds and k < 50:
+            O.step3(cfg, Q, P.cfl)
+            k += 1
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": cells * 3 * k / el, "unit": "cell-stage updates/s",
+                               "cores": O.threads(), "kind": "oracle",
+                               "sample": f"{k} whole SSP-RK3 steps of the same workload from its "
+                                         f"initial state ({cells * 3 * k} cell-stages) in {el:.1f} s"}
+        with torch.cuda.stream(s):
+            S = Solver3(P, stream=s, order=head_order)
+            for _ in range(k):
+                S.step()
+        G = S.state()
+        S.close()
+        d = np.abs(G - Q).reshape(5, -1)
+        out["error_vs_oracle"] = {"after_steps": k, "L1": d.mean(1).tolist(),
+                                  "Linf": d.max(1).tolist(),
+                                  "vars": ["rho", "rho_u", "rho_v", "rho_w", "E"]}
+    print(json.dumps(out), flush=True)
+
+
 def bench_batch(a, steps):
     """The batched workload: FP32 bulk + FP64 state (plain detector), every
     stage of all 512 grids in one launch, steps replayed as a HIP graph."""
@@ -399,6 +552,8 @@ def main():
     steps = a.steps if a.steps is not None else wsteps
     if fam == "batch":
         return bench_batch(a, steps)
+    if fam == "taylor_green3d":
+        return bench_3d(a, n)
     P = PB.make(fam, n, seed=seed) if fam != "vortex" else PB.vortex(n, cfl=0.5)
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()

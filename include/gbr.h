@@ -338,6 +338,62 @@ int gbr_batch_timing_read(gbr_batch *b, double *stage_ms, uint64_t *launches);
 int gbr_batch_get_dt(gbr_batch *b, double *dt, void *stream);
 int gbr_batch_check(gbr_batch *b, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Three dimensions: the inviscid 3D extension the paper tests with the
+ * Taylor-Green vortex (Sec. 3, comparison of fourth- and seventh-order GRB).
+ * The scheme is applied dimension by dimension: per direction, the rotated
+ * primitives (rho, u_n, u_t1, u_t2, p) with the tangential components taken
+ * cyclically (x: v, w; y: w, u; z: u, v), the same detector, GRB states, flux
+ * reconstruction, characteristic MP limiting (plus an identity row for the
+ * second tangential velocity) and HLLC as in 2D.  State Q: device FP64
+ * [5][nz][ny][nx] = (rho, rho u, rho v, rho w, E), x fastest, caller-owned.
+ * Each residual or stage call runs three line-sweep kernels (x, y, z) that
+ * accumulate into context scratch; the z sweep stores the residual or the
+ * stage.  Errors as for the 2D entry points.
+ * ------------------------------------------------------------------------- */
+typedef struct gbr3_ctx gbr3_ctx;
+
+/* Context for an nx x ny x nz grid (each >= 12), ratio of specific heats
+ * gamma > 1; default domain [0,1]^3, periodic, order 7.  Allocates the 5n
+ * FP64 residual accumulator and the time-step scratch on the current device. */
+int gbr3_init(int nx, int ny, int nz, double gamma, gbr3_ctx **out);
+int gbr3_destroy(gbr3_ctx *ctx);
+
+/* Domain and boundary type per axis (GBR_BC_PERIODIC or GBR_BC_TRANSMISSIVE). */
+int gbr3_set_geometry(gbr3_ctx *ctx, double x0, double x1, double y0, double y1, double z0,
+                      double z1, int bc_x, int bc_y, int bc_z);
+
+/* GRB order 7 (default) or 4 (the subset alpha = 4, beta = 0, eq. fourth). */
+int gbr3_set_order(gbr3_ctx *ctx, int order);
+
+/* Res = Res(Q) (eqs. eqn-differencing_residual, deriv in 3D).  Q and Res must
+ * not overlap. */
+int gbr3_residual(gbr3_ctx *ctx, const double *Q, double *Res, void *stream);
+
+/* SSP-RK3 stage (eq. rk), as gbr_rk_stage. */
+int gbr3_rk_stage(gbr3_ctx *ctx, int stage, const double *dt_dev, const double *Qn,
+                  const double *Qk, double *Qout, void *stream);
+
+/* dt = cfl min(dx/(|u|+c), dy/(|v|+c), dz/(|w|+c)) over the grid (Sec. 2.5,
+ * inviscid), to a device scalar; deterministic. */
+int gbr3_compute_dt(gbr3_ctx *ctx, const double *Q, double cfl, double *dt_dev, void *stream);
+
+/* Interface flags of the last residual or stage (after gbr3_export_flags(ctx,
+ * 1)): host arrays [nz][ny][nx+1], [nz][ny+1][nx], [nz+1][ny][nx]; any may be
+ * NULL.  Synchronous. */
+int gbr3_export_flags(gbr3_ctx *ctx, int enable);
+int gbr3_get_flags(gbr3_ctx *ctx, uint8_t *sig_x, uint8_t *sig_y, uint8_t *sig_z,
+                   void *stream);
+
+/* Status (non-finite or non-positive rho or p seen), as gbr_check. */
+int gbr3_check(gbr3_ctx *ctx, void *stream);
+
+/* Timing of residual and stage calls: two HIP events per call on the caller's
+ * stream; gbr3_timing_read returns the summed milliseconds of the three sweep
+ * kernels and the number of calls, and resets. */
+int gbr3_timing(gbr3_ctx *ctx, int enable);
+int gbr3_timing_read(gbr3_ctx *ctx, double *sweeps_ms, uint64_t *calls);
+
 #ifdef __cplusplus
 }
 #endif

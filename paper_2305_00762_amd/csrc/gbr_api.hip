@@ -11,6 +11,7 @@
 #include "batch_kernel.hpp"
 #include "dt_kernel.hpp"
 #include "mlp_kernels.hpp"
+#include "stage3d.hpp"
 #include "stage_f32.hpp"
 #include "stage_kernel.hpp"
 
@@ -1079,3 +1080,222 @@ int gbr_batch_autotune(gbr_batch* b, int reps, void* stream) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Three dimensions (inviscid): one line-sweep kernel per direction and stage.
+namespace {
+constexpr int k3NP = 32, k3NL = 8;   // positions per tile along the line, lines per workgroup
+using Sweep3Fn = void (*)(const Sweep3Params&, int, hipStream_t);
+template <int DIR, int ORD>
+void launch_sweep3(const Sweep3Params& P, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((meg7_sweep3_kernel<DIR, k3NP, k3NL, ORD>), dim3(grid), dim3(256), 0, s, P);
+}
+const Sweep3Fn kSweep3[2][3] = {
+    {launch_sweep3<0, 7>, launch_sweep3<1, 7>, launch_sweep3<2, 7>},
+    {launch_sweep3<0, 4>, launch_sweep3<1, 4>, launch_sweep3<2, 4>}};
+}  // namespace
+
+struct gbr3_ctx {
+  int n[3];
+  double gamma;
+  double lo[3], hi[3];
+  int bc[3];
+  int order;
+  int device;
+  int export_flags;
+  unsigned* d_status;         // [4]
+  double* d_partial;          // [2][kDtBlocks]
+  double* d_R;                // [5][nz][ny][nx] residual accumulator
+  uint8_t* d_sig[3];          // optional interface flags per direction
+  int timing;
+  std::vector<hipEvent_t> ev; // two per residual or stage call
+  size_t ev_used;
+};
+
+int gbr3_init(int nx, int ny, int nz, double gamma, gbr3_ctx** out) {
+  if (!out) return GBR_EINVAL;
+  *out = nullptr;
+  if (nx < 12 || ny < 12 || nz < 12 || !(gamma > 1.0)) return GBR_EINVAL;
+  if ((long long)nx * ny * nz > (1ll << 31) / 5) return GBR_EINVAL;
+  gbr3_ctx* c = new (std::nothrow) gbr3_ctx();
+  if (!c) return GBR_ENOMEM;
+  c->n[0] = nx; c->n[1] = ny; c->n[2] = nz; c->gamma = gamma;
+  for (int d = 0; d < 3; ++d) { c->lo[d] = 0.0; c->hi[d] = 1.0; c->bc[d] = GBR_BC_PERIODIC; }
+  c->order = 7;
+  const size_t n = (size_t)nx * ny * nz;
+  bool ok = hipGetDevice(&c->device) == hipSuccess &&
+            hipMalloc(&c->d_status, 4 * sizeof(unsigned)) == hipSuccess &&
+            hipMalloc(&c->d_partial, 2 * kDtBlocks * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->d_R, 5 * n * sizeof(double)) == hipSuccess &&
+            hipMemset(c->d_status, 0, 4 * sizeof(unsigned)) == hipSuccess &&
+            hipDeviceSynchronize() == hipSuccess;
+  if (!ok) {
+    (void)hipFree(c->d_status); (void)hipFree(c->d_partial); (void)hipFree(c->d_R);
+    delete c;
+    return GBR_ENOMEM;
+  }
+  *out = c;
+  return GBR_OK;
+}
+
+int gbr3_destroy(gbr3_ctx* c) {
+  if (!c) return GBR_OK;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(c->d_status);
+  (void)hipFree(c->d_partial);
+  (void)hipFree(c->d_R);
+  for (int d = 0; d < 3; ++d)
+    if (c->d_sig[d]) (void)hipFree(c->d_sig[d]);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+  return GBR_OK;
+}
+
+int gbr3_set_geometry(gbr3_ctx* c, double x0, double x1, double y0, double y1, double z0,
+                      double z1, int bc_x, int bc_y, int bc_z) {
+  if (!c || !(x1 > x0) || !(y1 > y0) || !(z1 > z0)) return GBR_EINVAL;
+  const int bc[3] = {bc_x, bc_y, bc_z};
+  for (int d = 0; d < 3; ++d)
+    if (bc[d] != GBR_BC_PERIODIC && bc[d] != GBR_BC_TRANSMISSIVE) return GBR_EINVAL;
+  c->lo[0] = x0; c->hi[0] = x1; c->lo[1] = y0; c->hi[1] = y1; c->lo[2] = z0; c->hi[2] = z1;
+  for (int d = 0; d < 3; ++d) c->bc[d] = bc[d];
+  return GBR_OK;
+}
+
+int gbr3_set_order(gbr3_ctx* c, int order) {
+  if (!c || (order != 7 && order != 4)) return GBR_EINVAL;
+  c->order = order;
+  return GBR_OK;
+}
+
+int gbr3_export_flags(gbr3_ctx* c, int enable) {
+  if (!c) return GBR_EINVAL;
+  if (enable) {
+    for (int d = 0; d < 3; ++d) {
+      if (c->d_sig[d]) continue;
+      size_t m = 1;
+      for (int e = 0; e < 3; ++e) m *= (size_t)c->n[e] + (e == d ? 1 : 0);
+      if (hipMalloc(&c->d_sig[d], m) != hipSuccess) return GBR_ENOMEM;
+    }
+  }
+  c->export_flags = enable ? 1 : 0;
+  return GBR_OK;
+}
+
+int gbr3_get_flags(gbr3_ctx* c, uint8_t* sig_x, uint8_t* sig_y, uint8_t* sig_z, void* stream) {
+  if (!c || !c->d_sig[0]) return GBR_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* dst[3] = {sig_x, sig_y, sig_z};
+  for (int d = 0; d < 3; ++d) {
+    if (!dst[d]) continue;
+    size_t m = 1;
+    for (int e = 0; e < 3; ++e) m *= (size_t)c->n[e] + (e == d ? 1 : 0);
+    if (hipMemcpyAsync(dst[d], c->d_sig[d], m, hipMemcpyDefault, s) != hipSuccess)
+      return GBR_EDEVICE;
+  }
+  return hip_ok(hipStreamSynchronize(s));
+}
+
+int gbr3_check(gbr3_ctx* c, void* stream) {
+  if (!c) return GBR_EINVAL;
+  unsigned h[4] = {0, 0, 0, 0};
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return GBR_EDEVICE;
+  if (hipMemcpy(h, c->d_status, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+    return GBR_EDEVICE;
+  if (hipMemset(c->d_status, 0, sizeof(h)) != hipSuccess) return GBR_EDEVICE;
+  if (hipDeviceSynchronize() != hipSuccess) return GBR_EDEVICE;
+  return (h[0] | h[1] | h[2] | h[3]) ? GBR_ESTATE : GBR_OK;
+}
+
+static int launch3(gbr3_ctx* c, int mode, const double* dt, const double* Qn, const double* Qk,
+                   double* out, hipStream_t s) {
+  hipEvent_t* tev = nullptr;
+  if (c->timing) {
+    if (c->ev_used + 2 > c->ev.size()) {
+      for (int k = 0; k < 2 * 64; ++k) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return GBR_EDEVICE;
+        c->ev.push_back(e);
+      }
+    }
+    tev = &c->ev[c->ev_used];
+    c->ev_used += 2;
+    if (hipEventRecord(tev[0], s) != hipSuccess) return GBR_EDEVICE;
+  }
+  for (int d = 0; d < 3; ++d) {
+    Sweep3Params P{};
+    P.Qk = Qk; P.Qn = Qn; P.R = c->d_R; P.out = out; P.dt = dt;
+    P.sig = c->export_flags ? c->d_sig[d] : nullptr;
+    P.status = c->d_status;
+    P.nx = c->n[0]; P.ny = c->n[1]; P.nz = c->n[2];
+    P.bc = c->bc[d];
+    P.inv_d = (double)c->n[d] / (c->hi[d] - c->lo[d]);
+    P.gamma = c->gamma; P.g1inv = 1.0 / (c->gamma - 1.0);
+    P.first = d == 0; P.last = d == 2;
+    P.mode = mode;
+    P.ptiles = (c->n[d] + k3NP - 1) / k3NP;
+    const long long lines = (long long)c->n[(d + 1) % 3] * c->n[(d + 2) % 3];
+    const long long groups = (lines + k3NL - 1) / k3NL;
+    const long long grid = groups * P.ptiles;
+    if (grid > 0x7fffffff) return GBR_EINVAL;
+    kSweep3[c->order == 4 ? 1 : 0][d](P, (int)grid, s);
+  }
+  if (tev && hipEventRecord(tev[1], s) != hipSuccess) return GBR_EDEVICE;
+  return hip_ok(hipGetLastError());
+}
+
+int gbr3_residual(gbr3_ctx* c, const double* Q, double* Res, void* stream) {
+  if (!c || !Q || !Res || Q == Res) return GBR_EINVAL;
+  return launch3(c, MODE_RESIDUAL, nullptr, Q, Q, Res, (hipStream_t)stream);
+}
+
+int gbr3_rk_stage(gbr3_ctx* c, int stage, const double* dt_dev, const double* Qn,
+                  const double* Qk, double* Qout, void* stream) {
+  if (!c || !dt_dev || !Qn || !Qk || !Qout) return GBR_EINVAL;
+  if (stage < 1 || stage > 3) return GBR_EINVAL;
+  if (Qout == Qn || Qout == Qk) return GBR_EINVAL;
+  if (stage == 1 && Qk != Qn) return GBR_EINVAL;
+  return launch3(c, stage, dt_dev, Qn, Qk, Qout, (hipStream_t)stream);
+}
+
+int gbr3_compute_dt(gbr3_ctx* c, const double* Q, double cfl, double* dt_dev, void* stream) {
+  if (!c || !Q || !dt_dev || !(cfl > 0.0)) return GBR_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  Dt3Params P{};
+  P.Q = Q; P.partial = c->d_partial; P.status = c->d_status;
+  P.nx = c->n[0]; P.ny = c->n[1]; P.nz = c->n[2];
+  P.dx = (c->hi[0] - c->lo[0]) / c->n[0];
+  P.dy = (c->hi[1] - c->lo[1]) / c->n[1];
+  P.dz = (c->hi[2] - c->lo[2]) / c->n[2];
+  P.gamma = c->gamma;
+  const size_t n = (size_t)c->n[0] * c->n[1] * c->n[2];
+  size_t want = (n + kDtThreads - 1) / kDtThreads;
+  const int blocks = (int)(want < (size_t)kDtBlocks ? want : (size_t)kDtBlocks);
+  hipLaunchKernelGGL(dt3_reduce_kernel, dim3(blocks), dim3(kDtThreads), 0, s, P);
+  hipLaunchKernelGGL(dt_finish_kernel, dim3(1), dim3(kDtThreads), 0, s, c->d_partial, blocks,
+                     dt_dev, cfl, c->d_status);
+  return hip_ok(hipGetLastError());
+}
+
+int gbr3_timing(gbr3_ctx* c, int enable) {
+  if (!c) return GBR_EINVAL;
+  c->timing = enable ? 1 : 0;
+  c->ev_used = 0;
+  return GBR_OK;
+}
+
+int gbr3_timing_read(gbr3_ctx* c, double* sweeps_ms, uint64_t* calls) {
+  if (!c) return GBR_EINVAL;
+  double t = 0.0;
+  for (size_t k = 0; k + 2 <= c->ev_used; k += 2) {
+    float a = 0.f;
+    if (hipEventSynchronize(c->ev[k + 1]) != hipSuccess ||
+        hipEventElapsedTime(&a, c->ev[k], c->ev[k + 1]) != hipSuccess)
+      return GBR_EDEVICE;
+    t += a;
+  }
+  if (sweeps_ms) *sweeps_ms = t;
+  if (calls) *calls = c->ev_used / 2;
+  c->ev_used = 0;
+  return GBR_OK;
+}

@@ -1,0 +1,405 @@
+// MEG7 in three dimensions (the Euler equations, inviscid) for gfx950.
+//
+// The method is applied dimension by dimension, so each direction is one
+// kernel over lines along that direction.  A workgroup owns NL lines x NP
+// positions plus a 6-cell halo along the line (periodic wrap or transmissive
+// clamp), stages the primitives in a frame rotated to the line,
+// (rho, u_n, u_t1, u_t2, p) with the tangential components taken cyclically
+// (x: v, w; y: w, u; z: u, v), and runs the passes of the 2D sweep:
+//   pass 1: cell fluxes, sixth-order gradients (eq. eqn:six), the density
+//           detector (Sec. 2.4);
+//   pass 2: per interface, sigma from the 6-cell buffer; smooth interfaces take
+//           the GRB states, the flux reconstruction and HLLC; flagged ones are
+//           compacted into an LDS queue by a wavefront ballot;
+//   pass 3: the queue: characteristic MEG7 states (Sec. 2.3), F(Q), HLLC;
+//   pass 4: flux differences into the residual accumulator.
+// The x sweep writes R = -dF/dx, the y sweep subtracts dG/dy, the z sweep
+// subtracts dH/dz and stores the residual or the SSP-RK3 stage (eq. rk).
+#pragma once
+#include "meg7_device.hpp"
+#include "stage_kernel.hpp"
+
+namespace gbr {
+
+struct Sweep3Params {
+  const double* __restrict__ Qk;  // state the residual is evaluated on [5][nz][ny][nx]
+  const double* __restrict__ Qn;  // Q^n (stages 2, 3)
+  double* R;                      // residual accumulator [5][nz][ny][nx]
+  double* out;                    // residual or Q^(k+1) (last sweep)
+  const double* __restrict__ dt;  // device scalar (stages)
+  uint8_t* sig;                   // optional interface flags of this direction
+  unsigned* status;
+  int nx, ny, nz;
+  int bc;                         // boundary kind along this direction
+  double inv_d;                   // 1 / spacing along this direction
+  double gamma, g1inv;
+  int first, last;                // first sweep writes R; the last one stores
+  int mode;                       // MODE_RESIDUAL or MODE_STAGE1..3
+  int ptiles;                     // position tiles along the direction
+};
+
+// Normal convective flux of W = (rho, u_n, u_t1, u_t2, p).
+__device__ __forceinline__ void conv_flux3(const double W[5], double g1inv, double F[5]) {
+  const double E = W[4] * g1inv + 0.5 * W[0] * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]);
+  const double m = W[0] * W[1];
+  F[0] = m;
+  F[1] = m * W[1] + W[4];
+  F[2] = m * W[2];
+  F[3] = m * W[3];
+  F[4] = W[1] * (E + W[4]);
+}
+
+// HLLC with Einfeldt (Roe-average) bounds in the wave-sum form, both
+// tangential momenta carried by the star states (as the 2D hllc).
+__device__ __forceinline__ void hllc3(const double WL[5], const double WR[5], const double Fm[5],
+                                      double gamma, double g1inv, double F[5]) {
+  const double rl = WL[0], ul = WL[1], vl = WL[2], wl = WL[3], pl = WL[4];
+  const double rr = WR[0], ur = WR[1], vr = WR[2], wr = WR[3], pr = WR[4];
+  const double yl = rsq_nr(rl), yr = rsq_nr(rr);
+  const double sl = rl * yl, sr = rr * yr;
+  const double irl = yl * yl, irr = yr * yr;
+  const double El = pl * g1inv + 0.5 * rl * (ul * ul + vl * vl + wl * wl);
+  const double Er = pr * g1inv + 0.5 * rr * (ur * ur + vr * vr + wr * wr);
+  const double cl = sqrt_nr(gamma * pl * irl), cr = sqrt_nr(gamma * pr * irr);
+  const double hl = (El + pl) * irl, hr = (Er + pr) * irr;
+  const double iss = rcp_nr(sl + sr);
+  const double ut = (sl * ul + sr * ur) * iss;
+  const double vt = (sl * vl + sr * vr) * iss;
+  const double wt = (sl * wl + sr * wr) * iss;
+  const double ht = (sl * hl + sr * hr) * iss;
+  const double ct = sqrt_nr((gamma - 1.0) * (ht - 0.5 * (ut * ut + vt * vt + wt * wt)));
+  const double SL = fmin(ul - cl, ut - ct);
+  const double SR = fmax(ur + cr, ut + ct);
+  const double ml = rl * (SL - ul), mr = rr * (SR - ur);
+  const double Ss = (pr - pl + ml * ul - mr * ur) * rcp_nr(ml - mr);
+  const double kl = ml * rcp_nr(SL - Ss), kr = mr * rcp_nr(SR - Ss);
+  const double QL[5] = {rl, rl * ul, rl * vl, rl * wl, El};
+  const double QR[5] = {rr, rr * ur, rr * vr, rr * wr, Er};
+  const double QsL[5] = {kl, kl * Ss, kl * vl, kl * wl,
+                         kl * (El * irl + (Ss - ul) * (Ss + pl * rcp_nr(ml)))};
+  const double QsR[5] = {kr, kr * Ss, kr * vr, kr * wr,
+                         kr * (Er * irr + (Ss - ur) * (Ss + pr * rcp_nr(mr)))};
+  const double aL = fabs(SL), aS = fabs(Ss), aR = fabs(SR);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const double diss = aL * (QsL[m] - QL[m]) + aS * (QsR[m] - QsL[m]) + aR * (QR[m] - QsR[m]);
+    F[m] = Fm[m] - 0.5 * diss;
+  }
+}
+
+// Characteristic MEG7 states in 3D: the primitive eigenvectors of the 2D
+// projection at the mean density and pressure, plus the identity row and
+// column of the second tangential velocity.  Wf(q, f) / Gf(q, f): rotated
+// primitive field f (0..4) and its spacing-scaled normal gradient at offset
+// q-2 from cell j.  Rows of L: (u_n, p), (rho, p), (u_t1), (u_t2), (u_n, p).
+template <int ORD, class FW, class FG>
+__device__ __forceinline__ void meg7_char_states3(FW Wf, FG Gf, double gamma, double WLo[5],
+                                                  double WRo[5]) {
+  const double rb = 0.5 * (Wf(2, 0) + Wf(3, 0));
+  const double pb = 0.5 * (Wf(2, 4) + Wf(3, 4));
+  const double irb = rcp_nr(rb);
+  const double cb = sqrt_nr(gamma * pb * irb);
+  const double icb = rcp_nr(cb);
+  const double h2c = 0.5 * icb, ic2 = icb * icb, h2c2 = 0.5 * ic2;
+  const double cor = cb * irb, c2 = cb * cb;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) { WLo[m] = 0.0; WRo[m] = 0.0; }
+#pragma unroll 1
+  for (int m = 0; m < 5; ++m) {
+    // row m of L as ca * field fa + cbv * field fb
+    const bool tang = (m == 2 || m == 3);
+    const int fa = (m == 1) ? 0 : (tang ? m : 1);
+    const int fb = tang ? m : 4;
+    const double ca = (m == 0) ? -rb * h2c : ((m == 4) ? rb * h2c : 1.0);
+    const double cbv = (m == 1) ? -ic2 : (tang ? 0.0 : h2c2);
+    double cv[6], cg[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      cv[q] = ca * Wf(q, fa) + cbv * Wf(q, fb);
+      cg[q] = ca * Gf(q, fa) + cbv * Gf(q, fb);
+    }
+    double cl, cr;
+    meg7_pair<ORD>(cv, cg, cl, cr);
+    // column m of R = L^{-1}: (1,-c/rho,0,0,c^2), (1,0,0,0,0), (0,0,1,0,0), (0,0,0,1,0),
+    // (1,c/rho,0,0,c^2)
+    const double b0 = tang ? 0.0 : 1.0;
+    const double b1 = (m == 0) ? -cor : ((m == 4) ? cor : 0.0);
+    const double b2 = (m == 2) ? 1.0 : 0.0;
+    const double b3 = (m == 3) ? 1.0 : 0.0;
+    const double b4 = (m == 0 || m == 4) ? c2 : 0.0;
+    WLo[0] += b0 * cl; WLo[1] += b1 * cl; WLo[2] += b2 * cl; WLo[3] += b3 * cl; WLo[4] += b4 * cl;
+    WRo[0] += b0 * cr; WRo[1] += b1 * cr; WRo[2] += b2 * cr; WRo[3] += b3 * cr; WRo[4] += b4 * cr;
+  }
+}
+
+template <int NP, int NL>
+struct Sweep3Cfg {
+  static constexpr int NT = 256;
+  static constexpr int H = 6;
+  static constexpr int WP = NP + 2 * H;   // staged positions per line
+  static constexpr int WD = NP + 6;       // gradients / detector: positions -3 .. NP+2
+  static constexpr int WF = NP + 10;      // cell fluxes: positions -5 .. NP+4
+  static constexpr int WFL = NP + 1;      // interfaces -1/2 .. NP-1/2
+};
+
+template <int DIR, int NP, int NL, int ORD>
+__global__ __launch_bounds__(256, 2) void meg7_sweep3_kernel(Sweep3Params P) {
+  using C = Sweep3Cfg<NP, NL>;
+  constexpr int NT = C::NT, H = C::H, WP = C::WP, WD = C::WD, WF = C::WF, WFL = C::WFL;
+  constexpr bool LINEFAST = DIR != 0;     // y and z lines: consecutive lines are consecutive x
+  __shared__ double sW[5][NL][WP];
+  __shared__ double sD[5][NL][WD];
+  __shared__ double sF[5][NL][WF];        // cell fluxes, then interface fluxes
+  __shared__ unsigned char sChi[NL][WD];
+  __shared__ unsigned short sQueue[NL * WFL];
+  __shared__ int sQCount;
+  const int tid = threadIdx.x;
+  const size_t n = (size_t)P.nx * P.ny * P.nz;
+  const int ndir = DIR == 0 ? P.nx : (DIR == 1 ? P.ny : P.nz);
+  const size_t sdir = DIR == 0 ? 1 : (DIR == 1 ? (size_t)P.nx : (size_t)P.nx * P.ny);
+  const int nlines = DIR == 0 ? P.ny * P.nz : (DIR == 1 ? P.nx * P.nz : P.nx * P.ny);
+  const int ptile = blockIdx.x % P.ptiles;
+  const int group = blockIdx.x / P.ptiles;
+  const int p0 = ptile * NP;
+  // first cell of line L (position 0)
+  auto line_base = [&](int L) -> size_t {
+    if (DIR == 0) return (size_t)L * P.nx;                                   // L = z ny + y
+    if (DIR == 1) return (size_t)(L / P.nx) * P.nx * P.ny + (L % P.nx);      // L = z nx + x
+    return (size_t)L;                                                       // L = y nx + x
+  };
+  // conserved index of rotated component m (cyclic tangential order)
+  auto cidx = [](int m) { return (m == 0 || m == 4) ? m : 1 + (DIR + m - 1) % 3; };
+
+  // ---- load: primitives of NL lines x (NP + 12) positions -----------------
+  bool bad = false;
+  for (int t = tid; t < NL * WP; t += NT) {
+    const int l = LINEFAST ? t % NL : t / WP;
+    const int p = LINEFAST ? t / NL : t % WP;
+    int L = group * NL + l;
+    const bool lv = L < nlines;
+    if (!lv) L = nlines - 1;
+    const int q = p0 + p - H;
+    const size_t s = line_base(L) + (size_t)bc_index(q, ndir, P.bc) * sdir;
+    const double r = P.Qk[s];
+    const double ir = rcp_nr(r);
+    double u[3];
+#pragma unroll
+    for (int m = 1; m <= 3; ++m) u[m - 1] = P.Qk[(size_t)cidx(m) * n + s] * ir;
+    const double E = P.Qk[4 * n + s];
+    const double pr = (P.gamma - 1.0) * (E - 0.5 * r * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
+    sW[0][l][p] = r;
+    sW[1][l][p] = u[0];
+    sW[2][l][p] = u[1];
+    sW[3][l][p] = u[2];
+    sW[4][l][p] = pr;
+    if (P.first && lv && q >= p0 && q < p0 + NP && q < ndir &&
+        !(r > 0.0 && pr > 0.0 && isfinite(E) && isfinite(u[0]) && isfinite(u[1]) &&
+          isfinite(u[2])))
+      bad = true;
+  }
+  if (bad) atomicOr(P.status, STATUS_BAD_STATE);
+  if (tid == 0) sQCount = 0;
+  __syncthreads();
+
+  // ---- pass 1: per cell --------------------------------------------------
+  for (int t = tid; t < NL * WF; t += NT) {
+    const int l = t / WF, pf = t % WF;
+    const int p = pf + 1;                 // staged index of position pf - 5
+    double W[5], f[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) W[m] = sW[m][l][p];
+    conv_flux3(W, P.g1inv, f);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) sF[m][l][pf] = f[m];
+    const int pd = pf - 2;                // position pf - 5 = pd - 3
+    if (pd >= 0 && pd < WD) {
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        const double* u = &sW[m][l][p];
+        sD[m][l][pd] = grad6(u[-3], u[-2], u[-1], u[1], u[2], u[3]);
+      }
+      const double* rho = &sW[0][l][p];
+      const double psi = detector_psi(rho[-2], rho[-1], rho[0], rho[1], rho[2]);
+      sChi[l][pd] = (psi < kPsiC) ? 1 : 0;
+    }
+  }
+  __syncthreads();
+
+  // ---- pass 2: interfaces, smooth branch; ballot-compact the flagged ------
+  constexpr int IPT = (NL * WFL + NT - 1) / NT;
+  double fsm[IPT][5];
+  bool has[IPT];
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    has[k] = false;
+    const int t = tid + k * NT;
+    bool flagged = false;
+    if (t < NL * WFL) {
+      const int l = t / WFL, pi = t % WFL;   // interface between positions pi-1 and pi
+      const int pos = pi - 1;                // left cell
+      bool sigma = true;
+#pragma unroll
+      for (int j = 1; j <= 6; ++j) sigma = sigma && (sChi[l][pos + j] == 0);
+      const int L = group * NL + l;
+      const int gi = p0 + pi;                // interface index along the line
+      if (P.sig && L < nlines && gi <= ndir) {
+        const size_t b = line_base(L);
+        // flags array: one longer along this direction
+        size_t o;
+        if (DIR == 0) o = b / P.nx * (P.nx + 1) + gi;
+        else if (DIR == 1) o = (b / ((size_t)P.nx * P.ny)) * (size_t)(P.ny + 1) * P.nx +
+                               (size_t)gi * P.nx + (b % P.nx);
+        else o = (size_t)gi * P.nx * P.ny + b;
+        P.sig[o] = sigma;
+      }
+      flagged = !sigma;
+      if (sigma) {
+        const int p = pos + H;               // staged index of the left cell
+        double WL[5], WR[5], Fm[5];
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+          double v[6], g[6], f[10];
+#pragma unroll
+          for (int q = 0; q < 6; ++q) v[q] = sW[m][l][p + q - 2];
+#pragma unroll
+          for (int q = 1; q < 5; ++q) g[q] = sD[m][l][pos + q + 1];
+          g[0] = g[5] = 0.0;
+          WL[m] = grb_l<ORD>(v, g);
+          WR[m] = grb_r<ORD>(v, g);
+#pragma unroll
+          for (int q = 0; q < 10; ++q) f[q] = sF[m][l][pos + q + 1];
+          Fm[m] = flux_mean<ORD>(f);
+        }
+        if (!(WL[0] > 0.0 && WL[4] > 0.0 && WR[0] > 0.0 && WR[4] > 0.0)) {
+          double f0[5], f1[5];
+#pragma unroll
+          for (int m = 0; m < 5; ++m) {
+            WL[m] = sW[m][l][p];
+            WR[m] = sW[m][l][p + 1];
+          }
+          conv_flux3(WL, P.g1inv, f0);
+          conv_flux3(WR, P.g1inv, f1);
+#pragma unroll
+          for (int m = 0; m < 5; ++m) Fm[m] = 0.5 * (f0[m] + f1[m]);
+        }
+        hllc3(WL, WR, Fm, P.gamma, P.g1inv, fsm[k]);
+        has[k] = true;
+      }
+    }
+    const unsigned long long ball = __ballot(flagged);
+    if (ball) {
+      const int lane = __lane_id();
+      int base = 0;
+      if (lane == 0) base = atomicAdd(&sQCount, (int)__popcll(ball));
+      base = __shfl(base, 0);
+      if (flagged) {
+        const int rank = (int)__popcll(ball & ((1ull << lane) - 1ull));
+        sQueue[base + rank] = (unsigned short)t;
+      }
+    }
+  }
+  __syncthreads();  // every read of the cell fluxes is done: sF becomes the interface fluxes
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    if (has[k]) {
+      const int t = tid + k * NT;
+      const int l = t / WFL, pi = t % WFL;
+#pragma unroll
+      for (int m = 0; m < 5; ++m) sF[m][l][pi] = fsm[k][m];
+    }
+  }
+
+  // ---- pass 3: the flagged interfaces --------------------------------------
+  const int nq = sQCount;
+  for (int qi = tid; qi < nq; qi += NT) {
+    const int t = sQueue[qi];
+    const int l = t / WFL, pi = t % WFL;
+    const int pos = pi - 1;
+    const int p = pos + H;
+    double WL[5], WR[5];
+    meg7_char_states3<ORD>([&](int q, int f) { return sW[f][l][p + q - 2]; },
+                           [&](int q, int f) { return sD[f][l][pos + q + 1]; }, P.gamma, WL,
+                           WR);
+    if (!(WL[0] > 0.0 && WL[4] > 0.0 && WR[0] > 0.0 && WR[4] > 0.0)) {
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        WL[m] = sW[m][l][p];
+        WR[m] = sW[m][l][p + 1];
+      }
+    }
+    double FL[5], FR[5], Fm[5], F[5];
+    conv_flux3(WL, P.g1inv, FL);
+    conv_flux3(WR, P.g1inv, FR);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) Fm[m] = 0.5 * (FL[m] + FR[m]);
+    hllc3(WL, WR, Fm, P.gamma, P.g1inv, F);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) sF[m][l][pi] = F[m];
+  }
+  __syncthreads();
+
+  // ---- pass 4: flux differences; residual accumulation / stage update ------
+  const double dtv = (P.last && P.mode != MODE_RESIDUAL) ? *P.dt : 0.0;
+  for (int t = tid; t < NL * NP; t += NT) {
+    const int l = LINEFAST ? t % NL : t / NP;
+    const int pc = LINEFAST ? t / NL : t % NP;
+    const int L = group * NL + l;
+    const int q = p0 + pc;
+    if (L >= nlines || q >= ndir) continue;
+    const size_t s = line_base(L) + (size_t)q * sdir;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const size_t o = (size_t)cidx(m) * n + s;
+      const double d = (sF[m][l][pc + 1] - sF[m][l][pc]) * P.inv_d;
+      double r = P.first ? -d : P.R[o] - d;
+      if (!P.last) {
+        P.R[o] = r;
+      } else if (P.mode == MODE_RESIDUAL) {
+        P.out[o] = r;
+      } else if (P.mode == MODE_STAGE1) {
+        P.out[o] = P.Qn[o] + dtv * r;
+      } else if (P.mode == MODE_STAGE2) {
+        P.out[o] = 0.75 * P.Qn[o] + 0.25 * P.Qk[o] + (0.25 * dtv) * r;
+      } else {
+        P.out[o] = (1.0 / 3.0) * P.Qn[o] + (2.0 / 3.0) * P.Qk[o] + ((2.0 / 3.0) * dtv) * r;
+      }
+    }
+  }
+}
+
+// CFL time step in 3D (inviscid), Sec. 2.5: pass 1 of the two-pass
+// reduction (pass 2 is dt_finish_kernel with no viscous limit).
+struct Dt3Params {
+  const double* __restrict__ Q;
+  double* partial;
+  unsigned* status;
+  int nx, ny, nz;
+  double dx, dy, dz, gamma;
+};
+
+__global__ __launch_bounds__(kDtThreads) void dt3_reduce_kernel(Dt3Params P) {
+#pragma clang fp contract(off)
+  __shared__ double red[kDtThreads / 64];
+  const size_t n = (size_t)P.nx * P.ny * P.nz;
+  double conv = __builtin_inf();
+  bool bad = false;
+  for (size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+       s += (size_t)gridDim.x * blockDim.x) {
+    const double rho = P.Q[s];
+    const double u = P.Q[n + s] / rho, v = P.Q[2 * n + s] / rho, w = P.Q[3 * n + s] / rho;
+    const double p = (P.gamma - 1.0) * (P.Q[4 * n + s] - rho * (u * u + v * v + w * w) / 2.0);
+    const double c = sqrt(P.gamma * p / rho);
+    if (!(rho > 0.0) || !(p > 0.0) || !isfinite(c) || !isfinite(u) || !isfinite(v) ||
+        !isfinite(w))
+      bad = true;
+    conv = fmin(conv, fmin(P.dx / (fabs(u) + c), fmin(P.dy / (fabs(v) + c), P.dz / (fabs(w) + c))));
+  }
+  if (bad) atomicOr(P.status, 1u);
+  conv = block_min(conv, red);
+  if (threadIdx.x == 0) {
+    P.partial[blockIdx.x] = conv;
+    P.partial[kDtBlocks + blockIdx.x] = __builtin_inf();
+  }
+}
+
+}  // namespace gbr

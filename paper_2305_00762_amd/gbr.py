@@ -87,6 +87,18 @@ SIGNATURES = {
     "gbr_timing_read": (_i, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                              C.POINTER(C.c_uint64)]),
     "gbr_mlp_stats": (_i, [_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), _i]),
+    "gbr3_init": (_i, [_i, _i, _i, _d, C.POINTER(_vp)]),
+    "gbr3_destroy": (_i, [_vp]),
+    "gbr3_set_geometry": (_i, [_vp, _d, _d, _d, _d, _d, _d, _i, _i, _i]),
+    "gbr3_set_order": (_i, [_vp, _i]),
+    "gbr3_residual": (_i, [_vp, _vp, _vp, _vp]),
+    "gbr3_rk_stage": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
+    "gbr3_compute_dt": (_i, [_vp, _vp, _d, _vp, _vp]),
+    "gbr3_export_flags": (_i, [_vp, _i]),
+    "gbr3_get_flags": (_i, [_vp, _vp, _vp, _vp, _vp]),
+    "gbr3_check": (_i, [_vp, _vp]),
+    "gbr3_timing": (_i, [_vp, _i]),
+    "gbr3_timing_read": (_i, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
 }
 
 _lib = None
@@ -427,4 +439,66 @@ def gbr_batch_timing_read(b):
     """(summed stage-launch ms, stage launches) since timing was enabled or read."""
     t, n = C.c_double(), C.c_uint64()
     _check(load().gbr_batch_timing_read(b, C.byref(t), C.byref(n)), "gbr_batch_timing_read")
+    return t.value, n.value
+
+
+# --------------------------------------------------------------------- 3D ---
+def gbr3_init(nx, ny, nz, gamma):
+    h = C.c_void_p()
+    _check(load().gbr3_init(nx, ny, nz, gamma, C.byref(h)), "gbr3_init")
+    return h.value
+
+
+def gbr3_destroy(ctx):
+    return _check(load().gbr3_destroy(ctx), "gbr3_destroy")
+
+
+def gbr3_set_geometry(ctx, x0, x1, y0, y1, z0, z1, bc_x, bc_y, bc_z):
+    return _check(load().gbr3_set_geometry(ctx, x0, x1, y0, y1, z0, z1, bc_x, bc_y, bc_z),
+                  "gbr3_set_geometry")
+
+
+def gbr3_set_order(ctx, order):
+    return _check(load().gbr3_set_order(ctx, order), "gbr3_set_order")
+
+
+def gbr3_residual(ctx, Q, Res, stream=None):
+    return _check(load().gbr3_residual(ctx, _addr(Q), _addr(Res), _stream(stream)),
+                  "gbr3_residual")
+
+
+def gbr3_rk_stage(ctx, stage, dt, Qn, Qk, Qout, stream=None):
+    return _check(load().gbr3_rk_stage(ctx, stage, _addr(dt), _addr(Qn), _addr(Qk), _addr(Qout),
+                                       _stream(stream)), "gbr3_rk_stage")
+
+
+def gbr3_compute_dt(ctx, Q, cfl, dt, stream=None):
+    return _check(load().gbr3_compute_dt(ctx, _addr(Q), cfl, _addr(dt), _stream(stream)),
+                  "gbr3_compute_dt")
+
+
+def gbr3_export_flags(ctx, enable):
+    return _check(load().gbr3_export_flags(ctx, 1 if enable else 0), "gbr3_export_flags")
+
+
+def gbr3_get_flags(ctx, sig_x, sig_y, sig_z, stream=None):
+    return _check(load().gbr3_get_flags(ctx, _addr(sig_x), _addr(sig_y), _addr(sig_z),
+                                        _stream(stream)), "gbr3_get_flags")
+
+
+def gbr3_check(ctx, stream=None):
+    code = load().gbr3_check(ctx, _stream(stream))
+    if code not in (GBR_OK, GBR_ESTATE):
+        raise GbrError(code, "gbr3_check")
+    return code
+
+
+def gbr3_timing(ctx, enable):
+    return _check(load().gbr3_timing(ctx, 1 if enable else 0), "gbr3_timing")
+
+
+def gbr3_timing_read(ctx):
+    """(summed ms of the sweep kernels, calls) since timing was enabled or read."""
+    t, n = C.c_double(), C.c_uint64()
+    _check(load().gbr3_timing_read(ctx, C.byref(t), C.byref(n)), "gbr3_timing_read")
     return t.value, n.value

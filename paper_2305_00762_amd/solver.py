@@ -135,3 +135,67 @@ class BatchSolver:
             self.close()
         except Exception:
             pass
+
+
+class Solver3:
+    """3D Euler (inviscid) grid: three device state buffers, SSP-RK3 steps
+    through gbr3_compute_dt and gbr3_rk_stage."""
+
+    def __init__(self, problem, device="cuda", stream=None, export_flags=False, order=7):
+        import torch
+        self.torch = torch
+        self.p = problem
+        self.stream = stream
+        self.ctx = gbr.gbr3_init(problem.nx, problem.ny, problem.nz, problem.gamma)
+        gbr.gbr3_set_geometry(self.ctx, *problem.geometry(), *problem.bc)
+        if order != 7:
+            gbr.gbr3_set_order(self.ctx, order)
+        if export_flags:
+            gbr.gbr3_export_flags(self.ctx, True)
+        shape = (5, problem.nz, problem.ny, problem.nx)
+        self.Q = torch.empty(shape, dtype=torch.float64, device=device)
+        self.Q1 = torch.empty_like(self.Q)
+        self.Q2 = torch.empty_like(self.Q)
+        self.dt = torch.zeros(1, dtype=torch.float64, device=device)
+        if problem.Q is not None:
+            self.Q.copy_(torch.from_numpy(np.ascontiguousarray(problem.Q, np.float64)))
+
+    def close(self):
+        if self.ctx:
+            gbr.gbr3_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def state(self):
+        self.torch.cuda.synchronize()
+        return self.Q.cpu().numpy()
+
+    def residual(self, Q=None):
+        Q = self.Q if Q is None else Q
+        R = self.torch.empty_like(Q)
+        gbr.gbr3_residual(self.ctx, Q, R, self.stream)
+        return R
+
+    def step(self, cfl=None):
+        gbr.gbr3_compute_dt(self.ctx, self.Q, self.p.cfl if cfl is None else cfl, self.dt,
+                            self.stream)
+        gbr.gbr3_rk_stage(self.ctx, 1, self.dt, self.Q, self.Q, self.Q1, self.stream)
+        gbr.gbr3_rk_stage(self.ctx, 2, self.dt, self.Q, self.Q1, self.Q2, self.stream)
+        gbr.gbr3_rk_stage(self.ctx, 3, self.dt, self.Q, self.Q2, self.Q1, self.stream)
+        self.Q, self.Q1 = self.Q1, self.Q
+
+    def flags(self):
+        p = self.p
+        sx = np.zeros((p.nz, p.ny, p.nx + 1), np.uint8)
+        sy = np.zeros((p.nz, p.ny + 1, p.nx), np.uint8)
+        sz = np.zeros((p.nz + 1, p.ny, p.nx), np.uint8)
+        gbr.gbr3_get_flags(self.ctx, sx, sy, sz, self.stream)
+        return sx, sy, sz
+
+    def check(self):
+        return gbr.gbr3_check(self.ctx, self.stream)

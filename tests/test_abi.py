@@ -19,7 +19,7 @@ def declared():
         if f.endswith(".h"):
             txt += open(os.path.join(ROOT, "include", f)).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(gbr_\w+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(gbr3?_\w+)\s*\(", txt)))
 
 
 def test_library_exports_every_declared_symbol():
