@@ -55,7 +55,7 @@ typedef struct {
     double split0, split_speed;
 } gbr_side;
 enum { GBR_RECON_PRIM = 0, GBR_RECON_CONS = 1 };
-enum { GBR_MP_FLAGGED = 0 };
+enum { GBR_MP_FLAGGED = 0, GBR_MP_EVERYWHERE = 1 };
 enum { GBR_PREC_FP64 = 0, GBR_PREC_FP32_BULK = 1 };
 enum { GBR_DET_PLAIN = 0, GBR_DET_MLP = 1 };
 
@@ -96,7 +96,11 @@ int gbr_set_geometry(gbr_ctx *ctx, double x0, double x1, double y0, double y1,
  * cells beside the interface, velocity gradients of the viscous flux by the
  * chain rule; FP64 with the plain detector only, on the 31x15 and 15x15
  * tilings), mp_mode = GBR_MP_FLAGGED (MP limiter in characteristic variables
- * at interfaces the detector flags, Secs. 2.3-2.4), precision = GBR_PREC_FP64
+ * at interfaces the detector flags, Secs. 2.3-2.4) or GBR_MP_EVERYWHERE (the
+ * MEG7 states -- characteristic projection and MP test -- at every
+ * interface, while smooth interfaces keep the reconstructed cell fluxes of
+ * eqs. flux-full, flux-right; FP64, plain detector, seventh order, HLLC, on
+ * the 31x15 and 15x15 tilings), precision = GBR_PREC_FP64
  * or GBR_PREC_FP32_BULK (gradients, reconstruction and fluxes in float32 with
  * FP64 state, stage update and flux differencing), detector = GBR_DET_PLAIN
  * (density detector, Sec. 2.4) or GBR_DET_MLP (learned detector, needs

@@ -19,11 +19,12 @@ namespace {
 
 using namespace gbr;
 
-template <class C, bool MLP = false, bool CONS = false, int ORD = 7, bool LM = false>
+template <class C, bool MLP = false, bool CONS = false, int ORD = 7, bool LM = false,
+          bool MPE = false>
 void launch_cfg(const StageParams& P, hipStream_t s) {
   static_assert(C::LDS_BYTES <= 160 * 1024, "LDS per workgroup");
-  hipLaunchKernelGGL((meg7_stage_kernel<C, MLP, CONS, ORD, LM>), dim3(P.ntiles), dim3(C::NT), 0,
-                     s, P);
+  hipLaunchKernelGGL((meg7_stage_kernel<C, MLP, CONS, ORD, LM, MPE>), dim3(P.ntiles), dim3(C::NT),
+                     0, s, P);
 }
 template <class C, bool MLP = false>
 void launch_cfg_f32(const StageParams& P, hipStream_t s) {
@@ -43,6 +44,7 @@ struct TileVariant {
   LaunchFn cons[2];       // MEG7-cons, FP64 with the plain detector: [viscous]; null: no build
   LaunchFn g4[2][2];      // fourth-order GRB, FP64 with the plain detector: [cons][viscous]
   LaunchFn ss[2][2];      // shock-stable HLLC, seventh order, FP64, plain: [cons][viscous]
+  LaunchFn mpe[2][2];     // MP test at every interface, seventh order, FP64, plain: [cons][viscous]
 };
 using E31 = TileCfg<31, 15, 15, 16, 256, false>;
 using V31 = TileCfg<31, 15, 8, 16, 256, true>;
@@ -59,7 +61,9 @@ const TileVariant kVariants[] = {
      {{launch_cfg<E31, false, false, 4>, launch_cfg<V31, false, false, 4>},
       {launch_cfg<E31, false, true, 4>, launch_cfg<V31, false, true, 4>}},
      {{launch_cfg<E31, false, false, 7, true>, launch_cfg<V31, false, false, 7, true>},
-      {launch_cfg<E31, false, true, 7, true>, launch_cfg<V31, false, true, 7, true>}}},
+      {launch_cfg<E31, false, true, 7, true>, launch_cfg<V31, false, true, 7, true>}},
+     {{launch_cfg<E31, false, false, 7, false, true>, launch_cfg<V31, false, false, 7, false, true>},
+      {launch_cfg<E31, false, true, 7, false, true>, launch_cfg<V31, false, true, 7, false, true>}}},
     // 16 interfaces per line both ways; 3-4 workgroups/CU
     {15, 15,
      {{{launch_cfg<E15>, launch_cfg<E15, true>}, {launch_cfg<V15>, launch_cfg<V15, true>}},
@@ -70,7 +74,9 @@ const TileVariant kVariants[] = {
      {{launch_cfg<E15, false, false, 4>, launch_cfg<V15, false, false, 4>},
       {launch_cfg<E15, false, true, 4>, launch_cfg<V15, false, true, 4>}},
      {{launch_cfg<E15, false, false, 7, true>, launch_cfg<V15, false, false, 7, true>},
-      {launch_cfg<E15, false, true, 7, true>, launch_cfg<V15, false, true, 7, true>}}},
+      {launch_cfg<E15, false, true, 7, true>, launch_cfg<V15, false, true, 7, true>}},
+     {{launch_cfg<E15, false, false, 7, false, true>, launch_cfg<V15, false, false, 7, false, true>},
+      {launch_cfg<E15, false, true, 7, false, true>, launch_cfg<V15, false, true, 7, false, true>}}},
     // 64 x-interfaces per row, 8 y-interfaces per column (Euler, plain detector)
     {63, 7,
      {{{launch_cfg<TileCfg<63, 7, 7, 32, 256, false>>,
@@ -81,6 +87,7 @@ const TileVariant kVariants[] = {
        {nullptr, nullptr}}},
      "63x7",
      {nullptr, nullptr},
+     {{nullptr, nullptr}, {nullptr, nullptr}},
      {{nullptr, nullptr}, {nullptr, nullptr}},
      {{nullptr, nullptr}, {nullptr, nullptr}}},
     // 31x8 / 15x16 interface blocks sized for 3 workgroups per CU in FP32 bulk
@@ -93,6 +100,7 @@ const TileVariant kVariants[] = {
        {nullptr, nullptr}}},
      "30x15",
      {nullptr, nullptr},
+     {{nullptr, nullptr}, {nullptr, nullptr}},
      {{nullptr, nullptr}, {nullptr, nullptr}},
      {{nullptr, nullptr}, {nullptr, nullptr}}},
 };
@@ -296,7 +304,8 @@ int gbr_set_sides(gbr_ctx* c, const gbr_side* sides) {
 int gbr_set_riemann(gbr_ctx* c, int kind) {
   if (!c || (kind != GBR_RIEMANN_HLLC && kind != GBR_RIEMANN_HLLC_SS)) return GBR_EINVAL;
   if (kind == GBR_RIEMANN_HLLC_SS &&
-      (c->precision != GBR_PREC_FP64 || c->detector != GBR_DET_PLAIN || c->order != 7))
+      (c->precision != GBR_PREC_FP64 || c->detector != GBR_DET_PLAIN || c->order != 7 ||
+       c->mp_mode != GBR_MP_FLAGGED))
     return GBR_EUNSUPPORTED;
   c->riemann = kind;
   return GBR_OK;
@@ -326,7 +335,11 @@ int gbr_advance_time(gbr_ctx* c, const double* dt_dev, void* stream) {
 int gbr_set_scheme(gbr_ctx* c, int recon, int mp_mode, int precision, int detector) {
   if (!c) return GBR_EINVAL;
   if (recon != GBR_RECON_PRIM && recon != GBR_RECON_CONS) return GBR_EUNSUPPORTED;
-  if (mp_mode != GBR_MP_FLAGGED) return GBR_EUNSUPPORTED;
+  if (mp_mode != GBR_MP_FLAGGED && mp_mode != GBR_MP_EVERYWHERE) return GBR_EUNSUPPORTED;
+  if (mp_mode == GBR_MP_EVERYWHERE &&
+      (precision != GBR_PREC_FP64 || detector != GBR_DET_PLAIN || c->order != 7 ||
+       c->riemann != GBR_RIEMANN_HLLC))
+    return GBR_EUNSUPPORTED;
   if (precision != GBR_PREC_FP64 && precision != GBR_PREC_FP32_BULK) return GBR_EUNSUPPORTED;
   if (detector != GBR_DET_PLAIN && detector != GBR_DET_MLP) return GBR_EUNSUPPORTED;
   if ((recon == GBR_RECON_CONS || c->order == 4 || c->use_sides || c->riemann) &&
@@ -341,7 +354,7 @@ int gbr_set_order(gbr_ctx* c, int order) {
   if (!c) return GBR_EINVAL;
   if (order != 7 && order != 4) return GBR_EINVAL;
   if (order == 4 && (c->precision != GBR_PREC_FP64 || c->detector != GBR_DET_PLAIN ||
-                     c->riemann != GBR_RIEMANN_HLLC))
+                     c->riemann != GBR_RIEMANN_HLLC || c->mp_mode != GBR_MP_FLAGGED))
     return GBR_EUNSUPPORTED;
   c->order = order;
   return GBR_OK;
@@ -387,6 +400,8 @@ int gbr_check(gbr_ctx* c, void* stream) {
 // variant has no build for it.
 static LaunchFn variant_fn(const gbr_ctx* c, int v) {
   const int visc = c->mu > 0.0 ? 1 : 0;
+  if (c->mp_mode == GBR_MP_EVERYWHERE)
+    return kVariants[v].mpe[c->recon == GBR_RECON_CONS ? 1 : 0][visc];
   if (c->riemann == GBR_RIEMANN_HLLC_SS)
     return kVariants[v].ss[c->recon == GBR_RECON_CONS ? 1 : 0][visc];
   if (c->order == 4) return kVariants[v].g4[c->recon == GBR_RECON_CONS ? 1 : 0][visc];

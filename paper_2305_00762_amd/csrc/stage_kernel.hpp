@@ -123,7 +123,7 @@ __device__ __forceinline__ void load_chimap(const StageParams& P, unsigned char*
   }
 }
 
-template <class C, int DIR, bool DETMLP, bool CONS, int ORD, bool LM>
+template <class C, int DIR, bool DETMLP, bool CONS, int ORD, bool LM, bool MPE>
 __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0, int tx0,
                                       int ty0, double (&res)[C::CPT][4]) {
   constexpr bool X = (DIR == 0);
@@ -308,7 +308,20 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
             for (int q = 0; q < 10; ++q) f[q] = sF[m * FSTR + bidx(line, pos + q + 1, WF)];
             Fm[m] = flux_mean<ORD>(f);
           }
-          if (CONS) {
+          if (MPE) {
+            // MP test at every interface (mp_mode everywhere): the states are
+            // the characteristic MEG7 ones; the fluxes stay reconstructed
+            auto Vf = [&](int q, int f) { return L.U[rot[f] * RS + r + (q - 2) * SN]; };
+            auto Gf = [&](int q, int f) { return sD[f * NL * WD + bidx(line, pos + q + 1, WD)]; };
+            if (CONS) {
+              double QL[4], QR[4];
+              meg7_char_states_cons<ORD>(Vf, Gf, P.gamma, QL, QR);
+              cons_to_prim(QL, P.gamma, WL);
+              cons_to_prim(QR, P.gamma, WR);
+            } else {
+              meg7_char_states<ORD>(Vf, Gf, P.gamma, WL, WR);
+            }
+          } else if (CONS) {
             // the GRB states above are conservative: to primitives
             const double QL[4] = {WL[0], WL[1], WL[2], WL[3]};
             const double QR[4] = {WR[0], WR[1], WR[2], WR[3]};
@@ -627,7 +640,8 @@ __device__ __forceinline__ void stage_store(const StageParams& P, const double (
 // One tile of the stage: load, both sweeps, store.  The LDS arrays are
 // passed in so that a kernel can run several tile shapes from one set of
 // arrays sized for the largest (the batched kernel).
-template <class C, bool DETMLP, bool CONS = false, int ORD = 7, bool LM = false>
+template <class C, bool DETMLP, bool CONS = false, int ORD = 7, bool LM = false,
+          bool MPE = false>
 __device__ __forceinline__ void stage_tile(const StageParams& P, int tx0, int ty0, double* sU,
                                            double* sPh, unsigned char* sChi,
                                            unsigned short* sQueue, int* sQCount,
@@ -642,13 +656,13 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int tx0, int ty
 #pragma unroll
     for (int m = 0; m < 4; ++m) res[k][m] = 0.0;
   for (int l0 = 0; l0 < C::TY; l0 += C::SX)
-    sweep<C, 0, DETMLP, CONS, ORD, LM>(P, L, l0, tx0, ty0, res);
+    sweep<C, 0, DETMLP, CONS, ORD, LM, MPE>(P, L, l0, tx0, ty0, res);
   for (int l0 = 0; l0 < C::TX; l0 += C::SY)
-    sweep<C, 1, DETMLP, CONS, ORD, LM>(P, L, l0, tx0, ty0, res);
+    sweep<C, 1, DETMLP, CONS, ORD, LM, MPE>(P, L, l0, tx0, ty0, res);
   stage_store<C>(P, res, tx0, ty0);
 }
 
-template <class C, bool DETMLP, bool CONS = false, int ORD = 7, bool LM = false>
+template <class C, bool DETMLP, bool CONS = false, int ORD = 7, bool LM = false, bool MPE = false>
 __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel(StageParams P) {
   __shared__ double sU[C::NF * C::RS];
   __shared__ double sPh[C::PH];
@@ -658,7 +672,8 @@ __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel(StageParams 
   __shared__ int sQCount;
   int tx0, ty0;
   if (!tile_origin(P, C::TX, C::TY, tx0, ty0)) return;
-  stage_tile<C, DETMLP, CONS, ORD, LM>(P, tx0, ty0, sU, sPh, sChi, sQueue, &sQCount, sChiF);
+  stage_tile<C, DETMLP, CONS, ORD, LM, MPE>(P, tx0, ty0, sU, sPh, sChi, sQueue, &sQCount,
+                                            sChiF);
 }
 
 }  // namespace gbr

@@ -30,6 +30,7 @@ GBR_RIEMANN_HLLC_SS = 1
 GBR_RECON_PRIM = 0
 GBR_RECON_CONS = 1
 GBR_MP_FLAGGED = 0
+GBR_MP_EVERYWHERE = 1
 GBR_PREC_FP64 = 0
 GBR_PREC_FP32_BULK = 1
 GBR_DET_PLAIN = 0

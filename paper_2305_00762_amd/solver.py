@@ -12,7 +12,7 @@ from . import gbr
 class Solver:
     def __init__(self, problem, device="cuda", stream=None, export_flags=False,
                  precision=gbr.GBR_PREC_FP64, detector=gbr.GBR_DET_PLAIN,
-                 recon=gbr.GBR_RECON_PRIM, order=7):
+                 recon=gbr.GBR_RECON_PRIM, order=7, mp_mode=gbr.GBR_MP_FLAGGED):
         import torch
         self.torch = torch
         self.p = problem
@@ -20,7 +20,7 @@ class Solver:
         self.stream = stream
         self.ctx = gbr.gbr_init(problem.nx, problem.ny, problem.gamma, problem.mu, problem.Pr)
         gbr.gbr_set_geometry(self.ctx, *problem.geometry())
-        gbr.gbr_set_scheme(self.ctx, recon, gbr.GBR_MP_FLAGGED, precision, detector)
+        gbr.gbr_set_scheme(self.ctx, recon, mp_mode, precision, detector)
         if order != 7:
             gbr.gbr_set_order(self.ctx, order)
         if getattr(problem, "sides", None) is not None:

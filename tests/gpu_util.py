@@ -52,12 +52,12 @@ def res_err(R, Ro, P):
     return np.abs(R - Ro).max(1) / scale
 
 
-def gpu_residual(P, precision=0, tiling=None, detector=0, recon=0, order=7):
+def gpu_residual(P, precision=0, tiling=None, detector=0, recon=0, order=7, mp_mode=0):
     from paper_2305_00762_amd.solver import Solver
     from paper_2305_00762_amd import gbr
     torch = require_gpu()
     S = Solver(P, export_flags=True, precision=precision, detector=detector, recon=recon,
-               order=order)
+               order=order, mp_mode=mp_mode)
     if tiling is not None:
         gbr.gbr_set_tiling(S.ctx, tiling)
     R = S.residual()

@@ -62,3 +62,20 @@ def test_mirror_symmetry(orc, seed):
     vl, _ = orc.meg7_left(p, g)
     vr, _ = orc.meg7_right(pm, gm)
     assert vl == pytest.approx(vr, abs=1e-13)
+
+
+def test_mp_everywhere_equals_flagged_where_all_flagged(orc):
+    """With every interface flagged (sigma forced to 0) the two MP modes
+    compute the same thing, MEG7 states and F(Q) at every interface, bit for
+    bit; with sigma free they differ exactly where the detector passes an
+    interface (the smooth ones take MEG7 states under mp_mode 1)."""
+    from paper_2305_00762_amd import problems as PB
+    P = PB.riemann(40, seed=9, ny=36)
+    for recon in (0, 1):
+        R0 = orc.residual(orc.make_cfg(40, 36, force_sigma=0, recon=recon), P.Q)
+        R1 = orc.residual(orc.make_cfg(40, 36, force_sigma=0, recon=recon, mp_mode=1), P.Q)
+        assert np.array_equal(R0, R1)
+        F0, sx, sy, _ = orc.residual(orc.make_cfg(40, 36, recon=recon), P.Q, want_flags=True)
+        F1 = orc.residual(orc.make_cfg(40, 36, recon=recon, mp_mode=1), P.Q)
+        assert sx.min() == 0 and sx.max() == 1
+        assert not np.array_equal(F0, F1)
