@@ -16,7 +16,7 @@ number of steps is compared with it (L1/Linf per variable).
 Prints ONE JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload riemann1024]
-                  [--path fp32_mlp|fp32|fp64|fp64_cons] [--no-cpu-baseline] [--no-compare]
+                  [--path fp32_mlp|fp32|fp64|fp64_cons|fp64_g4|fp64_mpe] [--no-cpu-baseline] [--no-compare]
 """
 import argparse
 import json
@@ -75,16 +75,21 @@ WORKLOADS = {
                  "stage over all grids, steps replayed as a HIP graph"),
 }
 
+def _path(prec, mlp, dtype, kernel, cons=False, order=7, mp_everywhere=False):
+    return {"prec": prec, "mlp": mlp, "dtype": dtype, "kernel": kernel, "cons": cons,
+            "order": order, "mp_everywhere": mp_everywhere}
+
+
 PATHS = {
-    # name: (precision, learned detector, dtype, kernel name, conservative
-    #        reconstruction, GRB order)
-    "fp32_mlp": ("fp32", True, "f32+f64", "meg7_stage_kernel_f32<mlp>", False, 7),
-    "fp32": ("fp32", False, "f32+f64", "meg7_stage_kernel_f32", False, 7),
-    "fp64": ("fp64", False, "f64", "meg7_stage_kernel", False, 7),
+    "fp32_mlp": _path("fp32", True, "f32+f64", "meg7_stage_kernel_f32<mlp>"),
+    "fp32": _path("fp32", False, "f32+f64", "meg7_stage_kernel_f32"),
+    "fp64": _path("fp64", False, "f64", "meg7_stage_kernel"),
     # MEG7-cons (Table 2): GRB and the MP procedure on conservative variables
-    "fp64_cons": ("fp64", False, "f64", "meg7_stage_kernel<cons>", True, 7),
+    "fp64_cons": _path("fp64", False, "f64", "meg7_stage_kernel<cons>", cons=True),
     # the fourth-order GRB subset (alpha = 4, beta = 0; eq. fourth)
-    "fp64_g4": ("fp64", False, "f64", "meg7_stage_kernel<g4>", False, 4),
+    "fp64_g4": _path("fp64", False, "f64", "meg7_stage_kernel<g4>", order=4),
+    # the MEG7 states at every interface (the MP test everywhere)
+    "fp64_mpe": _path("fp64", False, "f64", "meg7_stage_kernel<mpe>", mp_everywhere=True),
 }
 
 
@@ -128,7 +133,9 @@ class Path:
         import torch
         from paper_2305_00762_amd import gbr
         self.gbr, self.P, self.stream = gbr, P, stream
-        prec_name, mlp, self.dtype, self.kernel, self.cons, order = PATHS[path]
+        spec = PATHS[path]
+        prec_name, mlp, self.dtype, self.kernel = spec["prec"], spec["mlp"], spec["dtype"], spec["kernel"]
+        self.cons, order = spec["cons"], spec["order"]
         self.ctx = gbr.gbr_init(P.nx, P.ny, P.gamma, P.mu, P.Pr)
         gbr.gbr_set_geometry(self.ctx, *P.geometry())
         prec = gbr.GBR_PREC_FP32_BULK if prec_name == "fp32" else gbr.GBR_PREC_FP64
@@ -141,7 +148,8 @@ class Path:
                                      stream.cuda_stream)
             det = gbr.GBR_DET_MLP
         recon = gbr.GBR_RECON_CONS if self.cons else gbr.GBR_RECON_PRIM
-        gbr.gbr_set_scheme(self.ctx, recon, gbr.GBR_MP_FLAGGED, prec, det)
+        mp = gbr.GBR_MP_EVERYWHERE if spec["mp_everywhere"] else gbr.GBR_MP_FLAGGED
+        gbr.gbr_set_scheme(self.ctx, recon, mp, prec, det)
         if order != 7:
             gbr.gbr_set_order(self.ctx, order)
         self.order = order
@@ -252,14 +260,14 @@ def diff(Qa, Qb):
     return ([float(v) for v in d.mean(dim=1).cpu()], [float(v) for v in d.max(dim=1).values.cpu()])
 
 
-def cpu_baseline(P, seconds, max_steps=50, recon=0, order=7):
+def cpu_baseline(P, seconds, max_steps=50, recon=0, order=7, mp_mode=0):
     """The CPU oracle on a bounded sample of the same workload: whole SSP-RK3
     steps on the full grid from the initial state until about `seconds` of
     host time have passed.  Returns (record, state after the sample, steps)."""
     import numpy as np
     import oracle as O
     cfg = O.make_cfg(P.nx, P.ny, *P.geometry(), gamma=P.gamma, mu=P.mu, Pr=P.Pr, recon=recon,
-                     order=order, riemann=P.riemann,
+                     order=order, riemann=P.riemann, mp_mode=mp_mode,
                      sides=[O.side(*sd) for sd in P.sides] if P.sides is not None else None)
     Q = np.ascontiguousarray(P.Q.copy())
     steps, t0 = 0, time.perf_counter()
@@ -453,7 +461,8 @@ def bench_batch(a, steps):
     cells = sum(p.nx * p.ny for p in ps)
     torch.cuda.set_device(0)
     s = torch.cuda.Stream()
-    if PATHS[a.path][4] or PATHS[a.path][5] != 7:
+    spec = PATHS[a.path]
+    if spec["cons"] or spec["order"] != 7 or spec["mp_everywhere"]:
         print("bench.py: batched grids run seventh-order MEG7-prim; use --path fp64 or fp32",
               file=sys.stderr)
         sys.exit(2)
@@ -595,7 +604,7 @@ def main():
     # the timed launches over their summed duration from the library's events
     alg_bytes = sum(BYTES_PER_CELL_STAGE.values()) * cells * steps
     achieved = alg_bytes / (stage_ms * 1e-3) / 1e9
-    kname = head.kernel.replace("<mlp>", "_mlp").replace("<cons>", "_cons").replace("<g4>", "_g4")
+    kname = head.kernel.replace("<", "_").replace(">", "")
     traffic = load_traffic(kname, a.workload)
     out = {
         "metric": METRIC,
@@ -671,7 +680,8 @@ def main():
 
     if not a.no_cpu_baseline:
         rec, Qo, osteps = cpu_baseline(P, a.cpu_seconds, recon=1 if head.cons else 0,
-                                       order=head.order)
+                                       order=head.order,
+                                       mp_mode=1 if PATHS[a.path]["mp_everywhere"] else 0)
         out["cpu_baseline"] = rec
         head.reset()
         head.run(osteps, 0)
