@@ -273,6 +273,16 @@ int gbr_mlp_train_step(gbr_mlp *m, const uint16_t *feat, const uint8_t *labels, 
 int gbr_set_mlp_detector(gbr_ctx *ctx, const gbr_mlp *m, float margin, void *stream);
 int gbr_mlp_stats(gbr_ctx *ctx, uint64_t *evaluated, uint64_t *fallbacks, int reset);
 
+/* Self-test of the reciprocal the detector features use (the hardware
+ * estimate refined by one fused Newton step in place of IEEE division; the
+ * features of the learned detector take one reciprocal per stencil): compares
+ * it with IEEE float32 division over every float with bit pattern in
+ * [lo, hi), on the current device, and writes the number of differing results
+ * to *mismatches (host pointer).  Synchronises the device.  The features use
+ * it for normal x below 2^126, i.e. bit patterns [0x00800000, 0x7E800000),
+ * where the answer is 0.  Returns GBR_EINVAL if mismatches is NULL or lo > hi. */
+int gbr_selftest_reciprocal(uint32_t lo, uint32_t hi, uint64_t *mismatches);
+
 /* Synchronise `stream`, return GBR_ESTATE if any kernel since the last check
  * saw a non-finite value or rho <= 0 or p <= 0 in an interior cell, and
  * clear that record. */

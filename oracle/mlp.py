@@ -16,6 +16,8 @@ chi^d = [psi^d < psi_c] (computed by the C oracle), its input 28 features:
 
 Network 28 -> 32 -> 32 -> 1: h1 = relu(W1 x + b1), h1 rounded to bf16,
 h2 = relu(W2 h1 + b2), z = w3 . h2 + b3; weights are bf16, biases float32.
+Inference rounds h2 to bf16 as well (the output layer is a matrix-core
+product); training keeps h2 in float32.
 Loss: binary cross-entropy with logits, mean over the batch.
 
 Functions take numpy arrays; the forward/backward pass is evaluated in FP64
@@ -105,14 +107,18 @@ def unpack(w, b):
     return W1, W2, w3, b[:NH], b[NH:2 * NH], b[2 * NH]
 
 
-def forward(feat_bits, w_bf16, b, round_h1=True):
-    """Logits (FP64) for bf16 features and bf16-valued weights (float arrays)."""
+def forward(feat_bits, w_bf16, b, round_h1=True, round_h2=True):
+    """Logits (FP64) for bf16 features and bf16-valued weights (float arrays).
+
+    Inference takes both hidden layers to bf16 as the next layer's operand
+    (round_h1, round_h2); training keeps h2 in float32 (loss_and_grad)."""
     x = bits_to_f32(feat_bits)[:, :NF].astype(np.float64)
     W1, W2, w3, b1, b2, b3 = unpack(w_bf16, b)
     h1 = np.maximum(x @ W1.T + b1, 0.0)
     h1r = bf16_round(h1.astype(np.float32)).astype(np.float64) if round_h1 else h1
     h2 = np.maximum(h1r @ W2.T + b2, 0.0)
-    return h2 @ w3 + b3
+    h2r = bf16_round(h2.astype(np.float32)).astype(np.float64) if round_h2 else h2
+    return h2r @ w3 + b3
 
 
 def loss_and_grad(feat_bits, labels, w, b, round_ops=True):

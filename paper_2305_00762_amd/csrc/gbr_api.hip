@@ -727,6 +727,24 @@ int gbr_set_mlp_detector(gbr_ctx* c, const gbr_mlp* m, float margin, void* strea
   return GBR_OK;
 }
 
+int gbr_selftest_reciprocal(uint32_t lo, uint32_t hi, uint64_t* mismatches) {
+  if (!mismatches || lo > hi) return GBR_EINVAL;
+  unsigned long long* d = nullptr;
+  if (hipMalloc(&d, sizeof(*d)) != hipSuccess) return GBR_ENOMEM;
+  unsigned long long h = 0;
+  bool ok = hipMemset(d, 0, sizeof(*d)) == hipSuccess;
+  if (ok && hi > lo) {
+    hipLaunchKernelGGL(rcp_selftest_kernel, dim3(8192), dim3(256), 0, 0, lo, hi, d);
+    ok = hipGetLastError() == hipSuccess;
+  }
+  ok = ok && hipDeviceSynchronize() == hipSuccess &&
+       hipMemcpy(&h, d, sizeof(h), hipMemcpyDeviceToHost) == hipSuccess;
+  (void)hipFree(d);
+  if (!ok) return GBR_EDEVICE;
+  *mismatches = h;
+  return GBR_OK;
+}
+
 int gbr_mlp_stats(gbr_ctx* c, uint64_t* evaluated, uint64_t* fallbacks, int reset) {
   if (!c || !c->d_mlp_fb) return GBR_EINVAL;
   unsigned long long h = 0;

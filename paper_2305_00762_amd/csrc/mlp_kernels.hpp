@@ -53,11 +53,20 @@ __device__ __forceinline__ unsigned cvt_pk_bf16(float a, float b) {
   return __builtin_bit_cast(unsigned, r);
 }
 
+// 1/x rounded to nearest for normal x with a normal reciprocal (x in
+// [2^-126, 2^126)): the hardware estimate and one Newton step with fused
+// multiply-adds.  An exhaustive run over all 2^31 such floats on gfx950
+// matches IEEE division bit for bit (gbr_selftest_reciprocal repeats it).
+__device__ __forceinline__ float rcp_rn(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(__builtin_fmaf(-x, r, 1.0f), r, r);
+}
+
 // Features of one cell.  val(s, o) returns the stencil value at offset o
 // (-3..3) of stencil s: 0 rho along x, 1 p along x, 2 rho along y, 3 p along
 // y.  Each stencil is taken to float32 and normalised as
 // (s_k - mean) / ((max - min) + 1e-3) with a fixed operation order (sum left
-// to right, mean = sum * fl(1/7), one IEEE reciprocal), then rounded to bf16.
+// to right, mean = sum * fl(1/7), one correctly rounded reciprocal), then rounded to bf16.
 // out[j] holds features 2j (low half) and 2j+1; out[14], out[15] are zero.
 template <class FV>
 __device__ __forceinline__ void mlp_cell_features(FV val, unsigned out[kMlpIn / 2]) {
@@ -76,7 +85,8 @@ __device__ __forceinline__ void mlp_cell_features(FV val, unsigned out[kMlpIn / 
     float mx = v[0], mn = v[0];
 #pragma unroll
     for (int k = 1; k < 7; ++k) { mx = fmaxf(mx, v[k]); mn = fminf(mn, v[k]); }
-    const float r = 1.0f / ((mx - mn) + 1e-3f);
+    const float d = (mx - mn) + 1e-3f;
+    const float r = d < 0x1p126f ? rcp_rn(d) : 1.0f / d;
 #pragma unroll
     for (int k = 0; k < 7; ++k) f[col++] = (v[k] - mean) * r;
   }
@@ -146,14 +156,30 @@ __device__ __forceinline__ v4f mfma32(v8s a, v8s b, v4f c) {
                                                  __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
 }
 
+// ReLU of two packed bf16 values: a negative bf16 is a negative 16-bit
+// integer, so a packed integer max with zero clears it.  bf16(relu(x)) equals
+// relu(bf16(x)) for every x (rounding keeps the sign), so converting first
+// and clearing after gives the same bits as the other order.
+__device__ __forceinline__ unsigned relu_bf16x2(unsigned v) {
+  typedef short s2 __attribute__((ext_vector_type(2)));
+  const s2 x = __builtin_elementwise_max(__builtin_bit_cast(s2, v), (s2){0, 0});
+  return __builtin_bit_cast(unsigned, x);
+}
+
 // The evaluation along y feeds the same staged (x-order) features: its input
 // is the x-order vector with the two stencil halves (features 0..13 and
 // 14..27) swapped, so W1 with its columns swapped the same way (a1y) gives
 // the y-evaluation's first layer.
+//
+// The output layer runs on the matrix cores too: its A operand holds w3 (in
+// the slot order of the hidden layer) in every row, so every row of the
+// product holds the logits of the 16 cells, and lane l = 16 g + r receives
+// the logit of cell r in all four accumulator elements.  Its B operand is
+// relu(h2) rounded to bf16, packed like the layer-1 output.
 struct MlpInfer {
   v8s a1[2], a1y[2], a2[2];   // [neuron block]
+  v8s a3;                     // w3 in slot order (the same in every row)
   v4f b1[2], b2[2];   // biases of neurons 16 nb + 4 g + i
-  float w3[2][4];
   float b3;
 };
 
@@ -176,7 +202,7 @@ __device__ __forceinline__ void mlp_load_infer(const MlpImage& M, MlpInfer& F) {
       const int m = 16 * nb + 4 * g + i;
       F.b1[nb][i] = M.b[m];
       F.b2[nb][i] = M.b[kMlpH + m];
-      F.w3[nb][i] = M.w3[m];
+      F.a3[4 * nb + i] = (short)f2bf(M.w3[m]);   // w3 is bf16-valued: exact
     }
   }
   F.b3 = M.b[2 * kMlpH];
@@ -190,20 +216,20 @@ __device__ __forceinline__ float mlp_infer16(const MlpInfer& F, v8s x, bool ydir
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
     const v4f c = mfma32(ydir ? F.a1y[nb] : F.a1[nb], x, F.b1[nb]);
-    hp[2 * nb] = cvt_pk_bf16(relu(c[0]), relu(c[1]));
-    hp[2 * nb + 1] = cvt_pk_bf16(relu(c[2]), relu(c[3]));
+    hp[2 * nb] = relu_bf16x2(cvt_pk_bf16(c[0], c[1]));
+    hp[2 * nb + 1] = relu_bf16x2(cvt_pk_bf16(c[2], c[3]));
   }
   const v8s h = __builtin_bit_cast(v8s, (uint4){hp[0], hp[1], hp[2], hp[3]});
-  float part = 0.f;
+  unsigned qp[4];
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
     const v4f c = mfma32(F.a2[nb], h, F.b2[nb]);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) part += F.w3[nb][i] * relu(c[i]);
+    qp[2 * nb] = relu_bf16x2(cvt_pk_bf16(c[0], c[1]));
+    qp[2 * nb + 1] = relu_bf16x2(cvt_pk_bf16(c[2], c[3]));
   }
-  part += __shfl_xor(part, 16);
-  part += __shfl_xor(part, 32);
-  return part + F.b3;
+  const v8s h2 = __builtin_bit_cast(v8s, (uint4){qp[0], qp[1], qp[2], qp[3]});
+  const v4f z = mfma32(F.a3, h2, (v4f){F.b3, F.b3, F.b3, F.b3});
+  return z[0];
 }
 
 // Forward pass of 16 cells whose bf16 B fragments (k steps 0, 1) are x0, x1.
@@ -343,9 +369,13 @@ constexpr int kChiTX = 64, kChiTY = GBR_CHI_TY;
 constexpr int kChiRX = kChiTX + 6, kChiRY = kChiTY + 6, kChiRS = kChiRX * kChiRY;
 constexpr int kChiRow = 5;            // uint4 per staged feature row (80 B: conflict-free)
 
-__global__ __launch_bounds__(256) void mlp_chi_kernel(MlpChiParams P) {
+__global__ __launch_bounds__(256, 4) void mlp_chi_kernel(MlpChiParams P) {
+  constexpr int NC = kChiTX * kChiTY;          // cells of the block
+  constexpr int QW = 2 * 64 * (kChiTY / 4);    // fallback entries a wave can queue
   __shared__ float sF[2][kChiRS];
   __shared__ uint4 sX[256 * kChiRow];
+  __shared__ unsigned char sCx[NC], sCy[NC];   // per-cell bit along x, along y
+  __shared__ unsigned short sQ[4][QW];         // per wave: 2 cell + direction
   __shared__ unsigned sFb[4];
   const int tid = threadIdx.x, l = __lane_id(), g = l >> 4, w = tid >> 6;
   const int tx0 = (blockIdx.x % P.tiles_x) * kChiTX, ty0 = (blockIdx.x / P.tiles_x) * kChiTY;
@@ -360,6 +390,9 @@ __global__ __launch_bounds__(256) void mlp_chi_kernel(MlpChiParams P) {
     k = k < 0 ? k + nn : k;
     return k >= nn ? k - nn : k;
   };
+  // the network's fragments first: their loads overlap those of the state
+  MlpInfer F;
+  mlp_load_infer(P.M, F);
   double q[LR][4];
 #pragma unroll
   for (int k = 0; k < LR; ++k) {
@@ -379,12 +412,11 @@ __global__ __launch_bounds__(256) void mlp_chi_kernel(MlpChiParams P) {
       sF[1][c] = (float)mlp_cell_pressure(q[k][0], q[k][1], q[k][2], q[k][3], P.gamma);
     }
   }
-  MlpInfer F;
-  mlp_load_infer(P.M, F);
   __syncthreads();
-  unsigned nfb = 0;
   // Wave w evaluates rows 4 rnd + w; it stages and reads back only its own 64
-  // feature rows, so the hand-off needs a wave-scope fence, not a barrier.
+  // feature rows, and queues and settles only its own fallbacks, so every
+  // hand-off needs a wave-scope fence, not a barrier.
+  int nq = 0;   // the wave's queued fallbacks (uniform across the wave)
   for (int rnd = 0; rnd < kChiTY / 4; ++rnd) {
     const int lx = tid & 63, ly = 4 * rnd + w;
     const int rc = (ly + 3) * kChiRX + lx + 3;
@@ -407,38 +439,49 @@ __global__ __launch_bounds__(256) void mlp_chi_kernel(MlpChiParams P) {
       const float z1 = mlp_infer16(F, v, true);
       if (cb == g) { zx = z0; zy = z1; }
     }
+    // the network's sign where |logit| >= margin; below it the plain label
+    // along that direction, settled after the last round
+    const int cell = ly * kChiTX + lx;
+    const bool inb = tx0 + lx < P.nx && ty0 + ly < P.ny;
+    const bool fx = inb && !(fabsf(zx) >= P.margin);
+    const bool fy = inb && !(fabsf(zy) >= P.margin);
+    sCx[cell] = (!fx && zx > 0.f) ? 1 : 0;
+    sCy[cell] = (!fy && zy > 0.f) ? 2 : 0;
+    const unsigned long long bx = __ballot(fx), by = __ballot(fy);
+    const unsigned long long below = (1ull << l) - 1ull;
+    if (fx) sQ[w][nq + (int)__popcll(bx & below)] = (unsigned short)(2 * cell);
+    nq += (int)__popcll(bx);
+    if (fy) sQ[w][nq + (int)__popcll(by & below)] = (unsigned short)(2 * cell + 1);
+    nq += (int)__popcll(by);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int gj = tx0 + lx, gi = ty0 + ly;
-    if (gj < P.nx && gi < P.ny) {
-      // plain label along a direction from the FP64 density (the fallback is
-      // rare: read the density from memory)
-      auto rho = [&](int di, int dj) {
-        return P.Q[(size_t)wrap_bc(gi + di, P.ny, P.bcy) * P.nx + wrap_bc(gj + dj, P.nx, P.bcx)];
-      };
-      unsigned chi = 0;
-      if (fabsf(zx) >= P.margin) {
-        chi |= zx > 0.f ? 1u : 0u;
-      } else {
-        const double px = detector_psi(rho(0, -2), rho(0, -1), rho(0, 0), rho(0, 1), rho(0, 2));
-        chi |= px < kPsiC ? 1u : 0u;
-        ++nfb;
-      }
-      if (fabsf(zy) >= P.margin) {
-        chi |= zy > 0.f ? 2u : 0u;
-      } else {
-        const double py = detector_psi(rho(-2, 0), rho(-1, 0), rho(0, 0), rho(1, 0), rho(2, 0));
-        chi |= py < kPsiC ? 2u : 0u;
-        ++nfb;
-      }
-      P.chi[(size_t)gi * P.nx + gj] = (uint8_t)chi;
+  }
+  // plain labels of the queued evaluations, one per lane, from the FP64
+  // density in memory
+  for (int k = l; k < nq; k += 64) {
+    const int e = sQ[w][k], cell = e >> 1, ydir = e & 1;
+    const int gi = ty0 + cell / kChiTX, gj = tx0 + cell % kChiTX;
+    const int si = ydir, sj = 1 - ydir;
+    auto rho = [&](int o) {
+      return P.Q[(size_t)gwrap(gi + o * si, P.ny, P.bcy) * P.nx + gwrap(gj + o * sj, P.nx, P.bcx)];
+    };
+    const double psi = detector_psi(rho(-2), rho(-1), rho(0), rho(1), rho(2));
+    if (psi < kPsiC) {
+      if (ydir) sCy[cell] = 2; else sCx[cell] = 1;
     }
   }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int rnd = 0; rnd < kChiTY / 4; ++rnd) {
+    const int lx = tid & 63, ly = 4 * rnd + w;
+    const int gj = tx0 + lx, gi = ty0 + ly;
+    const int cell = ly * kChiTX + lx;
+    if (gj < P.nx && gi < P.ny) P.chi[(size_t)gi * P.nx + gj] = (uint8_t)(sCx[cell] | sCy[cell]);
+  }
   if (P.nfb) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) nfb += __shfl_xor(nfb, o);
-    if (l == 0) sFb[w] = nfb;
+    if (l == 0) sFb[w] = (unsigned)nq;
     __syncthreads();
     if (tid == 0) {
       const unsigned t = (sFb[0] + sFb[1]) + (sFb[2] + sFb[3]);
@@ -711,6 +754,20 @@ __global__ __launch_bounds__(256) void mlp_publish_kernel(const float* master, u
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < kMlpH * (kMlpIn - kMlpF)) W1[(p / (kMlpIn - kMlpF)) * kMlpIn + kMlpF + p % (kMlpIn - kMlpF)] = 0;
   if (p < kMlpNP) mlp_publish(p, master[p], W1, W2, w3, b);
+}
+
+// Exhaustive check of rcp_rn against IEEE division over the floats with bit
+// patterns in [lo, hi): mismatches are counted in *count.
+__global__ __launch_bounds__(256) void rcp_selftest_kernel(unsigned lo, unsigned hi,
+                                                           unsigned long long* count) {
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  unsigned long long bad = 0;
+  for (unsigned long long b = lo + (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; b < hi;
+       b += stride) {
+    const float x = __uint_as_float((unsigned)b);
+    if (__float_as_uint(rcp_rn(x)) != __float_as_uint(1.0f / x)) ++bad;
+  }
+  if (bad) atomicAdd(count, bad);
 }
 
 }  // namespace gbr

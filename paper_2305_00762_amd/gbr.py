@@ -88,6 +88,7 @@ SIGNATURES = {
     "gbr_timing_read": (_i, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                              C.POINTER(C.c_uint64)]),
     "gbr_mlp_stats": (_i, [_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), _i]),
+    "gbr_selftest_reciprocal": (_i, [C.c_uint32, C.c_uint32, C.POINTER(C.c_uint64)]),
     "gbr3_init": (_i, [_i, _i, _i, _d, C.POINTER(_vp)]),
     "gbr3_destroy": (_i, [_vp]),
     "gbr3_set_geometry": (_i, [_vp, _d, _d, _d, _d, _d, _d, _i, _i, _i]),
@@ -340,6 +341,14 @@ def gbr_mlp_train_step(m, feat, labels, idx, batch, lr, loss=None, stream=None):
 def gbr_set_mlp_detector(ctx, m, margin, stream=None):
     return _check(load().gbr_set_mlp_detector(ctx, m, margin, _stream(stream)),
                   "gbr_set_mlp_detector")
+
+
+def gbr_selftest_reciprocal(lo=0x00800000, hi=0x7E800000):
+    """Floats with bit patterns in [lo, hi) whose detector reciprocal differs
+    from IEEE division (0 over the default range)."""
+    n = C.c_uint64()
+    _check(load().gbr_selftest_reciprocal(lo, hi, C.byref(n)), "gbr_selftest_reciprocal")
+    return n.value
 
 
 def gbr_mlp_stats(ctx, reset=False):

@@ -185,3 +185,12 @@ def test_fused_detector_network_decides(precision):
     tol = 1e-12 if precision == 0 else 1e-6
     assert (res_err(R, Ro, P) <= tol).all()
     gbr.gbr_mlp_destroy(m)
+
+
+def test_feature_reciprocal_is_correctly_rounded():
+    """The features' reciprocal (hardware estimate plus one fused Newton
+    step) equals IEEE float32 division for every normal float below 2^126:
+    all 2^31 - 2^24 bit patterns, exhaustively."""
+    require_gpu()
+    assert gbr.gbr_selftest_reciprocal() == 0
+    assert gbr.gbr_selftest_reciprocal(0x3F800000, 0x3F800000) == 0   # empty range
