@@ -194,3 +194,27 @@ def test_feature_reciprocal_is_correctly_rounded():
     require_gpu()
     assert gbr.gbr_selftest_reciprocal() == 0
     assert gbr.gbr_selftest_reciprocal(0x3F800000, 0x3F800000) == 0   # empty range
+
+
+@pytest.mark.parametrize("fam,seed", [("riemann", 5000), ("shear", 5001)])
+def test_trained_detector_full_size_4096(fam, seed):
+    """The learned detector's evaluation workloads at full size (4096^2,
+    fresh seeds), with the shipped weights and default margin, through the
+    fused FP32-bulk residual as the bench launches it: the residual equals the
+    oracle's with the GPU's interface flags to the FP32-bulk bar, and those
+    flags are the plain method's wherever the network decides (the trained
+    network's quality bar: no more than 1e-4 of the interfaces differ)."""
+    from paper_2305_00762_amd import detector as D
+    m = D.load()
+    P = PB.make(fam, 4096, seed=seed)
+    R, sx, sy, ev, fb = fused(P, m, D.DEFAULT_MARGIN, gbr.GBR_PREC_FP32_BULK)
+    Ro = O.residual_sigma(ocfg(P), P.Q, sx, sy)
+    e = res_err(R, Ro, P)
+    _, ex, ey, _ = O.residual(ocfg(P), P.Q, want_flags=True)
+    mism = int((sx != ex).sum() + (sy != ey).sum())
+    report(f"trained detector {fam}4096", res_err=e.max(), flag_mismatch_vs_plain=mism,
+           fallback=fb / max(ev, 1))
+    assert ev == 2 * P.nx * P.ny
+    assert (e <= 1e-6).all(), e
+    assert mism <= 1e-4 * (sx.size + sy.size)
+    gbr.gbr_mlp_destroy(m)
