@@ -147,3 +147,41 @@ def test_batch_autotune_and_argument_errors():
                            gbr.GBR_PREC_FP64)                              # nx < 12
     with pytest.raises(gbr.GbrError):
         gbr.gbr_batch_init([64], [64], [[0, 1, 0, 1]], [[0, 0]], [1.4], [0.0], [0.72], [0.2], 7)
+
+
+def test_batch512_full_size():
+    """The batched workload at full size -- 512 grids of sides U{64..768}
+    (about 1.1e8 cells), FP32 bulk, autotuned launch form, steps replayed as a
+    graph, as the bench runs it: no bad state, and the four smallest grids
+    agree with the CPU oracle after two steps to the FP32-bulk trajectory bar
+    (L1 <= 1e-6 per conserved variable)."""
+    torch = require_gpu()
+    from paper_2305_00762_amd.solver import BatchSolver
+    ps = [PB.vortex(n, cfl=0.5) if fam == "vortex" else PB.make(fam, n, seed=sd)
+          for fam, n, sd in PB.batch_spec(512, seed=0)]
+    small = sorted(range(len(ps)), key=lambda k: ps[k].nx * ps[k].ny)[:4]
+    init = {k: np.ascontiguousarray(ps[k].Q.copy()) for k in small}
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        B = BatchSolver(ps, precision=gbr.GBR_PREC_FP32_BULK, stream=s)
+    s.synchronize()
+    for P in ps:
+        P.Q = None                      # the oracle starts from the saved copies
+    # autotuning times first stages into a scratch set; the state stays
+    form, tx, ty, total, wg = gbr.gbr_batch_autotune(B.b, 2, s)
+    with torch.cuda.stream(s):
+        B.step()
+        B.step()
+    s.synchronize()
+    assert B.check() == gbr.GBR_OK
+    st = B.states()
+    for k in small:
+        P = ps[k]
+        Q = init[k].copy()
+        cfg = ocfg(P)
+        O.step(cfg, Q, P.cfl)
+        O.step(cfg, Q, P.cfl)
+        l1 = np.abs(st[k].cpu().numpy() - Q).reshape(4, -1).mean(axis=1)
+        report(f"batch512 grid {k} ({P.family} {P.nx})", form=form, L1=l1.max())
+        assert (l1 <= 1e-6).all(), (k, l1)
+    B.close()
