@@ -378,7 +378,11 @@ __global__ __launch_bounds__(256, 4) void mlp_chi_kernel(MlpChiParams P) {
   __shared__ unsigned short sQ[4][QW];         // per wave: 2 cell + direction
   __shared__ unsigned sFb[4];
   const int tid = threadIdx.x, l = __lane_id(), g = l >> 4, w = tid >> 6;
-  const int tx0 = (blockIdx.x % P.tiles_x) * kChiTX, ty0 = (blockIdx.x / P.tiles_x) * kChiTY;
+  // workgroups are dealt to the 8 XCDs round-robin: give each XCD one
+  // contiguous run of blocks, so neighbouring blocks share halo rows in its L2
+  const int xcd = blockIdx.x & 7, per = gridDim.x >> 3, rem = gridDim.x & 7;
+  const int blk = xcd * per + (xcd < rem ? xcd : rem) + (blockIdx.x >> 3);
+  const int tx0 = (blk % P.tiles_x) * kChiTX, ty0 = (blk / P.tiles_x) * kChiTY;
   const size_t n = (size_t)P.nx * P.ny;
   constexpr int LR = (kChiRS + 255) / 256;
   // ghost cells: on grids of at least one block plus halo a single wrap (or
