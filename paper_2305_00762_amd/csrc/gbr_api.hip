@@ -573,9 +573,7 @@ int gbr_compute_dt(gbr_ctx* c, const double* Q, double cfl, double* dt_dev, void
   P.nx = c->nx; P.ny = c->ny;
   P.dx = (c->x1 - c->x0) / c->nx; P.dy = (c->y1 - c->y0) / c->ny;
   P.gamma = c->gamma; P.mu = c->mu; P.cfl = cfl;
-  const size_t n = (size_t)c->nx * c->ny;
-  size_t want = (n + kDtThreads - 1) / kDtThreads;
-  const int blocks = (int)(want < (size_t)kDtBlocks ? want : (size_t)kDtBlocks);
+  const int blocks = dt_blocks((size_t)c->nx * c->ny);
   hipLaunchKernelGGL(dt_reduce_kernel, dim3(blocks), dim3(kDtThreads), 0, s, P);
   hipLaunchKernelGGL(dt_finish_kernel, dim3(1), dim3(kDtThreads), 0, s, c->d_partial, blocks,
                      dt_dev, cfl, c->d_status);
@@ -1301,9 +1299,7 @@ int gbr3_compute_dt(gbr3_ctx* c, const double* Q, double cfl, double* dt_dev, vo
   P.dy = (c->hi[1] - c->lo[1]) / c->n[1];
   P.dz = (c->hi[2] - c->lo[2]) / c->n[2];
   P.gamma = c->gamma;
-  const size_t n = (size_t)c->n[0] * c->n[1] * c->n[2];
-  size_t want = (n + kDtThreads - 1) / kDtThreads;
-  const int blocks = (int)(want < (size_t)kDtBlocks ? want : (size_t)kDtBlocks);
+  const int blocks = dt_blocks((size_t)c->n[0] * c->n[1] * c->n[2]);
   hipLaunchKernelGGL(dt3_reduce_kernel, dim3(blocks), dim3(kDtThreads), 0, s, P);
   hipLaunchKernelGGL(dt_finish_kernel, dim3(1), dim3(kDtThreads), 0, s, c->d_partial, blocks,
                      dt_dev, cfl, c->d_status);
