@@ -126,6 +126,37 @@ def load_traffic(kernel, workload):
     return None
 
 
+# VALU issue peak of the chip: 256 CUs x 4 SIMDs, each issuing one wave64
+# VALU instruction per 4 cycles (16 lanes per cycle), at 2.4 GHz -- the FP64
+# vector peak (78.6 TFLOP/s) counted in lane operations (one FMA each).
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def load_valu(kernel_prefix, workload):
+    """VALU wave-instructions per launch of a stage kernel from the committed
+    rocprofv3 SQ-counter summary, if any (its SQ_INSTS_VALU line)."""
+    path = os.path.join(ROOT, "profiles", f"meg7_stage_kernels_{workload}_sq_counters.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        f = line.split()
+        if len(f) >= 4 and f[0] == kernel_prefix and f[1] == "SQ_INSTS_VALU" and f[2] == "mean":
+            return float(f[3])
+    return None
+
+
+def valu_roofline(kernel, workload, avg_us):
+    prefix = {"meg7_stage_kernel_f32<mlp>": "meg7_stage_kernel_f32",
+              "meg7_stage_kernel": "meg7_stage_kernel<"}.get(kernel)
+    instr = load_valu(prefix, workload) if prefix else None
+    if instr is None:
+        return None
+    achieved = instr * 64 / (avg_us * 1e-6)
+    return {"bound": "alu", "achieved": achieved / 1e9, "peak": VALU_PEAK_LANE_OPS / 1e9,
+            "unit": "G lane-op/s (issued)", "frac": achieved / VALU_PEAK_LANE_OPS,
+            "valu_wave_instructions_per_launch": instr}
+
+
 class Path:
     """One configured context and its three state buffers."""
 
@@ -637,6 +668,11 @@ def main():
             "avg_launch_us": stage_ms * 1e3 / max(launches, 1),
             "bytes_per_cell_stage": 256.0 / 3.0,
         },
+        # the same kernel against the VALU issue roofline (its intensity, ~1500
+        # lane-operations per 85 B, lies far right of the ridge): issued lane
+        # operations (SQ_INSTS_VALU x 64, from the committed counter summary)
+        # over the live launch duration
+        "roofline_valu": valu_roofline(head.kernel, a.workload, stage_ms * 1e3 / max(launches, 1)),
         "ms_per_step_with_kernel_events": ev_ms / steps,
         "kernels_us_per_launch": {"stage": stage_ms * 1e3 / max(launches, 1),
                                   "detector_flag_map": (det_ms * 1e3 / max(launches, 1)
