@@ -352,7 +352,8 @@ __global__ __launch_bounds__(256) void mlp_features_kernel(MlpFeatParams P) {
 // rounds of 256 cells each compute their features (one cell per thread),
 // stage them as bf16 rows and run the network on the matrix cores; a wave
 // evaluates exactly its own 64 cells, so the logit of lane l's cell lands in
-// lane l and the byte store is coalesced.
+// lane l.  Evaluations below the margin are queued per wave and settled after
+// the last round; the flag bytes are then stored coalesced, one row per wave.
 struct MlpChiParams {
   const double* Q;
   uint8_t* chi;                 // [ny][nx]: bit 0 chi^x, bit 1 chi^y
