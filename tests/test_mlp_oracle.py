@@ -7,7 +7,9 @@
   error of the exact one;
 * one Adam step equals torch.optim.Adam's;
 * features: the free stream gives zeros; a density step gives the closed
-  form (k - 3 + ...)/(H + 1e-3) pattern; padding is zero.
+  form (k - 3 + ...)/(H + 1e-3) pattern; padding is zero;
+* inference: without the h2 rounding it is the training forward pass; the
+  h2 rounding moves a logit by no more than its bf16 bound.
 """
 import numpy as np
 import pytest
@@ -137,3 +139,27 @@ def test_directional_labels_reproduce_the_method_flags(fam, bc):
     assert (ex == sx).all() and (ey == sy).all()
     if fam == "riemann":
         assert sx.min() == 0 and sy.min() == 0     # the case does flag
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_inference_forward_rounding_points(seed):
+    """Inference takes h1 and h2 to bf16 as matrix-unit operands: without the
+    h2 rounding its logits are the training forward pass's (same loss), and
+    with it they move by no more than the bf16 bound sum_n |w3_n| h2_n 2^-9 --
+    and do move."""
+    feat, labels, w, b = _data(seed, B=256)
+    wq = M.bf16_round(w)
+    z0 = M.forward(feat, wq, b, round_h2=False)
+    loss, _, _ = M.loss_and_grad(feat, labels, w, b, round_ops=True)
+    y = labels.astype(np.float64)
+    assert np.isclose(np.mean(np.logaddexp(0.0, z0) - y * z0), loss, rtol=1e-13, atol=0)
+    z1 = M.forward(feat, wq, b)
+    # h2 of the same pass, computed here from its definition
+    x = M.bits_to_f32(feat)[:, :M.NF].astype(np.float64)
+    W1, W2, w3, b1, b2, _ = M.unpack(wq, b)
+    h1 = M.bf16_round(np.maximum(x @ W1.T + b1, 0.0).astype(np.float32)).astype(np.float64)
+    h2 = np.maximum(h1 @ W2.T + b2, 0.0)
+    # bf16 unit roundoff 2^-9, plus the float32 step before it and FP64 sums
+    bound = (np.abs(w3) * h2).sum(axis=1) * 2.0 ** -9 * (1 + 2.0 ** -14)
+    assert (np.abs(z1 - z0) <= bound).all()
+    assert (z1 != z0).any()
