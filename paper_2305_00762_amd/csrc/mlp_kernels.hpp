@@ -161,6 +161,9 @@ __device__ __forceinline__ v4f mfma32(v8s a, v8s b, v4f c) {
 // relu(bf16(x)) for every x (rounding keeps the sign), so converting first
 // and clearing after gives the same bits as the other order.
 __device__ __forceinline__ unsigned relu_bf16x2(unsigned v) {
+  // an empty asm keeps the packed conversion that produced v whole: without
+  // it the compiler splits the conversion into two single ones and a permute
+  asm("" : "+v"(v));
   typedef short s2 __attribute__((ext_vector_type(2)));
   const s2 x = __builtin_elementwise_max(__builtin_bit_cast(s2, v), (s2){0, 0});
   return __builtin_bit_cast(unsigned, x);
