@@ -55,8 +55,9 @@ __device__ __forceinline__ unsigned cvt_pk_bf16(float a, float b) {
 
 // 1/x rounded to nearest for normal x with a normal reciprocal (x in
 // [2^-126, 2^126)): the hardware estimate and one Newton step with fused
-// multiply-adds.  An exhaustive run over all 2^31 such floats on gfx950
-// matches IEEE division bit for bit (gbr_selftest_reciprocal repeats it).
+// multiply-adds.  An exhaustive run over all such floats (2^31 - 2^24 of
+// them) on gfx950 matches IEEE division bit for bit (gbr_selftest_reciprocal
+// repeats it).
 __device__ __forceinline__ float rcp_rn(float x) {
   const float r = __builtin_amdgcn_rcpf(x);
   return __builtin_fmaf(__builtin_fmaf(-x, r, 1.0f), r, r);
@@ -144,12 +145,6 @@ __device__ __forceinline__ void mlp_load_frags(const MlpImage& M, MlpFrags& F) {
 // registers.  The biases initialise the accumulators.
 typedef short v8s __attribute__((ext_vector_type(8)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
-
-// max(x, 0) on the bit pattern: negative floats are negative integers, so one
-// integer max (no NaN canonicalisation of the float max in IEEE mode).
-__device__ __forceinline__ float relu(float x) {
-  return __int_as_float(max(__float_as_int(x), 0));
-}
 
 __device__ __forceinline__ v4f mfma32(v8s a, v8s b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
