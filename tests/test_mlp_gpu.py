@@ -218,3 +218,35 @@ def test_trained_detector_full_size_4096(fam, seed):
     assert (e <= 1e-6).all(), e
     assert mism <= 1e-4 * (sx.size + sy.size)
     gbr.gbr_mlp_destroy(m)
+
+
+@pytest.mark.parametrize("tiling", [2, 3])
+@pytest.mark.parametrize("margin", [1e30, 0.0])
+def test_fused_detector_other_tilings(tiling, margin):
+    """The FP32-bulk kernels with the learned detector on the 63x7 and 30x15
+    tiles: all evaluations falling back give the plain method's flags; with
+    the network deciding, the residual equals the oracle's given the GPU's
+    flags (FP32-bulk bar)."""
+    from paper_2305_00762_amd.solver import Solver
+    torch = require_gpu()
+    m, w, b = make_net(6)
+    P = PB.riemann(90, seed=8, ny=70)
+    S = Solver(P, export_flags=True, precision=gbr.GBR_PREC_FP32_BULK)
+    gbr.gbr_set_mlp_detector(S.ctx, m, margin)
+    gbr.gbr_set_scheme(S.ctx, gbr.GBR_RECON_PRIM, gbr.GBR_MP_FLAGGED, gbr.GBR_PREC_FP32_BULK,
+                       gbr.GBR_DET_MLP)
+    gbr.gbr_set_tiling(S.ctx, tiling)
+    assert gbr.gbr_get_tiling(S.ctx)[0] == tiling
+    R = S.residual()
+    torch.cuda.synchronize()
+    sx, sy = S.flags()
+    R = R.cpu().numpy()
+    S.close()
+    if margin > 1e20:
+        _, ex, ey, _ = O.residual(ocfg(P), P.Q, want_flags=True)
+        assert (sx == ex).all() and (sy == ey).all()
+    Ro = O.residual_sigma(ocfg(P), P.Q, sx, sy)
+    e = res_err(R, Ro, P)
+    report(f"fused tiling {tiling} margin {margin:g}", res_err=e.max())
+    assert (e <= 1e-6).all(), e
+    gbr.gbr_mlp_destroy(m)
