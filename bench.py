@@ -132,6 +132,17 @@ def load_traffic(kernel, workload):
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
+def cpu_model():
+    """The host CPU's model name (for the cpu_baseline record), if known."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def load_valu(kernel_prefix, workload):
     """VALU wave-instructions per launch of a stage kernel from the committed
     rocprofv3 SQ-counter summary, if any (its SQ_INSTS_VALU line)."""
@@ -309,7 +320,7 @@ def cpu_baseline(P, seconds, max_steps=50, recon=0, order=7, mp_mode=0):
         if el >= seconds or steps >= max_steps:
             break
     cells = P.nx * P.ny * 3 * steps
-    rec = {"value": cells / el, "unit": "cell-stage updates/s", "cores": O.threads(),
+    rec = {"value": cells / el, "unit": "cell-stage updates/s", "cores": O.threads(), "cpu": cpu_model(),
            "kind": "oracle",
            "sample": f"{steps} whole SSP-RK3 steps of the same workload from its initial "
                      f"state ({cells} cell-stages) in {el:.1f} s"}
@@ -466,7 +477,7 @@ def bench_3d(a, n):
             k += 1
         el = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": cells * 3 * k / el, "unit": "cell-stage updates/s",
-                               "cores": O.threads(), "kind": "oracle",
+                               "cores": O.threads(), "cpu": cpu_model(), "kind": "oracle",
                                "sample": f"{k} whole SSP-RK3 steps of the same workload from its "
                                          f"initial state ({cells * 3 * k} cell-stages) in {el:.1f} s"}
         with torch.cuda.stream(s):
@@ -572,7 +583,7 @@ def bench_batch(a, steps):
             errs.append({"grid": k, "family": P.family, "n": P.nx, "L1": d.mean(1).tolist(),
                          "Linf": d.max(1).tolist()})
         out["cpu_baseline"] = {"value": cs / t_cpu, "unit": "cell-stage updates/s",
-                               "cores": O.threads(), "kind": "oracle",
+                               "cores": O.threads(), "cpu": cpu_model(), "kind": "oracle",
                                "sample": f"the {len(small)} smallest grids of the batch, {done} "
                                          f"whole steps each ({cs} cell-stages) in {t_cpu:.1f} s"}
         out["error_vs_oracle"] = {"after_steps": done, "grids": errs}
