@@ -588,21 +588,23 @@ void orc_char_cons_state(const double Qa[4], const double Qb[4], double gamma, o
     s->b2 = 0.5 * s->b1 * (s->ub * s->ub + s->vb * s->vb);
 }
 
-/* Flux through one interface (rotated frame). Returns sigma in *sig_out. */
-static void line_flux(const orc_line *L, const orc_cfg *c, double Fout[4], int *sig_out,
-                      int *nlimited, int sig_given)
+/* Mean density and sound speed of reading R-CHAR at interface j+1/2, from
+ * the primitive states (rho, un, ut, p) of cells j and j+1. */
+static void char_prim_state(const double Wa[4], const double Wb[4], double gamma, double *rb,
+                            double *cb)
+{
+    *rb = 0.5 * (Wa[0] + Wb[0]);
+    double pb = 0.5 * (Wa[3] + Wb[3]);
+    *cb = sqrt(gamma * pb / *rb);
+}
+
+/* Interface states (rotated primitives) at j+1/2 before the Riemann solver:
+ * use_mp = 0 the unlimited GRB states (Sec. 2.2), use_mp = 1 the MEG7 states
+ * in characteristic variables (Sec. 2.3; R-CHAR, or R-CHARC for MEG7-cons). */
+static void interface_states(const orc_line *L, const orc_cfg *c, int use_mp, double WL[4],
+                             double WR[4], int *nlimited)
 {
     const double gamma = c->gamma;
-    /* eq. (buffer): psi_{j+1/2} = min(psi_{j-2..j+3}); sigma = 0 iff < psi_c */
-    double pmin = L->psi[0];
-    for (int k = 1; k < 6; ++k) pmin = fmin(pmin, L->psi[k]);
-    int sigma = (pmin < PSI_C) ? 0 : 1;
-    if (c->force_sigma == 0 || c->force_sigma == 1) sigma = c->force_sigma;
-    if (sig_given == 0 || sig_given == 1) sigma = sig_given;
-    *sig_out = sigma;
-
-    double WL[4], WR[4], FL[4], FR[4];
-    int use_mp = (sigma == 0) || (c->mp_mode == 1);
     if (c->recon == 1 && !use_mp) {
         /* MEG7-cons, Sec. 2.2: unlimited GRB states on conservative variables */
         double QL[4], QR[4];
@@ -645,9 +647,9 @@ static void line_flux(const orc_line *L, const orc_cfg *c, double Fout[4], int *
         }
     } else {
         /* Sec. 2.3: MEG7 in characteristic variables (R-CHAR) */
-        double rb = 0.5 * (L->W[0][4] + L->W[0][5]);
-        double pb = 0.5 * (L->W[3][4] + L->W[3][5]);
-        double cb = sqrt(gamma * pb / rb);
+        double wa[4], wb[4], rb, cb;
+        for (int m = 0; m < 4; ++m) { wa[m] = L->W[m][4]; wb[m] = L->W[m][5]; }
+        char_prim_state(wa, wb, gamma, &rb, &cb);
         double cw[4][6], cg[4][6];
         for (int k = 0; k < 6; ++k) {
             double u[4], w[4], g[4], wg[4];
@@ -666,6 +668,24 @@ static void line_flux(const orc_line *L, const orc_cfg *c, double Fout[4], int *
         char_bwd(wl, rb, cb, WL);
         char_bwd(wr, rb, cb, WR);
     }
+}
+
+/* Flux through one interface (rotated frame). Returns sigma in *sig_out. */
+static void line_flux(const orc_line *L, const orc_cfg *c, double Fout[4], int *sig_out,
+                      int *nlimited, int sig_given)
+{
+    const double gamma = c->gamma;
+    /* eq. (buffer): psi_{j+1/2} = min(psi_{j-2..j+3}); sigma = 0 iff < psi_c */
+    double pmin = L->psi[0];
+    for (int k = 1; k < 6; ++k) pmin = fmin(pmin, L->psi[k]);
+    int sigma = (pmin < PSI_C) ? 0 : 1;
+    if (c->force_sigma == 0 || c->force_sigma == 1) sigma = c->force_sigma;
+    if (sig_given == 0 || sig_given == 1) sigma = sig_given;
+    *sig_out = sigma;
+
+    double WL[4], WR[4], FL[4], FR[4];
+    int use_mp = (sigma == 0) || (c->mp_mode == 1);
+    interface_states(L, c, use_mp, WL, WR, nlimited);
     if (sigma == 1) {
         /* eqs. (flux-full), (flux-right) on f = F^c(U) at cell centres */
         double f[4][10];
@@ -1169,6 +1189,40 @@ void orc_line_flux(const double *W40, const double *G24, const double *T2, const
     for (int k = 0; k < 6; ++k) L.psi[k] = psi6[k];
     L.dn = dn;
     line_flux(&L, c, F, sigma, NULL, -1);
+}
+
+/* Test export: the interface states line_flux hands to the Riemann solver
+ * for sigma = 0 (MEG7 characteristic states) or sigma = 1 (GRB states), from
+ * W/G arrays as in orc_line (primitive reconstruction), before the
+ * positivity fallback of R-POS. */
+void orc_interface_states(const double *W40, const double *G24, const orc_cfg *c, int sigma,
+                          double WL[4], double WR[4])
+{
+    orc_line L;
+    memset(&L, 0, sizeof(L));
+    for (int m = 0; m < 4; ++m) {
+        for (int k = 0; k < 10; ++k) L.W[m][k] = W40[m * 10 + k];
+        for (int k = 0; k < 6; ++k) L.G[m][k] = G24[m * 6 + k];
+    }
+    interface_states(&L, c, sigma == 0 || c->mp_mode == 1, WL, WR, NULL);
+}
+
+/* Test export: the characteristic projection of R-CHAR at the interface
+ * between the rotated primitive states Wa, Wb, as 4x4 matrices (row-major):
+ * Lm maps primitives to characteristic variables, Rm back. */
+void orc_char_prim(const double Wa[4], const double Wb[4], double gamma, double Lm[16],
+                   double Rm[16])
+{
+    double rb, cb;
+    char_prim_state(Wa, Wb, gamma, &rb, &cb);
+    for (int k = 0; k < 4; ++k) {
+        double e[4] = {0.0, 0.0, 0.0, 0.0}, o[4];
+        e[k] = 1.0;
+        char_fwd(e, rb, cb, o);
+        for (int m = 0; m < 4; ++m) Lm[m * 4 + k] = o[m];
+        char_bwd(e, rb, cb, o);
+        for (int m = 0; m < 4; ++m) Rm[m * 4 + k] = o[m];
+    }
 }
 
 /* Plain detector flags chi = [psi_x < psi_c or psi_y < psi_c] per cell

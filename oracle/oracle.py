@@ -129,6 +129,10 @@ def lib():
         L.orc_char_cons_fwd.argtypes = [C.POINTER(OrcCState), dp, dp]
         L.orc_char_cons_bwd.restype = None
         L.orc_char_cons_bwd.argtypes = [C.POINTER(OrcCState), dp, dp]
+        L.orc_interface_states.restype = None
+        L.orc_interface_states.argtypes = [dp, dp, C.POINTER(OrcCfg), C.c_int, dp, dp]
+        L.orc_char_prim.restype = None
+        L.orc_char_prim.argtypes = [dp, dp, C.c_double, dp, dp]
         _lib = L
     return _lib
 
@@ -319,6 +323,28 @@ def char_cons(Qa, Qb, gamma=1.4):
         lib().orc_char_cons_bwd(C.byref(st), e, out)
         Rm[:, k] = out
     return Lm, Rm
+
+
+def interface_states(W40, G24, sigma, gamma=1.4, order=7, mp_mode=0):
+    """(WL, WR): the rotated primitive states at interface j+1/2 that the
+    Riemann solver receives, sigma = 1 the GRB states (Sec. 2.2), sigma = 0
+    the MEG7 characteristic states (Sec. 2.3), from W [4][10] (offsets -4..5)
+    and spacing-scaled gradients G [4][6] (offsets -2..3)."""
+    cfg = make_cfg(16, 16, gamma=gamma, order=order, mp_mode=mp_mode)
+    WL, WR = np.zeros(4), np.zeros(4)
+    lib().orc_interface_states(np.ascontiguousarray(W40, np.float64).reshape(40),
+                               np.ascontiguousarray(G24, np.float64).reshape(24),
+                               C.byref(cfg), int(sigma), WL, WR)
+    return WL, WR
+
+
+def char_prim(Wa, Wb, gamma=1.4):
+    """(L, R): the primitive characteristic projection (reading R-CHAR) at the
+    interface between rotated primitive states Wa, Wb, as 4x4 matrices."""
+    Lm, Rm = np.zeros(16), np.zeros(16)
+    lib().orc_char_prim(np.ascontiguousarray(Wa, np.float64), np.ascontiguousarray(Wb, np.float64),
+                        gamma, Lm, Rm)
+    return Lm.reshape(4, 4), Rm.reshape(4, 4)
 
 
 # ---------------------------------------------------------------- 3D ---

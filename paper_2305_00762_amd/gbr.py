@@ -1,9 +1,16 @@
 """ctypes binding of libgbr.so (argument marshalling only).
 
 Every function forwards to the C entry point of the same name declared in
-include/gbr.h.  Device arrays are passed as torch tensors (float64, CUDA/HIP
-device, contiguous, [4][ny][nx]) or as raw integer device addresses; streams
-as torch.cuda.Stream, a raw hipStream_t integer, or None (current stream).
+include/gbr.h.  Device arrays are passed as torch tensors on the HIP device,
+or as raw integer device addresses (taken as given); streams as
+torch.cuda.Stream, a raw hipStream_t integer, or None (current stream).
+Before any call is made, a tensor argument is checked against what the
+entry point reads or writes: on the device, contiguous, of the element type
+and at least the size the call accesses (state arrays: exactly the
+context's [4][ny][nx] or [5][nz][ny][nx]).  A host array (numpy or a CPU
+tensor) is accepted only where the header allows host memory (flag export,
+MLP parameters, the batch tables).  A violation raises GbrError(GBR_EINVAL)
+and nothing is enqueued.
 The library must be built (``python -m paper_2305_00762_amd.build`` or
 ``__graft_entry__.build()``); there is no fallback: a missing library is an
 error.
@@ -157,6 +164,68 @@ def _addr(x):
     raise TypeError(f"cannot take the address of {type(x)}")
 
 
+# grid sizes of live contexts, for the size checks: handle -> (nx, ny[, nz])
+_dims = {}
+
+
+def _bad(where, what):
+    raise GbrError(GBR_EINVAL, f"{where}: {what}")
+
+
+def _dev(x, where, name, dtypes, numel, exact=False, optional=False, host_ok=False):
+    """Address of argument x after checking it against the call: a torch
+    tensor on the HIP device (or, with host_ok, a host array), contiguous, of
+    one of the element types `dtypes` (names, e.g. "float64"), with numel
+    elements (at least numel unless exact).  Raw integers pass unchecked."""
+    if x is None:
+        if optional:
+            return None
+        _bad(where, f"{name} is required")
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        if not x.is_cuda and not host_ok:
+            _bad(where, f"{name} must be a device tensor (got a host tensor)")
+        if not x.is_contiguous():
+            _bad(where, f"{name} must be contiguous")
+        dt = str(x.dtype).replace("torch.", "")
+        n = x.numel()
+    elif hasattr(x, "ctypes") and hasattr(x, "dtype"):
+        if not host_ok:
+            _bad(where, f"{name} must be device memory (got a host array)")
+        if not x.flags.c_contiguous:
+            _bad(where, f"{name} must be contiguous")
+        dt = str(x.dtype)
+        n = x.size
+    else:
+        raise TypeError(f"{where}: cannot take the address of {type(x)} ({name})")
+    if dt not in dtypes:
+        _bad(where, f"{name} must have element type {' or '.join(dtypes)} (got {dt})")
+    if (n != numel) if exact else (n < numel):
+        _bad(where, f"{name} has {n} elements, the call {'needs exactly' if exact else 'accesses'}"
+                    f" {numel}")
+    return _addr(x)
+
+
+def _cells(ctx, where):
+    d = _dims.get(ctx)
+    if d is None:
+        _bad(where, "unknown or destroyed context")
+    n = 1
+    for v in d:
+        n *= v
+    return n
+
+
+def _state(ctx, x, where, name, nvar=4, optional=False):
+    return _dev(x, where, name, ("float64",), nvar * _cells(ctx, where), exact=True,
+                optional=optional)
+
+
+def _scalar(x, where, name, dtype="float64", optional=False, host_ok=False):
+    return _dev(x, where, name, (dtype,), 1, optional=optional, host_ok=host_ok)
+
+
 def _stream(s):
     if s is None:
         import torch
@@ -175,10 +244,12 @@ def _check(code, where):
 def gbr_init(nx, ny, gamma, mu, Pr):
     h = C.c_void_p()
     _check(load().gbr_init(nx, ny, gamma, mu, Pr, C.byref(h)), "gbr_init")
+    _dims[h.value] = (nx, ny)
     return h.value
 
 
 def gbr_destroy(ctx):
+    _dims.pop(ctx, None)
     return _check(load().gbr_destroy(ctx), "gbr_destroy")
 
 
@@ -233,22 +304,27 @@ def gbr_get_time(ctx):
 
 
 def gbr_advance_time(ctx, dt, stream=None):
-    return _check(load().gbr_advance_time(ctx, _addr(dt), _stream(stream)), "gbr_advance_time")
+    w = "gbr_advance_time"
+    return _check(load().gbr_advance_time(ctx, _scalar(dt, w, "dt"), _stream(stream)), w)
 
 
 def gbr_residual(ctx, Q, Res, stream=None):
-    return _check(load().gbr_residual(ctx, _addr(Q), _addr(Res), _stream(stream)),
-                  "gbr_residual")
+    w = "gbr_residual"
+    return _check(load().gbr_residual(ctx, _state(ctx, Q, w, "Q"), _state(ctx, Res, w, "Res"),
+                                      _stream(stream)), w)
 
 
 def gbr_rk_stage(ctx, stage, dt_dev, Qn, Qk, Qout, stream=None):
-    return _check(load().gbr_rk_stage(ctx, stage, _addr(dt_dev), _addr(Qn), _addr(Qk),
-                                      _addr(Qout), _stream(stream)), "gbr_rk_stage")
+    w = "gbr_rk_stage"
+    return _check(load().gbr_rk_stage(ctx, stage, _scalar(dt_dev, w, "dt_dev"),
+                                      _state(ctx, Qn, w, "Qn"), _state(ctx, Qk, w, "Qk"),
+                                      _state(ctx, Qout, w, "Qout"), _stream(stream)), w)
 
 
 def gbr_compute_dt(ctx, Q, cfl, dt_dev, stream=None):
-    return _check(load().gbr_compute_dt(ctx, _addr(Q), cfl, _addr(dt_dev), _stream(stream)),
-                  "gbr_compute_dt")
+    w = "gbr_compute_dt"
+    return _check(load().gbr_compute_dt(ctx, _state(ctx, Q, w, "Q"), cfl,
+                                        _scalar(dt_dev, w, "dt_dev"), _stream(stream)), w)
 
 
 def gbr_export_flags(ctx, enable=True):
@@ -256,8 +332,12 @@ def gbr_export_flags(ctx, enable=True):
 
 
 def gbr_get_flags(ctx, sig_x, sig_y, stream=None):
-    return _check(load().gbr_get_flags(ctx, _addr(sig_x), _addr(sig_y), _stream(stream)),
-                  "gbr_get_flags")
+    w = "gbr_get_flags"
+    nx, ny = _dims.get(ctx) or _bad(w, "unknown or destroyed context")
+    return _check(load().gbr_get_flags(
+        ctx, _dev(sig_x, w, "sig_x", ("uint8",), ny * (nx + 1), optional=True, host_ok=True),
+        _dev(sig_y, w, "sig_y", ("uint8",), (ny + 1) * nx, optional=True, host_ok=True),
+        _stream(stream)), w)
 
 
 def gbr_check(ctx, stream=None):
@@ -284,7 +364,8 @@ def gbr_get_tiling(ctx):
 
 
 def gbr_autotune(ctx, Q, reps=3, stream=None):
-    _check(load().gbr_autotune(ctx, _addr(Q), reps, _stream(stream)), "gbr_autotune")
+    w = "gbr_autotune"
+    _check(load().gbr_autotune(ctx, _state(ctx, Q, w, "Q"), reps, _stream(stream)), w)
     return gbr_get_tiling(ctx)
 
 
@@ -318,24 +399,43 @@ def gbr_mlp_get_params(m):
     return w, b
 
 
+_BF16 = ("int16", "uint16")
+
+
 def gbr_mlp_features(ctx, Q, feat, chi=None, stream=None):
-    return _check(load().gbr_mlp_features(ctx, _addr(Q), _addr(feat), _addr(chi), _stream(stream)),
-                  "gbr_mlp_features")
+    w = "gbr_mlp_features"
+    n = _cells(ctx, w)
+    return _check(load().gbr_mlp_features(
+        ctx, _state(ctx, Q, w, "Q"), _dev(feat, w, "feat", _BF16, 2 * n * 32),
+        _dev(chi, w, "chi", ("uint8",), 2 * n, optional=True), _stream(stream)), w)
 
 
 def gbr_mlp_forward(m, feat, n, logits, stream=None):
-    return _check(load().gbr_mlp_forward(m, _addr(feat), n, _addr(logits), _stream(stream)),
-                  "gbr_mlp_forward")
+    w = "gbr_mlp_forward"
+    return _check(load().gbr_mlp_forward(m, _dev(feat, w, "feat", _BF16, 32 * n), n,
+                                         _dev(logits, w, "logits", ("float32",), n),
+                                         _stream(stream)), w)
+
+
+def _train_args(w, feat, labels, idx, batch):
+    # the indices address rows of feat and labels; their values are the
+    # caller's (checking them would read device memory)
+    return (_dev(feat, w, "feat", _BF16, 32), _dev(labels, w, "labels", ("uint8",), 1),
+            _dev(idx, w, "idx", ("int32",), batch))
 
 
 def gbr_mlp_grad(m, feat, labels, idx, batch, grad, stream=None):
-    return _check(load().gbr_mlp_grad(m, _addr(feat), _addr(labels), _addr(idx), batch,
-                                      _addr(grad), _stream(stream)), "gbr_mlp_grad")
+    w = "gbr_mlp_grad"
+    return _check(load().gbr_mlp_grad(m, *_train_args(w, feat, labels, idx, batch), batch,
+                                      _dev(grad, w, "grad", ("float32",), MLP_NW + MLP_NB + 1),
+                                      _stream(stream)), w)
 
 
 def gbr_mlp_train_step(m, feat, labels, idx, batch, lr, loss=None, stream=None):
-    return _check(load().gbr_mlp_train_step(m, _addr(feat), _addr(labels), _addr(idx), batch, lr,
-                                            _addr(loss), _stream(stream)), "gbr_mlp_train_step")
+    w = "gbr_mlp_train_step"
+    return _check(load().gbr_mlp_train_step(
+        m, *_train_args(w, feat, labels, idx, batch), batch, lr,
+        _scalar(loss, w, "loss", "float32", optional=True, host_ok=True), _stream(stream)), w)
 
 
 def gbr_set_mlp_detector(ctx, m, margin, stream=None):
@@ -382,16 +482,26 @@ def gbr_batch_init(nx, ny, geom, bc, gamma, mu, Pr, cfl, precision):
     h = C.c_void_p()
     _check(load().gbr_batch_init(n, *[x.ctypes.data for x in arrs], precision, C.byref(h)),
            "gbr_batch_init")
+    _dims[h.value] = [(int(a), int(c)) for a, c in zip(arrs[0], arrs[1])]
     return h.value
 
 
 def gbr_batch_destroy(b):
+    _dims.pop(b, None)
     return _check(load().gbr_batch_destroy(b), "gbr_batch_destroy")
 
 
 def gbr_batch_set_arrays(b, X, Y, Z):
     """X, Y, Z: sequences of device arrays (tensors or addresses), one per grid."""
-    tabs = [(C.c_void_p * len(v))(*[_addr(t) for t in v]) for v in (X, Y, Z)]
+    w = "gbr_batch_set_arrays"
+    grids = _dims.get(b)
+    if grids is None:
+        _bad(w, "unknown or destroyed batch")
+    if any(len(v) != len(grids) for v in (X, Y, Z)):
+        _bad(w, f"every array set needs {len(grids)} arrays")
+    tabs = [(C.c_void_p * len(v))(*[_dev(t, w, f"{nm}[{k}]", ("float64",), 4 * g[0] * g[1],
+                                         exact=True) for k, (t, g) in enumerate(zip(v, grids))])
+            for nm, v in (("X", X), ("Y", Y), ("Z", Z))]
     return _check(load().gbr_batch_set_arrays(b, *[C.cast(t, C.c_void_p) for t in tabs]),
                   "gbr_batch_set_arrays")
 
@@ -456,10 +566,12 @@ def gbr_batch_timing_read(b):
 def gbr3_init(nx, ny, nz, gamma):
     h = C.c_void_p()
     _check(load().gbr3_init(nx, ny, nz, gamma, C.byref(h)), "gbr3_init")
+    _dims[h.value] = (nx, ny, nz)
     return h.value
 
 
 def gbr3_destroy(ctx):
+    _dims.pop(ctx, None)
     return _check(load().gbr3_destroy(ctx), "gbr3_destroy")
 
 
@@ -473,18 +585,22 @@ def gbr3_set_order(ctx, order):
 
 
 def gbr3_residual(ctx, Q, Res, stream=None):
-    return _check(load().gbr3_residual(ctx, _addr(Q), _addr(Res), _stream(stream)),
-                  "gbr3_residual")
+    w = "gbr3_residual"
+    return _check(load().gbr3_residual(ctx, _state(ctx, Q, w, "Q", 5), _state(ctx, Res, w, "Res", 5),
+                                       _stream(stream)), w)
 
 
 def gbr3_rk_stage(ctx, stage, dt, Qn, Qk, Qout, stream=None):
-    return _check(load().gbr3_rk_stage(ctx, stage, _addr(dt), _addr(Qn), _addr(Qk), _addr(Qout),
-                                       _stream(stream)), "gbr3_rk_stage")
+    w = "gbr3_rk_stage"
+    return _check(load().gbr3_rk_stage(ctx, stage, _scalar(dt, w, "dt"), _state(ctx, Qn, w, "Qn", 5),
+                                       _state(ctx, Qk, w, "Qk", 5), _state(ctx, Qout, w, "Qout", 5),
+                                       _stream(stream)), w)
 
 
 def gbr3_compute_dt(ctx, Q, cfl, dt, stream=None):
-    return _check(load().gbr3_compute_dt(ctx, _addr(Q), cfl, _addr(dt), _stream(stream)),
-                  "gbr3_compute_dt")
+    w = "gbr3_compute_dt"
+    return _check(load().gbr3_compute_dt(ctx, _state(ctx, Q, w, "Q", 5), cfl, _scalar(dt, w, "dt"),
+                                         _stream(stream)), w)
 
 
 def gbr3_export_flags(ctx, enable):
@@ -492,8 +608,12 @@ def gbr3_export_flags(ctx, enable):
 
 
 def gbr3_get_flags(ctx, sig_x, sig_y, sig_z, stream=None):
-    return _check(load().gbr3_get_flags(ctx, _addr(sig_x), _addr(sig_y), _addr(sig_z),
-                                        _stream(stream)), "gbr3_get_flags")
+    w = "gbr3_get_flags"
+    nx, ny, nz = _dims.get(ctx) or _bad(w, "unknown or destroyed context")
+    f = lambda x, nm, n: _dev(x, w, nm, ("uint8",), n, optional=True, host_ok=True)
+    return _check(load().gbr3_get_flags(ctx, f(sig_x, "sig_x", nz * ny * (nx + 1)),
+                                        f(sig_y, "sig_y", nz * (ny + 1) * nx),
+                                        f(sig_z, "sig_z", (nz + 1) * ny * nx), _stream(stream)), w)
 
 
 def gbr3_check(ctx, stream=None):
