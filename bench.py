@@ -1,23 +1,33 @@
 """Throughput of the MEG7 hot path on one MI355X: cell-stage updates/s.
 
-A step is one SSP-RK3 time step of the whole hot path on one grid: the device
-time step (CFL reduction) and three stage calls, each the learned detector's
-per-cell flag map (when selected) and the fused residual + stage-update
-kernel.  Inputs are resident in HBM before the timed region.
+A step is one SSP-RK3 time step of the whole hot path on one grid: the time
+step (Sec. 2.5) and three stage calls, each the learned detector's per-cell
+flag map (when selected and due) and the fused residual + stage-update
+kernel.  The first step's time step is a reduction over Q^n; every later one
+comes from the extrema the previous step's stage-3 kernel reduced while
+writing Q^n (gbr_stage_dt, bit-identical).  Inputs are resident in HBM before
+the timed region.
 
-The headline path is FP32 bulk arithmetic with the learned detector (FP64
-state and stage update); the plain FP64 path runs the same steps from the
-same initial state beside it, and the line reports both throughputs, their
-ratio, and the L1/Linf difference per conserved variable between the two
-final states.  The CPU oracle runs a bounded sample (whole steps on the full
-grid) as the cpu_baseline leg, and the headline path's state after the same
-number of steps is compared with it (L1/Linf per variable).
+Default workload: the learned detector's evaluation field, the four-quadrant
+Riemann problem at 4096^2 (seed 5000), whose state does not fit the 256 MB
+Infinity Cache.  The headline path is FP32 bulk arithmetic with the learned
+detector evaluated once per step on Q^n (FP64 state and stage update); the
+plain FP64 path, the FP32-bulk path with the plain detector and the learned
+detector evaluated every stage run the same steps from the same initial state
+beside it, and the line reports their throughputs, the speedups and the
+L1/Linf difference per conserved variable against the plain FP64 state.  The
+shear layer at 4096^2 (seed 5001) is reported beside it the same way.  The
+CPU oracle runs a bounded sample on all host threads and on one thread as
+the cpu_baseline leg, and the headline path's state after the same number of
+steps is compared with it (L1/Linf per variable).
 
 Prints ONE JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload riemann1024]
-                  [--path fp32_mlp|fp32|fp64|fp64_cons|fp64_g4|fp64_mpe] [--no-cpu-baseline] [--no-compare]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload riemann4096]
+                  [--path fp32_mlp_step|fp32_mlp|fp32|fp64|fp64_cons|fp64_g4|fp64_mpe]
+                  [--no-cpu-baseline] [--no-compare] [--no-secondary]
 """
+import hashlib
 import argparse
 import json
 import os
@@ -52,11 +62,10 @@ WORKLOADS = {
                   "CFL 0.2"),
     "riemann4096": ("riemann", 4096, 5000, 50,
                     "2D Euler four-quadrant Riemann problem, 4096x4096, seed 5000, transmissive, "
-                    "CFL 0.2"),
-    "taylor_green64": ("taylor_green", 64, 0, 2600,
-                       "2D inviscid Taylor-Green vortex 64x64 on [0, 2 pi)^2 (the z = 0 plane of the "
-                       "paper's Taylor-Green initial state, Mach ~0.085), periodic, CFL 0.5; 2600 "
-                       "steps reach t ~ 10"),
+                    "CFL 0.2 (the learned detector's evaluation field)"),
+    "shear4096": ("shear", 4096, 5001, 50,
+                  "2D Navier-Stokes periodic shear layer 4096x4096, seed 5001, Re 1e4, Pr 0.72, "
+                  "Mach 0.3, CFL 0.2 (the learned detector's evaluation field)"),
     "double_mach": ("double_mach", 1024, 0, None,
                     "Double Mach reflection 1024x256 on [0,4]x[0,1] (Mach-10 shock at 60 degrees, "
                     "reflecting wall, inflow, exact moving top boundary, shock-stable HLLC), run "
@@ -75,12 +84,15 @@ WORKLOADS = {
                  "stage over all grids, steps replayed as a HIP graph"),
 }
 
-def _path(prec, mlp, dtype, kernel, cons=False, order=7, mp_everywhere=False):
+def _path(prec, mlp, dtype, kernel, cons=False, order=7, mp_everywhere=False, per_step=False):
     return {"prec": prec, "mlp": mlp, "dtype": dtype, "kernel": kernel, "cons": cons,
-            "order": order, "mp_everywhere": mp_everywhere}
+            "order": order, "mp_everywhere": mp_everywhere, "per_step": per_step}
 
 
 PATHS = {
+    # learned detector evaluated once per step on Q^n and reused by stages 2
+    # and 3 (a change of the method; its L1 error is reported)
+    "fp32_mlp_step": _path("fp32", True, "f32+f64", "meg7_stage_kernel_f32<mlp>", per_step=True),
     "fp32_mlp": _path("fp32", True, "f32+f64", "meg7_stage_kernel_f32<mlp>"),
     "fp32": _path("fp32", False, "f32+f64", "meg7_stage_kernel_f32"),
     "fp64": _path("fp64", False, "f64", "meg7_stage_kernel"),
@@ -99,14 +111,17 @@ def parse():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default: the workload's step count)")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="riemann1024", choices=sorted(WORKLOADS))
-    ap.add_argument("--path", default="fp32_mlp", choices=sorted(PATHS))
+    ap.add_argument("--workload", default="riemann4096", choices=sorted(WORKLOADS))
+    ap.add_argument("--path", default="fp32_mlp_step", choices=sorted(PATHS))
     ap.add_argument("--weights", default=None, help="detector weights (.npz)")
     ap.add_argument("--margin", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
-                    help="skip the plain FP64 run beside the headline path")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+                    help="skip the comparison paths beside the headline path")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the shear-layer field reported beside the 4096^2 Riemann field")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="host seconds of the all-threads oracle sample")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
     ap.add_argument("--tiling", default="auto",
@@ -114,16 +129,32 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_source_sha():
+    """Hash of the HIP sources the kernels are built from."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2305_00762_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def load_traffic(kernel, workload):
     """HBM bytes per launch from the committed rocprofv3 PMC summary, if any
-    (a line 'bytes_per_launch = <value>')."""
+    (a line 'bytes_per_launch = <value>'), and only if the summary was taken
+    on the current kernel sources (its 'source_sha = <hash>' line): counters
+    of a kernel that has changed since are not reported."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.txt")
     if not os.path.exists(path):
         return None
+    val, sha = None, None
     for line in open(path):
-        if line.strip().startswith("bytes_per_launch") and "=" in line:
-            return float(line.split("=", 1)[1].split()[0])
-    return None
+        t = line.strip()
+        if t.startswith("bytes_per_launch") and "=" in t:
+            val = float(t.split("=", 1)[1].split()[0])
+        if t.startswith("source_sha") and "=" in t:
+            sha = t.split("=", 1)[1].split()[0]
+    return val if sha == kernel_source_sha() else None
 
 
 # VALU issue peak of the chip: 256 CUs x 4 SIMDs, each issuing one wave64
@@ -133,14 +164,32 @@ VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
 def cpu_model():
-    """The host CPU's model name (for the cpu_baseline record), if known."""
+    """The host CPU as /proc/cpuinfo describes it (model name, family, model,
+    stepping, sockets, logical CPUs) and the CPUs this process may run on."""
+    info = {}
     try:
+        ids = set()
+        nlog = 0
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            if ":" not in line:
+                continue
+            k, v = (x.strip() for x in line.split(":", 1))
+            if k == "processor":
+                nlog += 1
+            elif k == "physical id":
+                ids.add(v)
+            elif k in ("model name", "cpu family", "model", "stepping", "cpu MHz", "cache size") \
+                    and k not in info:
+                info[k] = v
+        info["sockets"] = len(ids) or None
+        info["logical_cpus"] = nlog
     except OSError:
         pass
-    return None
+    try:
+        info["usable_cpus"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        info["usable_cpus"] = os.cpu_count()
+    return info
 
 
 def load_valu(kernel_prefix, workload):
@@ -192,6 +241,11 @@ class Path:
         recon = gbr.GBR_RECON_CONS if self.cons else gbr.GBR_RECON_PRIM
         mp = gbr.GBR_MP_EVERYWHERE if spec["mp_everywhere"] else gbr.GBR_MP_FLAGGED
         gbr.gbr_set_scheme(self.ctx, recon, mp, prec, det)
+        if spec["per_step"]:
+            gbr.gbr_set_mlp_reuse(self.ctx, True)
+        self.name = path
+        # the next time step comes from the last stage-3 output's extrema
+        self.fresh = False
         if order != 7:
             gbr.gbr_set_order(self.ctx, order)
         self.order = order
@@ -216,12 +270,17 @@ class Path:
             q.copy_(torch.from_numpy(self.P.Q))
         torch.cuda.synchronize()
         self.gbr.gbr_set_time(self.ctx, 0.0)
+        self.fresh = False
 
     def step(self):
         """One SSP-RK3 step on self.stream; Q^{n+1} ends in self.Q[0]."""
         g, sh = self.gbr, self.stream.cuda_stream
         Q, Q1, Q2 = self.Q
-        g.gbr_compute_dt(self.ctx, Q, self.P.cfl, self.dt, sh)
+        if self.fresh:
+            g.gbr_stage_dt(self.ctx, self.P.cfl, self.dt, sh)
+        else:
+            g.gbr_compute_dt(self.ctx, Q, self.P.cfl, self.dt, sh)
+        self.fresh = True
         g.gbr_rk_stage(self.ctx, 1, self.dt, Q, Q, Q1, sh)
         g.gbr_rk_stage(self.ctx, 2, self.dt, Q, Q1, Q2, sh)
         g.gbr_rk_stage(self.ctx, 3, self.dt, Q, Q2, Q1, sh)
@@ -293,24 +352,23 @@ class Path:
             self.gbr.gbr_mlp_destroy(self.net)
 
 
-def kinetic_energy(Q):
-    return float((0.5 * (Q[1] * Q[1] + Q[2] * Q[2]) / Q[0]).mean())
-
-
 def diff(Qa, Qb):
     d = (Qa - Qb).abs().reshape(4, -1)
     return ([float(v) for v in d.mean(dim=1).cpu()], [float(v) for v in d.max(dim=1).values.cpu()])
 
 
-def cpu_baseline(P, seconds, max_steps=50, recon=0, order=7, mp_mode=0):
+def cpu_baseline(P, seconds, max_steps=50, recon=0, order=7, mp_mode=0, one_thread=True):
     """The CPU oracle on a bounded sample of the same workload: whole SSP-RK3
-    steps on the full grid from the initial state until about `seconds` of
-    host time have passed.  Returns (record, state after the sample, steps)."""
+    steps on the full grid from the initial state, on all host threads, until
+    about `seconds` of host time have passed; and one thread on one stage-1
+    call over the full grid (16.8M cell-stages at 4096^2, about 10 s).
+    Returns (record, state after the all-threads sample, steps)."""
     import numpy as np
     import oracle as O
     cfg = O.make_cfg(P.nx, P.ny, *P.geometry(), gamma=P.gamma, mu=P.mu, Pr=P.Pr, recon=recon,
                      order=order, riemann=P.riemann, mp_mode=mp_mode,
                      sides=[O.side(*sd) for sd in P.sides] if P.sides is not None else None)
+    O.set_threads(0)
     Q = np.ascontiguousarray(P.Q.copy())
     steps, t0 = 0, time.perf_counter()
     while True:
@@ -320,10 +378,21 @@ def cpu_baseline(P, seconds, max_steps=50, recon=0, order=7, mp_mode=0):
         if el >= seconds or steps >= max_steps:
             break
     cells = P.nx * P.ny * 3 * steps
-    rec = {"value": cells / el, "unit": "cell-stage updates/s", "cores": O.threads(), "cpu": cpu_model(),
-           "kind": "oracle",
+    rec = {"value": cells / el, "unit": "cell-stage updates/s", "cores": O.threads(),
+           "cpu": cpu_model(), "kind": "oracle",
            "sample": f"{steps} whole SSP-RK3 steps of the same workload from its initial "
-                     f"state ({cells} cell-stages) in {el:.1f} s"}
+                     f"state ({cells} cell-stages) in {el:.1f} s, all host threads"}
+    if one_thread:
+        O.set_threads(1)
+        Q0 = np.ascontiguousarray(P.Q.copy())
+        dt = O.dt(cfg, Q0, P.cfl)
+        t1 = time.perf_counter()
+        O.rk_stage(cfg, 1, dt, Q0, Q0)
+        el1 = time.perf_counter() - t1
+        O.set_threads(0)
+        rec["one_thread"] = {"value": P.nx * P.ny / el1, "unit": "cell-stage updates/s",
+                             "cores": 1, "sample": f"one stage-1 call over the full grid "
+                                                   f"({P.nx * P.ny} cell-stages) in {el1:.1f} s"}
     return rec, Q, steps
 
 
@@ -591,82 +660,105 @@ def bench_batch(a, steps):
     print(json.dumps(out), flush=True)
 
 
-def main():
-    a = parse()
-    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: runs on one GPU only; the decomposition over several GPUs (halo "
-              "exchange per stage, one min-reduction of the time step) is designed, not "
-              "built; use --gpus 1", file=sys.stderr)
-        sys.exit(2)
-    import torch
+def run_path(P, path, stream, a, steps, t_final, weights=None, margin=None):
+    """One path over the workload: a kernel pass with HIP events around every
+    launch (per-kernel durations for the roofline; the events add gaps
+    between launches), then the same work from the same initial state
+    without them for the throughput.  Returns (record, final state, Path)."""
     from paper_2305_00762_amd import gbr
-    from paper_2305_00762_amd import problems as PB
-
-    fam, n, seed, wsteps, desc = WORKLOADS[a.workload]
-    steps = a.steps if a.steps is not None else wsteps
-    if fam == "batch":
-        return bench_batch(a, steps)
-    if fam == "taylor_green3d":
-        return bench_3d(a, n)
-    P = PB.make(fam, n, seed=seed) if fam != "vortex" else PB.vortex(n, cfl=0.5)
-    torch.cuda.set_device(0)
-    stream = torch.cuda.Stream()
     cells = P.nx * P.ny
-
-    calibration_copy(a.calib_copy_mb)
-    head = Path(P, a.path, stream, a.tiling, a.weights, a.margin)
-    t_final = P.t_final if steps is None else None
+    h = Path(P, path, stream, a.tiling, weights, margin)
     if t_final is not None:
         # the whole run of the test case: warm-up steps, then from the
         # initial state at t = 0 until the device clock reaches t_final,
         # timed; the kernel pass repeats the same number of steps
-        head.run(a.warmup, 0)
-        head.reset()
-        total_ms, steps = head.run_to(t_final)
-        Qhead = head.Q[0].clone()
-        t_reached = gbr.gbr_get_time(head.ctx)
-        status_ok = head.status
-        head.reset()
-        ev_ms, (det_ms, stage_ms, launches) = head.run(0, steps, timing=True)
+        h.run(a.warmup, 0)
+        h.reset()
+        total_ms, steps = h.run_to(t_final)
+        Qf = h.Q[0].clone()
+        t_reached = gbr.gbr_get_time(h.ctx)
+        status = h.status
+        h.reset()
+        ev_ms, (det_ms, stage_ms, launches) = h.run(0, steps, timing=True)
     else:
-        # kernel pass: the same warm-up and steps with HIP events around every
-        # launch (per-kernel durations for the roofline); the events add gaps
-        # between launches, so the throughput comes from a second pass over the
-        # same work from the same initial state without them
-        ev_ms, (det_ms, stage_ms, launches) = head.run(a.warmup, steps, timing=True)
-        head.reset()
-        total_ms, _ = head.run(a.warmup, steps)
-        Qhead = head.Q[0].clone()
-        status_ok = head.status
-    value = cells * 3 * steps / (total_ms * 1e-3)
-    status = gbr.strerror(status_ok)
-    fb_rate = None
-    if head.net is not None:
-        ev, fb = gbr.gbr_mlp_stats(head.ctx, reset=True)
-        fb_rate = fb / max(ev, 1)
+        ev_ms, (det_ms, stage_ms, launches) = h.run(a.warmup, steps, timing=True)
+        h.reset()
+        total_ms, _ = h.run(a.warmup, steps)
+        Qf = h.Q[0].clone()
+        status = h.status
+        t_reached = None
+    rec = {"value": cells * 3 * steps / (total_ms * 1e-3), "ms_per_step": total_ms / steps,
+           "steps": steps, "tile": f"{h.tile[1]}x{h.tile[2]}", "status": gbr.strerror(status),
+           "ms_per_step_with_kernel_events": ev_ms / steps,
+           "kernels_us_per_launch": {
+               "stage": stage_ms * 1e3 / max(launches, 1),
+               # per stage call: the flag map's time summed over the step's
+               # evaluations, divided by the three stage calls
+               "detector_flag_map": (det_ms * 1e3 / max(launches, 1) if h.net is not None
+                                     else None)},
+           "_stage_ms": stage_ms, "_det_ms": det_ms, "_launches": launches,
+           "_total_ms": total_ms}
+    if t_final is not None:
+        rec["time_to_solution_s"] = total_ms * 1e-3
+        rec["t_final"] = t_final
+        rec["t_reached"] = t_reached
+    if h.net is not None:
+        ev, fb = gbr.gbr_mlp_stats(h.ctx, reset=True)
+        rec["detector_fallback_rate"] = fb / max(ev, 1)
+        rec["detector_evaluations_per_step"] = (2 if PATHS[path]["per_step"] else 6) * cells
+    return rec, Qf, h
 
+
+def public(rec):
+    return {k: v for k, v in rec.items() if not k.startswith("_")}
+
+
+def compare_paths(head_path):
+    """Paths run beside the headline one: the plain FP64 path always; the
+    FP32-bulk path with the plain detector for an FP32-bulk headline; the
+    per-stage learned detector beside the per-step one."""
+    out = ["fp64"] if head_path != "fp64" else []
+    if PATHS[head_path]["prec"] == "fp32" and head_path != "fp32":
+        out.append("fp32")
+    if head_path == "fp32_mlp_step":
+        out.append("fp32_mlp")
+    return out
+
+
+COMPARE_KEY = {"fp64": "fp64_plain", "fp32": "fp32_plain", "fp32_mlp": "fp32_mlp_per_stage"}
+
+
+def bench_2d(a, workload, steps_arg, stream, cpu=True, secondary=False):
+    """The record of one 2D workload: the headline path, its roofline, the
+    comparison paths and (cpu) the oracle baseline."""
+    import torch
+    from paper_2305_00762_amd import problems as PB
+    fam, n, seed, wsteps, desc = WORKLOADS[workload]
+    steps = steps_arg if steps_arg is not None else wsteps
+    P = PB.make(fam, n, seed=seed) if fam != "vortex" else PB.vortex(n, cfl=0.5)
+    cells = P.nx * P.ny
+    t_final = P.t_final if steps is None else None
+    head_rec, Qhead, head = run_path(P, a.path, stream, a, steps, t_final, a.weights, a.margin)
+    steps = head_rec["steps"]
+    stage_ms, launches = head_rec["_stage_ms"], head_rec["_launches"]
     # roofline of the dominant kernel (the stage kernel): algorithmic bytes of
     # the timed launches over their summed duration from the library's events
     alg_bytes = sum(BYTES_PER_CELL_STAGE.values()) * cells * steps
     achieved = alg_bytes / (stage_ms * 1e-3) / 1e9
     kname = head.kernel.replace("<", "_").replace(">", "")
-    traffic = load_traffic(kname, a.workload)
     out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "cell-stage updates/s",
-        "n_gpus": 1,
+        "value": head_rec["value"],
+        "ms_per_step": head_rec["ms_per_step"],
         "steps": steps,
-        "warmup": a.warmup,
-        "ms_per_step": total_ms / steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": head.dtype,
-        "data": "synthetic",
-        "config": {"workload": a.workload, "description": desc, "nx": P.nx, "ny": P.ny,
-                   "path": a.path, "tile": f"{head.tile[1]}x{head.tile[2]}",
-                   "step": "device dt + 3 x (learned-detector flag map if selected + fused "
+        "config": {"workload": workload, "description": desc, "nx": P.nx, "ny": P.ny,
+                   "path": a.path, "tile": head_rec["tile"],
+                   "detector": ("learned, evaluated once per step on Q^n and reused by stages 2 "
+                                "and 3 (a change of the method; its error is reported)"
+                                if PATHS[a.path]["per_step"] else
+                                "learned, evaluated at every stage" if PATHS[a.path]["mlp"]
+                                else "plain (Sec. 2.4)"),
+                   "step": "dt (first step: reduction over Q^n; then from the stage-3 extrema) + "
+                           "3 x (learned-detector flag map if selected and due + fused "
                            "residual/stage kernel)"},
         "roofline": {
             "bound": "hbm",
@@ -674,7 +766,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
+            "traffic": load_traffic(kname, workload),
             "kernel": head.kernel,
             "avg_launch_us": stage_ms * 1e3 / max(launches, 1),
             "bytes_per_cell_stage": 256.0 / 3.0,
@@ -683,62 +775,83 @@ def main():
         # lane-operations per 85 B, lies far right of the ridge): issued lane
         # operations (SQ_INSTS_VALU x 64, from the committed counter summary)
         # over the live launch duration
-        "roofline_valu": valu_roofline(head.kernel, a.workload, stage_ms * 1e3 / max(launches, 1)),
-        "ms_per_step_with_kernel_events": ev_ms / steps,
-        "kernels_us_per_launch": {"stage": stage_ms * 1e3 / max(launches, 1),
-                                  "detector_flag_map": (det_ms * 1e3 / max(launches, 1)
-                                                        if head.net is not None else None)},
-        # flag map: reads Q (32 B) and writes one byte per cell
-        "detector_flag_map_GBs": (33.0 * cells * launches / (det_ms * 1e-3) / 1e9
-                                  if det_ms > 0 and head.net is not None else None),
-        "status": status,
+        "roofline_valu": valu_roofline(head.kernel, workload, stage_ms * 1e3 / max(launches, 1)),
+        "status": head_rec["status"],
     }
-    if t_final is not None:
-        out["time_to_solution_s"] = total_ms * 1e-3
-        out["t_final"] = t_final
-        out["t_reached"] = t_reached
-    if fb_rate is not None:
-        out["detector_fallback_rate"] = fb_rate
+    out.update({k: v for k, v in public(head_rec).items()
+                if k not in ("value", "ms_per_step", "steps", "tile", "status")})
+    if head.net is not None and head_rec["_det_ms"] > 0:
+        # flag map: reads Q (32 B) and writes one byte per cell, per evaluation
+        evals = steps * (1 if PATHS[a.path]["per_step"] else 3)
+        out["detector_flag_map_GBs"] = 33.0 * cells * evals / (head_rec["_det_ms"] * 1e-3) / 1e9
+    head.close()
 
-    if not a.no_compare and a.path != "fp64":
-        base = Path(P, "fp64", stream, a.tiling, None, None)
-        if t_final is not None:
-            base.run(a.warmup, 0)
-            base.reset()
-            bms, bsteps = base.run_to(t_final)
-        else:
-            bsteps = steps
-            bms, _ = base.run(a.warmup, steps)
-        bval = cells * 3 * bsteps / (bms * 1e-3)
-        l1, linf = diff(Qhead, base.Q[0])
-        out["fp64_plain"] = {"value": bval, "ms_per_step": bms / bsteps,
-                             "tile": f"{base.tile[1]}x{base.tile[2]}",
-                             "status": gbr.strerror(base.status)}
-        if t_final is not None:
-            out["fp64_plain"].update({"steps": bsteps, "time_to_solution_s": bms * 1e-3})
-            out["time_to_solution_ratio_vs_fp64_plain"] = total_ms / bms
-        out["speedup_vs_fp64_plain"] = value / bval
-        after = f"t = {t_final}" if t_final is not None else a.warmup + steps
-        out["error_vs_fp64_plain"] = {"after_steps": after, "L1": l1, "Linf": linf,
-                                      "vars": ["rho", "rho_u", "rho_v", "E"]}
-        if fam == "taylor_green":
-            # kinetic-energy budget of the inviscid vortex: KE(t)/KE(0) of both paths
-            out["kinetic_energy_ratio"] = {"after_steps": a.warmup + steps,
-                                           a.path: kinetic_energy(Qhead) / kinetic_energy(head.Q0),
-                                           "fp64": kinetic_energy(base.Q[0]) / kinetic_energy(head.Q0)}
-        base.close()
+    if not a.no_compare:
+        base_Q = None
+        for cp in compare_paths(a.path):
+            rec, Qc, h = run_path(P, cp, stream, a, steps if t_final is None else None, t_final)
+            h.close()
+            key = COMPARE_KEY.get(cp, cp)
+            out[key] = public(rec)
+            out[f"speedup_vs_{key}"] = out["value"] / rec["value"]
+            if t_final is not None:
+                out[f"time_to_solution_ratio_vs_{key}"] = (head_rec["_total_ms"] /
+                                                          rec["_total_ms"])
+            if cp == "fp64":
+                base_Q = Qc
+            else:
+                del Qc
+        if base_Q is not None:
+            l1, linf = diff(Qhead, base_Q)
+            after = f"t = {t_final}" if t_final is not None else a.warmup + steps
+            out["error_vs_fp64_plain"] = {"after_steps": after, "L1": l1, "Linf": linf,
+                                          "vars": ["rho", "rho_u", "rho_v", "E"]}
+            del base_Q
+    del Qhead
+    torch.cuda.empty_cache()
 
-    if not a.no_cpu_baseline:
-        rec, Qo, osteps = cpu_baseline(P, a.cpu_seconds, recon=1 if head.cons else 0,
-                                       order=head.order,
+    if cpu:
+        rec, Qo, osteps = cpu_baseline(P, a.cpu_seconds, recon=1 if PATHS[a.path]["cons"] else 0,
+                                       order=PATHS[a.path]["order"],
                                        mp_mode=1 if PATHS[a.path]["mp_everywhere"] else 0)
         out["cpu_baseline"] = rec
-        head.reset()
-        head.run(osteps, 0)
-        l1, linf = diff(head.Q[0].cpu(), torch.from_numpy(Qo))
+        h = Path(P, a.path, stream, a.tiling, a.weights, a.margin)
+        h.run(osteps, 0)
+        l1, linf = diff(h.Q[0].cpu(), torch.from_numpy(Qo))
+        h.close()
         out["error_vs_oracle"] = {"after_steps": osteps, "L1": l1, "Linf": linf,
-                                  "vars": ["rho", "rho_u", "rho_v", "E"]}
-    head.close()
+                                  "vars": ["rho", "rho_u", "rho_v", "E"],
+                                  "oracle": "plain method (Sec. 2.4 detector), FP64"}
+    return out
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: runs on one GPU only; the decomposition over several GPUs (halo "
+              "exchange per stage, one min-reduction of the time step) is designed, not "
+              "built; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    fam, n, seed, wsteps, desc = WORKLOADS[a.workload]
+    steps = a.steps if a.steps is not None else wsteps
+    if fam == "batch":
+        return bench_batch(a, steps)
+    if fam == "taylor_green3d":
+        return bench_3d(a, n)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    calibration_copy(a.calib_copy_mb)
+    rec = bench_2d(a, a.workload, a.steps, stream, cpu=not a.no_cpu_baseline)
+    out = {"metric": METRIC, "value": rec.pop("value"), "unit": "cell-stage updates/s",
+           "n_gpus": 1, "steps": rec.pop("steps"), "warmup": a.warmup,
+           "ms_per_step": rec.pop("ms_per_step"), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": PATHS[a.path]["dtype"], "data": "synthetic"}
+    out.update(rec)
+    if a.workload == "riemann4096" and not a.no_secondary:
+        # the other evaluation field of the learned detector, reported beside
+        out["shear4096"] = bench_2d(a, "shear4096", a.steps, stream, cpu=False)
     print(json.dumps(out), flush=True)
 
 

@@ -179,6 +179,19 @@ int gbr_rk_stage(gbr_ctx *ctx, int stage, const double *dt_dev, const double *Qn
 int gbr_compute_dt(gbr_ctx *ctx, const double *Q, double cfl, double *dt_dev,
                    void *stream);
 
+/* The same time step (Sec. 2.5) of the state the last stage-3 call wrote,
+ * without another pass over it: every stage-3 call (gbr_rk_stage with
+ * stage = 3) reduces, while it writes Q^(n+1), the extrema the time step
+ * needs -- max(|u|+c), max(|v|+c) and min(rho) over the grid, per cell with
+ * the arithmetic of gbr_compute_dt -- into context words.  Since fl(a/x) is
+ * monotone in x, dt from the extrema equals gbr_compute_dt on that state bit
+ * for bit, provided the state was not modified after the stage-3 call.  The
+ * call reads and clears the words (a single small kernel on `stream`), so
+ * each stage-3 output serves one call; it returns GBR_EINVAL when no stage-3
+ * call came since the last one (or since gbr_init).  cfl > 0; dt_dev: device
+ * double. */
+int gbr_stage_dt(gbr_ctx *ctx, double cfl, double *dt_dev, void *stream);
+
 /* Flag export (debugging and parity): when enabled, every residual or stage
  * call records the detector outcome sigma (1 = smooth, 0 = flagged) of each
  * interface in context buffers.  gbr_get_flags copies the last call's flags
@@ -272,6 +285,22 @@ int gbr_mlp_train_step(gbr_mlp *m, const uint16_t *feat, const uint8_t *labels, 
  * counts). */
 int gbr_set_mlp_detector(gbr_ctx *ctx, const gbr_mlp *m, float margin, void *stream);
 int gbr_mlp_stats(gbr_ctx *ctx, uint64_t *evaluated, uint64_t *fallbacks, int reset);
+
+/* Per-step evaluation of the learned detector (a change of the method, off
+ * by default): with per_step = 1 the flag map is evaluated only by residual
+ * calls and stage-1 calls, i.e. on Q^n, and stages 2 and 3 reuse it, so the
+ * detector sees Q^n for all three stages of a step instead of each stage's
+ * input.  The caller must run the stages of a step in order on one context;
+ * a stage-2 or stage-3 call with no flag map evaluated before it returns
+ * GBR_EINVAL.  GBR_EINVAL if per_step is not 0 or 1. */
+int gbr_set_mlp_reuse(gbr_ctx *ctx, int per_step);
+
+/* Copy the learned detector's per-cell flag map of the last evaluation
+ * (nx*ny bytes, row-major [ny][nx]: bit 0 chi^x, bit 1 chi^y; the network's
+ * sign where |logit| >= margin, else the plain label) to chi, a host or
+ * device pointer; synchronises `stream`.  GBR_EINVAL if the context has no
+ * flag map (gbr_set_mlp_detector was never called). */
+int gbr_mlp_get_flagmap(gbr_ctx *ctx, uint8_t *chi, void *stream);
 
 /* Self-test of the reciprocal the detector features use (the hardware
  * estimate refined by one fused Newton step in place of IEEE division; the

@@ -91,6 +91,7 @@
  * operation in the order written).
  */
 #include <math.h>
+#include <omp.h>
 #include <stddef.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -135,6 +136,18 @@ static const double XI_MP = 7.0;        /* eq. (eqn:alpha): xi = 7              
 static const double MP_TOL = 1e-40;     /* eq. (eqn:hocus/mp5Condition)             */
 static const double PSI_C = 0.5;        /* eq. (buffer)                             */
 static const double XI_DET = 1e-3;      /* eq. (buffer)                             */
+
+/* Threads of the parallel loops (OpenMP; n < 1 restores the default) and the
+ * number a parallel loop would use now. */
+void orc_set_threads(int n)
+{
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+}
+
+int orc_get_threads(void)
+{
+    return omp_get_max_threads();
+}
 
 double orc_detector_eps(void)
 {

@@ -133,6 +133,10 @@ def lib():
         L.orc_interface_states.argtypes = [dp, dp, C.POINTER(OrcCfg), C.c_int, dp, dp]
         L.orc_char_prim.restype = None
         L.orc_char_prim.argtypes = [dp, dp, C.c_double, dp, dp]
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_get_threads.restype = C.c_int
+        L.orc_get_threads.argtypes = []
         _lib = L
     return _lib
 
@@ -300,9 +304,13 @@ def cell_flags(cfg, Q):
 
 
 def threads():
-    """OpenMP threads the oracle will use (OMP_NUM_THREADS or all cores)."""
-    v = os.environ.get("OMP_NUM_THREADS")
-    return int(v) if v else os.cpu_count()
+    """OpenMP threads the oracle's parallel loops use now."""
+    return int(lib().orc_get_threads())
+
+
+def set_threads(n):
+    """Threads for the oracle's parallel loops (n < 1: all processors)."""
+    lib().orc_set_threads(int(n))
 
 
 def char_cons(Qa, Qb, gamma=1.4):

@@ -27,7 +27,7 @@ inline int dt_blocks(size_t n) {
 
 struct DtParams {
   const double* __restrict__ Q;
-  double* partial;   // [2][kDtBlocks]
+  double* partial;   // [2][kDtBlocks] (context scratch holds [3][kDtBlocks])
   double* dt;
   unsigned* status;
   int nx, ny;
@@ -95,6 +95,73 @@ __global__ __launch_bounds__(kDtThreads) void dt_finish_kernel(const double* par
   conv = block_min(conv, red);
   visc = block_min(visc, red);
   if (threadIdx.x == 0) {
+    const double d = cfl * fmin(visc / kAlphaV, conv);
+    *dt = d;
+    if (!(d > 0.0) || !isfinite(d)) atomicOr(status, 2u);
+  }
+}
+
+// dt from the extrema the stage-3 kernel left per workgroup, in two passes
+// like the reduction above: pass 1 folds the slots [3][nslot] into
+// kDtBlocks partial extrema, pass 2 (one workgroup) finishes with the
+// arithmetic of dt_cell and dt_finish_kernel -- the minimum over cells of
+// fl(dx/(|u|+c)) is fl(dx/max(|u|+c)), and that of fl(fl(dx dx)/fl(mu/rho))
+// is fl(fl(dx dx)/fl(mu/min rho)), since fl(d/x) is monotone in x.
+__device__ __forceinline__ double block_max(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if (__lane_id() == 0) red[w] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int k = 1; k < (int)(blockDim.x >> 6); ++k) r = fmax(r, red[k]);
+  return r;
+}
+
+__global__ __launch_bounds__(kDtThreads) void dt_extrema_reduce_kernel(const double* slots,
+                                                                       int nslot,
+                                                                       double* partial) {
+  __shared__ double red[kDtThreads / 64];
+  double a = 0.0, b = 0.0, r = __builtin_inf();
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nslot; k += gridDim.x * blockDim.x) {
+    a = fmax(a, slots[k]);
+    b = fmax(b, slots[nslot + k]);
+    r = fmin(r, slots[2 * nslot + k]);
+  }
+  a = block_max(a, red);
+  b = block_max(b, red);
+  r = block_min(r, red);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = a;
+    partial[kDtBlocks + blockIdx.x] = b;
+    partial[2 * kDtBlocks + blockIdx.x] = r;
+  }
+}
+
+__global__ __launch_bounds__(kDtThreads) void dt_from_extrema_kernel(const double* partial,
+                                                                     int nblk, double* dt,
+                                                                     double cfl, double dx,
+                                                                     double dy, double mu,
+                                                                     unsigned* status) {
+#pragma clang fp contract(off)
+  __shared__ double red[kDtThreads / 64];
+  double a = 0.0, b = 0.0, r = __builtin_inf();
+  for (int k = threadIdx.x; k < nblk; k += blockDim.x) {
+    a = fmax(a, partial[k]);
+    b = fmax(b, partial[kDtBlocks + k]);
+    r = fmin(r, partial[2 * kDtBlocks + k]);
+  }
+  a = block_max(a, red);
+  b = block_max(b, red);
+  r = block_min(r, red);
+  if (threadIdx.x == 0) {
+    const double conv = fmin(dx / a, dy / b);
+    double visc = __builtin_inf();
+    if (mu > 0.0) {
+      const double nu = mu / r;
+      visc = fmin(dx * dx / nu, dy * dy / nu);
+    }
     const double d = cfl * fmin(visc / kAlphaV, conv);
     *dt = d;
     if (!(d > 0.0) || !isfinite(d)) atomicOr(status, 2u);

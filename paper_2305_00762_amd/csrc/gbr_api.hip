@@ -159,7 +159,10 @@ struct gbr_ctx {
   int device;
   int export_flags;
   unsigned* d_status;         // [4]
-  double* d_partial;          // [2][kDtBlocks] time-step partial minima
+  double* d_partial;          // [3][kDtBlocks] time-step partial extrema
+  double* d_dtx;              // [3][ntiles] per-workgroup time-step extrema of a stage-3 output
+  int dtx_cap;                // tiles d_dtx holds (the most of any tile shape)
+  int stage3_tiles;           // tiles of the last stage-3 call; 0: none since gbr_stage_dt
   uint8_t* d_sigx;
   uint8_t* d_sigy;
   int tiling;                 // index into kVariants
@@ -169,6 +172,8 @@ struct gbr_ctx {
   float mlp_margin;
   int mlp_ready;
   uint8_t* d_chimap;          // [ny][nx] learned-detector flag per cell
+  int mlp_reuse;              // 1: flag map evaluated on Q^n only (residual and stage 1)
+  int chimap_valid;           // a flag map has been evaluated
   unsigned long long* d_mlp_fb;   // plain fallbacks of the learned detector
   unsigned long long mlp_evaluated;
   // kernel timing (gbr_timing): events recorded around every launch of a
@@ -223,7 +228,7 @@ int gbr_init(int nx, int ny, double gamma, double mu, double Pr, gbr_ctx** out) 
   c->precision = GBR_PREC_FP64; c->detector = GBR_DET_PLAIN;
   if (hipGetDevice(&c->device) != hipSuccess) { delete c; return GBR_EDEVICE; }
   if (hipMalloc(&c->d_status, 4 * sizeof(unsigned)) != hipSuccess) { delete c; return GBR_ENOMEM; }
-  if (hipMalloc(&c->d_partial, 2 * kDtBlocks * sizeof(double)) != hipSuccess) {
+  if (hipMalloc(&c->d_partial, 3 * kDtBlocks * sizeof(double)) != hipSuccess) {
     (void)hipFree(c->d_status); delete c; return GBR_ENOMEM;
   }
   if (hipMalloc(&c->d_sides, 4 * sizeof(SideDev)) != hipSuccess) {
@@ -233,11 +238,23 @@ int gbr_init(int nx, int ny, double gamma, double mu, double Pr, gbr_ctx** out) 
     (void)hipFree(c->d_status); (void)hipFree(c->d_partial); (void)hipFree(c->d_sides);
     delete c; return GBR_ENOMEM;
   }
+  // per-workgroup time-step extrema of stage-3 outputs: room for the tiles
+  // of the smallest tile shape
+  c->dtx_cap = 0;
+  for (int v = 0; v < kNumVariants; ++v) {
+    const int t = ((nx + kVariants[v].tx - 1) / kVariants[v].tx) *
+                  ((ny + kVariants[v].ty - 1) / kVariants[v].ty);
+    c->dtx_cap = t > c->dtx_cap ? t : c->dtx_cap;
+  }
+  if (hipMalloc(&c->d_dtx, 3 * (size_t)c->dtx_cap * sizeof(double)) != hipSuccess) {
+    (void)hipFree(c->d_status); (void)hipFree(c->d_partial); (void)hipFree(c->d_sides);
+    (void)hipFree(c->d_time); delete c; return GBR_ENOMEM;
+  }
   if (hipMemset(c->d_status, 0, 4 * sizeof(unsigned)) != hipSuccess ||
       hipMemset(c->d_time, 0, sizeof(double)) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     (void)hipFree(c->d_status); (void)hipFree(c->d_partial); (void)hipFree(c->d_sides);
-    (void)hipFree(c->d_time); delete c; return GBR_EDEVICE;
+    (void)hipFree(c->d_time); (void)hipFree(c->d_dtx); delete c; return GBR_EDEVICE;
   }
   *out = c;
   return GBR_OK;
@@ -250,6 +267,7 @@ int gbr_destroy(gbr_ctx* c) {
   (void)hipFree(c->d_partial);
   (void)hipFree(c->d_sides);
   (void)hipFree(c->d_time);
+  (void)hipFree(c->d_dtx);
   if (c->d_sigx) (void)hipFree(c->d_sigx);
   if (c->d_sigy) (void)hipFree(c->d_sigy);
   if (c->d_mlp_w) (void)hipFree(c->d_mlp_w);
@@ -431,7 +449,11 @@ static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn
   P.tc = mode == MODE_STAGE2 ? 1.0 : (mode == MODE_STAGE3 ? 0.5 : 0.0);
   P.x0 = c->x0; P.y0 = c->y0;
   P.dx = (c->x1 - c->x0) / c->nx; P.dy = (c->y1 - c->y0) / c->ny;
+  P.dtx = mode == MODE_STAGE3 ? c->d_dtx : nullptr;
   const int det = c->detector == GBR_DET_MLP ? 1 : 0;
+  // per-step detector: stages 2 and 3 reuse the flag map of Q^n
+  const bool reuse = det && c->mlp_reuse && (mode == MODE_STAGE2 || mode == MODE_STAGE3);
+  if (reuse && !c->chimap_valid) return GBR_EINVAL;
   hipEvent_t* tev = nullptr;
   if (c->timing) {
     if (c->ev_used + 3 > c->ev.size()) {
@@ -445,7 +467,7 @@ static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn
     c->ev_used += 3;
     if (hipEventRecord(tev[0], s) != hipSuccess) return GBR_EDEVICE;
   }
-  if (det) {
+  if (det && !reuse) {
     MlpChiParams M{};
     M.Q = Qk; M.chi = c->d_chimap; M.nfb = c->d_mlp_fb;
     M.M.W1 = c->d_mlp_w;
@@ -459,8 +481,9 @@ static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn
     const int nblk = M.tiles_x * ((c->ny + kChiTY - 1) / kChiTY);
     hipLaunchKernelGGL(mlp_chi_kernel, dim3(nblk), dim3(256), 0, s, M);
     c->mlp_evaluated += 2ull * c->nx * c->ny;   // along x and along y
-    P.chimap = c->d_chimap;
+    c->chimap_valid = 1;
   }
+  if (det) P.chimap = c->d_chimap;
   const int vi = active_variant(c);
   const TileVariant* v = &kVariants[vi];
   P.tiles_x = (c->nx + v->tx - 1) / v->tx;
@@ -468,6 +491,7 @@ static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn
   if (tev && hipEventRecord(tev[1], s) != hipSuccess) return GBR_EDEVICE;
   variant_fn(c, vi)(P, s);
   if (tev && hipEventRecord(tev[2], s) != hipSuccess) return GBR_EDEVICE;
+  if (mode == MODE_STAGE3) c->stage3_tiles = P.ntiles;
   return hip_ok(hipGetLastError());
 }
 
@@ -577,6 +601,20 @@ int gbr_compute_dt(gbr_ctx* c, const double* Q, double cfl, double* dt_dev, void
   hipLaunchKernelGGL(dt_reduce_kernel, dim3(blocks), dim3(kDtThreads), 0, s, P);
   hipLaunchKernelGGL(dt_finish_kernel, dim3(1), dim3(kDtThreads), 0, s, c->d_partial, blocks,
                      dt_dev, cfl, c->d_status);
+  return hip_ok(hipGetLastError());
+}
+
+int gbr_stage_dt(gbr_ctx* c, double cfl, double* dt_dev, void* stream) {
+  if (!c || !dt_dev || !(cfl > 0.0) || c->stage3_tiles <= 0) return GBR_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int nslot = c->stage3_tiles;
+  const int blocks = dt_blocks((size_t)nslot);
+  hipLaunchKernelGGL(dt_extrema_reduce_kernel, dim3(blocks), dim3(kDtThreads), 0, s,
+                     (const double*)c->d_dtx, nslot, c->d_partial);
+  hipLaunchKernelGGL(dt_from_extrema_kernel, dim3(1), dim3(kDtThreads), 0, s,
+                     (const double*)c->d_partial, blocks, dt_dev, cfl,
+                     (c->x1 - c->x0) / c->nx, (c->y1 - c->y0) / c->ny, c->mu, c->d_status);
+  c->stage3_tiles = 0;
   return hip_ok(hipGetLastError());
 }
 
@@ -722,6 +760,21 @@ int gbr_set_mlp_detector(gbr_ctx* c, const gbr_mlp* m, float margin, void* strea
     return GBR_EDEVICE;
   c->mlp_margin = margin;
   c->mlp_ready = 1;
+  return GBR_OK;
+}
+
+int gbr_set_mlp_reuse(gbr_ctx* c, int per_step) {
+  if (!c || (per_step != 0 && per_step != 1)) return GBR_EINVAL;
+  c->mlp_reuse = per_step;
+  return GBR_OK;
+}
+
+int gbr_mlp_get_flagmap(gbr_ctx* c, uint8_t* chi, void* stream) {
+  if (!c || !chi || !c->d_chimap) return GBR_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(chi, c->d_chimap, (size_t)c->nx * c->ny, hipMemcpyDefault, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return GBR_EDEVICE;
   return GBR_OK;
 }
 

@@ -52,6 +52,9 @@ struct StageParams {
   const double* tnow;             // device time of Q^n (moving boundary segments)
   double tc;                      // stage abscissa: boundary time = tnow + tc dt
   double x0, y0, dx, dy;          // cell-centre coordinates of the boundary segments
+  // stage 3 only (else null): per-workgroup time-step extrema of the output,
+  // [3][ntiles]: max(|u|+c), max(|v|+c), min rho
+  double* dtx;
 };
 
 // Ghost cells by index: periodic wrap or transmissive clamp.  The offsets
@@ -592,9 +595,55 @@ __device__ __forceinline__ void stage_load(const StageParams& P, double* sU, int
   if (bad) atomicOr(P.status, STATUS_BAD_STATE);
 }
 
+// Time-step extrema of one cell of the new state (Sec. 2.5): |u|+c, |v|+c
+// and rho, each rounded exactly as the time-step kernel rounds them (one
+// rounding per operation, IEEE division and square root), folded into
+// (amax, bmax, rmin).  Since fl(d/x) is monotone in x, the minima of the
+// per-cell limits follow from these extrema without loss.
+__device__ __forceinline__ void dt_extrema_cell(const double q[4], double gamma, double& amax,
+                                                double& bmax, double& rmin, bool& bad) {
+#pragma clang fp contract(off)
+  const double rho = q[0];
+  const double u = q[1] / rho, v = q[2] / rho;
+  const double p = (gamma - 1.0) * (q[3] - rho * (u * u + v * v) / 2.0);
+  const double c = sqrt(gamma * p / rho);
+  if (!(rho > 0.0) || !(p > 0.0) || !isfinite(c) || !isfinite(u) || !isfinite(v)) bad = true;
+  amax = fmax(amax, fabs(u) + c);
+  bmax = fmax(bmax, fabs(v) + c);
+  rmin = fmin(rmin, rho);
+}
+
+// Workgroup extrema written to slot `slot` of the partial arrays w[3][nslot]
+// (plain stores; the time-step kernels reduce the slots in a fixed order).
+// Every thread of the workgroup calls it.
+__device__ __forceinline__ void dt_extrema_commit(double* w, int nslot, int slot, double a,
+                                                  double b, double r) {
+  __shared__ double red[3][16];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a = fmax(a, __shfl_xor(a, o));
+    b = fmax(b, __shfl_xor(b, o));
+    r = fmin(r, __shfl_xor(r, o));
+  }
+  const int wv = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+  if (__lane_id() == 0) { red[0][wv] = a; red[1][wv] = b; red[2][wv] = r; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < nw; ++k) {
+      a = fmax(a, red[0][k]);
+      b = fmax(b, red[1][k]);
+      r = fmin(r, red[2][k]);
+    }
+    w[slot] = a;
+    w[nslot + slot] = b;
+    w[2 * nslot + slot] = r;
+  }
+}
+
 // Residual store or SSP-RK3 stage update, eq. (rk), for the cells this
 // thread owns (c = tid + k NT, row-major in the tile); one coalesced FP64
-// store per conserved variable.
+// store per conserved variable.  Stage 3 with P.dtx set also reduces the
+// time-step extrema of the new state.
 template <class C>
 __device__ __forceinline__ void stage_store(const StageParams& P, const double (&res)[C::CPT][4],
                                             int tx0, int ty0) {
@@ -617,23 +666,31 @@ __device__ __forceinline__ void stage_store(const StageParams& P, const double (
       qk[k][m] = (own[k] && P.mode >= MODE_STAGE2) ? P.Qk[m * n + so[k]] : 0.0;
     }
   }
+  const bool ext = P.dtx != nullptr;
+  double amax = 0.0, bmax = 0.0, rmin = __builtin_inf();
+  bool bad = false;
 #pragma unroll
   for (int k = 0; k < C::CPT; ++k) {
     if (!own[k]) continue;
+    double v[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const double R = res[k][m];
-      double v;
       if (P.mode == MODE_RESIDUAL)
-        v = R;
+        v[m] = R;
       else if (P.mode == MODE_STAGE1)
-        v = qn[k][m] + dt * R;
+        v[m] = qn[k][m] + dt * R;
       else if (P.mode == MODE_STAGE2)
-        v = 0.75 * qn[k][m] + 0.25 * qk[k][m] + (0.25 * dt) * R;
+        v[m] = 0.75 * qn[k][m] + 0.25 * qk[k][m] + (0.25 * dt) * R;
       else
-        v = (1.0 / 3.0) * qn[k][m] + (2.0 / 3.0) * qk[k][m] + ((2.0 / 3.0) * dt) * R;
-      P.out[m * n + so[k]] = v;
+        v[m] = (1.0 / 3.0) * qn[k][m] + (2.0 / 3.0) * qk[k][m] + ((2.0 / 3.0) * dt) * R;
+      P.out[m * n + so[k]] = v[m];
     }
+    if (ext) dt_extrema_cell(v, P.gamma, amax, bmax, rmin, bad);
+  }
+  if (ext) {
+    if (bad) atomicOr(P.status, 1u);
+    dt_extrema_commit(P.dtx, P.ntiles, blockIdx.x, amax, bmax, rmin);
   }
 }
 

@@ -61,6 +61,7 @@ SIGNATURES = {
     "gbr_residual": (_i, [_vp, _vp, _vp, _vp]),
     "gbr_rk_stage": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
     "gbr_compute_dt": (_i, [_vp, _vp, _d, _vp, _vp]),
+    "gbr_stage_dt": (_i, [_vp, _d, _vp, _vp]),
     "gbr_export_flags": (_i, [_vp, _i]),
     "gbr_get_flags": (_i, [_vp, _vp, _vp, _vp]),
     "gbr_check": (_i, [_vp, _vp]),
@@ -77,6 +78,8 @@ SIGNATURES = {
     "gbr_mlp_grad": (_i, [_vp, _vp, _vp, _vp, _i, _vp, _vp]),
     "gbr_mlp_train_step": (_i, [_vp, _vp, _vp, _vp, _i, C.c_float, _vp, _vp]),
     "gbr_set_mlp_detector": (_i, [_vp, _vp, C.c_float, _vp]),
+    "gbr_set_mlp_reuse": (_i, [_vp, _i]),
+    "gbr_mlp_get_flagmap": (_i, [_vp, _vp, _vp]),
     "gbr_batch_init": (_i, [_i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, C.POINTER(_vp)]),
     "gbr_batch_destroy": (_i, [_vp]),
     "gbr_batch_set_arrays": (_i, [_vp, _vp, _vp, _vp]),
@@ -327,6 +330,11 @@ def gbr_compute_dt(ctx, Q, cfl, dt_dev, stream=None):
                                         _scalar(dt_dev, w, "dt_dev"), _stream(stream)), w)
 
 
+def gbr_stage_dt(ctx, cfl, dt_dev, stream=None):
+    w = "gbr_stage_dt"
+    return _check(load().gbr_stage_dt(ctx, cfl, _scalar(dt_dev, w, "dt_dev"), _stream(stream)), w)
+
+
 def gbr_export_flags(ctx, enable=True):
     return _check(load().gbr_export_flags(ctx, 1 if enable else 0), "gbr_export_flags")
 
@@ -441,6 +449,22 @@ def gbr_mlp_train_step(m, feat, labels, idx, batch, lr, loss=None, stream=None):
 def gbr_set_mlp_detector(ctx, m, margin, stream=None):
     return _check(load().gbr_set_mlp_detector(ctx, m, margin, _stream(stream)),
                   "gbr_set_mlp_detector")
+
+
+def gbr_set_mlp_reuse(ctx, per_step=True):
+    return _check(load().gbr_set_mlp_reuse(ctx, 1 if per_step else 0), "gbr_set_mlp_reuse")
+
+
+def gbr_mlp_get_flagmap(ctx, chi=None, stream=None):
+    """The per-cell flag map of the last learned-detector evaluation as a host
+    uint8 array [ny][nx] (bit 0 chi^x, bit 1 chi^y), or into chi."""
+    import numpy as np
+    w = "gbr_mlp_get_flagmap"
+    nx, ny = _dims.get(ctx) or _bad(w, "unknown or destroyed context")
+    out = np.zeros((ny, nx), np.uint8) if chi is None else chi
+    _check(load().gbr_mlp_get_flagmap(ctx, _dev(out, w, "chi", ("uint8",), nx * ny, host_ok=True),
+                                      _stream(stream)), w)
+    return out
 
 
 def gbr_selftest_reciprocal(lo=0x00800000, hi=0x7E800000):

@@ -12,8 +12,13 @@ from . import gbr
 class Solver:
     def __init__(self, problem, device="cuda", stream=None, export_flags=False,
                  precision=gbr.GBR_PREC_FP64, detector=gbr.GBR_DET_PLAIN,
-                 recon=gbr.GBR_RECON_PRIM, order=7, mp_mode=gbr.GBR_MP_FLAGGED):
+                 recon=gbr.GBR_RECON_PRIM, order=7, mp_mode=gbr.GBR_MP_FLAGGED,
+                 fused_dt=False):
         import torch
+        # fused_dt: after the first step, take dt from the extrema the last
+        # stage-3 kernel reduced (gbr_stage_dt) instead of another pass over Q
+        self.fused_dt = fused_dt
+        self._stage3_fresh = False
         self.torch = torch
         self.p = problem
         self.device = device
@@ -50,6 +55,7 @@ class Solver:
 
     def set_state(self, Q):
         self.Q.copy_(self.torch.from_numpy(np.ascontiguousarray(Q, np.float64)))
+        self._stage3_fresh = False
 
     def state(self):
         self.torch.cuda.synchronize()
@@ -62,8 +68,12 @@ class Solver:
         return R
 
     def compute_dt(self, cfl=None):
-        gbr.gbr_compute_dt(self.ctx, self.Q, self.p.cfl if cfl is None else cfl, self.dt,
-                           self.stream)
+        cfl = self.p.cfl if cfl is None else cfl
+        if self.fused_dt and self._stage3_fresh:
+            gbr.gbr_stage_dt(self.ctx, cfl, self.dt, self.stream)
+            self._stage3_fresh = False
+        else:
+            gbr.gbr_compute_dt(self.ctx, self.Q, cfl, self.dt, self.stream)
         return self.dt
 
     def step(self, cfl=None):
@@ -76,6 +86,7 @@ class Solver:
         gbr.gbr_rk_stage(self.ctx, 3, self.dt, self.Q, self.Q2, self.Q1, self.stream)
         gbr.gbr_advance_time(self.ctx, self.dt, self.stream)
         self.Q, self.Q1 = self.Q1, self.Q
+        self._stage3_fresh = True
 
     def time(self):
         self.torch.cuda.synchronize()

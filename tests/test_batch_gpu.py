@@ -152,15 +152,20 @@ def test_batch_autotune_and_argument_errors():
 def test_batch512_full_size():
     """The batched workload at full size -- 512 grids of sides U{64..768}
     (about 1.1e8 cells), FP32 bulk, autotuned launch form, steps replayed as a
-    graph, as the bench runs it: no bad state, and the four smallest grids
-    agree with the CPU oracle after two steps to the FP32-bulk trajectory bar
-    (L1 <= 1e-6 per conserved variable)."""
+    graph, as the bench runs it: no bad state, and the four smallest grids,
+    the largest Riemann grid and the largest (viscous) shear-layer grid agree
+    with the CPU oracle after two steps to the FP32-bulk trajectory bar (L1 <=
+    1e-6 per conserved variable)."""
     torch = require_gpu()
     from paper_2305_00762_amd.solver import BatchSolver
     ps = [PB.vortex(n, cfl=0.5) if fam == "vortex" else PB.make(fam, n, seed=sd)
           for fam, n, sd in PB.batch_spec(512, seed=0)]
-    small = sorted(range(len(ps)), key=lambda k: ps[k].nx * ps[k].ny)[:4]
-    init = {k: np.ascontiguousarray(ps[k].Q.copy()) for k in small}
+    by_size = sorted(range(len(ps)), key=lambda k: ps[k].nx * ps[k].ny)
+    small = by_size[:4]
+    large = [max((k for k in by_size if ps[k].family == fam), key=lambda k: ps[k].nx * ps[k].ny)
+             for fam in ("riemann", "shear")]
+    assert ps[large[1]].mu > 0.0
+    init = {k: np.ascontiguousarray(ps[k].Q.copy()) for k in small + large}
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         B = BatchSolver(ps, precision=gbr.GBR_PREC_FP32_BULK, stream=s)
@@ -175,7 +180,7 @@ def test_batch512_full_size():
     s.synchronize()
     assert B.check() == gbr.GBR_OK
     st = B.states()
-    for k in small:
+    for k in small + large:
         P = ps[k]
         Q = init[k].copy()
         cfg = ocfg(P)
