@@ -312,6 +312,18 @@ int gbr_mlp_get_flagmap(gbr_ctx *ctx, uint8_t *chi, void *stream);
  * where the answer is 0.  Returns GBR_EINVAL if mismatches is NULL or lo > hi. */
 int gbr_selftest_reciprocal(uint32_t lo, uint32_t hi, uint64_t *mismatches);
 
+/* Self-test of the division inside the time-step extrema of stage 3 (one
+ * reciprocal of rho refined by two Newton steps shared by three quotients,
+ * each with one fused correction -- the steps of the hardware's IEEE
+ * division when its scaling step is idle): compares it with IEEE division on
+ * `count` operand pairs drawn by a counter-based hash from `seed`
+ * (magnitudes log-uniform over [2^-300, 2^300], random signs, every 16th
+ * numerator zero, where only the sign of a zero quotient may differ) on the
+ * current device, and writes the number of differing quotients to
+ * *mismatches (host pointer); 0 is the expected answer.  Synchronises the
+ * device.  GBR_EINVAL if mismatches is NULL. */
+int gbr_selftest_division(uint64_t seed, uint64_t count, uint64_t *mismatches);
+
 /* Synchronise `stream`, return GBR_ESTATE if any kernel since the last check
  * saw a non-finite value or rho <= 0 or p <= 0 in an interior cell, and
  * clear that record. */

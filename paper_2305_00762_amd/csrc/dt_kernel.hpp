@@ -9,7 +9,7 @@
 // atomics are used.  A bad cell (non-finite, rho <= 0, p <= 0) is recorded
 // in the status word, since fmin would otherwise drop a NaN.
 #pragma once
-#include "meg7_device.hpp"
+#include "stage_kernel.hpp"
 
 namespace gbr {
 
@@ -166,6 +166,42 @@ __global__ __launch_bounds__(kDtThreads) void dt_from_extrema_kernel(const doubl
     *dt = d;
     if (!(d > 0.0) || !isfinite(d)) atomicOr(status, 2u);
   }
+}
+
+// Self-test of div_rb (the shared-reciprocal quotient of the time-step
+// extrema) against IEEE division: `count` operand pairs drawn from a
+// counter-based hash (splitmix64 of seed + index), magnitudes log-uniform over
+// [2^-300, 2^300] with random signs, every 16th numerator zero; a zero
+// quotient may differ in sign only.
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+__device__ __forceinline__ double selftest_operand(unsigned long long h) {
+  // exponent in [-300, 299], 52 random mantissa bits, random sign
+  const long long e = (long long)((h >> 53) % 600ull) - 300;
+  const unsigned long long bits = ((unsigned long long)(e + 1023) << 52) |
+                                  (h & 0x000FFFFFFFFFFFFFull) | ((h >> 52 & 1ull) << 63);
+  return __longlong_as_double((long long)bits);
+}
+__global__ __launch_bounds__(256) void div_selftest_kernel(unsigned long long seed,
+                                                           unsigned long long count,
+                                                           unsigned long long* bad_count) {
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  unsigned long long bad = 0;
+  for (unsigned long long k = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+       k < count; k += stride) {
+    const unsigned long long h1 = splitmix64(seed + 2 * k), h2 = splitmix64(seed + 2 * k + 1);
+    const double a = (k % 16 == 15) ? 0.0 : selftest_operand(h1);
+    const double b = selftest_operand(h2);
+    const double q = div_rb(a, b, rcp_nr(b)), ref = a / b;
+    const bool same = __double_as_longlong(q) == __double_as_longlong(ref) ||
+                      (q == 0.0 && ref == 0.0);
+    if (!(div_rb_ok(a) && div_rb_ok(b)) || !same) ++bad;
+  }
+  if (bad) atomicAdd(bad_count, bad);
 }
 
 // t += dt on the device (the clock of moving boundary segments).

@@ -19,16 +19,23 @@ namespace {
 
 using namespace gbr;
 
+// Threads per workgroup of every single-grid stage kernel: a stage-3 launch
+// leaves one time-step slot per wave, kStageThreads / 64 per tile.
+constexpr int kStageThreads = 256;
+constexpr int kStageWaves = kStageThreads / 64;
+
 template <class C, bool MLP = false, bool CONS = false, int ORD = 7, bool LM = false,
           bool MPE = false>
 void launch_cfg(const StageParams& P, hipStream_t s) {
   static_assert(C::LDS_BYTES <= 160 * 1024, "LDS per workgroup");
+  static_assert(C::NT == kStageThreads, "time-step slots assume kStageThreads per workgroup");
   hipLaunchKernelGGL((meg7_stage_kernel<C, MLP, CONS, ORD, LM, MPE>), dim3(P.ntiles), dim3(C::NT),
                      0, s, P);
 }
 template <class C, bool MLP = false>
 void launch_cfg_f32(const StageParams& P, hipStream_t s) {
   static_assert(F32Cfg<C>::LDS_BYTES <= 160 * 1024, "LDS per workgroup");
+  static_assert(C::NT == kStageThreads, "time-step slots assume kStageThreads per workgroup");
   hipLaunchKernelGGL((meg7_stage_kernel_f32<C, MLP>), dim3(P.ntiles), dim3(C::NT), 0, s, P);
 }
 using LaunchFn = void (*)(const StageParams&, hipStream_t);
@@ -160,9 +167,9 @@ struct gbr_ctx {
   int export_flags;
   unsigned* d_status;         // [4]
   double* d_partial;          // [3][kDtBlocks] time-step partial extrema
-  double* d_dtx;              // [3][ntiles] per-workgroup time-step extrema of a stage-3 output
-  int dtx_cap;                // tiles d_dtx holds (the most of any tile shape)
-  int stage3_tiles;           // tiles of the last stage-3 call; 0: none since gbr_stage_dt
+  double* d_dtx;              // [3][slots] per-wave time-step extrema of a stage-3 output
+  int dtx_cap;                // slots d_dtx holds (the most of any tile shape)
+  int stage3_slots;           // slots of the last stage-3 call; 0: none since gbr_stage_dt
   uint8_t* d_sigx;
   uint8_t* d_sigy;
   int tiling;                 // index into kVariants
@@ -238,12 +245,12 @@ int gbr_init(int nx, int ny, double gamma, double mu, double Pr, gbr_ctx** out) 
     (void)hipFree(c->d_status); (void)hipFree(c->d_partial); (void)hipFree(c->d_sides);
     delete c; return GBR_ENOMEM;
   }
-  // per-workgroup time-step extrema of stage-3 outputs: room for the tiles
-  // of the smallest tile shape
+  // per-wave time-step extrema of stage-3 outputs: room for the waves of
+  // the smallest tile shape
   c->dtx_cap = 0;
   for (int v = 0; v < kNumVariants; ++v) {
     const int t = ((nx + kVariants[v].tx - 1) / kVariants[v].tx) *
-                  ((ny + kVariants[v].ty - 1) / kVariants[v].ty);
+                  ((ny + kVariants[v].ty - 1) / kVariants[v].ty) * kStageWaves;
     c->dtx_cap = t > c->dtx_cap ? t : c->dtx_cap;
   }
   if (hipMalloc(&c->d_dtx, 3 * (size_t)c->dtx_cap * sizeof(double)) != hipSuccess) {
@@ -491,7 +498,7 @@ static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn
   if (tev && hipEventRecord(tev[1], s) != hipSuccess) return GBR_EDEVICE;
   variant_fn(c, vi)(P, s);
   if (tev && hipEventRecord(tev[2], s) != hipSuccess) return GBR_EDEVICE;
-  if (mode == MODE_STAGE3) c->stage3_tiles = P.ntiles;
+  if (mode == MODE_STAGE3) c->stage3_slots = P.ntiles * kStageWaves;
   return hip_ok(hipGetLastError());
 }
 
@@ -605,16 +612,16 @@ int gbr_compute_dt(gbr_ctx* c, const double* Q, double cfl, double* dt_dev, void
 }
 
 int gbr_stage_dt(gbr_ctx* c, double cfl, double* dt_dev, void* stream) {
-  if (!c || !dt_dev || !(cfl > 0.0) || c->stage3_tiles <= 0) return GBR_EINVAL;
+  if (!c || !dt_dev || !(cfl > 0.0) || c->stage3_slots <= 0) return GBR_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  const int nslot = c->stage3_tiles;
+  const int nslot = c->stage3_slots;
   const int blocks = dt_blocks((size_t)nslot);
   hipLaunchKernelGGL(dt_extrema_reduce_kernel, dim3(blocks), dim3(kDtThreads), 0, s,
                      (const double*)c->d_dtx, nslot, c->d_partial);
   hipLaunchKernelGGL(dt_from_extrema_kernel, dim3(1), dim3(kDtThreads), 0, s,
                      (const double*)c->d_partial, blocks, dt_dev, cfl,
                      (c->x1 - c->x0) / c->nx, (c->y1 - c->y0) / c->ny, c->mu, c->d_status);
-  c->stage3_tiles = 0;
+  c->stage3_slots = 0;
   return hip_ok(hipGetLastError());
 }
 
@@ -786,6 +793,25 @@ int gbr_selftest_reciprocal(uint32_t lo, uint32_t hi, uint64_t* mismatches) {
   bool ok = hipMemset(d, 0, sizeof(*d)) == hipSuccess;
   if (ok && hi > lo) {
     hipLaunchKernelGGL(rcp_selftest_kernel, dim3(8192), dim3(256), 0, 0, lo, hi, d);
+    ok = hipGetLastError() == hipSuccess;
+  }
+  ok = ok && hipDeviceSynchronize() == hipSuccess &&
+       hipMemcpy(&h, d, sizeof(h), hipMemcpyDeviceToHost) == hipSuccess;
+  (void)hipFree(d);
+  if (!ok) return GBR_EDEVICE;
+  *mismatches = h;
+  return GBR_OK;
+}
+
+int gbr_selftest_division(uint64_t seed, uint64_t count, uint64_t* mismatches) {
+  if (!mismatches) return GBR_EINVAL;
+  unsigned long long* d = nullptr;
+  if (hipMalloc(&d, sizeof(*d)) != hipSuccess) return GBR_ENOMEM;
+  unsigned long long h = 0;
+  bool ok = hipMemset(d, 0, sizeof(*d)) == hipSuccess;
+  if (ok && count > 0) {
+    hipLaunchKernelGGL(div_selftest_kernel, dim3(8192), dim3(256), 0, 0, (unsigned long long)seed,
+                       (unsigned long long)count, d);
     ok = hipGetLastError() == hipSuccess;
   }
   ok = ok && hipDeviceSynchronize() == hipSuccess &&

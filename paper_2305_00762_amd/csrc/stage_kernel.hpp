@@ -52,8 +52,8 @@ struct StageParams {
   const double* tnow;             // device time of Q^n (moving boundary segments)
   double tc;                      // stage abscissa: boundary time = tnow + tc dt
   double x0, y0, dx, dy;          // cell-centre coordinates of the boundary segments
-  // stage 3 only (else null): per-workgroup time-step extrema of the output,
-  // [3][ntiles]: max(|u|+c), max(|v|+c), min rho
+  // stage 3 only (else null): per-wave time-step extrema of the output,
+  // [3][ntiles x waves per workgroup]: max(|u|+c), max(|v|+c), min rho
   double* dtx;
 };
 
@@ -595,6 +595,24 @@ __device__ __forceinline__ void stage_load(const StageParams& P, double* sU, int
   if (bad) atomicOr(P.status, STATUS_BAD_STATE);
 }
 
+// fl(a / b) from rb = rcp_nr(b): the quotient a rb and one correction by the
+// exact residual.  These are the steps of the hardware's IEEE division after
+// its scaling step (reciprocal estimate, two Newton steps, quotient, fused
+// correction), and that step leaves operands unchanged when both magnitudes
+// lie in [2^-300, 2^300] or the numerator is zero (div_rb_ok): there the
+// result is the IEEE quotient bit for bit, up to the sign of a zero result
+// (gbr_selftest_division checks it on the device).  One reciprocal then
+// serves the three quotients of a cell.
+__device__ __forceinline__ double div_rb(double a, double b, double rb) {
+#pragma clang fp contract(off)
+  const double q = a * rb;
+  return fma(fma(-b, q, a), rb, q);
+}
+__device__ __forceinline__ bool div_rb_ok(double a) {
+  const double m = fabs(a);
+  return m <= 0x1p300 && (m >= 0x1p-300 || m == 0.0);
+}
+
 // Time-step extrema of one cell of the new state (Sec. 2.5): |u|+c, |v|+c
 // and rho, each rounded exactly as the time-step kernel rounds them (one
 // rounding per operation, IEEE division and square root), folded into
@@ -604,39 +622,73 @@ __device__ __forceinline__ void dt_extrema_cell(const double q[4], double gamma,
                                                 double& bmax, double& rmin, bool& bad) {
 #pragma clang fp contract(off)
   const double rho = q[0];
-  const double u = q[1] / rho, v = q[2] / rho;
+  const double rb = rcp_nr(rho);
+  const bool fast = rho != 0.0 && div_rb_ok(rho) && div_rb_ok(q[1]) && div_rb_ok(q[2]);
+  double u, v;
+  if (fast) {
+    u = div_rb(q[1], rho, rb);
+    v = div_rb(q[2], rho, rb);
+  } else {
+    u = q[1] / rho;
+    v = q[2] / rho;
+  }
   const double p = (gamma - 1.0) * (q[3] - rho * (u * u + v * v) / 2.0);
-  const double c = sqrt(gamma * p / rho);
+  const double gp = gamma * p;
+  const double c = sqrt((fast && div_rb_ok(gp)) ? div_rb(gp, rho, rb) : gp / rho);
   if (!(rho > 0.0) || !(p > 0.0) || !isfinite(c) || !isfinite(u) || !isfinite(v)) bad = true;
   amax = fmax(amax, fabs(u) + c);
   bmax = fmax(bmax, fabs(v) + c);
   rmin = fmin(rmin, rho);
 }
 
-// Workgroup extrema written to slot `slot` of the partial arrays w[3][nslot]
-// (plain stores; the time-step kernels reduce the slots in a fixed order).
-// Every thread of the workgroup calls it.
+// A double moved across lanes by a DPP pattern (both 32-bit halves); lanes
+// without a source lane, and rows the row mask leaves out, get `ident`.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v, double ident) {
+  const long long b = __double_as_longlong(v), id = __double_as_longlong(ident);
+  const int lo = __builtin_amdgcn_update_dpp((int)id, (int)b, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(id >> 32), (int)(b >> 32), CTRL, ROWS, 0xf,
+                                             false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned)lo));
+}
+
+// Maximum (MAX) or minimum over the 64 lanes of the wave, in VALU lane moves:
+// row shifts by 1, 2, 4, 8 leave each row's extremum in its lane 15, the
+// broadcasts of lanes 15 and 31 carry it into rows 1 and 3 and then rows 2
+// and 3, so lane 63 ends with the wave's extremum, which is read out.
+template <bool MAX>
+__device__ __forceinline__ double wave_extremum(double x) {
+  const double id = MAX ? -__builtin_inf() : __builtin_inf();
+  auto op = [](double a, double b) { return MAX ? fmax(a, b) : fmin(a, b); };
+  x = op(x, dpp_f64<0x111, 0xf>(x, id));   // row_shr:1
+  x = op(x, dpp_f64<0x112, 0xf>(x, id));   // row_shr:2
+  x = op(x, dpp_f64<0x114, 0xf>(x, id));   // row_shr:4
+  x = op(x, dpp_f64<0x118, 0xf>(x, id));   // row_shr:8
+  x = op(x, dpp_f64<0x142, 0xa>(x, id));   // row_bcast:15 into rows 1, 3
+  x = op(x, dpp_f64<0x143, 0xc>(x, id));   // row_bcast:31 into rows 2, 3
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned)lo));
+}
+
+// Wave extrema written to slot `slot` of the partial arrays w[3][nslot]
+// (plain stores, no barrier; the time-step kernels reduce the slots).  With
+// square cells (dx = dy) min(fl(dx/a), fl(dy/b)) = fl(dx/max(a, b)), so one
+// maximum serves both slots; without viscosity min rho is not needed.  Every
+// lane of the wave calls it (square, visc uniform).
 __device__ __forceinline__ void dt_extrema_commit(double* w, int nslot, int slot, double a,
-                                                  double b, double r) {
-  __shared__ double red[3][16];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    a = fmax(a, __shfl_xor(a, o));
-    b = fmax(b, __shfl_xor(b, o));
-    r = fmin(r, __shfl_xor(r, o));
-  }
-  const int wv = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
-  if (__lane_id() == 0) { red[0][wv] = a; red[1][wv] = b; red[2][wv] = r; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int k = 1; k < nw; ++k) {
-      a = fmax(a, red[0][k]);
-      b = fmax(b, red[1][k]);
-      r = fmin(r, red[2][k]);
-    }
+                                                  double b, double r, bool square, bool visc) {
+  if (square) a = fmax(a, b);
+  a = wave_extremum<true>(a);
+  if (!square) b = wave_extremum<true>(b);
+  if (visc) r = wave_extremum<false>(r);
+  if (__lane_id() == 0) {
     w[slot] = a;
-    w[nslot + slot] = b;
-    w[2 * nslot + slot] = r;
+    w[nslot + slot] = square ? a : b;
+    w[2 * nslot + slot] = visc ? r : __builtin_inf();
   }
 }
 
@@ -666,31 +718,40 @@ __device__ __forceinline__ void stage_store(const StageParams& P, const double (
       qk[k][m] = (own[k] && P.mode >= MODE_STAGE2) ? P.Qk[m * n + so[k]] : 0.0;
     }
   }
-  const bool ext = P.dtx != nullptr;
-  double amax = 0.0, bmax = 0.0, rmin = __builtin_inf();
-  bool bad = false;
+  double v[C::CPT][4];
 #pragma unroll
   for (int k = 0; k < C::CPT; ++k) {
-    if (!own[k]) continue;
-    double v[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const double R = res[k][m];
       if (P.mode == MODE_RESIDUAL)
-        v[m] = R;
+        v[k][m] = R;
       else if (P.mode == MODE_STAGE1)
-        v[m] = qn[k][m] + dt * R;
+        v[k][m] = qn[k][m] + dt * R;
       else if (P.mode == MODE_STAGE2)
-        v[m] = 0.75 * qn[k][m] + 0.25 * qk[k][m] + (0.25 * dt) * R;
+        v[k][m] = 0.75 * qn[k][m] + 0.25 * qk[k][m] + (0.25 * dt) * R;
       else
-        v[m] = (1.0 / 3.0) * qn[k][m] + (2.0 / 3.0) * qk[k][m] + ((2.0 / 3.0) * dt) * R;
-      P.out[m * n + so[k]] = v[m];
+        v[k][m] = (1.0 / 3.0) * qn[k][m] + (2.0 / 3.0) * qk[k][m] + ((2.0 / 3.0) * dt) * R;
     }
-    if (ext) dt_extrema_cell(v, P.gamma, amax, bmax, rmin, bad);
   }
-  if (ext) {
+  if (P.dtx) {
+    // the time-step extrema of the new state, before the stores (stores
+    // first would make the wave wait for them before reusing their registers)
+    double amax = 0.0, bmax = 0.0, rmin = __builtin_inf();
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < C::CPT; ++k)
+      if (own[k]) dt_extrema_cell(v[k], P.gamma, amax, bmax, rmin, bad);
     if (bad) atomicOr(P.status, 1u);
-    dt_extrema_commit(P.dtx, P.ntiles, blockIdx.x, amax, bmax, rmin);
+    constexpr int NW = NT / 64;
+    dt_extrema_commit(P.dtx, P.ntiles * NW, blockIdx.x * NW + (threadIdx.x >> 6), amax, bmax,
+                      rmin, P.dx == P.dy, P.mu > 0.0);
+  }
+#pragma unroll
+  for (int k = 0; k < C::CPT; ++k) {
+    if (!own[k]) continue;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) P.out[m * n + so[k]] = v[k][m];
   }
 }
 

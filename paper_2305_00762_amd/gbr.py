@@ -99,6 +99,7 @@ SIGNATURES = {
                              C.POINTER(C.c_uint64)]),
     "gbr_mlp_stats": (_i, [_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), _i]),
     "gbr_selftest_reciprocal": (_i, [C.c_uint32, C.c_uint32, C.POINTER(C.c_uint64)]),
+    "gbr_selftest_division": (_i, [C.c_uint64, C.c_uint64, C.POINTER(C.c_uint64)]),
     "gbr3_init": (_i, [_i, _i, _i, _d, C.POINTER(_vp)]),
     "gbr3_destroy": (_i, [_vp]),
     "gbr3_set_geometry": (_i, [_vp, _d, _d, _d, _d, _d, _d, _i, _i, _i]),
@@ -472,6 +473,13 @@ def gbr_selftest_reciprocal(lo=0x00800000, hi=0x7E800000):
     from IEEE division (0 over the default range)."""
     n = C.c_uint64()
     _check(load().gbr_selftest_reciprocal(lo, hi, C.byref(n)), "gbr_selftest_reciprocal")
+    return n.value
+
+
+def gbr_selftest_division(seed=1, count=1 << 26):
+    """Operand pairs whose time-step quotient differs from IEEE division (0)."""
+    n = C.c_uint64()
+    _check(load().gbr_selftest_division(seed, count, C.byref(n)), "gbr_selftest_division")
     return n.value
 
 

@@ -1,6 +1,7 @@
 """The time step reduced inside the stage-3 kernel (Sec. 2.5; gbr_stage_dt)
 against the two-pass reduction over the state (gbr_compute_dt) and the
-oracle's time step: bit for bit on the state the stage-3 call wrote, for
+oracle's time step: its division replica equals IEEE division on random
+operands; bit for bit on the state the stage-3 call wrote, for
 inviscid and viscous grids, periodic and transmissive, FP64 and FP32 bulk,
 both default tilings; a trajectory stepped with it equals, bit for bit, one
 stepped with the separate reduction; without a stage-3 call since the last
@@ -18,8 +19,17 @@ pytestmark = pytest.mark.gpu
 CASES = {
     "riemann": lambda: PB.riemann(90, seed=3, ny=70),
     "shear": lambda: PB.shear(64, seed=2, ny=48),
+    "shear_square": lambda: PB.shear(64, seed=2),
     "vortex": lambda: PB.vortex(48),
 }
+
+
+def test_division_replica_is_ieee():
+    """The shared-reciprocal quotient of the stage-3 extrema equals IEEE
+    division on 2^27 random operand pairs of its range (and zero numerators)."""
+    require_gpu()
+    assert gbr.gbr_selftest_division(seed=1, count=1 << 27) == 0
+    assert gbr.gbr_selftest_division(seed=2 ** 40 + 7, count=1 << 27) == 0
 
 
 def dt_bits(t):
