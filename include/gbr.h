@@ -179,6 +179,24 @@ int gbr_rk_stage(gbr_ctx *ctx, int stage, const double *dt_dev, const double *Qn
 int gbr_compute_dt(gbr_ctx *ctx, const double *Q, double cfl, double *dt_dev,
                    void *stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the time
+ * step of gbr_compute_dt without a context and without any allocation.  The
+ * grid is nx x ny cells (1 <= nx, ny; nx ny <= GBR_NOALLOC_MAX_CELLS) of size
+ * dx x dy (> 0), gamma > 1, mu >= 0, cfl > 0; Q and dt_dev as for
+ * gbr_compute_dt (caller-owned device memory).  The reduction's scratch --
+ * partial minima of at most 1024 first-pass workgroups and a status word,
+ * 16.5 KB -- is a file-scope device array of the library, one per GPU, held
+ * until the process ends; its address is looked up once per device (on the
+ * first call there, or by gbr_init).  A bad state (non-finite, rho <= 0,
+ * p <= 0) makes *dt_dev NaN, since there is no context to report it to; the
+ * status word is cleared again by the call.  Calls that overlap on one GPU
+ * (on different streams) share that scratch and race: serialise them.
+ * Returns GBR_EINVAL for sizes beyond the limits. */
+#define GBR_NOALLOC_MAX_CELLS (1 << 29)
+int gbr_compute_dt_noalloc(int nx, int ny, double dx, double dy, double gamma, double mu,
+                           const double *Q, double cfl, double *dt_dev, void *stream);
+
 /* The same time step (Sec. 2.5) of the state the last stage-3 call wrote,
  * without another pass over it: every stage-3 call (gbr_rk_stage with
  * stage = 3) reduces, while it writes Q^(n+1), the extrema the time step

@@ -101,6 +101,30 @@ __global__ __launch_bounds__(kDtThreads) void dt_finish_kernel(const double* par
   }
 }
 
+// Second pass of the time step without a context: as dt_finish_kernel, with
+// the status word in the same scratch as the partials.  A bad state seen by
+// the first pass makes dt NaN (the caller has no context to ask), and the
+// word is cleared for the next call.
+__global__ __launch_bounds__(kDtThreads) void dt_finish_noalloc_kernel(const double* partial,
+                                                                       int nblk, double* dt,
+                                                                       double cfl,
+                                                                       unsigned* status) {
+#pragma clang fp contract(off)
+  __shared__ double red[kDtThreads / 64];
+  double conv = __builtin_inf(), visc = __builtin_inf();
+  for (int k = threadIdx.x; k < nblk; k += blockDim.x) {
+    conv = fmin(conv, partial[k]);
+    visc = fmin(visc, partial[kDtBlocks + k]);
+  }
+  conv = block_min(conv, red);
+  visc = block_min(visc, red);
+  if (threadIdx.x == 0) {
+    const double d = cfl * fmin(visc / kAlphaV, conv);
+    *dt = (*status != 0u) ? __builtin_nan("") : d;
+    *status = 0u;
+  }
+}
+
 // dt from the extrema the stage-3 kernel left per workgroup, in two passes
 // like the reduction above: pass 1 folds the slots [3][nslot] into
 // kDtBlocks partial extrema, pass 2 (one workgroup) finishes with the

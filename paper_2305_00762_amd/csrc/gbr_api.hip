@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -203,6 +204,32 @@ struct gbr_mlp {
   int t;                      // Adam step count
 };
 
+// Scratch of the entry point that allocates nothing (gbr_compute_dt_noalloc):
+// the first pass's partial minima [2][kDtBlocks], then a status word.  In host
+// code the name `scratch` is only a stand-in for the device array: its device
+// address, one per GPU, comes from hipGetSymbolAddress and is kept below.
+constexpr int kNoallocScratchDoubles = 2 * gbr::kDtBlocks + 32;
+static __device__ __align__(256) double scratch[kNoallocScratchDoubles];
+constexpr int kNoallocMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static double* g_scratch_ptr[kNoallocMaxDevices];
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+static int noalloc_scratch(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return GBR_EDEVICE;
+  if (dev < 0 || dev >= kNoallocMaxDevices) return GBR_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GBR_EDEVICE;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return GBR_OK;
+}
+
 extern "C" {
 
 const char* gbr_strerror(int s) {
@@ -257,9 +284,10 @@ int gbr_init(int nx, int ny, double gamma, double mu, double Pr, gbr_ctx** out) 
     (void)hipFree(c->d_status); (void)hipFree(c->d_partial); (void)hipFree(c->d_sides);
     (void)hipFree(c->d_time); delete c; return GBR_ENOMEM;
   }
+  double* noalloc = nullptr;   // set-up of the allocation-free entry point on this device
   if (hipMemset(c->d_status, 0, 4 * sizeof(unsigned)) != hipSuccess ||
       hipMemset(c->d_time, 0, sizeof(double)) != hipSuccess ||
-      hipDeviceSynchronize() != hipSuccess) {
+      noalloc_scratch(&noalloc) != GBR_OK || hipDeviceSynchronize() != hipSuccess) {
     (void)hipFree(c->d_status); (void)hipFree(c->d_partial); (void)hipFree(c->d_sides);
     (void)hipFree(c->d_time); (void)hipFree(c->d_dtx); delete c; return GBR_EDEVICE;
   }
@@ -608,6 +636,27 @@ int gbr_compute_dt(gbr_ctx* c, const double* Q, double cfl, double* dt_dev, void
   hipLaunchKernelGGL(dt_reduce_kernel, dim3(blocks), dim3(kDtThreads), 0, s, P);
   hipLaunchKernelGGL(dt_finish_kernel, dim3(1), dim3(kDtThreads), 0, s, c->d_partial, blocks,
                      dt_dev, cfl, c->d_status);
+  return hip_ok(hipGetLastError());
+}
+
+int gbr_compute_dt_noalloc(int nx, int ny, double dx, double dy, double gamma, double mu,
+                           const double* Q, double cfl, double* dt_dev, void* stream) {
+  if (nx < 1 || ny < 1 || (long long)nx * ny > (long long)GBR_NOALLOC_MAX_CELLS) return GBR_EINVAL;
+  if (!Q || !dt_dev || !(dx > 0.0) || !(dy > 0.0) || !(gamma > 1.0) || !(mu >= 0.0) ||
+      !(cfl > 0.0))
+    return GBR_EINVAL;
+  double* ptr = nullptr;
+  const int rc = noalloc_scratch(&ptr);
+  if (rc != GBR_OK) return rc;
+  unsigned* status = reinterpret_cast<unsigned*>(ptr + 2 * kDtBlocks);
+  hipStream_t s = (hipStream_t)stream;
+  DtParams P{};
+  P.Q = Q; P.partial = ptr; P.dt = dt_dev; P.status = status;
+  P.nx = nx; P.ny = ny; P.dx = dx; P.dy = dy; P.gamma = gamma; P.mu = mu; P.cfl = cfl;
+  const int blocks = dt_blocks((size_t)nx * ny);   // <= kDtBlocks: the partials fit
+  hipLaunchKernelGGL(dt_reduce_kernel, dim3(blocks), dim3(kDtThreads), 0, s, P);
+  hipLaunchKernelGGL(dt_finish_noalloc_kernel, dim3(1), dim3(kDtThreads), 0, s,
+                     (const double*)ptr, blocks, dt_dev, cfl, status);
   return hip_ok(hipGetLastError());
 }
 

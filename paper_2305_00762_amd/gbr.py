@@ -62,6 +62,7 @@ SIGNATURES = {
     "gbr_rk_stage": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
     "gbr_compute_dt": (_i, [_vp, _vp, _d, _vp, _vp]),
     "gbr_stage_dt": (_i, [_vp, _d, _vp, _vp]),
+    "gbr_compute_dt_noalloc": (_i, [_i, _i, _d, _d, _d, _d, _vp, _d, _vp, _vp]),
     "gbr_export_flags": (_i, [_vp, _i]),
     "gbr_get_flags": (_i, [_vp, _vp, _vp, _vp]),
     "gbr_check": (_i, [_vp, _vp]),
@@ -334,6 +335,13 @@ def gbr_compute_dt(ctx, Q, cfl, dt_dev, stream=None):
 def gbr_stage_dt(ctx, cfl, dt_dev, stream=None):
     w = "gbr_stage_dt"
     return _check(load().gbr_stage_dt(ctx, cfl, _scalar(dt_dev, w, "dt_dev"), _stream(stream)), w)
+
+
+def gbr_compute_dt_noalloc(nx, ny, dx, dy, gamma, mu, Q, cfl, dt_dev, stream=None):
+    w = "gbr_compute_dt_noalloc"
+    q = _dev(Q, w, "Q", ("float64",), 4 * nx * ny, exact=True)
+    return _check(load().gbr_compute_dt_noalloc(nx, ny, dx, dy, gamma, mu, q, cfl,
+                                                _scalar(dt_dev, w, "dt_dev"), _stream(stream)), w)
 
 
 def gbr_export_flags(ctx, enable=True):
