@@ -40,6 +40,24 @@ __device__ __forceinline__ double sqrt_nr(double x) {
   return fma(0.5 * y, fma(-s, s, x), s);
 }
 
+// fl(a / b) from rb = rcp_nr(b): the quotient a rb and one correction by the
+// exact residual.  These are the steps of the hardware's IEEE division after
+// its scaling step (reciprocal estimate, two Newton steps, quotient, fused
+// correction), and that step leaves operands unchanged when both magnitudes
+// lie in [2^-300, 2^300] or the numerator is zero (div_rb_ok): there the
+// result is the IEEE quotient bit for bit, up to the sign of a zero result
+// (gbr_selftest_division checks it on the device).  One reciprocal then
+// serves the three quotients of a cell.
+__device__ __forceinline__ double div_rb(double a, double b, double rb) {
+#pragma clang fp contract(off)
+  const double q = a * rb;
+  return fma(fma(-b, q, a), rb, q);
+}
+__device__ __forceinline__ bool div_rb_ok(double a) {
+  const double m = fabs(a);
+  return m <= 0x1p300 && (m >= 0x1p-300 || m == 0.0);
+}
+
 // Sixth-order central first derivative, eq. (eqn:six), scaled by the
 // spacing: returns dx * dPhi/dx from Phi_{-3..3} (pm3 .. p3).
 __device__ __forceinline__ double grad6(double pm3, double pm2, double pm1, double p1,

@@ -293,11 +293,20 @@ __device__ __forceinline__ int wrap_bc(int k, int n, int bc) {
 
 // Pressure of a cell as the features define it: u = (rho u)/rho and v by
 // IEEE division, p = (gamma-1) (E - rho (u u + v v) / 2), every product and
-// sum rounded on its own.
+// sum rounded on its own.  The two quotients share one refined reciprocal
+// (div_rb: the IEEE quotient bit for bit inside its operand range).
 __device__ __forceinline__ double mlp_cell_pressure(double r, double mx, double my, double E,
                                                     double gamma) {
 #pragma clang fp contract(off)
-  const double u = mx / r, v = my / r;
+  double u, v;
+  if (r != 0.0 && div_rb_ok(r) && div_rb_ok(mx) && div_rb_ok(my)) {
+    const double rb = rcp_nr(r);
+    u = div_rb(mx, r, rb);
+    v = div_rb(my, r, rb);
+  } else {
+    u = mx / r;
+    v = my / r;
+  }
   return (gamma - 1.0) * (E - r * (u * u + v * v) / 2.0);
 }
 

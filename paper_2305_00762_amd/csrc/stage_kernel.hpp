@@ -119,10 +119,12 @@ template <class C>
 __device__ __forceinline__ void load_chimap(const StageParams& P, unsigned char* chif, int tx0,
                                             int ty0) {
   constexpr int W6 = C::TX + 6, NC = (C::TX + 6) * (C::TY + 6);
+  const bool inner = tx0 >= 3 && ty0 >= 3 && tx0 + C::TX + 3 <= P.nx && ty0 + C::TY + 3 <= P.ny;
   for (int c = threadIdx.x; c < NC; c += C::NT) {
-    const int gi = bc_index(ty0 + c / W6 - 3, P.ny, P.bcy);
-    const int gj = bc_index(tx0 + c % W6 - 3, P.nx, P.bcx);
-    chif[c] = P.chimap[(size_t)gi * P.nx + gj];
+    const int ly = c / W6 - 3, lx = c - (ly + 3) * W6 - 3;
+    const int gi = inner ? ty0 + ly : bc_index(ty0 + ly, P.ny, P.bcy);
+    const int gj = inner ? tx0 + lx : bc_index(tx0 + lx, P.nx, P.bcx);
+    chif[c] = P.chimap[gi * P.nx + gj];
   }
 }
 
@@ -515,10 +517,10 @@ __device__ __forceinline__ void stage_load(const StageParams& P, double* sU, int
   const int tid = threadIdx.x;
   const size_t n = (size_t)P.nx * P.ny;
   bool bad = false;
-  // one cell of the tile: conservative values (ghost rules applied) to the
-  // staged variables; op as packed by ghost_op
-  auto put = [&](int c, double r, double mx, double my, double E, unsigned op) {
-    const int ly = c / RX - H, lx = c % RX - H;
+  // one cell of the tile at (lx, ly): conservative values (ghost rules
+  // applied) to the staged variables; op as packed by ghost_op
+  auto put = [&](int lx, int ly, double r, double mx, double my, double E, unsigned op) {
+    const int c = (ly + H) * RX + (lx + H);
     if (op & 1u) mx = -mx;
     if (op & 2u) my = -my;
     double ir = rcp_nr(r);
@@ -543,29 +545,40 @@ __device__ __forceinline__ void stage_load(const StageParams& P, double* sU, int
                       isfinite(r)))
       bad = true;
   };
+  // a tile whose halo stays inside the grid needs no ghost rules
+  const bool inner = tx0 >= H && ty0 >= H && tx0 + TX + H <= P.nx && ty0 + TY + H <= P.ny;
   // the side table matters only where the tile's halo reaches past the grid
-  const bool walls = P.sides != nullptr &&
-                     !(tx0 >= H && ty0 >= H && tx0 + TX + H <= P.nx && ty0 + TY + H <= P.ny);
+  const bool walls = P.sides != nullptr && !inner;
   if (!walls) {
     // all global loads issued before any is consumed: the memory latency is
-    // paid once rather than once per round
+    // paid once rather than once per round.  Element offsets fit 32 bits
+    // (4 nx ny <= 2^31 - 1).
     double q[LR][4];
+    const double* Q0 = P.Qk;
+    const double* Q1 = P.Qk + n;
+    const double* Q2 = P.Qk + 2 * n;
+    const double* Q3 = P.Qk + 3 * n;
 #pragma unroll
     for (int k = 0; k < LR; ++k) {
       const int c = tid + k * NT;
       if (c < RS) {
-        const int ly = c / RX - H, lx = c % RX - H;
-        const int gi = bc_index(ty0 + ly, P.ny, P.bcy);
-        const int gj = bc_index(tx0 + lx, P.nx, P.bcx);
-        const size_t s = (size_t)gi * P.nx + gj;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) q[k][m] = P.Qk[m * n + s];
+        const int ly = c / RX - H, lx = c - (ly + H) * RX - H;
+        const int gi = inner ? ty0 + ly : bc_index(ty0 + ly, P.ny, P.bcy);
+        const int gj = inner ? tx0 + lx : bc_index(tx0 + lx, P.nx, P.bcx);
+        const int o = gi * P.nx + gj;
+        q[k][0] = Q0[o];
+        q[k][1] = Q1[o];
+        q[k][2] = Q2[o];
+        q[k][3] = Q3[o];
       }
     }
 #pragma unroll
     for (int k = 0; k < LR; ++k) {
       const int c = tid + k * NT;
-      if (c < RS) put(c, q[k][0], q[k][1], q[k][2], q[k][3], 0u);
+      if (c < RS) {
+        const int ly = c / RX - H, lx = c - (ly + H) * RX - H;
+        put(lx, ly, q[k][0], q[k][1], q[k][2], q[k][3], 0u);
+      }
     }
   } else {
     // boundary tiles with a side table: one cell at a time
@@ -588,29 +601,11 @@ __device__ __forceinline__ void stage_load(const StageParams& P, double* sU, int
       const int kx = side_kind(P, 0, j, yc, tb, sx, gx, gj);
       const int ky = side_kind(P, 1, i, xc, tb, sy, gy, gi);
       const size_t s = (size_t)gi * P.nx + gj;
-      put(c, P.Qk[s], P.Qk[n + s], P.Qk[2 * n + s], P.Qk[3 * n + s],
+      put(lx, ly, P.Qk[s], P.Qk[n + s], P.Qk[2 * n + s], P.Qk[3 * n + s],
           ghost_op(kx, ky, sx, gx, sy, gy));
     }
   }
   if (bad) atomicOr(P.status, STATUS_BAD_STATE);
-}
-
-// fl(a / b) from rb = rcp_nr(b): the quotient a rb and one correction by the
-// exact residual.  These are the steps of the hardware's IEEE division after
-// its scaling step (reciprocal estimate, two Newton steps, quotient, fused
-// correction), and that step leaves operands unchanged when both magnitudes
-// lie in [2^-300, 2^300] or the numerator is zero (div_rb_ok): there the
-// result is the IEEE quotient bit for bit, up to the sign of a zero result
-// (gbr_selftest_division checks it on the device).  One reciprocal then
-// serves the three quotients of a cell.
-__device__ __forceinline__ double div_rb(double a, double b, double rb) {
-#pragma clang fp contract(off)
-  const double q = a * rb;
-  return fma(fma(-b, q, a), rb, q);
-}
-__device__ __forceinline__ bool div_rb_ok(double a) {
-  const double m = fabs(a);
-  return m <= 0x1p300 && (m >= 0x1p-300 || m == 0.0);
 }
 
 // Time-step extrema of one cell of the new state (Sec. 2.5): |u|+c, |v|+c
