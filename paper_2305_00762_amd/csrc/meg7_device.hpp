@@ -79,6 +79,25 @@ __device__ __forceinline__ double detector_psi(double rm2, double rm1, double r0
   return num / den;
 }
 
+// The detector's decision psi < psi_c (= 1/2) without the division: with
+// num = 2ab + eps and den = a^2 + b^2 + eps as above (both positive),
+// fl(num / den) < 1/2 holds exactly when num / den < 1/2 - 2^-55 (the rounding
+// boundary below 1/2; a tie rounds to 1/2, whose significand is even), i.e.
+// when 2 num - den < -den 2^-54.  2 num is exact, 2 num - den is exact
+// wherever the two are within a factor 2 of each other (Sterbenz) and has the
+// sign that decides otherwise, and den 2^-54 is exact: the comparison below
+// is the division's decision bit for bit, for a fraction of its cost.
+static_assert(kPsiC == 0.5, "the division-free decision assumes psi_c = 1/2");
+__device__ __forceinline__ bool detector_flag(double rm2, double rm1, double r0, double rp1,
+                                              double rp2) {
+#pragma clang fp contract(off)
+  double a = fabs(r0 - rm1) + fabs((r0 - 2.0 * rm1) + rm2);
+  double b = fabs(r0 - rp1) + fabs((r0 - 2.0 * rp1) + rp2);
+  double num = (2.0 * a) * b + kDetEps;
+  double den = (a * a + b * b) + kDetEps;
+  return (2.0 * num - den) < -(den * 0x1p-54);
+}
+
 __device__ __forceinline__ double minmod(double a, double b) {
   // (sign a + sign b)/2 * min(|a|,|b|), eq. (eqn:alpha)
   double m = fmin(fabs(a), fabs(b));

@@ -478,8 +478,7 @@ __global__ __launch_bounds__(256, 4) void mlp_chi_kernel(MlpChiParams P) {
     auto rho = [&](int o) {
       return P.Q[(size_t)gwrap(gi + o * si, P.ny, P.bcy) * P.nx + gwrap(gj + o * sj, P.nx, P.bcx)];
     };
-    const double psi = detector_psi(rho(-2), rho(-1), rho(0), rho(1), rho(2));
-    if (psi < kPsiC) {
+    if (detector_flag(rho(-2), rho(-1), rho(0), rho(1), rho(2))) {
       if (ydir) sCy[cell] = 2; else sCx[cell] = 1;
     }
   }

@@ -219,8 +219,7 @@ __global__ __launch_bounds__(256, 2) void meg7_sweep3_kernel(Sweep3Params P) {
         sD[m][l][pd] = grad6(u[-3], u[-2], u[-1], u[1], u[2], u[3]);
       }
       const double* rho = &sW[0][l][p];
-      const double psi = detector_psi(rho[-2], rho[-1], rho[0], rho[1], rho[2]);
-      sChi[l][pd] = (psi < kPsiC) ? 1 : 0;
+      sChi[l][pd] = detector_flag(rho[-2], rho[-1], rho[0], rho[1], rho[2]) ? 1 : 0;
     }
   }
   __syncthreads();

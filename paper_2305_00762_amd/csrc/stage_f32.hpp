@@ -173,8 +173,8 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
             (L.chif[mlp_chi_index<C>(X ? k : l0 + line, X ? l0 + line : k)] >> DIR) & 1;
       } else {
         const double* rho = U + r;
-        const double psi = detector_psi(rho[-2 * SN], rho[-SN], rho[0], rho[SN], rho[2 * SN]);
-        L.chi[bidx(line, k + 3, WD)] = (psi < kPsiC) ? 1 : 0;
+        L.chi[bidx(line, k + 3, WD)] =
+            detector_flag(rho[-2 * SN], rho[-SN], rho[0], rho[SN], rho[2 * SN]) ? 1 : 0;
       }
     }
     if (C::VISC && k >= -1 && k < N + 1) {

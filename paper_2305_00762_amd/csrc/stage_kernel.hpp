@@ -239,8 +239,8 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
             (L.chif[mlp_chi_index<C>(X ? pos : l0 + line, X ? l0 + line : pos)] >> DIR) & 1;
       } else {
         const double* rho = U + r;
-        const double psi = detector_psi(rho[-2 * SN], rho[-SN], rho[0], rho[SN], rho[2 * SN]);
-        L.chi[bidx(line, pd, WD)] = (psi < kPsiC) ? 1 : 0;
+        L.chi[bidx(line, pd, WD)] =
+            detector_flag(rho[-2 * SN], rho[-SN], rho[0], rho[SN], rho[2 * SN]) ? 1 : 0;
       }
     }
     if (C::VISC && CONS && pos >= -1 && pos < N + 1) {
@@ -539,11 +539,12 @@ __device__ __forceinline__ void stage_load(const StageParams& P, double* sU, int
     sU[2 * RS + c] = CONS ? my : v;
     sU[3 * RS + c] = CONS ? E : p;
     if (C::VISC) sU[4 * RS + c] = P.gamma * p * ir;
-    const bool interior = lx >= 0 && lx < TX && ly >= 0 && ly < TY && tx0 + lx < P.nx &&
-                          ty0 + ly < P.ny;
-    if (interior && !(r > 0.0 && p > 0.0 && isfinite(E) && isfinite(mx) && isfinite(my) &&
-                      isfinite(r)))
-      bad = true;
+    // the state check covers the tile's own cells (a branch, so waves that
+    // stage only halo cells skip it)
+    if (lx >= 0 && lx < TX && ly >= 0 && ly < TY && tx0 + lx < P.nx && ty0 + ly < P.ny) {
+      if (!(r > 0.0 && p > 0.0 && isfinite(E) && isfinite(mx) && isfinite(my) && isfinite(r)))
+        bad = true;
+    }
   };
   // a tile whose halo stays inside the grid needs no ghost rules
   const bool inner = tx0 >= H && ty0 >= H && tx0 + TX + H <= P.nx && ty0 + TY + H <= P.ny;
