@@ -236,9 +236,11 @@ __global__ __launch_bounds__(256, 2) void meg7_sweep3_kernel(Sweep3Params P) {
     if (t < NL * WFL) {
       const int l = t / WFL, pi = t % WFL;   // interface between positions pi-1 and pi
       const int pos = pi - 1;                // left cell
-      bool sigma = true;
+      // eq. (buffer): the six flags read at once and OR-ed
+      unsigned any = 0u;
 #pragma unroll
-      for (int j = 1; j <= 6; ++j) sigma = sigma && (sChi[l][pos + j] == 0);
+      for (int j = 1; j <= 6; ++j) any |= sChi[l][pos + j];
+      const bool sigma = any == 0u;
       const int L = group * NL + l;
       const int gi = p0 + pi;                // interface index along the line
       if (P.sig && L < nlines && gi <= ndir) {

@@ -202,9 +202,12 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
       const int p = t % WFL;
       const int pos = p - 1;
       if (line < nl) {
-        bool sigma = true;
+        // eq. (buffer): the six flags read at once and OR-ed (a short-circuit
+        // chain would wait for each LDS read in turn)
+        unsigned any = 0u;
 #pragma unroll
-        for (int q = 1; q <= 6; ++q) sigma = sigma && (L.chi[bidx(line, pos + q, WD)] == 0);
+        for (int q = 1; q <= 6; ++q) any |= L.chi[bidx(line, pos + q, WD)];
+        const bool sigma = any == 0u;
         if (X) {
           const int gi = ty0 + l0 + line, gj = tx0 + pos;
           if (P.sigx && gi < P.ny && gj < P.nx) P.sigx[(size_t)gi * (P.nx + 1) + gj + 1] = sigma;
