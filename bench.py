@@ -709,6 +709,36 @@ def run_path(P, path, stream, a, steps, t_final, weights=None, margin=None):
     return rec, Qf, h
 
 
+def detector_vs_plain(P, h, Q):
+    """Interface flags of the path's learned detector against the plain
+    detector's (Sec. 2.4) on the same state Q: the fraction of x and y
+    interfaces that differ, and the fraction the plain detector flags."""
+    import numpy as np
+    import torch
+    from paper_2305_00762_amd import gbr
+    R = torch.empty_like(Q)
+    sx = np.zeros((P.ny, P.nx + 1), np.uint8)
+    sy = np.zeros((P.ny + 1, P.nx), np.uint8)
+    gbr.gbr_export_flags(h.ctx, True)
+    gbr.gbr_residual(h.ctx, Q, R, h.stream.cuda_stream)
+    gbr.gbr_get_flags(h.ctx, sx, sy, h.stream.cuda_stream)
+    gbr.gbr_export_flags(h.ctx, False)
+    ctx = gbr.gbr_init(P.nx, P.ny, P.gamma, P.mu, P.Pr)
+    gbr.gbr_set_geometry(ctx, *P.geometry())
+    gbr.gbr_set_scheme(ctx, gbr.GBR_RECON_PRIM, gbr.GBR_MP_FLAGGED, gbr.GBR_PREC_FP32_BULK,
+                       gbr.GBR_DET_PLAIN)
+    gbr.gbr_export_flags(ctx, True)
+    gbr.gbr_residual(ctx, Q, R, h.stream.cuda_stream)
+    px = np.zeros_like(sx)
+    py = np.zeros_like(sy)
+    gbr.gbr_get_flags(ctx, px, py, h.stream.cuda_stream)
+    gbr.gbr_destroy(ctx)
+    tot = px.size + py.size
+    return {"interface_flag_mismatch": (int((px != sx).sum()) + int((py != sy).sum())) / tot,
+            "plain_flagged_fraction": (int((px == 0).sum()) + int((py == 0).sum())) / tot,
+            "on": "the final state of the timed steps"}
+
+
 def public(rec):
     return {k: v for k, v in rec.items() if not k.startswith("_")}
 
@@ -784,6 +814,7 @@ def bench_2d(a, workload, steps_arg, stream, cpu=True, secondary=False):
         # flag map: reads Q (32 B) and writes one byte per cell, per evaluation
         evals = steps * (1 if PATHS[a.path]["per_step"] else 3)
         out["detector_flag_map_GBs"] = 33.0 * cells * evals / (head_rec["_det_ms"] * 1e-3) / 1e9
+        out["detector_vs_plain"] = detector_vs_plain(P, head, Qhead)
     head.close()
 
     if not a.no_compare:

@@ -1,21 +1,26 @@
-"""What the trained detector network gains over the same network untrained,
-and what it costs against the plain detector (through the C ABI).
+"""The learned detector against the method without it -- the plain density
+detector of Sec. 2.4 (eqs. detector, buffer) -- through the C ABI.
 
-On a fresh-seed four-quadrant Riemann field (seed 7000, not among the
-training seeds) advanced with the plain FP64 method:
+On fresh-seed fields (Riemann seed 7000 and the shear layer seed 7001, not
+among the training seeds) at 1024^2, FP32 bulk:
 
-* raw agreement with the plain detector's directional labels (margin 0,
-  the network decides everything): the trained network's balanced error
-  (mean of its false-negative and false-positive rates) is at most 15 %,
-  the untrained network's (its initial weights) at least 25 %;
-* as the method uses it (default margin, plain fallback below it): the
-  trained network decides at least 90 % of the evaluations itself and its
-  decisions disagree with the plain labels on at most 0.1 % of all
-  evaluations, while the untrained one falls back on more than half (there
-  the method is the plain detector plus the network's cost);
-* the solution: 20 FP32-bulk steps with the learned detector stay within L1
-  density 1e-6 of the same steps with the plain detector, and the learned
-  path's fallback count matches the evaluations it reports.
+* decisions: on the same state, the interface flags of the learned detector
+  (shipped weights, default margin) differ from the plain detector's on at
+  most 1e-4 of the interfaces;
+* solution: 20 steps with the learned detector, evaluated at every stage
+  and once per step (gbr_set_mlp_reuse), stay within L1(rho) 1e-6 of the same
+  steps with the plain detector;
+* cost: the learned detector does not make the method cheaper -- its flag
+  map is extra work that the plain detector's few operations per cell do not
+  need.  The test records the kernel time per step of the three forms and
+  bounds the cost of the per-step form (at most 35 % over the plain detector's
+  step), so that a regression shows; the throughput at 4096^2 is in the bench
+  line (speedup_vs_fp32_plain).
+
+Training itself is pinned separately: the trained network agrees with the
+plain labels far better than its initial weights do (balanced error at most
+15 % against at least 25 %), and at the default margin it decides at least
+90 % of the evaluations itself with at most 0.1 % disagreement.
 """
 import numpy as np
 import pytest
@@ -32,7 +37,7 @@ def _rates(m, S, n, margin):
     return D.flag_rates(m, S.ctx, S.Q, n * n, margin)
 
 
-def test_trained_network_gain():
+def test_training_agreement_with_plain_labels():
     torch = require_gpu()
     from paper_2305_00762_amd import detector as D
     from paper_2305_00762_amd.solver import Solver
@@ -47,37 +52,77 @@ def test_trained_network_gain():
     t0 = _rates(trained, S, n, 0.0)
     u0 = _rates(untrained, S, n, 0.0)
     tm = _rates(trained, S, n, D.DEFAULT_MARGIN)
-    um = _rates(untrained, S, n, D.DEFAULT_MARGIN)
     bal = lambda r: 0.5 * (r["false_neg_rate"] + r["false_pos_rate"])
-    report("detector gain", trained_balanced_error=bal(t0), untrained_balanced_error=bal(u0),
-           trained_mismatch=t0["mismatch_rate"], untrained_mismatch=u0["mismatch_rate"],
-           trained_mismatch_at_margin=tm["mismatch_rate"],
-           trained_fallback=tm["fallback_rate"], untrained_fallback=um["fallback_rate"],
-           flagged=t0["flagged_fraction"])
-    assert t0["flagged_fraction"] > 1e-3               # the field has discontinuities
+    report("training agreement", trained_balanced_error=bal(t0),
+           untrained_balanced_error=bal(u0), trained_mismatch_at_margin=tm["mismatch_rate"],
+           trained_fallback=tm["fallback_rate"], flagged=t0["flagged_fraction"])
+    assert t0["flagged_fraction"] > 1e-3
     assert bal(t0) <= 0.15 and bal(u0) >= 0.25
     assert tm["fallback_rate"] <= 0.10 and tm["mismatch_rate"] <= 1e-3
-    assert um["fallback_rate"] >= 0.5
     S.close()
     gbr.gbr_mlp_destroy(untrained)
-
-    # solution: learned vs plain detector on the FP32-bulk path, same steps
-    runs = {}
-    for name, det in (("plain", None), ("learned", trained)):
-        R = Solver(P, precision=gbr.GBR_PREC_FP32_BULK)
-        if det is not None:
-            gbr.gbr_set_mlp_detector(R.ctx, det, D.DEFAULT_MARGIN)
-            gbr.gbr_set_scheme(R.ctx, gbr.GBR_RECON_PRIM, gbr.GBR_MP_FLAGGED,
-                               gbr.GBR_PREC_FP32_BULK, gbr.GBR_DET_MLP)
-        for _ in range(20):
-            R.step()
-        assert R.check() == gbr.GBR_OK
-        if det is not None:
-            ev, fb = gbr.gbr_mlp_stats(R.ctx, reset=True)
-            assert ev == 2 * n * n * 3 * 20 and fb <= 0.10 * ev
-        runs[name] = R.Q.clone()
-        R.close()
-    l1 = (runs["learned"] - runs["plain"]).abs().reshape(4, -1).mean(dim=1).cpu().numpy()
-    report("learned vs plain detector, 20 steps", L1=l1.tolist())
-    assert l1[0] <= 1e-6
     gbr.gbr_mlp_destroy(trained)
+
+
+def _run(P, form, net, steps):
+    """FP32-bulk steps with the plain detector (net None) or the learned one
+    (form "stage" or "step"); returns (state, kernel ms per step)."""
+    from paper_2305_00762_amd import detector as D
+    from paper_2305_00762_amd.solver import Solver
+    torch = require_gpu()
+    R = Solver(P, precision=gbr.GBR_PREC_FP32_BULK, fused_dt=True)
+    if net is not None:
+        gbr.gbr_set_mlp_detector(R.ctx, net, D.DEFAULT_MARGIN)
+        gbr.gbr_set_scheme(R.ctx, gbr.GBR_RECON_PRIM, gbr.GBR_MP_FLAGGED,
+                           gbr.GBR_PREC_FP32_BULK, gbr.GBR_DET_MLP)
+        gbr.gbr_set_mlp_reuse(R.ctx, form == "step")
+    gbr.gbr_set_tiling(R.ctx, 1)
+    R.step()                                    # warm-up, outside the timing
+    gbr.gbr_timing(R.ctx, True)
+    for _ in range(steps):
+        R.step()
+    det_ms, stage_ms, calls = gbr.gbr_timing_read(R.ctx)
+    gbr.gbr_timing(R.ctx, False)
+    assert R.check() == gbr.GBR_OK
+    Q = R.Q.clone()
+    R.close()
+    return Q, (det_ms + stage_ms) / steps
+
+
+@pytest.mark.parametrize("fam,seed", [("riemann", 7000), ("shear", 7001)])
+def test_learned_against_plain_detector(fam, seed):
+    torch = require_gpu()
+    from paper_2305_00762_amd import detector as D
+    from paper_2305_00762_amd.solver import Solver
+    n = 1024
+    P = PB.make(fam, n, seed=seed)
+    net = D.load()
+    # decisions on the same (advanced) state
+    S = Solver(P, export_flags=True, precision=gbr.GBR_PREC_FP32_BULK)
+    for _ in range(20):
+        S.step()
+    S.residual()
+    px, py = S.flags()
+    gbr.gbr_set_mlp_detector(S.ctx, net, D.DEFAULT_MARGIN)
+    gbr.gbr_set_scheme(S.ctx, gbr.GBR_RECON_PRIM, gbr.GBR_MP_FLAGGED, gbr.GBR_PREC_FP32_BULK,
+                       gbr.GBR_DET_MLP)
+    S.residual()
+    lx, ly = S.flags()
+    S.close()
+    mism = (int((px != lx).sum()) + int((py != ly).sum())) / (px.size + py.size)
+    flagged = (int((px == 0).sum()) + int((py == 0).sum())) / (px.size + py.size)
+    # trajectories and kernel time per step
+    steps = 20
+    Qp, tp = _run(P, None, None, steps)
+    Qs, ts = _run(P, "stage", net, steps)
+    Qt, tt = _run(P, "step", net, steps)
+    l1s = (Qs - Qp).abs().reshape(4, -1).mean(dim=1).cpu().numpy()
+    l1t = (Qt - Qp).abs().reshape(4, -1).mean(dim=1).cpu().numpy()
+    report(f"learned vs plain detector {fam}{n}", flag_mismatch=mism, flagged_interfaces=flagged,
+           L1_per_stage=l1s.tolist(), L1_per_step=l1t.tolist(), ms_step_plain=tp,
+           ms_step_learned_per_stage=ts, ms_step_learned_per_step=tt,
+           cost_per_stage=ts / tp - 1.0, cost_per_step=tt / tp - 1.0)
+    assert mism <= 1e-4
+    assert l1s[0] <= 1e-6 and l1t[0] <= 1e-6
+    assert tt <= 1.35 * tp
+    gbr.gbr_mlp_destroy(net)
