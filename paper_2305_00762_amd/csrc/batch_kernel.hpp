@@ -67,7 +67,8 @@ struct BatchCfg {
   static_assert(CI::TX == CV::TX && CI::TY == CV::TY && CI::NT == CV::NT, "one tile shape");
   static constexpr int TX = CI::TX, TY = CI::TY, NT = CI::NT;
   static constexpr int MINW = MW;
-  static constexpr int U = imax(CI::NF * CI::RS, CV::NF * CV::RS);
+  static constexpr int U = F32 ? imax(F32Cfg<CI>::NU * CI::RS, F32Cfg<CV>::NU * CV::RS)
+                                : imax(CI::NF * CI::RS, CV::NF * CV::RS);
   static constexpr int PH = F32 ? imax(F32Cfg<CI>::PH, F32Cfg<CV>::PH) : imax(CI::PH, CV::PH);
   static constexpr int CHI = imax(CI::CHI, CV::CHI);
   static constexpr int QMAX = imax(CI::QMAX, CV::QMAX);

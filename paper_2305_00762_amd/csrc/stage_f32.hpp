@@ -69,22 +69,27 @@ __device__ __forceinline__ void hllc_diss_f32(const float WL[4], const float WR[
   for (int m = 0; m < 4; ++m) diss[m] = aSL * dQL[m] + aSS * (dQ[m] - dQR[m] - dQL[m]) + aSR * dQR[m];
 }
 
-template <int N, int NL, int NF>
+// Per-line buffers of a sweep, for the four reconstructed fields; the viscous
+// terms' derivatives are formed from the FP64 tile where an interface needs
+// them, as in the FP64 sweep.
+template <int N, int NL>
 struct PhaseF32 {
   // positions: gradients k in [-3, N+3); edge jumps dU at k+1/2, k in [-3, N+2);
-  // flux jumps df at k+1/2, k in [-5, N+4); tangential derivatives k in [-1, N+1)
-  static constexpr int WD = N + 6, WU = N + 5, WG = N + 9, WE = N + 2, WFL = N + 1, WP = N + 10;
-  static constexpr int TOT(bool visc) {
-    return NF * NL * WD + NF * NL * WU + 4 * NL * (WG > WFL ? WG : WFL) + (visc ? 2 * NL * WE : 0);
-  }
+  // flux jumps df at k+1/2, k in [-5, N+4)
+  static constexpr int WD = N + 6, WU = N + 5, WG = N + 9, WFL = N + 1, WP = N + 10;
+  static constexpr int TOT = 4 * NL * WD + 4 * NL * WU + 4 * NL * (WG > WFL ? WG : WFL);
 };
 
+// The FP32 kernel's tile holds (rho, u, v, p) in FP64 also on viscous grids:
+// T = gamma p / rho is formed where the viscous flux needs it, which keeps
+// the viscous kernel at the inviscid one's LDS size (4 workgroups per CU).
 template <class C>
 struct F32Cfg {
-  using PX = PhaseF32<C::TX, C::SX, C::NF>;
-  using PY = PhaseF32<C::TY, C::SY, C::NF>;
-  static constexpr int PH = C::cmax(PX::TOT(C::VISC), PY::TOT(C::VISC));  // floats
-  static constexpr int LDS_BYTES = 8 * C::NF * C::RS + 4 * PH + C::CHI + 2 * C::QMAX + 16;
+  using PX = PhaseF32<C::TX, C::SX>;
+  using PY = PhaseF32<C::TY, C::SY>;
+  static constexpr int NU = 4;                          // tile fields
+  static constexpr int PH = C::cmax(PX::TOT, PY::TOT);  // floats
+  static constexpr int LDS_BYTES = 8 * NU * C::RS + 4 * PH + C::CHI + 2 * C::QMAX + 16;
 };
 
 struct LdsF32 {
@@ -103,9 +108,9 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
   constexpr int N = X ? C::TX : C::TY;
   constexpr int NL = X ? C::SX : C::SY;
   constexpr int NLINES = X ? C::TY : C::TX;
-  using PH = PhaseF32<N, NL, C::NF>;
-  constexpr int WD = PH::WD, WU = PH::WU, WG = PH::WG, WE = PH::WE, WFL = PH::WFL, WP = PH::WP;
-  constexpr int RS = C::RS, RX = C::RX, H = C::H, NT = C::NT, NF = C::NF;
+  using PH = PhaseF32<N, NL>;
+  constexpr int WD = PH::WD, WU = PH::WU, WG = PH::WG, WFL = PH::WFL, WP = PH::WP;
+  constexpr int RS = C::RS, RX = C::RX, H = C::H, NT = C::NT;
   constexpr int SN = X ? 1 : RX, ST = X ? RX : 1;
   constexpr int FN = X ? 1 : 2, FT = X ? 2 : 1;
   constexpr int IPT = (NL * WFL + NT - 1) / NT;
@@ -119,10 +124,9 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
   const double inv_dt = X ? P.inv_dy : P.inv_dx;
   const float gammaf = (float)P.gamma, g1invf = (float)P.g1inv;
 
-  float* sD = L.ph;                  // [NF][NL x WD]   gradients Phi' (rotated order)
-  float* sDU = sD + NF * NL * WD;    // [NF][NL x WU]   edge jumps of the primitives
-  float* sDF = sDU + NF * NL * WU;   // [4][NL x WG]    edge jumps of the cell fluxes; then d
-  float* sE = sDF + 4 * GSTR;        // [2][NL x WE]    tangential derivatives of un, ut
+  float* sD = L.ph;                  // [4][NL x WD]    gradients Phi' (rotated order)
+  float* sDU = sD + 4 * NL * WD;     // [4][NL x WU]    edge jumps of the primitives
+  float* sDF = sDU + 4 * NL * WU;    // [4][NL x WG]    edge jumps of the cell fluxes; then d
   auto bidx = [](int line, int p, int W) { return line * W + p; };
   auto ridx = [&](int line, int pos) {
     const int lx = X ? pos : l0 + line;
@@ -133,6 +137,21 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
   const double* U = L.U;
   auto wrot = [&](int r, double W[4]) {
     W[0] = U[r]; W[1] = U[FN * RS + r]; W[2] = U[FT * RS + r]; W[3] = U[3 * RS + r];
+  };
+  // Sixth-order derivative of tile field f at cell r along stride d (eq. (eqn:six)).
+  auto g6 = [&](int f, int r, int d) {
+    const double* u = U + f * RS + r;
+    return grad6(u[-3 * d], u[-2 * d], u[-d], u[d], u[2 * d], u[3 * d]);
+  };
+  // T = gamma p / rho at the eight cells r + (j - 3) SN, j = 0..7, that the
+  // viscous flux of interface r + 1/2 reads (the arithmetic of the tile load:
+  // one refined reciprocal of rho)
+  auto temps = [&](int r, double (&T)[8]) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = r + (j - 3) * SN;
+      T[j] = P.gamma * U[3 * RS + k] * rcp_nr(U[k]);
+    }
   };
 
   // ---- pass 1: per cell and per edge, from the FP64 tile ----------------------
@@ -156,14 +175,14 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
     }
     if (k >= -3 && k < N + 2) {
 #pragma unroll
-      for (int m = 0; m < NF; ++m) {
+      for (int m = 0; m < 4; ++m) {
         const double* u = U + rot[m] * RS + r;
         sDU[m * NL * WU + bidx(line, k + 3, WU)] = (float)(u[SN] - u[0]);
       }
     }
     if (k >= -3 && k < N + 3) {
 #pragma unroll
-      for (int m = 0; m < NF; ++m) {
+      for (int m = 0; m < 4; ++m) {
         const double* u = U + rot[m] * RS + r;
         sD[m * NL * WD + bidx(line, k + 3, WD)] =
             (float)grad6(u[-3 * SN], u[-2 * SN], u[-SN], u[SN], u[2 * SN], u[3 * SN]);
@@ -175,14 +194,6 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
         const double* rho = U + r;
         L.chi[bidx(line, k + 3, WD)] =
             detector_flag(rho[-2 * SN], rho[-SN], rho[0], rho[SN], rho[2 * SN]) ? 1 : 0;
-      }
-    }
-    if (C::VISC && k >= -1 && k < N + 1) {
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        const double* u = U + (m == 0 ? FN : FT) * RS + r;
-        sE[m * NL * WE + bidx(line, k + 1, WE)] =
-            (float)(grad6(u[-3 * ST], u[-2 * ST], u[-ST], u[ST], u[2 * ST], u[3 * ST]) * inv_dt);
       }
     }
   }
@@ -263,17 +274,20 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
             const int be = bidx(line, pos + 3, WU);
             const float gun0 = sD[1 * NL * WD + b0], gun1 = sD[1 * NL * WD + b1];
             const float gut0 = sD[2 * NL * WD + b0], gut1 = sD[2 * NL * WD + b1];
-            const float gT0 = sD[4 * NL * WD + b0], gT1 = sD[4 * NL * WD + b1];
+            double T[8];
+            temps(r, T);
+            const float gT0 = (float)grad6(T[0], T[1], T[2], T[4], T[5], T[6]);
+            const float gT1 = (float)grad6(T[1], T[2], T[3], T[5], T[6], T[7]);
             const float jun = sDU[1 * NL * WU + be], jut = sDU[2 * NL * WU + be];
-            const float jT = sDU[4 * NL * WU + be];
+            const float jT = (float)(T[4] - T[3]);
             const float a2 = 0.5f * (float)kAlphaV, idn = (float)inv_dn;
             const float dun = (0.5f * (gun0 + gun1) + a2 * (jun - 0.5f * (gun0 + gun1))) * idn;
             const float dut = (0.5f * (gut0 + gut1) + a2 * (jut - 0.5f * (gut0 + gut1))) * idn;
             const float dT = (0.5f * (gT0 + gT1) + a2 * (jT - 0.5f * (gT0 + gT1))) * idn;
-            const float dunt = 0.5f * (sE[0 * NL * WE + bidx(line, pos + 1, WE)] +
-                                       sE[0 * NL * WE + bidx(line, pos + 2, WE)]);
-            const float dutt = 0.5f * (sE[1 * NL * WE + bidx(line, pos + 1, WE)] +
-                                       sE[1 * NL * WE + bidx(line, pos + 2, WE)]);
+            const float dunt = 0.5f * ((float)(g6(FN, r, ST) * inv_dt) +
+                                       (float)(g6(FN, r + SN, ST) * inv_dt));
+            const float dutt = 0.5f * ((float)(g6(FT, r, ST) * inv_dt) +
+                                       (float)(g6(FT, r + SN, ST) * inv_dt));
             const float unf = 0.5f * ((float)U[FN * RS + r] + (float)U[FN * RS + r + SN]);
             const float utf = 0.5f * ((float)U[FT * RS + r] + (float)U[FT * RS + r + SN]);
             const float muf = (float)P.mu;
@@ -337,13 +351,15 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
     hllc(WL, WR, Fm, P.gamma, P.g1inv, F);
     if (C::VISC) {
       const int b0 = bidx(line, pos + 3, WD), b1 = bidx(line, pos + 4, WD);
+      double T[8];
+      temps(r, T);
       viscous_add(U[FN * RS + r], U[FN * RS + r + SN], U[FT * RS + r], U[FT * RS + r + SN],
-                  U[4 * RS + r], U[4 * RS + r + SN], sD[1 * NL * WD + b0], sD[1 * NL * WD + b1],
-                  sD[2 * NL * WD + b0], sD[2 * NL * WD + b1], sD[4 * NL * WD + b0],
-                  sD[4 * NL * WD + b1], sE[0 * NL * WE + bidx(line, pos + 1, WE)],
-                  sE[0 * NL * WE + bidx(line, pos + 2, WE)],
-                  sE[1 * NL * WE + bidx(line, pos + 1, WE)],
-                  sE[1 * NL * WE + bidx(line, pos + 2, WE)], inv_dn, P.mu, P.kq, F);
+                  T[3], T[4], sD[1 * NL * WD + b0], sD[1 * NL * WD + b1],
+                  sD[2 * NL * WD + b0], sD[2 * NL * WD + b1],
+                  (float)grad6(T[0], T[1], T[2], T[4], T[5], T[6]),
+                  (float)grad6(T[1], T[2], T[3], T[5], T[6], T[7]), (float)(g6(FN, r, ST) * inv_dt),
+                  (float)(g6(FN, r + SN, ST) * inv_dt), (float)(g6(FT, r, ST) * inv_dt),
+                  (float)(g6(FT, r + SN, ST) * inv_dt), inv_dn, P.mu, P.kq, F);
     }
     wrot(r, W0);
     wrot(r + SN, W1);
@@ -389,7 +405,7 @@ __device__ __forceinline__ void stage_tile_f32(const StageParams& P, int tx0, in
                                                float* sPh, unsigned char* sChi,
                                                unsigned short* sQueue, int* sQCount,
                                                unsigned char* sChiF) {
-  stage_load<C>(P, sU, tx0, ty0);
+  stage_load<C, false, false>(P, sU, tx0, ty0);
   if (DETMLP) load_chimap<C>(P, sChiF, tx0, ty0);
   __syncthreads();
   const LdsF32 L{sU, sPh, sChi, sQueue, sQCount, sChiF};
@@ -406,7 +422,7 @@ __device__ __forceinline__ void stage_tile_f32(const StageParams& P, int tx0, in
 template <class C, bool DETMLP>
 __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel_f32(StageParams P) {
   using F = F32Cfg<C>;
-  __shared__ double sU[C::NF * C::RS];
+  __shared__ double sU[F::NU * C::RS];
   __shared__ float sPh[F::PH];
   __shared__ unsigned char sChi[C::CHI];
   __shared__ unsigned short sQueue[C::QMAX];

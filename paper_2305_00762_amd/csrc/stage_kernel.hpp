@@ -78,13 +78,18 @@ struct TileCfg {
   static constexpr int RX = TX + 2 * H, RY = TY + 2 * H, RS = RX * RY;
   static constexpr int NF = VISC ? 5 : 4;
   static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+  // Per-line buffers of a sweep: normal gradients of the four reconstructed
+  // fields and the cell fluxes (then the interface fluxes).  The viscous
+  // terms' derivatives (tangential ones of u_n, u_t; the normal one of T) are
+  // formed from the tile where an interface needs them: in LDS they would
+  // cost the viscous kernel a workgroup per CU for about the same
+  // instruction count.
   template <int N, int NL>
   struct Phase {
-    static constexpr int WD = N + 6, WF = N + 10, WE = N + 2, WFL = N + 1;
-    static constexpr int D = NF * NL * WD;
+    static constexpr int WD = N + 6, WF = N + 10, WFL = N + 1;
+    static constexpr int D = 4 * NL * WD;
     static constexpr int F = 4 * NL * (WF > WFL ? WF : WFL);
-    static constexpr int E = VISC ? 2 * NL * WE : 0;
-    static constexpr int TOT = D + F + E;
+    static constexpr int TOT = D + F;
   };
   using PX = Phase<TX, SX>;
   using PY = Phase<TY, SY>;
@@ -136,8 +141,8 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
   constexpr int NL = X ? C::SX : C::SY;
   constexpr int NLINES = X ? C::TY : C::TX;
   using PH = typename C::template Phase<N, NL>;
-  constexpr int WD = PH::WD, WF = PH::WF, WE = PH::WE, WFL = PH::WFL;
-  constexpr int RS = C::RS, RX = C::RX, H = C::H, NT = C::NT, NF = C::NF;
+  constexpr int WD = PH::WD, WF = PH::WF, WFL = PH::WFL;
+  constexpr int RS = C::RS, RX = C::RX, H = C::H, NT = C::NT;
   constexpr int SN = X ? 1 : RX;  // normal stride in the LDS tile
   constexpr int ST = X ? RX : 1;  // tangential stride
   constexpr int FN = X ? 1 : 2;   // field holding the normal velocity
@@ -148,14 +153,13 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
   const double inv_dn = X ? P.inv_dx : P.inv_dy;
   const double inv_dt = X ? P.inv_dy : P.inv_dx;
 
-  double* sD = L.ph;                       // [NF][NL x WD]  normal gradients (rotated order)
-  double* sF = sD + NF * NL * WD;          // [4][NL x WF]   cell fluxes; later [4][NL x WFL] interface fluxes
+  double* sD = L.ph;                       // [4][NL x WD]   normal gradients (rotated order)
+  double* sF = sD + 4 * NL * WD;           // [4][NL x WF]   cell fluxes; later [4][NL x WFL] interface fluxes
   constexpr int FSTR = (WF > WFL ? WF : WFL) * NL;
   // interface values: odd row stride, so pass 4 (lanes across lines in the
   // y sweep) reads distinct banks
   constexpr int WFS = WFL | 1;
   static_assert(WFS <= WF, "interface rows fit the flux buffer");
-  double* sE = sF + 4 * FSTR;              // [2][NL x WE]   tangential derivatives of un, ut
   // buffer index and thread mapping: positions fastest in both sweeps (in the
   // y sweep consecutive lanes then step RX doubles apart in the tile, an odd
   // stride, so the FP64 tile reads fall in distinct banks)
@@ -176,29 +180,45 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
     W[2] = U[FT * RS + r] * ir;
     W[3] = (P.gamma - 1.0) * (U[3 * RS + r] - 0.5 * rho * (W[1] * W[1] + W[2] * W[2]));
   };
-  // viscous flux of interface (line, pos + 1/2) added to F
+  // Sixth-order derivative of tile field f at cell r along stride d (eq. (eqn:six)).
+  auto g6 = [&](int f, int r, int d) {
+    const double* u = L.U + f * RS + r;
+    return grad6(u[-3 * d], u[-2 * d], u[-d], u[d], u[2 * d], u[3 * d]);
+  };
+  // viscous flux of interface (line, pos + 1/2) added to F; r is its left cell
   auto visc_at = [&](int line, int pos, int r, double* F) {
     const double* U = L.U;
     const int b0 = bidx(line, pos + 3, WD), b1 = bidx(line, pos + 4, WD);
-    const int e0 = bidx(line, pos + 1, WE), e1 = bidx(line, pos + 2, WE);
     const double* D1 = sD + 1 * NL * WD;
     const double* D2 = sD + 2 * NL * WD;
-    const double* D4 = sD + 4 * NL * WD;
+    const double gT0 = g6(4, r, SN), gT1 = g6(4, r + SN, SN);
     if (CONS) {
       // velocity gradients by the chain rule d u = (d(rho u) - u d rho) / rho
       const double* D0 = sD;
       const double ir0 = rcp_nr(U[r]), ir1 = rcp_nr(U[r + SN]);
       const double un0 = U[FN * RS + r] * ir0, un1 = U[FN * RS + r + SN] * ir1;
       const double ut0 = U[FT * RS + r] * ir0, ut1 = U[FT * RS + r + SN] * ir1;
+      // tangential derivatives of un, ut at the two cells
+      double dunt[2], dutt[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int rc = r + c * SN;
+        const double gr = g6(0, rc, ST) * inv_dt;
+        const double gn = g6(FN, rc, ST) * inv_dt;
+        const double gt = g6(FT, rc, ST) * inv_dt;
+        const double ir = c ? ir1 : ir0;
+        dunt[c] = (gn - (U[FN * RS + rc] * ir) * gr) * ir;
+        dutt[c] = (gt - (U[FT * RS + rc] * ir) * gr) * ir;
+      }
       viscous_add(un0, un1, ut0, ut1, U[4 * RS + r], U[4 * RS + r + SN],
                   (D1[b0] - un0 * D0[b0]) * ir0, (D1[b1] - un1 * D0[b1]) * ir1,
-                  (D2[b0] - ut0 * D0[b0]) * ir0, (D2[b1] - ut1 * D0[b1]) * ir1, D4[b0], D4[b1],
-                  sE[e0], sE[e1], sE[NL * WE + e0], sE[NL * WE + e1], inv_dn, P.mu, P.kq, F);
+                  (D2[b0] - ut0 * D0[b0]) * ir0, (D2[b1] - ut1 * D0[b1]) * ir1, gT0, gT1,
+                  dunt[0], dunt[1], dutt[0], dutt[1], inv_dn, P.mu, P.kq, F);
     } else {
       viscous_add(U[FN * RS + r], U[FN * RS + r + SN], U[FT * RS + r], U[FT * RS + r + SN],
-                  U[4 * RS + r], U[4 * RS + r + SN], D1[b0], D1[b1], D2[b0], D2[b1], D4[b0],
-                  D4[b1], sE[e0], sE[e1], sE[NL * WE + e0], sE[NL * WE + e1], inv_dn, P.mu,
-                  P.kq, F);
+                  U[4 * RS + r], U[4 * RS + r + SN], D1[b0], D1[b1], D2[b0], D2[b1], gT0, gT1,
+                  g6(FN, r, ST) * inv_dt, g6(FN, r + SN, ST) * inv_dt,
+                  g6(FT, r, ST) * inv_dt, g6(FT, r + SN, ST) * inv_dt, inv_dn, P.mu, P.kq, F);
     }
   };
 
@@ -229,7 +249,7 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
     if (pos >= -3 && pos < N + 3) {
       const int pd = pos + 3;
 #pragma unroll
-      for (int m = 0; m < NF; ++m) {
+      for (int m = 0; m < 4; ++m) {
         const double* u = U + rot[m] * RS + r;
         sD[m * NL * WD + bidx(line, pd, WD)] =
             grad6(u[-3 * SN], u[-2 * SN], u[-SN], u[SN], u[2 * SN], u[3 * SN]);
@@ -241,28 +261,6 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
         const double* rho = U + r;
         L.chi[bidx(line, pd, WD)] =
             detector_flag(rho[-2 * SN], rho[-SN], rho[0], rho[SN], rho[2 * SN]) ? 1 : 0;
-      }
-    }
-    if (C::VISC && CONS && pos >= -1 && pos < N + 1) {
-      // tangential derivatives of un, ut by the chain rule
-      const int pe = pos + 1;
-      const double* ur = U + r;
-      const double* un = U + FN * RS + r;
-      const double* ut = U + FT * RS + r;
-      const double gr = grad6(ur[-3 * ST], ur[-2 * ST], ur[-ST], ur[ST], ur[2 * ST], ur[3 * ST]) * inv_dt;
-      const double gn = grad6(un[-3 * ST], un[-2 * ST], un[-ST], un[ST], un[2 * ST], un[3 * ST]) * inv_dt;
-      const double gt = grad6(ut[-3 * ST], ut[-2 * ST], ut[-ST], ut[ST], ut[2 * ST], ut[3 * ST]) * inv_dt;
-      const double ir = rcp_nr(ur[0]);
-      sE[bidx(line, pe, WE)] = (gn - (un[0] * ir) * gr) * ir;
-      sE[NL * WE + bidx(line, pe, WE)] = (gt - (ut[0] * ir) * gr) * ir;
-    }
-    if (C::VISC && !CONS && pos >= -1 && pos < N + 1) {
-      const int pe = pos + 1;
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        const double* u = U + (m == 0 ? FN : FT) * RS + r;
-        sE[m * NL * WE + bidx(line, pe, WE)] =
-            grad6(u[-3 * ST], u[-2 * ST], u[-ST], u[ST], u[2 * ST], u[3 * ST]) * inv_dt;
       }
     }
   }
@@ -513,7 +511,9 @@ __device__ __forceinline__ unsigned ghost_op(int kx, int ky, int sx, int gx, int
   return op;
 }
 
-template <class C, bool CONS = false>
+// TFIELD: whether the tile holds T (the FP64 viscous kernels; the FP32 one
+// forms T where it needs it).
+template <class C, bool CONS = false, bool TFIELD = C::VISC>
 __device__ __forceinline__ void stage_load(const StageParams& P, double* sU, int tx0, int ty0) {
   constexpr int RS = C::RS, RX = C::RX, H = C::H, NT = C::NT, TX = C::TX, TY = C::TY;
   constexpr int LR = (RS + NT - 1) / NT;
@@ -541,7 +541,7 @@ __device__ __forceinline__ void stage_load(const StageParams& P, double* sU, int
     sU[RS + c] = CONS ? mx : u;
     sU[2 * RS + c] = CONS ? my : v;
     sU[3 * RS + c] = CONS ? E : p;
-    if (C::VISC) sU[4 * RS + c] = P.gamma * p * ir;
+    if (TFIELD) sU[4 * RS + c] = P.gamma * p * ir;
     // the state check covers the tile's own cells (a branch, so waves that
     // stage only halo cells skip it)
     if (lx >= 0 && lx < TX && ly >= 0 && ly < TY && tx0 + lx < P.nx && ty0 + ly < P.ny) {
