@@ -405,8 +405,10 @@ __device__ __forceinline__ void stage_tile_f32(const StageParams& P, int tx0, in
                                                float* sPh, unsigned char* sChi,
                                                unsigned short* sQueue, int* sQCount,
                                                unsigned char* sChiF) {
+  ChiMap<C> cm;
+  if (DETMLP) fetch_chimap<C>(P, cm, tx0, ty0);
   stage_load<C, false, false>(P, sU, tx0, ty0);
-  if (DETMLP) load_chimap<C>(P, sChiF, tx0, ty0);
+  if (DETMLP) put_chimap<C>(cm, sChiF);
   __syncthreads();
   const LdsF32 L{sU, sPh, sChi, sQueue, sQCount, sChiF};
   double res[C::CPT][4];

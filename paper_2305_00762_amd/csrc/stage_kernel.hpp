@@ -119,17 +119,37 @@ __device__ __forceinline__ int mlp_chi_index(int lx, int ly) {
 
 // Learned-detector flags of the tile cells the sigma buffers read,
 // [-3, TX+3) x [-3, TY+3), from the per-cell flag map (ghost cells take the
-// flag of the cell they copy: periodic wrap or transmissive clamp).
+// flag of the cell they copy: periodic wrap or transmissive clamp).  Fetched
+// into registers before the tile's loads are issued and stored to LDS after
+// the tile is staged, so their latency overlaps the tile's.
 template <class C>
-__device__ __forceinline__ void load_chimap(const StageParams& P, unsigned char* chif, int tx0,
-                                            int ty0) {
-  constexpr int W6 = C::TX + 6, NC = (C::TX + 6) * (C::TY + 6);
+struct ChiMap {
+  static constexpr int NC = (C::TX + 6) * (C::TY + 6);
+  static constexpr int R = (NC + C::NT - 1) / C::NT;
+  unsigned char v[R];
+};
+template <class C>
+__device__ __forceinline__ void fetch_chimap(const StageParams& P, ChiMap<C>& m, int tx0,
+                                             int ty0) {
+  constexpr int W6 = C::TX + 6;
   const bool inner = tx0 >= 3 && ty0 >= 3 && tx0 + C::TX + 3 <= P.nx && ty0 + C::TY + 3 <= P.ny;
-  for (int c = threadIdx.x; c < NC; c += C::NT) {
-    const int ly = c / W6 - 3, lx = c - (ly + 3) * W6 - 3;
-    const int gi = inner ? ty0 + ly : bc_index(ty0 + ly, P.ny, P.bcy);
-    const int gj = inner ? tx0 + lx : bc_index(tx0 + lx, P.nx, P.bcx);
-    chif[c] = P.chimap[gi * P.nx + gj];
+#pragma unroll
+  for (int k = 0; k < ChiMap<C>::R; ++k) {
+    const int c = threadIdx.x + k * C::NT;
+    if (c < ChiMap<C>::NC) {
+      const int ly = c / W6 - 3, lx = c - (ly + 3) * W6 - 3;
+      const int gi = inner ? ty0 + ly : bc_index(ty0 + ly, P.ny, P.bcy);
+      const int gj = inner ? tx0 + lx : bc_index(tx0 + lx, P.nx, P.bcx);
+      m.v[k] = P.chimap[gi * P.nx + gj];
+    }
+  }
+}
+template <class C>
+__device__ __forceinline__ void put_chimap(const ChiMap<C>& m, unsigned char* chif) {
+#pragma unroll
+  for (int k = 0; k < ChiMap<C>::R; ++k) {
+    const int c = threadIdx.x + k * C::NT;
+    if (c < ChiMap<C>::NC) chif[c] = m.v[k];
   }
 }
 
@@ -763,8 +783,10 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int tx0, int ty
                                            double* sPh, unsigned char* sChi,
                                            unsigned short* sQueue, int* sQCount,
                                            unsigned char* sChiF) {
+  ChiMap<C> cm;
+  if (DETMLP) fetch_chimap<C>(P, cm, tx0, ty0);
   stage_load<C, CONS>(P, sU, tx0, ty0);
-  if (DETMLP) load_chimap<C>(P, sChiF, tx0, ty0);
+  if (DETMLP) put_chimap<C>(cm, sChiF);
   __syncthreads();
   const Lds L{sU, sPh, sChi, sQueue, sQCount, sChiF};
   double res[C::CPT][4];
