@@ -182,6 +182,11 @@ struct gbr_ctx {
   uint8_t* d_chimap;          // [ny][nx] learned-detector flag per cell
   int mlp_reuse;              // 1: flag map evaluated on Q^n only (residual and stage 1)
   int chimap_valid;           // a flag map has been evaluated
+  // per-step detector: float32 (rho, p) of the last stage-3 output [2][ny][nx],
+  // written by that stage kernel and read by the next flag map in place of Q
+  float* d_rp;
+  const double* rp_src;       // the stage-3 output d_rp describes
+  int rp_valid;
   unsigned long long* d_mlp_fb;   // plain fallbacks of the learned detector
   unsigned long long mlp_evaluated;
   // kernel timing (gbr_timing): events recorded around every launch of a
@@ -309,6 +314,7 @@ int gbr_destroy(gbr_ctx* c) {
   if (c->d_mlp_f) (void)hipFree(c->d_mlp_f);
   if (c->d_chimap) (void)hipFree(c->d_chimap);
   if (c->d_mlp_fb) (void)hipFree(c->d_mlp_fb);
+  if (c->d_rp) (void)hipFree(c->d_rp);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   delete c;
   return GBR_OK;
@@ -486,9 +492,11 @@ static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn
   P.dx = (c->x1 - c->x0) / c->nx; P.dy = (c->y1 - c->y0) / c->ny;
   P.dtx = mode == MODE_STAGE3 ? c->d_dtx : nullptr;
   const int det = c->detector == GBR_DET_MLP ? 1 : 0;
-  // per-step detector: stages 2 and 3 reuse the flag map of Q^n
+  // per-step detector: stages 2 and 3 reuse the flag map of Q^n, and stage 3
+  // leaves (rho, p) of Q^(n+1) for the next step's flag map
   const bool reuse = det && c->mlp_reuse && (mode == MODE_STAGE2 || mode == MODE_STAGE3);
   if (reuse && !c->chimap_valid) return GBR_EINVAL;
+  P.rp = (mode == MODE_STAGE3 && det && c->mlp_reuse) ? c->d_rp : nullptr;
   hipEvent_t* tev = nullptr;
   if (c->timing) {
     if (c->ev_used + 3 > c->ev.size()) {
@@ -505,6 +513,7 @@ static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn
   if (det && !reuse) {
     MlpChiParams M{};
     M.Q = Qk; M.chi = c->d_chimap; M.nfb = c->d_mlp_fb;
+    M.rp = (c->mlp_reuse && c->rp_valid && c->rp_src == Qk) ? c->d_rp : nullptr;
     M.M.W1 = c->d_mlp_w;
     M.M.W2 = c->d_mlp_w + kMlpH * kMlpIn;
     M.M.w3 = c->d_mlp_f;
@@ -526,7 +535,11 @@ static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn
   if (tev && hipEventRecord(tev[1], s) != hipSuccess) return GBR_EDEVICE;
   variant_fn(c, vi)(P, s);
   if (tev && hipEventRecord(tev[2], s) != hipSuccess) return GBR_EDEVICE;
-  if (mode == MODE_STAGE3) c->stage3_slots = P.ntiles * kStageWaves;
+  if (mode == MODE_STAGE3) {
+    c->stage3_slots = P.ntiles * kStageWaves;
+    c->rp_valid = P.rp != nullptr;
+    c->rp_src = out;
+  }
   return hip_ok(hipGetLastError());
 }
 
@@ -821,7 +834,13 @@ int gbr_set_mlp_detector(gbr_ctx* c, const gbr_mlp* m, float margin, void* strea
 
 int gbr_set_mlp_reuse(gbr_ctx* c, int per_step) {
   if (!c || (per_step != 0 && per_step != 1)) return GBR_EINVAL;
+  if (per_step && !c->d_rp &&
+      hipMalloc(&c->d_rp, 2 * (size_t)c->nx * c->ny * sizeof(float)) != hipSuccess) {
+    c->d_rp = nullptr;
+    return GBR_ENOMEM;
+  }
   c->mlp_reuse = per_step;
+  c->rp_valid = 0;
   return GBR_OK;
 }
 

@@ -363,6 +363,10 @@ __global__ __launch_bounds__(256) void mlp_features_kernel(MlpFeatParams P) {
 // the last round; the flag bytes are then stored coalesced, one row per wave.
 struct MlpChiParams {
   const double* Q;
+  // optional: rho and p of Q already rounded to float32, [2][ny][nx] (the
+  // values the block staging computes from Q; written beside Q by the
+  // stage that produced it), read instead of Q
+  const float* rp;
   uint8_t* chi;                 // [ny][nx]: bit 0 chi^x, bit 1 chi^y
   unsigned long long* nfb;      // plain fallbacks (summed over both directions)
   MlpImage M;
@@ -405,23 +409,47 @@ __global__ __launch_bounds__(256, 4) void mlp_chi_kernel(MlpChiParams P) {
   // the network's fragments first: their loads overlap those of the state
   MlpInfer F;
   mlp_load_infer(P.M, F);
-  double q[LR][4];
+  auto src = [&](int c) {
+    return (size_t)gwrap(ty0 + c / kChiRX - 3, P.ny, P.bcy) * P.nx +
+           gwrap(tx0 + c % kChiRX - 3, P.nx, P.bcx);
+  };
+  if (P.rp) {
+    float q[LR][2];
 #pragma unroll
-  for (int k = 0; k < LR; ++k) {
-    const int c = tid + 256 * k;
-    if (c < kChiRS) {
-      const size_t s = (size_t)gwrap(ty0 + c / kChiRX - 3, P.ny, P.bcy) * P.nx +
-                       gwrap(tx0 + c % kChiRX - 3, P.nx, P.bcx);
-#pragma unroll
-      for (int m = 0; m < 4; ++m) q[k][m] = P.Q[m * n + s];
+    for (int k = 0; k < LR; ++k) {
+      const int c = tid + 256 * k;
+      if (c < kChiRS) {
+        const size_t s = src(c);
+        q[k][0] = P.rp[s];
+        q[k][1] = P.rp[n + s];
+      }
     }
-  }
 #pragma unroll
-  for (int k = 0; k < LR; ++k) {
-    const int c = tid + 256 * k;
-    if (c < kChiRS) {
-      sF[0][c] = (float)q[k][0];
-      sF[1][c] = (float)mlp_cell_pressure(q[k][0], q[k][1], q[k][2], q[k][3], P.gamma);
+    for (int k = 0; k < LR; ++k) {
+      const int c = tid + 256 * k;
+      if (c < kChiRS) {
+        sF[0][c] = q[k][0];
+        sF[1][c] = q[k][1];
+      }
+    }
+  } else {
+    double q[LR][4];
+#pragma unroll
+    for (int k = 0; k < LR; ++k) {
+      const int c = tid + 256 * k;
+      if (c < kChiRS) {
+        const size_t s = src(c);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) q[k][m] = P.Q[m * n + s];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < LR; ++k) {
+      const int c = tid + 256 * k;
+      if (c < kChiRS) {
+        sF[0][c] = (float)q[k][0];
+        sF[1][c] = (float)mlp_cell_pressure(q[k][0], q[k][1], q[k][2], q[k][3], P.gamma);
+      }
     }
   }
   __syncthreads();

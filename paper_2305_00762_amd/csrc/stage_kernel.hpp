@@ -55,6 +55,9 @@ struct StageParams {
   // stage 3 only (else null): per-wave time-step extrema of the output,
   // [3][ntiles x waves per workgroup]: max(|u|+c), max(|v|+c), min rho
   double* dtx;
+  // stage 3 only (else null): density and pressure of the output rounded to
+  // float32, [2][ny][nx], the learned detector's inputs for the next step
+  float* rp;
 };
 
 // Ghost cells by index: periodic wrap or transmissive clamp.  The offsets
@@ -632,31 +635,49 @@ __device__ __forceinline__ void stage_load(const StageParams& P, double* sU, int
   if (bad) atomicOr(P.status, STATUS_BAD_STATE);
 }
 
+// Velocity and pressure of a conservative state with one rounding per
+// operation and IEEE division: u = (rho u)/rho, v = (rho v)/rho,
+// p = (gamma-1)(E - rho (u u + v v)/2).  Inside div_rb's operand range the
+// quotients share one refined reciprocal rb (the IEEE quotient bit for bit);
+// fast says whether they did.  The time step and the learned detector's
+// pressure are defined on exactly these values.
+struct CellUVP {
+  double u, v, p, rb;
+  bool fast;
+};
+__device__ __forceinline__ CellUVP cell_uvp(const double q[4], double gamma) {
+#pragma clang fp contract(off)
+  CellUVP c;
+  const double rho = q[0];
+  c.rb = rcp_nr(rho);
+  c.fast = rho != 0.0 && div_rb_ok(rho) && div_rb_ok(q[1]) && div_rb_ok(q[2]);
+  if (c.fast) {
+    c.u = div_rb(q[1], rho, c.rb);
+    c.v = div_rb(q[2], rho, c.rb);
+  } else {
+    c.u = q[1] / rho;
+    c.v = q[2] / rho;
+  }
+  c.p = (gamma - 1.0) * (q[3] - rho * (c.u * c.u + c.v * c.v) / 2.0);
+  return c;
+}
+
 // Time-step extrema of one cell of the new state (Sec. 2.5): |u|+c, |v|+c
 // and rho, each rounded exactly as the time-step kernel rounds them (one
 // rounding per operation, IEEE division and square root), folded into
 // (amax, bmax, rmin).  Since fl(d/x) is monotone in x, the minima of the
 // per-cell limits follow from these extrema without loss.
-__device__ __forceinline__ void dt_extrema_cell(const double q[4], double gamma, double& amax,
-                                                double& bmax, double& rmin, bool& bad) {
+__device__ __forceinline__ void dt_extrema_cell(const double q[4], const CellUVP& w, double gamma,
+                                                double& amax, double& bmax, double& rmin,
+                                                bool& bad) {
 #pragma clang fp contract(off)
   const double rho = q[0];
-  const double rb = rcp_nr(rho);
-  const bool fast = rho != 0.0 && div_rb_ok(rho) && div_rb_ok(q[1]) && div_rb_ok(q[2]);
-  double u, v;
-  if (fast) {
-    u = div_rb(q[1], rho, rb);
-    v = div_rb(q[2], rho, rb);
-  } else {
-    u = q[1] / rho;
-    v = q[2] / rho;
-  }
-  const double p = (gamma - 1.0) * (q[3] - rho * (u * u + v * v) / 2.0);
-  const double gp = gamma * p;
-  const double c = sqrt((fast && div_rb_ok(gp)) ? div_rb(gp, rho, rb) : gp / rho);
-  if (!(rho > 0.0) || !(p > 0.0) || !isfinite(c) || !isfinite(u) || !isfinite(v)) bad = true;
-  amax = fmax(amax, fabs(u) + c);
-  bmax = fmax(bmax, fabs(v) + c);
+  const double gp = gamma * w.p;
+  const double c = sqrt((w.fast && div_rb_ok(gp)) ? div_rb(gp, rho, w.rb) : gp / rho);
+  if (!(rho > 0.0) || !(w.p > 0.0) || !isfinite(c) || !isfinite(w.u) || !isfinite(w.v))
+    bad = true;
+  amax = fmax(amax, fabs(w.u) + c);
+  bmax = fmax(bmax, fabs(w.v) + c);
   rmin = fmin(rmin, rho);
 }
 
@@ -753,24 +774,35 @@ __device__ __forceinline__ void stage_store(const StageParams& P, const double (
         v[k][m] = (1.0 / 3.0) * qn[k][m] + (2.0 / 3.0) * qk[k][m] + ((2.0 / 3.0) * dt) * R;
     }
   }
-  if (P.dtx) {
+  float prp[C::CPT];
+  if (P.dtx || P.rp) {
     // the time-step extrema of the new state, before the stores (stores
     // first would make the wave wait for them before reusing their registers)
     double amax = 0.0, bmax = 0.0, rmin = __builtin_inf();
     bool bad = false;
 #pragma unroll
-    for (int k = 0; k < C::CPT; ++k)
-      if (own[k]) dt_extrema_cell(v[k], P.gamma, amax, bmax, rmin, bad);
-    if (bad) atomicOr(P.status, 1u);
-    constexpr int NW = NT / 64;
-    dt_extrema_commit(P.dtx, P.ntiles * NW, blockIdx.x * NW + (threadIdx.x >> 6), amax, bmax,
-                      rmin, P.dx == P.dy, P.mu > 0.0);
+    for (int k = 0; k < C::CPT; ++k) {
+      if (!own[k]) continue;
+      const CellUVP w = cell_uvp(v[k], P.gamma);
+      prp[k] = (float)w.p;
+      if (P.dtx) dt_extrema_cell(v[k], w, P.gamma, amax, bmax, rmin, bad);
+    }
+    if (P.dtx) {
+      if (bad) atomicOr(P.status, 1u);
+      constexpr int NW = NT / 64;
+      dt_extrema_commit(P.dtx, P.ntiles * NW, blockIdx.x * NW + (threadIdx.x >> 6), amax, bmax,
+                        rmin, P.dx == P.dy, P.mu > 0.0);
+    }
   }
 #pragma unroll
   for (int k = 0; k < C::CPT; ++k) {
     if (!own[k]) continue;
 #pragma unroll
     for (int m = 0; m < 4; ++m) P.out[m * n + so[k]] = v[k][m];
+    if (P.rp) {
+      P.rp[so[k]] = (float)v[k][0];
+      P.rp[n + so[k]] = prp[k];
+    }
   }
 }
 

@@ -299,6 +299,46 @@ def test_per_step_detector_reuse(precision):
     gbr.gbr_mlp_destroy(m)
 
 
+@pytest.mark.parametrize("fam", ["riemann", "vortex"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_per_step_flag_map_from_stored_values(fam, precision):
+    """Per-step evaluation, a step after the first: the stage-3 kernel stores
+    the float32 density and pressure of its output, and the next flag map
+    reads them in place of the state.  That flag map decides as the oracle
+    network does on the advanced state (cell by cell where its logit is
+    clear), and equals bit for bit the flag map evaluated from the state
+    itself (the same context after gbr_set_mlp_reuse drops the stored
+    values)."""
+    import dataclasses
+    from paper_2305_00762_amd.solver import Solver
+    torch = require_gpu()
+    m, w, b = make_net(5)
+    P = PB.riemann(90, seed=7, ny=70) if fam == "riemann" else PB.vortex(48)
+    S = Solver(P, export_flags=True, precision=precision, fused_dt=True)
+    gbr.gbr_set_mlp_detector(S.ctx, m, split_margin(oracle_logits(P, w, b)))
+    gbr.gbr_set_scheme(S.ctx, gbr.GBR_RECON_PRIM, gbr.GBR_MP_FLAGGED, precision, gbr.GBR_DET_MLP)
+    gbr.gbr_set_mlp_reuse(S.ctx, True)
+    for _ in range(3):
+        S.step()
+    P2 = dataclasses.replace(P, Q=S.state())
+    zo = oracle_logits(P2, w, b)
+    margin = split_margin(zo)
+    gbr.gbr_set_mlp_detector(S.ctx, m, margin)     # the stored values stay
+    S.compute_dt()
+    gbr.gbr_rk_stage(S.ctx, 1, S.dt, S.Q, S.Q, S.Q1)   # flag map from the stored values
+    sx, sy = S.flags()
+    chi_stored = gbr.gbr_mlp_get_flagmap(S.ctx)
+    check_flag_map(P2, chi_stored, zo, margin, sx, sy)
+    gbr.gbr_set_mlp_reuse(S.ctx, True)                 # drops them
+    gbr.gbr_rk_stage(S.ctx, 1, S.dt, S.Q, S.Q, S.Q1)   # flag map from the state
+    chi_state = gbr.gbr_mlp_get_flagmap(S.ctx)
+    report(f"stored-value flag map {fam} p{precision}", flagged=float((chi_state != 0).mean()))
+    assert (chi_stored == chi_state).all()
+    assert S.check() == gbr.GBR_OK
+    S.close()
+    gbr.gbr_mlp_destroy(m)
+
+
 def test_feature_reciprocal_is_correctly_rounded():
     """The features' reciprocal (hardware estimate plus one fused Newton
     step) equals IEEE float32 division for every normal float below 2^126:
