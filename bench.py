@@ -50,6 +50,11 @@ BYTES_PER_CELL_STAGE = {1: 64.0, 2: 96.0, 3: 96.0}
 # reads Q^n (stage 1) or Q^n and Q^(k) (stages 2, 3) for the update:
 # 120 + (40 + 80 + 80)/3 B.  Per cell-stage on average:
 BYTES_PER_CELL_STAGE_3D = 80.0 + 120.0 + 120.0 + 200.0 / 3.0
+# With the x and y sweeps fused over tiles of a z plane, the fused kernel
+# reads Q^(k) and writes the accumulator (80 B) and the z sweep moves the
+# 186.7 B above.
+BYTES_PER_CELL_STAGE_3D_FUSED = 80.0 + 120.0 + 200.0 / 3.0
+SWEEPS3 = {"lines": 0, "fused": 1, "fused_half": 2}
 
 WORKLOADS = {
     # name: (family, n, seed, steps, description)
@@ -78,6 +83,9 @@ WORKLOADS = {
                        "Inviscid Taylor-Green vortex 64^3 on [0, 2 pi)^3 (the paper's 3D case), "
                        "periodic, CFL 0.2, run from t = 0 to t = 10; kinetic energy and enstrophy "
                        "at t = 1..10"),
+    "riemann3d128": ("riemann3d", 128, 0, 20,
+                     "3D Euler eight-octant Riemann problem 128^3, octant states from seed 0, "
+                     "transmissive, CFL 0.2"),
     "batch512": ("batch", 0, 0, 10,
                  "512 independent grids, side n ~ U{64..768} (seed 0), families uniform over "
                  "vortex / Riemann / shear layer, per-grid seed 10000 + index; one launch per "
@@ -124,6 +132,8 @@ def parse():
                     help="host seconds of the all-threads oracle sample")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
+    ap.add_argument("--sweeps3", default="lines", choices=sorted(SWEEPS3),
+                    help="3D launch form: line sweeps, or x/y fused over z-plane tiles")
     ap.add_argument("--tiling", default="auto",
                     help="tile variant index, or 'auto' (gbr_autotune on the initial state)")
     return ap.parse_args()
@@ -456,7 +466,7 @@ def bench_3d(a, n):
         """Steps to t = 10 with diagnostics at t = 1..10 (device time summed on
         the stream, read after batches that shrink near each target)."""
         with torch.cuda.stream(s):
-            S = Solver3(P, stream=s, order=order)
+            S = Solver3(P, stream=s, order=order, sweeps=SWEEPS3[a.sweeps3])
             tacc = torch.zeros(1, dtype=torch.float64, device="cuda")
         k0 = tg_diagnostics(P.Q, dx)
         hist, steps, batch = [], 0, 50
@@ -480,34 +490,7 @@ def bench_3d(a, n):
         return hist, steps, status
 
     def timed(order, steps):
-        with torch.cuda.stream(s):
-            S = Solver3(P, stream=s, order=order)
-            for _ in range(a.warmup):
-                S.step()
-        s.synchronize()
-        S.Q.copy_(torch.from_numpy(P.Q))
-        torch.cuda.synchronize()
-        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        with torch.cuda.stream(s):
-            start.record(s)
-            for _ in range(steps):
-                S.step()
-            stop.record(s)
-        s.synchronize()
-        ms = start.elapsed_time(stop)
-        # kernel pass: the same run again from t = 0 with events around every
-        # stage's three sweeps (the average over the whole run)
-        S.Q.copy_(torch.from_numpy(P.Q))
-        torch.cuda.synchronize()
-        gbr.gbr3_timing(S.ctx, True)
-        with torch.cuda.stream(s):
-            for _ in range(steps):
-                S.step()
-        sweep_ms, calls = gbr.gbr3_timing_read(S.ctx)
-        gbr.gbr3_timing(S.ctx, False)
-        st = gbr.strerror(S.check())
-        S.close()
-        return ms, sweep_ms / max(calls, 1), st
+        return timed3(a, P, s, order, steps)
 
     out_orders = {}
     for order in ([head_order] + ([11 - head_order] if not a.no_compare else [])):
@@ -518,20 +501,20 @@ def bench_3d(a, n):
                              "stage_us": stage_ms * 1e3, "history": hist,
                              "status": st if st == st2 else f"{st}/{st2}"}
     h = out_orders[head_order]
-    achieved = BYTES_PER_CELL_STAGE_3D * cells / (h["stage_us"] * 1e-6) / 1e9
+    bpc = bytes_3d(a)
+    achieved = bpc * cells / (h["stage_us"] * 1e-6) / 1e9
     out = {
         "metric": METRIC, "value": h["value"], "unit": "cell-stage updates/s", "n_gpus": 1,
         "steps": h["steps_to_t10"], "warmup": a.warmup, "ms_per_step": h["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "taylor_green3d", "description": WORKLOADS["taylor_green3d"][4],
-                   "nx": n, "ny": n, "nz": n, "order": head_order,
-                   "step": "device dt + 3 x (x, y, z line-sweep kernels)"},
+                   "nx": n, "ny": n, "nz": n, "order": head_order, "sweeps": a.sweeps3,
+                   "step": step_3d(a)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "meg7_sweep3_kernel (x, y, z per stage)",
-                     "avg_launch_us": h["stage_us"],
-                     "bytes_per_cell_stage": BYTES_PER_CELL_STAGE_3D},
+                     "kernel": kernel_3d(a), "avg_launch_us": h["stage_us"],
+                     "bytes_per_cell_stage": bpc},
         "time_to_solution_s": h["time_to_solution_s"],
         "status": h["status"],
         "orders": {str(k): v for k, v in out_orders.items()},
@@ -550,7 +533,121 @@ def bench_3d(a, n):
                                "sample": f"{k} whole SSP-RK3 steps of the same workload from its "
                                          f"initial state ({cells * 3 * k} cell-stages) in {el:.1f} s"}
         with torch.cuda.stream(s):
-            S = Solver3(P, stream=s, order=head_order)
+            S = Solver3(P, stream=s, order=head_order, sweeps=SWEEPS3[a.sweeps3])
+            for _ in range(k):
+                S.step()
+        G = S.state()
+        S.close()
+        d = np.abs(G - Q).reshape(5, -1)
+        out["error_vs_oracle"] = {"after_steps": k, "L1": d.mean(1).tolist(),
+                                  "Linf": d.max(1).tolist(),
+                                  "vars": ["rho", "rho_u", "rho_v", "rho_w", "E"]}
+    print(json.dumps(out), flush=True)
+
+
+def bytes_3d(a):
+    return BYTES_PER_CELL_STAGE_3D if a.sweeps3 == "lines" else BYTES_PER_CELL_STAGE_3D_FUSED
+
+
+def step_3d(a):
+    if a.sweeps3 == "lines":
+        return "device dt + 3 x (x, y, z line-sweep kernels)"
+    return "device dt + 3 x (x/y kernel over z-plane tiles + z line-sweep kernel)"
+
+
+def kernel_3d(a):
+    if a.sweeps3 == "lines":
+        return "meg7_sweep3_kernel (x, y, z per stage)"
+    return "meg7_xy3_kernel + meg7_sweep3_kernel (z) per stage"
+
+
+def timed3(a, P, s, order, steps):
+    """Whole-step time of `steps` steps from the initial state (after warm-up
+    steps), then the same steps again with events around every stage's
+    kernels: (ms, ms per stage, status)."""
+    import torch
+    from paper_2305_00762_amd import gbr
+    from paper_2305_00762_amd.solver import Solver3
+    with torch.cuda.stream(s):
+        S = Solver3(P, stream=s, order=order, sweeps=SWEEPS3[a.sweeps3])
+        for _ in range(a.warmup):
+            S.step()
+    s.synchronize()
+    S.Q.copy_(torch.from_numpy(P.Q))
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(s):
+        start.record(s)
+        for _ in range(steps):
+            S.step()
+        stop.record(s)
+    s.synchronize()
+    ms = start.elapsed_time(stop)
+    S.Q.copy_(torch.from_numpy(P.Q))
+    torch.cuda.synchronize()
+    gbr.gbr3_timing(S.ctx, True)
+    with torch.cuda.stream(s):
+        for _ in range(steps):
+            S.step()
+    sweep_ms, calls = gbr.gbr3_timing_read(S.ctx)
+    gbr.gbr3_timing(S.ctx, False)
+    st = gbr.strerror(S.check())
+    S.close()
+    return ms, sweep_ms / max(calls, 1), st
+
+
+def bench_3d_fixed(a, n, steps):
+    """The eight-octant 3D Riemann problem at n^3: a fixed number of steps from
+    the initial state (whole-step throughput and the per-stage kernel time),
+    the other launch form beside it, and the error against the oracle after a
+    few steps."""
+    import numpy as np
+    import torch
+    from paper_2305_00762_amd import problems as PB
+    from paper_2305_00762_amd.solver import Solver3
+    torch.cuda.set_device(0)
+    s = torch.cuda.Stream()
+    P = PB.riemann3d(n, seed=0)
+    cells = P.nx * P.ny * P.nz
+    calibration_copy(a.calib_copy_mb)
+    ms, stage_ms, st = timed3(a, P, s, 7, steps)
+    bpc = bytes_3d(a)
+    achieved = bpc * cells / (stage_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": cells * 3 * steps / (ms * 1e-3), "unit": "cell-stage updates/s",
+        "n_gpus": 1, "steps": steps, "warmup": a.warmup, "ms_per_step": ms / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "description": WORKLOADS[a.workload][4],
+                   "nx": n, "ny": n, "nz": n, "order": 7, "sweeps": a.sweeps3,
+                   "step": step_3d(a)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel_3d(a),
+                     "avg_launch_us": stage_ms * 1e3, "bytes_per_cell_stage": bpc},
+        "status": st,
+    }
+    if not a.no_compare:
+        other = "lines" if a.sweeps3 != "lines" else "fused"
+        b = argparse.Namespace(**vars(a))
+        b.sweeps3 = other
+        ms2, stage2, st2 = timed3(b, P, s, 7, steps)
+        out["other_form"] = {"sweeps": other, "value": cells * 3 * steps / (ms2 * 1e-3),
+                             "ms_per_step": ms2 / steps, "stage_us": stage2 * 1e3, "status": st2}
+    if not a.no_cpu_baseline:
+        import oracle as O
+        cfg = O.make_cfg3(n, n, n, *P.geometry(), bc=P.bc, gamma=P.gamma, order=7)
+        Q = np.ascontiguousarray(P.Q.copy())
+        k = 3
+        t0 = time.perf_counter()
+        for _ in range(k):
+            O.step3(cfg, Q, P.cfl)
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": cells * 3 * k / el, "unit": "cell-stage updates/s",
+                               "cores": O.threads(), "cpu": cpu_model(), "kind": "oracle",
+                               "sample": f"{k} whole SSP-RK3 steps of the same workload from its "
+                                         f"initial state ({cells * 3 * k} cell-stages) in {el:.1f} s"}
+        with torch.cuda.stream(s):
+            S = Solver3(P, stream=s, sweeps=SWEEPS3[a.sweeps3])
             for _ in range(k):
                 S.step()
         G = S.state()
@@ -871,6 +968,8 @@ def main():
         return bench_batch(a, steps)
     if fam == "taylor_green3d":
         return bench_3d(a, n)
+    if fam == "riemann3d":
+        return bench_3d_fixed(a, n, steps)
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     calibration_copy(a.calib_copy_mb)

@@ -428,9 +428,10 @@ int gbr_batch_check(gbr_batch *b, void *stream);
  * reconstruction, characteristic MP limiting (plus an identity row for the
  * second tangential velocity) and HLLC as in 2D.  State Q: device FP64
  * [5][nz][ny][nx] = (rho, rho u, rho v, rho w, E), x fastest, caller-owned.
- * Each residual or stage call runs three line-sweep kernels (x, y, z) that
- * accumulate into context scratch; the z sweep stores the residual or the
- * stage.  Errors as for the 2D entry points.
+ * Each residual or stage call accumulates -dF/dx - dG/dy - dH/dz into
+ * context scratch and the last kernel stores the residual or the stage: by
+ * default three line-sweep kernels, x, y, z (gbr3_set_sweeps selects
+ * another launch form).  Errors as for the 2D entry points.
  * ------------------------------------------------------------------------- */
 typedef struct gbr3_ctx gbr3_ctx;
 
@@ -446,6 +447,19 @@ int gbr3_set_geometry(gbr3_ctx *ctx, double x0, double x1, double y0, double y1,
 
 /* GRB order 7 (default) or 4 (the subset alpha = 4, beta = 0, eq. fourth). */
 int gbr3_set_order(gbr3_ctx *ctx, int order);
+
+/* How a residual or stage call is launched (the same scheme; the residuals
+ * agree to rounding, the flags exactly):
+ *   GBR3_SWEEPS_LINES (default): three line-sweep kernels, x, y, z, each
+ *     reading Q and the accumulator (32 positions x 8 lines per workgroup);
+ *   GBR3_SWEEPS_XY_FUSED: the x and y sweeps in one kernel over
+ *     15x15 tiles of each z plane (the tile staged once, the residual kept
+ *     in registers), then the z line sweep;
+ *   GBR3_SWEEPS_XY_FUSED_HALF: as the fused form, sweeping 8 lines of the
+ *     tile at a time (less LDS per workgroup).
+ * GBR_EINVAL for another value. */
+enum { GBR3_SWEEPS_LINES = 0, GBR3_SWEEPS_XY_FUSED = 1, GBR3_SWEEPS_XY_FUSED_HALF = 2 };
+int gbr3_set_sweeps(gbr3_ctx *ctx, int form);
 
 /* Res = Res(Q) (eqs. eqn-differencing_residual, deriv in 3D).  Q and Res must
  * not overlap. */

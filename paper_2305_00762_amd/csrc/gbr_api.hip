@@ -1271,6 +1271,18 @@ void launch_sweep3(const Sweep3Params& P, int grid, hipStream_t s) {
 const Sweep3Fn kSweep3[2][3] = {
     {launch_sweep3<0, 7>, launch_sweep3<1, 7>, launch_sweep3<2, 7>},
     {launch_sweep3<0, 4>, launch_sweep3<1, 4>, launch_sweep3<2, 4>}};
+// fused x/y forms: 15x15 tiles of a z plane, all 15 lines of a sweep at once
+// (two workgroups per CU) or 8 at a time (three)
+using XY3Fn = void (*)(const XY3Params&, int, hipStream_t);
+template <int NL, int ORD>
+void launch_xy3(const XY3Params& P, int grid, hipStream_t s) {
+  using C = XY3Cfg<15, 15, NL>;
+  static_assert(C::LDS_BYTES <= 160 * 1024, "LDS per workgroup");
+  hipLaunchKernelGGL((meg7_xy3_kernel<C, ORD>), dim3(grid), dim3(C::NT), 0, s, P);
+}
+const XY3Fn kXY3[2][2] = {{launch_xy3<15, 7>, launch_xy3<8, 7>},
+                          {launch_xy3<15, 4>, launch_xy3<8, 4>}};
+constexpr int kXY3T = 15;   // tile side of the fused forms
 }  // namespace
 
 struct gbr3_ctx {
@@ -1279,6 +1291,7 @@ struct gbr3_ctx {
   double lo[3], hi[3];
   int bc[3];
   int order;
+  int sweeps;                 // GBR3_SWEEPS_*
   int device;
   int export_flags;
   unsigned* d_status;         // [4]
@@ -1300,6 +1313,7 @@ int gbr3_init(int nx, int ny, int nz, double gamma, gbr3_ctx** out) {
   c->n[0] = nx; c->n[1] = ny; c->n[2] = nz; c->gamma = gamma;
   for (int d = 0; d < 3; ++d) { c->lo[d] = 0.0; c->hi[d] = 1.0; c->bc[d] = GBR_BC_PERIODIC; }
   c->order = 7;
+  c->sweeps = GBR3_SWEEPS_LINES;
   const size_t n = (size_t)nx * ny * nz;
   bool ok = hipGetDevice(&c->device) == hipSuccess &&
             hipMalloc(&c->d_status, 4 * sizeof(unsigned)) == hipSuccess &&
@@ -1343,6 +1357,12 @@ int gbr3_set_geometry(gbr3_ctx* c, double x0, double x1, double y0, double y1, d
 int gbr3_set_order(gbr3_ctx* c, int order) {
   if (!c || (order != 7 && order != 4)) return GBR_EINVAL;
   c->order = order;
+  return GBR_OK;
+}
+
+int gbr3_set_sweeps(gbr3_ctx* c, int form) {
+  if (!c || form < GBR3_SWEEPS_LINES || form > GBR3_SWEEPS_XY_FUSED_HALF) return GBR_EINVAL;
+  c->sweeps = form;
   return GBR_OK;
 }
 
@@ -1400,7 +1420,26 @@ static int launch3(gbr3_ctx* c, int mode, const double* dt, const double* Qn, co
     c->ev_used += 2;
     if (hipEventRecord(tev[0], s) != hipSuccess) return GBR_EDEVICE;
   }
-  for (int d = 0; d < 3; ++d) {
+  const int o4 = c->order == 4 ? 1 : 0;
+  const bool fused = c->sweeps != GBR3_SWEEPS_LINES;
+  if (fused) {
+    XY3Params X{};
+    X.Qk = Qk; X.R = c->d_R;
+    X.sigx = c->export_flags ? c->d_sig[0] : nullptr;
+    X.sigy = c->export_flags ? c->d_sig[1] : nullptr;
+    X.status = c->d_status;
+    X.nx = c->n[0]; X.ny = c->n[1]; X.nz = c->n[2]; X.bcx = c->bc[0]; X.bcy = c->bc[1];
+    X.tiles_x = (c->n[0] + kXY3T - 1) / kXY3T;
+    X.tiles_y = (c->n[1] + kXY3T - 1) / kXY3T;
+    const long long nt = (long long)X.tiles_x * X.tiles_y * c->n[2];
+    if (nt > 0x7fffffff) return GBR_EINVAL;
+    X.ntiles = (int)nt;
+    X.inv_dx = (double)c->n[0] / (c->hi[0] - c->lo[0]);
+    X.inv_dy = (double)c->n[1] / (c->hi[1] - c->lo[1]);
+    X.gamma = c->gamma; X.g1inv = 1.0 / (c->gamma - 1.0);
+    kXY3[o4][c->sweeps == GBR3_SWEEPS_XY_FUSED ? 0 : 1](X, X.ntiles, s);
+  }
+  for (int d = fused ? 2 : 0; d < 3; ++d) {
     Sweep3Params P{};
     P.Qk = Qk; P.Qn = Qn; P.R = c->d_R; P.out = out; P.dt = dt;
     P.sig = c->export_flags ? c->d_sig[d] : nullptr;
@@ -1409,14 +1448,14 @@ static int launch3(gbr3_ctx* c, int mode, const double* dt, const double* Qn, co
     P.bc = c->bc[d];
     P.inv_d = (double)c->n[d] / (c->hi[d] - c->lo[d]);
     P.gamma = c->gamma; P.g1inv = 1.0 / (c->gamma - 1.0);
-    P.first = d == 0; P.last = d == 2;
+    P.first = !fused && d == 0; P.last = d == 2;
     P.mode = mode;
     P.ptiles = (c->n[d] + k3NP - 1) / k3NP;
     const long long lines = (long long)c->n[(d + 1) % 3] * c->n[(d + 2) % 3];
     const long long groups = (lines + k3NL - 1) / k3NL;
     const long long grid = groups * P.ptiles;
     if (grid > 0x7fffffff) return GBR_EINVAL;
-    kSweep3[c->order == 4 ? 1 : 0][d](P, (int)grid, s);
+    kSweep3[o4][d](P, (int)grid, s);
   }
   if (tev && hipEventRecord(tev[1], s) != hipSuccess) return GBR_EDEVICE;
   return hip_ok(hipGetLastError());

@@ -368,6 +368,301 @@ __global__ __launch_bounds__(256, 2) void meg7_sweep3_kernel(Sweep3Params P) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// The x and y sweeps fused: one workgroup per TX x TY tile of one z plane.
+// The tile plus a 6-cell halo in x and y is staged once as (rho, u, v, w, p);
+// the x sweep and then the y sweep run the passes above on lines of the tile
+// (NL lines at a time), each thread keeping the residual of its cell in
+// registers, and the sum -dF/dx - dG/dy is written to the accumulator once.
+// The z line sweep then adds -dH/dz and stores the residual or the stage.
+// Per cell-stage this moves Q^(k) and the accumulator once instead of three
+// times.  The residual of a cell is accumulated in the order of the line
+// sweeps (0 - dF/dx - dG/dy), so the fused and the line-sweep forms give the
+// same residual up to the pressure of a cell, which the line sweeps form
+// with the squared velocities summed in rotated order.
+struct XY3Params {
+  const double* __restrict__ Qk;  // [5][nz][ny][nx]
+  double* R;                      // accumulator [5][nz][ny][nx] (conserved order)
+  uint8_t* sigx;                  // optional flags [nz][ny][nx+1]
+  uint8_t* sigy;                  // optional flags [nz][ny+1][nx]
+  unsigned* status;
+  int nx, ny, nz, bcx, bcy;
+  int tiles_x, tiles_y, ntiles;
+  double inv_dx, inv_dy, gamma, g1inv;
+};
+
+template <int TX_, int TY_, int NL_>
+struct XY3Cfg {
+  static constexpr int TX = TX_, TY = TY_, NL = NL_, NT = 256, H = 6;
+  static constexpr int RX = TX + 2 * H, RY = TY + 2 * H, RS = RX * RY;
+  static constexpr int CPT = (TX * TY + NT - 1) / NT;
+  static constexpr int imax(int a, int b) { return a > b ? a : b; }
+  static constexpr int WD(int N) { return N + 6; }
+  static constexpr int WF(int N) { return N + 10; }
+  static constexpr int WFL(int N) { return N + 1; }
+  static constexpr int NMAX = imax(TX, TY);
+  static constexpr int D = 5 * NL * WD(NMAX);                               // gradients
+  static constexpr int F = 5 * NL * imax(WF(NMAX), WFL(NMAX) | 1);          // fluxes
+  static constexpr int CHI = NL * WD(NMAX);
+  static constexpr int QMAX = NL * WFL(NMAX);
+  static constexpr int LDS_BYTES = 8 * (5 * RS + D + F) + CHI + 2 * QMAX + 16;
+};
+
+template <class C, int DIR, int ORD>
+__device__ __forceinline__ void sweep_xy3(const XY3Params& P, const double* sU, double* sD,
+                                          double* sF, unsigned char* sChi,
+                                          unsigned short* sQueue, int* sQCount, int l0,
+                                          int tx0, int ty0, int z, double (&res)[C::CPT][5]) {
+  constexpr bool X = DIR == 0;
+  constexpr int N = X ? C::TX : C::TY, NLINES = X ? C::TY : C::TX, NL = C::NL;
+  constexpr int WD = C::WD(N), WF = C::WF(N), WFL = C::WFL(N), WFS = WFL | 1;
+  constexpr int RS = C::RS, RX = C::RX, H = C::H, NT = C::NT;
+  constexpr int SN = X ? 1 : RX;
+  constexpr int FSTR = NL * (WF > WFS ? WF : WFS);   // field stride of sF
+  // rotated component m -> tile field (and conserved component): the
+  // tangential velocities cyclically (x: v, w; y: w, u)
+  constexpr int R1 = X ? 1 : 2, R2 = X ? 2 : 3, R3 = X ? 3 : 1;
+  const int rot[5] = {0, R1, R2, R3, 4};
+  const int tid = threadIdx.x;
+  const int nl = (NLINES - l0) < NL ? (NLINES - l0) : NL;
+  const double inv_d = X ? P.inv_dx : P.inv_dy;
+  auto ridx = [&](int line, int pos) {
+    const int lx = X ? pos : l0 + line;
+    const int ly = X ? l0 + line : pos;
+    return (ly + H) * RX + (lx + H);
+  };
+
+  // ---- pass 1: cell fluxes, gradients, detector ------------------------------
+  for (int t = tid; t < NL * WF; t += NT) {
+    const int line = t / WF, pf = t % WF;
+    if (line >= nl) continue;
+    const int pos = pf - 5;
+    const int r = ridx(line, pos);
+    double W[5], f[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) W[m] = sU[rot[m] * RS + r];
+    conv_flux3(W, P.g1inv, f);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) sF[m * FSTR + line * WF + pf] = f[m];
+    if (pos >= -3 && pos < N + 3) {
+      const int pd = pos + 3;
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        const double* u = sU + rot[m] * RS + r;
+        sD[(m * NL + line) * WD + pd] =
+            grad6(u[-3 * SN], u[-2 * SN], u[-SN], u[SN], u[2 * SN], u[3 * SN]);
+      }
+      const double* rho = sU + r;
+      sChi[line * WD + pd] =
+          detector_flag(rho[-2 * SN], rho[-SN], rho[0], rho[SN], rho[2 * SN]) ? 1 : 0;
+    }
+  }
+  if (tid == 0) *sQCount = 0;
+  __syncthreads();
+
+  // ---- pass 2: interfaces, smooth branch; ballot-compact the flagged --------
+  constexpr int IPT = (NL * WFL + NT - 1) / NT;
+  double fsm[IPT][5];
+  bool has[IPT];
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    has[k] = false;
+    const int t = tid + k * NT;
+    bool flagged = false;
+    if (t < NL * WFL) {
+      const int line = t / WFL, pi = t % WFL;
+      const int pos = pi - 1;                 // interface pos + 1/2
+      if (line < nl) {
+        // eq. (buffer): the six flags read at once and OR-ed
+        unsigned any = 0u;
+#pragma unroll
+        for (int j = 1; j <= 6; ++j) any |= sChi[line * WD + pos + j];
+        const bool sigma = any == 0u;
+        if (X) {
+          const int gy = ty0 + l0 + line, gi = tx0 + pi;
+          if (P.sigx && gy < P.ny && gi <= P.nx)
+            P.sigx[((size_t)z * P.ny + gy) * (P.nx + 1) + gi] = sigma;
+        } else {
+          const int gx = tx0 + l0 + line, gi = ty0 + pi;
+          if (P.sigy && gx < P.nx && gi <= P.ny)
+            P.sigy[((size_t)z * (P.ny + 1) + gi) * P.nx + gx] = sigma;
+        }
+        flagged = !sigma;
+        if (sigma) {
+          const int r = ridx(line, pos);
+          double WL[5], WR[5], Fm[5];
+#pragma unroll
+          for (int m = 0; m < 5; ++m) {
+            const double* u = sU + rot[m] * RS + r;
+            double v[6], g[6], f[10];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) v[q] = u[(q - 2) * SN];
+#pragma unroll
+            for (int q = 1; q < 5; ++q) g[q] = sD[(m * NL + line) * WD + pos + q + 1];
+            g[0] = g[5] = 0.0;
+            WL[m] = grb_l<ORD>(v, g);
+            WR[m] = grb_r<ORD>(v, g);
+#pragma unroll
+            for (int q = 0; q < 10; ++q) f[q] = sF[m * FSTR + line * WF + pos + q + 1];
+            Fm[m] = flux_mean<ORD>(f);
+          }
+          if (!(WL[0] > 0.0 && WL[4] > 0.0 && WR[0] > 0.0 && WR[4] > 0.0)) {
+            double f0[5], f1[5];
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+              WL[m] = sU[rot[m] * RS + r];
+              WR[m] = sU[rot[m] * RS + r + SN];
+            }
+            conv_flux3(WL, P.g1inv, f0);
+            conv_flux3(WR, P.g1inv, f1);
+#pragma unroll
+            for (int m = 0; m < 5; ++m) Fm[m] = 0.5 * (f0[m] + f1[m]);
+          }
+          hllc3(WL, WR, Fm, P.gamma, P.g1inv, fsm[k]);
+          has[k] = true;
+        }
+      }
+    }
+    const unsigned long long ball = __ballot(flagged);
+    if (ball) {
+      const int lane = __lane_id();
+      int base = 0;
+      if (lane == 0) base = atomicAdd(sQCount, (int)__popcll(ball));
+      base = __shfl(base, 0);
+      if (flagged) {
+        const int rank = (int)__popcll(ball & ((1ull << lane) - 1ull));
+        sQueue[base + rank] = (unsigned short)t;
+      }
+    }
+  }
+  __syncthreads();  // every read of the cell fluxes is done: sF becomes the interface fluxes
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    if (has[k]) {
+      const int t = tid + k * NT;
+      const int line = t / WFL, pi = t % WFL;
+#pragma unroll
+      for (int m = 0; m < 5; ++m) sF[m * FSTR + line * WFS + pi] = fsm[k][m];
+    }
+  }
+
+  // ---- pass 3: the flagged interfaces -----------------------------------------
+  const int nq = *sQCount;
+  for (int qi = tid; qi < nq; qi += NT) {
+    const int t = sQueue[qi];
+    const int line = t / WFL, pi = t % WFL;
+    const int pos = pi - 1;
+    const int r = ridx(line, pos);
+    double WL[5], WR[5];
+    meg7_char_states3<ORD>([&](int q, int f) { return sU[rot[f] * RS + r + (q - 2) * SN]; },
+                           [&](int q, int f) { return sD[(f * NL + line) * WD + pos + q + 1]; },
+                           P.gamma, WL, WR);
+    if (!(WL[0] > 0.0 && WL[4] > 0.0 && WR[0] > 0.0 && WR[4] > 0.0)) {
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        WL[m] = sU[rot[m] * RS + r];
+        WR[m] = sU[rot[m] * RS + r + SN];
+      }
+    }
+    double FL[5], FR[5], Fm[5], F[5];
+    conv_flux3(WL, P.g1inv, FL);
+    conv_flux3(WR, P.g1inv, FR);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) Fm[m] = 0.5 * (FL[m] + FR[m]);
+    hllc3(WL, WR, Fm, P.gamma, P.g1inv, F);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) sF[m * FSTR + line * WFS + pi] = F[m];
+  }
+  __syncthreads();
+
+  // ---- pass 4: flux differences into the cell residuals -----------------------
+#pragma unroll
+  for (int k = 0; k < C::CPT; ++k) {
+    const int c = tid + k * NT;
+    if (c < C::TX * C::TY) {
+      const int lx = c % C::TX, ly = c / C::TX;
+      const int line = (X ? ly : lx) - l0;
+      const int pos = X ? lx : ly;
+      if (line >= 0 && line < nl) {
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+          const double d = (sF[m * FSTR + line * WFS + pos + 1] - sF[m * FSTR + line * WFS + pos]) *
+                           inv_d;
+          res[k][rot[m]] -= d;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <class C, int ORD>
+__global__ __launch_bounds__(256, 2) void meg7_xy3_kernel(XY3Params P) {
+  constexpr int RS = C::RS, RX = C::RX, H = C::H, NT = C::NT, TX = C::TX, TY = C::TY;
+  __shared__ double sU[5 * RS];
+  __shared__ double sD[C::D];
+  __shared__ double sF[C::F];
+  __shared__ unsigned char sChi[C::CHI];
+  __shared__ unsigned short sQueue[C::QMAX];
+  __shared__ int sQCount;
+  // tile of this workgroup: consecutive tiles (x fastest, then y, then z) in
+  // one XCD, as in the 2D kernels
+  const int b = blockIdx.x, nb = gridDim.x;
+  const int xcd = b & 7, per = nb >> 3, rem = nb & 7;
+  const int tile = xcd * per + (xcd < rem ? xcd : rem) + (b >> 3);
+  if (tile >= P.ntiles) return;
+  const int tpp = P.tiles_x * P.tiles_y;
+  const int z = tile / tpp, tp = tile - z * tpp;
+  const int tx0 = (tp % P.tiles_x) * TX, ty0 = (tp / P.tiles_x) * TY;
+  const size_t n = (size_t)P.nx * P.ny * P.nz;
+  const size_t zb = (size_t)z * P.ny * P.nx;
+  const int tid = threadIdx.x;
+
+  // ---- load: (rho, u, v, w, p) of the tile and its halo ------------------------
+  bool bad = false;
+  for (int c = tid; c < RS; c += NT) {
+    const int ly = c / RX - H, lx = c % RX - H;
+    const int gy = bc_index(ty0 + ly, P.ny, P.bcy), gx = bc_index(tx0 + lx, P.nx, P.bcx);
+    const size_t s = zb + (size_t)gy * P.nx + gx;
+    const double r = P.Qk[s];
+    const double ir = rcp_nr(r);
+    const double u = P.Qk[n + s] * ir, v = P.Qk[2 * n + s] * ir, w = P.Qk[3 * n + s] * ir;
+    const double E = P.Qk[4 * n + s];
+    const double pr = (P.gamma - 1.0) * (E - 0.5 * r * (u * u + v * v + w * w));
+    sU[c] = r;
+    sU[RS + c] = u;
+    sU[2 * RS + c] = v;
+    sU[3 * RS + c] = w;
+    sU[4 * RS + c] = pr;
+    if (lx >= 0 && lx < TX && ly >= 0 && ly < TY && tx0 + lx < P.nx && ty0 + ly < P.ny &&
+        !(r > 0.0 && pr > 0.0 && isfinite(E) && isfinite(u) && isfinite(v) && isfinite(w)))
+      bad = true;
+  }
+  if (bad) atomicOr(P.status, STATUS_BAD_STATE);
+  __syncthreads();
+
+  double res[C::CPT][5];
+#pragma unroll
+  for (int k = 0; k < C::CPT; ++k)
+#pragma unroll
+    for (int m = 0; m < 5; ++m) res[k][m] = 0.0;
+  for (int l0 = 0; l0 < TY; l0 += C::NL)
+    sweep_xy3<C, 0, ORD>(P, sU, sD, sF, sChi, sQueue, &sQCount, l0, tx0, ty0, z, res);
+  for (int l0 = 0; l0 < TX; l0 += C::NL)
+    sweep_xy3<C, 1, ORD>(P, sU, sD, sF, sChi, sQueue, &sQCount, l0, tx0, ty0, z, res);
+
+#pragma unroll
+  for (int k = 0; k < C::CPT; ++k) {
+    const int c = tid + k * NT;
+    const int gx = tx0 + c % TX, gy = ty0 + c / TX;
+    if (c < TX * TY && gx < P.nx && gy < P.ny) {
+      const size_t s = zb + (size_t)gy * P.nx + gx;
+#pragma unroll
+      for (int m = 0; m < 5; ++m) P.R[m * n + s] = res[k][m];
+    }
+  }
+}
+
 // CFL time step in 3D (inviscid), Sec. 2.5: pass 1 of the two-pass
 // reduction (pass 2 is dt_finish_kernel with no viscous limit).
 struct Dt3Params {

@@ -42,6 +42,9 @@ GBR_PREC_FP64 = 0
 GBR_PREC_FP32_BULK = 1
 GBR_DET_PLAIN = 0
 GBR_DET_MLP = 1
+GBR3_SWEEPS_LINES = 0
+GBR3_SWEEPS_XY_FUSED = 1
+GBR3_SWEEPS_XY_FUSED_HALF = 2
 
 # every symbol include/gbr.h declares, with (restype, argtypes)
 _vp, _i, _d = C.c_void_p, C.c_int, C.c_double
@@ -105,6 +108,7 @@ SIGNATURES = {
     "gbr3_destroy": (_i, [_vp]),
     "gbr3_set_geometry": (_i, [_vp, _d, _d, _d, _d, _d, _d, _i, _i, _i]),
     "gbr3_set_order": (_i, [_vp, _i]),
+    "gbr3_set_sweeps": (_i, [_vp, _i]),
     "gbr3_residual": (_i, [_vp, _vp, _vp, _vp]),
     "gbr3_rk_stage": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
     "gbr3_compute_dt": (_i, [_vp, _vp, _d, _vp, _vp]),
@@ -622,6 +626,10 @@ def gbr3_set_geometry(ctx, x0, x1, y0, y1, z0, z1, bc_x, bc_y, bc_z):
 
 def gbr3_set_order(ctx, order):
     return _check(load().gbr3_set_order(ctx, order), "gbr3_set_order")
+
+
+def gbr3_set_sweeps(ctx, form):
+    return _check(load().gbr3_set_sweeps(ctx, form), "gbr3_set_sweeps")
 
 
 def gbr3_residual(ctx, Q, Res, stream=None):

@@ -152,7 +152,8 @@ class Solver3:
     """3D Euler (inviscid) grid: three device state buffers, SSP-RK3 steps
     through gbr3_compute_dt and gbr3_rk_stage."""
 
-    def __init__(self, problem, device="cuda", stream=None, export_flags=False, order=7):
+    def __init__(self, problem, device="cuda", stream=None, export_flags=False, order=7,
+                 sweeps=None):
         import torch
         self.torch = torch
         self.p = problem
@@ -161,6 +162,8 @@ class Solver3:
         gbr.gbr3_set_geometry(self.ctx, *problem.geometry(), *problem.bc)
         if order != 7:
             gbr.gbr3_set_order(self.ctx, order)
+        if sweeps is not None:
+            gbr.gbr3_set_sweeps(self.ctx, sweeps)
         if export_flags:
             gbr.gbr3_export_flags(self.ctx, True)
         shape = (5, problem.nz, problem.ny, problem.nx)

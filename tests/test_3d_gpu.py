@@ -1,5 +1,7 @@
-"""The 3D extension (inviscid, three line-sweep kernels per stage) vs the 3D
-CPU oracle, through the C ABI.
+"""The 3D extension (inviscid) vs the 3D CPU oracle, through the C ABI, in
+each launch form: three line-sweep kernels, and the x and y sweeps fused over
+15x15 tiles of each z plane (all lines at once, or 8 at a time) followed by
+the z line sweep.
 
 Bar as in 2D: interface flags bit-exact in all three directions; residuals
 within 1e-12 of the flux-divergence scale; states after SSP-RK3 steps within
@@ -19,6 +21,7 @@ from gpu_util import relerr, report, require_gpu
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
+FORMS = [gbr.GBR3_SWEEPS_LINES, gbr.GBR3_SWEEPS_XY_FUSED, gbr.GBR3_SWEEPS_XY_FUSED_HALF]
 
 
 def ocfg3(P, order=7):
@@ -39,10 +42,11 @@ def flux_scale3(P):
     return m / d
 
 
-def check3(name, P, order=7):
+def check3(name, P, order=7, sweeps=gbr.GBR3_SWEEPS_LINES):
     from paper_2305_00762_amd.solver import Solver3
     torch = require_gpu()
-    S = Solver3(P, export_flags=True, order=order)
+    S = Solver3(P, export_flags=True, order=order, sweeps=sweeps)
+    name = f"{name} form{sweeps}"
     R = S.residual()
     torch.cuda.synchronize()
     sx, sy, sz = S.flags()
@@ -61,41 +65,47 @@ def check3(name, P, order=7):
     return nflag
 
 
-def test_advected_wave():
-    assert check3("3d advected wave 24^3", PB.advected_wave3d(24)) == 0
+@pytest.mark.parametrize("sweeps", FORMS)
+def test_advected_wave(sweeps):
+    assert check3("3d advected wave 24^3", PB.advected_wave3d(24), sweeps=sweeps) == 0
 
 
+@pytest.mark.parametrize("sweeps", FORMS)
 @pytest.mark.parametrize("bc", [PB.BC_PERIODIC, PB.BC_TRANSMISSIVE])
 @pytest.mark.parametrize("seed", [0, 1])
-def test_riemann3d_ragged(seed, bc):
+def test_riemann3d_ragged(seed, bc, sweeps):
     P = PB.riemann3d(40, seed=seed, ny=33, nz=20)
     P.bc = (bc,) * 3
-    assert check3(f"3d riemann 40x33x20 s{seed} bc{bc}", P) > 0
+    assert check3(f"3d riemann 40x33x20 s{seed} bc{bc}", P, sweeps=sweeps) > 0
 
 
-def test_riemann3d_mixed_bc_and_order4():
+@pytest.mark.parametrize("sweeps", FORMS)
+def test_riemann3d_mixed_bc_and_order4(sweeps):
     P = PB.riemann3d(36, seed=3, ny=13, nz=45)
     P.bc = (PB.BC_TRANSMISSIVE, PB.BC_PERIODIC, PB.BC_TRANSMISSIVE)
-    check3("3d riemann 36x13x45 mixed", P)
-    check3("3d riemann 36x13x45 mixed order4", P, order=4)
+    check3("3d riemann 36x13x45 mixed", P, sweeps=sweeps)
+    check3("3d riemann 36x13x45 mixed order4", P, order=4, sweeps=sweeps)
 
 
-def test_smallest_grid():
-    check3("3d riemann 12^3", PB.riemann3d(12, seed=4))
+@pytest.mark.parametrize("sweeps", FORMS)
+def test_smallest_grid(sweeps):
+    check3("3d riemann 12^3", PB.riemann3d(12, seed=4), sweeps=sweeps)
 
 
-def test_taylor_green_64_full_size():
-    check3("3d taylor-green 64^3", PB.taylor_green3d(64))
-    check3("3d taylor-green 64^3 order4", PB.taylor_green3d(64), order=4)
+@pytest.mark.parametrize("sweeps", FORMS)
+def test_taylor_green_64_full_size(sweeps):
+    check3("3d taylor-green 64^3", PB.taylor_green3d(64), sweeps=sweeps)
+    check3("3d taylor-green 64^3 order4", PB.taylor_green3d(64), order=4, sweeps=sweeps)
 
 
+@pytest.mark.parametrize("sweeps", FORMS)
 @pytest.mark.parametrize("order", [7, 4])
-def test_trajectory_riemann3d(order):
+def test_trajectory_riemann3d(order, sweeps):
     from paper_2305_00762_amd.solver import Solver3
     torch = require_gpu()
     P = PB.riemann3d(32, seed=5, ny=24, nz=20)
     cfg = ocfg3(P, order)
-    S = Solver3(P, order=order)
+    S = Solver3(P, order=order, sweeps=sweeps)
     Q = P.Q.copy()
     for k in range(10):
         do = O.step3(cfg, Q, P.cfl)
@@ -104,7 +114,7 @@ def test_trajectory_riemann3d(order):
             torch.cuda.synchronize()
             assert float(S.dt.cpu()[0]) == do
     e = relerr(S.state().reshape(5, -1), Q.reshape(5, -1))
-    report(f"3d riemann 32x24x20 10 steps order{order}", relerr=e.max())
+    report(f"3d riemann 32x24x20 10 steps order{order} form{sweeps}", relerr=e.max())
     assert (e <= TOL).all(), e
     assert S.check() == gbr.GBR_OK
     S.close()
@@ -128,6 +138,30 @@ def test_trajectory_taylor_green():
     S.close()
 
 
+@pytest.mark.parametrize("order", [7, 4])
+def test_forms_agree(order):
+    """The fused forms against the line sweeps on the same state: interface
+    flags identical, residuals equal to rounding (the cell pressure is formed
+    with the squared velocities summed in another order)."""
+    from paper_2305_00762_amd.solver import Solver3
+    torch = require_gpu()
+    P = PB.riemann3d(47, seed=6, ny=31, nz=17)
+    out = []
+    for f in FORMS:
+        S = Solver3(P, export_flags=True, order=order, sweeps=f)
+        R = S.residual()
+        torch.cuda.synchronize()
+        out.append((R.cpu().numpy(), S.flags()))
+        S.close()
+    R0, f0 = out[0]
+    scale = np.maximum(np.abs(R0).reshape(5, -1).max(1), flux_scale3(P))
+    for (R, fl), f in zip(out[1:], FORMS[1:]):
+        e = np.abs(R - R0).reshape(5, -1).max(1) / scale
+        report(f"3d forms {f} vs lines order{order}", relerr=e.max())
+        assert all((a == b).all() for a, b in zip(fl, f0))
+        assert (e <= 1e-13).all(), e
+
+
 def test_argument_errors():
     torch = require_gpu()
     with pytest.raises(gbr.GbrError):
@@ -137,6 +171,8 @@ def test_argument_errors():
     ctx = gbr.gbr3_init(16, 16, 16, 1.4)
     with pytest.raises(gbr.GbrError):
         gbr.gbr3_set_order(ctx, 5)
+    with pytest.raises(gbr.GbrError):
+        gbr.gbr3_set_sweeps(ctx, 3)
     with pytest.raises(gbr.GbrError):
         gbr.gbr3_set_geometry(ctx, 0, 1, 0, 1, 1, 0, 0, 0, 0)
     Q = torch.zeros((5, 16, 16, 16), dtype=torch.float64, device="cuda")
