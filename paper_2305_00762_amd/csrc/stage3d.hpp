@@ -158,8 +158,14 @@ __global__ __launch_bounds__(256, 2) void meg7_sweep3_kernel(Sweep3Params P) {
   const int ndir = DIR == 0 ? P.nx : (DIR == 1 ? P.ny : P.nz);
   const size_t sdir = DIR == 0 ? 1 : (DIR == 1 ? (size_t)P.nx : (size_t)P.nx * P.ny);
   const int nlines = DIR == 0 ? P.ny * P.nz : (DIR == 1 ? P.nx * P.nz : P.nx * P.ny);
-  const int ptile = blockIdx.x % P.ptiles;
-  const int group = blockIdx.x / P.ptiles;
+  // workgroups are dealt to the 8 XCDs round-robin: give each XCD one
+  // contiguous run of tiles, so the halo of neighbouring position tiles and
+  // the 128-byte lines that neighbouring line groups share (y and z sweeps:
+  // 8 consecutive x per position) meet in one L2
+  const int xcd = blockIdx.x & 7, per = gridDim.x >> 3, rem = gridDim.x & 7;
+  const int tile = xcd * per + (xcd < rem ? xcd : rem) + (blockIdx.x >> 3);
+  const int ptile = tile % P.ptiles;
+  const int group = tile / P.ptiles;
   const int p0 = ptile * NP;
   // first cell of line L (position 0)
   auto line_base = [&](int L) -> size_t {
