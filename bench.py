@@ -120,7 +120,7 @@ def parse():
                     help="timed steps (default: the workload's step count)")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="riemann4096", choices=sorted(WORKLOADS))
-    ap.add_argument("--path", default="fp32_mlp_step", choices=sorted(PATHS))
+    ap.add_argument("--path", default="fp32_mlp", choices=sorted(PATHS))
     ap.add_argument("--weights", default=None, help="detector weights (.npz)")
     ap.add_argument("--margin", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -841,18 +841,22 @@ def public(rec):
 
 
 def compare_paths(head_path):
-    """Paths run beside the headline one: the plain FP64 path always; the
-    FP32-bulk path with the plain detector for an FP32-bulk headline; the
-    per-stage learned detector beside the per-step one."""
+    """Paths run beside the headline one: the plain FP64 path always (first:
+    the others' errors are taken against it); the FP32-bulk path with the
+    plain detector for an FP32-bulk headline; the learned detector once per
+    step beside the per-stage one and the reverse."""
     out = ["fp64"] if head_path != "fp64" else []
     if PATHS[head_path]["prec"] == "fp32" and head_path != "fp32":
         out.append("fp32")
     if head_path == "fp32_mlp_step":
         out.append("fp32_mlp")
+    if head_path == "fp32_mlp":
+        out.append("fp32_mlp_step")
     return out
 
 
-COMPARE_KEY = {"fp64": "fp64_plain", "fp32": "fp32_plain", "fp32_mlp": "fp32_mlp_per_stage"}
+COMPARE_KEY = {"fp64": "fp64_plain", "fp32": "fp32_plain", "fp32_mlp": "fp32_mlp_per_stage",
+               "fp32_mlp_step": "fp32_mlp_per_step"}
 
 
 def bench_2d(a, workload, steps_arg, stream, cpu=True, secondary=False):
@@ -908,9 +912,13 @@ def bench_2d(a, workload, steps_arg, stream, cpu=True, secondary=False):
     out.update({k: v for k, v in public(head_rec).items()
                 if k not in ("value", "ms_per_step", "steps", "tile", "status")})
     if head.net is not None and head_rec["_det_ms"] > 0:
-        # flag map: reads Q (32 B) and writes one byte per cell, per evaluation
-        evals = steps * (1 if PATHS[a.path]["per_step"] else 3)
-        out["detector_flag_map_GBs"] = 33.0 * cells * evals / (head_rec["_det_ms"] * 1e-3) / 1e9
+        # flag map: reads Q (32 B) and writes one byte per cell, per evaluation;
+        # evaluated once per step, it reads after the first step the float32
+        # (rho, p) the previous stage 3 stored (8 B)
+        per_step = PATHS[a.path]["per_step"]
+        evals = steps * (1 if per_step else 3)
+        nbytes = (33.0 + 9.0 * (steps - 1)) if per_step else 33.0 * evals
+        out["detector_flag_map_GBs"] = nbytes * cells / (head_rec["_det_ms"] * 1e-3) / 1e9
         out["detector_vs_plain"] = detector_vs_plain(P, head, Qhead)
     head.close()
 
@@ -928,6 +936,9 @@ def bench_2d(a, workload, steps_arg, stream, cpu=True, secondary=False):
             if cp == "fp64":
                 base_Q = Qc
             else:
+                if base_Q is not None:
+                    l1, linf = diff(Qc, base_Q)
+                    out[key]["error_vs_fp64_plain"] = {"L1": l1, "Linf": linf}
                 del Qc
         if base_Q is not None:
             l1, linf = diff(Qhead, base_Q)

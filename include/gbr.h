@@ -313,12 +313,15 @@ int gbr_mlp_stats(gbr_ctx *ctx, uint64_t *evaluated, uint64_t *fallbacks, int re
  * GBR_EINVAL.  With per_step = 1 every stage-3 call also stores the density
  * and pressure of its output, rounded to float32, in a context buffer
  * (8*nx*ny bytes, allocated by the first call with per_step = 1;
- * GBR_ENOMEM if that fails), and the next flag map whose input is that same
- * output buffer reads them instead of the state -- the values it would
- * compute from it, so the flags are unchanged.  A caller that writes that
- * buffer between a stage-3 call and the next step calls gbr_set_mlp_reuse
- * again, which drops the stored values.  GBR_EINVAL if per_step is not 0
- * or 1. */
+ * GBR_ENOMEM if that fails).  Like the time-step extrema of gbr_stage_dt
+ * they describe the output as that call wrote it: when gbr_stage_dt takes
+ * the next step's time step from those extrema, the next flag map whose
+ * input is that same output buffer reads the stored values instead of the
+ * state (the values it would compute from it, so the flags are unchanged).
+ * A step begun otherwise -- gbr_compute_dt, a time step of the caller's, a
+ * state the caller wrote -- evaluates the flag map from the state; a caller
+ * that writes the output buffer and then calls gbr_stage_dt breaks both
+ * contracts alike.  GBR_EINVAL if per_step is not 0 or 1. */
 int gbr_set_mlp_reuse(gbr_ctx *ctx, int per_step);
 
 /* Copy the learned detector's per-cell flag map of the last evaluation

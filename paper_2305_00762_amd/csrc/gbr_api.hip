@@ -184,9 +184,11 @@ struct gbr_ctx {
   int chimap_valid;           // a flag map has been evaluated
   // per-step detector: float32 (rho, p) of the last stage-3 output [2][ny][nx],
   // written by that stage kernel and read by the next flag map in place of Q
+  // when gbr_stage_dt took the step's time step from that output (armed)
   float* d_rp;
   const double* rp_src;       // the stage-3 output d_rp describes
   int rp_valid;
+  int rp_armed;
   unsigned long long* d_mlp_fb;   // plain fallbacks of the learned detector
   unsigned long long mlp_evaluated;
   // kernel timing (gbr_timing): events recorded around every launch of a
@@ -513,7 +515,8 @@ static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn
   if (det && !reuse) {
     MlpChiParams M{};
     M.Q = Qk; M.chi = c->d_chimap; M.nfb = c->d_mlp_fb;
-    M.rp = (c->mlp_reuse && c->rp_valid && c->rp_src == Qk) ? c->d_rp : nullptr;
+    M.rp = (c->mlp_reuse && c->rp_armed && c->rp_valid && c->rp_src == Qk) ? c->d_rp : nullptr;
+    c->rp_armed = 0;
     M.M.W1 = c->d_mlp_w;
     M.M.W2 = c->d_mlp_w + kMlpH * kMlpIn;
     M.M.w3 = c->d_mlp_f;
@@ -539,6 +542,7 @@ static int launch_stage(gbr_ctx* c, int mode, const double* dt, const double* Qn
     c->stage3_slots = P.ntiles * kStageWaves;
     c->rp_valid = P.rp != nullptr;
     c->rp_src = out;
+    c->rp_armed = 0;
   }
   return hip_ok(hipGetLastError());
 }
@@ -649,6 +653,7 @@ int gbr_compute_dt(gbr_ctx* c, const double* Q, double cfl, double* dt_dev, void
   hipLaunchKernelGGL(dt_reduce_kernel, dim3(blocks), dim3(kDtThreads), 0, s, P);
   hipLaunchKernelGGL(dt_finish_kernel, dim3(1), dim3(kDtThreads), 0, s, c->d_partial, blocks,
                      dt_dev, cfl, c->d_status);
+  c->rp_armed = 0;   // a step begun from the state itself
   return hip_ok(hipGetLastError());
 }
 
@@ -684,6 +689,7 @@ int gbr_stage_dt(gbr_ctx* c, double cfl, double* dt_dev, void* stream) {
                      (const double*)c->d_partial, blocks, dt_dev, cfl,
                      (c->x1 - c->x0) / c->nx, (c->y1 - c->y0) / c->ny, c->mu, c->d_status);
   c->stage3_slots = 0;
+  c->rp_armed = c->rp_valid;
   return hip_ok(hipGetLastError());
 }
 
@@ -841,6 +847,7 @@ int gbr_set_mlp_reuse(gbr_ctx* c, int per_step) {
   }
   c->mlp_reuse = per_step;
   c->rp_valid = 0;
+  c->rp_armed = 0;
   return GBR_OK;
 }
 

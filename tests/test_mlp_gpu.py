@@ -339,6 +339,36 @@ def test_per_step_flag_map_from_stored_values(fam, precision):
     gbr.gbr_mlp_destroy(m)
 
 
+def test_per_step_state_written_between_steps():
+    """A step begun with gbr_compute_dt evaluates the flag map from the state
+    even when its input is the buffer the last stage-3 call wrote: after
+    steps with the fused time step, the initial state is copied back into
+    that buffer, and the flag map equals that of a fresh context on the
+    initial state."""
+    from paper_2305_00762_amd.solver import Solver
+    torch = require_gpu()
+    m, w, b = make_net(5)
+    P = PB.riemann(90, seed=7, ny=70)
+    margin = split_margin(oracle_logits(P, w, b))
+    maps = []
+    for nsteps in (3, 0):
+        S = Solver(P, precision=1, fused_dt=True)
+        gbr.gbr_set_mlp_detector(S.ctx, m, margin)
+        gbr.gbr_set_scheme(S.ctx, gbr.GBR_RECON_PRIM, gbr.GBR_MP_FLAGGED, 1, gbr.GBR_DET_MLP)
+        gbr.gbr_set_mlp_reuse(S.ctx, True)
+        for _ in range(nsteps):
+            S.step()
+        S.Q.copy_(torch.from_numpy(P.Q))
+        gbr.gbr_compute_dt(S.ctx, S.Q, P.cfl, S.dt)
+        gbr.gbr_rk_stage(S.ctx, 1, S.dt, S.Q, S.Q, S.Q1)
+        maps.append(gbr.gbr_mlp_get_flagmap(S.ctx))
+        S.close()
+    report("flag map after a written state", flagged=float((maps[1] != 0).mean()),
+           differ=int((maps[0] != maps[1]).sum()))
+    assert (maps[0] == maps[1]).all()
+    gbr.gbr_mlp_destroy(m)
+
+
 def test_feature_reciprocal_is_correctly_rounded():
     """The features' reciprocal (hardware estimate plus one fused Newton
     step) equals IEEE float32 division for every normal float below 2^126:
