@@ -466,7 +466,7 @@ def bench_3d(a, n):
         """Steps to t = 10 with diagnostics at t = 1..10 (device time summed on
         the stream, read after batches that shrink near each target)."""
         with torch.cuda.stream(s):
-            S = Solver3(P, stream=s, order=order, sweeps=SWEEPS3[a.sweeps3])
+            S = Solver3(P, stream=s, order=order, sweeps=SWEEPS3[a.sweeps3], fused_dt=True)
             tacc = torch.zeros(1, dtype=torch.float64, device="cuda")
         k0 = tg_diagnostics(P.Q, dx)
         hist, steps, batch = [], 0, 50
@@ -533,7 +533,7 @@ def bench_3d(a, n):
                                "sample": f"{k} whole SSP-RK3 steps of the same workload from its "
                                          f"initial state ({cells * 3 * k} cell-stages) in {el:.1f} s"}
         with torch.cuda.stream(s):
-            S = Solver3(P, stream=s, order=head_order, sweeps=SWEEPS3[a.sweeps3])
+            S = Solver3(P, stream=s, order=head_order, sweeps=SWEEPS3[a.sweeps3], fused_dt=True)
             for _ in range(k):
                 S.step()
         G = S.state()
@@ -550,9 +550,10 @@ def bytes_3d(a):
 
 
 def step_3d(a):
+    dt = "dt (first step: reduction over Q^n; then from the stage-3 extrema)"
     if a.sweeps3 == "lines":
-        return "device dt + 3 x (x, y, z line-sweep kernels)"
-    return "device dt + 3 x (x/y kernel over z-plane tiles + z line-sweep kernel)"
+        return f"{dt} + 3 x (x, y, z line-sweep kernels)"
+    return f"{dt} + 3 x (x/y kernel over z-plane tiles + z line-sweep kernel)"
 
 
 def kernel_3d(a):
@@ -569,11 +570,11 @@ def timed3(a, P, s, order, steps):
     from paper_2305_00762_amd import gbr
     from paper_2305_00762_amd.solver import Solver3
     with torch.cuda.stream(s):
-        S = Solver3(P, stream=s, order=order, sweeps=SWEEPS3[a.sweeps3])
+        S = Solver3(P, stream=s, order=order, sweeps=SWEEPS3[a.sweeps3], fused_dt=True)
         for _ in range(a.warmup):
             S.step()
     s.synchronize()
-    S.Q.copy_(torch.from_numpy(P.Q))
+    S.set_state(P.Q)
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     with torch.cuda.stream(s):
@@ -583,7 +584,7 @@ def timed3(a, P, s, order, steps):
         stop.record(s)
     s.synchronize()
     ms = start.elapsed_time(stop)
-    S.Q.copy_(torch.from_numpy(P.Q))
+    S.set_state(P.Q)
     torch.cuda.synchronize()
     gbr.gbr3_timing(S.ctx, True)
     with torch.cuda.stream(s):
@@ -647,7 +648,7 @@ def bench_3d_fixed(a, n, steps):
                                "sample": f"{k} whole SSP-RK3 steps of the same workload from its "
                                          f"initial state ({cells * 3 * k} cell-stages) in {el:.1f} s"}
         with torch.cuda.stream(s):
-            S = Solver3(P, stream=s, sweeps=SWEEPS3[a.sweeps3])
+            S = Solver3(P, stream=s, sweeps=SWEEPS3[a.sweeps3], fused_dt=True)
             for _ in range(k):
                 S.step()
         G = S.state()

@@ -476,6 +476,14 @@ int gbr3_rk_stage(gbr3_ctx *ctx, int stage, const double *dt_dev, const double *
  * inviscid), to a device scalar; deterministic. */
 int gbr3_compute_dt(gbr3_ctx *ctx, const double *Q, double cfl, double *dt_dev, void *stream);
 
+/* The same time step of the state the last stage-3 call wrote, from the
+ * extrema max(|u|+c), max(|v|+c), max(|w|+c) its z sweep reduced while
+ * writing it (as gbr_stage_dt in 2D): equal to gbr3_compute_dt on that state
+ * bit for bit, provided the state was not modified after the stage-3 call.
+ * Each stage-3 output serves one call; GBR_EINVAL when no stage-3 call came
+ * since the last one (or since gbr3_init).  cfl > 0; dt_dev: device double. */
+int gbr3_stage_dt(gbr3_ctx *ctx, double cfl, double *dt_dev, void *stream);
+
 /* Interface flags of the last residual or stage (after gbr3_export_flags(ctx,
  * 1)): host arrays [nz][ny][nx+1], [nz][ny+1][nx], [nz+1][ny][nx]; any may be
  * NULL.  Synchronous. */

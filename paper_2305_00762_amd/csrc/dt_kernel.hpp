@@ -143,19 +143,22 @@ __device__ __forceinline__ double block_max(double v, double* red) {
   return r;
 }
 
+// MAX3: the third extremum is a maximum (3D: max(|w|+c)), else a minimum
+// (2D: min rho).
+template <bool MAX3 = false>
 __global__ __launch_bounds__(kDtThreads) void dt_extrema_reduce_kernel(const double* slots,
                                                                        int nslot,
                                                                        double* partial) {
   __shared__ double red[kDtThreads / 64];
-  double a = 0.0, b = 0.0, r = __builtin_inf();
+  double a = 0.0, b = 0.0, r = MAX3 ? 0.0 : __builtin_inf();
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nslot; k += gridDim.x * blockDim.x) {
     a = fmax(a, slots[k]);
     b = fmax(b, slots[nslot + k]);
-    r = fmin(r, slots[2 * nslot + k]);
+    r = MAX3 ? fmax(r, slots[2 * nslot + k]) : fmin(r, slots[2 * nslot + k]);
   }
   a = block_max(a, red);
   b = block_max(b, red);
-  r = block_min(r, red);
+  r = MAX3 ? block_max(r, red) : block_min(r, red);
   if (threadIdx.x == 0) {
     partial[blockIdx.x] = a;
     partial[kDtBlocks + blockIdx.x] = b;
@@ -187,6 +190,33 @@ __global__ __launch_bounds__(kDtThreads) void dt_from_extrema_kernel(const doubl
       visc = fmin(dx * dx / nu, dy * dy / nu);
     }
     const double d = cfl * fmin(visc / kAlphaV, conv);
+    *dt = d;
+    if (!(d > 0.0) || !isfinite(d)) atomicOr(status, 2u);
+  }
+}
+
+// 3D (inviscid): dt = cfl min(dx/a, dy/b, dz/c) from the partial maxima of
+// |u|+c, |v|+c, |w|+c, with the arithmetic of dt3_reduce_kernel and
+// dt_finish_kernel.
+__global__ __launch_bounds__(kDtThreads) void dt3_from_extrema_kernel(const double* partial,
+                                                                      int nblk, double* dt,
+                                                                      double cfl, double dx,
+                                                                      double dy, double dz,
+                                                                      unsigned* status) {
+#pragma clang fp contract(off)
+  __shared__ double red[kDtThreads / 64];
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += blockDim.x) {
+    a = fmax(a, partial[k]);
+    b = fmax(b, partial[kDtBlocks + k]);
+    c = fmax(c, partial[2 * kDtBlocks + k]);
+  }
+  a = block_max(a, red);
+  b = block_max(b, red);
+  c = block_max(c, red);
+  if (threadIdx.x == 0) {
+    const double conv = fmin(dx / a, fmin(dy / b, dz / c));
+    const double d = cfl * fmin(__builtin_inf() / kAlphaV, conv);
     *dt = d;
     if (!(d > 0.0) || !isfinite(d)) atomicOr(status, 2u);
   }

@@ -683,7 +683,7 @@ int gbr_stage_dt(gbr_ctx* c, double cfl, double* dt_dev, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   const int nslot = c->stage3_slots;
   const int blocks = dt_blocks((size_t)nslot);
-  hipLaunchKernelGGL(dt_extrema_reduce_kernel, dim3(blocks), dim3(kDtThreads), 0, s,
+  hipLaunchKernelGGL(dt_extrema_reduce_kernel<false>, dim3(blocks), dim3(kDtThreads), 0, s,
                      (const double*)c->d_dtx, nslot, c->d_partial);
   hipLaunchKernelGGL(dt_from_extrema_kernel, dim3(1), dim3(kDtThreads), 0, s,
                      (const double*)c->d_partial, blocks, dt_dev, cfl,
@@ -1304,6 +1304,8 @@ struct gbr3_ctx {
   unsigned* d_status;         // [4]
   double* d_partial;          // [2][kDtBlocks]
   double* d_R;                // [5][nz][ny][nx] residual accumulator
+  double* d_dtx;              // [3][slots] per-wave time-step extrema of a stage-3 output
+  int stage3_slots;           // slots of the last stage-3 call; 0: none since gbr3_stage_dt
   uint8_t* d_sig[3];          // optional interface flags per direction
   int timing;
   std::vector<hipEvent_t> ev; // two per residual or stage call
@@ -1322,14 +1324,18 @@ int gbr3_init(int nx, int ny, int nz, double gamma, gbr3_ctx** out) {
   c->order = 7;
   c->sweeps = GBR3_SWEEPS_LINES;
   const size_t n = (size_t)nx * ny * nz;
+  // the z sweep's workgroups: line groups of the xy plane x position tiles
+  const size_t zslots = 4 * (((size_t)nx * ny + k3NL - 1) / k3NL) * ((nz + k3NP - 1) / k3NP);
   bool ok = hipGetDevice(&c->device) == hipSuccess &&
             hipMalloc(&c->d_status, 4 * sizeof(unsigned)) == hipSuccess &&
-            hipMalloc(&c->d_partial, 2 * kDtBlocks * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->d_partial, 3 * kDtBlocks * sizeof(double)) == hipSuccess &&
             hipMalloc(&c->d_R, 5 * n * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->d_dtx, 3 * zslots * sizeof(double)) == hipSuccess &&
             hipMemset(c->d_status, 0, 4 * sizeof(unsigned)) == hipSuccess &&
             hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
     (void)hipFree(c->d_status); (void)hipFree(c->d_partial); (void)hipFree(c->d_R);
+    (void)hipFree(c->d_dtx);
     delete c;
     return GBR_ENOMEM;
   }
@@ -1343,6 +1349,7 @@ int gbr3_destroy(gbr3_ctx* c) {
   (void)hipFree(c->d_status);
   (void)hipFree(c->d_partial);
   (void)hipFree(c->d_R);
+  (void)hipFree(c->d_dtx);
   for (int d = 0; d < 3; ++d)
     if (c->d_sig[d]) (void)hipFree(c->d_sig[d]);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -1462,7 +1469,9 @@ static int launch3(gbr3_ctx* c, int mode, const double* dt, const double* Qn, co
     const long long groups = (lines + k3NL - 1) / k3NL;
     const long long grid = groups * P.ptiles;
     if (grid > 0x7fffffff) return GBR_EINVAL;
+    P.dtx = (d == 2 && mode == MODE_STAGE3) ? c->d_dtx : nullptr;
     kSweep3[o4][d](P, (int)grid, s);
+    if (P.dtx) c->stage3_slots = (int)grid * 4;
   }
   if (tev && hipEventRecord(tev[1], s) != hipSuccess) return GBR_EDEVICE;
   return hip_ok(hipGetLastError());
@@ -1496,6 +1505,21 @@ int gbr3_compute_dt(gbr3_ctx* c, const double* Q, double cfl, double* dt_dev, vo
   hipLaunchKernelGGL(dt3_reduce_kernel, dim3(blocks), dim3(kDtThreads), 0, s, P);
   hipLaunchKernelGGL(dt_finish_kernel, dim3(1), dim3(kDtThreads), 0, s, c->d_partial, blocks,
                      dt_dev, cfl, c->d_status);
+  return hip_ok(hipGetLastError());
+}
+
+int gbr3_stage_dt(gbr3_ctx* c, double cfl, double* dt_dev, void* stream) {
+  if (!c || !dt_dev || !(cfl > 0.0) || c->stage3_slots <= 0) return GBR_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int nslot = c->stage3_slots;
+  const int blocks = dt_blocks((size_t)nslot);
+  hipLaunchKernelGGL(dt_extrema_reduce_kernel<true>, dim3(blocks), dim3(kDtThreads), 0, s,
+                     (const double*)c->d_dtx, nslot, c->d_partial);
+  hipLaunchKernelGGL(dt3_from_extrema_kernel, dim3(1), dim3(kDtThreads), 0, s,
+                     (const double*)c->d_partial, blocks, dt_dev, cfl,
+                     (c->hi[0] - c->lo[0]) / c->n[0], (c->hi[1] - c->lo[1]) / c->n[1],
+                     (c->hi[2] - c->lo[2]) / c->n[2], c->d_status);
+  c->stage3_slots = 0;
   return hip_ok(hipGetLastError());
 }
 

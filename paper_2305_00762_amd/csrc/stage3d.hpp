@@ -36,7 +36,29 @@ struct Sweep3Params {
   int first, last;                // first sweep writes R; the last one stores
   int mode;                       // MODE_RESIDUAL or MODE_STAGE1..3
   int ptiles;                     // position tiles along the direction
+  // last sweep of stage 3 only (else null): per-wave time-step extrema of
+  // the output, [3][gridDim.x x 4]: max(|u|+c), max(|v|+c), max(|w|+c)
+  double* dtx;
 };
+
+// |u|+c, |v|+c, |w|+c of one cell of the new state, each rounded as the
+// time-step kernel rounds them (IEEE division and square root, one rounding
+// per operation), folded into (ea, eb, ec); since fl(d/x) is monotone in x,
+// the minima of the per-cell limits follow from the maxima without loss.
+__device__ __forceinline__ void dt3_extrema_cell(const double q[5], double gamma, double& ea,
+                                                 double& eb, double& ec, bool& bad) {
+#pragma clang fp contract(off)
+  const double rho = q[0];
+  const double u = q[1] / rho, v = q[2] / rho, w = q[3] / rho;
+  const double p = (gamma - 1.0) * (q[4] - rho * (u * u + v * v + w * w) / 2.0);
+  const double c = sqrt(gamma * p / rho);
+  if (!(rho > 0.0) || !(p > 0.0) || !isfinite(c) || !isfinite(u) || !isfinite(v) ||
+      !isfinite(w))
+    bad = true;
+  ea = fmax(ea, fabs(u) + c);
+  eb = fmax(eb, fabs(v) + c);
+  ec = fmax(ec, fabs(w) + c);
+}
 
 // Normal convective flux of W = (rho, u_n, u_t1, u_t2, p).
 __device__ __forceinline__ void conv_flux3(const double W[5], double g1inv, double F[5]) {
@@ -347,6 +369,8 @@ __global__ __launch_bounds__(256, 2) void meg7_sweep3_kernel(Sweep3Params P) {
 
   // ---- pass 4: flux differences; residual accumulation / stage update ------
   const double dtv = (P.last && P.mode != MODE_RESIDUAL) ? *P.dt : 0.0;
+  double ea = 0.0, eb = 0.0, ec = 0.0;   // time-step extrema (stage 3, P.dtx)
+  bool ebad = false;
   for (int t = tid; t < NL * NP; t += NT) {
     const int l = LINEFAST ? t % NL : t / NP;
     const int pc = LINEFAST ? t / NL : t % NP;
@@ -354,6 +378,7 @@ __global__ __launch_bounds__(256, 2) void meg7_sweep3_kernel(Sweep3Params P) {
     const int q = p0 + pc;
     if (L >= nlines || q >= ndir) continue;
     const size_t s = line_base(L) + (size_t)q * sdir;
+    double nv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // the new state, conserved order (stage 3)
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
       const size_t o = (size_t)cidx(m) * n + s;
@@ -368,8 +393,26 @@ __global__ __launch_bounds__(256, 2) void meg7_sweep3_kernel(Sweep3Params P) {
       } else if (P.mode == MODE_STAGE2) {
         P.out[o] = 0.75 * P.Qn[o] + 0.25 * P.Qk[o] + (0.25 * dtv) * r;
       } else {
-        P.out[o] = (1.0 / 3.0) * P.Qn[o] + (2.0 / 3.0) * P.Qk[o] + ((2.0 / 3.0) * dtv) * r;
+        const double v = (1.0 / 3.0) * P.Qn[o] + (2.0 / 3.0) * P.Qk[o] + ((2.0 / 3.0) * dtv) * r;
+        P.out[o] = v;
+        nv[cidx(m)] = v;
       }
+    }
+    if (P.dtx) dt3_extrema_cell(nv, P.gamma, ea, eb, ec, ebad);
+  }
+  if (P.dtx) {
+    // every lane of every wave reaches this point (the cell loop's bounds
+    // are uniform): wave extrema into the wave's slot
+    if (ebad) atomicOr(P.status, 1u);
+    constexpr int NW = NT / 64;
+    const int nslot = gridDim.x * NW, slot = blockIdx.x * NW + (tid >> 6);
+    ea = wave_extremum<true>(ea);
+    eb = wave_extremum<true>(eb);
+    ec = wave_extremum<true>(ec);
+    if (__lane_id() == 0) {
+      P.dtx[slot] = ea;
+      P.dtx[nslot + slot] = eb;
+      P.dtx[2 * nslot + slot] = ec;
     }
   }
 }

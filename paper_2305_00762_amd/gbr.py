@@ -109,6 +109,7 @@ SIGNATURES = {
     "gbr3_set_geometry": (_i, [_vp, _d, _d, _d, _d, _d, _d, _i, _i, _i]),
     "gbr3_set_order": (_i, [_vp, _i]),
     "gbr3_set_sweeps": (_i, [_vp, _i]),
+    "gbr3_stage_dt": (_i, [_vp, _d, _vp, _vp]),
     "gbr3_residual": (_i, [_vp, _vp, _vp, _vp]),
     "gbr3_rk_stage": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
     "gbr3_compute_dt": (_i, [_vp, _vp, _d, _vp, _vp]),
@@ -649,6 +650,11 @@ def gbr3_compute_dt(ctx, Q, cfl, dt, stream=None):
     w = "gbr3_compute_dt"
     return _check(load().gbr3_compute_dt(ctx, _state(ctx, Q, w, "Q", 5), cfl, _scalar(dt, w, "dt"),
                                          _stream(stream)), w)
+
+
+def gbr3_stage_dt(ctx, cfl, dt, stream=None):
+    w = "gbr3_stage_dt"
+    return _check(load().gbr3_stage_dt(ctx, cfl, _scalar(dt, w, "dt"), _stream(stream)), w)
 
 
 def gbr3_export_flags(ctx, enable):

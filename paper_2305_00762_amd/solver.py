@@ -153,11 +153,15 @@ class Solver3:
     through gbr3_compute_dt and gbr3_rk_stage."""
 
     def __init__(self, problem, device="cuda", stream=None, export_flags=False, order=7,
-                 sweeps=None):
+                 sweeps=None, fused_dt=False):
         import torch
         self.torch = torch
         self.p = problem
         self.stream = stream
+        # fused_dt: after the first step, the time step from the extrema the
+        # last stage-3 call reduced (gbr3_stage_dt), bit-identical
+        self.fused_dt = fused_dt
+        self._stage3_fresh = False
         self.ctx = gbr.gbr3_init(problem.nx, problem.ny, problem.nz, problem.gamma)
         gbr.gbr3_set_geometry(self.ctx, *problem.geometry(), *problem.bc)
         if order != 7:
@@ -195,13 +199,28 @@ class Solver3:
         gbr.gbr3_residual(self.ctx, Q, R, self.stream)
         return R
 
+    def set_state(self, Q):
+        """Copy a host or device state into Q; the next step takes its time
+        step from that state."""
+        self.Q.copy_(self.torch.as_tensor(np.ascontiguousarray(Q, np.float64)))
+        self._stage3_fresh = False
+
+    def compute_dt(self, cfl=None):
+        cfl = self.p.cfl if cfl is None else cfl
+        if self.fused_dt and self._stage3_fresh:
+            gbr.gbr3_stage_dt(self.ctx, cfl, self.dt, self.stream)
+            self._stage3_fresh = False
+        else:
+            gbr.gbr3_compute_dt(self.ctx, self.Q, cfl, self.dt, self.stream)
+        return self.dt
+
     def step(self, cfl=None):
-        gbr.gbr3_compute_dt(self.ctx, self.Q, self.p.cfl if cfl is None else cfl, self.dt,
-                            self.stream)
+        self.compute_dt(cfl)
         gbr.gbr3_rk_stage(self.ctx, 1, self.dt, self.Q, self.Q, self.Q1, self.stream)
         gbr.gbr3_rk_stage(self.ctx, 2, self.dt, self.Q, self.Q1, self.Q2, self.stream)
         gbr.gbr3_rk_stage(self.ctx, 3, self.dt, self.Q, self.Q2, self.Q1, self.stream)
         self.Q, self.Q1 = self.Q1, self.Q
+        self._stage3_fresh = True
 
     def flags(self):
         p = self.p

@@ -138,6 +138,57 @@ def test_trajectory_taylor_green():
     S.close()
 
 
+@pytest.mark.parametrize("sweeps", [gbr.GBR3_SWEEPS_LINES, gbr.GBR3_SWEEPS_XY_FUSED])
+@pytest.mark.parametrize("case", ["riemann_ragged", "taylor_green"])
+def test_stage_dt3_equals_two_pass(case, sweeps):
+    """The 3D time step from the extrema the stage-3 z sweep reduces
+    (gbr3_stage_dt) equals the two-pass reduction over the state it wrote and
+    the oracle's time step, bit for bit; a second read without a stage-3 call
+    in between is rejected."""
+    from paper_2305_00762_amd.solver import Solver3
+    torch = require_gpu()
+    if case == "riemann_ragged":
+        P = PB.riemann3d(40, seed=2, ny=33, nz=45)
+        P.bc = (PB.BC_TRANSMISSIVE, PB.BC_PERIODIC, PB.BC_TRANSMISSIVE)
+    else:
+        P = PB.taylor_green3d(32)
+    S = Solver3(P, sweeps=sweeps)
+    with pytest.raises(gbr.GbrError):
+        gbr.gbr3_stage_dt(S.ctx, P.cfl, S.dt)             # no stage-3 output yet
+    fused = torch.zeros(1, dtype=torch.float64, device="cuda")
+    cfg = ocfg3(P)
+    bits = lambda t: t.cpu().numpy().view(np.uint64)[0]
+    for k in range(3):
+        S.step()
+        gbr.gbr3_stage_dt(S.ctx, P.cfl, fused)
+        gbr.gbr3_compute_dt(S.ctx, S.Q, P.cfl, S.dt)
+        torch.cuda.synchronize()
+        o = np.float64(O.dt3(cfg, S.state(), P.cfl)).view(np.uint64)
+        report(f"3d stage dt {case} form{sweeps} step {k}", fused=float(fused.item()),
+               two_pass=float(S.dt.item()))
+        assert bits(fused) == bits(S.dt) == o
+    with pytest.raises(gbr.GbrError):
+        gbr.gbr3_stage_dt(S.ctx, P.cfl, fused)            # already read
+    assert S.check() == gbr.GBR_OK
+    S.close()
+
+
+def test_trajectory_fused_dt3_bit_identical():
+    """Steps taken with the fused time step equal, bit for bit, steps taken
+    with the two-pass reduction."""
+    from paper_2305_00762_amd.solver import Solver3
+    require_gpu()
+    P = PB.riemann3d(32, seed=5, ny=24, nz=20)
+    A, B = Solver3(P), Solver3(P, fused_dt=True)
+    for _ in range(5):
+        A.step()
+        B.step()
+    qa, qb = A.state(), B.state()
+    assert (qa.view(np.uint64) == qb.view(np.uint64)).all()
+    A.close()
+    B.close()
+
+
 @pytest.mark.parametrize("order", [7, 4])
 def test_forms_agree(order):
     """The fused forms against the line sweeps on the same state: interface
