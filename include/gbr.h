@@ -36,7 +36,7 @@ enum {
     GBR_ENOMEM = -2,       /* device allocation failed                       */
     GBR_EDEVICE = -3,      /* HIP runtime error                              */
     GBR_ESTATE = -4,       /* non-finite / non-positive rho or p seen        */
-    GBR_EUNSUPPORTED = -5  /* option not available in this build             */
+    GBR_EUNSUPPORTED = -5  /* option not available in the library            */
 };
 
 enum { GBR_BC_PERIODIC = 0, GBR_BC_TRANSMISSIVE = 1, GBR_BC_REFLECT = 2, GBR_BC_NOSLIP = 3,

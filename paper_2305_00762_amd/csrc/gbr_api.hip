@@ -246,7 +246,7 @@ const char* gbr_strerror(int s) {
     case GBR_ENOMEM: return "device allocation failed";
     case GBR_EDEVICE: return "HIP runtime error";
     case GBR_ESTATE: return "non-finite value or non-positive density/pressure on the device";
-    case GBR_EUNSUPPORTED: return "option not supported by this build";
+    case GBR_EUNSUPPORTED: return "option not supported by the library";
     default: return "unknown status";
   }
 }
