@@ -70,10 +70,12 @@ struct BatchCfg {
   static constexpr int U = F32 ? imax(F32Cfg<CI>::NU * CI::RS, F32Cfg<CV>::NU * CV::RS)
                                 : imax(CI::NF * CI::RS, CV::NF * CV::RS);
   static constexpr int PH = F32 ? imax(F32Cfg<CI>::PH, F32Cfg<CV>::PH) : imax(CI::PH, CV::PH);
-  static constexpr int CHI = imax(CI::CHI, CV::CHI);
+  static constexpr int CHI = F32 ? imax(F32Cfg<CI>::CHI, F32Cfg<CV>::CHI) : imax(CI::CHI, CV::CHI);
   static constexpr int QMAX = imax(CI::QMAX, CV::QMAX);
   using PhT = typename std::conditional<F32, float, double>::type;
-  static constexpr int LDS_BYTES = 8 * U + (int)sizeof(PhT) * PH + CHI + 2 * QMAX + 16;
+  // queue entries: bytes where every slot fits (FP32 form), else 16 bits
+  using QT = typename std::conditional<(F32 && QMAX <= 256), unsigned char, unsigned short>::type;
+  static constexpr int LDS_BYTES = 8 * U + (int)sizeof(PhT) * PH + CHI + (int)sizeof(QT) * QMAX + 16;
 };
 
 template <class CI, class CV, bool F32, int MW, bool LOOP>
@@ -83,7 +85,7 @@ __global__ __launch_bounds__(CI::NT, MW) void meg7_batch_kernel(BatchParams B) {
   __shared__ double sU[BC::U];
   __shared__ PhT sPh[BC::PH];
   __shared__ unsigned char sChi[BC::CHI];
-  __shared__ unsigned short sQueue[BC::QMAX];
+  __shared__ typename BC::QT sQueue[BC::QMAX];
   __shared__ int sQCount;
   const int G = gridDim.x, b = blockIdx.x;
   const int xcd = b & 7, per = G >> 3;   // G is a multiple of 8

@@ -20,6 +20,8 @@
 // Each interface flux is F = B + d with d in FP32; the divergence is formed in
 // FP64 as (f_{j+1} - f_{j-1})/2 + (d_{j+1/2} - d_{j-1/2}).
 #pragma once
+#include <type_traits>
+
 #include "stage_kernel.hpp"
 
 namespace gbr {
@@ -72,51 +74,76 @@ __device__ __forceinline__ void hllc_diss_f32(const float WL[4], const float WR[
 // Per-line buffers of a sweep, for the four reconstructed fields; the viscous
 // terms' derivatives are formed from the FP64 tile where an interface needs
 // them, as in the FP64 sweep.
+//
+// Bank layout.  Pass 2 gives one interface to a lane, WFL = N + 1 interfaces
+// per line, so a half-wave (the 32 lanes one LDS cycle serves on 32 banks)
+// covers G = 32 / WFL lines when WFL divides 32.  Row-major rows would then
+// put those lines' reads at offsets W apart, which collide on the banks for
+// every row width W that fits.  Instead the rows of each group of G lines are
+// interleaved element by element -- element p of line g0 + i at word
+// g0 W + G p + i -- so the half-wave reads G consecutive words per position:
+// 32 distinct banks.  The line count is padded to whole groups (NLP), which
+// keeps the stride G a constant.
 template <int N, int NL>
 struct PhaseF32 {
   // positions: gradients k in [-3, N+3); edge jumps dU at k+1/2, k in [-3, N+2);
   // flux jumps df at k+1/2, k in [-5, N+4)
   static constexpr int WD = N + 6, WU = N + 5, WG = N + 9, WFL = N + 1, WP = N + 10;
-  static constexpr int TOT = 4 * NL * WD + 4 * NL * WU + 4 * NL * (WG > WFL ? WG : WFL);
+  static constexpr int G = (32 % WFL == 0) ? 32 / WFL : 1;
+  static constexpr int NLP = (NL + G - 1) / G * G;
+  // interface values d (pass 2/3 writes, pass 4 reads across lines in y):
+  // width WFL + 2 under interleaving, else the odd width WFL | 1
+  static constexpr int WFS = G > 1 ? WFL + 2 : (WFL | 1);
+  static constexpr int TOT = 4 * NLP * WD + 4 * NLP * WU + 4 * NLP * (WG > WFL ? WG : WFL);
+  static constexpr int CHI = NLP * WD;   // plain-detector flags
+  __device__ static __forceinline__ int idx(int line, int p, int W) {
+    return line / G * G * W + G * p + line % G;
+  }
 };
 
 // The FP32 kernel's tile holds (rho, u, v, p) in FP64 also on viscous grids:
 // T = gamma p / rho is formed where the viscous flux needs it, which keeps
 // the viscous kernel at the inviscid one's LDS size (4 workgroups per CU).
+// Flagged-interface queue entries are interface slots, bytes where they fit.
 template <class C>
 struct F32Cfg {
   using PX = PhaseF32<C::TX, C::SX>;
   using PY = PhaseF32<C::TY, C::SY>;
   static constexpr int NU = 4;                          // tile fields
   static constexpr int PH = C::cmax(PX::TOT, PY::TOT);  // floats
-  static constexpr int LDS_BYTES = 8 * NU * C::RS + 4 * PH + C::CHI + 2 * C::QMAX + 16;
+  static constexpr int CHI = C::cmax(PX::CHI, PY::CHI);
+  static constexpr int QMAX = C::QMAX;
+  using QT = typename std::conditional<(QMAX <= 256), unsigned char, unsigned short>::type;
+  static constexpr int LDS_BYTES =
+      8 * NU * C::RS + 4 * PH + CHI + (int)sizeof(QT) * QMAX + 16;
 };
 
+template <class QT>
 struct LdsF32 {
   double* U;
   float* ph;
-  unsigned char* chi;
-  unsigned short* queue;
+  unsigned char* chi;         // plain-detector flags (unused with the flag map)
+  QT* queue;
   int* qcount;
-  const unsigned char* chif;
+  const unsigned char* chif;  // flag-map bits of the tile cells (learned detector)
 };
 
-template <class C, int DIR, bool DETMLP>
-__device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L, int l0, int tx0,
-                                          int ty0, double (&res)[C::CPT][4]) {
+template <class C, int DIR, bool DETMLP, class QT>
+__device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>& L, int l0,
+                                          int tx0, int ty0, double (&res)[C::CPT][4]) {
   constexpr bool X = (DIR == 0);
   constexpr int N = X ? C::TX : C::TY;
   constexpr int NL = X ? C::SX : C::SY;
   constexpr int NLINES = X ? C::TY : C::TX;
   using PH = PhaseF32<N, NL>;
   constexpr int WD = PH::WD, WU = PH::WU, WG = PH::WG, WFL = PH::WFL, WP = PH::WP;
+  constexpr int NLP = PH::NLP;
   constexpr int RS = C::RS, RX = C::RX, H = C::H, NT = C::NT;
   constexpr int SN = X ? 1 : RX, ST = X ? RX : 1;
   constexpr int FN = X ? 1 : 2, FT = X ? 2 : 1;
   constexpr int IPT = (NL * WFL + NT - 1) / NT;
-  constexpr int GSTR = (WG > WFL ? WG : WFL) * NL;
-  // interface values: odd row stride (pass 4 reads across lines in y)
-  constexpr int WFS = WFL | 1;
+  constexpr int GSTR = (WG > WFL ? WG : WFL) * NLP;
+  constexpr int WFS = PH::WFS;
   static_assert(WFS <= WG, "interface rows fit the buffer");
   const int tid = threadIdx.x;
   const int nl = (NLINES - l0) < NL ? (NLINES - l0) : NL;
@@ -124,10 +151,10 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
   const double inv_dt = X ? P.inv_dy : P.inv_dx;
   const float gammaf = (float)P.gamma, g1invf = (float)P.g1inv;
 
-  float* sD = L.ph;                  // [4][NL x WD]    gradients Phi' (rotated order)
-  float* sDU = sD + 4 * NL * WD;     // [4][NL x WU]    edge jumps of the primitives
-  float* sDF = sDU + 4 * NL * WU;    // [4][NL x WG]    edge jumps of the cell fluxes; then d
-  auto bidx = [](int line, int p, int W) { return line * W + p; };
+  float* sD = L.ph;                  // [4][NLP x WD]   gradients Phi' (rotated order)
+  float* sDU = sD + 4 * NLP * WD;    // [4][NLP x WU]   edge jumps of the primitives
+  float* sDF = sDU + 4 * NLP * WU;   // [4][NLP x WG]   edge jumps of the cell fluxes; then d
+  auto bidx = [](int line, int p, int W) { return PH::idx(line, p, W); };
   auto ridx = [&](int line, int pos) {
     const int lx = X ? pos : l0 + line;
     const int ly = X ? l0 + line : pos;
@@ -177,20 +204,17 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const double* u = U + rot[m] * RS + r;
-        sDU[m * NL * WU + bidx(line, k + 3, WU)] = (float)(u[SN] - u[0]);
+        sDU[m * NLP * WU + bidx(line, k + 3, WU)] = (float)(u[SN] - u[0]);
       }
     }
     if (k >= -3 && k < N + 3) {
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const double* u = U + rot[m] * RS + r;
-        sD[m * NL * WD + bidx(line, k + 3, WD)] =
+        sD[m * NLP * WD + bidx(line, k + 3, WD)] =
             (float)grad6(u[-3 * SN], u[-2 * SN], u[-SN], u[SN], u[2 * SN], u[3 * SN]);
       }
-      if (DETMLP) {
-        L.chi[bidx(line, k + 3, WD)] =
-            (L.chif[mlp_chi_index<C>(X ? k : l0 + line, X ? l0 + line : k)] >> DIR) & 1;
-      } else {
+      if (!DETMLP) {
         const double* rho = U + r;
         L.chi[bidx(line, k + 3, WD)] =
             detector_flag(rho[-2 * SN], rho[-SN], rho[0], rho[SN], rho[2 * SN]) ? 1 : 0;
@@ -215,9 +239,19 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
       if (line < nl) {
         // eq. (buffer): the six flags read at once and OR-ed (a short-circuit
         // chain would wait for each LDS read in turn)
+        // (flag-map bits are read from the tile's flag map directly)
         unsigned any = 0u;
+        if (DETMLP) {
 #pragma unroll
-        for (int q = 1; q <= 6; ++q) any |= L.chi[bidx(line, pos + q, WD)];
+          for (int q = 1; q <= 6; ++q) {
+            const int k = pos + q - 3;
+            any |= L.chif[mlp_chi_index<C>(X ? k : l0 + line, X ? l0 + line : k)];
+          }
+          any &= 1u << DIR;
+        } else {
+#pragma unroll
+          for (int q = 1; q <= 6; ++q) any |= L.chi[bidx(line, pos + q, WD)];
+        }
         const bool sigma = any == 0u;
         if (X) {
           const int gi = ty0 + l0 + line, gj = tx0 + pos;
@@ -235,9 +269,9 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
             // edge jumps e[q] at (pos-2+q)+1/2, q = 0..4; gradients g[q] at pos-1+q
             float e[5], g[4];
 #pragma unroll
-            for (int q = 0; q < 5; ++q) e[q] = sDU[m * NL * WU + bidx(line, pos + 1 + q, WU)];
+            for (int q = 0; q < 5; ++q) e[q] = sDU[m * NLP * WU + bidx(line, pos + 1 + q, WU)];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) g[q] = sD[m * NL * WD + bidx(line, pos + 2 + q, WD)];
+            for (int q = 0; q < 4; ++q) g[q] = sD[m * NLP * WD + bidx(line, pos + 2 + q, WD)];
             constexpr float s = 1.0f / 840.0f;
             const float cL = s * (420.0f * g[1] + 60.0f * (g[0] - g[2]) +
                                   181.0f * (e[2] - e[1]) + 3.0f * (e[3] - e[0]));
@@ -261,7 +295,7 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
             for (int m = 0; m < 4; ++m) {
               WL[m] = (float)U[rot[m] * RS + r];
               WR[m] = (float)U[rot[m] * RS + r + SN];
-              dW[m] = sDU[m * NL * WU + bidx(line, pos + 3, WU)];
+              dW[m] = sDU[m * NLP * WU + bidx(line, pos + 3, WU)];
               dF[m] = 0.f;
             }
           }
@@ -272,13 +306,13 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
           if (C::VISC) {
             const int b0 = bidx(line, pos + 3, WD), b1 = bidx(line, pos + 4, WD);
             const int be = bidx(line, pos + 3, WU);
-            const float gun0 = sD[1 * NL * WD + b0], gun1 = sD[1 * NL * WD + b1];
-            const float gut0 = sD[2 * NL * WD + b0], gut1 = sD[2 * NL * WD + b1];
+            const float gun0 = sD[1 * NLP * WD + b0], gun1 = sD[1 * NLP * WD + b1];
+            const float gut0 = sD[2 * NLP * WD + b0], gut1 = sD[2 * NLP * WD + b1];
             double T[8];
             temps(r, T);
             const float gT0 = (float)grad6(T[0], T[1], T[2], T[4], T[5], T[6]);
             const float gT1 = (float)grad6(T[1], T[2], T[3], T[5], T[6], T[7]);
-            const float jun = sDU[1 * NL * WU + be], jut = sDU[2 * NL * WU + be];
+            const float jun = sDU[1 * NLP * WU + be], jut = sDU[2 * NLP * WU + be];
             const float jT = (float)(T[4] - T[3]);
             const float a2 = 0.5f * (float)kAlphaV, idn = (float)inv_dn;
             const float dun = (0.5f * (gun0 + gun1) + a2 * (jun - 0.5f * (gun0 + gun1))) * idn;
@@ -310,7 +344,7 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
       base = __shfl(base, 0);
       if (flagged) {
         const int rank = (int)__popcll(ball & ((1ull << lane) - 1ull));
-        L.queue[base + rank] = (unsigned short)t;
+        L.queue[base + rank] = (QT)t;
       }
     }
   }
@@ -337,7 +371,7 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
     double WL[4], WR[4];
     meg7_char_states(
         [&](int q, int f) { return U[rot[f] * RS + r + (q - 2) * SN]; },
-        [&](int q, int f) { return (double)sD[f * NL * WD + bidx(line, pos + q + 1, WD)]; },
+        [&](int q, int f) { return (double)sD[f * NLP * WD + bidx(line, pos + q + 1, WD)]; },
         P.gamma, WL, WR);
     if (!(WL[0] > 0.0 && WL[3] > 0.0 && WR[0] > 0.0 && WR[3] > 0.0)) {
       wrot(r, WL);
@@ -354,8 +388,8 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
       double T[8];
       temps(r, T);
       viscous_add(U[FN * RS + r], U[FN * RS + r + SN], U[FT * RS + r], U[FT * RS + r + SN],
-                  T[3], T[4], sD[1 * NL * WD + b0], sD[1 * NL * WD + b1],
-                  sD[2 * NL * WD + b0], sD[2 * NL * WD + b1],
+                  T[3], T[4], sD[1 * NLP * WD + b0], sD[1 * NLP * WD + b1],
+                  sD[2 * NLP * WD + b0], sD[2 * NLP * WD + b1],
                   (float)grad6(T[0], T[1], T[2], T[4], T[5], T[6]),
                   (float)grad6(T[1], T[2], T[3], T[5], T[6], T[7]), (float)(g6(FN, r, ST) * inv_dt),
                   (float)(g6(FN, r + SN, ST) * inv_dt), (float)(g6(FT, r, ST) * inv_dt),
@@ -373,9 +407,8 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
   // ---- pass 4: divergence in FP64: (f_{j+1} - f_{j-1})/2 + d_{j+1/2} - d_{j-1/2}
 #pragma unroll
   for (int k = 0; k < C::CPT; ++k) {
-    const int c = tid + k * NT;
-    if (c < C::TX * C::TY) {
-      const int lx = c % C::TX, ly = c / C::TX;
+    int lx, ly;
+    if (tile_cell<C>(tid, k, lx, ly)) {
       const int line = (X ? ly : lx) - l0;
       const int pos = X ? lx : ly;
       if (line >= 0 && line < nl) {
@@ -400,17 +433,17 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32& L,
 }
 
 // One tile of the FP32-bulk stage (LDS arrays passed in, as stage_tile).
-template <class C, bool DETMLP>
+template <class C, bool DETMLP, class QT>
 __device__ __forceinline__ void stage_tile_f32(const StageParams& P, int tx0, int ty0, double* sU,
-                                               float* sPh, unsigned char* sChi,
-                                               unsigned short* sQueue, int* sQCount,
-                                               unsigned char* sChiF) {
+                                               float* sPh, unsigned char* sChi, QT* sQueue,
+                                               int* sQCount, unsigned char* sChiF) {
+  static_assert(C::QMAX <= (1 << (8 * sizeof(QT))), "queue entries hold every interface slot");
   ChiMap<C> cm;
   if (DETMLP) fetch_chimap<C>(P, cm, tx0, ty0);
   stage_load<C, false, false>(P, sU, tx0, ty0);
   if (DETMLP) put_chimap<C>(cm, sChiF);
   __syncthreads();
-  const LdsF32 L{sU, sPh, sChi, sQueue, sQCount, sChiF};
+  const LdsF32<QT> L{sU, sPh, sChi, sQueue, sQCount, sChiF};
   double res[C::CPT][4];
 #pragma unroll
   for (int k = 0; k < C::CPT; ++k)
@@ -426,8 +459,8 @@ __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel_f32(StagePar
   using F = F32Cfg<C>;
   __shared__ double sU[F::NU * C::RS];
   __shared__ float sPh[F::PH];
-  __shared__ unsigned char sChi[C::CHI];
-  __shared__ unsigned short sQueue[C::QMAX];
+  __shared__ unsigned char sChi[DETMLP ? 1 : F::CHI];
+  __shared__ typename F::QT sQueue[F::QMAX];
   __shared__ unsigned char sChiF[DETMLP ? (C::TX + 6) * (C::TY + 6) : 1];
   __shared__ int sQCount;
   int tx0, ty0;

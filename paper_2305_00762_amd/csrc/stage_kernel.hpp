@@ -103,6 +103,28 @@ struct TileCfg {
   static constexpr int LDS_BYTES = 8 * (NF * RS + PH) + CHI + 2 * QMAX + 16;
 };
 
+// Cell slot k of thread tid: tile cell (lx, ly); false for an idle slot.
+// Row-major in general.  For 15 x 15 tiles on 256 threads each half-wave
+// (32 lanes) takes two rows three apart, 16 lanes per row (the last idle):
+// the LDS tile's row stride is 27 doubles and 3 x 27 = 17 mod 32, so the two
+// rows' doubles fall on disjoint halves of the 32 eight-byte slots a
+// half-wave reads at once (rows 12 and 14, two apart, share a half-wave).
+template <class C>
+__device__ __forceinline__ bool tile_cell(int tid, int k, int& lx, int& ly) {
+  if constexpr (C::TX == 15 && C::TY == 15 && C::NT == 256) {
+    const int h = tid >> 5, i = tid & 31;
+    const int a = h / 3 * 6 + h % 3;   // rows a, a + 3 (h = 6: 12, 14; h = 7: 13)
+    lx = i & 15;
+    ly = i < 16 ? a : (h == 6 ? 14 : a + 3);
+    return lx < 15 && ly < 15;
+  } else {
+    const int c = tid + k * C::NT;
+    lx = c % C::TX;
+    ly = c / C::TX;
+    return c < C::TX * C::TY;
+  }
+}
+
 // Shared-memory views handed to the sweep.
 struct Lds {
   double* U;
@@ -453,9 +475,8 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
   // ---- pass 4: flux differences, eq. (deriv) -------------------------------
 #pragma unroll
   for (int k = 0; k < C::CPT; ++k) {
-    const int c = tid + k * NT;
-    if (c < C::TX * C::TY) {
-      const int lx = c % C::TX, ly = c / C::TX;
+    int lx, ly;
+    if (tile_cell<C>(tid, k, lx, ly)) {
       const int line = (X ? ly : lx) - l0;
       const int pos = X ? lx : ly;
       if (line >= 0 && line < nl) {
@@ -739,7 +760,7 @@ __device__ __forceinline__ void dt_extrema_commit(double* w, int nslot, int slot
 template <class C>
 __device__ __forceinline__ void stage_store(const StageParams& P, const double (&res)[C::CPT][4],
                                             int tx0, int ty0) {
-  constexpr int TX = C::TX, TY = C::TY, NT = C::NT;
+  constexpr int NT = C::NT;
   const int tid = threadIdx.x;
   const size_t n = (size_t)P.nx * P.ny;
   const double dt = (P.mode == MODE_RESIDUAL) ? 0.0 : *P.dt;
@@ -748,9 +769,10 @@ __device__ __forceinline__ void stage_store(const StageParams& P, const double (
   size_t so[C::CPT];
 #pragma unroll
   for (int k = 0; k < C::CPT; ++k) {
-    const int c = tid + k * NT;
-    const int gj = tx0 + c % TX, gi = ty0 + c / TX;
-    own[k] = c < TX * TY && gj < P.nx && gi < P.ny;
+    int lx, ly;
+    const bool in = tile_cell<C>(tid, k, lx, ly);
+    const int gj = tx0 + lx, gi = ty0 + ly;
+    own[k] = in && gj < P.nx && gi < P.ny;
     so[k] = (size_t)gi * P.nx + gj;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
