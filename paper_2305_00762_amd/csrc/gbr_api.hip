@@ -58,6 +58,10 @@ using E31 = TileCfg<31, 15, 15, 16, 256, false>;
 using V31 = TileCfg<31, 15, 8, 16, 256, true>;
 using E15 = TileCfg<15, 15, 15, 15, 256, false>;
 using V15 = TileCfg<15, 15, 15, 15, 256, true>;
+// FP32 bulk on 15x15 tiles: 4 workgroups per CU fit the LDS, so the register
+// budget is held to 4 waves per SIMD (128 VGPRs)
+using F15 = TileCfg<15, 15, 15, 15, 256, false, 4>;
+using FV15 = TileCfg<15, 15, 15, 15, 256, true, 4>;
 const TileVariant kVariants[] = {
     // 32 x-interfaces per row, 16 y-interfaces per column; 2 workgroups/CU
     {31, 15,
@@ -75,8 +79,8 @@ const TileVariant kVariants[] = {
     // 16 interfaces per line both ways; 3-4 workgroups/CU
     {15, 15,
      {{{launch_cfg<E15>, launch_cfg<E15, true>}, {launch_cfg<V15>, launch_cfg<V15, true>}},
-      {{launch_cfg_f32<E15>, launch_cfg_f32<E15, true>},
-       {launch_cfg_f32<V15>, launch_cfg_f32<V15, true>}}},
+      {{launch_cfg_f32<F15>, launch_cfg_f32<F15, true>},
+       {launch_cfg_f32<FV15>, launch_cfg_f32<FV15, true>}}},
      "15x15",
      {launch_cfg<E15, false, true>, launch_cfg<V15, false, true>},
      {{launch_cfg<E15, false, false, 4>, launch_cfg<V15, false, false, 4>},

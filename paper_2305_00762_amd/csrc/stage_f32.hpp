@@ -7,11 +7,12 @@
 // quantities only, so its rounding scales with the local variation of the
 // solution rather than with its magnitude:
 //   * per cell edge: jumps dU = U_{k+1} - U_k and df = f_{k+1} - f_k, formed
-//     in FP64 (df on the primitive jumps) and rounded to FP32; per cell:
-//     gradients Phi' (FP32);
+//     in FP64 (df on the primitive jumps) and rounded to FP32;
 //   * GRB states as corrections: U^L = U_j + cL, U^R = U_{j+1} + cR, with cL, cR
-//     written on gradients and edge jumps (eq. eqn:grb minus U_j, using that
-//     its value weights sum to 840), and U^R - U^L = dU_{j+1/2} + cR - cL;
+//     written on edge jumps alone: eq. (eqn:grb) minus U_j (its value weights
+//     sum to 840) with the gradients of eq. (eqn:six) expanded into the same
+//     edge jumps, an 8-tap stencil on dU_{j-7/2} .. dU_{j+7/2} (resp. one edge
+//     further right); U^R - U^L = dU_{j+1/2} + cR - cL;
 //   * the mean reconstructed flux minus the central flux
 //     B = (f_j + f_{j+1})/2 as a stencil on edge jumps (eqs. flux-full,
 //     flux-right minus B: the weights sum to zero);
@@ -71,9 +72,11 @@ __device__ __forceinline__ void hllc_diss_f32(const float WL[4], const float WR[
   for (int m = 0; m < 4; ++m) diss[m] = aSL * dQL[m] + aSS * (dQ[m] - dQR[m] - dQL[m]) + aSR * dQR[m];
 }
 
-// Per-line buffers of a sweep, for the four reconstructed fields; the viscous
-// terms' derivatives are formed from the FP64 tile where an interface needs
-// them, as in the FP64 sweep.
+// Per-line buffers of a sweep, for the four reconstructed fields: edge jumps
+// of the primitives and of the cell fluxes.  No gradient buffer: the smooth
+// branch reads gradients only through its edge-jump stencils (the viscous
+// normal derivatives likewise), and the flagged branch forms them in FP64 from
+// the tile.
 //
 // Bank layout.  Pass 2 gives one interface to a lane, WFL = N + 1 interfaces
 // per line, so a half-wave (the 32 lanes one LDS cycle serves on 32 banks)
@@ -86,15 +89,15 @@ __device__ __forceinline__ void hllc_diss_f32(const float WL[4], const float WR[
 // keeps the stride G a constant.
 template <int N, int NL>
 struct PhaseF32 {
-  // positions: gradients k in [-3, N+3); edge jumps dU at k+1/2, k in [-3, N+2);
-  // flux jumps df at k+1/2, k in [-5, N+4)
-  static constexpr int WD = N + 6, WU = N + 5, WG = N + 9, WFL = N + 1, WP = N + 10;
+  // edge jumps dU and df at k+1/2, k in [-5, N+4) (pass 1, one edge per item);
+  // plain-detector flags at k in [-3, N+3)
+  static constexpr int WU = N + 9, WG = N + 9, WFL = N + 1, WP = N + 9, WD = N + 6;
   static constexpr int G = (32 % WFL == 0) ? 32 / WFL : 1;
   static constexpr int NLP = (NL + G - 1) / G * G;
   // interface values d (pass 2/3 writes, pass 4 reads across lines in y):
   // width WFL + 2 under interleaving, else the odd width WFL | 1
   static constexpr int WFS = G > 1 ? WFL + 2 : (WFL | 1);
-  static constexpr int TOT = 4 * NLP * WD + 4 * NLP * WU + 4 * NLP * (WG > WFL ? WG : WFL);
+  static constexpr int TOT = 4 * NLP * WU + 4 * NLP * (WG > WFL ? WG : WFL);
   static constexpr int CHI = NLP * WD;   // plain-detector flags
   __device__ static __forceinline__ int idx(int line, int p, int W) {
     return line / G * G * W + G * p + line % G;
@@ -151,8 +154,7 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>
   const double inv_dt = X ? P.inv_dy : P.inv_dx;
   const float gammaf = (float)P.gamma, g1invf = (float)P.g1inv;
 
-  float* sD = L.ph;                  // [4][NLP x WD]   gradients Phi' (rotated order)
-  float* sDU = sD + 4 * NLP * WD;    // [4][NLP x WU]   edge jumps of the primitives
+  float* sDU = L.ph;                 // [4][NLP x WU]   edge jumps of the primitives (rotated order)
   float* sDF = sDU + 4 * NLP * WU;   // [4][NLP x WG]   edge jumps of the cell fluxes; then d
   auto bidx = [](int line, int p, int W) { return PH::idx(line, p, W); };
   auto ridx = [&](int line, int pos) {
@@ -181,7 +183,8 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>
     }
   };
 
-  // ---- pass 1: per cell and per edge, from the FP64 tile ----------------------
+  // ---- pass 1: per edge, from the FP64 tile ----------------------------------
+  // item p: edge k+1/2, k = p - 5 in [-5, N+4); plain flags at k in [-3, N+3)
   constexpr int P1R = (NL * WP + NT - 1) / NT;
 #pragma unroll
   for (int k1 = 0; k1 < P1R; ++k1) {
@@ -192,33 +195,19 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>
     if (line >= nl) continue;
     const int k = p - 5;
     const int r = ridx(line, k);
-    if (k < N + 4) {
-      double W0[4], W1[4], df[4];
-      wrot(r, W0);
-      wrot(r + SN, W1);
-      conv_flux_jump(W0, W1, P.g1inv, df);
+    double W0[4], W1[4], df[4];
+    wrot(r, W0);
+    wrot(r + SN, W1);
+    conv_flux_jump(W0, W1, P.g1inv, df);
 #pragma unroll
-      for (int m = 0; m < 4; ++m) sDF[m * GSTR + bidx(line, p, WG)] = (float)df[m];
+    for (int m = 0; m < 4; ++m) {
+      sDF[m * GSTR + bidx(line, p, WG)] = (float)df[m];
+      sDU[m * NLP * WU + bidx(line, p, WU)] = (float)(W1[m] - W0[m]);
     }
-    if (k >= -3 && k < N + 2) {
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const double* u = U + rot[m] * RS + r;
-        sDU[m * NLP * WU + bidx(line, k + 3, WU)] = (float)(u[SN] - u[0]);
-      }
-    }
-    if (k >= -3 && k < N + 3) {
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const double* u = U + rot[m] * RS + r;
-        sD[m * NLP * WD + bidx(line, k + 3, WD)] =
-            (float)grad6(u[-3 * SN], u[-2 * SN], u[-SN], u[SN], u[2 * SN], u[3 * SN]);
-      }
-      if (!DETMLP) {
-        const double* rho = U + r;
-        L.chi[bidx(line, k + 3, WD)] =
-            detector_flag(rho[-2 * SN], rho[-SN], rho[0], rho[SN], rho[2 * SN]) ? 1 : 0;
-      }
+    if (!DETMLP && k >= -3 && k < N + 3) {
+      const double* rho = U + r;
+      L.chi[bidx(line, k + 3, WD)] =
+          detector_flag(rho[-2 * SN], rho[-SN], rho[0], rho[SN], rho[2 * SN]) ? 1 : 0;
     }
   }
   if (tid == 0) *L.qcount = 0;
@@ -264,23 +253,31 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>
         if (sigma) {
           const int r = ridx(line, pos);
           float WL[4], WR[4], dW[4], dF[4];
+          float gv[2][2], jv[2];   // viscous: normal derivatives of u_n, u_t at pos, pos+1; jumps
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
-            // edge jumps e[q] at (pos-2+q)+1/2, q = 0..4; gradients g[q] at pos-1+q
-            float e[5], g[4];
+            // edge jumps E[a] = dU at (pos+a-4)+1/2, a = 0..8
+            float E[9];
 #pragma unroll
-            for (int q = 0; q < 5; ++q) e[q] = sDU[m * NLP * WU + bidx(line, pos + 1 + q, WU)];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) g[q] = sD[m * NLP * WD + bidx(line, pos + 2 + q, WD)];
+            for (int a = 0; a < 9; ++a) E[a] = sDU[m * NLP * WU + bidx(line, pos + 1 + a, WU)];
+            // eq. (eqn:grb) with eq. (eqn:six) substituted, minus U_j (resp. U_{j+1});
+            // integer weights over 840
             constexpr float s = 1.0f / 840.0f;
-            const float cL = s * (420.0f * g[1] + 60.0f * (g[0] - g[2]) +
-                                  181.0f * (e[2] - e[1]) + 3.0f * (e[3] - e[0]));
-            const float cR = s * (-420.0f * g[2] + 60.0f * (g[1] - g[3]) +
-                                  181.0f * (e[3] - e[2]) + 3.0f * (e[4] - e[1]));
+            const float cL = s * ((E[0] - E[1] - E[7]) - 23.0f * E[2] + 123.0f * E[3] +
+                                  395.0f * E[4] - 89.0f * E[5] + 15.0f * E[6]);
+            const float cR = s * ((E[1] - E[8] + E[7]) - 15.0f * E[2] + 89.0f * E[3] -
+                                  395.0f * E[4] - 123.0f * E[5] + 23.0f * E[6]);
             const double* u = U + rot[m] * RS + r;
             WL[m] = (float)u[0] + cL;
             WR[m] = (float)u[SN] + cR;
-            dW[m] = e[2] + (cR - cL);
+            dW[m] = E[4] + (cR - cL);
+            if (C::VISC && (m == 1 || m == 2)) {
+              // eq. (eqn:six) at pos and pos+1 on the edge jumps (weights over 60)
+              constexpr float z = 1.0f / 60.0f;
+              gv[m - 1][0] = z * (37.0f * (E[3] + E[4]) - 8.0f * (E[2] + E[5]) + (E[1] + E[6]));
+              gv[m - 1][1] = z * (37.0f * (E[4] + E[5]) - 8.0f * (E[3] + E[6]) + (E[2] + E[7]));
+              jv[m - 1] = E[4];
+            }
             // mean reconstructed flux minus (f_j + f_{j+1})/2 on flux edge jumps
             // h[q] at (pos-4+q)+1/2, q = 0..8
             float h[9];
@@ -295,7 +292,7 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>
             for (int m = 0; m < 4; ++m) {
               WL[m] = (float)U[rot[m] * RS + r];
               WR[m] = (float)U[rot[m] * RS + r + SN];
-              dW[m] = sDU[m * NLP * WU + bidx(line, pos + 3, WU)];
+              dW[m] = sDU[m * NLP * WU + bidx(line, pos + 5, WU)];
               dF[m] = 0.f;
             }
           }
@@ -304,15 +301,13 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>
 #pragma unroll
           for (int m = 0; m < 4; ++m) dsm[kk][m] = dF[m] - 0.5f * diss[m];
           if (C::VISC) {
-            const int b0 = bidx(line, pos + 3, WD), b1 = bidx(line, pos + 4, WD);
-            const int be = bidx(line, pos + 3, WU);
-            const float gun0 = sD[1 * NLP * WD + b0], gun1 = sD[1 * NLP * WD + b1];
-            const float gut0 = sD[2 * NLP * WD + b0], gut1 = sD[2 * NLP * WD + b1];
+            const float gun0 = gv[0][0], gun1 = gv[0][1];
+            const float gut0 = gv[1][0], gut1 = gv[1][1];
             double T[8];
             temps(r, T);
             const float gT0 = (float)grad6(T[0], T[1], T[2], T[4], T[5], T[6]);
             const float gT1 = (float)grad6(T[1], T[2], T[3], T[5], T[6], T[7]);
-            const float jun = sDU[1 * NLP * WU + be], jut = sDU[2 * NLP * WU + be];
+            const float jun = jv[0], jut = jv[1];
             const float jT = (float)(T[4] - T[3]);
             const float a2 = 0.5f * (float)kAlphaV, idn = (float)inv_dn;
             const float dun = (0.5f * (gun0 + gun1) + a2 * (jun - 0.5f * (gun0 + gun1))) * idn;
@@ -368,10 +363,27 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>
     const int p = t % WFL;
     const int pos = p - 1;
     const int r = ridx(line, pos);
+    // normal gradients (eq. eqn:six) on the edge jumps, as in the smooth
+    // branch: edge(f, a) = dU of rotated field f at (pos+a-5)+1/2, a = 0..10;
+    // the edge below the stored range (a = 0, pos = -1) and the one above it
+    // (a = 10, pos = N-1) from the tile
+    auto edge = [&](int f, int a) -> float {
+      if ((a == 0 && pos < 0) || (a == 10 && pos >= N - 1)) {
+        const double* u = U + rot[f] * RS + r;
+        return (float)(u[(a - 4) * SN] - u[(a - 5) * SN]);
+      }
+      return sDU[f * NLP * WU + bidx(line, pos + a, WU)];
+    };
+    // at pos + q - 2, q = 0..5
+    auto grad = [&](int q, int f) -> float {
+      constexpr float z = 1.0f / 60.0f;
+      return z * (37.0f * (edge(f, q + 2) + edge(f, q + 3)) -
+                  8.0f * (edge(f, q + 1) + edge(f, q + 4)) + (edge(f, q) + edge(f, q + 5)));
+    };
     double WL[4], WR[4];
     meg7_char_states(
         [&](int q, int f) { return U[rot[f] * RS + r + (q - 2) * SN]; },
-        [&](int q, int f) { return (double)sD[f * NLP * WD + bidx(line, pos + q + 1, WD)]; },
+        [&](int q, int f) { return (double)grad(q, f); },
         P.gamma, WL, WR);
     if (!(WL[0] > 0.0 && WL[3] > 0.0 && WR[0] > 0.0 && WR[3] > 0.0)) {
       wrot(r, WL);
@@ -384,12 +396,10 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>
     for (int m = 0; m < 4; ++m) Fm[m] = 0.5 * (FL[m] + FR[m]);
     hllc(WL, WR, Fm, P.gamma, P.g1inv, F);
     if (C::VISC) {
-      const int b0 = bidx(line, pos + 3, WD), b1 = bidx(line, pos + 4, WD);
       double T[8];
       temps(r, T);
       viscous_add(U[FN * RS + r], U[FN * RS + r + SN], U[FT * RS + r], U[FT * RS + r + SN],
-                  T[3], T[4], sD[1 * NLP * WD + b0], sD[1 * NLP * WD + b1],
-                  sD[2 * NLP * WD + b0], sD[2 * NLP * WD + b1],
+                  T[3], T[4], grad(2, 1), grad(3, 1), grad(2, 2), grad(3, 2),
                   (float)grad6(T[0], T[1], T[2], T[4], T[5], T[6]),
                   (float)grad6(T[1], T[2], T[3], T[5], T[6], T[7]), (float)(g6(FN, r, ST) * inv_dt),
                   (float)(g6(FN, r + SN, ST) * inv_dt), (float)(g6(FT, r, ST) * inv_dt),
