@@ -89,9 +89,10 @@ __device__ __forceinline__ void hllc_diss_f32(const float WL[4], const float WR[
 // keeps the stride G a constant.
 template <int N, int NL>
 struct PhaseF32 {
-  // edge jumps dU and df at k+1/2, k in [-5, N+4) (pass 1, one edge per item);
-  // plain-detector flags at k in [-3, N+3)
-  static constexpr int WU = N + 9, WG = N + 9, WFL = N + 1, WP = N + 9, WD = N + 6;
+  // edge jumps df at k+1/2, k in [-5, N+4), and dU, k in [-6, N+5) (pass 1,
+  // one edge per item; the two outermost dU where a line end is flagged, for
+  // the flagged branch's gradients); plain-detector flags at k in [-3, N+3)
+  static constexpr int WU = N + 11, WG = N + 9, WFL = N + 1, WP = N + 9, WD = N + 6;
   static constexpr int G = (32 % WFL == 0) ? 32 / WFL : 1;
   static constexpr int NLP = (NL + G - 1) / G * G;
   // interface values d (pass 2/3 writes, pass 4 reads across lines in y):
@@ -202,7 +203,7 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       sDF[m * GSTR + bidx(line, p, WG)] = (float)df[m];
-      sDU[m * NLP * WU + bidx(line, p, WU)] = (float)(W1[m] - W0[m]);
+      sDU[m * NLP * WU + bidx(line, p + 1, WU)] = (float)(W1[m] - W0[m]);
     }
     if (!DETMLP && k >= -3 && k < N + 3) {
       const double* rho = U + r;
@@ -250,6 +251,17 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>
           if (P.sigy && gj < P.nx && gi < P.ny) P.sigy[(size_t)(gi + 1) * P.nx + gj] = sigma;
         }
         flagged = !sigma;
+        if (flagged && (pos == -1 || pos == N - 1)) {
+          // the edge past pass 1's range that the flagged branch's gradients
+          // reach at a line end: (-6)+1/2 or (N+4)+1/2
+          const int r = ridx(line, pos);
+          const int o = pos < 0 ? -5 : 5, ix = pos < 0 ? 0 : WU - 1;
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const double* u = U + rot[m] * RS + r + o * SN;
+            sDU[m * NLP * WU + bidx(line, ix, WU)] = (float)(u[SN] - u[0]);
+          }
+        }
         if (sigma) {
           const int r = ridx(line, pos);
           float WL[4], WR[4], dW[4], dF[4];
@@ -259,7 +271,7 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>
             // edge jumps E[a] = dU at (pos+a-4)+1/2, a = 0..8
             float E[9];
 #pragma unroll
-            for (int a = 0; a < 9; ++a) E[a] = sDU[m * NLP * WU + bidx(line, pos + 1 + a, WU)];
+            for (int a = 0; a < 9; ++a) E[a] = sDU[m * NLP * WU + bidx(line, pos + 2 + a, WU)];
             // eq. (eqn:grb) with eq. (eqn:six) substituted, minus U_j (resp. U_{j+1});
             // integer weights over 840
             constexpr float s = 1.0f / 840.0f;
@@ -292,7 +304,7 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>
             for (int m = 0; m < 4; ++m) {
               WL[m] = (float)U[rot[m] * RS + r];
               WR[m] = (float)U[rot[m] * RS + r + SN];
-              dW[m] = sDU[m * NLP * WU + bidx(line, pos + 5, WU)];
+              dW[m] = sDU[m * NLP * WU + bidx(line, pos + 6, WU)];
               dF[m] = 0.f;
             }
           }
@@ -364,15 +376,9 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>
     const int pos = p - 1;
     const int r = ridx(line, pos);
     // normal gradients (eq. eqn:six) on the edge jumps, as in the smooth
-    // branch: edge(f, a) = dU of rotated field f at (pos+a-5)+1/2, a = 0..10;
-    // the edge below the stored range (a = 0, pos = -1) and the one above it
-    // (a = 10, pos = N-1) from the tile
+    // branch: edge(f, a) = dU of rotated field f at (pos+a-5)+1/2, a = 0..10
     auto edge = [&](int f, int a) -> float {
-      if ((a == 0 && pos < 0) || (a == 10 && pos >= N - 1)) {
-        const double* u = U + rot[f] * RS + r;
-        return (float)(u[(a - 4) * SN] - u[(a - 5) * SN]);
-      }
-      return sDU[f * NLP * WU + bidx(line, pos + a, WU)];
+      return sDU[f * NLP * WU + bidx(line, pos + 1 + a, WU)];
     };
     // at pos + q - 2, q = 0..5
     auto grad = [&](int q, int f) -> float {
