@@ -150,7 +150,7 @@ const BatchVariant kBatchVariants[] = {
     GBR_BATCH_VARIANT(31, 15, E31, V31, 2, 2, true, "31x15 persistent"),
     GBR_BATCH_VARIANT(15, 15, E15, V15, 3, 2, true, "15x15 persistent"),
     GBR_BATCH_VARIANT(31, 15, E31, V31, 2, 2, false, "31x15 one tile per workgroup"),
-    GBR_BATCH_VARIANT(15, 15, E15, V15, 2, 2, false, "15x15 one tile per workgroup"),
+    GBR_BATCH_VARIANT(15, 15, E15, V15, 2, 4, false, "15x15 one tile per workgroup"),
 };
 #undef GBR_BATCH_VARIANT
 constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);

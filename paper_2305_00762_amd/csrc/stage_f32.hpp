@@ -187,13 +187,10 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>
   // ---- pass 1: per edge, from the FP64 tile ----------------------------------
   // item p: edge k+1/2, k = p - 5 in [-5, N+4); plain flags at k in [-3, N+3)
   constexpr int P1R = (NL * WP + NT - 1) / NT;
-#pragma unroll
-  for (int k1 = 0; k1 < P1R; ++k1) {
-    const int t = tid + k1 * NT;
-    if (t >= NL * WP) break;
+  auto pass1 = [&](int t) {
     const int line = t / WP;
     const int p = t % WP;
-    if (line >= nl) continue;
+    if (line >= nl) return;
     const int k = p - 5;
     const int r = ridx(line, k);
     double W0[4], W1[4], df[4];
@@ -210,6 +207,17 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>
       L.chi[bidx(line, k + 3, WD)] =
           detector_flag(rho[-2 * SN], rho[-SN], rho[0], rho[SN], rho[2 * SN]) ? 1 : 0;
     }
+  };
+  if constexpr (DETMLP) {
+#pragma unroll
+    for (int k1 = 0; k1 < P1R; ++k1)
+      if (tid + k1 * NT < NL * WP) pass1(tid + k1 * NT);
+  } else {
+    // rounds kept apart: the FP64 density detector's registers would
+    // otherwise overlap the next round's loads past the 128-VGPR budget
+#pragma unroll 1
+    for (int k1 = 0; k1 < P1R; ++k1)
+      if (tid + k1 * NT < NL * WP) pass1(tid + k1 * NT);
   }
   if (tid == 0) *L.qcount = 0;
   __syncthreads();
