@@ -41,6 +41,22 @@ def test_residual_variants(tiling):
     check(f"f32 shear96 viscous t{tiling}", P, tiling)
 
 
+@pytest.mark.parametrize("tiling", [0, 1, 2, 3])
+def test_noise_all_flagged(tiling):
+    # every interface flagged: the characteristic branch runs at every line
+    # end of every tile, where its gradients reach one edge past the first
+    # pass's range (the edge the flagged interface stores itself)
+    rng = np.random.default_rng(12)
+    for n, ny, mu in ((48, 48, 0.0), (50, 37, 1e-3)):
+        rho = rng.uniform(0.5, 1.5, (ny, n))
+        u, v = rng.uniform(-0.5, 0.5, (2, ny, n))
+        p = rng.uniform(0.5, 1.5, (ny, n))
+        P = PB.free_stream(n, ny=ny)
+        P.Q = PB.prim_to_state(rho, u, v, p)
+        P.mu = mu
+        check(f"f32 noise{n}x{ny} mu={mu} t{tiling}", P, tiling)
+
+
 def test_residual_full_sizes():
     check("f32 riemann1024", PB.riemann(1024, seed=0))
     check("f32 shear2048", PB.shear(2048, seed=0))

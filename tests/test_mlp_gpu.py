@@ -212,7 +212,13 @@ def check_flag_map(P, chi, zo, margin, sx, sy):
 @pytest.mark.parametrize("tiling", [0, 1])
 def test_fused_detector_all_fallback(precision, tiling):
     m, w, b = make_net(4)
-    for P in (PB.riemann(90, seed=6, ny=70), PB.shear(64, seed=1, ny=48)):
+    # a noise field flags every interface: the flagged branch then runs at the
+    # ends of every line of every tile
+    rng = np.random.default_rng(13)
+    noise = PB.free_stream(50, ny=37)
+    noise.Q = PB.prim_to_state(rng.uniform(0.5, 1.5, (37, 50)), *rng.uniform(-0.5, 0.5, (2, 37, 50)),
+                               rng.uniform(0.5, 1.5, (37, 50)))
+    for P in (PB.riemann(90, seed=6, ny=70), PB.shear(64, seed=1, ny=48), noise):
         from paper_2305_00762_amd.solver import Solver
         R, sx, sy, ev, fb = fused(P, m, 1e30, precision)
         Ro, ex, ey, _ = O.residual(ocfg(P), P.Q, want_flags=True)
