@@ -60,23 +60,30 @@ __device__ __forceinline__ void hllc_diss_f32(const float WL[4], const float WR[
   const float aR = (dp - du * ml) * iden;   // S* - u_R
   const float Ss = ul + aL;
   const float iL = rcpf(SL - Ss), iR = rcpf(SR - Ss);
-  const float gl = rl * aL * iL, gr = rr * aR * iR;
-  // Q*_L - Q_L and Q_R - Q*_R
-  const float dQL[4] = {gl, gl * SL, gl * vl, aL * iL * (El + pl + ml * Ss)};
-  const float dQR[4] = {-gr, -gr * SR, -gr * vr, -aR * iR * (Er + pr + mr * Ss)};
   // Q_R - Q_L from the primitive jumps
   const float dQ[4] = {dr, rr * du + ul * dr, rr * dv + vl * dr,
                        dp * g1inv + 0.5f * (dr * kl2 + rr * (du * (ur + ul) + dv * (vr + vl)))};
   const float aSL = fabsf(SL), aSS = fabsf(Ss), aSR = fabsf(SR);
-#pragma unroll
-  for (int m = 0; m < 4; ++m) diss[m] = aSL * dQL[m] + aSS * (dQ[m] - dQR[m] - dQL[m]) + aSR * dQR[m];
+  // |S_L| dQL + |S*| (dQ - dQR - dQL) + |S_R| dQR gathered per jump as
+  // (|S_L| - |S*|) dQL + (|S_R| - |S*|) dQR + |S*| dQ, with
+  //   dQL = Q*_L - Q_L = g_L (1, S_L, v_L, .),  g_L = rho_L a_L / (S_L - S*),
+  //   dQR = Q_R - Q*_R = -g_R (1, S_R, v_R, .), g_R = rho_R a_R / (S_R - S*),
+  // and the energy rows a_L/(S_L - S*) (E_L + p_L + m_L S*), resp. R
+  const float aiL = aL * iL, aiR = aR * iR;
+  const float wL = aSL - aSS, wR = aSR - aSS;
+  const float GL = wL * (rl * aiL), GR = wR * (rr * aiR);
+  const float HL = wL * aiL * (El + pl + ml * Ss), HR = wR * aiR * (Er + pr + mr * Ss);
+  diss[0] = (GL - GR) + aSS * dQ[0];
+  diss[1] = (GL * SL - GR * SR) + aSS * dQ[1];
+  diss[2] = (GL * vl - GR * vr) + aSS * dQ[2];
+  diss[3] = (HL - HR) + aSS * dQ[3];
 }
 
 // Per-line buffers of a sweep, for the four reconstructed fields: edge jumps
 // of the primitives and of the cell fluxes.  No gradient buffer: the smooth
 // branch reads gradients only through its edge-jump stencils (the viscous
-// normal derivatives likewise), and the flagged branch forms them in FP64 from
-// the tile.
+// normal derivatives likewise), and the flagged branch forms its gradients
+// from the same edge jumps.
 //
 // Bank layout.  Pass 2 gives one interface to a lane, WFL = N + 1 interfaces
 // per line, so a half-wave (the 32 lanes one LDS cycle serves on 32 banks)
@@ -87,7 +94,7 @@ __device__ __forceinline__ void hllc_diss_f32(const float WL[4], const float WR[
 // g0 W + G p + i -- so the half-wave reads G consecutive words per position:
 // 32 distinct banks.  The line count is padded to whole groups (NLP), which
 // keeps the stride G a constant.
-template <int N, int NL>
+template <int N, int NL, int NE = 4>
 struct PhaseF32 {
   // edge jumps df at k+1/2, k in [-5, N+4), and dU, k in [-6, N+5) (pass 1,
   // one edge per item; the two outermost dU where a line end is flagged, for
@@ -98,7 +105,8 @@ struct PhaseF32 {
   // interface values d (pass 2/3 writes, pass 4 reads across lines in y):
   // width WFL + 2 under interleaving, else the odd width WFL | 1
   static constexpr int WFS = G > 1 ? WFL + 2 : (WFL | 1);
-  static constexpr int TOT = 4 * NLP * WU + 4 * NLP * (WG > WFL ? WG : WFL);
+  // NE fields of primitive edge jumps (viscous: T = gamma p / rho as a fifth)
+  static constexpr int TOT = NE * NLP * WU + 4 * NLP * (WG > WFL ? WG : WFL);
   static constexpr int CHI = NLP * WD;   // plain-detector flags
   __device__ static __forceinline__ int idx(int line, int p, int W) {
     return line / G * G * W + G * p + line % G;
@@ -111,8 +119,8 @@ struct PhaseF32 {
 // Flagged-interface queue entries are interface slots, bytes where they fit.
 template <class C>
 struct F32Cfg {
-  using PX = PhaseF32<C::TX, C::SX>;
-  using PY = PhaseF32<C::TY, C::SY>;
+  using PX = PhaseF32<C::TX, C::SX, C::VISC ? 5 : 4>;
+  using PY = PhaseF32<C::TY, C::SY, C::VISC ? 5 : 4>;
   static constexpr int NU = 4;                          // tile fields
   static constexpr int PH = C::cmax(PX::TOT, PY::TOT);  // floats
   static constexpr int CHI = C::cmax(PX::CHI, PY::CHI);
@@ -139,7 +147,8 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>
   constexpr int N = X ? C::TX : C::TY;
   constexpr int NL = X ? C::SX : C::SY;
   constexpr int NLINES = X ? C::TY : C::TX;
-  using PH = PhaseF32<N, NL>;
+  constexpr int NE = C::VISC ? 5 : 4;
+  using PH = PhaseF32<N, NL, NE>;
   constexpr int WD = PH::WD, WU = PH::WU, WG = PH::WG, WFL = PH::WFL, WP = PH::WP;
   constexpr int NLP = PH::NLP;
   constexpr int RS = C::RS, RX = C::RX, H = C::H, NT = C::NT;
@@ -156,7 +165,7 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>
   const float gammaf = (float)P.gamma, g1invf = (float)P.g1inv;
 
   float* sDU = L.ph;                 // [4][NLP x WU]   edge jumps of the primitives (rotated order)
-  float* sDF = sDU + 4 * NLP * WU;   // [4][NLP x WG]   edge jumps of the cell fluxes; then d
+  float* sDF = sDU + NE * NLP * WU;  // [4][NLP x WG]   edge jumps of the cell fluxes; then d
   auto bidx = [](int line, int p, int W) { return PH::idx(line, p, W); };
   auto ridx = [&](int line, int pos) {
     const int lx = X ? pos : l0 + line;
@@ -201,6 +210,13 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>
     for (int m = 0; m < 4; ++m) {
       sDF[m * GSTR + bidx(line, p, WG)] = (float)df[m];
       sDU[m * NLP * WU + bidx(line, p + 1, WU)] = (float)(W1[m] - W0[m]);
+    }
+    if (C::VISC) {
+      // T = gamma p / rho with the tile load's arithmetic (one refined
+      // reciprocal of rho), its edge jump as a fifth field
+      const double T0 = P.gamma * W0[3] * rcp_nr(W0[0]);
+      const double T1 = P.gamma * W1[3] * rcp_nr(W1[0]);
+      sDU[4 * NLP * WU + bidx(line, p + 1, WU)] = (float)(T1 - T0);
     }
     if (!DETMLP && k >= -3 && k < N + 3) {
       const double* rho = U + r;
@@ -323,12 +339,16 @@ __device__ __forceinline__ void sweep_f32(const StageParams& P, const LdsF32<QT>
           if (C::VISC) {
             const float gun0 = gv[0][0], gun1 = gv[0][1];
             const float gut0 = gv[1][0], gut1 = gv[1][1];
-            double T[8];
-            temps(r, T);
-            const float gT0 = (float)grad6(T[0], T[1], T[2], T[4], T[5], T[6]);
-            const float gT1 = (float)grad6(T[1], T[2], T[3], T[5], T[6], T[7]);
+            // T's normal derivative at pos and pos+1 and its jump, on its edge
+            // jumps as u_n's and u_t's (ET[a] = dT at (pos+a-4)+1/2)
+            float ET[8];
+#pragma unroll
+            for (int a = 1; a < 8; ++a) ET[a] = sDU[4 * NLP * WU + bidx(line, pos + 2 + a, WU)];
+            constexpr float z = 1.0f / 60.0f;
+            const float gT0 = z * (37.0f * (ET[3] + ET[4]) - 8.0f * (ET[2] + ET[5]) + (ET[1] + ET[6]));
+            const float gT1 = z * (37.0f * (ET[4] + ET[5]) - 8.0f * (ET[3] + ET[6]) + (ET[2] + ET[7]));
             const float jun = jv[0], jut = jv[1];
-            const float jT = (float)(T[4] - T[3]);
+            const float jT = ET[4];
             const float a2 = 0.5f * (float)kAlphaV, idn = (float)inv_dn;
             const float dun = (0.5f * (gun0 + gun1) + a2 * (jun - 0.5f * (gun0 + gun1))) * idn;
             const float dut = (0.5f * (gut0 + gut1) + a2 * (jut - 0.5f * (gut0 + gut1))) * idn;
