@@ -67,9 +67,12 @@ struct BatchCfg {
   static_assert(CI::TX == CV::TX && CI::TY == CV::TY && CI::NT == CV::NT, "one tile shape");
   static constexpr int TX = CI::TX, TY = CI::TY, NT = CI::NT;
   static constexpr int MINW = MW;
+  // the FP64 tiles take the edge form (primitive MEG7, MP test where flagged)
+  using LI = typename CI::template Layout<true>;
+  using LV = typename CV::template Layout<true>;
   static constexpr int U = F32 ? imax(F32Cfg<CI>::NU * CI::RS, F32Cfg<CV>::NU * CV::RS)
-                                : imax(CI::NF * CI::RS, CV::NF * CV::RS);
-  static constexpr int PH = F32 ? imax(F32Cfg<CI>::PH, F32Cfg<CV>::PH) : imax(CI::PH, CV::PH);
+                                : imax(LI::NFU * CI::RS, LV::NFU * CV::RS);
+  static constexpr int PH = F32 ? imax(F32Cfg<CI>::PH, F32Cfg<CV>::PH) : imax(LI::PH, LV::PH);
   static constexpr int CHI = F32 ? imax(F32Cfg<CI>::CHI, F32Cfg<CV>::CHI) : imax(CI::CHI, CV::CHI);
   static constexpr int QMAX = imax(CI::QMAX, CV::QMAX);
   using PhT = typename std::conditional<F32, float, double>::type;

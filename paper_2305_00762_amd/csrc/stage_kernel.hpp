@@ -3,9 +3,12 @@
 // One workgroup owns a TX x TY tile of cells.  It stages the tile plus a
 // 6-cell halo of primitive variables in LDS once (periodic wrap or
 // transmissive clamp in the index math), then sweeps x and y:
-//   pass 1 (per cell):      shared sixth-order gradients (eq. eqn:six),
-//                           density detector (Sec. 2.4), cell-centre fluxes,
-//                           tangential derivatives for the viscous terms;
+//   pass 1 (per cell):      edge jumps of the reconstructed fields (and of
+//                           T, viscous) from which the sixth-order gradients
+//                           of eq. (eqn:six) are formed where read; staged
+//                           gradients instead for MEG7-cons and the MP test
+//                           everywhere; density detector (Sec. 2.4),
+//                           cell-centre fluxes;
 //   pass 2 (per interface): sigma from the 6-cell buffer; smooth interfaces
 //                           take GRB states + flux reconstruction + HLLC +
 //                           viscous flux at once; flagged ones are compacted
@@ -79,29 +82,50 @@ struct TileCfg {
   static constexpr bool VISC = VISC_;
   static constexpr int H = 6;
   static constexpr int RX = TX + 2 * H, RY = TY + 2 * H, RS = RX * RY;
-  static constexpr int NF = VISC ? 5 : 4;
   static constexpr int cmax(int a, int b) { return a > b ? a : b; }
-  // Per-line buffers of a sweep: normal gradients of the four reconstructed
-  // fields and the cell fluxes (then the interface fluxes).  The viscous
-  // terms' derivatives (tangential ones of u_n, u_t; the normal one of T) are
-  // formed from the tile where an interface needs them: in LDS they would
-  // cost the viscous kernel a workgroup per CU for about the same
-  // instruction count.
-  template <int N, int NL>
+  // Per-line buffers of a sweep: a first buffer of NE fields and the cell
+  // fluxes (then the interface fluxes).  The first buffer holds either the
+  // normal gradients of the four reconstructed fields (MEG7-cons, MP test
+  // everywhere) or the edge jumps of those fields, from which every gradient
+  // is formed where it is read (the edge form: the other variants); the
+  // viscous edge form adds the edge jumps of T as a fifth field, and its tile
+  // then holds no T.  The tangential derivatives of u_n, u_t are formed from
+  // the tile where an interface needs them.
+  template <int N, int NL, int NE = 4>
   struct Phase {
     static constexpr int WD = N + 6, WF = N + 10, WFL = N + 1;
-    static constexpr int D = 4 * NL * WD;
+    static constexpr int WE = N + 10;   // edges j+1/2, j in [-5, N+5)
+    static constexpr int D = NE * NL * (WE > WD ? WE : WD);
     static constexpr int F = 4 * NL * (WF > WFL ? WF : WFL);
     static constexpr int TOT = D + F;
   };
+  template <bool EDGE>
+  struct Layout {
+    static constexpr bool TFIELD = VISC && !EDGE;   // the tile holds T
+    static constexpr int NFU = TFIELD ? 5 : 4;      // tile fields
+    static constexpr int NE = VISC && EDGE ? 5 : 4;
+    static constexpr int PH = cmax(Phase<TX, SX, NE>::TOT, Phase<TY, SY, NE>::TOT);
+  };
   using PX = Phase<TX, SX>;
   using PY = Phase<TY, SY>;
-  static constexpr int PH = cmax(PX::TOT, PY::TOT);
+  // the largest of the two layouts (bounds and the batched kernel's arrays)
+  static constexpr int NF = cmax(Layout<false>::NFU, Layout<true>::NFU);
+  static constexpr int PH = cmax(Layout<false>::PH, Layout<true>::PH);
   static constexpr int CHI = cmax(SX * PX::WD, SY * PY::WD);
   static constexpr int QMAX = cmax(SX * PX::WFL, SY * PY::WFL);
   static constexpr int CPT = (TX * TY + NT - 1) / NT;
   static constexpr int LDS_BYTES = 8 * (NF * RS + PH) + CHI + 2 * QMAX + 16;
+  template <bool EDGE>
+  static constexpr int lds_bytes() {
+    return 8 * (Layout<EDGE>::NFU * RS + Layout<EDGE>::PH) + CHI + 2 * QMAX + 16;
+  }
 };
+
+// The edge form (per-line edge jumps instead of staged gradients) serves
+// every variant but MEG7-cons and the MP test at every interface, which read
+// many gradients per interface.
+template <bool CONS, bool MPE>
+constexpr bool edge_form() { return !CONS && !MPE; }
 
 // Cell slot k of thread tid: tile cell (lx, ly); false for an idle slot.
 // Row-major in general.  For 15 x 15 tiles on 256 threads each half-wave
@@ -185,8 +209,10 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
   constexpr int N = X ? C::TX : C::TY;
   constexpr int NL = X ? C::SX : C::SY;
   constexpr int NLINES = X ? C::TY : C::TX;
-  using PH = typename C::template Phase<N, NL>;
-  constexpr int WD = PH::WD, WF = PH::WF, WFL = PH::WFL;
+  constexpr bool EDGE = edge_form<CONS, MPE>();
+  constexpr bool ET = C::VISC && EDGE;   // T edges in the first buffer, no T in the tile
+  using PH = typename C::template Phase<N, NL, C::template Layout<EDGE>::NE>;
+  constexpr int WD = PH::WD, WF = PH::WF, WFL = PH::WFL, WE = PH::WE;
   constexpr int RS = C::RS, RX = C::RX, H = C::H, NT = C::NT;
   constexpr int SN = X ? 1 : RX;  // normal stride in the LDS tile
   constexpr int ST = X ? RX : 1;  // tangential stride
@@ -198,8 +224,9 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
   const double inv_dn = X ? P.inv_dx : P.inv_dy;
   const double inv_dt = X ? P.inv_dy : P.inv_dx;
 
-  double* sD = L.ph;                       // [4][NL x WD]   normal gradients (rotated order)
-  double* sF = sD + 4 * NL * WD;           // [4][NL x WF]   cell fluxes; later [4][NL x WFL] interface fluxes
+  double* sD = L.ph;                       // [4][NL x WD]   normal gradients (rotated order), or
+  double* sE = L.ph;                       // [4|5][NL x WE] edge jumps (rotated order, then T) at j + 5
+  double* sF = sD + PH::D;                 // [4][NL x WF]   cell fluxes; later [4][NL x WFL] interface fluxes
   constexpr int FSTR = (WF > WFL ? WF : WFL) * NL;
   // interface values: odd row stride, so pass 4 (lanes across lines in the
   // y sweep) reads distinct banks
@@ -230,16 +257,68 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
     const double* u = L.U + f * RS + r;
     return grad6(u[-3 * d], u[-2 * d], u[-d], u[d], u[2 * d], u[3 * d]);
   };
-  // viscous flux of interface (line, pos + 1/2) added to F; r is its left cell
-  auto visc_at = [&](int line, int pos, int r, double* F) {
+  // Edge form: edge jump j+1/2 of rotated field m (m < 4) on line `line`
+  // (pass 1 stores j in [-5, N+5); the edge j = -6, which only gradients at
+  // a line's first interface reach, is formed from the tile), and the normal
+  // gradient of eq. (eqn:six) at cell k on the edges: the stencil
+  // (45, -9, 1)/60 on value differences becomes (37, -8, 1)/60 on the pairs
+  // of edges around k.
+  auto edge = [&](int m, int line, int j) -> double {
+    if (j < -5) {
+      const double* u = L.U + rot[m] * RS + ridx(line, -6);
+      return u[SN] - u[0];
+    }
+    return sE[m * NL * WE + bidx(line, j + 5, WE)];
+  };
+  auto g6e = [](double e0, double e1, double e2, double e3, double e4, double e5) {
+    constexpr double z = 1.0 / 60.0;
+    return z * (37.0 * (e2 + e3) - 8.0 * (e1 + e4) + (e0 + e5));
+  };
+  auto gradE = [&](int m, int line, int k) -> double {
+    return g6e(edge(m, line, k - 3), edge(m, line, k - 2), edge(m, line, k - 1),
+               edge(m, line, k), edge(m, line, k + 1), edge(m, line, k + 2));
+  };
+  // normal gradient of rotated field m at cell k of line `line`
+  auto grad_at = [&](int m, int line, int k) -> double {
+    if constexpr (EDGE) return gradE(m, line, k);
+    else return sD[m * NL * WD + bidx(line, k + 3, WD)];
+  };
+  // Normal differences the viscous flux of interface (line, pos + 1/2)
+  // takes, r its left cell: gv = {g(u_n), g(u_n)', g(u_t), g(u_t)', g(T),
+  // g(T)', T' - T} (g at the left cell, ' at the right one; velocity entries
+  // for the primitive forms only, and only with vel)
+  auto visc_normal = [&](int line, int pos, int r, double* gv, bool vel) {
+    if constexpr (ET) {
+      // T edges pos-3 .. pos+3: stored for every interface pos in [-1, N)
+      const double* e = sE + 4 * NL * WE;
+      double t[7];
+#pragma unroll
+      for (int a = 0; a < 7; ++a) t[a] = e[bidx(line, pos + a + 2, WE)];
+      gv[4] = g6e(t[0], t[1], t[2], t[3], t[4], t[5]);
+      gv[5] = g6e(t[1], t[2], t[3], t[4], t[5], t[6]);
+      gv[6] = t[3];
+    } else {
+      gv[4] = g6(4, r, SN);
+      gv[5] = g6(4, r + SN, SN);
+      gv[6] = L.U[4 * RS + r + SN] - L.U[4 * RS + r];
+    }
+    if (!CONS && vel) {
+      gv[0] = grad_at(1, line, pos);
+      gv[1] = grad_at(1, line, pos + 1);
+      gv[2] = grad_at(2, line, pos);
+      gv[3] = grad_at(2, line, pos + 1);
+    }
+  };
+  // viscous flux of interface (line, pos + 1/2) added to F (gv as above)
+  auto visc_at = [&](int line, int pos, int r, const double* gv, double* F) {
     const double* U = L.U;
-    const int b0 = bidx(line, pos + 3, WD), b1 = bidx(line, pos + 4, WD);
-    const double* D1 = sD + 1 * NL * WD;
-    const double* D2 = sD + 2 * NL * WD;
-    const double gT0 = g6(4, r, SN), gT1 = g6(4, r + SN, SN);
+    const double gT0 = gv[4], gT1 = gv[5];
     if (CONS) {
       // velocity gradients by the chain rule d u = (d(rho u) - u d rho) / rho
+      const int b0 = bidx(line, pos + 3, WD), b1 = bidx(line, pos + 4, WD);
       const double* D0 = sD;
+      const double* D1 = sD + 1 * NL * WD;
+      const double* D2 = sD + 2 * NL * WD;
       const double ir0 = rcp_nr(U[r]), ir1 = rcp_nr(U[r + SN]);
       const double un0 = U[FN * RS + r] * ir0, un1 = U[FN * RS + r + SN] * ir1;
       const double ut0 = U[FT * RS + r] * ir0, ut1 = U[FT * RS + r + SN] * ir1;
@@ -255,13 +334,13 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
         dunt[c] = (gn - (U[FN * RS + rc] * ir) * gr) * ir;
         dutt[c] = (gt - (U[FT * RS + rc] * ir) * gr) * ir;
       }
-      viscous_add(un0, un1, ut0, ut1, U[4 * RS + r], U[4 * RS + r + SN],
+      viscous_add(un0, un1, ut0, ut1, 0.0, gv[6],
                   (D1[b0] - un0 * D0[b0]) * ir0, (D1[b1] - un1 * D0[b1]) * ir1,
                   (D2[b0] - ut0 * D0[b0]) * ir0, (D2[b1] - ut1 * D0[b1]) * ir1, gT0, gT1,
                   dunt[0], dunt[1], dutt[0], dutt[1], inv_dn, P.mu, P.kq, F);
     } else {
       viscous_add(U[FN * RS + r], U[FN * RS + r + SN], U[FT * RS + r], U[FT * RS + r + SN],
-                  U[4 * RS + r], U[4 * RS + r + SN], D1[b0], D1[b1], D2[b0], D2[b1], gT0, gT1,
+                  0.0, gv[6], gv[0], gv[1], gv[2], gv[3], gT0, gT1,
                   g6(FN, r, ST) * inv_dt, g6(FN, r + SN, ST) * inv_dt,
                   g6(FT, r, ST) * inv_dt, g6(FT, r + SN, ST) * inv_dt, inv_dn, P.mu, P.kq, F);
     }
@@ -291,13 +370,29 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
 #pragma unroll
       for (int m = 0; m < 4; ++m) sF[m * FSTR + bidx(line, p, WF)] = f[m];
     }
-    if (pos >= -3 && pos < N + 3) {
-      const int pd = pos + 3;
+    if (EDGE) {
+      // edge jump pos + 1/2, pos in [-5, N+5)
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const double* u = U + rot[m] * RS + r;
-        sD[m * NL * WD + bidx(line, pd, WD)] =
-            grad6(u[-3 * SN], u[-2 * SN], u[-SN], u[SN], u[2 * SN], u[3 * SN]);
+        sE[m * NL * WE + bidx(line, pos + 5, WE)] = u[SN] - u[0];
+      }
+      if (ET) {
+        // T = gamma p / rho on both sides (the tile holds no T)
+        const double T0 = P.gamma * U[3 * RS + r] * rcp_nr(U[r]);
+        const double T1 = P.gamma * U[3 * RS + r + SN] * rcp_nr(U[r + SN]);
+        sE[4 * NL * WE + bidx(line, pos + 5, WE)] = T1 - T0;
+      }
+    }
+    if (pos >= -3 && pos < N + 3) {
+      const int pd = pos + 3;
+      if (!EDGE) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const double* u = U + rot[m] * RS + r;
+          sD[m * NL * WD + bidx(line, pd, WD)] =
+              grad6(u[-3 * SN], u[-2 * SN], u[-SN], u[SN], u[2 * SN], u[3 * SN]);
+        }
       }
       if (DETMLP) {
         L.chi[bidx(line, pd, WD)] =
@@ -341,18 +436,48 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
         flagged = !sigma;
         if (sigma) {
           const int r = ridx(line, pos);
-          double WL[4], WR[4], Fm[4];
+          double WL[4], WR[4], Fm[4], gv[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
             const double* u = L.U + rot[m] * RS + r;
-            double v[6], g[6];
+            if constexpr (EDGE) {
+              // eq. (eqn:grb) (ORD 7) or its fourth-order subset with the
+              // gradients of eq. (eqn:six) substituted, minus Phi_j (resp.
+              // Phi_{j+1}): stencils on the edge jumps E[a] at (pos+a-4)+1/2
+              double E[9];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) v[q] = u[(q - 2) * SN];
+              for (int a = 0; a < 9; ++a) E[a] = sE[m * NL * WE + bidx(line, pos + a + 1, WE)];
+              double cL, cR;
+              if (ORD == 4) {
+                constexpr double s4 = 1.0 / 1440.0;
+                cL = s4 * ((E[0] - E[7]) + 4.0 * E[1] - 60.0 * E[2] + 249.0 * E[3] + 639.0 * E[4] -
+                           132.0 * E[5] + 20.0 * E[6]);
+                cR = s4 * ((E[1] - E[8]) - 20.0 * E[2] + 132.0 * E[3] - 639.0 * E[4] -
+                           249.0 * E[5] + 60.0 * E[6] - 4.0 * E[7]);
+              } else {
+                constexpr double s7 = 1.0 / 840.0;
+                cL = s7 * ((E[0] - E[1] - E[7]) - 23.0 * E[2] + 123.0 * E[3] + 395.0 * E[4] -
+                           89.0 * E[5] + 15.0 * E[6]);
+                cR = s7 * ((E[1] - E[8] + E[7]) - 15.0 * E[2] + 89.0 * E[3] - 395.0 * E[4] -
+                           123.0 * E[5] + 23.0 * E[6]);
+              }
+              WL[m] = u[0] + cL;
+              WR[m] = u[SN] + cR;
+              if (C::VISC && (m == 1 || m == 2)) {
+                // velocity gradients at cells pos, pos+1 from the same edges
+                gv[2 * m - 2] = g6e(E[1], E[2], E[3], E[4], E[5], E[6]);
+                gv[2 * m - 1] = g6e(E[2], E[3], E[4], E[5], E[6], E[7]);
+              }
+            } else {
+              double v[6], g[6];
 #pragma unroll
-            for (int q = 1; q < 5; ++q) g[q] = sD[m * NL * WD + bidx(line, pos + q + 1, WD)];
-            g[0] = g[5] = 0.0;
-            WL[m] = grb_l<ORD>(v, g);
-            WR[m] = grb_r<ORD>(v, g);
+              for (int q = 0; q < 6; ++q) v[q] = u[(q - 2) * SN];
+#pragma unroll
+              for (int q = 1; q < 5; ++q) g[q] = sD[m * NL * WD + bidx(line, pos + q + 1, WD)];
+              g[0] = g[5] = 0.0;
+              WL[m] = grb_l<ORD>(v, g);
+              WR[m] = grb_r<ORD>(v, g);
+            }
             // (F(f_L) + F(f_R))/2 on the cell fluxes f_{j-4..j+5}
             double f[10];
 #pragma unroll
@@ -398,7 +523,11 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
             for (int m = 0; m < 4; ++m) Fm[m] = 0.5 * (f0[m] + f1[m]);
           }
           hllc<LM>(WL, WR, Fm, P.gamma, P.g1inv, fsm[k]);
-          if (C::VISC) visc_at(line, pos, r, fsm[k]);
+          if (C::VISC) {
+            // edge form: the velocity entries came with the GRB states above
+            visc_normal(line, pos, r, gv, !EDGE);
+            visc_at(line, pos, r, gv, fsm[k]);
+          }
           has[k] = true;
         }
       }
@@ -439,7 +568,7 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
     const double* U = L.U;
     double WL[4], WR[4];
     auto Vf = [&](int q, int f) { return U[rot[f] * RS + r + (q - 2) * SN]; };
-    auto Gf = [&](int q, int f) { return sD[f * NL * WD + bidx(line, pos + q + 1, WD)]; };
+    auto Gf = [&](int q, int f) { return grad_at(f, line, pos + q - 2); };
     if (CONS) {
       double QL[4], QR[4];
       meg7_char_states_cons<ORD>(Vf, Gf, P.gamma, QL, QR);
@@ -466,7 +595,11 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
 #pragma unroll
     for (int m = 0; m < 4; ++m) Fm[m] = 0.5 * (FL[m] + FR[m]);
     hllc<LM>(WL, WR, Fm, P.gamma, P.g1inv, F);
-    if (C::VISC) visc_at(line, pos, r, F);
+    if (C::VISC) {
+      double gv[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      visc_normal(line, pos, r, gv, true);
+      visc_at(line, pos, r, gv, F);
+    }
 #pragma unroll
     for (int m = 0; m < 4; ++m) sF[m * FSTR + bidx(line, p, WFS)] = F[m];
   }
@@ -555,8 +688,9 @@ __device__ __forceinline__ unsigned ghost_op(int kx, int ky, int sx, int gx, int
   return op;
 }
 
-// TFIELD: whether the tile holds T (the FP64 viscous kernels; the FP32 one
-// forms T where it needs it).
+// TFIELD: whether the tile holds T (the FP64 viscous kernels of MEG7-cons
+// and of the MP test everywhere; the edge-form and FP32 ones form T where
+// they need it).
 template <class C, bool CONS = false, bool TFIELD = C::VISC>
 __device__ __forceinline__ void stage_load(const StageParams& P, double* sU, int tx0, int ty0) {
   constexpr int RS = C::RS, RX = C::RX, H = C::H, NT = C::NT, TX = C::TX, TY = C::TY;
@@ -839,7 +973,7 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int tx0, int ty
                                            unsigned char* sChiF) {
   ChiMap<C> cm;
   if (DETMLP) fetch_chimap<C>(P, cm, tx0, ty0);
-  stage_load<C, CONS>(P, sU, tx0, ty0);
+  stage_load<C, CONS, C::template Layout<edge_form<CONS, MPE>()>::TFIELD>(P, sU, tx0, ty0);
   if (DETMLP) put_chimap<C>(cm, sChiF);
   __syncthreads();
   const Lds L{sU, sPh, sChi, sQueue, sQCount, sChiF};
@@ -857,8 +991,9 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int tx0, int ty
 
 template <class C, bool DETMLP, bool CONS = false, int ORD = 7, bool LM = false, bool MPE = false>
 __global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel(StageParams P) {
-  __shared__ double sU[C::NF * C::RS];
-  __shared__ double sPh[C::PH];
+  using LY = typename C::template Layout<edge_form<CONS, MPE>()>;
+  __shared__ double sU[LY::NFU * C::RS];
+  __shared__ double sPh[LY::PH];
   __shared__ unsigned char sChi[C::CHI];
   __shared__ unsigned short sQueue[C::QMAX];
   __shared__ unsigned char sChiF[DETMLP ? (C::TX + 6) * (C::TY + 6) : 1];
