@@ -202,17 +202,18 @@ __device__ __forceinline__ void meg7_pair(const double* v, const double* g, doub
 }
 
 // Characteristic MEG7 states at an interface (Secs. 2.3, 2.4, flagged
-// branch).  Wf(q, f) / Gf(q, f) return rotated primitive field f and its
-// normal gradient (spacing-scaled) at offset q-2 (q = 0..5) from cell j.
-// Eigenvectors of the primitive normal Jacobian are taken at the mean density
-// and pressure of cells j, j+1.  Each characteristic field combines two
-// primitive fields (rows of L: (u_n, p), (rho, p), (u_t), (u_n, p)); the four
-// fields are limited one at a time in a rolled loop that reads only its two
-// primitive fields, which keeps the register footprint small, and are
-// projected back by accumulating the columns of R.
-template <int ORD = 7, class FW, class FG>
-__device__ __forceinline__ void meg7_char_states(FW Wf, FG Gf, double gamma, double WLo[4],
-                                                 double WRo[4]) {
+// branch).  Wf(q, f) returns rotated primitive field f at offset q-2
+// (q = 0..5) from cell j; CG(fa, fb, ca, cb, cg) writes the normal gradients
+// (spacing-scaled) of the combination ca * field fa + cb * field fb at the
+// same six offsets.  Eigenvectors of the primitive normal Jacobian are taken
+// at the mean density and pressure of cells j, j+1.  Each characteristic
+// field combines two primitive fields (rows of L: (u_n, p), (rho, p), (u_t),
+// (u_n, p)); the four fields are limited one at a time in a rolled loop that
+// reads only its two primitive fields, which keeps the register footprint
+// small, and are projected back by accumulating the columns of R.
+template <int ORD = 7, class FW, class FC>
+__device__ __forceinline__ void meg7_char_states_comb(FW Wf, FC CG, double gamma, double WLo[4],
+                                                      double WRo[4]) {
   const double rb = 0.5 * (Wf(2, 0) + Wf(3, 0));
   const double pb = 0.5 * (Wf(2, 3) + Wf(3, 3));
   const double irb = rcp_nr(rb);
@@ -231,10 +232,8 @@ __device__ __forceinline__ void meg7_char_states(FW Wf, FG Gf, double gamma, dou
     const double cbv = (m == 1) ? -ic2 : ((m == 2) ? 0.0 : h2c2);
     double cv[6], cg[6];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      cv[q] = ca * Wf(q, fa) + cbv * Wf(q, fb);
-      cg[q] = ca * Gf(q, fa) + cbv * Gf(q, fb);
-    }
+    for (int q = 0; q < 6; ++q) cv[q] = ca * Wf(q, fa) + cbv * Wf(q, fb);
+    CG(fa, fb, ca, cbv, cg);
     double cl, cr;
     meg7_pair<ORD>(cv, cg, cl, cr);
     // column m of R = L^{-1}: (1,-c/rho,0,c^2), (1,0,0,0), (0,0,1,0), (1,c/rho,0,c^2)
@@ -245,6 +244,42 @@ __device__ __forceinline__ void meg7_char_states(FW Wf, FG Gf, double gamma, dou
     WLo[0] += b0 * cl; WLo[1] += b1 * cl; WLo[2] += b2 * cl; WLo[3] += b3 * cl;
     WRo[0] += b0 * cr; WRo[1] += b1 * cr; WRo[2] += b2 * cr; WRo[3] += b3 * cr;
   }
+}
+
+// The same with staged gradients: Gf(q, f) is the normal gradient of rotated
+// field f at offset q-2.
+template <int ORD = 7, class FW, class FG>
+__device__ __forceinline__ void meg7_char_states(FW Wf, FG Gf, double gamma, double WLo[4],
+                                                 double WRo[4]) {
+  meg7_char_states_comb<ORD>(
+      Wf,
+      [&](int fa, int fb, double ca, double cb, double cg[6]) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) cg[q] = ca * Gf(q, fa) + cb * Gf(q, fb);
+      },
+      gamma, WLo, WRo);
+}
+
+// The same with the gradients formed from edge jumps: Ef(a, f) is the jump of
+// rotated field f across edge (j - 5 + a) + 1/2, a = 0..10.  The gradient of
+// eq. (eqn:six) at cell k is (37, -8, 1)/60 on the pairs of edges around k;
+// being linear, it is taken once on the combined jumps of the two fields.
+template <int ORD = 7, class FW, class FE>
+__device__ __forceinline__ void meg7_char_states_edges(FW Wf, FE Ef, double gamma, double WLo[4],
+                                                       double WRo[4]) {
+  meg7_char_states_comb<ORD>(
+      Wf,
+      [&](int fa, int fb, double ca, double cb, double cg[6]) {
+        double ce[11];
+#pragma unroll
+        for (int a = 0; a < 11; ++a) ce[a] = ca * Ef(a, fa) + cb * Ef(a, fb);
+        constexpr double z = 1.0 / 60.0;
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+          cg[q] = z * (37.0 * (ce[q + 2] + ce[q + 3]) - 8.0 * (ce[q + 1] + ce[q + 4]) +
+                       (ce[q] + ce[q + 5]));
+      },
+      gamma, WLo, WRo);
 }
 
 // Conservative (rho, rho un, rho ut, E) to primitive (rho, un, ut, p),

@@ -91,11 +91,11 @@ struct TileCfg {
   // viscous edge form adds the edge jumps of T as a fifth field, and its tile
   // then holds no T.  The tangential derivatives of u_n, u_t are formed from
   // the tile where an interface needs them.
-  template <int N, int NL, int NE = 4>
+  template <int N, int NL, int NE = 4, bool EDGE = true>
   struct Phase {
     static constexpr int WD = N + 6, WF = N + 10, WFL = N + 1;
     static constexpr int WE = N + 10;   // edges j+1/2, j in [-5, N+5)
-    static constexpr int D = NE * NL * (WE > WD ? WE : WD);
+    static constexpr int D = NE * NL * (EDGE ? WE : WD);
     static constexpr int F = 4 * NL * (WF > WFL ? WF : WFL);
     static constexpr int TOT = D + F;
   };
@@ -104,7 +104,7 @@ struct TileCfg {
     static constexpr bool TFIELD = VISC && !EDGE;   // the tile holds T
     static constexpr int NFU = TFIELD ? 5 : 4;      // tile fields
     static constexpr int NE = VISC && EDGE ? 5 : 4;
-    static constexpr int PH = cmax(Phase<TX, SX, NE>::TOT, Phase<TY, SY, NE>::TOT);
+    static constexpr int PH = cmax(Phase<TX, SX, NE, EDGE>::TOT, Phase<TY, SY, NE, EDGE>::TOT);
   };
   using PX = Phase<TX, SX>;
   using PY = Phase<TY, SY>;
@@ -211,7 +211,7 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
   constexpr int NLINES = X ? C::TY : C::TX;
   constexpr bool EDGE = edge_form<CONS, MPE>();
   constexpr bool ET = C::VISC && EDGE;   // T edges in the first buffer, no T in the tile
-  using PH = typename C::template Phase<N, NL, C::template Layout<EDGE>::NE>;
+  using PH = typename C::template Phase<N, NL, C::template Layout<EDGE>::NE, EDGE>;
   constexpr int WD = PH::WD, WF = PH::WF, WFL = PH::WFL, WE = PH::WE;
   constexpr int RS = C::RS, RX = C::RX, H = C::H, NT = C::NT;
   constexpr int SN = X ? 1 : RX;  // normal stride in the LDS tile
@@ -569,11 +569,15 @@ __device__ __forceinline__ void sweep(const StageParams& P, const Lds& L, int l0
     double WL[4], WR[4];
     auto Vf = [&](int q, int f) { return U[rot[f] * RS + r + (q - 2) * SN]; };
     auto Gf = [&](int q, int f) { return grad_at(f, line, pos + q - 2); };
+    // edge form: the jumps across edges (pos-5)+1/2 .. (pos+5)+1/2
+    auto Ef = [&](int a, int f) { return edge(f, line, pos - 5 + a); };
     if (CONS) {
       double QL[4], QR[4];
       meg7_char_states_cons<ORD>(Vf, Gf, P.gamma, QL, QR);
       cons_to_prim(QL, P.gamma, WL);
       cons_to_prim(QR, P.gamma, WR);
+    } else if constexpr (EDGE) {
+      meg7_char_states_edges<ORD>(Vf, Ef, P.gamma, WL, WR);
     } else {
       meg7_char_states<ORD>(Vf, Gf, P.gamma, WL, WR);
     }
