@@ -56,8 +56,10 @@ struct TileVariant {
 };
 using E31 = TileCfg<31, 15, 15, 16, 256, false>;
 using V31 = TileCfg<31, 15, 8, 16, 256, true>;
-using E15 = TileCfg<15, 15, 15, 15, 256, false>;
-using V15 = TileCfg<15, 15, 15, 15, 256, true>;
+// FP64 on 15x15 tiles: 3 workgroups per CU fit the LDS, so the register
+// budget is held to 3 waves per SIMD (168 VGPRs)
+using E15 = TileCfg<15, 15, 15, 15, 256, false, 3>;
+using V15 = TileCfg<15, 15, 15, 15, 256, true, 3>;
 // FP32 bulk on 15x15 tiles: 4 workgroups per CU fit the LDS, so the register
 // budget is held to 4 waves per SIMD (128 VGPRs)
 using F15 = TileCfg<15, 15, 15, 15, 256, false, 4>;

@@ -993,8 +993,11 @@ __device__ __forceinline__ void stage_tile(const StageParams& P, int tx0, int ty
   stage_store<C>(P, res, tx0, ty0);
 }
 
+// The MP test at every interface needs more registers than any budget of
+// three waves per SIMD leaves without spilling: those variants get two.
 template <class C, bool DETMLP, bool CONS = false, int ORD = 7, bool LM = false, bool MPE = false>
-__global__ __launch_bounds__(C::NT, C::MINW) void meg7_stage_kernel(StageParams P) {
+__global__ __launch_bounds__(C::NT, (MPE && C::MINW > 2) ? 2 : C::MINW) void meg7_stage_kernel(
+    StageParams P) {
   using LY = typename C::template Layout<edge_form<CONS, MPE>()>;
   __shared__ double sU[LY::NFU * C::RS];
   __shared__ double sPh[LY::PH];
