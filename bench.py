@@ -149,22 +149,27 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel, workload):
+def load_traffic(kernel, workload, **launch):
     """HBM bytes per launch from the committed rocprofv3 PMC summary, if any
     (a line 'bytes_per_launch = <value>'), and only if the summary was taken
-    on the current kernel sources (its 'source_sha = <hash>' line): counters
-    of a kernel that has changed since are not reported."""
+    on the current kernel sources (its 'source_sha = <hash>' line) and on the
+    launch being reported (a 'key = value' line for every keyword, e.g. the
+    tile shape): counters of another kernel or launch are not reported."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.txt")
     if not os.path.exists(path):
         return None
-    val, sha = None, None
+    keys = {}
     for line in open(path):
         t = line.strip()
-        if t.startswith("bytes_per_launch") and "=" in t:
-            val = float(t.split("=", 1)[1].split()[0])
-        if t.startswith("source_sha") and "=" in t:
-            sha = t.split("=", 1)[1].split()[0]
-    return val if sha == kernel_source_sha() else None
+        if "=" in t and not t.startswith(" "):
+            k, v = t.split("=", 1)
+            if k.strip() in ("bytes_per_launch", "source_sha") or k.strip() in launch:
+                keys[k.strip()] = v.strip().split()[0] if v.strip() else ""
+    if keys.get("source_sha") != kernel_source_sha() or "bytes_per_launch" not in keys:
+        return None
+    if any(keys.get(k) != str(v) for k, v in launch.items()):
+        return None
+    return float(keys["bytes_per_launch"])
 
 
 # VALU issue peak of the chip: 256 CUs x 4 SIMDs, each issuing one wave64
@@ -726,7 +731,10 @@ def bench_batch(a, steps):
                    "setup_s": round(time.time() - t0, 1)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": load_traffic("meg7_batch_kernel", "batch512"),
+                     "traffic": load_traffic("meg7_batch_kernel", "batch512",
+                                             path="fp32" if prec else "fp64",
+                                             launch_form=form,
+                                             tile=f"{tx}x{ty}"),
                      "kernel": "meg7_batch_kernel", "avg_launch_us": avg_ms * 1e3,
                      "bytes_per_cell_stage": 256.0 / 3.0},
         "status": status,
@@ -898,7 +906,7 @@ def bench_2d(a, workload, steps_arg, stream, cpu=True, secondary=False):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": load_traffic(kname, workload),
+            "traffic": load_traffic(kname, workload, tile=head_rec["tile"]),
             "kernel": head.kernel,
             "avg_launch_us": stage_ms * 1e3 / max(launches, 1),
             "bytes_per_cell_stage": 256.0 / 3.0,
