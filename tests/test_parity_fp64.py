@@ -75,6 +75,51 @@ def test_noise_all_flagged():
     check_residual("noise48 viscous", P)
 
 
+def _noise(rng, n, ny):
+    rho = rng.uniform(0.5, 1.5, (ny, n))
+    u, v = rng.uniform(-0.5, 0.5, (2, ny, n))
+    p = rng.uniform(0.5, 1.5, (ny, n))
+    P = PB.free_stream(n, ny=ny)
+    P.Q = PB.prim_to_state(rho, u, v, p)
+    return P
+
+
+def check_residual_kw(name, P, tiling, **kw):
+    R, sx, sy, st = gpu_residual(P, tiling=tiling, **kw)
+    okw = {k: v for k, v in kw.items() if k in ("recon", "order")}
+    Ro, sxo, syo, nlim = O.residual(ocfg(P, **okw), P.Q, want_flags=True)
+    e = res_err(R, Ro, P)
+    report(name, relerr=e.max(), flagged=int((sxo == 0).sum() + (syo == 0).sum()),
+           flag_mismatch=int((sx != sxo).sum() + (sy != syo).sum()))
+    assert st == 0
+    assert (sx == sxo).all() and (sy == syo).all()
+    assert (e <= TOL).all(), e
+
+
+@pytest.mark.parametrize("order", [7, 4])
+@pytest.mark.parametrize("tiling", [0, 1, 2, 3])
+def test_noise_all_flagged_every_tiling(tiling, order):
+    # every interface flagged, so the characteristic branch runs at the first
+    # and last interface of every line of every tile: with the edge-jump form
+    # its gradients there reach the outermost edges (the first of them formed
+    # from the tile); inviscid and viscous (T as an edge field), periodic and
+    # with walls and the shock-stable HLLC (the side table, ghost rules)
+    rng = np.random.default_rng(21 + order)
+    for n, ny, mu in ((48, 48, 0.0), (50, 37, 1e-3)):
+        P = _noise(rng, n, ny)
+        P.mu = mu
+        check_residual_kw(f"noise{n}x{ny} mu={mu} t{tiling} o{order}", P, tiling, order=order)
+    P = _noise(rng, 45, 34)
+    P.sides = [(PB.BC_REFLECT, None, PB.BC_REFLECT, None, float("inf"), 0.0),
+               (PB.BC_TRANSMISSIVE, None, PB.BC_TRANSMISSIVE, None, float("inf"), 0.0),
+               (PB.BC_NOSLIP, None, PB.BC_NOSLIP, None, float("inf"), 0.0),
+               (PB.BC_TRANSMISSIVE, None, PB.BC_TRANSMISSIVE, None, float("inf"), 0.0)]
+    P.riemann = 1 if order == 7 else 0      # the shock-stable HLLC is built for order 7
+    P.mu = 1e-3
+    check_residual_kw(f"noise45x34 walls riemann{P.riemann} viscous t{tiling} o{order}", P,
+                      tiling, order=order)
+
+
 def test_free_stream_exact_zero():
     for bc in (PB.BC_PERIODIC, PB.BC_TRANSMISSIVE):
         P = PB.free_stream(40, bc=bc, ny=33, mu=1e-3)
