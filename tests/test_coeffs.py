@@ -145,3 +145,39 @@ def test_oracle_tables_are_printed(orc, which):
     num, den = orc.table(which)
     e = GOLD[TABLES[which]]
     assert [Fr(n, den) for n in num] == [Fr(n, e["den"]) for n in e["num"]]
+
+
+# The stage kernels hold the reconstruction as stencils on edge jumps
+# E_a = Phi_{j+a-3} - Phi_{j+a-4} (a = 0..8, j the left cell of the interface):
+# the GRB state with the sixth-order gradients substituted, minus Phi_j (left)
+# or Phi_{j+1} (right), is linear in the jumps because its weights sum to one.
+EDGE_STENCILS = {
+    # order: (denominator, left weights E0..E8, right weights E0..E8)
+    7: (840, [1, -1, -23, 123, 395, -89, 15, -1, 0], [0, 1, -15, 89, -395, -123, 23, 1, -1]),
+    4: (1440, [1, 4, -60, 249, 639, -132, 20, -1, 0], [0, 1, -20, 132, -639, -249, 60, -4, -1]),
+}
+
+
+def edge_form(den, w):
+    out = {}
+    for a, c in enumerate(w):
+        for k, s in ((a - 3, 1), (a - 4, -1)):
+            out[("v", k)] = out.get(("v", k), 0) + Fr(c * s, den)
+    return {k: v for k, v in out.items() if v != 0}
+
+
+@pytest.mark.parametrize("order", [7, 4])
+def test_edge_jump_stencils_are_grb_with_grad6(order):
+    ab = GOLD["alpha_beta_7th" if order == 7 else "alpha_beta_4th"]
+    a, b = Fr(*ab["alpha"]), Fr(*ab["beta"])
+    den, wl, wr = EDGE_STENCILS[order]
+    assert edge_form(den, wl) == add(substitute_grad6(grb_left(a, b)), V(0), coef=[1, -1])
+    assert edge_form(den, wr) == add(substitute_grad6(grb_right(a, b)), V(1), coef=[1, -1])
+
+
+def test_grad6_on_edge_pairs():
+    # eq. (eqn:six) at cell 0 as (37, -8, 1)/60 on the edge pairs around it
+    e = lambda k: add(V(k + 1), V(k), coef=[1, -1])
+    g = add(e(-1), e(0), e(-2), e(1), e(-3), e(2),
+            coef=[Fr(37, 60), Fr(37, 60), Fr(-8, 60), Fr(-8, 60), Fr(1, 60), Fr(1, 60)])
+    assert g == substitute_grad6(G(0))
