@@ -108,17 +108,13 @@ struct TileCfg {
   };
   using PX = Phase<TX, SX>;
   using PY = Phase<TY, SY>;
-  // the largest of the two layouts (bounds and the batched kernel's arrays)
+  // the larger of the two layouts (the LDS bound checked at the launch sites)
   static constexpr int NF = cmax(Layout<false>::NFU, Layout<true>::NFU);
   static constexpr int PH = cmax(Layout<false>::PH, Layout<true>::PH);
   static constexpr int CHI = cmax(SX * PX::WD, SY * PY::WD);
   static constexpr int QMAX = cmax(SX * PX::WFL, SY * PY::WFL);
   static constexpr int CPT = (TX * TY + NT - 1) / NT;
   static constexpr int LDS_BYTES = 8 * (NF * RS + PH) + CHI + 2 * QMAX + 16;
-  template <bool EDGE>
-  static constexpr int lds_bytes() {
-    return 8 * (Layout<EDGE>::NFU * RS + Layout<EDGE>::PH) + CHI + 2 * QMAX + 16;
-  }
 };
 
 // The edge form (per-line edge jumps instead of staged gradients) serves
